@@ -1,0 +1,253 @@
+"""Pins of the oracle's backward passes (Algorithm 2, Algorithm 4) against
+finite differences, the classical full-rank formula, the degenerate-case
+theorem and the closed forms at orthogonal M (CPU only)."""
+import numpy as np
+import pytest
+
+from paper_2609_32505_amd import inputs
+
+
+def _aligned_svd(orc, M, U0, V0):
+    U, S, V, _ = orc.svd(M)
+    sg = np.sign(np.sum(U * U0, axis=0))
+    sg[sg == 0] = 1.0
+    return U * sg, S, V * sg
+
+
+def _fd(f, M, E, h):
+    return (f(M + h * E) - f(M - h * E)) / (2 * h)
+
+
+def _directions(rng, shape, k):
+    out = []
+    for _ in range(k):
+        E = rng.standard_normal(shape)
+        out.append(E / np.linalg.norm(E))
+    return out
+
+
+def test_polar_backward_vs_fd(orc):
+    # exact polar backward theorem (Algorithm 2 with eps = 0) on a polar loss
+    rng = inputs.rng_for(21, 0)
+    m, n = 7, 4
+    M = inputs.matrix_with_spectrum(rng, m, n, np.array([2.0, 1.0, 0.7, 0.3]))
+    GW = rng.standard_normal((m, n))
+    GH = rng.standard_normal((n, n))
+
+    def loss(X):
+        U, S, V, _ = orc.svd(X)
+        W, H = orc.polar_from_svd(U, S, V)
+        return np.sum(GW * W) + np.sum(GH * H)
+
+    U, S, V, _ = orc.svd(M)
+    _, H = orc.polar_from_svd(U, S, V)
+    G = orc.polar_bwd(M, H, GW, GH, 0.0, 0.0)
+    for E in _directions(rng, (m, n), 8):
+        fd = _fd(loss, M, E, 1e-5)
+        assert np.sum(G * E) == pytest.approx(fd, rel=1e-7, abs=1e-9)
+
+
+def test_polar_backward_with_repeated_singular_values_vs_fd(orc):
+    # the polar factors stay smooth at repeated singular values (full rank)
+    rng = inputs.rng_for(22, 0)
+    m, n = 6, 4
+    M = inputs.matrix_with_spectrum(rng, m, n, np.array([1.5, 1.0, 1.0, 0.5]))
+    GW = rng.standard_normal((m, n))
+    GH = rng.standard_normal((n, n))
+
+    def loss(X):
+        U, S, V, _ = orc.svd(X)
+        W, H = orc.polar_from_svd(U, S, V)
+        return np.sum(GW * W) + np.sum(GH * H)
+
+    U, S, V, _ = orc.svd(M)
+    _, H = orc.polar_from_svd(U, S, V)
+    G = orc.polar_bwd(M, H, GW, GH, 0.0, 0.0)
+    for E in _directions(rng, (m, n), 6):
+        assert np.sum(G * E) == pytest.approx(_fd(loss, M, E, 1e-5), rel=1e-6, abs=1e-9)
+
+
+def test_svd_backward_generic_loss_vs_fd(orc):
+    # Algorithm 4 with eps = 0 on a generic loss at distinct singular values
+    rng = inputs.rng_for(23, 0)
+    m, n = 6, 4
+    M = inputs.matrix_with_spectrum(rng, m, n, np.array([2.0, 1.2, 0.8, 0.3]))
+    U0, S0, V0, _ = orc.svd(M)
+    dU = rng.standard_normal((m, n)); dS = rng.standard_normal(n)
+    dV = rng.standard_normal((n, n))
+
+    def loss(X):
+        U, S, V = _aligned_svd(orc, X, U0, V0)
+        return np.sum(dU * U) + np.sum(dS * S) + np.sum(dV * V)
+
+    G = orc.svd_bwd(M, U0, S0, V0, dU, dS, dV, 0.0, 0.0, 0.0)
+    for E in _directions(rng, (m, n), 8):
+        assert np.sum(G * E) == pytest.approx(_fd(loss, M, E, 1e-5), rel=1e-6, abs=1e-8)
+
+
+def test_svd_backward_matches_classical_formula(orc):
+    rng = inputs.rng_for(24, 0)
+    m, n = 9, 5
+    M = inputs.matrix_with_spectrum(rng, m, n, np.array([3.0, 2.0, 1.1, 0.6, 0.2]))
+    U, S, V, _ = orc.svd(M)
+    dU = rng.standard_normal((m, n)); dS = rng.standard_normal(n)
+    dV = rng.standard_normal((n, n))
+    G4 = orc.svd_bwd(M, U, S, V, dU, dS, dV, 0.0, 0.0, 0.0)
+    GT = orc.townsend_bwd(U, S, V, dU, dS, dV)
+    np.testing.assert_allclose(G4, GT, atol=1e-12 * np.abs(GT).max())
+
+
+def test_svd_backward_gauge_invariant_loss_at_degenerate_spectrum_vs_fd(orc):
+    # L = <G1, U V^T> + <g, sigma> with g constant on clusters is differentiable
+    # at repeated singular values, and Algorithm 4 returns its gradient there.
+    rng = inputs.rng_for(25, 0)
+    m, n = 7, 5
+    s = np.array([2.0, 1.0, 1.0, 0.6, 0.6])
+    M = inputs.matrix_with_spectrum(rng, m, n, s)
+    U, S, V, _ = orc.svd(M)
+    G1 = rng.standard_normal((m, n))
+    g = np.array([0.3, -1.0, -1.0, 0.5, 0.5])
+
+    def loss(X):
+        Uu, Ss, Vv, _ = orc.svd(X)
+        return np.sum(G1 * (Uu @ Vv.T)) + np.sum(g * Ss)
+
+    dU = G1 @ V
+    dV = G1.T @ U
+    # computed clusters differ by rounding (~1e-16), where an unregularised
+    # 1/(s_i - s_j) multiplies rounding noise; take the exact clusters, or a
+    # tiny Tikhonov eps_K that damps those entries
+    G = orc.svd_bwd(M, U, s, V, dU, g, dV, 0.0, 0.0, 0.0)
+    Gk = orc.svd_bwd(M, U, S, V, dU, g, dV, 1e-12, 0.0, 0.0)
+    assert np.all(np.isfinite(G))
+    np.testing.assert_allclose(Gk, G, atol=1e-8)
+    for E in _directions(rng, (m, n), 8):
+        assert np.sum(G * E) == pytest.approx(_fd(loss, M, E, 1e-5), rel=1e-6, abs=1e-8)
+
+
+def test_svd_backward_spectral_function_loss_near_degenerate_vs_fd(orc):
+    # <G2, U f(Sigma) V^T> with f(x) = x^2 at a gap of 1e-4: the divided
+    # differences (f_i - f_j)/(s_i - s_j) enter through K; Algorithm 4 with
+    # eps = 0 is the gradient.  (At an exact tie K_ij = 0 by the pseudo-
+    # gradient definition, which drops the within-cluster part: there the
+    # result is the pseudo-gradient, not the limit of gradients.)
+    rng = inputs.rng_for(31, 0)
+    m, n = 7, 5
+    s = np.array([2.0, 1.0, 1.0 - 1e-4, 0.6, 0.6 - 1e-4])
+    M = inputs.matrix_with_spectrum(rng, m, n, s)
+    U, S, V, _ = orc.svd(M)
+    G2 = rng.standard_normal((m, n))
+
+    def loss(X):
+        Uu, Ss, Vv, _ = orc.svd(X)
+        return np.sum(G2 * ((Uu * Ss ** 2) @ Vv.T))
+
+    dU = (G2 @ V) * S ** 2
+    dV = (G2.T @ U) * S ** 2
+    dS = np.sum(U * (G2 @ V), axis=0) * 2 * S
+    G = orc.svd_bwd(M, U, S, V, dU, dS, dV, 0.0, 0.0, 0.0)
+    for E in _directions(rng, (m, n), 6):
+        assert np.sum(G * E) == pytest.approx(_fd(loss, M, E, 1e-7), rel=1e-5, abs=1e-8)
+
+
+def test_degenerate_theorem_agrees_on_gauge_invariant_loss(orc):
+    # the degenerate-case SVD backward theorem (F, G masks) equals Algorithm 4
+    # (eps = 0) when the loss is invariant to rotations inside clusters
+    rng = inputs.rng_for(26, 0)
+    n = 5
+    s = np.array([2.0, 1.0, 1.0, 0.4, 0.4])
+    M = inputs.matrix_with_spectrum(rng, n, n, s)
+    U, S, V, _ = orc.svd(M)
+    S = s.copy()  # exact clusters
+    G1 = rng.standard_normal((n, n))
+    dU = G1 @ V; dV = G1.T @ U; dS = rng.standard_normal(n)
+    dS[2] = dS[1]; dS[4] = dS[3]
+    A = U.T @ dU; B = V.T @ dV
+    F = np.zeros((n, n)); Gm = np.zeros((n, n))
+    for i in range(n):
+        for j in range(n):
+            if S[i] != S[j]:
+                F[i, j] = 1.0 / (S[j] ** 2 - S[i] ** 2)
+            elif S[i] > 0:
+                Gm[i, j] = 1.0 / (2 * S[i])
+    Sg = np.diag(S)
+    skew = lambda X: 0.5 * (X - X.T)
+    inner = F * ((A - A.T) @ Sg + Sg @ (B - B.T)) + np.diag(dS) + Gm * skew(A - B)
+    Gdeg = U @ inner @ V.T
+    G4 = orc.svd_bwd(M, U, S, V, dU, dS, dV, 0.0, 0.0, 0.0)
+    np.testing.assert_allclose(G4, Gdeg, atol=1e-12)
+
+
+def test_orthogonal_input_closed_forms(orc):
+    # M = Q1 Q2^T (all singular values 1): U-only gives U skew(U^T dU) V^T,
+    # V-only gives 0, Sigma-only gives U diag(dS) V^T.
+    rng = inputs.rng_for(27, 0)
+    n = 6
+    U = inputs.orthonormal(rng, n, n); V = inputs.orthonormal(rng, n, n)
+    S = np.ones(n); M = U @ V.T
+    dU = rng.standard_normal((n, n)); dV = rng.standard_normal((n, n))
+    dS = rng.standard_normal(n)
+    skew = lambda X: 0.5 * (X - X.T)
+    np.testing.assert_allclose(orc.svd_bwd(M, U, S, V, dU=dU), U @ skew(U.T @ dU) @ V.T,
+                               atol=1e-13)
+    np.testing.assert_allclose(orc.svd_bwd(M, U, S, V, dV=dV), 0.0, atol=1e-13)
+    np.testing.assert_allclose(orc.svd_bwd(M, U, S, V, dS=dS), (U * dS) @ V.T, atol=1e-13)
+
+
+def test_regularised_backward_converges(orc):
+    # the regularised polar gradient approaches the exact one as eps -> 0
+    rng = inputs.rng_for(28, 0)
+    m, n = 8, 5
+    M = inputs.matrix_with_spectrum(rng, m, n, np.array([1.0, 0.5, 0.3, 0.1, 0.05]))
+    U, S, V, _ = orc.svd(M)
+    _, H = orc.polar_from_svd(U, S, V)
+    dW = rng.standard_normal((m, n)); dH = rng.standard_normal((n, n))
+    exact = orc.polar_bwd(M, H, dW, dH, 0.0, 0.0)
+    errs = []
+    for eps in [1e-4, 1e-8, 1e-12, 1e-16]:
+        _, eR, eT = orc.paper_eps(eps)
+        errs.append(np.linalg.norm(orc.polar_bwd(M, H, dW, dH, eR, eT) - exact))
+    assert all(errs[i + 1] < errs[i] for i in range(3))
+    assert errs[-1] < 1e-2 * np.linalg.norm(exact)
+
+
+def test_tikhonov_keeps_gradient_finite_at_tiny_gap(orc):
+    # Table 3's qualitative claim: eps_K > 0 keeps the gradient bounded at
+    # vanishing gaps, while the unregularised K blows up as 1/gap.
+    rng = inputs.rng_for(29, 0)
+    n = 6
+    norms = {}
+    for gap in [1e-1, 1e-6, 1e-12]:
+        s = np.array([6.0, 5.0, 4.0, 3.0, 2.0, 2.0 - gap])
+        M = inputs.matrix_with_spectrum(inputs.rng_for(29, 1), n, n, s)
+        U, S, V, _ = orc.svd(M)
+        dU = rng.standard_normal((n, n)); dV = rng.standard_normal((n, n))
+        dS = rng.standard_normal(n)
+        g0 = orc.svd_bwd(M, U, S, V, dU, dS, dV, 0.0, 0.0, 0.0)
+        g1 = orc.svd_bwd(M, U, S, V, dU, dS, dV, 1e-8, 0.0, 0.0)
+        norms[gap] = (np.linalg.norm(g0), np.linalg.norm(g1))
+    assert norms[1e-1][1] == pytest.approx(norms[1e-1][0], rel=1e-5)
+    assert norms[1e-12][0] > 1e6 * norms[1e-1][0]
+    assert norms[1e-12][1] < 1e5
+
+
+def test_lyapunov_identity_on_oracle_solution(orc):
+    # Lyapunov identity lemma: with HY + YH = A and HX + XH = B,
+    # <A, X> = <Y, B>; the eigenbasis solution of the proposition on solving
+    # the symmetric Lyapunov equation satisfies both equations.
+    rng = inputs.rng_for(30, 0)
+    n = 6
+    Q = inputs.orthonormal(rng, n, n)
+    lam = np.array([3.0, 2.0, 2.0, 1.0, 0.5, 0.1])
+    H = (Q * lam) @ Q.T
+    A = rng.standard_normal((n, n)); B = rng.standard_normal((n, n))
+    lam_o, V, _ = orc.eigh(H)
+
+    def solve(C):
+        Ct = V.T @ C @ V
+        return V @ (Ct / (lam_o[:, None] + lam_o[None, :])) @ V.T
+
+    X = solve(B); Y = solve(A)
+    np.testing.assert_allclose(H @ X + X @ H, B, atol=1e-12)
+    np.testing.assert_allclose(H @ Y + Y @ H, A, atol=1e-12)
+    assert np.sum(A * X) == pytest.approx(np.sum(Y * B), rel=1e-12)

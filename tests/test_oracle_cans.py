@@ -1,0 +1,162 @@
+"""Pins of the oracle's CANS polynomial, schedule and FP64 iteration, the
+sketch features and the predictor MLP (CPU only)."""
+import numpy as np
+import pytest
+
+from paper_2609_32505_amd import inputs
+
+
+@pytest.mark.parametrize("a,b", [(0.01, 1.99), (1e-3, 1.0), (0.5, 1.0), (0.9, 1.1), (0.2, 1.7)])
+def test_cans_poly_equioscillates_and_is_minimax(orc, a, b):
+    al, be, lo, hi = orc.cans_poly(a, b)
+    x = np.linspace(a, b, 200001)
+    err = 1.0 - (al * x + be * x ** 3)
+    E = np.abs(err).max()
+    xs = np.sqrt((a * a + a * b + b * b) / 3.0)
+    e_a = 1 - (al * a + be * a ** 3)
+    e_x = 1 - (al * xs + be * xs ** 3)
+    e_b = 1 - (al * b + be * b ** 3)
+    # equal magnitude, alternating sign at a, x*, b; nothing larger inside
+    assert e_a == pytest.approx(E, rel=1e-9)
+    assert e_x == pytest.approx(-E, rel=1e-9)
+    assert e_b == pytest.approx(E, rel=1e-9)
+    assert lo == pytest.approx(1 - E, rel=1e-12) and hi == pytest.approx(1 + E, rel=1e-12)
+    # brute force: no nearby odd cubic does better (minimax)
+    rng = np.random.default_rng(0)
+    for _ in range(300):
+        da, db = rng.standard_normal(2) * 1e-3
+        e2 = np.abs(1.0 - ((al + da) * x + (be + db) * x ** 3)).max()
+        assert e2 >= E * (1 - 1e-12)
+
+
+def test_cans_poly_newton_schulz_limit(orc):
+    al, be, lo, hi = orc.cans_poly(1.0, 1.0)
+    assert (al, be) == (1.5, -0.5) and lo == 1.0 and hi == 1.0
+
+
+def test_interval_recursion_shrinks(orc):
+    a, b = 0.01, 1.99
+    prev = 1.0
+    for _ in range(9):
+        _, _, a, b = orc.cans_poly(a, b)
+        e = max(1 - a, b - 1)
+        assert e < prev
+        prev = e
+    # slow while the interval is wide, then faster than quadratic
+    assert prev < 1e-8
+
+
+def test_preprocess_boundary(orc):
+    t = orc.cans_preprocess_t(0.99)
+    def two(t0):
+        a, b = t0, 1.0
+        for _ in range(2):
+            _, _, a, b = orc.cans_poly(a, b)
+        return max(1 - a, b - 1)
+    assert two(t) == pytest.approx(0.99, abs=1e-9)
+    assert two(t * 0.999) > 0.99 and two(t * 1.001) < 0.99
+    assert 7e-4 < t < 8e-4
+
+
+def test_conservative_table_layout(orc):
+    tab = orc.cans_schedule_conservative()
+    assert tab.shape == (50, 2)
+    t = orc.cans_preprocess_t(0.99)
+    np.testing.assert_allclose(tab[0], orc.cans_poly(t, 1.0)[:2])
+    np.testing.assert_allclose(tab[-1], [1.5, -0.5], atol=1e-12)
+
+
+def test_normaliser_bounds_spectral_norm(orc):
+    rng = inputs.rng_for(40, 0)
+    for m, n in [(16, 16), (40, 12)]:
+        A = rng.standard_normal((m, n))
+        s = orc.ns_normaliser(A)
+        assert s >= np.linalg.norm(A, 2) * (1 - 1e-12)
+        assert s == pytest.approx(np.sqrt(np.abs(A).sum(0).max() * np.abs(A).sum(1).max()))
+
+
+@pytest.mark.parametrize("m,n,kappa", [(24, 24, 1e2), (40, 16, 1e4)])
+def test_cans_polar_reaches_jacobi_polar_factor(orc, m, n, kappa):
+    rng = inputs.rng_for(41, m)
+    A = inputs.matrix_with_spectrum(rng, m, n, inputs.geometric(n, kappa))
+    U, S, V, _ = orc.svd(A)
+    W_ref, _ = orc.polar_from_svd(U, S, V)
+    W, it = orc.cans_polar(A, orc.cans_schedule_conservative(), tol=1e-13)
+    assert it < 50
+    np.testing.assert_allclose(W, W_ref, atol=1e-10 * kappa)
+    # interval path started at the true relative bound converges in fewer steps
+    tab, _ = orc.cans_schedule_interval(S[-1] / S[0])
+    W2, it2 = orc.cans_polar(A, tab, tol=1e-13, scale=S[0])
+    np.testing.assert_allclose(W2, W_ref, atol=1e-10 * kappa)
+    assert it2 < it
+
+
+def test_features_diagonal_equal_spectral(orc):
+    rng = np.random.default_rng(42)
+    s = np.sort(np.exp(rng.uniform(-5, 0, 30)))[::-1]
+    z = rng.standard_normal(30)
+    f1, r1, F1 = orc.sketch_features(np.diag(s), z)
+    f2, r2, F2 = orc.spectral_features(s, z, 30)
+    np.testing.assert_allclose(f1, f2, rtol=1e-12, atol=1e-12)
+    assert r1 == pytest.approx(r2, rel=1e-12) and F1 == pytest.approx(F2, rel=1e-12)
+
+
+def test_features_orthogonal_invariance_and_scale(orc):
+    rng = inputs.rng_for(43, 0)
+    m, n = 50, 30
+    s = inputs.log_uniform(rng, n, 1e-3, 1.0)
+    Q1 = inputs.orthonormal(rng, m, n); Q2 = inputs.orthonormal(rng, n, n)
+    A = (Q1 * s) @ Q2.T
+    z = rng.standard_normal(n)
+    f1, r1, F1 = orc.sketch_features(A, Q2 @ z)
+    f2, r2, _ = orc.spectral_features(s, z, m)
+    np.testing.assert_allclose(f1, f2, atol=1e-10)
+    f3, r3, F3 = orc.sketch_features(1e3 * A, Q2 @ z)
+    np.testing.assert_allclose(f3, f1, atol=1e-10)
+    assert r3 == pytest.approx(1e3 * r1, rel=1e-10)
+    # r_7 is a lower bound of sigma_max
+    assert r1 <= s[0] * (1 + 1e-12)
+    assert f1[-1] == pytest.approx(np.log(m / n))
+
+
+def test_mlp_backward_vs_fd(orc):
+    rng = np.random.default_rng(44)
+    p = rng.standard_normal(orc.N_PARAMS) * 0.3
+    X = rng.standard_normal((5, orc.N_FEAT))
+    D = rng.standard_normal((5, orc.N_OUT))
+    out, cache = orc.mlp_forward(p, X)
+    assert out.shape == (5, 2) and orc.N_PARAMS == 4866
+    g = orc.mlp_backward(p, cache, D)
+    f = lambda q: np.sum(D * orc.mlp_forward(q, X)[0])
+    idx = rng.choice(orc.N_PARAMS, 60, replace=False)
+    for i in idx:
+        e = np.zeros(orc.N_PARAMS); e[i] = 1e-6
+        fd = (f(p + e) - f(p - e)) / 2e-6
+        assert g[i] == pytest.approx(fd, rel=1e-6, abs=1e-9)
+
+
+def test_pinball_loss_and_gradient(orc):
+    rng = np.random.default_rng(45)
+    out = rng.standard_normal((7, 2)); tgt = rng.standard_normal((7, 2))
+    taus = [0.9, 0.1]
+    L, G = orc.pinball_loss(out, tgt, taus)
+    # closed form on a single entry
+    u = tgt - out
+    ref = sum(max(t * u[r, j], (t - 1) * u[r, j]) for r in range(7) for j, t in enumerate(taus)) / 7
+    assert L == pytest.approx(ref)
+    for r in range(7):
+        for j in range(2):
+            e = np.zeros_like(out); e[r, j] = 1e-7
+            fd = (orc.pinball_loss(out + e, tgt, taus)[0] - orc.pinball_loss(out - e, tgt, taus)[0]) / 2e-7
+            assert G[r, j] == pytest.approx(fd, rel=1e-6)
+
+
+def test_adam_constant_gradient_closed_form(orc):
+    # with a constant gradient the bias-corrected moments equal g and g^2 at
+    # every step, so each step moves by lr * g / (|g| + eps)
+    g = np.array([0.5, -2.0, 1e-3])
+    p = np.zeros(3); m = np.zeros(3); v = np.zeros(3)
+    for t in range(1, 6):
+        p_new, m, v = orc.adam_step(p, m, v, g, t, lr=0.01, eps=1e-12)
+        np.testing.assert_allclose(p_new - p, -0.01 * g / (np.abs(g) + 1e-12), rtol=1e-9)
+        p = p_new
