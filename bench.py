@@ -1,0 +1,202 @@
+#!/usr/bin/env python3
+"""Benchmark: differentiable SVD (forward + backward) throughput in matrices/s.
+
+Workload: a batch of 256 square 512 x 512 FP32 matrices A = Q1 diag(s) Q2^T
+(Q1, Q2 Haar from Householder QR of seeded Gaussians, s log-uniform in
+[1e-3, 1]) with upstream gradients dU, dS, dV ~ N(0, 1), all resident in HBM
+before the timed region.  One step = svd_polar_fwd + svd_polar_bwd of the
+whole batch.  Two paths run in the same process on the same inputs:
+  * learned: sketch features -> predictor MLP -> interval-optimal CANS steps
+    (FP32 while the interval's lower end is small, then BF16 MFMA), FP32
+    refinement, block-Jacobi eigh, backward (the reported `value`);
+  * plain: conservative FP32 CANS (Algorithm 3 scaling, delta preprocessing,
+    tolerance 1e-5) with the same eigh and backward.
+The sigma error of every matrix is checked against the plain FP32 result and
+the plain result against the FP64 oracle on sampled matrices (bound 1e-3,
+normwise).  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAKS = {  # MI355X published dense peaks
+    "mfma_fp32": 157.3, "mfma_bf16": 2500.0, "alu_fp32": 157.3, "alu_fp64": 78.6, "hbm": 8000.0,
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_profile(L):
+    import ctypes
+    out = {}
+    for name, kind in L.PROF_KINDS.items():
+        ms = ctypes.c_double(); cnt = ctypes.c_int64(); work = ctypes.c_double()
+        L.check(L.load().svdp_profile_read(kind, ctypes.byref(ms), ctypes.byref(cnt), ctypes.byref(work)),
+                "profile_read")
+        out[name] = {"ms": ms.value, "launches": cnt.value, "flops": work.value}
+    return out
+
+
+def roofline_of(prof):
+    name = max(prof, key=lambda k: prof[k]["ms"])
+    rec = prof[name]
+    if name in ("gemm_f32", "jac_apply"):
+        bound, peak = "mfma", PEAKS["mfma_fp32"]
+    elif name == "gemm_bf16":
+        bound, peak = "mfma", PEAKS["mfma_bf16"]
+    elif name == "jac_solve_f64":
+        bound, peak = "alu", PEAKS["alu_fp64"]
+    else:
+        bound, peak = "alu", PEAKS["alu_fp32"]
+    avg_ms = rec["ms"] / max(rec["launches"], 1)
+    per_launch = rec["flops"] / max(rec["launches"], 1)
+    achieved = per_launch / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
+    return name, {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                  "frac": round(achieved / peak, 5), "traffic": None,
+                  "kernel": name, "avg_launch_ms": round(avg_ms, 4),
+                  "flops_per_launch": per_launch}
+
+
+def cpu_baseline(A, dU, dS, dV, sample: int):
+    """FP64 oracle (one-sided Jacobi SVD + literal Algorithm 4), OpenMP one
+    matrix per thread, on the first `sample` matrices of the workload."""
+    import numpy as np
+    import oracle
+    threads = min(os.cpu_count() or 1, 16)
+    a = A[:sample].astype(np.float64)
+    t0 = time.time()
+    U, S, V, _ = oracle.svd_batch(a, threads=threads)
+    oracle.svd_bwd_batch(a, U, S, V, dU[:sample], dS[:sample], dV[:sample], threads=threads)
+    dt = time.time() - t0
+    return {"value": round(sample / dt, 4), "unit": "matrices/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {sample} of the 256 matrices (512 x 512), forward SVD + Algorithm 4 "
+                      f"backward in FP64, {dt:.1f} s"}, S
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--cpu-sample", type=int, default=16)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-only", action="store_true",
+                    help="run warmup + steps of the learned path only (for rocprofv3)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2609_32505_amd import _lib as L, api, inputs, predictor
+
+    B, n = args.batch, args.n
+    t0 = time.time()
+    A, S_gen = inputs.square_loguniform(seed=2, batch=B, n=n)
+    rng = inputs.rng_for(12, 0)
+    dU = rng.standard_normal((B, n, n)).astype(np.float32)
+    dS = rng.standard_normal((B, n)).astype(np.float32)
+    dV = rng.standard_normal((B, n, n)).astype(np.float32)
+    probe = inputs.probe(13, B, n)
+    log(f"inputs generated in {time.time() - t0:.1f} s")
+
+    dev = torch.device("cuda:0")
+    Ad = torch.from_numpy(A).to(dev)
+    dUd, dSd, dVd = (torch.from_numpy(x).to(dev) for x in (dU, dS, dV))
+    pd = torch.from_numpy(probe).to(dev)
+    h = api.Handle()
+    h.set_model(predictor.load())
+    eps = dict(eps_K=1e-12, eps_R=0.0, eps_T=0.0)
+
+    def step(learned: bool):
+        if learned:
+            U, S, V, info = api.svd_fwd(Ad, handle=h, precision=L.PREC_BF16, bound=L.BOUND_LEARNED, probe=pd)
+        else:
+            U, S, V, info = api.svd_fwd(Ad, handle=h)
+        dA = api.svd_bwd(U, S, V, dUd, dSd, dVd, handle=h, **eps)
+        return S, info, dA
+
+    def timed(learned: bool, profile: bool):
+        for _ in range(args.warmup):
+            step(learned)
+        torch.cuda.synchronize()
+        if profile:
+            L.load().svdp_profile_reset()
+            L.load().svdp_profile_enable(1)
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        out = None
+        for _ in range(args.steps):
+            out = step(learned)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / args.steps
+        prof = None
+        if profile:
+            L.load().svdp_profile_enable(0)
+            prof = kernel_profile(L)
+        return ms, out, prof
+
+    ms_l, (S_l, info_l, _), prof = timed(True, True)
+    log(f"learned: {ms_l:.2f} ms/step")
+    if args.profile_only:
+        print(json.dumps({"profile_only": True, "ms_per_step": ms_l}))
+        return
+    ms_p, (S_p, info_p, _), _ = timed(False, False)
+    log(f"plain fp32: {ms_p:.2f} ms/step")
+
+    il, ip = api.info_to_numpy(info_l), api.info_to_numpy(info_p)
+    Sl, Sp = S_l.cpu().double().numpy(), S_p.cpu().double().numpy()
+    err_lp = float((np.abs(Sl - Sp).max(axis=1) / Sp[:, 0]).max())
+    # plain vs FP64 oracle, and the CPU baseline on the same sample
+    cpu, S_or = None, None
+    if not args.no_cpu_baseline:
+        cpu, S_or = cpu_baseline(A, dU, dS, dV, args.cpu_sample)
+    else:
+        import oracle
+        S_or = np.stack([oracle.svd(A[i].astype(np.float64))[1] for i in range(2)])
+    k = S_or.shape[0]
+    err_po = float((np.abs(Sp[:k] - S_or).max(axis=1) / S_or[:, 0]).max())
+    err_lo = float((np.abs(Sl[:k] - S_or).max(axis=1) / S_or[:, 0]).max())
+    valid = err_lp + err_po <= 1e-3 and err_lo <= 1e-3
+
+    name, roof = roofline_of(prof)
+    value = B / (ms_l * 1e-3)
+    rec = {
+        "metric": "SVD fwd+bwd matrices/s, 512^2 batch, sigma err<=1e-3; learned BF16 vs plain FP32 CANS",
+        "value": round(value, 3), "unit": "matrices/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_l, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16+fp32", "data": "synthetic",
+        "config": {"workload": f"{B} x {n} x {n} FP32, sigma log-uniform [1e-3,1], svd_polar_fwd + "
+                               f"svd_polar_bwd, learned-bound BF16 CANS", "batch": B, "m": n, "n": n},
+        "plain_fp32": {"value": round(B / (ms_p * 1e-3), 3), "ms_per_step": round(ms_p, 3),
+                       "iters": [int(il["iters"].max()), int(ip["iters"].max())]},
+        "speedup_learned_vs_plain": round(ms_p / ms_l, 4),
+        "sigma_err": {"learned_vs_plain_max": err_lp, "plain_vs_oracle_sampled": err_po,
+                      "learned_vs_oracle_sampled": err_lo, "valid": bool(valid)},
+        "learned_info": {"iters_max": int(il["iters"].max()), "sweeps_max": int(il["sweeps"].max()),
+                         "fallbacks": int(((il["flags"] & L.FLAG_FALLBACK_USED) != 0).sum())},
+        "roofline": roof,
+        "kernels": {k2: {"ms_per_step": round(v["ms"] / args.steps, 3), "launches": v["launches"]}
+                    for k2, v in prof.items()},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

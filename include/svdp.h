@@ -1,0 +1,275 @@
+/*
+ * svdp -- differentiable SVD via polar decomposition on AMD Instinct MI355X
+ * (gfx950).  C ABI.
+ *
+ * Method ("Fast Differentiable SVD on GPU via Polar Decomposition"):
+ *   forward  (Algorithm 1): normalise A (Algorithm 3), compute the polar
+ *            factor W by the CANS polynomial iteration (chains of batched
+ *            GEMMs), H = sym(W^T A), eigendecomposition H = V Sigma V^T,
+ *            U = W V, rank-deficiency test on the column norms of U;
+ *   backward (Algorithm 4, and Algorithm 2 for the polar factors): the
+ *            regularised adjoint, a Sylvester solve in the eigenbasis of H.
+ *
+ * Conventions for every entry point:
+ *   - Matrices are dense FP32, row-major, batched: matrix b of an argument X
+ *     starts at X + b * sX, and entry (i, j) is X[b * sX + i * ldX + j]
+ *     (ld >= number of columns).  Vectors (S, dS) use only a batch stride.
+ *   - All array pointers are DEVICE pointers owned by the caller, except
+ *     where a comment says host.  The library allocates no device memory per
+ *     call: scratch comes from the caller's workspace `ws` of `ws_bytes`
+ *     bytes, sized by svdp_workspace_size() (alignment 256 bytes).
+ *   - Work is enqueued on `stream` (a hipStream_t passed as void*; null =
+ *     the default stream).  Calls return after enqueueing, except that the
+ *     forward passes read a few device counters back to the host (iteration
+ *     control of CANS and Jacobi), which synchronises `stream`.
+ *   - Errors: arguments are checked before anything is launched; a non-OK
+ *     status means no work was enqueued, except SVDP_ERR_HIP, which reports
+ *     a failed launch or copy (svdp_last_error() gives the HIP message).
+ *     Numerical trouble never fails a call: it is reported per matrix in
+ *     `info` (svdp_info flags).
+ *   - A null upstream gradient (dU, dS, dV, dW, dH) means zero.
+ */
+#ifndef SVDP_H
+#define SVDP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SVDP_OK = 0,
+  SVDP_ERR_INVALID_ARG = 1, /* null pointer, bad precision/bound/op, ld too small */
+  SVDP_ERR_SHAPE = 2,       /* m < n, n < 1, batch < 0 or > 65535, n > 8192, m*n > 2^31 */
+  SVDP_ERR_WORKSPACE = 3,   /* ws_bytes below svdp_workspace_size() */
+  SVDP_ERR_HIP = 4,         /* a HIP launch or copy failed */
+  SVDP_ERR_NO_MODEL = 5     /* learned bounds requested, no model loaded */
+} svdp_status;
+
+/* arithmetic of the CANS polar iteration */
+typedef enum {
+  SVDP_PREC_FP32 = 0, /* FP32 GEMMs on FP32 MFMA throughout */
+  SVDP_PREC_BF16 = 1  /* BF16 MFMA (FP32 accumulate), then FP32 refinement steps */
+} svdp_precision;
+
+/* how the spectral interval of A is bounded before CANS */
+typedef enum {
+  SVDP_BOUND_CONSERVATIVE = 0, /* sqrt(|A|_1 |A|_inf) scale + delta preprocessing */
+  SVDP_BOUND_LEARNED = 1,      /* sketch features -> MLP -> [sigma_min, sigma_max] */
+  SVDP_BOUND_USER = 2          /* caller's [sigma_min, sigma_max] per matrix */
+} svdp_bound;
+
+/* per-matrix result flags (svdp_info.flags) */
+#define SVDP_FLAG_NOT_CONVERGED 1        /* CANS stopped at max_iters above tol */
+#define SVDP_FLAG_FALLBACK_USED 2        /* learned/user bound failed; conservative CANS rerun */
+#define SVDP_FLAG_NEG_EIGENVALUE 4       /* H had an eigenvalue below -1e-4 max|lambda| */
+#define SVDP_FLAG_RANK_DEFICIENT 8       /* some | |U_i| - 1 | > eps_qr (QR fix not applied) */
+#define SVDP_FLAG_NONFINITE 16           /* non-finite input or result */
+#define SVDP_FLAG_EIGH_NOT_CONVERGED 32  /* Jacobi hit max_sweeps */
+
+typedef struct {
+  int64_t batch, m, n;     /* m >= n >= 1 */
+  int32_t precision;       /* svdp_precision */
+  int32_t bound;           /* svdp_bound */
+  int32_t max_iters;       /* CANS step cap, preprocessing included (50) */
+  int32_t pre_iters;       /* conservative preprocessing steps (2) */
+  int32_t refine_steps;    /* FP32 steps after the BF16 phase (2) */
+  int32_t max_sweeps;      /* Jacobi sweep cap (20) */
+  int32_t inner_sweeps;    /* scalar sweeps per 64 x 64 Jacobi subproblem (1) */
+  int32_t fp64_sweeps;     /* final Jacobi sweeps with FP64 subproblem solves (1) */
+  double delta;            /* CANS preprocessing target [1-delta, 1+delta] (0.99) */
+  double tol;              /* CANS stop: |X_k+1 - X_k|_F <= tol |X_k+1|_F (1e-5) */
+  double eps_qr;           /* column-norm tolerance of U (1e-5) */
+  double bf16_handoff;     /* BF16 phase ends when the interval error <= this (1e-2) */
+  double refine_tol;       /* learned path falls back when the refinement residual exceeds this (1e-2) */
+  double jacobi_tol;       /* Jacobi stops after a sweep whose largest rotated |h_pq| is
+                              <= jacobi_tol sqrt(|h_pp h_qq|); the final FP64 sweep then
+                              leaves about jacobi_tol^2 (quadratic convergence) (1e-3) */
+  double jacobi_abs;       /* entries below jacobi_abs |H|_F are ignored by that test (1e-9) */
+  double bf16_from;        /* bounded paths: FP32 steps until the interval's lower end
+                              reaches this value, BF16 steps after it (0.1) */
+  double eps_K, eps_R, eps_T; /* backward regularisers (absolute, units of sigma^2):
+                              K_ij = (s_i - s_j)/((s_i - s_j)^2 + eps_K),
+                              R = V S (S^2 + eps_R)^-1 V^T,
+                              T_ij = (s_i + s_j)/((s_i + s_j)^2 + eps_T).
+                              Algorithm 4 takes (eps^1/2, eps^1/2, eps^1/4). */
+  double margin_max;       /* learned/user sigma_max is multiplied by this (1.1) */
+  double margin_min;       /* learned/user sigma_min is multiplied by this (0.5) */
+  const float* user_bounds; /* device, batch x 2 (sigma_min, sigma_max), bound == USER */
+  const float* probe;      /* device, batch x n Gaussian probe vectors, bound == LEARNED */
+} svdp_params;
+
+/* per-matrix diagnostics, device array of `batch` records */
+typedef struct {
+  int32_t iters;    /* CANS steps taken (BF16 + FP32) */
+  int32_t sweeps;   /* Jacobi sweeps (FP32 phase) */
+  int32_t flags;    /* SVDP_FLAG_* */
+  float residual;   /* |X^T X - I|_F / sqrt(n) of the iterate entering the last CANS step */
+} svdp_info;
+
+typedef struct svdp_handle svdp_handle;
+
+/* Fill `p` with the defaults quoted in the field comments (the paper's CANS
+ * hyperparameters from its reproducibility appendix; eps triple zero). */
+void svdp_default_params(svdp_params* p, int64_t batch, int64_t m, int64_t n);
+
+/* Library handle: owns the predictor model (device copy) and a pinned host
+ * word for counter read-back.  One handle per thread / stream. */
+svdp_status svdp_create(svdp_handle** h);
+svdp_status svdp_destroy(svdp_handle* h);
+
+/* Load the interval predictor: `host_model` (HOST pointer) holds
+ * SVDP_MODEL_FLOATS floats: the MLP parameters (layout of svdp_mlp_fwd)
+ * followed by 8 feature means and 8 feature standard deviations. */
+#define SVDP_MLP_PARAMS 4866
+#define SVDP_MODEL_FLOATS (SVDP_MLP_PARAMS + 16)
+svdp_status svdp_set_model(svdp_handle* h, const float* host_model);
+
+/* op codes of svdp_workspace_size */
+#define SVDP_OP_SVD_FWD 0
+#define SVDP_OP_SVD_BWD 1
+#define SVDP_OP_POLAR_FWD 2
+#define SVDP_OP_POLAR_BWD 3
+#define SVDP_OP_EIGH 4
+#define SVDP_OP_FEATURES 5
+svdp_status svdp_workspace_size(const svdp_params* p, int32_t op, size_t* bytes);
+
+const char* svdp_status_string(svdp_status s);
+/* message of the last failing call on this thread (static storage) */
+const char* svdp_last_error(void);
+
+/* Forward SVD A = U diag(S) V^T (Algorithm 1).
+ * A: m x n.  U: m x n.  S: n values, descending.  V: n x n (V, not V^T).
+ * info: device, batch records (may be null). */
+svdp_status svd_polar_fwd(svdp_handle* h, const svdp_params* p,
+                          const float* A, int64_t lda, int64_t sA,
+                          float* U, int64_t ldu, int64_t sU,
+                          float* S, int64_t sS,
+                          float* V, int64_t ldv, int64_t sV,
+                          svdp_info* info, void* ws, size_t ws_bytes, void* stream);
+
+/* Backward of svd_polar_fwd (Algorithm 4, regularisers from p->eps_*), in
+ * the eigenbasis of H: with Ahat = U^T dU and P = V^T dV it forms
+ * C = sym(diag dS + K^T o skew(P + Ahat) - diag(D S) Ahat diag(D)),
+ * D = S / (S^2 + eps_R), Y = T o C, and dA = (dU diag(D) + 2 U S Y) V^T,
+ * which equals Algorithm 4's dW R + 2 M X with M = U S V^T.
+ * U, S, V: the forward's outputs.  dU (m x n), dS (n), dV (n x n, the
+ * gradient of V; for a loss on V^T pass its transpose).  dA: m x n. */
+svdp_status svd_polar_bwd(svdp_handle* h, const svdp_params* p,
+                          const float* U, int64_t ldu, int64_t sU,
+                          const float* S, int64_t sS,
+                          const float* V, int64_t ldv, int64_t sV,
+                          const float* dU, int64_t lddu, int64_t sdU,
+                          const float* dS, int64_t sdS,
+                          const float* dV, int64_t lddv, int64_t sdV,
+                          float* dA, int64_t ldda, int64_t sdA,
+                          void* ws, size_t ws_bytes, void* stream);
+
+/* Polar decomposition A = W H (Algorithm 1 up to the symmetric factor).
+ * W: m x n with orthonormal columns.  H: n x n, sym(W^T A).  Optional
+ * S_cache (n) / V_cache (n x n): eigenvalues (descending) and eigenvectors
+ * of H for polar_bwd; both null to skip the eigendecomposition. */
+svdp_status polar_fwd(svdp_handle* h, const svdp_params* p,
+                      const float* A, int64_t lda, int64_t sA,
+                      float* W, int64_t ldw, int64_t sW,
+                      float* H, int64_t ldh, int64_t sH,
+                      float* S_cache, int64_t sS,
+                      float* V_cache, int64_t ldv, int64_t sV,
+                      svdp_info* info, void* ws, size_t ws_bytes, void* stream);
+
+/* Backward of the polar decomposition (Algorithm 2 with regularisers eps_R,
+ * eps_T from p): dA = (dW V D + 2 (A V) Xt) V^T with
+ * Xt = T o (sym(V^T dH V) - D sym((A V)^T (dW V)) D), D = S/(S^2 + eps_R).
+ * A: the forward input.  H: n x n.  S_cache / V_cache: the eigenpairs of H
+ * from polar_fwd, or both null to compute them here first (Algorithm 2,
+ * step 1).  dW: m x n, dH: n x n (either may be null).  dA: m x n. */
+svdp_status polar_bwd(svdp_handle* h, const svdp_params* p,
+                      const float* A, int64_t lda, int64_t sA,
+                      const float* H, int64_t ldh, int64_t sH,
+                      const float* S_cache, int64_t sS,
+                      const float* V_cache, int64_t ldv, int64_t sV,
+                      const float* dW, int64_t lddw, int64_t sdW,
+                      const float* dH, int64_t lddh, int64_t sdH,
+                      float* dA, int64_t ldda, int64_t sdA,
+                      void* ws, size_t ws_bytes, void* stream);
+
+/* Symmetric eigendecomposition H = V diag(lam) V^T (the EVD step of
+ * Algorithm 1) by batched block Jacobi; lam descending (signed), V n x n.
+ * Uses p->batch, p->n (m ignored), max_sweeps, inner_sweeps, fp64_sweeps,
+ * jacobi_tol, jacobi_abs.  info: sweeps and flags (may be null). */
+svdp_status svdp_eigh(svdp_handle* h, const svdp_params* p,
+                      const float* H, int64_t ldh, int64_t sH,
+                      float* lam, int64_t slam,
+                      float* V, int64_t ldv, int64_t sV,
+                      svdp_info* info, void* ws, size_t ws_bytes, void* stream);
+
+/* Sketch features of each matrix (the learned interval predictor's input).
+ * probe: batch x n.  With y0 = probe, y1 = A y0, y2 = A^T y1, ... up to y7
+ * and r_k = |y_k| / |y_(k-1)|:  F[b] = (log(|A|_F / r_7),
+ * log(r_2 / r_3), ..., log(r_6 / r_7), log(n), log(m / n)) (8 floats);
+ * aux[b] = (r_7, |A|_F).  F: batch x 8, aux: batch x 2. */
+svdp_status svdp_bound_features(svdp_handle* h, const svdp_params* p,
+                                const float* A, int64_t lda, int64_t sA,
+                                const float* probe, float* F, float* aux,
+                                void* ws, size_t ws_bytes, void* stream);
+
+/* The same features for A = Q1 diag(s) Q2^T with probe Q2 z, which depend on
+ * (s, z) only: |y_k| = |s^k * z|.  s, z: rows x n; m_over_n: rows (host
+ * scalar semantics per row, device array).  Used to build training sets. */
+svdp_status svdp_spectral_features(const float* s, const float* z, int64_t rows, int64_t n,
+                                   const float* m_over_n, float* F, float* aux, void* stream);
+
+/* MLP 8 -> 64 -> 64 -> 2 with tanh hidden layers.  params (4866 floats):
+ * W1 (64 x 8), b1 (64), W2 (64 x 64), b2 (64), W3 (2 x 64), b3 (2), weights
+ * row-major (out x in).  Inputs are standardised as (X - mu) / sd when mu, sd
+ * (8 floats each) are given.  X: rows x 8.  out: rows x 2.  act: rows x 128
+ * (hidden activations, kept for the backward; may be null in forward-only
+ * use). */
+svdp_status svdp_mlp_fwd(const float* params, const float* mu, const float* sd,
+                         const float* X, int64_t rows, float* out, float* act, void* stream);
+/* dparams = d(sum dout * out)/d params (overwritten).  ws: at least
+ * svdp_mlp_bwd_ws_bytes(rows) bytes. */
+size_t svdp_mlp_bwd_ws_bytes(int64_t rows);
+svdp_status svdp_mlp_bwd(const float* params, const float* mu, const float* sd,
+                         const float* X, const float* act, const float* dout, int64_t rows,
+                         float* dparams, void* ws, size_t ws_bytes, void* stream);
+/* Pinball (quantile) loss mean_rows sum_j rho_tau_j(target_j - out_j),
+ * rho_tau(u) = max(tau u, (tau - 1) u): dout (rows x 2) and *loss (device,
+ * accumulated: clear it first). */
+svdp_status svdp_pinball(const float* out, const float* target, int64_t rows, float tau0,
+                         float tau1, float* dout, float* loss, void* stream);
+/* One Adam step (bias-corrected, step count t >= 1) on n parameters. */
+svdp_status svdp_adam_step(float* params, float* m, float* v, const float* grad, int64_t n,
+                           float lr, float beta1, float beta2, float eps, int64_t t,
+                           void* stream);
+
+/* HOST helper: the coefficient table (alpha_k, beta_k) of p(x) = alpha x +
+ * beta x^3 for `steps` CANS steps into host `table` (steps x 2 doubles).
+ * kind 0: conservative (pre_iters steps on [t, 1], t the smallest value they
+ * map into [1-delta, 1+delta], then the interval recursion from
+ * [1-delta, 1+delta]); kind 1: interval recursion from [lo, 1].
+ * Returns the preprocessing t (kind 0) or lo (kind 1) in *t_out. */
+svdp_status svdp_cans_table(int32_t kind, double delta, int32_t pre_iters, double lo,
+                            int32_t steps, double* table, double* t_out);
+
+/* Kernel timing for benchmarks: while enabled, every launch of the kernel
+ * classes below is bracketed by HIP events on its stream.  read() waits for
+ * the recorded events and returns, for one class, the summed milliseconds,
+ * the launch count and the summed algorithmic work in flops (the method's
+ * operation count for the matrices each launch processed); reset() forgets
+ * the records. */
+#define SVDP_PROF_JAC_SOLVE_F32 0 /* Jacobi 64 x 64 pair solves, FP32 */
+#define SVDP_PROF_JAC_SOLVE_F64 1 /* Jacobi pair solves of the FP64 sweep */
+#define SVDP_PROF_JAC_APPLY 2     /* Jacobi block rotations on MFMA */
+#define SVDP_PROF_GEMM_F32 3      /* batched GEMMs on FP32 MFMA */
+#define SVDP_PROF_GEMM_BF16 4     /* batched GEMMs on BF16 MFMA */
+void svdp_profile_enable(int on);
+void svdp_profile_reset(void);
+int svdp_profile_read(int kind, double* total_ms, int64_t* launches, double* work);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SVDP_H */

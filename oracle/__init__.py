@@ -303,7 +303,8 @@ N_PARAMS = HID * N_FEAT + HID + HID * HID + HID + N_OUT * HID + N_OUT  # 4866
 
 def _features_from_norms(F, norms, m, n):
     r = [norms[k] / norms[k - 1] for k in range(1, 8)]
-    f = [np.log(F / r[6])] + [np.log(r[k] / r[k + 1]) for k in range(6)] + [np.log(m / n)]
+    f = ([np.log(F / r[6])] + [np.log(r[k] / r[k + 1]) for k in range(1, 6)]
+         + [np.log(n), np.log(m / n)])
     return np.array(f), r[6], F
 
 
@@ -312,8 +313,9 @@ def sketch_features(A, g):
 
     Power sequence y0 = g, y1 = A y0, y2 = A^T y1, ... alternating up to y7;
     r_k = |y_k| / |y_{k-1}| (lower bounds on sigma_max that rise towards it).
-    Features: log(|A|_F / r_7), log(r_k / r_{k+1}) for k = 1..6, log(m / n).
-    All are invariant to scaling A.  Returns (features, r_7, |A|_F).
+    Features: log(|A|_F / r_7), log(r_k / r_{k+1}) for k = 2..6, log(n),
+    log(m / n).  All are invariant to scaling A.  Returns (features, r_7,
+    |A|_F).
     """
     A = np.asarray(A, dtype=np.float64)
     m, n = A.shape

@@ -1,0 +1,949 @@
+// C-ABI entry points: argument checks, workspace carving and the host-side
+// orchestration of the kernels (no arithmetic of the method runs on the host
+// except the scalar CANS coefficient recursion).
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "common.hpp"
+#include "eigh.hpp"
+#include "kernels.hpp"
+#include "svdp.h"
+
+struct svdp_handle {
+  float* model = nullptr;  // device: SVDP_MODEL_FLOATS
+  bool has_model = false;
+  int* host_word = nullptr;  // pinned: counter read-back
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+svdp_status fail(svdp_status s, const char* msg) {
+  g_last_error = msg;
+  return s;
+}
+svdp_status hip_fail(hipError_t e, const char* where) {
+  g_last_error = std::string(where) + ": " + hipGetErrorString(e);
+  return SVDP_ERR_HIP;
+}
+#define HIPCHK(x, where)                      \
+  do {                                        \
+    hipError_t _e = (x);                      \
+    if (_e != hipSuccess) return hip_fail(_e, where); \
+  } while (0)
+
+// Bump allocator over the caller's workspace (null base = size query).
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(void* b) : base((char*)b) {}
+  template <class T>
+  T* take(size_t count) {
+    size_t bytes = std::max<size_t>(count * sizeof(T), 1);
+    size_t o = off;
+    off += (bytes + 255) / 256 * 256;
+    return base ? (T*)(base + o) : nullptr;
+  }
+  void* take_bytes(size_t bytes) { return take<char>(bytes); }
+};
+
+// ---------------------------------------------------------------- CANS tables
+
+// Degree-3 odd polynomial closest to 1 in max norm on [a, b]: the error
+// equioscillates at a, at the stationary point x*, and at b.
+void cans_poly(double a, double b, double& al, double& be, double& lo, double& hi) {
+  double s = a * a + a * b + b * b;
+  double xs = std::sqrt(s / 3.0);
+  be = -2.0 / (a * b * (a + b) + 2.0 * xs * xs * xs);
+  al = -be * s;
+  lo = al * a + be * a * a * a;
+  hi = al * xs + be * xs * xs * xs;
+}
+
+// smallest t whose `steps` optimal steps from [t, 1] land in [1-delta, 1+delta]
+double preprocess_t(double delta, int steps) {
+  auto err = [&](double t) {
+    double a = t, b = 1.0, al, be;
+    for (int k = 0; k < steps; ++k) cans_poly(a, b, al, be, a, b);
+    return std::max(1.0 - a, b - 1.0);
+  };
+  double lo = 1e-16, hi = 1.0;
+  for (int it = 0; it < 200; ++it) {
+    double mid = std::sqrt(lo * hi);
+    if (err(mid) <= delta) hi = mid;
+    else lo = mid;
+  }
+  return hi;
+}
+
+void table_conservative(double delta, int pre, int steps, double* tab, double* t_out) {
+  double t = preprocess_t(delta, pre);
+  double a = t, b = 1.0;
+  int k = 0;
+  for (; k < std::min(pre, steps); ++k) cans_poly(a, b, tab[2 * k], tab[2 * k + 1], a, b);
+  a = 1.0 - delta;
+  b = 1.0 + delta;
+  for (; k < steps; ++k) cans_poly(a, b, tab[2 * k], tab[2 * k + 1], a, b);
+  if (t_out) *t_out = t;
+}
+
+void table_interval(double lo, int steps, double* tab) {
+  double a = lo, b = 1.0;
+  for (int k = 0; k < steps; ++k) cans_poly(a, b, tab[2 * k], tab[2 * k + 1], a, b);
+}
+
+// ---------------------------------------------------------------- checks
+
+bool bad_shape(const svdp_params* p) {
+  return p->batch < 0 || p->n < 1 || p->m < p->n || p->batch > 65535 || p->m > (1 << 20) ||
+         p->n > 8192 || p->m * p->n > (int64_t)1 << 31;
+}
+bool bad_ld(int64_t ld, int64_t cols, int64_t stride, int64_t rows) {
+  return ld < cols || stride < 0 || (stride > 0 && stride < (rows - 1) * ld + cols);
+}
+svdp_status check_common(const svdp_params* p) {
+  if (!p) return fail(SVDP_ERR_INVALID_ARG, "null params");
+  if (bad_shape(p)) return fail(SVDP_ERR_SHAPE, "need batch >= 0, m >= n >= 1 (n <= 8192)");
+  if (p->precision != SVDP_PREC_FP32 && p->precision != SVDP_PREC_BF16)
+    return fail(SVDP_ERR_INVALID_ARG, "unknown precision");
+  if (p->bound < 0 || p->bound > 2) return fail(SVDP_ERR_INVALID_ARG, "unknown bound mode");
+  if (p->max_iters < 1 || p->max_iters > 64) return fail(SVDP_ERR_INVALID_ARG, "max_iters must be in [1, 64]");
+  if (p->pre_iters < 0 || p->pre_iters > p->max_iters) return fail(SVDP_ERR_INVALID_ARG, "bad pre_iters");
+  if (p->refine_steps < 0 || p->refine_steps > 8) return fail(SVDP_ERR_INVALID_ARG, "refine_steps must be in [0, 8]");
+  if (p->max_sweeps < 1 || p->max_sweeps > 100) return fail(SVDP_ERR_INVALID_ARG, "max_sweeps must be in [1, 100]");
+  if (p->inner_sweeps < 1 || p->inner_sweeps > 16) return fail(SVDP_ERR_INVALID_ARG, "inner_sweeps must be in [1, 16]");
+  if (p->fp64_sweeps < 0 || p->fp64_sweeps > 4) return fail(SVDP_ERR_INVALID_ARG, "fp64_sweeps must be in [0, 4]");
+  if (!(p->delta > 0 && p->delta < 1)) return fail(SVDP_ERR_INVALID_ARG, "delta must be in (0, 1)");
+  if (!(p->tol > 0)) return fail(SVDP_ERR_INVALID_ARG, "tol must be > 0");
+  if (p->eps_K < 0 || p->eps_R < 0 || p->eps_T < 0) return fail(SVDP_ERR_INVALID_ARG, "eps must be >= 0");
+  return SVDP_OK;
+}
+
+EighOpts eigh_opts(const svdp_params* p) {
+  EighOpts o;
+  o.inner_sweeps = p->inner_sweeps;
+  o.fp64_sweeps = p->fp64_sweeps;
+  o.fp64_inner = p->inner_sweeps;
+  o.tol = (float)p->jacobi_tol;
+  o.abs_tol = (float)p->jacobi_abs;
+  o.neg_tol = 1e-4f;
+  return o;
+}
+
+// ---------------------------------------------------------------- forward workspace
+
+struct FwdWs {
+  float *X0, *X1, *G;
+  void* eigh;
+  float *scale, *conv, *resid, *colsum, *rowmax, *fro2, *coef, *rcoef, *F, *aux, *mlpout, *nrm, *y0, *y1;
+  int *active, *where, *iters, *flags, *sweeps, *mask, *counter, *ksteps, *kmax;
+};
+
+FwdWs carve_fwd(void* base, const svdp_params* p, size_t* total) {
+  Carver c(base);
+  FwdWs w;
+  const size_t b = p->batch, m = p->m, n = p->n;
+  w.X0 = c.take<float>(b * m * n);
+  w.X1 = c.take<float>(b * m * n);
+  w.G = c.take<float>(b * n * n);
+  w.eigh = c.take_bytes(eigh_ws_bytes(b, n, p->max_sweeps));
+  w.scale = c.take<float>(b);
+  w.conv = c.take<float>(2 * b);
+  w.resid = c.take<float>(b);
+  w.colsum = c.take<float>(b * n);
+  w.rowmax = c.take<float>(b);
+  w.fro2 = c.take<float>(b);
+  w.coef = c.take<float>(b * 64 * 2);
+  w.rcoef = c.take<float>(64 * 2);
+  w.F = c.take<float>(b * 8);
+  w.aux = c.take<float>(b * 2);
+  w.mlpout = c.take<float>(b * 2);
+  w.nrm = c.take<float>(b * 8);
+  w.y0 = c.take<float>(b * m);
+  w.y1 = c.take<float>(b * m);
+  w.active = c.take<int>(b);
+  w.where = c.take<int>(b);
+  w.iters = c.take<int>(b);
+  w.flags = c.take<int>(b);
+  w.sweeps = c.take<int>(b);
+  w.mask = c.take<int>(b);
+  w.counter = c.take<int>(16);
+  w.ksteps = c.take<int>(b);
+  w.kmax = c.take<int>(16);
+  if (total) *total = c.off;
+  return w;
+}
+
+GemmArgs gemm_base(int M, int N, int K, int batch) {
+  GemmArgs g;
+  std::memset(&g, 0, sizeof(g));
+  g.M = M; g.N = N; g.K = K; g.batch = batch;
+  g.alpha = 1.f; g.beta = 0.f;
+  return g;
+}
+
+struct Ctx {
+  svdp_handle* h;
+  const svdp_params* p;
+  FwdWs w;
+  hipStream_t st;
+  int batch, m, n;
+  const float* A;
+  int64_t lda, sA;
+};
+
+svdp_status read_counter(Ctx& c, const int* dev, int* out) {
+  HIPCHK(hipMemcpyAsync(c.h->host_word, dev, sizeof(int), hipMemcpyDeviceToHost, c.st), "counter copy");
+  HIPCHK(hipStreamSynchronize(c.st), "counter sync");
+  *out = *c.h->host_word;
+  return SVDP_OK;
+}
+
+// One CANS step on buffers (Xc -> Xn): G = Xc^T Xc, Xn = alpha Xc + beta Xc G.
+hipError_t cans_step(Ctx& c, int prec, const void* Xc, void* Xn, int in_bf16, int out_bf16,
+                     const float* coef, int64_t coef_bstride, int kidx, const int* active,
+                     float* conv, int n_active = 0) {
+  const int m = c.m, n = c.n, B = c.batch;
+  GemmArgs g = gemm_base(n, n, m, B);
+  g.work_batch = n_active;
+  g.A = Xc; g.lda = n; g.sA = (int64_t)m * n;
+  g.B = Xc; g.ldb = n; g.sB = (int64_t)m * n;
+  g.C = c.w.G; g.ldc = n; g.sC = (int64_t)n * n;
+  g.sym = 1;
+  g.active = active;
+  g.in_bf16 = in_bf16;
+  g.out_bf16 = prec == PREC_BF16 ? 1 : 0;
+  hipError_t e = gemm_launch(g, prec, 1, 0, c.st);
+  if (e) return e;
+  GemmArgs u = gemm_base(m, n, n, B);
+  u.A = Xc; u.lda = n; u.sA = (int64_t)m * n;
+  // G is symmetric: read it as B^T (k-contiguous rows) for the BF16 kernel
+  u.B = c.w.G; u.ldb = n; u.sB = (int64_t)n * n;
+  u.C = Xn; u.ldc = n; u.sC = (int64_t)m * n;
+  u.Cin = Xc; u.ldcin = n; u.sCin = (int64_t)m * n; u.cin_bf16 = in_bf16;
+  u.coef = coef; u.coef_bstride = coef_bstride; u.coef_idx = kidx;
+  u.active = active;
+  u.work_batch = n_active;
+  u.conv = conv;
+  u.in_bf16 = in_bf16;
+  u.out_bf16 = out_bf16;
+  return gemm_launch(u, prec, 0, prec == PREC_BF16 ? 1 : 0, c.st);
+}
+
+// Conservative CANS in FP32 with per-matrix stopping (mask: matrices to run,
+// null = all): Algorithm 3 scaling, pre_iters preprocessing steps, then the
+// interval recursion from [1 - delta, 1 + delta] until the relative change is
+// below tol.  Leaves W of matrix b in X0 (where[b] = 0) or X1 (where[b] = 1).
+svdp_status conservative_fp32(Ctx& c, const int* mask) {
+  const svdp_params* p = c.p;
+  FwdWs& w = c.w;
+  const int B = c.batch, m = c.m, n = c.n;
+  HIPCHK(norms_launch(c.A, c.lda, c.sA, B, m, n, w.colsum, w.rowmax, w.fro2, w.flags, mask, c.st), "norms");
+  HIPCHK(ns_scale_launch(w.colsum, w.rowmax, B, n, w.scale, mask, c.st), "scale");
+  HIPCHK(scale_copy_launch(c.A, c.lda, c.sA, B, m, n, w.scale, w.X0, 0, mask, c.st), "normalise");
+  double tab[128];
+  table_conservative(p->delta, p->pre_iters, p->max_iters, tab, nullptr);
+  HIPCHK(set_coef_launch(w.coef, tab, p->max_iters, c.st), "coef");
+  if (mask) HIPCHK(copy_i32(w.active, mask, B, c.st), "active");
+  else HIPCHK(fill_i32(w.active, 1, B, c.st), "active");
+  HIPCHK(fill_masked_launch(w.where, 0, B, mask, c.st), "where");
+  HIPCHK(fill_f32(w.conv, 0.f, 2 * B, c.st), "conv");
+  int remaining = B;
+  if (mask) {
+    HIPCHK(count_mask_launch(B, mask, w.counter, c.st), "count");
+    svdp_status s0 = read_counter(c, w.counter, &remaining);
+    if (s0) return s0;
+  }
+  for (int k = 0; k < p->max_iters; ++k) {
+    const float* Xc = (k & 1) ? w.X1 : w.X0;
+    float* Xn = (k & 1) ? w.X0 : w.X1;
+    HIPCHK(cans_step(c, PREC_F32, Xc, Xn, 0, 0, w.coef, 0, k, w.active, w.conv, remaining), "cans step");
+    HIPCHK(cans_check_launch(B, w.conv, (float)p->tol, k, w.active, w.where, w.iters, w.flags, w.counter, c.st),
+           "cans check");
+    // poll the device for stragglers once the schedule can have converged
+    if (k >= p->pre_iters + 4 || k == p->max_iters - 1) {
+      svdp_status s = read_counter(c, w.counter, &remaining);
+      if (s) return s;
+      if (remaining == 0) break;
+    }
+  }
+  if (remaining > 0)
+    HIPCHK(or_flags_launch(B, w.flags, SVDP_FLAG_NOT_CONVERGED, w.active, c.st), "flags");
+  return SVDP_OK;
+}
+
+// Bounded path: learned (sketch features -> MLP) or user bounds give a
+// per-matrix scale and interval [lo, 1]; K interval-optimal steps (batch
+// maximum of the per-matrix counts to the BF16 hand-off) in `prec`, then
+// refine_steps FP32 steps.  Result in X0 / X1 with a uniform where[].
+svdp_status bounded(Ctx& c) {
+  const svdp_params* p = c.p;
+  FwdWs& w = c.w;
+  const int B = c.batch, m = c.m, n = c.n;
+  const int kcap = std::min(p->max_iters, 64);
+  if (p->bound == SVDP_BOUND_LEARNED) {
+    // features: |A|_F^2 via the row pass, then the alternating power sequence
+    HIPCHK(norms_launch(c.A, c.lda, c.sA, B, m, n, w.colsum, w.rowmax, w.fro2, w.flags, nullptr, c.st), "norms");
+    HIPCHK(vnorm_launch(p->probe, n, B, n, w.nrm, 0, c.st), "probe norm");
+    const float* x = p->probe;
+    int64_t sx = n;
+    for (int k = 1; k <= 7; ++k) {
+      float* y = (k & 1) ? w.y0 : w.y1;
+      int trans = (k & 1) ? 0 : 1;
+      int len = trans ? n : m;
+      HIPCHK(matvec_launch(c.A, c.lda, c.sA, B, m, n, x, sx, y, m, trans, c.st), "matvec");
+      HIPCHK(vnorm_launch(y, m, B, len, w.nrm, k, c.st), "vnorm");
+      x = y;
+      sx = m;
+    }
+    HIPCHK(features_launch(w.fro2, w.nrm, B, m, n, w.F, w.aux, c.st), "features");
+    HIPCHK(mlp_fwd_launch(c.h->model, c.h->model + SVDP_MLP_PARAMS, c.h->model + SVDP_MLP_PARAMS + 8, w.F, B,
+                          w.mlpout, nullptr, c.st), "mlp");
+    HIPCHK(bounds_launch(B, 0, w.mlpout, w.aux, nullptr, p->margin_max, p->margin_min, p->bf16_handoff,
+                         p->bf16_from, kcap, w.scale, w.coef, w.ksteps, w.kmax, nullptr, c.st), "bounds");
+  } else {
+    HIPCHK(bounds_launch(B, 1, nullptr, nullptr, p->user_bounds, p->margin_max, p->margin_min, p->bf16_handoff,
+                         p->bf16_from, kcap, w.scale, w.coef, w.ksteps, w.kmax, nullptr, c.st), "bounds");
+  }
+  // kmax[0] = steps to the hand-off, kmax[1] = FP32 steps before BF16 (batch maxima)
+  int K = 0, K1 = 0;
+  {
+    HIPCHK(hipMemcpyAsync(c.h->host_word, w.kmax, 2 * sizeof(int), hipMemcpyDeviceToHost, c.st), "kmax copy");
+    HIPCHK(hipStreamSynchronize(c.st), "kmax sync");
+    K = c.h->host_word[0];
+    K1 = c.h->host_word[1];
+  }
+  K = std::max(1, std::min(K, kcap));
+  const int bf16 = p->precision == SVDP_PREC_BF16;
+  K1 = bf16 ? std::max(0, std::min(K1, K)) : K;
+  // steps [0, K1) in FP32 while small singular values are still small
+  // (BF16 rounding would rotate their singular vectors), [K1, K) in BF16
+  HIPCHK(scale_copy_launch(c.A, c.lda, c.sA, B, m, n, w.scale, w.X0, K1 == 0 ? 1 : 0, nullptr, c.st), "normalise");
+  for (int k = 0; k < K; ++k) {
+    const void* Xc = (k & 1) ? w.X1 : w.X0;
+    void* Xn = (k & 1) ? w.X0 : w.X1;
+    const int prec = k < K1 ? PREC_F32 : PREC_BF16;
+    const int in_bf = k >= K1;
+    const int out_bf = (k + 1 >= K1) && (k + 1 < K);
+    HIPCHK(cans_step(c, prec, Xc, Xn, in_bf, out_bf, w.coef, kcap, k, nullptr, nullptr), "cans step");
+  }
+  // FP32 refinement: interval recursion from [1 - h, 1 + h]
+  const int R = p->refine_steps;
+  if (R > 0) {
+    double tab[128];
+    double h = std::min(std::max(p->bf16_handoff, 1e-8), 0.5);
+    table_interval(1.0 - h, R, tab);
+    float* tcoef = w.rcoef;
+    HIPCHK(set_coef_launch(tcoef, tab, R, c.st), "refine coef");
+    for (int r = 0; r < R; ++r) {
+      const int k = K + r;
+      const float* Xc = (k & 1) ? w.X1 : w.X0;
+      float* Xn = (k & 1) ? w.X0 : w.X1;
+      HIPCHK(cans_step(c, PREC_F32, Xc, Xn, 0, 0, tcoef, 0, r, nullptr, nullptr), "refine step");
+    }
+  }
+  HIPCHK(fill_i32(w.where, (K + R) & 1, B, c.st), "where");
+  HIPCHK(fill_i32(w.iters, K + R, B, c.st), "iters");
+  return SVDP_OK;
+}
+
+// residual |W^T W - I|_F / sqrt(n) of the final iterate (Gram into G)
+svdp_status final_residual(Ctx& c, const int* mask) {
+  FwdWs& w = c.w;
+  const int B = c.batch, m = c.m, n = c.n;
+  GemmArgs g = gemm_base(n, n, m, B);
+  g.A = w.X0; g.A_alt = w.X1; g.a_sel = w.where; g.lda = n; g.sA = (int64_t)m * n;
+  g.B = w.X0; g.B_alt = w.X1; g.b_sel = w.where; g.ldb = n; g.sB = (int64_t)m * n;
+  g.C = w.G; g.ldc = n; g.sC = (int64_t)n * n;
+  g.sym = 1;
+  g.active = mask;
+  HIPCHK(gemm_launch(g, PREC_F32, 1, 0, c.st), "W^T W");
+  HIPCHK(residual_launch(w.G, 0, B, n, w.resid, mask, c.st), "residual");
+  return SVDP_OK;
+}
+
+// H = W^T A (full; the eigensolver and the polar output symmetrise it) into G
+svdp_status form_h(Ctx& c, const int* mask) {
+  FwdWs& w = c.w;
+  const int B = c.batch, m = c.m, n = c.n;
+  GemmArgs g = gemm_base(n, n, m, B);
+  g.A = w.X0; g.A_alt = w.X1; g.a_sel = w.where; g.lda = n; g.sA = (int64_t)m * n;
+  g.B = c.A; g.ldb = c.lda; g.sB = c.sA;
+  g.C = w.G; g.ldc = n; g.sC = (int64_t)n * n;
+  g.active = mask;
+  HIPCHK(gemm_launch(g, PREC_F32, 1, 0, c.st), "H = W^T A");
+  return SVDP_OK;
+}
+
+// CANS polar factor of every matrix (Algorithm 1 steps 1-3).
+svdp_status polar_core(Ctx& c) {
+  const svdp_params* p = c.p;
+  FwdWs& w = c.w;
+  const int B = c.batch;
+  HIPCHK(fill_i32(w.flags, 0, B, c.st), "flags");
+  HIPCHK(fill_i32(w.iters, 0, B, c.st), "iters");
+  HIPCHK(fill_i32(w.sweeps, 0, B, c.st), "sweeps");
+  HIPCHK(fill_f32(w.resid, 0.f, B, c.st), "resid");
+  svdp_status s = p->bound == SVDP_BOUND_CONSERVATIVE ? conservative_fp32(c, nullptr) : bounded(c);
+  if (s) return s;
+  return final_residual(c, nullptr);
+}
+
+// H, eigh(H), U = W V with eigenvalue signs, column-norm test (Algorithm 1
+// steps 4-7) for every matrix or the masked ones.
+svdp_status svd_tail(Ctx& c, float* U, int64_t ldu, int64_t sU, float* S, int64_t sS, float* V,
+                     int64_t ldv, int64_t sV, const int* mask) {
+  const svdp_params* p = c.p;
+  FwdWs& w = c.w;
+  const int B = c.batch, m = c.m, n = c.n;
+  svdp_status s = form_h(c, mask);
+  if (s) return s;
+  EighWs e = eigh_ws_carve(w.eigh, B, n, p->max_sweeps);
+  HIPCHK(eigh_run(e, w.G, n, (int64_t)n * n, 1, eigh_opts(p), S, sS, V, ldv, sV, w.sweeps, w.flags,
+                  c.h->host_word, mask, c.st), "eigh");
+  GemmArgs g = gemm_base(m, n, n, B);
+  g.A = w.X0; g.A_alt = w.X1; g.a_sel = w.where; g.lda = n; g.sA = (int64_t)m * n;
+  g.B = V; g.ldb = ldv; g.sB = sV;
+  g.C = U; g.ldc = ldu; g.sC = sU;
+  g.colscale = e.sgn; g.cs_stride = n;
+  g.active = mask;
+  HIPCHK(gemm_launch(g, PREC_F32, 0, 0, c.st), "U = W V");
+  HIPCHK(colnorm_check_launch(U, ldu, sU, B, m, n, w.colsum, (float)p->eps_qr, w.flags, mask, c.st), "colnorm");
+  return SVDP_OK;
+}
+
+svdp_status check_model(svdp_handle* h, const svdp_params* p) {
+  if (p->bound == SVDP_BOUND_LEARNED) {
+    if (!h->has_model) return fail(SVDP_ERR_NO_MODEL, "learned bounds need svdp_set_model first");
+    if (!p->probe) return fail(SVDP_ERR_INVALID_ARG, "learned bounds need params.probe");
+  }
+  if (p->bound == SVDP_BOUND_USER && !p->user_bounds)
+    return fail(SVDP_ERR_INVALID_ARG, "user bounds need params.user_bounds");
+  return SVDP_OK;
+}
+
+// Fallback of the bounded paths: matrices with a residual above refine_tol,
+// a negative eigenvalue of H or non-finite values rerun conservative CANS.
+svdp_status fallback_mask(Ctx& c, int* count) {
+  FwdWs& w = c.w;
+  HIPCHK(fallback_mask_launch(c.batch, w.flags, SVDP_FLAG_NEG_EIGENVALUE | SVDP_FLAG_NONFINITE, w.resid,
+                              (float)c.p->refine_tol, w.mask, w.counter, c.st), "fallback mask");
+  return read_counter(c, w.counter, count);
+}
+
+}  // namespace
+
+// =====================================================================
+// C ABI
+// =====================================================================
+
+extern "C" {
+
+void svdp_default_params(svdp_params* p, int64_t batch, int64_t m, int64_t n) {
+  std::memset(p, 0, sizeof(*p));
+  p->batch = batch; p->m = m; p->n = n;
+  p->precision = SVDP_PREC_FP32;
+  p->bound = SVDP_BOUND_CONSERVATIVE;
+  p->max_iters = 50;
+  p->pre_iters = 2;
+  p->refine_steps = 2;
+  p->max_sweeps = 20;
+  p->inner_sweeps = 1;
+  p->fp64_sweeps = 1;
+  p->delta = 0.99;
+  p->tol = 1e-5;
+  p->eps_qr = 1e-5;
+  p->bf16_handoff = 1e-2;
+  p->refine_tol = 1e-2;
+  p->jacobi_tol = 1e-3;
+  p->jacobi_abs = 1e-9;
+  p->bf16_from = 0.1;
+  p->margin_max = 1.1;
+  p->margin_min = 0.5;
+}
+
+const char* svdp_status_string(svdp_status s) {
+  switch (s) {
+    case SVDP_OK: return "ok";
+    case SVDP_ERR_INVALID_ARG: return "invalid argument";
+    case SVDP_ERR_SHAPE: return "bad shape";
+    case SVDP_ERR_WORKSPACE: return "workspace too small";
+    case SVDP_ERR_HIP: return "HIP error";
+    case SVDP_ERR_NO_MODEL: return "no model loaded";
+  }
+  return "unknown status";
+}
+
+const char* svdp_last_error(void) { return g_last_error.c_str(); }
+
+svdp_status svdp_create(svdp_handle** out) {
+  if (!out) return fail(SVDP_ERR_INVALID_ARG, "null handle pointer");
+  svdp_handle* h = new svdp_handle();
+  hipError_t e = hipMalloc((void**)&h->model, SVDP_MODEL_FLOATS * sizeof(float));
+  if (e == hipSuccess) e = hipHostMalloc((void**)&h->host_word, 64, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    if (h->model) (void)hipFree(h->model);
+    delete h;
+    return hip_fail(e, "svdp_create");
+  }
+  *out = h;
+  return SVDP_OK;
+}
+
+svdp_status svdp_destroy(svdp_handle* h) {
+  if (!h) return SVDP_OK;
+  if (h->model) (void)hipFree(h->model);
+  if (h->host_word) (void)hipHostFree(h->host_word);
+  delete h;
+  return SVDP_OK;
+}
+
+svdp_status svdp_set_model(svdp_handle* h, const float* host_model) {
+  if (!h || !host_model) return fail(SVDP_ERR_INVALID_ARG, "null handle or model");
+  HIPCHK(hipMemcpy(h->model, host_model, SVDP_MODEL_FLOATS * sizeof(float), hipMemcpyHostToDevice), "set_model");
+  h->has_model = true;
+  return SVDP_OK;
+}
+
+static size_t bwd_bytes(const svdp_params* p, int polar) {
+  Carver c(nullptr);
+  const size_t b = p->batch, m = p->m, n = p->n;
+  c.take<float>(b * n * n);  // X1 (Ahat / V^T dH V)
+  c.take<float>(b * n * n);  // X2 (P / (MV)^T dW V)
+  c.take<float>(b * n * n);  // Y
+  c.take<float>(b * n * n);  // T1
+  c.take<float>(b * m * n);  // Z
+  c.take<float>(b * n);      // D
+  if (polar) {
+    c.take<float>(b * m * n);  // MV
+    c.take<float>(b * m * n);  // dW V
+    c.take<float>(b * n);      // S (own eigh)
+    c.take<float>(b * n * n);  // V (own eigh)
+    c.take<int>(b);            // sweeps
+    c.take<int>(b);            // flags
+    c.take_bytes(eigh_ws_bytes(b, n, p->max_sweeps));
+  }
+  return c.off;
+}
+
+svdp_status svdp_workspace_size(const svdp_params* p, int32_t op, size_t* bytes) {
+  if (!bytes) return fail(SVDP_ERR_INVALID_ARG, "null bytes");
+  svdp_status s = check_common(p);
+  if (s) return s;
+  size_t total = 0;
+  switch (op) {
+    case SVDP_OP_SVD_FWD:
+    case SVDP_OP_POLAR_FWD:
+    case SVDP_OP_FEATURES: carve_fwd(nullptr, p, &total); break;
+    case SVDP_OP_SVD_BWD: total = bwd_bytes(p, 0); break;
+    case SVDP_OP_POLAR_BWD: total = bwd_bytes(p, 1); break;
+    case SVDP_OP_EIGH: {
+      Carver c(nullptr);
+      c.take<int>(p->batch);
+      c.take<int>(p->batch);
+      c.take_bytes(eigh_ws_bytes(p->batch, p->n, p->max_sweeps));
+      total = c.off;
+      break;
+    }
+    default: return fail(SVDP_ERR_INVALID_ARG, "unknown op");
+  }
+  *bytes = total;
+  return SVDP_OK;
+}
+
+#define REQ(ptr) \
+  if (!(ptr)) return fail(SVDP_ERR_INVALID_ARG, "null pointer argument: " #ptr)
+#define LDCHK(ld, cols, stride, rows) \
+  if (bad_ld(ld, cols, stride, rows)) return fail(SVDP_ERR_INVALID_ARG, "leading dimension or stride too small: " #ld)
+
+svdp_status svd_polar_fwd(svdp_handle* h, const svdp_params* p, const float* A, int64_t lda, int64_t sA,
+                          float* U, int64_t ldu, int64_t sU, float* S, int64_t sS, float* V, int64_t ldv,
+                          int64_t sV, svdp_info* info, void* ws, size_t ws_bytes, void* stream) {
+  REQ(h);
+  svdp_status s = check_common(p);
+  if (s) return s;
+  if ((s = check_model(h, p))) return s;
+  if (p->batch == 0) return SVDP_OK;
+  REQ(A); REQ(U); REQ(S); REQ(V);
+  LDCHK(lda, p->n, p->batch > 1 ? sA : 0, p->m);
+  LDCHK(ldu, p->n, p->batch > 1 ? sU : 0, p->m);
+  LDCHK(ldv, p->n, p->batch > 1 ? sV : 0, p->n);
+  if (p->batch > 1 && sS < p->n) return fail(SVDP_ERR_INVALID_ARG, "sS < n");
+  size_t need = 0;
+  carve_fwd(nullptr, p, &need);
+  if (!ws || ws_bytes < need) return fail(SVDP_ERR_WORKSPACE, "workspace too small");
+  Ctx c{h, p, carve_fwd(ws, p, nullptr), (hipStream_t)stream, (int)p->batch, (int)p->m, (int)p->n, A, lda, sA};
+  if ((s = polar_core(c))) return s;
+  if ((s = svd_tail(c, U, ldu, sU, S, sS, V, ldv, sV, nullptr))) return s;
+  if (p->bound != SVDP_BOUND_CONSERVATIVE) {
+    int cnt = 0;
+    if ((s = fallback_mask(c, &cnt))) return s;
+    if (cnt > 0) {
+      const int* mk = c.w.mask;
+      if ((s = conservative_fp32(c, mk))) return s;
+      if ((s = final_residual(c, mk))) return s;
+      if ((s = svd_tail(c, U, ldu, sU, S, sS, V, ldv, sV, mk))) return s;
+      HIPCHK(or_flags_launch(c.batch, c.w.flags, SVDP_FLAG_FALLBACK_USED, mk, c.st), "flags");
+    }
+  }
+  if (info) HIPCHK(info_pack_launch(c.batch, c.w.iters, c.w.sweeps, c.w.flags, c.w.resid, info, nullptr, c.st), "info");
+  return SVDP_OK;
+}
+
+svdp_status polar_fwd(svdp_handle* h, const svdp_params* p, const float* A, int64_t lda, int64_t sA, float* W,
+                      int64_t ldw, int64_t sW, float* H, int64_t ldh, int64_t sH, float* S_cache, int64_t sS,
+                      float* V_cache, int64_t ldv, int64_t sV, svdp_info* info, void* ws, size_t ws_bytes,
+                      void* stream) {
+  REQ(h);
+  svdp_status s = check_common(p);
+  if (s) return s;
+  if ((s = check_model(h, p))) return s;
+  if (p->batch == 0) return SVDP_OK;
+  REQ(A); REQ(W); REQ(H);
+  if ((S_cache == nullptr) != (V_cache == nullptr))
+    return fail(SVDP_ERR_INVALID_ARG, "S_cache and V_cache must both be given or both null");
+  LDCHK(lda, p->n, p->batch > 1 ? sA : 0, p->m);
+  LDCHK(ldw, p->n, p->batch > 1 ? sW : 0, p->m);
+  LDCHK(ldh, p->n, p->batch > 1 ? sH : 0, p->n);
+  if (V_cache) LDCHK(ldv, p->n, p->batch > 1 ? sV : 0, p->n);
+  size_t need = 0;
+  carve_fwd(nullptr, p, &need);
+  if (!ws || ws_bytes < need) return fail(SVDP_ERR_WORKSPACE, "workspace too small");
+  Ctx c{h, p, carve_fwd(ws, p, nullptr), (hipStream_t)stream, (int)p->batch, (int)p->m, (int)p->n, A, lda, sA};
+  const int B = c.batch, m = c.m, n = c.n;
+  if ((s = polar_core(c))) return s;
+  auto tail = [&](const int* mask) -> svdp_status {
+    svdp_status s2 = form_h(c, mask);
+    if (s2) return s2;
+    if (V_cache) {
+      EighWs e = eigh_ws_carve(c.w.eigh, B, n, p->max_sweeps);
+      HIPCHK(eigh_run(e, c.w.G, n, (int64_t)n * n, 0, eigh_opts(p), S_cache, sS, V_cache, ldv, sV, c.w.sweeps,
+                      c.w.flags, h->host_word, mask, c.st), "eigh");
+    }
+    return SVDP_OK;
+  };
+  if ((s = tail(nullptr))) return s;
+  if (p->bound != SVDP_BOUND_CONSERVATIVE) {
+    int cnt = 0;
+    if ((s = fallback_mask(c, &cnt))) return s;
+    if (cnt > 0) {
+      const int* mk = c.w.mask;
+      if ((s = conservative_fp32(c, mk))) return s;
+      if ((s = final_residual(c, mk))) return s;
+      if ((s = tail(mk))) return s;
+      HIPCHK(or_flags_launch(B, c.w.flags, SVDP_FLAG_FALLBACK_USED, mk, c.st), "flags");
+    }
+  }
+  HIPCHK(symmetrize_launch(c.w.G, B, n, H, ldh, sH, c.st), "H out");
+  HIPCHK(copy_launch(c.w.X0, n, (int64_t)m * n, c.w.where, c.w.X1, W, ldw, sW, B, m, n, c.st), "W out");
+  if (info) HIPCHK(info_pack_launch(B, c.w.iters, c.w.sweeps, c.w.flags, c.w.resid, info, nullptr, c.st), "info");
+  return SVDP_OK;
+}
+
+svdp_status svd_polar_bwd(svdp_handle* h, const svdp_params* p, const float* U, int64_t ldu, int64_t sU,
+                          const float* S, int64_t sS, const float* V, int64_t ldv, int64_t sV, const float* dU,
+                          int64_t lddu, int64_t sdU, const float* dS, int64_t sdS, const float* dV,
+                          int64_t lddv, int64_t sdV, float* dA, int64_t ldda, int64_t sdA, void* ws,
+                          size_t ws_bytes, void* stream) {
+  REQ(h);
+  svdp_status s = check_common(p);
+  if (s) return s;
+  if (p->batch == 0) return SVDP_OK;
+  REQ(U); REQ(S); REQ(V); REQ(dA);
+  const int B = (int)p->batch, m = (int)p->m, n = (int)p->n;
+  LDCHK(ldu, n, B > 1 ? sU : 0, m);
+  LDCHK(ldv, n, B > 1 ? sV : 0, n);
+  LDCHK(ldda, n, B > 1 ? sdA : 0, m);
+  if (dU) LDCHK(lddu, n, B > 1 ? sdU : 0, m);
+  if (dV) LDCHK(lddv, n, B > 1 ? sdV : 0, n);
+  if (!ws || ws_bytes < bwd_bytes(p, 0)) return fail(SVDP_ERR_WORKSPACE, "workspace too small");
+  hipStream_t st = (hipStream_t)stream;
+  Carver c(ws);
+  float* X1 = c.take<float>((size_t)B * n * n);
+  float* X2 = c.take<float>((size_t)B * n * n);
+  float* Y = c.take<float>((size_t)B * n * n);
+  c.take<float>((size_t)B * n * n);
+  float* Z = c.take<float>((size_t)B * m * n);
+  float* D = c.take<float>((size_t)B * n);
+  if (dU) {  // Ahat = U^T dU
+    GemmArgs g = gemm_base(n, n, m, B);
+    g.A = U; g.lda = ldu; g.sA = sU;
+    g.B = dU; g.ldb = lddu; g.sB = sdU;
+    g.C = X1; g.ldc = n; g.sC = (int64_t)n * n;
+    HIPCHK(gemm_launch(g, PREC_F32, 1, 0, st), "U^T dU");
+  }
+  if (dV) {  // P = V^T dV
+    GemmArgs g = gemm_base(n, n, n, B);
+    g.A = V; g.lda = ldv; g.sA = sV;
+    g.B = dV; g.ldb = lddv; g.sB = sdV;
+    g.C = X2; g.ldc = n; g.sC = (int64_t)n * n;
+    HIPCHK(gemm_launch(g, PREC_F32, 1, 0, st), "V^T dV");
+  }
+  HIPCHK(dvec_launch(S, sS, B, n, p->eps_R, D, st), "D");
+  HIPCHK(sylvester_launch(0, dU ? X1 : nullptr, dV ? X2 : nullptr, S, sS, dS, sdS, D, B, n, p->eps_K, p->eps_T, Y,
+                          st), "sylvester");
+  {  // Z = 2 U (S Y) + dU diag(D)
+    GemmArgs g = gemm_base(m, n, n, B);
+    g.A = U; g.lda = ldu; g.sA = sU;
+    g.B = Y; g.ldb = n; g.sB = (int64_t)n * n;
+    g.C = Z; g.ldc = n; g.sC = (int64_t)m * n;
+    g.alpha = 2.f;
+    if (dU) {
+      g.Cin = dU; g.ldcin = lddu; g.sCin = sdU; g.beta = 1.f;
+      g.colscale_in = D; g.csin_stride = n;
+    }
+    HIPCHK(gemm_launch(g, PREC_F32, 0, 0, st), "Z");
+  }
+  {  // dA = Z V^T
+    GemmArgs g = gemm_base(m, n, n, B);
+    g.A = Z; g.lda = n; g.sA = (int64_t)m * n;
+    g.B = V; g.ldb = ldv; g.sB = sV;
+    g.C = dA; g.ldc = ldda; g.sC = sdA;
+    HIPCHK(gemm_launch(g, PREC_F32, 0, 1, st), "Z V^T");
+  }
+  return SVDP_OK;
+}
+
+svdp_status polar_bwd(svdp_handle* h, const svdp_params* p, const float* A, int64_t lda, int64_t sA,
+                      const float* H, int64_t ldh, int64_t sH, const float* S_cache, int64_t sS,
+                      const float* V_cache, int64_t ldv, int64_t sV, const float* dW, int64_t lddw,
+                      int64_t sdW, const float* dH, int64_t lddh, int64_t sdH, float* dA, int64_t ldda,
+                      int64_t sdA, void* ws, size_t ws_bytes, void* stream) {
+  REQ(h);
+  svdp_status s = check_common(p);
+  if (s) return s;
+  if (p->batch == 0) return SVDP_OK;
+  REQ(A); REQ(dA);
+  if ((S_cache == nullptr) != (V_cache == nullptr))
+    return fail(SVDP_ERR_INVALID_ARG, "S_cache and V_cache must both be given or both null");
+  if (!V_cache) REQ(H);
+  const int B = (int)p->batch, m = (int)p->m, n = (int)p->n;
+  LDCHK(lda, n, B > 1 ? sA : 0, m);
+  LDCHK(ldda, n, B > 1 ? sdA : 0, m);
+  if (H) LDCHK(ldh, n, B > 1 ? sH : 0, n);
+  if (V_cache) LDCHK(ldv, n, B > 1 ? sV : 0, n);
+  if (dW) LDCHK(lddw, n, B > 1 ? sdW : 0, m);
+  if (dH) LDCHK(lddh, n, B > 1 ? sdH : 0, n);
+  if (!ws || ws_bytes < bwd_bytes(p, 1)) return fail(SVDP_ERR_WORKSPACE, "workspace too small");
+  hipStream_t st = (hipStream_t)stream;
+  Carver c(ws);
+  float* X1 = c.take<float>((size_t)B * n * n);
+  float* X2 = c.take<float>((size_t)B * n * n);
+  float* Y = c.take<float>((size_t)B * n * n);
+  float* T1 = c.take<float>((size_t)B * n * n);
+  float* Z = c.take<float>((size_t)B * m * n);
+  float* D = c.take<float>((size_t)B * n);
+  float* MV = c.take<float>((size_t)B * m * n);
+  float* WV = c.take<float>((size_t)B * m * n);
+  float* Sown = c.take<float>((size_t)B * n);
+  float* Vown = c.take<float>((size_t)B * n * n);
+  int* sweeps = c.take<int>(B);
+  int* flags = c.take<int>(B);
+  void* ews = c.take_bytes(eigh_ws_bytes(B, n, p->max_sweeps));
+  const float* Sx = S_cache;
+  const float* Vx = V_cache;
+  int64_t sSx = sS, ldvx = ldv, sVx = sV;
+  if (!V_cache) {  // Algorithm 2, step 1: EVD of H
+    EighWs e = eigh_ws_carve(ews, B, n, p->max_sweeps);
+    HIPCHK(fill_i32(flags, 0, B, st), "flags");
+    HIPCHK(eigh_run(e, H, ldh, sH, 0, eigh_opts(p), Sown, n, Vown, n, (int64_t)n * n, sweeps, flags, h->host_word,
+                    nullptr, st), "eigh");
+    Sx = Sown; Vx = Vown; sSx = n; ldvx = n; sVx = (int64_t)n * n;
+  }
+  {  // MV = A V
+    GemmArgs g = gemm_base(m, n, n, B);
+    g.A = A; g.lda = lda; g.sA = sA;
+    g.B = Vx; g.ldb = ldvx; g.sB = sVx;
+    g.C = MV; g.ldc = n; g.sC = (int64_t)m * n;
+    HIPCHK(gemm_launch(g, PREC_F32, 0, 0, st), "A V");
+  }
+  if (dW) {
+    GemmArgs g = gemm_base(m, n, n, B);  // dW V
+    g.A = dW; g.lda = lddw; g.sA = sdW;
+    g.B = Vx; g.ldb = ldvx; g.sB = sVx;
+    g.C = WV; g.ldc = n; g.sC = (int64_t)m * n;
+    HIPCHK(gemm_launch(g, PREC_F32, 0, 0, st), "dW V");
+    GemmArgs q = gemm_base(n, n, m, B);  // (A V)^T (dW V)
+    q.A = MV; q.lda = n; q.sA = (int64_t)m * n;
+    q.B = WV; q.ldb = n; q.sB = (int64_t)m * n;
+    q.C = X2; q.ldc = n; q.sC = (int64_t)n * n;
+    HIPCHK(gemm_launch(q, PREC_F32, 1, 0, st), "(AV)^T dW V");
+  }
+  if (dH) {
+    GemmArgs g = gemm_base(n, n, n, B);  // V^T dH
+    g.A = Vx; g.lda = ldvx; g.sA = sVx;
+    g.B = dH; g.ldb = lddh; g.sB = sdH;
+    g.C = T1; g.ldc = n; g.sC = (int64_t)n * n;
+    HIPCHK(gemm_launch(g, PREC_F32, 1, 0, st), "V^T dH");
+    GemmArgs q = gemm_base(n, n, n, B);  // (V^T dH) V
+    q.A = T1; q.lda = n; q.sA = (int64_t)n * n;
+    q.B = Vx; q.ldb = ldvx; q.sB = sVx;
+    q.C = X1; q.ldc = n; q.sC = (int64_t)n * n;
+    HIPCHK(gemm_launch(q, PREC_F32, 0, 0, st), "V^T dH V");
+  }
+  HIPCHK(dvec_launch(Sx, sSx, B, n, p->eps_R, D, st), "D");
+  HIPCHK(sylvester_launch(1, dH ? X1 : nullptr, dW ? X2 : nullptr, Sx, sSx, nullptr, 0, D, B, n, p->eps_K,
+                          p->eps_T, Y, st), "sylvester");
+  {  // Z = 2 (A V) Xt + (dW V) diag(D)
+    GemmArgs g = gemm_base(m, n, n, B);
+    g.A = MV; g.lda = n; g.sA = (int64_t)m * n;
+    g.B = Y; g.ldb = n; g.sB = (int64_t)n * n;
+    g.C = Z; g.ldc = n; g.sC = (int64_t)m * n;
+    g.alpha = 2.f;
+    if (dW) {
+      g.Cin = WV; g.ldcin = n; g.sCin = (int64_t)m * n; g.beta = 1.f;
+      g.colscale_in = D; g.csin_stride = n;
+    }
+    HIPCHK(gemm_launch(g, PREC_F32, 0, 0, st), "Z");
+  }
+  {  // dA = Z V^T
+    GemmArgs g = gemm_base(m, n, n, B);
+    g.A = Z; g.lda = n; g.sA = (int64_t)m * n;
+    g.B = Vx; g.ldb = ldvx; g.sB = sVx;
+    g.C = dA; g.ldc = ldda; g.sC = sdA;
+    HIPCHK(gemm_launch(g, PREC_F32, 0, 1, st), "Z V^T");
+  }
+  return SVDP_OK;
+}
+
+svdp_status svdp_eigh(svdp_handle* h, const svdp_params* p, const float* H, int64_t ldh, int64_t sH, float* lam,
+                      int64_t slam, float* V, int64_t ldv, int64_t sV, svdp_info* info, void* ws, size_t ws_bytes,
+                      void* stream) {
+  REQ(h);
+  svdp_status s = check_common(p);
+  if (s) return s;
+  if (p->batch == 0) return SVDP_OK;
+  REQ(H); REQ(lam); REQ(V);
+  const int B = (int)p->batch, n = (int)p->n;
+  LDCHK(ldh, n, B > 1 ? sH : 0, n);
+  LDCHK(ldv, n, B > 1 ? sV : 0, n);
+  if (B > 1 && slam < n) return fail(SVDP_ERR_INVALID_ARG, "slam < n");
+  size_t need = 0;
+  svdp_workspace_size(p, SVDP_OP_EIGH, &need);
+  if (!ws || ws_bytes < need) return fail(SVDP_ERR_WORKSPACE, "workspace too small");
+  hipStream_t st = (hipStream_t)stream;
+  Carver c(ws);
+  int* sweeps = c.take<int>(B);
+  int* flags = c.take<int>(B);
+  void* ews = c.take_bytes(eigh_ws_bytes(B, n, p->max_sweeps));
+  EighWs e = eigh_ws_carve(ews, B, n, p->max_sweeps);
+  HIPCHK(fill_i32(flags, 0, B, st), "flags");
+  HIPCHK(fill_i32(sweeps, 0, B, st), "sweeps");
+  HIPCHK(eigh_run(e, H, ldh, sH, 0, eigh_opts(p), lam, slam, V, ldv, sV, sweeps, flags, h->host_word, nullptr, st),
+         "eigh");
+  if (info) HIPCHK(info_pack_launch(B, nullptr, sweeps, flags, nullptr, info, nullptr, st), "info");
+  return SVDP_OK;
+}
+
+svdp_status svdp_bound_features(svdp_handle* h, const svdp_params* p, const float* A, int64_t lda, int64_t sA,
+                                const float* probe, float* F, float* aux, void* ws, size_t ws_bytes,
+                                void* stream) {
+  REQ(h);
+  svdp_status s = check_common(p);
+  if (s) return s;
+  if (p->batch == 0) return SVDP_OK;
+  REQ(A); REQ(probe); REQ(F); REQ(aux);
+  LDCHK(lda, p->n, p->batch > 1 ? sA : 0, p->m);
+  size_t need = 0;
+  carve_fwd(nullptr, p, &need);
+  if (!ws || ws_bytes < need) return fail(SVDP_ERR_WORKSPACE, "workspace too small");
+  FwdWs w = carve_fwd(ws, p, nullptr);
+  hipStream_t st = (hipStream_t)stream;
+  const int B = (int)p->batch, m = (int)p->m, n = (int)p->n;
+  HIPCHK(fill_i32(w.flags, 0, B, st), "flags");
+  HIPCHK(norms_launch(A, lda, sA, B, m, n, w.colsum, w.rowmax, w.fro2, w.flags, nullptr, st), "norms");
+  HIPCHK(vnorm_launch(probe, n, B, n, w.nrm, 0, st), "probe norm");
+  const float* x = probe;
+  int64_t sx = n;
+  for (int k = 1; k <= 7; ++k) {
+    float* y = (k & 1) ? w.y0 : w.y1;
+    int trans = (k & 1) ? 0 : 1;
+    HIPCHK(matvec_launch(A, lda, sA, B, m, n, x, sx, y, m, trans, st), "matvec");
+    HIPCHK(vnorm_launch(y, m, B, trans ? n : m, w.nrm, k, st), "vnorm");
+    x = y;
+    sx = m;
+  }
+  HIPCHK(features_launch(w.fro2, w.nrm, B, m, n, F, aux, st), "features");
+  return SVDP_OK;
+}
+
+svdp_status svdp_spectral_features(const float* sv, const float* z, int64_t rows, int64_t n,
+                                   const float* m_over_n, float* F, float* aux, void* stream) {
+  if (rows == 0) return SVDP_OK;
+  REQ(sv); REQ(z); REQ(m_over_n); REQ(F); REQ(aux);
+  if (rows < 0 || n < 1 || rows > (1 << 26)) return fail(SVDP_ERR_SHAPE, "bad rows / n");
+  HIPCHK(spectral_features_launch(sv, z, (int)rows, (int)n, m_over_n, F, aux, (hipStream_t)stream), "features");
+  return SVDP_OK;
+}
+
+svdp_status svdp_mlp_fwd(const float* params, const float* mu, const float* sd, const float* X, int64_t rows,
+                         float* out, float* act, void* stream) {
+  if (rows == 0) return SVDP_OK;
+  REQ(params); REQ(X); REQ(out);
+  if ((mu == nullptr) != (sd == nullptr)) return fail(SVDP_ERR_INVALID_ARG, "mu and sd go together");
+  if (rows < 0 || rows > (1 << 26)) return fail(SVDP_ERR_SHAPE, "bad rows");
+  HIPCHK(mlp_fwd_launch(params, mu, sd, X, (int)rows, out, act, (hipStream_t)stream), "mlp fwd");
+  return SVDP_OK;
+}
+
+size_t svdp_mlp_bwd_ws_bytes(int64_t rows) {
+  return rows <= 0 ? 256 : mlp_bwd_partial_floats((int)rows) * sizeof(float);
+}
+
+svdp_status svdp_mlp_bwd(const float* params, const float* mu, const float* sd, const float* X, const float* act,
+                         const float* dout, int64_t rows, float* dparams, void* ws, size_t ws_bytes, void* stream) {
+  REQ(params); REQ(dparams);
+  if ((mu == nullptr) != (sd == nullptr)) return fail(SVDP_ERR_INVALID_ARG, "mu and sd go together");
+  if (rows < 0 || rows > (1 << 26)) return fail(SVDP_ERR_SHAPE, "bad rows");
+  hipStream_t st = (hipStream_t)stream;
+  if (rows == 0) {
+    HIPCHK(fill_f32(dparams, 0.f, SVDP_MLP_PARAMS, st), "zero grad");
+    return SVDP_OK;
+  }
+  REQ(X); REQ(act); REQ(dout);
+  if (!ws || ws_bytes < svdp_mlp_bwd_ws_bytes(rows)) return fail(SVDP_ERR_WORKSPACE, "workspace too small");
+  HIPCHK(mlp_bwd_launch(params, mu, sd, X, act, dout, (int)rows, (float*)ws, dparams, st), "mlp bwd");
+  return SVDP_OK;
+}
+
+svdp_status svdp_pinball(const float* out, const float* target, int64_t rows, float tau0, float tau1, float* dout,
+                         float* loss, void* stream) {
+  if (rows == 0) return SVDP_OK;
+  REQ(out); REQ(target); REQ(dout);
+  if (rows < 0 || rows > (1 << 26)) return fail(SVDP_ERR_SHAPE, "bad rows");
+  if (!(tau0 > 0 && tau0 < 1 && tau1 > 0 && tau1 < 1)) return fail(SVDP_ERR_INVALID_ARG, "tau must be in (0, 1)");
+  HIPCHK(pinball_launch(out, target, (int)rows, tau0, tau1, dout, loss, (hipStream_t)stream), "pinball");
+  return SVDP_OK;
+}
+
+svdp_status svdp_adam_step(float* params, float* m, float* v, const float* grad, int64_t n, float lr, float beta1,
+                           float beta2, float eps, int64_t t, void* stream) {
+  if (n == 0) return SVDP_OK;
+  REQ(params); REQ(m); REQ(v); REQ(grad);
+  if (n < 0 || t < 1) return fail(SVDP_ERR_INVALID_ARG, "need n >= 0 and t >= 1");
+  HIPCHK(adam_launch(params, m, v, grad, n, lr, beta1, beta2, eps, (int)t, (hipStream_t)stream), "adam");
+  return SVDP_OK;
+}
+
+svdp_status svdp_cans_table(int32_t kind, double delta, int32_t pre_iters, double lo, int32_t steps, double* table,
+                            double* t_out) {
+  REQ(table);
+  if (steps < 0) return fail(SVDP_ERR_INVALID_ARG, "steps < 0");
+  if (kind == 0) {
+    if (!(delta > 0 && delta < 1) || pre_iters < 0) return fail(SVDP_ERR_INVALID_ARG, "bad delta / pre_iters");
+    table_conservative(delta, pre_iters, steps, table, t_out);
+  } else if (kind == 1) {
+    if (!(lo > 0 && lo <= 1)) return fail(SVDP_ERR_INVALID_ARG, "lo must be in (0, 1]");
+    table_interval(lo, steps, table);
+    if (t_out) *t_out = lo;
+  } else {
+    return fail(SVDP_ERR_INVALID_ARG, "kind must be 0 or 1");
+  }
+  return SVDP_OK;
+}
+
+}  // extern "C"

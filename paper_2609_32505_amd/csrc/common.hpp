@@ -1,0 +1,53 @@
+// Shared device/host definitions of the gfx950 library (no torch types).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+typedef __bf16 bf16_t;
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef float f16v __attribute__((ext_vector_type(16)));
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+
+#define SVDP_DEV __device__ __forceinline__
+
+// One batched GEMM launch: out[b] = epilogue(op(A[b]) * op(B[b])).
+// Row-major storage.  op(A) is M x K: A[i*lda + k] (ta = 0) or A[k*lda + i]
+// (ta = 1).  op(B) is K x N: B[k*ldb + j] (tb = 0) or B[j*ldb + k] (tb = 1).
+// Epilogue (per matrix b, entry (i, j)):
+//   out = s_acc * acc * cs[j] + s_in * Cin[i, j] * csin[j]
+// where (s_in, s_acc) = coef[b*coef_bstride + coef_idx] when coef is set,
+// else (beta, alpha); cs / csin default to 1 when null.
+struct GemmArgs {
+  int M, N, K, batch;
+  const void* A; int64_t lda, sA;
+  const void* A_alt;   // matrix b reads A_alt instead of A when a_sel[b] != 0
+  const int* a_sel;
+  const void* B; int64_t ldb, sB;
+  const void* B_alt;   // likewise for B
+  const int* b_sel;
+  void* C; int64_t ldc, sC;
+  const void* Cin; int64_t ldcin, sCin;
+  float alpha, beta;
+  const float* coef; int64_t coef_bstride; int coef_idx;
+  const float* colscale; int64_t cs_stride;
+  const float* colscale_in; int64_t csin_stride;
+  const int* active;   // matrix b is skipped when active[b] == 0
+  float* conv;         // per matrix: += sum (out - Cin)^2, += sum out^2
+  int sym;             // output symmetric: upper tiles computed, mirrored
+  int work_batch;      // matrices actually computed (for work accounting; 0 = batch)
+  int out_bf16, in_bf16, cin_bf16;
+};
+
+enum { PREC_F32 = 0, PREC_BF16 = 1 };
+
+// Launch a batched GEMM.  prec selects FP32 MFMA (inputs FP32) or BF16 MFMA
+// (inputs FP32 or BF16 per in_bf16, rounded to BF16, FP32 accumulation).
+hipError_t gemm_launch(const GemmArgs& g, int prec, int ta, int tb, hipStream_t st);
+
+SVDP_DEV float bf2f(bf16_t x) { return (float)x; }
+SVDP_DEV bf16_t f2bf(float x) { return (bf16_t)x; }
+
+template <typename T>
+SVDP_DEV float ldf(const T* p, int64_t i) { return (float)p[i]; }
+
+static inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }

@@ -1,0 +1,40 @@
+// Batched block-Jacobi eigh: workspace layout and host entry points.
+#pragma once
+#include "common.hpp"
+#include "svdp.h"
+
+struct EighWs {
+  int batch, n, np, nb, max_sweeps;
+  float* Hw;      // batch x np x np working matrix
+  float* Vw;      // batch x np x np accumulated rotations
+  float* V2;      // batch x np x np re-orthonormalised eigenvectors
+  float* lamr;    // batch x n Rayleigh-quotient eigenvalues
+  float* Qw;      // batch x (nb/2) x 64 x 64 block rotations of the current step
+  float* hnorm2;  // batch: |H|_F^2
+  float* sgn;     // batch x n: sign of each sorted eigenvalue
+  int* perm;      // batch x n: sorted position -> working column
+  int* rotcnt;    // batch x (max_sweeps + 2): largest relative entry rotated (float bits)
+  int* active;    // batch: 1 while not converged
+  int* counter;   // device scalar: active matrices after a sweep
+};
+
+struct EighOpts {
+  int inner_sweeps;  // scalar sweeps per 64 x 64 pair subproblem (FP32)
+  int fp64_sweeps;   // final block sweeps with FP64 pair solves
+  int fp64_inner;    // scalar sweeps per pair subproblem in those
+  float tol;         // converged after a sweep whose largest rotated |h_pq| is
+                     // <= tol sqrt(|h_pp h_qq|) (quadratic convergence: the next
+                     // sweep, the FP64 one, leaves ~tol^2)
+  float abs_tol;     // entries below abs_tol |H|_F do not count
+  float neg_tol;     // NEG_EIGENVALUE when lam_min < -neg_tol max|lam| (mode 1)
+};
+
+size_t eigh_ws_bytes(int64_t batch, int64_t n, int max_sweeps);
+EighWs eigh_ws_carve(void* ws, int64_t batch, int64_t n, int max_sweeps);
+hipError_t eigh_run(EighWs e, const float* H, int64_t ldh, int64_t sH, int mode,
+                    const EighOpts& o, float* lam, int64_t slam, float* Vout, int64_t ldv,
+                    int64_t sV, int* sweeps_out, int* flags, int* host_counter, const int* mask,
+                    hipStream_t st);
+hipError_t copy_i32(int* dst, const int* src, int64_t n, hipStream_t st);
+hipError_t fill_i32(int* p, int v, int64_t n, hipStream_t st);
+hipError_t fill_f32(float* p, float v, int64_t n, hipStream_t st);

@@ -1,0 +1,454 @@
+// Batched strided GEMM on gfx950 matrix cores (MFMA), with the fused
+// epilogues the SVD path needs (CANS update alpha X + beta X G, symmetric
+// Gram output, column scaling, per-matrix skip and convergence sums).
+//
+// Two kernels: FP32 inputs on v_mfma_f32_32x32x2f32, and BF16 operands (from
+// FP32 or BF16 storage) on v_mfma_f32_32x32x16_bf16, both accumulating in
+// FP32.  A 256-thread workgroup owns a BM x BN output tile (4 waves, each a
+// (BM/2) x (BN/2) sub-tile of 32x32 MFMA blocks); K is walked in BK slices
+// staged through double-buffered LDS.  Operands stored with the contraction
+// index strided are transposed on their way into LDS, so the MFMA operand
+// reads are always contiguous.
+#include "common.hpp"
+#include "prof.hpp"
+
+namespace {
+
+thread_local int g_prof_kind = PROF_GEMM_F32;
+thread_local double g_prof_batch = 0.0;
+
+// Linear block id -> (matrix, tile).  Workgroups are dealt to the 8 XCDs
+// round-robin by linear id; with remap every tile of matrix b runs on XCD
+// b % 8, so the panels of one matrix are fetched into one L2 only.
+SVDP_DEV bool map_block(int ntiles, int batch, int remap, int& b, int& tile) {
+  int L = blockIdx.x;
+  if (!remap) {
+    b = L / ntiles;
+    tile = L - b * ntiles;
+    return b < batch;
+  }
+  int x = L & 7, q = L >> 3;
+  int grp = q / ntiles;
+  tile = q - grp * ntiles;
+  b = grp * 8 + x;
+  return b < batch;
+}
+
+// upper-triangular tile enumeration (tm <= tn), row by row
+SVDP_DEV void sym_tile(int t, int T, int& tm, int& tn) {
+  int r = 0;
+  while (t >= T - r) { t -= T - r; ++r; }
+  tm = r;
+  tn = r + t;
+}
+
+template <typename T>
+SVDP_DEV float ld_elem(const void* p, int64_t i) { return (float)((const T*)p)[i]; }
+
+SVDP_DEV float ld_any(const void* p, int64_t i, int isbf) {
+  return isbf ? (float)((const bf16_t*)p)[i] : ((const float*)p)[i];
+}
+
+// Shared epilogue over one wave's accumulators.  acc[f] holds a 32x32 block
+// in the MFMA output layout: lane l, slot 4g + r -> row 8g + 4(l/32) + r,
+// column l % 32.
+template <int FM, int FN>
+SVDP_DEV void epilogue(const GemmArgs& g, int b, int rowbase, int colbase, int tm, int tn,
+                       f16v (&acc)[FM][FN]) {
+  const int lane = threadIdx.x & 63;
+  float s_acc = g.alpha, s_in = g.beta;
+  if (g.coef) {
+    const float* c = g.coef + (b * g.coef_bstride + g.coef_idx) * 2;
+    s_in = c[0];
+    s_acc = c[1];
+  }
+  const float* cs = g.colscale ? g.colscale + b * g.cs_stride : nullptr;
+  const float* csi = g.colscale_in ? g.colscale_in + b * g.csin_stride : nullptr;
+  const char* cin = g.Cin ? (const char*)g.Cin + b * g.sCin * (g.cin_bf16 ? 2 : 4) : nullptr;
+  char* out = (char*)g.C + b * g.sC * (g.out_bf16 ? 2 : 4);
+  float d2 = 0.f, o2 = 0.f;
+  const bool mirror = g.sym && tm != tn;
+#pragma unroll
+  for (int mi = 0; mi < FM; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < FN; ++ni) {
+      const int j = colbase + ni * 32 + (lane & 31);
+      if (j >= g.N) continue;
+      const float csj = cs ? cs[j] : 1.f;
+      const float csij = csi ? csi[j] : 1.f;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = rowbase + mi * 32 + 8 * q + 4 * (lane >> 5) + r;
+          if (i >= g.M) continue;
+          float v = s_acc * acc[mi][ni][4 * q + r] * csj;
+          if (cin) {
+            float c = ld_any(cin, (int64_t)i * g.ldcin + j, g.cin_bf16);
+            v += s_in * c * csij;
+            d2 += (v - c) * (v - c);
+          }
+          o2 += v * v;
+          if (g.out_bf16) {
+            ((bf16_t*)out)[(int64_t)i * g.ldc + j] = f2bf(v);
+            if (mirror) ((bf16_t*)out)[(int64_t)j * g.ldc + i] = f2bf(v);
+          } else {
+            ((float*)out)[(int64_t)i * g.ldc + j] = v;
+            if (mirror) ((float*)out)[(int64_t)j * g.ldc + i] = v;
+          }
+        }
+    }
+  if (g.conv) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      d2 += __shfl_xor(d2, off);
+      o2 += __shfl_xor(o2, off);
+    }
+    if (lane == 0) {
+      atomicAdd(g.conv + 2 * b, d2);
+      atomicAdd(g.conv + 2 * b + 1, o2);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ FP32
+
+template <int BM, int BN, bool TA, bool TB, bool VEC>
+__global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs g, int tiles_m, int tiles_n,
+                                                  int ntiles, int remap) {
+  constexpr int BK = 16;
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int FM = WM / 32, FN = WN / 32;
+  constexpr int PAD = 4;
+  __shared__ float As[2][BK][BM + PAD];
+  __shared__ float Bs[2][BK][BN + PAD];
+  int b, tile;
+  if (!map_block(ntiles, g.batch, remap, b, tile)) return;
+  if (g.active && !g.active[b]) return;
+  int tm, tn;
+  if (g.sym) sym_tile(tile, tiles_m, tm, tn);
+  else { tm = tile / tiles_n; tn = tile - tm * tiles_n; }
+  const int m0 = tm * BM, n0 = tn * BN;
+  const float* A = (const float*)((g.a_sel && g.a_sel[b]) ? g.A_alt : g.A) + b * g.sA;
+  const float* B = (const float*)((g.b_sel && g.b_sel[b]) ? g.B_alt : g.B) + b * g.sB;
+  const int M = g.M, N = g.N, K = g.K;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wm = w >> 1, wn = w & 1;
+
+  // A tile: BM x BK of op(A) = BM*BK/4 float4 units, UA per thread
+  constexpr int UA = BM * BK / 4 / 256;
+  constexpr int UB = BN * BK / 4 / 256;
+  f4v ra[UA], rb[UB];
+
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < UA; ++u) {
+      int idx = t + 256 * u;
+      int i, k;
+      if (TA) { k = idx / (BM / 4); i = (idx % (BM / 4)) * 4; }   // rows of k, m contiguous
+      else { i = idx / (BK / 4); k = (idx % (BK / 4)) * 4; }      // rows of m, k contiguous
+      int gi = m0 + i, gk = k0 + k;
+      f4v v = {0.f, 0.f, 0.f, 0.f};
+      if (TA) {
+        if (gk < K) {
+          const float* p = A + (int64_t)gk * g.lda + gi;
+          if (VEC && gi + 3 < M) v = *(const f4v*)p;
+          else for (int c = 0; c < 4; ++c) v[c] = (gi + c < M) ? p[c] : 0.f;
+        }
+      } else {
+        if (gi < M) {
+          const float* p = A + (int64_t)gi * g.lda + gk;
+          if (VEC && gk + 3 < K) v = *(const f4v*)p;
+          else for (int c = 0; c < 4; ++c) v[c] = (gk + c < K) ? p[c] : 0.f;
+        }
+      }
+      ra[u] = v;
+    }
+#pragma unroll
+    for (int u = 0; u < UB; ++u) {
+      int idx = t + 256 * u;
+      int j, k;
+      if (!TB) { k = idx / (BN / 4); j = (idx % (BN / 4)) * 4; }
+      else { j = idx / (BK / 4); k = (idx % (BK / 4)) * 4; }
+      int gj = n0 + j, gk = k0 + k;
+      f4v v = {0.f, 0.f, 0.f, 0.f};
+      if (!TB) {
+        if (gk < K) {
+          const float* p = B + (int64_t)gk * g.ldb + gj;
+          if (VEC && gj + 3 < N) v = *(const f4v*)p;
+          else for (int c = 0; c < 4; ++c) v[c] = (gj + c < N) ? p[c] : 0.f;
+        }
+      } else {
+        if (gj < N) {
+          const float* p = B + (int64_t)gj * g.ldb + gk;
+          if (VEC && gk + 3 < K) v = *(const f4v*)p;
+          else for (int c = 0; c < 4; ++c) v[c] = (gk + c < K) ? p[c] : 0.f;
+        }
+      }
+      rb[u] = v;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < UA; ++u) {
+      int idx = t + 256 * u;
+      if (TA) {
+        int k = idx / (BM / 4), i = (idx % (BM / 4)) * 4;
+        *(f4v*)&As[buf][k][i] = ra[u];
+      } else {
+        int i = idx / (BK / 4), k = (idx % (BK / 4)) * 4;
+        for (int c = 0; c < 4; ++c) As[buf][k + c][i] = ra[u][c];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < UB; ++u) {
+      int idx = t + 256 * u;
+      if (!TB) {
+        int k = idx / (BN / 4), j = (idx % (BN / 4)) * 4;
+        *(f4v*)&Bs[buf][k][j] = rb[u];
+      } else {
+        int j = idx / (BK / 4), k = (idx % (BK / 4)) * 4;
+        for (int c = 0; c < 4; ++c) Bs[buf][k + c][j] = rb[u][c];
+      }
+    }
+  };
+
+  f16v acc[FM][FN];
+#pragma unroll
+  for (int mi = 0; mi < FM; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < FN; ++ni)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[mi][ni][e] = 0.f;
+
+  const int nk = (K + BK - 1) / BK;
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) load((kt + 1) * BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 2) {
+      float av[FM], bv[FN];
+#pragma unroll
+      for (int mi = 0; mi < FM; ++mi) av[mi] = As[cur][kk + (lane >> 5)][wm * WM + mi * 32 + (lane & 31)];
+#pragma unroll
+      for (int ni = 0; ni < FN; ++ni) bv[ni] = Bs[cur][kk + (lane >> 5)][wn * WN + ni * 32 + (lane & 31)];
+#pragma unroll
+      for (int mi = 0; mi < FM; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < FN; ++ni)
+          acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[mi], bv[ni], acc[mi][ni], 0, 0, 0);
+    }
+    if (kt + 1 < nk) store(cur ^ 1);
+    __syncthreads();
+  }
+  epilogue<FM, FN>(g, b, m0 + wm * WM, n0 + wn * WN, tm, tn, acc);
+}
+
+// ------------------------------------------------------------------ BF16
+
+template <int BM, int BN, bool TA, bool TB, bool INBF, bool VEC>
+__global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g, int tiles_m, int tiles_n,
+                                                   int ntiles, int remap) {
+  constexpr int BK = 64;
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int FM = WM / 32, FN = WN / 32;
+  constexpr int LDK = BK + 8;  // row stride (bf16) of the k-contiguous LDS tiles
+  __shared__ bf16_t As[2][BM][LDK];
+  __shared__ bf16_t Bs[2][BN][LDK];
+  int b, tile;
+  if (!map_block(ntiles, g.batch, remap, b, tile)) return;
+  if (g.active && !g.active[b]) return;
+  int tm, tn;
+  if (g.sym) sym_tile(tile, tiles_m, tm, tn);
+  else { tm = tile / tiles_n; tn = tile - tm * tiles_n; }
+  const int m0 = tm * BM, n0 = tn * BN;
+  const int esz = INBF ? 2 : 4;
+  const char* A = (const char*)((g.a_sel && g.a_sel[b]) ? g.A_alt : g.A) + b * g.sA * esz;
+  const char* B = (const char*)((g.b_sel && g.b_sel[b]) ? g.B_alt : g.B) + b * g.sB * esz;
+  const int M = g.M, N = g.N, K = g.K;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wm = w >> 1, wn = w & 1;
+
+  constexpr int UA = BM * BK / 8 / 256;
+  constexpr int UB = BN * BK / 8 / 256;
+  bf8v ra[UA], rb[UB];
+
+  // 8 consecutive elements starting at p (element units), masked by count
+  auto ld8 = [&](const char* base, int64_t off, int valid) -> bf8v {
+    bf8v v;
+    if (INBF) {
+      const bf16_t* p = (const bf16_t*)base + off;
+      if (VEC && valid >= 8) v = *(const bf8v*)p;
+      else for (int c = 0; c < 8; ++c) v[c] = c < valid ? p[c] : f2bf(0.f);
+    } else {
+      const float* p = (const float*)base + off;
+      if (VEC && valid >= 8) {
+        f4v x0 = *(const f4v*)p, x1 = *(const f4v*)(p + 4);
+        for (int c = 0; c < 4; ++c) { v[c] = f2bf(x0[c]); v[c + 4] = f2bf(x1[c]); }
+      } else {
+        for (int c = 0; c < 8; ++c) v[c] = f2bf(c < valid ? p[c] : 0.f);
+      }
+    }
+    return v;
+  };
+  const bf8v zero8 = {};
+
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < UA; ++u) {
+      int idx = t + 256 * u;
+      if (TA) {  // A stored K x M: vectors along m
+        int k = idx / (BM / 8), i = (idx % (BM / 8)) * 8;
+        int gk = k0 + k, gi = m0 + i;
+        ra[u] = (gk < K && gi < M) ? ld8(A, (int64_t)gk * g.lda + gi, M - gi) : zero8;
+      } else {   // A stored M x K: vectors along k
+        int i = idx / (BK / 8), k = (idx % (BK / 8)) * 8;
+        int gk = k0 + k, gi = m0 + i;
+        ra[u] = (gi < M && gk < K) ? ld8(A, (int64_t)gi * g.lda + gk, K - gk) : zero8;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < UB; ++u) {
+      int idx = t + 256 * u;
+      if (!TB) {  // B stored K x N: vectors along n
+        int k = idx / (BN / 8), j = (idx % (BN / 8)) * 8;
+        int gk = k0 + k, gj = n0 + j;
+        rb[u] = (gk < K && gj < N) ? ld8(B, (int64_t)gk * g.ldb + gj, N - gj) : zero8;
+      } else {    // B stored N x K: vectors along k
+        int j = idx / (BK / 8), k = (idx % (BK / 8)) * 8;
+        int gk = k0 + k, gj = n0 + j;
+        rb[u] = (gj < N && gk < K) ? ld8(B, (int64_t)gj * g.ldb + gk, K - gk) : zero8;
+      }
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < UA; ++u) {
+      int idx = t + 256 * u;
+      if (TA) {
+        int k = idx / (BM / 8), i = (idx % (BM / 8)) * 8;
+        for (int c = 0; c < 8; ++c) As[buf][i + c][k] = ra[u][c];
+      } else {
+        int i = idx / (BK / 8), k = (idx % (BK / 8)) * 8;
+        *(bf8v*)&As[buf][i][k] = ra[u];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < UB; ++u) {
+      int idx = t + 256 * u;
+      if (!TB) {
+        int k = idx / (BN / 8), j = (idx % (BN / 8)) * 8;
+        for (int c = 0; c < 8; ++c) Bs[buf][j + c][k] = rb[u][c];
+      } else {
+        int j = idx / (BK / 8), k = (idx % (BK / 8)) * 8;
+        *(bf8v*)&Bs[buf][j][k] = rb[u];
+      }
+    }
+  };
+
+  f16v acc[FM][FN];
+#pragma unroll
+  for (int mi = 0; mi < FM; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < FN; ++ni)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[mi][ni][e] = 0.f;
+
+  const int nk = (K + BK - 1) / BK;
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) load((kt + 1) * BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 16) {
+      bf8v av[FM], bv[FN];
+#pragma unroll
+      for (int mi = 0; mi < FM; ++mi)
+        av[mi] = *(const bf8v*)&As[cur][wm * WM + mi * 32 + (lane & 31)][kk + (lane >> 5) * 8];
+#pragma unroll
+      for (int ni = 0; ni < FN; ++ni)
+        bv[ni] = *(const bf8v*)&Bs[cur][wn * WN + ni * 32 + (lane & 31)][kk + (lane >> 5) * 8];
+#pragma unroll
+      for (int mi = 0; mi < FM; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < FN; ++ni)
+          acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[mi], bv[ni], acc[mi][ni], 0, 0, 0);
+    }
+    if (kt + 1 < nk) store(cur ^ 1);
+    __syncthreads();
+  }
+  epilogue<FM, FN>(g, b, m0 + wm * WM, n0 + wn * WN, tm, tn, acc);
+}
+
+template <typename KernelT>
+hipError_t launch_tiles(KernelT kern, const GemmArgs& g, int BM, int BN, hipStream_t st) {
+  int tiles_m = cdiv(g.M, BM), tiles_n = cdiv(g.N, BN);
+  int ntiles = g.sym ? tiles_m * (tiles_m + 1) / 2 : tiles_m * tiles_n;
+  int remap = g.batch >= 8 ? 1 : 0;
+  int64_t blocks = remap ? (int64_t)cdiv(g.batch, 8) * 8 * ntiles : (int64_t)g.batch * ntiles;
+  if (blocks <= 0) return hipSuccess;
+  if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
+  // algorithmic flops: 2 M N K per matrix, half of it for a symmetric output
+  ProfScope ps(g_prof_kind, st, (g.sym ? 1.0 : 2.0) * g.M * (double)g.N * g.K * g_prof_batch);
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), 0, st, g, tiles_m, tiles_n, ntiles, remap);
+  return hipGetLastError();
+}
+
+template <int BM, bool TA, bool TB, bool VEC>
+hipError_t dispatch_f32(const GemmArgs& g, hipStream_t st) {
+  return launch_tiles(k_gemm_f32<BM, BM, TA, TB, VEC>, g, BM, BM, st);
+}
+
+template <int BM, bool TA, bool TB, bool INBF, bool VEC>
+hipError_t dispatch_bf16(const GemmArgs& g, hipStream_t st) {
+  return launch_tiles(k_gemm_bf16<BM, BM, TA, TB, INBF, VEC>, g, BM, BM, st);
+}
+
+template <int BM, bool VEC>
+hipError_t by_trans_f32(const GemmArgs& g, int ta, int tb, hipStream_t st) {
+  if (ta && tb) return dispatch_f32<BM, true, true, VEC>(g, st);
+  if (ta) return dispatch_f32<BM, true, false, VEC>(g, st);
+  if (tb) return dispatch_f32<BM, false, true, VEC>(g, st);
+  return dispatch_f32<BM, false, false, VEC>(g, st);
+}
+
+template <int BM, bool INBF, bool VEC>
+hipError_t by_trans_bf16(const GemmArgs& g, int ta, int tb, hipStream_t st) {
+  if (ta && tb) return dispatch_bf16<BM, true, true, INBF, VEC>(g, st);
+  if (ta) return dispatch_bf16<BM, true, false, INBF, VEC>(g, st);
+  if (tb) return dispatch_bf16<BM, false, true, INBF, VEC>(g, st);
+  return dispatch_bf16<BM, false, false, INBF, VEC>(g, st);
+}
+
+bool aligned(const void* p, int64_t ld, int64_t stride, int elems, int esz) {
+  return ((uintptr_t)p % (elems * esz)) == 0 && ld % elems == 0 && stride % elems == 0;
+}
+
+}  // namespace
+
+hipError_t gemm_launch(const GemmArgs& g, int prec, int ta, int tb, hipStream_t st) {
+  if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
+  g_prof_kind = prec == PREC_F32 ? PROF_GEMM_F32 : PROF_GEMM_BF16;
+  g_prof_batch = g.work_batch > 0 ? g.work_batch : g.batch;
+  if (g.sym && g.M != g.N) return hipErrorInvalidValue;
+  const bool big = g.M > 64 && g.N > 64;
+  if (prec == PREC_F32) {
+    bool vec = aligned(g.A, g.lda, g.sA, 4, 4) && aligned(g.B, g.ldb, g.sB, 4, 4);
+    if (big) return vec ? by_trans_f32<128, true>(g, ta, tb, st) : by_trans_f32<128, false>(g, ta, tb, st);
+    return vec ? by_trans_f32<64, true>(g, ta, tb, st) : by_trans_f32<64, false>(g, ta, tb, st);
+  }
+  const int esz = g.in_bf16 ? 2 : 4;
+  const int el = g.in_bf16 ? 8 : 4;
+  bool vec = aligned(g.A, g.lda, g.sA, el, esz) && aligned(g.B, g.ldb, g.sB, el, esz);
+  if (g.in_bf16) {
+    if (big) return vec ? by_trans_bf16<128, true, true>(g, ta, tb, st) : by_trans_bf16<128, true, false>(g, ta, tb, st);
+    return vec ? by_trans_bf16<64, true, true>(g, ta, tb, st) : by_trans_bf16<64, true, false>(g, ta, tb, st);
+  }
+  if (big) return vec ? by_trans_bf16<128, false, true>(g, ta, tb, st) : by_trans_bf16<128, false, false>(g, ta, tb, st);
+  return vec ? by_trans_bf16<64, false, true>(g, ta, tb, st) : by_trans_bf16<64, false, false>(g, ta, tb, st);
+}

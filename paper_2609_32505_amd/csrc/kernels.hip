@@ -1,0 +1,862 @@
+// Element-wise, reduction and small-network kernels of the SVD path:
+// normalisation (Algorithm 3), CANS bookkeeping, the rank-deficiency test on
+// U, the eigenbasis Sylvester scaling of the backward (Algorithms 2 and 4),
+// the sketch features, and the interval-predictor MLP (forward, backward,
+// pinball loss, Adam) with the bound -> coefficient-table step.
+#include <algorithm>
+#include "common.hpp"
+#include "kernels.hpp"
+#include "eigh.hpp"
+
+namespace {
+
+SVDP_DEV float wave_sum(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+SVDP_DEV float wave_max(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
+  return v;
+}
+// non-negative float max through its int bit pattern
+SVDP_DEV void atomic_max_pos(float* p, float v) { atomicMax((int*)p, __float_as_int(v)); }
+
+SVDP_DEV bool skip(const int* mask, int b) { return mask && !mask[b]; }
+
+// ------------------------------------------------------------ normalisation
+
+// one wave per row: row abs sum -> rowmax, squares -> fro2, non-finite flag
+__global__ void k_rownorms(const float* A, int64_t lda, int64_t sA, int m, int n, float* rowmax,
+                           float* fro2, int* flags, const int* mask) {
+  const int b = blockIdx.y;
+  if (skip(mask, b)) return;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + w;
+  if (i >= m) return;
+  const float* r = A + b * sA + (int64_t)i * lda;
+  float s = 0.f, q = 0.f;
+  bool bad = false;
+  for (int j = lane; j < n; j += 64) {
+    float v = r[j];
+    bad |= !isfinite(v);
+    s += fabsf(v);
+    q += v * v;
+  }
+  s = wave_sum(s);
+  q = wave_sum(q);
+  unsigned long long anybad = __ballot(bad);
+  if (lane == 0) {
+    atomic_max_pos(rowmax + b, isfinite(s) ? s : 0.f);
+    atomicAdd(fro2 + b, q);
+    if (anybad) atomicOr(flags + b, SVDP_FLAG_NONFINITE);
+  }
+}
+
+// column abs sums over a chunk of rows (coalesced across threads)
+__global__ void k_colsums(const float* A, int64_t lda, int64_t sA, int m, int n, int rows_per,
+                          float* colsum, const int* mask) {
+  const int b = blockIdx.z;
+  if (skip(mask, b)) return;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const int i0 = blockIdx.y * rows_per, i1 = min(m, i0 + rows_per);
+  const float* p = A + b * sA + j;
+  float s = 0.f;
+  for (int i = i0; i < i1; ++i) s += fabsf(p[(int64_t)i * lda]);
+  atomicAdd(colsum + (int64_t)b * n + j, s);
+}
+
+__global__ void k_ns_scale(const float* colsum, const float* rowmax, int batch, int n, float* scale,
+                           const int* mask) {
+  const int b = blockIdx.x;
+  if (b >= batch || skip(mask, b)) return;
+  float mx = 0.f;
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    float c = colsum[(int64_t)b * n + j];
+    mx = fmaxf(mx, isfinite(c) ? c : 0.f);
+  }
+  mx = wave_max(mx);
+  __shared__ float part[16];
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float v = 0.f;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) v = fmaxf(v, part[w]);
+    double s = sqrt((double)v * (double)rowmax[b]);
+    scale[b] = s > 0.0 ? (float)s : 1.f;
+  }
+}
+
+__global__ void k_scale_copy(const float* A, int64_t lda, int64_t sA, int m, int n, const float* scale,
+                             void* X, int out_bf16, const int* mask) {
+  const int b = blockIdx.y;
+  if (skip(mask, b)) return;
+  const float inv = 1.f / scale[b];
+  const int64_t total = (int64_t)m * n;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    int i = (int)(idx / n), j = (int)(idx - (int64_t)i * n);
+    float v = A[b * sA + (int64_t)i * lda + j] * inv;
+    if (out_bf16) ((bf16_t*)X)[b * total + idx] = f2bf(v);
+    else ((float*)X)[b * total + idx] = v;
+  }
+}
+
+// ------------------------------------------------------------ CANS bookkeeping
+
+struct CoefTab { float v[128]; };
+__global__ void k_set_coef(float* coef, CoefTab t, int steps) {
+  int i = threadIdx.x;
+  if (i < 2 * steps) coef[i] = t.v[i];
+}
+
+__global__ void k_cans_check(int batch, float* conv, float tol, int k, int* active, int* where,
+                             int* iters, int* flags, int* counter) {
+  __shared__ int cnt;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  int mine = 0;
+  for (int b = threadIdx.x; b < batch; b += blockDim.x) {
+    if (!active[b]) continue;
+    float d2 = conv[2 * b], o2 = conv[2 * b + 1];
+    conv[2 * b] = 0.f;
+    conv[2 * b + 1] = 0.f;
+    iters[b] = k + 1;
+    where[b] = (k + 1) & 1;
+    if (!isfinite(d2) || !isfinite(o2)) {
+      active[b] = 0;
+      atomicOr(flags + b, SVDP_FLAG_NONFINITE);
+    } else if (d2 <= tol * tol * o2) {
+      active[b] = 0;
+    } else {
+      ++mine;
+    }
+  }
+  atomicAdd(&cnt, mine);
+  __syncthreads();
+  if (threadIdx.x == 0) *counter = cnt;
+}
+
+__global__ void k_residual(const void* G, int gbf16, int n, float* resid, const int* mask) {
+  const int b = blockIdx.y;
+  if (skip(mask, b)) return;
+  const int64_t total = (int64_t)n * n;
+  float s = 0.f;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    int i = (int)(idx / n), j = (int)(idx - (int64_t)i * n);
+    float g = gbf16 ? bf2f(((const bf16_t*)G)[b * total + idx]) : ((const float*)G)[b * total + idx];
+    float d = g - (i == j ? 1.f : 0.f);
+    s += d * d;
+  }
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) atomicAdd(resid + b, s);
+}
+
+__global__ void k_residual_finish(int batch, int n, float* resid, const int* mask) {
+  int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < batch && !skip(mask, b)) resid[b] = sqrtf(resid[b] / (float)n);
+}
+
+// ------------------------------------------------------------ U column norms
+
+__global__ void k_colnorm(const float* U, int64_t ldu, int64_t sU, int m, int n, int rows_per,
+                          float* cn2, const int* mask) {
+  const int b = blockIdx.z;
+  if (skip(mask, b)) return;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const int i0 = blockIdx.y * rows_per, i1 = min(m, i0 + rows_per);
+  const float* p = U + b * sU + j;
+  float s = 0.f;
+  for (int i = i0; i < i1; ++i) {
+    float v = p[(int64_t)i * ldu];
+    s += v * v;
+  }
+  atomicAdd(cn2 + (int64_t)b * n + j, s);
+}
+
+__global__ void k_colnorm_flag(const float* cn2, int n, float eps_qr, int* flags, const int* mask) {
+  const int b = blockIdx.x;
+  if (skip(mask, b)) return;
+  int bad = 0, nonfin = 0;
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    float c = cn2[(int64_t)b * n + j];
+    if (!isfinite(c)) nonfin = 1;
+    else if (fabsf(sqrtf(c) - 1.f) > eps_qr) bad = 1;
+  }
+  if (__any(bad)) if ((threadIdx.x & 63) == 0) atomicOr(flags + b, SVDP_FLAG_RANK_DEFICIENT);
+  if (__any(nonfin)) if ((threadIdx.x & 63) == 0) atomicOr(flags + b, SVDP_FLAG_NONFINITE);
+}
+
+// ------------------------------------------------------------ backward
+
+__global__ void k_dvec(const float* S, int64_t sS, int n, double eR, float* D) {
+  const int b = blockIdx.y;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double s = S[b * sS + j];
+  double den = s * s + eR;
+  D[(int64_t)b * n + j] = den == 0.0 ? 0.f : (float)(s / den);
+}
+
+SVDP_DEV double reg_ratio(double x, double e) {
+  double d = x * x + e;
+  return d == 0.0 ? 0.0 : x / d;
+}
+
+// 32 x 32 output tile per workgroup (256 threads, 4 entries each); the tile
+// at (I, J) and its transpose partner (J, I) of both inputs go through LDS so
+// all global reads are row-contiguous.
+__global__ void k_sylvester(int mode, const float* X1, const float* X2, const float* S, int64_t sS,
+                            const float* dS, int64_t sdS, const float* D, int n, double eK,
+                            double eT, float* out) {
+  __shared__ float a_ij[32][33], a_ji[32][33], p_ij[32][33], p_ji[32][33];
+  const int b = blockIdx.z;
+  const int I0 = blockIdx.y * 32, J0 = blockIdx.x * 32;
+  const int64_t base = (int64_t)b * n * n;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int r = ty; r < 32; r += 8) {
+    int i = I0 + r, j = J0 + tx;     // (i, j) row-contiguous in j
+    int i2 = J0 + r, j2 = I0 + tx;   // transposed partner tile
+    bool in1 = i < n && j < n, in2 = i2 < n && j2 < n;
+    a_ij[r][tx] = (X1 && in1) ? X1[base + (int64_t)i * n + j] : 0.f;
+    p_ij[r][tx] = (X2 && in1) ? X2[base + (int64_t)i * n + j] : 0.f;
+    a_ji[r][tx] = (X1 && in2) ? X1[base + (int64_t)i2 * n + j2] : 0.f;
+    p_ji[r][tx] = (X2 && in2) ? X2[base + (int64_t)i2 * n + j2] : 0.f;
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int i = I0 + r, j = J0 + tx;
+    if (i >= n || j >= n) continue;
+    const double si = S[b * sS + i], sj = S[b * sS + j];
+    const double Di = D[(int64_t)b * n + i], Dj = D[(int64_t)b * n + j];
+    // element (i, j) of input X is *_ij[r][tx]; element (j, i) is *_ji[tx][r]
+    const double x1ij = a_ij[r][tx], x1ji = a_ji[tx][r];
+    const double x2ij = p_ij[r][tx], x2ji = p_ji[tx][r];
+    double c;
+    if (mode == 0) {
+      // X1 = U^T dU (Ahat), X2 = V^T dV (P)
+      double bs = 0.5 * (x2ij + x1ij - x2ji - x1ji);          // skew(P + Ahat)_ij
+      double kji = reg_ratio(sj - si, eK);                     // (K^T)_ij
+      c = kji * bs - 0.5 * Di * Dj * (si * x1ij + sj * x1ji);  // sym(.. - diag(D s) Ahat diag(D))
+      if (i == j && dS) c += dS[b * sdS + i];
+      double t = reg_ratio(si + sj, eT);
+      out[base + (int64_t)i * n + j] = (float)(si * t * c);
+    } else {
+      // X1 = V^T dH V, X2 = (M V)^T (dW V)
+      c = 0.5 * (x1ij + x1ji) - 0.5 * Di * Dj * (x2ij + x2ji);
+      double t = reg_ratio(si + sj, eT);
+      out[base + (int64_t)i * n + j] = (float)(t * c);
+    }
+  }
+}
+
+__global__ void k_symmetrize(const float* in, int n, float* out, int64_t ldo, int64_t so) {
+  const int b = blockIdx.y;
+  const int64_t total = (int64_t)n * n;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    int i = (int)(idx / n), j = (int)(idx - (int64_t)i * n);
+    out[b * so + (int64_t)i * ldo + j] = 0.5f * (in[b * total + idx] + in[b * total + (int64_t)j * n + i]);
+  }
+}
+
+__global__ void k_copy(const float* src, int64_t lds, int64_t ss, const int* sel, const float* src_alt,
+                       float* dst, int64_t ldd, int64_t sd, int m, int n) {
+  const int b = blockIdx.y;
+  const float* s = (sel && sel[b]) ? src_alt : src;
+  const int64_t total = (int64_t)m * n;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    int i = (int)(idx / n), j = (int)(idx - (int64_t)i * n);
+    dst[b * sd + (int64_t)i * ldd + j] = s[b * ss + (int64_t)i * lds + j];
+  }
+}
+
+// ------------------------------------------------------------ features
+
+// y = A x: one wave per row
+__global__ void k_matvec_n(const float* A, int64_t lda, int64_t sA, int m, int n, const float* x,
+                           int64_t sx, float* y, int64_t sy) {
+  const int b = blockIdx.y;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + w;
+  if (i >= m) return;
+  const float* r = A + b * sA + (int64_t)i * lda;
+  const float* xb = x + b * sx;
+  float s = 0.f;
+  for (int j = lane; j < n; j += 64) s += r[j] * xb[j];
+  s = wave_sum(s);
+  if (lane == 0) y[b * sy + i] = s;
+}
+// y = A^T x: thread per column over a chunk of rows, atomics into cleared y
+__global__ void k_matvec_t(const float* A, int64_t lda, int64_t sA, int m, int n, int rows_per,
+                           const float* x, int64_t sx, float* y, int64_t sy) {
+  const int b = blockIdx.z;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const int i0 = blockIdx.y * rows_per, i1 = min(m, i0 + rows_per);
+  const float* p = A + b * sA + j;
+  const float* xb = x + b * sx;
+  float s = 0.f;
+  for (int i = i0; i < i1; ++i) s += p[(int64_t)i * lda] * xb[i];
+  atomicAdd(y + b * sy + j, s);
+}
+
+__global__ void k_vnorm(const float* v, int64_t sv, int len, float* nrm, int slot) {
+  const int b = blockIdx.x;
+  float s = 0.f;
+  for (int j = threadIdx.x; j < len; j += blockDim.x) {
+    float x = v[b * sv + j];
+    s += x * x;
+  }
+  s = wave_sum(s);
+  __shared__ float part[16];
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float t = 0.f;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += part[w];
+    nrm[b * 8 + slot] = sqrtf(t);
+  }
+}
+
+SVDP_DEV void features_from(double F, const double* nr, double n, double m_over_n, float* f,
+                            float* aux) {
+  double r[7];
+  for (int k = 0; k < 7; ++k) r[k] = nr[k + 1] / nr[k];
+  f[0] = (float)log(F / r[6]);
+  for (int k = 1; k < 6; ++k) f[k] = (float)log(r[k] / r[k + 1]);
+  f[6] = (float)log(n);
+  f[7] = (float)log(m_over_n);
+  aux[0] = (float)r[6];
+  aux[1] = (float)F;
+}
+
+__global__ void k_features(const float* fro2, const float* nrm, int batch, int m, int n, float* F,
+                           float* aux) {
+  int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= batch) return;
+  double nr[8];
+  for (int k = 0; k < 8; ++k) nr[k] = nrm[b * 8 + k];
+  features_from(sqrt((double)fro2[b]), nr, (double)n, (double)m / (double)n, F + b * 8, aux + b * 2);
+}
+
+// one wave per row: |s^k z| for k = 0..7 and |s|
+__global__ void k_spectral_features(const float* s, const float* z, int rows, int n,
+                                    const float* m_over_n, float* F, float* aux) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + w;
+  if (row >= rows) return;
+  const float* sr = s + (int64_t)row * n;
+  const float* zr = z + (int64_t)row * n;
+  double acc[9];
+  for (int k = 0; k < 9; ++k) acc[k] = 0.0;
+  for (int j = lane; j < n; j += 64) {
+    double sv = sr[j], p = zr[j];
+    acc[8] += sv * sv;
+    for (int k = 0; k < 8; ++k) {
+      acc[k] += p * p;
+      p *= sv;
+    }
+  }
+  for (int k = 0; k < 9; ++k)
+    for (int off = 32; off > 0; off >>= 1) acc[k] += __shfl_xor(acc[k], off);
+  if (lane == 0) {
+    double nr[8];
+    for (int k = 0; k < 8; ++k) nr[k] = sqrt(acc[k]);
+    features_from(sqrt(acc[8]), nr, (double)n, (double)m_over_n[row], F + (int64_t)row * 8, aux + (int64_t)row * 2);
+  }
+}
+
+// ------------------------------------------------------------ MLP
+
+constexpr int NF = 8, HID = 64, NO = 2;
+constexpr int OW1 = 0, OB1 = OW1 + HID * NF, OW2 = OB1 + HID, OB2 = OW2 + HID * HID,
+              OW3 = OB2 + HID, OB3 = OW3 + NO * HID, NPAR = OB3 + NO;
+static_assert(NPAR == SVDP_MLP_PARAMS, "parameter count");
+
+SVDP_DEV void load_params(float* sp, const float* P) {
+  for (int i = threadIdx.x; i < NPAR; i += blockDim.x) sp[i] = P[i];
+}
+SVDP_DEV void std_input(const float* X, int row, const float* mu, const float* sd, float* x) {
+  for (int f = 0; f < NF; ++f) {
+    float v = X[(int64_t)row * NF + f];
+    x[f] = (mu && sd) ? (v - mu[f]) / sd[f] : v;
+  }
+}
+
+// one thread per row, parameters staged in LDS
+__global__ __launch_bounds__(256) void k_mlp_fwd(const float* P, const float* mu, const float* sd,
+                                                 const float* X, int rows, float* out, float* act) {
+  __shared__ float sp[NPAR];
+  load_params(sp, P);
+  __syncthreads();
+  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= rows) return;
+  float x[NF], h1[HID];
+  std_input(X, row, mu, sd, x);
+  for (int o = 0; o < HID; ++o) {
+    float a = sp[OB1 + o];
+    for (int f = 0; f < NF; ++f) a += sp[OW1 + o * NF + f] * x[f];
+    h1[o] = tanhf(a);
+    if (act) act[(int64_t)row * 2 * HID + o] = h1[o];
+  }
+  float o0 = sp[OB3], o1 = sp[OB3 + 1];
+  for (int o = 0; o < HID; ++o) {
+    float a = sp[OB2 + o];
+    for (int i = 0; i < HID; ++i) a += sp[OW2 + o * HID + i] * h1[i];
+    float h2 = tanhf(a);
+    if (act) act[(int64_t)row * 2 * HID + HID + o] = h2;
+    o0 += sp[OW3 + o] * h2;
+    o1 += sp[OW3 + HID + o] * h2;
+  }
+  out[(int64_t)row * NO] = o0;
+  out[(int64_t)row * NO + 1] = o1;
+}
+
+// Backward over a chunk of 64 rows per workgroup: per-row deltas by one
+// thread each, then the weight gradients of the chunk as small outer-product
+// sums; partial[chunk] holds them, a second kernel adds the chunks in order.
+constexpr int RCH = 32;
+__global__ __launch_bounds__(256) void k_mlp_bwd(const float* P, const float* mu, const float* sd,
+                                                 const float* X, const float* act, const float* dout,
+                                                 int rows, float* partial) {
+  __shared__ float sW2[HID * HID];
+  __shared__ float sW3[NO * HID];
+  __shared__ float xs[RCH][NF + 1];
+  __shared__ float h1s[RCH][HID + 1];
+  __shared__ float h2s[RCH][HID + 1];
+  __shared__ float d1s[RCH][HID + 1];
+  __shared__ float d2s[RCH][HID + 1];
+  __shared__ float dos[RCH][NO];
+  for (int i = threadIdx.x; i < HID * HID; i += blockDim.x) sW2[i] = P[OW2 + i];
+  for (int i = threadIdx.x; i < NO * HID; i += blockDim.x) sW3[i] = P[OW3 + i];
+  const int r0 = blockIdx.x * RCH;
+  for (int idx = threadIdx.x; idx < RCH * HID; idx += blockDim.x) {
+    int r = idx / HID, o = idx % HID, row = r0 + r;
+    bool in = row < rows;
+    h1s[r][o] = in ? act[(int64_t)row * 2 * HID + o] : 0.f;
+    h2s[r][o] = in ? act[(int64_t)row * 2 * HID + HID + o] : 0.f;
+  }
+  for (int idx = threadIdx.x; idx < RCH * NO; idx += blockDim.x) {
+    int r = idx / NO, o = idx % NO, row = r0 + r;
+    dos[r][o] = row < rows ? dout[(int64_t)row * NO + o] : 0.f;
+  }
+  if (threadIdx.x < RCH) {
+    int row = r0 + threadIdx.x;
+    float x[NF];
+    if (row < rows) std_input(X, row, mu, sd, x);
+    else for (int f = 0; f < NF; ++f) x[f] = 0.f;
+    for (int f = 0; f < NF; ++f) xs[threadIdx.x][f] = x[f];
+  }
+  __syncthreads();
+  // d2 = (W3^T dout) * (1 - h2^2): entry (r, o) per thread
+  for (int idx = threadIdx.x; idx < RCH * HID; idx += blockDim.x) {
+    int r = idx / HID, o = idx % HID;
+    float g = sW3[o] * dos[r][0] + sW3[HID + o] * dos[r][1];
+    float h = h2s[r][o];
+    d2s[r][o] = g * (1.f - h * h);
+  }
+  __syncthreads();
+  // d1 = (W2^T d2) * (1 - h1^2)
+  for (int idx = threadIdx.x; idx < RCH * HID; idx += blockDim.x) {
+    int r = idx / HID, i = idx % HID;
+    float g = 0.f;
+    for (int o = 0; o < HID; ++o) g += sW2[o * HID + i] * d2s[r][o];
+    float h = h1s[r][i];
+    d1s[r][i] = g * (1.f - h * h);
+  }
+  __syncthreads();
+  float* part = partial + (int64_t)blockIdx.x * NPAR;
+  // dW2[o][i] = sum_r d2[r][o] h1[r][i]
+  for (int idx = threadIdx.x; idx < HID * HID; idx += blockDim.x) {
+    int o = idx / HID, i = idx % HID;
+    float s = 0.f;
+    for (int r = 0; r < RCH; ++r) s += d2s[r][o] * h1s[r][i];
+    part[OW2 + idx] = s;
+  }
+  for (int idx = threadIdx.x; idx < HID * NF; idx += blockDim.x) {
+    int o = idx / NF, f = idx % NF;
+    float s = 0.f;
+    for (int r = 0; r < RCH; ++r) s += d1s[r][o] * xs[r][f];
+    part[OW1 + idx] = s;
+  }
+  for (int idx = threadIdx.x; idx < NO * HID; idx += blockDim.x) {
+    int c = idx / HID, o = idx % HID;
+    float s = 0.f;
+    for (int r = 0; r < RCH; ++r) s += dos[r][c] * h2s[r][o];
+    part[OW3 + idx] = s;
+  }
+  for (int o = threadIdx.x; o < HID; o += blockDim.x) {
+    float s1 = 0.f, s2 = 0.f;
+    for (int r = 0; r < RCH; ++r) { s1 += d1s[r][o]; s2 += d2s[r][o]; }
+    part[OB1 + o] = s1;
+    part[OB2 + o] = s2;
+  }
+  if (threadIdx.x < NO) {
+    float s = 0.f;
+    for (int r = 0; r < RCH; ++r) s += dos[r][threadIdx.x];
+    part[OB3 + threadIdx.x] = s;
+  }
+}
+
+__global__ void k_sum_chunks(const float* partial, int chunks, float* dP) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= NPAR) return;
+  float s = 0.f;
+  for (int c = 0; c < chunks; ++c) s += partial[(int64_t)c * NPAR + i];
+  dP[i] = s;
+}
+
+__global__ void k_pinball(const float* out, const float* target, int rows, float tau0, float tau1,
+                          float* dout, float* loss) {
+  int row = blockIdx.x * blockDim.x + threadIdx.x;
+  float l = 0.f;
+  if (row < rows) {
+    for (int j = 0; j < 2; ++j) {
+      float tau = j ? tau1 : tau0;
+      float u = target[(int64_t)row * 2 + j] - out[(int64_t)row * 2 + j];
+      l += fmaxf(tau * u, (tau - 1.f) * u);
+      dout[(int64_t)row * 2 + j] = (u < 0.f ? 1.f - tau : -tau) / (float)rows;
+    }
+  }
+  l = wave_sum(l);
+  if ((threadIdx.x & 63) == 0 && loss) atomicAdd(loss, l / (float)rows);
+}
+
+__global__ void k_adam(float* p, float* m, float* v, const float* g, int64_t n, float lr, float b1,
+                       float b2, float eps, float c1, float c2) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float gi = g[i];
+  float mi = b1 * m[i] + (1.f - b1) * gi;
+  float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// ------------------------------------------------------------ bounds
+
+// degree-3 interval-optimal polynomial on [a, b] (equioscillation at a, x*, b)
+SVDP_DEV void cans_poly_dev(double a, double b, double& al, double& be, double& lo, double& hi) {
+  double s = a * a + a * b + b * b;
+  double xs = sqrt(s / 3.0);
+  be = -2.0 / (a * b * (a + b) + 2.0 * xs * xs * xs);
+  al = -be * s;
+  lo = al * a + be * a * a * a;
+  hi = al * xs + be * xs * xs * xs;
+}
+
+// mode 0: learned (mlp_out = (log(smax / r7), log(smax / smin)), aux = (r7, |A|_F))
+// mode 1: user bounds (sigma_min, sigma_max)
+__global__ void k_bounds(int batch, int mode, const float* mlp_out, const float* aux,
+                         const float* user_bounds, double margin_max, double margin_min,
+                         double handoff, double bf16_from, int kcap, float* scale, float* coef,
+                         int* ksteps, int* kmax, const int* mask) {
+  int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= batch || skip(mask, b)) return;
+  double smax, smin;
+  if (mode == 0) {
+    double r7 = aux[2 * b];
+    double o1 = fmax((double)mlp_out[2 * b], 0.0);      // r7 <= sigma_max
+    double o2 = fmax((double)mlp_out[2 * b + 1], 0.0);  // kappa >= 1
+    smax = r7 * exp(o1);
+    smin = smax * exp(-o2);
+  } else {
+    smin = user_bounds[2 * b];
+    smax = user_bounds[2 * b + 1];
+  }
+  // widen the interval: BF16 rounding of the iterate moves its singular
+  // values, and a value pushed past the cubic's positive root changes sign
+  smax *= margin_max;
+  smin *= margin_min;
+  if (!(smax > 0.0) || !isfinite(smax)) smax = 1.0;
+  double lo = smin / smax;
+  if (!(lo > 1e-12)) lo = 1e-12;
+  if (lo > 1.0) lo = 1.0;
+  scale[b] = (float)smax;
+  double a = lo, hb = 1.0;
+  int K = kcap, K1 = a >= bf16_from ? 0 : kcap;
+  for (int k = 0; k < kcap; ++k) {
+    double al, be, l2, h2;
+    cans_poly_dev(a, hb, al, be, l2, h2);
+    coef[((int64_t)b * kcap + k) * 2] = (float)al;
+    coef[((int64_t)b * kcap + k) * 2 + 1] = (float)be;
+    a = l2;
+    hb = h2;
+    if (K == kcap && fmax(1.0 - a, hb - 1.0) <= handoff) K = k + 1;
+    if (K1 == kcap && a >= bf16_from) K1 = k + 1;
+  }
+  ksteps[b] = K;
+  atomicMax(kmax, K);
+  atomicMax(kmax + 1, K1);
+}
+
+// ------------------------------------------------------------ info
+
+__global__ void k_info(int batch, const int* iters, const int* sweeps, const int* flags,
+                       const float* resid, svdp_info* info, const int* mask) {
+  int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= batch || skip(mask, b)) return;
+  svdp_info r;
+  r.iters = iters ? iters[b] : 0;
+  r.sweeps = sweeps ? sweeps[b] : 0;
+  r.flags = flags ? flags[b] : 0;
+  r.residual = resid ? resid[b] : 0.f;
+  info[b] = r;
+}
+
+__global__ void k_fallback_mask(int batch, int* flags, int bits, const float* resid, float rtol,
+                                int* mask, int* counter) {
+  __shared__ int cnt;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  int mine = 0;
+  for (int b = threadIdx.x; b < batch; b += blockDim.x) {
+    int f = (flags[b] & bits) != 0 || !(resid[b] <= rtol);
+    mask[b] = f;
+    if (f) flags[b] = 0;  // the rerun reports its own flags
+    mine += f;
+  }
+  atomicAdd(&cnt, mine);
+  __syncthreads();
+  if (threadIdx.x == 0) *counter = cnt;
+}
+
+__global__ void k_fill_masked(int* p, int v, int n, const int* mask) {
+  int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < n && !skip(mask, b)) p[b] = v;
+}
+
+__global__ void k_or_flags(int batch, int* flags, int bits, const int* mask) {
+  int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < batch && !skip(mask, b)) flags[b] |= bits;
+}
+
+inline int grid1(int64_t total, int cap = 2048) { return (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(total, 256), cap)); }
+
+}  // namespace
+
+#define LAUNCH_CHECK() return hipGetLastError()
+
+hipError_t norms_launch(const float* A, int64_t lda, int64_t sA, int batch, int m, int n,
+                        float* colsum, float* rowmax, float* fro2, int* flags, const int* mask,
+                        hipStream_t st) {
+  hipError_t e;
+  if ((e = fill_f32(colsum, 0.f, (int64_t)batch * n, st))) return e;
+  if ((e = fill_f32(rowmax, 0.f, batch, st))) return e;
+  if ((e = fill_f32(fro2, 0.f, batch, st))) return e;
+  hipLaunchKernelGGL(k_rownorms, dim3(cdiv(m, 4), batch), dim3(256), 0, st, A, lda, sA, m, n, rowmax,
+                     fro2, flags, mask);
+  if ((e = hipGetLastError())) return e;
+  const int rows_per = 256;
+  hipLaunchKernelGGL(k_colsums, dim3(cdiv(n, 256), cdiv(m, rows_per), batch), dim3(256), 0, st, A, lda,
+                     sA, m, n, rows_per, colsum, mask);
+  LAUNCH_CHECK();
+}
+
+hipError_t ns_scale_launch(const float* colsum, const float* rowmax, int batch, int n, float* scale,
+                           const int* mask, hipStream_t st) {
+  hipLaunchKernelGGL(k_ns_scale, dim3(batch), dim3(256), 0, st, colsum, rowmax, batch, n, scale, mask);
+  LAUNCH_CHECK();
+}
+
+hipError_t scale_copy_launch(const float* A, int64_t lda, int64_t sA, int batch, int m, int n,
+                             const float* scale, void* X, int out_bf16, const int* mask, hipStream_t st) {
+  hipLaunchKernelGGL(k_scale_copy, dim3(grid1((int64_t)m * n), batch), dim3(256), 0, st, A, lda, sA, m,
+                     n, scale, X, out_bf16, mask);
+  LAUNCH_CHECK();
+}
+
+hipError_t set_coef_launch(float* coef, const double* tab, int steps, hipStream_t st) {
+  CoefTab t;
+  if (steps > 64) steps = 64;
+  for (int i = 0; i < 2 * steps; ++i) t.v[i] = (float)tab[i];
+  hipLaunchKernelGGL(k_set_coef, dim3(1), dim3(128), 0, st, coef, t, steps);
+  LAUNCH_CHECK();
+}
+
+hipError_t cans_check_launch(int batch, float* conv, float tol, int k, int* active, int* where,
+                             int* iters, int* flags, int* counter, hipStream_t st) {
+  hipLaunchKernelGGL(k_cans_check, dim3(1), dim3(1024), 0, st, batch, conv, tol, k, active, where,
+                     iters, flags, counter);
+  LAUNCH_CHECK();
+}
+
+hipError_t residual_launch(const void* G, int gbf16, int batch, int n, float* resid, const int* mask,
+                           hipStream_t st) {
+  hipError_t e;
+  if ((e = fill_f32(resid, 0.f, batch, st))) return e;
+  hipLaunchKernelGGL(k_residual, dim3(grid1((int64_t)n * n, 64), batch), dim3(256), 0, st, G, gbf16, n,
+                     resid, mask);
+  if ((e = hipGetLastError())) return e;
+  hipLaunchKernelGGL(k_residual_finish, dim3(cdiv(batch, 256)), dim3(256), 0, st, batch, n, resid, mask);
+  LAUNCH_CHECK();
+}
+
+hipError_t colnorm_check_launch(const float* U, int64_t ldu, int64_t sU, int batch, int m, int n,
+                                float* colnorm2, float eps_qr, int* flags, const int* mask,
+                                hipStream_t st) {
+  hipError_t e;
+  if ((e = fill_f32(colnorm2, 0.f, (int64_t)batch * n, st))) return e;
+  const int rows_per = 256;
+  hipLaunchKernelGGL(k_colnorm, dim3(cdiv(n, 256), cdiv(m, rows_per), batch), dim3(256), 0, st, U, ldu,
+                     sU, m, n, rows_per, colnorm2, mask);
+  if ((e = hipGetLastError())) return e;
+  hipLaunchKernelGGL(k_colnorm_flag, dim3(batch), dim3(256), 0, st, colnorm2, n, eps_qr, flags, mask);
+  LAUNCH_CHECK();
+}
+
+hipError_t dvec_launch(const float* S, int64_t sS, int batch, int n, double eR, float* D, hipStream_t st) {
+  hipLaunchKernelGGL(k_dvec, dim3(cdiv(n, 256), batch), dim3(256), 0, st, S, sS, n, eR, D);
+  LAUNCH_CHECK();
+}
+
+hipError_t sylvester_launch(int mode, const float* X1, const float* X2, const float* S, int64_t sS,
+                            const float* dS, int64_t sdS, const float* D, int batch, int n, double eK,
+                            double eT, float* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_sylvester, dim3(cdiv(n, 32), cdiv(n, 32), batch), dim3(256), 0, st, mode, X1, X2,
+                     S, sS, dS, sdS, D, n, eK, eT, out);
+  LAUNCH_CHECK();
+}
+
+hipError_t symmetrize_launch(const float* in, int batch, int n, float* out, int64_t ldo, int64_t so,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(k_symmetrize, dim3(grid1((int64_t)n * n), batch), dim3(256), 0, st, in, n, out, ldo,
+                     so);
+  LAUNCH_CHECK();
+}
+
+hipError_t copy_launch(const float* src, int64_t lds, int64_t ss, const int* sel, const float* src_alt,
+                       float* dst, int64_t ldd, int64_t sd, int batch, int m, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_copy, dim3(grid1((int64_t)m * n), batch), dim3(256), 0, st, src, lds, ss, sel,
+                     src_alt, dst, ldd, sd, m, n);
+  LAUNCH_CHECK();
+}
+
+hipError_t matvec_launch(const float* A, int64_t lda, int64_t sA, int batch, int m, int n, const float* x,
+                         int64_t sx, float* y, int64_t sy, int trans, hipStream_t st) {
+  if (!trans) {
+    hipLaunchKernelGGL(k_matvec_n, dim3(cdiv(m, 4), batch), dim3(256), 0, st, A, lda, sA, m, n, x, sx, y,
+                       sy);
+    LAUNCH_CHECK();
+  }
+  hipError_t e;
+  // y cleared by a strided fill: batch rows of length n with stride sy
+  if ((e = fill_f32(y, 0.f, (int64_t)(batch - 1) * sy + n, st))) return e;
+  const int rows_per = 256;
+  hipLaunchKernelGGL(k_matvec_t, dim3(cdiv(n, 256), cdiv(m, rows_per), batch), dim3(256), 0, st, A, lda,
+                     sA, m, n, rows_per, x, sx, y, sy);
+  LAUNCH_CHECK();
+}
+
+hipError_t vnorm_launch(const float* v, int64_t sv, int batch, int len, float* nrm, int slot,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(k_vnorm, dim3(batch), dim3(256), 0, st, v, sv, len, nrm, slot);
+  LAUNCH_CHECK();
+}
+
+hipError_t features_launch(const float* fro2, const float* nrm, int batch, int m, int n, float* F,
+                           float* aux, hipStream_t st) {
+  hipLaunchKernelGGL(k_features, dim3(cdiv(batch, 64)), dim3(64), 0, st, fro2, nrm, batch, m, n, F, aux);
+  LAUNCH_CHECK();
+}
+
+hipError_t spectral_features_launch(const float* s, const float* z, int rows, int n, const float* m_over_n,
+                                    float* F, float* aux, hipStream_t st) {
+  hipLaunchKernelGGL(k_spectral_features, dim3(cdiv(rows, 4)), dim3(256), 0, st, s, z, rows, n, m_over_n,
+                     F, aux);
+  LAUNCH_CHECK();
+}
+
+hipError_t mlp_fwd_launch(const float* P, const float* mu, const float* sd, const float* X, int rows,
+                          float* out, float* act, hipStream_t st) {
+  hipLaunchKernelGGL(k_mlp_fwd, dim3(cdiv(rows, 256)), dim3(256), 0, st, P, mu, sd, X, rows, out, act);
+  LAUNCH_CHECK();
+}
+
+size_t mlp_bwd_partial_floats(int rows) { return (size_t)cdiv(rows, RCH) * NPAR; }
+
+hipError_t mlp_bwd_launch(const float* P, const float* mu, const float* sd, const float* X,
+                          const float* act, const float* dout, int rows, float* partial, float* dP,
+                          hipStream_t st) {
+  int chunks = cdiv(rows, RCH);
+  hipLaunchKernelGGL(k_mlp_bwd, dim3(chunks), dim3(256), 0, st, P, mu, sd, X, act, dout, rows, partial);
+  hipError_t e;
+  if ((e = hipGetLastError())) return e;
+  hipLaunchKernelGGL(k_sum_chunks, dim3(cdiv(NPAR, 256)), dim3(256), 0, st, partial, chunks, dP);
+  LAUNCH_CHECK();
+}
+
+hipError_t pinball_launch(const float* out, const float* target, int rows, float tau0, float tau1,
+                          float* dout, float* loss, hipStream_t st) {
+  hipLaunchKernelGGL(k_pinball, dim3(cdiv(rows, 256)), dim3(256), 0, st, out, target, rows, tau0, tau1,
+                     dout, loss);
+  LAUNCH_CHECK();
+}
+
+hipError_t adam_launch(float* p, float* m, float* v, const float* g, int64_t n, float lr, float b1,
+                       float b2, float eps, int t, hipStream_t st) {
+  float c1 = 1.f - powf(b1, (float)t), c2 = 1.f - powf(b2, (float)t);
+  hipLaunchKernelGGL(k_adam, dim3(cdiv(n, 256)), dim3(256), 0, st, p, m, v, g, n, lr, b1, b2, eps, c1, c2);
+  LAUNCH_CHECK();
+}
+
+hipError_t bounds_launch(int batch, int mode, const float* mlp_out, const float* aux,
+                         const float* user_bounds, double margin_max, double margin_min, double handoff,
+                         double bf16_from, int kcap, float* scale, float* coef, int* ksteps, int* kmax,
+                         const int* mask, hipStream_t st) {
+  hipError_t e;
+  if ((e = fill_i32(kmax, 0, 2, st))) return e;
+  hipLaunchKernelGGL(k_bounds, dim3(cdiv(batch, 64)), dim3(64), 0, st, batch, mode, mlp_out, aux,
+                     user_bounds, margin_max, margin_min, handoff, bf16_from, kcap, scale, coef, ksteps,
+                     kmax, mask);
+  LAUNCH_CHECK();
+}
+
+hipError_t info_pack_launch(int batch, const int* iters, const int* sweeps, const int* flags,
+                            const float* resid, svdp_info* info, const int* mask, hipStream_t st) {
+  hipLaunchKernelGGL(k_info, dim3(cdiv(batch, 256)), dim3(256), 0, st, batch, iters, sweeps, flags, resid,
+                     info, mask);
+  LAUNCH_CHECK();
+}
+
+hipError_t fallback_mask_launch(int batch, int* flags, int bits, const float* resid, float rtol,
+                                int* mask, int* counter, hipStream_t st) {
+  hipLaunchKernelGGL(k_fallback_mask, dim3(1), dim3(1024), 0, st, batch, flags, bits, resid, rtol, mask,
+                     counter);
+  LAUNCH_CHECK();
+}
+
+hipError_t or_flags_launch(int batch, int* flags, int bits, const int* mask, hipStream_t st) {
+  hipLaunchKernelGGL(k_or_flags, dim3(cdiv(batch, 256)), dim3(256), 0, st, batch, flags, bits, mask);
+  LAUNCH_CHECK();
+}
+
+hipError_t fill_masked_launch(int* p, int v, int n, const int* mask, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_masked, dim3(cdiv(n, 256)), dim3(256), 0, st, p, v, n, mask);
+  LAUNCH_CHECK();
+}
+
+namespace {
+__global__ void k_count_mask(int batch, const int* mask, int* counter) {
+  __shared__ int cnt;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  int mine = 0;
+  for (int b = threadIdx.x; b < batch; b += blockDim.x) mine += mask[b] != 0;
+  atomicAdd(&cnt, mine);
+  __syncthreads();
+  if (threadIdx.x == 0) *counter = cnt;
+}
+}  // namespace
+
+hipError_t count_mask_launch(int batch, const int* mask, int* counter, hipStream_t st) {
+  hipLaunchKernelGGL(k_count_mask, dim3(1), dim3(1024), 0, st, batch, mask, counter);
+  LAUNCH_CHECK();
+}

@@ -1,0 +1,99 @@
+// Launchers of the element-wise, reduction and small-network kernels.
+#pragma once
+#include "common.hpp"
+#include "svdp.h"
+
+// ---- normalisation (Algorithm 3): s_b = sqrt(|A_b|_1 |A_b|_inf) ----------
+// colsum: batch x n scratch, rowmax/colmax/fro2: batch floats (all cleared here).
+hipError_t norms_launch(const float* A, int64_t lda, int64_t sA, int batch, int m, int n,
+                        float* colsum, float* rowmax, float* fro2, int* flags,
+                        const int* mask, hipStream_t st);
+// scale[b] = sqrt(max_j colsum[b, j] * rowmax[b]) (1 for a zero matrix)
+hipError_t ns_scale_launch(const float* colsum, const float* rowmax, int batch, int n,
+                           float* scale, const int* mask, hipStream_t st);
+// X[b] = A[b] / scale[b], contiguous m x n, FP32 or BF16
+hipError_t scale_copy_launch(const float* A, int64_t lda, int64_t sA, int batch, int m, int n,
+                             const float* scale, void* X, int out_bf16, const int* mask,
+                             hipStream_t st);
+
+// ---- CANS bookkeeping ------------------------------------------------------
+// Broadcast a coefficient table of up to 64 steps into coef (kcap x 2 floats).
+hipError_t set_coef_launch(float* coef, const double* tab, int steps, hipStream_t st);
+// After step k: matrices whose relative change is <= tol stop (active = 0),
+// where[b] = parity of the buffer holding their last iterate; iters[b] = k+1;
+// conv sums are cleared; *counter = number still active.
+hipError_t cans_check_launch(int batch, float* conv, float tol, int k, int* active,
+                             int* where, int* iters, int* flags, int* counter, hipStream_t st);
+// residual[b] = |G - I|_F / sqrt(n) from a Gram matrix G (FP32 or BF16)
+hipError_t residual_launch(const void* G, int gbf16, int batch, int n, float* resid,
+                           const int* mask, hipStream_t st);
+
+// ---- U column-norm check (Algorithm 1, rank-deficiency test) --------------
+hipError_t colnorm_check_launch(const float* U, int64_t ldu, int64_t sU, int batch, int m, int n,
+                                float* colnorm2, float eps_qr, int* flags, const int* mask,
+                                hipStream_t st);
+
+// ---- backward element-wise steps -------------------------------------------
+// D[b, j] = s_j / (s_j^2 + eR) in FP64
+hipError_t dvec_launch(const float* S, int64_t sS, int batch, int n, double eR, float* D,
+                       hipStream_t st);
+// mode 0 (SVD, Algorithm 4 in the eigenbasis): X1 = U^T dU, X2 = V^T dV,
+//   out = diag(s) (T o sym(diag dS + K^T o skew(X2 + X1) - diag(D s) X1 diag(D)))
+// mode 1 (polar, Algorithm 2): X1 = V^T dH V, X2 = (M V)^T (dW V),
+//   out = T o (sym(X1) - diag(D) sym(X2) diag(D))
+// X1 / X2 may be null (zero).  n x n, contiguous per matrix.
+hipError_t sylvester_launch(int mode, const float* X1, const float* X2, const float* S, int64_t sS,
+                            const float* dS, int64_t sdS, const float* D, int batch, int n,
+                            double eK, double eT, float* out, hipStream_t st);
+// out = (in + in^T) / 2 into a strided destination
+hipError_t symmetrize_launch(const float* in, int batch, int n, float* out, int64_t ldo,
+                             int64_t so, hipStream_t st);
+// strided batch copy (m x n)
+hipError_t copy_launch(const float* src, int64_t lds, int64_t ss, const int* sel,
+                       const float* src_alt, float* dst, int64_t ldd, int64_t sd, int batch, int m,
+                       int n, hipStream_t st);
+
+// ---- sketch features and the interval predictor ---------------------------
+// y[b] = A[b] x[b] (trans = 0, length m) or A[b]^T x[b] (trans = 1, length n)
+hipError_t matvec_launch(const float* A, int64_t lda, int64_t sA, int batch, int m, int n,
+                         const float* x, int64_t sx, float* y, int64_t sy, int trans,
+                         hipStream_t st);
+// nrm[b * 8 + slot] = |v[b]|_2 (v length len, stride sv)
+hipError_t vnorm_launch(const float* v, int64_t sv, int batch, int len, float* nrm, int slot,
+                        hipStream_t st);
+// features from |A|_F^2 and the 8 power-sequence norms (see svdp_bound_features)
+hipError_t features_launch(const float* fro2, const float* nrm, int batch, int m, int n,
+                           float* F, float* aux, hipStream_t st);
+// features of A = Q1 diag(s) Q2^T with probe Q2 z, from (s, z)
+hipError_t spectral_features_launch(const float* s, const float* z, int rows, int n,
+                                    const float* m_over_n, float* F, float* aux, hipStream_t st);
+hipError_t mlp_fwd_launch(const float* P, const float* mu, const float* sd, const float* X, int rows,
+                          float* out, float* act, hipStream_t st);
+hipError_t mlp_bwd_launch(const float* P, const float* mu, const float* sd, const float* X,
+                          const float* act, const float* dout, int rows, float* partial,
+                          float* dP, hipStream_t st);
+size_t mlp_bwd_partial_floats(int rows);
+hipError_t pinball_launch(const float* out, const float* target, int rows, float tau0, float tau1,
+                          float* dout, float* loss, hipStream_t st);
+hipError_t adam_launch(float* p, float* m, float* v, const float* g, int64_t n, float lr, float b1,
+                       float b2, float eps, int t, hipStream_t st);
+// Learned / user bounds -> per-matrix scale, interval-optimal coefficient
+// table and BF16 step count (FP64 scalar recursion); *kmax = max count.
+// kmax[0] = max steps to the hand-off, kmax[1] = max FP32 steps before the
+// interval's lower end reaches bf16_from.
+hipError_t bounds_launch(int batch, int mode, const float* mlp_out, const float* aux,
+                         const float* user_bounds, double margin_max, double margin_min,
+                         double handoff, double bf16_from, int kcap, float* scale, float* coef,
+                         int* ksteps, int* kmax, const int* mask, hipStream_t st);
+
+// ---- info ------------------------------------------------------------------
+hipError_t info_pack_launch(int batch, const int* iters, const int* sweeps, const int* flags,
+                            const float* resid, svdp_info* info, const int* mask, hipStream_t st);
+// mask[b] = 1 if flags[b] & bits or resid[b] > rtol; *counter = count
+hipError_t fallback_mask_launch(int batch, int* flags, int bits, const float* resid,
+                                float rtol, int* mask, int* counter, hipStream_t st);
+hipError_t or_flags_launch(int batch, int* flags, int bits, const int* mask, hipStream_t st);
+// p[b] = v where mask[b] != 0 (all b when mask is null)
+hipError_t fill_masked_launch(int* p, int v, int n, const int* mask, hipStream_t st);
+// *counter = number of nonzero mask entries
+hipError_t count_mask_launch(int batch, const int* mask, int* counter, hipStream_t st);

@@ -116,7 +116,7 @@ def test_features_orthogonal_invariance_and_scale(orc):
     assert r3 == pytest.approx(1e3 * r1, rel=1e-10)
     # r_7 is a lower bound of sigma_max
     assert r1 <= s[0] * (1 + 1e-12)
-    assert f1[-1] == pytest.approx(np.log(m / n))
+    assert f1[-1] == pytest.approx(np.log(m / n)) and f1[-2] == pytest.approx(np.log(n))
 
 
 def test_mlp_backward_vs_fd(orc):
