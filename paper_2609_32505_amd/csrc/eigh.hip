@@ -1,20 +1,23 @@
 // Batched symmetric eigendecomposition H = V diag(lam) V^T by block Jacobi
 // (the EVD step of the SVD-via-polar algorithm, Algorithm 1).
 //
-// The (padded) index range is cut into 32-wide blocks; a parallel step pairs
-// the blocks round-robin, and each pair (P, Q) owns the 64 x 64 subproblem
+// The (padded) index range is cut into 16-wide blocks; a parallel step pairs
+// the blocks round-robin, and each pair (P, Q) owns the 32 x 32 subproblem
 // H[P u Q, P u Q].
-//   * k_jac_solve: one workgroup per pair runs cyclic scalar Jacobi sweeps on
-//     the subproblem in LDS (32 disjoint rotations per inner step, each 2 x 2
-//     block of the subproblem updated independently), accumulates the 64 x 64
-//     orthogonal J, writes the rotated diagonal block back into H and J to a
-//     per-pair buffer.  FP32, or FP64 for the final sweep.
+//   * k_jac_solve: one WAVEFRONT per pair runs a cyclic scalar Jacobi sweep on
+//     the subproblem held in its own slice of LDS (16 disjoint rotations per
+//     inner step; each 2 x 2 block of the subproblem is updated independently),
+//     accumulates the 32 x 32 orthogonal J in FP64, writes the rotated
+//     diagonal block back into H and J to a per-pair buffer.  The wave works
+//     alone on its data, so its inner steps need no workgroup barrier: LDS
+//     operations of one wave complete in program order.  FP32 subproblem
+//     arithmetic, or FP64 for the final sweep.
 //   * k_jac_apply: every off-diagonal pair block H[P, R] <- J_P^T H[P, R] J_R
-//     (upper triangle only, mirrored) and every 64-row slab V[:, P] <-
-//     V[:, P] J_P, as 64 x 64 x 64 products on FP32 MFMA (32x32x2).
-// A sweep is nb - 1 steps.  A matrix has converged when a sweep rotated no
-// pair with |h_pq| > tol sqrt(|h_pp h_qq|) (and above an absolute floor);
-// converged matrices are skipped by later launches.
+//     (upper triangle, mirrored) and every 32-row slab V[:, P] <- V[:, P] J_P,
+//     one wavefront per 32 x 32 x 32 product on FP32 MFMA (32x32x2).
+// A sweep is nb - 1 steps.  Convergence is tested per matrix on the largest
+// relative off-diagonal entry rotated during a sweep; converged matrices are
+// skipped by later launches.
 #include <algorithm>
 #include <cstring>
 #include "common.hpp"
@@ -22,6 +25,11 @@
 #include "prof.hpp"
 
 namespace {
+
+constexpr int BS = 16;       // block width
+constexpr int PB = 2 * BS;   // pair subproblem size (32)
+constexpr int NPP = PB / 2;  // disjoint rotations per inner step (16)
+constexpr int LP = PB + 1;   // LDS row pitch
 
 // Round-robin (circle method) pairing of `players` (even) in `round`:
 // position 0 is fixed, the others rotate; pair k joins positions k and
@@ -35,8 +43,15 @@ SVDP_DEV void rr_pair(int k, int round, int players, int& x, int& y) {
   y = a < c ? c : a;
 }
 
-// local index (0..63) of a pair subproblem -> global index
-SVDP_DEV int gidx(int a, int p, int q) { return a < 32 ? p * 32 + a : q * 32 + (a - 32); }
+// local index (0..31) of a pair subproblem -> global index
+SVDP_DEV int gidx(int a, int p, int q) { return a < BS ? p * BS + a : q * BS + (a - BS); }
+
+// orders the wave's own LDS traffic: no instruction is moved across it, and
+// LDS operations of one wave complete in issue order
+SVDP_DEV void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
 
 template <typename R>
 SVDP_DEV void rotation(R app, R aqq, R apq, R& c, R& s) {
@@ -50,185 +65,200 @@ SVDP_DEV void rotation(R app, R aqq, R apq, R& c, R& s) {
 
 template <typename R>
 __global__ __launch_bounds__(256) void k_jac_solve(EighWs e, int step, int inner_sweeps,
-                                                   float conv_tol, float abs_tol, int* rotcnt) {
+                                                   float abs_tol, int* rotmax) {
+  __shared__ R Sall[4][PB][LP];
+  __shared__ double Jall[4][PB][LP];
+  __shared__ R csall[4][2][NPP];
+  __shared__ unsigned char ptab[PB - 1][NPP][2];
+  const int t = threadIdx.x;
+  for (int i = t; i < (PB - 1) * NPP; i += 256) {
+    int x, y;
+    rr_pair(i % NPP, i / NPP, PB, x, y);
+    ptab[i / NPP][i % NPP][0] = (unsigned char)x;
+    ptab[i / NPP][i % NPP][1] = (unsigned char)y;
+  }
+  __syncthreads();
+  const int wave = t >> 6, lane = t & 63;
   const int npairs = e.nb / 2;
-  const int b = blockIdx.x / npairs, k = blockIdx.x - b * npairs;
+  const int task = blockIdx.x * 4 + wave;
+  const int b = task / npairs, k = task - b * npairs;
   if (b >= e.batch) return;
   if (e.active && !e.active[b]) return;
+  R (*S)[LP] = Sall[wave];
+  double (*J)[LP] = Jall[wave];
+  R* cs_c = csall[wave][0];
+  R* cs_s = csall[wave][1];
   int p, q;
   rr_pair(k, step, e.nb, p, q);
-  __shared__ R S[64][65];
-  __shared__ double J[64][65];  // accumulated in FP64: J is a product of ~100 rotations
-  __shared__ R cs_c[32], cs_s[32];
-  __shared__ unsigned char ptab[63][32][2];  // inner round-robin pairs per step
-  __shared__ int any_rot;
-  __shared__ float max_rel;
-  const int t = threadIdx.x;
-  for (int i = t; i < 63 * 32; i += 256) {
-    int x, y;
-    rr_pair(i & 31, i >> 5, 64, x, y);
-    ptab[i >> 5][i & 31][0] = (unsigned char)x;
-    ptab[i >> 5][i & 31][1] = (unsigned char)y;
-  }
   float* H = e.Hw + (int64_t)b * e.np * e.np;
-  for (int idx = t; idx < 4096; idx += 256) {
-    int a = idx >> 6, c = idx & 63;
+  for (int idx = lane; idx < PB * PB; idx += 64) {
+    int a = idx / PB, c = idx % PB;
     S[a][c] = (R)H[(int64_t)gidx(a, p, q) * e.np + gidx(c, p, q)];
     J[a][c] = a == c ? 1.0 : 0.0;
   }
-  if (t == 0) max_rel = 0.f;
   const R floor_abs = (R)abs_tol * (R)sqrtf(e.hnorm2[b]);
+  float mrel = 0.f;
+  wave_sync();
   for (int sw = 0; sw < inner_sweeps; ++sw) {
-    if (t == 0) any_rot = 0;
-    __syncthreads();
-    for (int s = 0; s < 63; ++s) {
-      if (t < 32) {
-        const int x = ptab[s][t][0], y = ptab[s][t][1];
+    int any = 0;
+    for (int s = 0; s < PB - 1; ++s) {
+      if (lane < NPP) {
+        const int x = ptab[s][lane][0], y = ptab[s][lane][1];
         R app = S[x][x], aqq = S[y][y], apq = S[y][x] * R(0.5) + S[x][y] * R(0.5);
         R c = 1, sn = 0;
         if (apq != R(0) && isfinite((float)apq)) {
           rotation(app, aqq, apq, c, sn);
-          any_rot = 1;
+          any = 1;
           if (fabs(apq) > floor_abs) {
             R den = sqrt(fabs(app * aqq));
-            float rel = den > R(0) ? (float)(fabs(apq) / den) : 1e30f;
-            atomicMax((int*)&max_rel, __float_as_int(rel));  // rel >= 0
+            mrel = fmaxf(mrel, den > R(0) ? (float)(fabs(apq) / den) : 1e30f);
           }
         }
-        cs_c[t] = c;
-        cs_s[t] = sn;
+        cs_c[lane] = c;
+        cs_s[lane] = sn;
       }
-      __syncthreads();
-      for (int blk = t; blk < 1024; blk += 256) {
-        int kx = blk >> 5, ky = blk & 31;
+      wave_sync();
+      // 16 x 16 blocks of 2 x 2, four per lane
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int blk = lane + 64 * u;
+        const int kx = blk >> 4, ky = blk & 15;
         const int x1 = ptab[s][kx][0], y1 = ptab[s][kx][1];
         const int x2 = ptab[s][ky][0], y2 = ptab[s][ky][1];
-        R c1 = cs_c[kx], s1 = cs_s[kx], c2 = cs_c[ky], s2 = cs_s[ky];
-        R a = S[x1][x2], bq = S[x1][y2], cq = S[y1][x2], d = S[y1][y2];
-        R t00 = c1 * a - s1 * cq, t01 = c1 * bq - s1 * d;
-        R t10 = s1 * a + c1 * cq, t11 = s1 * bq + c1 * d;
+        const R c1 = cs_c[kx], s1 = cs_s[kx], c2 = cs_c[ky], s2 = cs_s[ky];
+        const R a = S[x1][x2], bq = S[x1][y2], cq = S[y1][x2], d = S[y1][y2];
+        const R t00 = c1 * a - s1 * cq, t01 = c1 * bq - s1 * d;
+        const R t10 = s1 * a + c1 * cq, t11 = s1 * bq + c1 * d;
         R y00 = c2 * t00 - s2 * t01, y01 = s2 * t00 + c2 * t01;
         R y10 = c2 * t10 - s2 * t11, y11 = s2 * t10 + c2 * t11;
         if (kx == ky && s1 != R(0)) { y01 = 0; y10 = 0; }
         S[x1][x2] = y00; S[x1][y2] = y01; S[y1][x2] = y10; S[y1][y2] = y11;
       }
-      for (int it = t; it < 2048; it += 256) {
-        int r = it >> 5, kk = it & 31;
+      // rotation accumulation: 32 rows x 16 pairs, eight per lane
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int it = lane + 64 * u;
+        const int r = it >> 4, kk = it & 15;
         const int x = ptab[s][kk][0], y = ptab[s][kk][1];
-        double c = cs_c[kk], sn = cs_s[kk];
-        double jx = J[r][x], jy = J[r][y];
+        const double c = cs_c[kk], sn = cs_s[kk];
+        const double jx = J[r][x], jy = J[r][y];
         J[r][x] = c * jx - sn * jy;
         J[r][y] = sn * jx + c * jy;
       }
-      __syncthreads();
+      wave_sync();
     }
-    if (!any_rot) break;
+    // every lane of the wave takes the same exit
+    if (!__any(any)) break;
   }
-  __syncthreads();
-  for (int idx = t; idx < 4096; idx += 256) {
-    int a = idx >> 6, c = idx & 63;
+  for (int idx = lane; idx < PB * PB; idx += 64) {
+    int a = idx / PB, c = idx % PB;
     H[(int64_t)gidx(a, p, q) * e.np + gidx(c, p, q)] = (float)S[a][c];
-    e.Qw[((int64_t)b * npairs + k) * 4096 + idx] = (float)J[a][c];
+    e.Qw[((int64_t)b * npairs + k) * (PB * PB) + idx] = (float)J[a][c];
   }
-  // largest relative off-diagonal entry rotated by this workgroup (as bits)
-  if (t == 0 && rotcnt) atomicMax(rotcnt + b, __float_as_int(max_rel));
+  // largest relative off-diagonal entry rotated by this wave (float bits)
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) mrel = fmaxf(mrel, __shfl_xor(mrel, off));
+  if (lane == 0 && rotmax) atomicMax(rotmax + b, __float_as_int(mrel));
 }
 
-// 64 x 64 x 64 product on one workgroup: wave w owns the 32 x 32 quadrant
-// (w / 2, w % 2).  Xa is read as A[i][k] = xa(i, k), Jb as B[k][j].
-constexpr int LP = 65;
-
-SVDP_DEV f16v mm64(const float (*A)[LP], bool a_trans, const float (*Bm)[LP], int wm, int wn, int lane) {
+// 32 x 32 x 32 product on one wavefront: A read as A[i][k] (or A[k][i] when
+// a_trans), B as B[k][j]; returns the 32 x 32 MFMA accumulator (lane l,
+// slot 4g + r -> row 8g + 4(l / 32) + r, column l % 32).
+SVDP_DEV f16v mm32(const float (*A)[LP], bool a_trans, const float (*Bm)[LP], int lane) {
   f16v acc;
 #pragma unroll
   for (int e2 = 0; e2 < 16; ++e2) acc[e2] = 0.f;
-#pragma unroll 8
-  for (int kk = 0; kk < 64; kk += 2) {
-    const int kr = kk + (lane >> 5), ic = lane & 31;
-    float av = a_trans ? A[kr][wm * 32 + ic] : A[wm * 32 + ic][kr];
-    float bv = Bm[kr][wn * 32 + ic];
+  const int kh = lane >> 5, ic = lane & 31;
+#pragma unroll
+  for (int kk = 0; kk < PB; kk += 2) {
+    float av = a_trans ? A[kk + kh][ic] : A[ic][kk + kh];
+    float bv = Bm[kk + kh][ic];
     acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
   }
   return acc;
 }
 
 __global__ __launch_bounds__(256) void k_jac_apply(EighWs e, int step) {
+  __shared__ float Xall[4][PB][LP];
+  __shared__ float JLall[4][PB][LP];
+  __shared__ float JRall[4][PB][LP];
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
   const int npairs = e.nb / 2;
   const int nh = npairs * (npairs - 1) / 2;
-  const int nrc = e.np / 64;
-  const int ntask = nh + nrc * npairs;
-  const int b = blockIdx.x / ntask, task = blockIdx.x - b * ntask;
+  const int nrs = e.np / PB;
+  const int ntask = nh + nrs * npairs;
+  const int gt = blockIdx.x * 4 + wave;
+  const int b = gt / ntask, task = gt - b * ntask;
   if (b >= e.batch) return;
   if (e.active && !e.active[b]) return;
-  __shared__ float X[64][LP];
-  __shared__ float Jl[64][LP];
-  __shared__ float Jr[64][LP];
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6, wm = w >> 1, wn = w & 1;
+  float (*X)[LP] = Xall[wave];
+  float (*JL)[LP] = JLall[wave];
+  float (*JR)[LP] = JRall[wave];
   float* H = e.Hw + (int64_t)b * e.np * e.np;
   float* V = e.Vw + (int64_t)b * e.np * e.np;
-  const float* Q = e.Qw + (int64_t)b * npairs * 4096;
+  const float* Q = e.Qw + (int64_t)b * npairs * (PB * PB);
+  const int jc = lane & 31;
   if (task < nh) {
     // upper-triangular pair index (kp < kr)
     int tt = task, kp = 0;
     while (tt >= npairs - 1 - kp) { tt -= npairs - 1 - kp; ++kp; }
-    int kr = kp + 1 + tt;
+    const int kr = kp + 1 + tt;
     int p1, q1, p2, q2;
     rr_pair(kp, step, e.nb, p1, q1);
     rr_pair(kr, step, e.nb, p2, q2);
-    for (int idx = t; idx < 1024; idx += 256) {
-      int a = idx >> 4, c = (idx & 15) * 4;
-      f4v v = *(const f4v*)&H[(int64_t)gidx(a, p1, q1) * e.np + gidx(c, p2, q2)];
-      X[a][c] = v[0]; X[a][c + 1] = v[1]; X[a][c + 2] = v[2]; X[a][c + 3] = v[3];
-      f4v jl = *(const f4v*)&Q[(int64_t)kp * 4096 + a * 64 + c];
-      f4v jr = *(const f4v*)&Q[(int64_t)kr * 4096 + a * 64 + c];
-      for (int u = 0; u < 4; ++u) { Jl[a][c + u] = jl[u]; Jr[a][c + u] = jr[u]; }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int idx = lane + 64 * u;  // 32 rows x 8 float4
+      const int a = idx >> 3, c = (idx & 7) * 4;
+      const f4v v = *(const f4v*)&H[(int64_t)gidx(a, p1, q1) * e.np + gidx(c, p2, q2)];
+      const f4v jl = *(const f4v*)&Q[(int64_t)kp * (PB * PB) + a * PB + c];
+      const f4v jr = *(const f4v*)&Q[(int64_t)kr * (PB * PB) + a * PB + c];
+#pragma unroll
+      for (int w2 = 0; w2 < 4; ++w2) { X[a][c + w2] = v[w2]; JL[a][c + w2] = jl[w2]; JR[a][c + w2] = jr[w2]; }
     }
-    __syncthreads();
-    f16v T = mm64(Jl, true, X, wm, wn, lane);  // J_P^T X
-    __syncthreads();
+    wave_sync();
+    const f16v T = mm32(JL, true, X, lane);  // J_P^T X
+    wave_sync();
 #pragma unroll
-    for (int qd = 0; qd < 4; ++qd)
+    for (int g = 0; g < 4; ++g)
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
-        X[wm * 32 + 8 * qd + 4 * (lane >> 5) + r][wn * 32 + (lane & 31)] = T[4 * qd + r];
-    __syncthreads();
-    f16v Y = mm64(X, false, Jr, wm, wn, lane);  // (J_P^T X) J_R
-    const int j = wn * 32 + (lane & 31);
-    const int gj = gidx(j, p2, q2);
+      for (int r = 0; r < 4; ++r) X[8 * g + 4 * (lane >> 5) + r][jc] = T[4 * g + r];
+    wave_sync();
+    const f16v Y = mm32(X, false, JR, lane);  // (J_P^T X) J_R
+    const int gj = gidx(jc, p2, q2);
 #pragma unroll
-    for (int qd = 0; qd < 4; ++qd) {
-      const int i0 = wm * 32 + 8 * qd + 4 * (lane >> 5);
+    for (int g = 0; g < 4; ++g) {
+      const int i0 = 8 * g + 4 * (lane >> 5);
       f4v col;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int gi = gidx(i0 + r, p1, q1);
-        H[(int64_t)gi * e.np + gj] = Y[4 * qd + r];
-        col[r] = Y[4 * qd + r];
+        H[(int64_t)gidx(i0 + r, p1, q1) * e.np + gj] = Y[4 * g + r];
+        col[r] = Y[4 * g + r];
       }
-      // mirror: row gj, columns gidx(i0..i0+3) are contiguous (same 32-block)
+      // mirror: row gj, columns gidx(i0 .. i0+3) are contiguous (one 16-block)
       *(f4v*)&H[(int64_t)gj * e.np + gidx(i0, p1, q1)] = col;
     }
   } else {
-    const int v = task - nh, rc = v / npairs, kp = v - rc * npairs;
+    const int v = task - nh, rs = v / npairs, kp = v - rs * npairs;
     int p1, q1;
     rr_pair(kp, step, e.nb, p1, q1);
-    for (int idx = t; idx < 1024; idx += 256) {
-      int a = idx >> 4, c = (idx & 15) * 4;
-      f4v x = *(const f4v*)&V[(int64_t)(rc * 64 + a) * e.np + gidx(c, p1, q1)];
-      f4v jl = *(const f4v*)&Q[(int64_t)kp * 4096 + a * 64 + c];
-      for (int u = 0; u < 4; ++u) { X[a][c + u] = x[u]; Jl[a][c + u] = jl[u]; }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int idx = lane + 64 * u;
+      const int a = idx >> 3, c = (idx & 7) * 4;
+      const f4v x = *(const f4v*)&V[(int64_t)(rs * PB + a) * e.np + gidx(c, p1, q1)];
+      const f4v jl = *(const f4v*)&Q[(int64_t)kp * (PB * PB) + a * PB + c];
+#pragma unroll
+      for (int w2 = 0; w2 < 4; ++w2) { X[a][c + w2] = x[w2]; JL[a][c + w2] = jl[w2]; }
     }
-    __syncthreads();
-    f16v Y = mm64(X, false, Jl, wm, wn, lane);
-    const int j = wn * 32 + (lane & 31);
-    const int gj = gidx(j, p1, q1);
+    wave_sync();
+    const f16v Y = mm32(X, false, JL, lane);
+    const int gj = gidx(jc, p1, q1);
 #pragma unroll
-    for (int qd = 0; qd < 4; ++qd)
+    for (int g = 0; g < 4; ++g)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = wm * 32 + 8 * qd + 4 * (lane >> 5) + r;
-        V[(int64_t)(rc * 64 + i) * e.np + gj] = Y[4 * qd + r];
-      }
+      for (int r = 0; r < 4; ++r)
+        V[(int64_t)(rs * PB + 8 * g + 4 * (lane >> 5) + r) * e.np + gj] = Y[4 * g + r];
   }
 }
 
@@ -413,12 +443,12 @@ hipError_t fill_f32(float* p, float v, int64_t n, hipStream_t st) {
 }
 
 size_t eigh_ws_bytes(int64_t batch, int64_t n, int max_sweeps) {
-  int64_t np = (n + 63) / 64 * 64;
-  int64_t npairs = np / 64;
+  int64_t np = (n + 31) / 32 * 32;
+  int64_t npairs = np / 32;
   size_t f = 0;
   f += 3 * batch * np * np;          // Hw, Vw, V2
   f += batch * n;                    // lamr
-  f += batch * npairs * 4096;        // Qw
+  f += batch * npairs * 1024;        // Qw
   f += batch;                        // hnorm2
   f += 2 * batch * n;                // sign, (perm as int)
   size_t i = batch * (size_t)(max_sweeps + 2) + batch + 16;  // rotcnt, active, counters
@@ -429,16 +459,16 @@ EighWs eigh_ws_carve(void* ws, int64_t batch, int64_t n, int max_sweeps) {
   EighWs e;
   e.batch = (int)batch;
   e.n = (int)n;
-  e.np = (int)((n + 63) / 64 * 64);
-  e.nb = e.np / 32;
-  int64_t np = e.np, npairs = np / 64;
+  e.np = (int)((n + 31) / 32 * 32);
+  e.nb = e.np / 16;
+  int64_t np = e.np, npairs = np / 32;
   char* p = (char*)ws;
   auto take = [&](size_t bytes) { char* r = p; p += (bytes + 255) / 256 * 256; return (void*)r; };
   e.Hw = (float*)take(batch * np * np * 4);
   e.Vw = (float*)take(batch * np * np * 4);
   e.V2 = (float*)take(batch * np * np * 4);
   e.lamr = (float*)take(batch * n * 4);
-  e.Qw = (float*)take(batch * npairs * 4096 * 4);
+  e.Qw = (float*)take(batch * npairs * 1024 * 4);
   e.hnorm2 = (float*)take(batch * 4);
   e.sgn = (float*)take(batch * n * 4);
   e.perm = (int*)take(batch * n * 4);
@@ -467,14 +497,16 @@ hipError_t eigh_run(EighWs e, const float* H, int64_t ldh, int64_t sH, int mode,
   }
   const int npairs = e.nb / 2;
   const int nh = npairs * (npairs - 1) / 2;
-  const int ntask = nh + (e.np / 64) * npairs;
+  const int ntask = nh + (e.np / 32) * npairs;
   const int steps = e.nb - 1;
+  const unsigned solve_blocks = (unsigned)cdiv((int64_t)batch * npairs, 4);
+  const unsigned apply_blocks = (unsigned)cdiv((int64_t)batch * ntask, 4);
   // algorithmic flops per matrix and step: pair solves (2 x 2 block updates,
   // 24 flops each, and rotation accumulation, 6 per entry pair) and the
-  // block rotations (two 64^3 products per off-diagonal pair block, one per
-  // 64-row slab of V)
-  const double solve_work = (double)npairs * 63.0 * (1024.0 * 24.0 + 2048.0 * 6.0);
-  const double apply_work = (double)nh * 4.0 * 262144.0 + (double)(e.np / 64) * npairs * 2.0 * 262144.0;
+  // block rotations (two 32^3 products per off-diagonal pair block, one per
+  // 32-row slab of V)
+  const double solve_work = (double)npairs * 31.0 * (256.0 * 24.0 + 512.0 * 6.0);
+  const double apply_work = (double)nh * 4.0 * 32768.0 + (double)(e.np / 32) * npairs * 2.0 * 32768.0;
   int n_active = batch;
   if (mask) {  // active count of a masked run is only needed for the work tally
     n_active = batch;
@@ -485,13 +517,13 @@ hipError_t eigh_run(EighWs e, const float* H, int64_t ldh, int64_t sH, int mode,
     for (int s = 0; s < steps; ++s) {
       {
         ProfScope ps(PROF_JAC_SOLVE_F32, st, solve_work * o.inner_sweeps * n_active);
-        hipLaunchKernelGGL(k_jac_solve<float>, dim3(batch * npairs), dim3(256), 0, st, e, s,
-                           o.inner_sweeps, o.tol, o.abs_tol, rc);
+        hipLaunchKernelGGL(k_jac_solve<float>, dim3(solve_blocks), dim3(256), 0, st, e, s,
+                           o.inner_sweeps, o.abs_tol, rc);
       }
       if ((err = hipGetLastError())) return err;
       if (ntask > 0) {
         ProfScope ps(PROF_JAC_APPLY, st, apply_work * n_active);
-        hipLaunchKernelGGL(k_jac_apply, dim3(batch * ntask), dim3(256), 0, st, e, s);
+        hipLaunchKernelGGL(k_jac_apply, dim3(apply_blocks), dim3(256), 0, st, e, s);
         if ((err = hipGetLastError())) return err;
       }
     }
@@ -517,13 +549,13 @@ hipError_t eigh_run(EighWs e, const float* H, int64_t ldh, int64_t sH, int mode,
       for (int s = 0; s < steps; ++s) {
         {
           ProfScope ps(PROF_JAC_SOLVE_F64, st, solve_work * o.fp64_inner * batch);
-          hipLaunchKernelGGL(k_jac_solve<double>, dim3(batch * npairs), dim3(256), 0, st, e, s,
-                             o.fp64_inner, o.tol, o.abs_tol, (int*)nullptr);
+          hipLaunchKernelGGL(k_jac_solve<double>, dim3(solve_blocks), dim3(256), 0, st, e, s,
+                             o.fp64_inner, o.abs_tol, (int*)nullptr);
         }
         if ((err = hipGetLastError())) return err;
         if (ntask > 0) {
           ProfScope ps(PROF_JAC_APPLY, st, apply_work * batch);
-          hipLaunchKernelGGL(k_jac_apply, dim3(batch * ntask), dim3(256), 0, st, e, s);
+          hipLaunchKernelGGL(k_jac_apply, dim3(apply_blocks), dim3(256), 0, st, e, s);
           if ((err = hipGetLastError())) return err;
         }
       }
