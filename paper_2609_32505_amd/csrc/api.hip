@@ -138,9 +138,10 @@ EighOpts eigh_opts(const svdp_params* p) {
 
 struct FwdWs {
   float *X0, *X1, *G;
+  void *Y0, *Y1;  // BF16 iterates (never aliasing the FP32 ones)
   void* eigh;
   float *scale, *conv, *resid, *colsum, *rowmax, *fro2, *coef, *rcoef, *F, *aux, *mlpout, *nrm, *y0, *y1;
-  int *active, *where, *iters, *flags, *sweeps, *mask, *counter, *ksteps, *kmax;
+  int *active, *where, *iters, *flags, *sweeps, *mask, *counter, *ksteps, *kmax, *hist, *gmask;
 };
 
 FwdWs carve_fwd(void* base, const svdp_params* p, size_t* total) {
@@ -149,6 +150,8 @@ FwdWs carve_fwd(void* base, const svdp_params* p, size_t* total) {
   const size_t b = p->batch, m = p->m, n = p->n;
   w.X0 = c.take<float>(b * m * n);
   w.X1 = c.take<float>(b * m * n);
+  w.Y0 = c.take<uint16_t>(b * m * n);
+  w.Y1 = c.take<uint16_t>(b * m * n);
   w.G = c.take<float>(b * n * n);
   w.eigh = c.take_bytes(eigh_ws_bytes(b, n, p->max_sweeps));
   w.scale = c.take<float>(b);
@@ -171,9 +174,11 @@ FwdWs carve_fwd(void* base, const svdp_params* p, size_t* total) {
   w.flags = c.take<int>(b);
   w.sweeps = c.take<int>(b);
   w.mask = c.take<int>(b);
+  w.gmask = c.take<int>(b);
   w.counter = c.take<int>(16);
-  w.ksteps = c.take<int>(b);
+  w.ksteps = c.take<int>(2 * b);
   w.kmax = c.take<int>(16);
+  w.hist = c.take<int>(2 * 65);
   if (total) *total = c.off;
   return w;
 }
@@ -309,45 +314,54 @@ svdp_status bounded(Ctx& c) {
     HIPCHK(bounds_launch(B, 1, nullptr, nullptr, p->user_bounds, p->margin_max, p->margin_min, p->bf16_handoff,
                          p->bf16_from, kcap, w.scale, w.coef, w.ksteps, w.kmax, nullptr, c.st), "bounds");
   }
-  // kmax[0] = steps to the hand-off, kmax[1] = FP32 steps before BF16 (batch maxima)
-  int K = 0, K1 = 0;
-  {
-    HIPCHK(hipMemcpyAsync(c.h->host_word, w.kmax, 2 * sizeof(int), hipMemcpyDeviceToHost, c.st), "kmax copy");
-    HIPCHK(hipStreamSynchronize(c.st), "kmax sync");
-    K = c.h->host_word[0];
-    K1 = c.h->host_word[1];
-  }
-  K = std::max(1, std::min(K, kcap));
+  // Matrices are grouped by their own step count K (to the BF16 hand-off);
+  // each group runs its schedule under a mask: FP32 steps [0, K1), BF16
+  // steps [K1, K) with K1 the group's largest FP32 count, then the FP32
+  // refinement.  The host reads the histogram of K (one synchronisation).
+  HIPCHK(step_hist_launch(B, w.ksteps, kcap, w.hist, w.hist + 65, c.st), "step hist");
+  HIPCHK(hipMemcpyAsync(c.h->host_word, w.hist, 130 * sizeof(int), hipMemcpyDeviceToHost, c.st), "hist copy");
+  HIPCHK(hipStreamSynchronize(c.st), "hist sync");
+  int hist[65], k1g[65];
+  for (int i = 0; i <= kcap; ++i) { hist[i] = c.h->host_word[i]; k1g[i] = c.h->host_word[65 + i]; }
   const int bf16 = p->precision == SVDP_PREC_BF16;
-  K1 = bf16 ? std::max(0, std::min(K1, K)) : K;
-  // steps [0, K1) in FP32 while small singular values are still small
-  // (BF16 rounding would rotate their singular vectors), [K1, K) in BF16
-  HIPCHK(scale_copy_launch(c.A, c.lda, c.sA, B, m, n, w.scale, w.X0, K1 == 0 ? 1 : 0, nullptr, c.st), "normalise");
-  for (int k = 0; k < K; ++k) {
-    const void* Xc = (k & 1) ? w.X1 : w.X0;
-    void* Xn = (k & 1) ? w.X0 : w.X1;
-    const int prec = k < K1 ? PREC_F32 : PREC_BF16;
-    const int in_bf = k >= K1;
-    const int out_bf = (k + 1 >= K1) && (k + 1 < K);
-    HIPCHK(cans_step(c, prec, Xc, Xn, in_bf, out_bf, w.coef, kcap, k, nullptr, nullptr), "cans step");
-  }
-  // FP32 refinement: interval recursion from [1 - h, 1 + h]
   const int R = p->refine_steps;
+  double rtab[128];
   if (R > 0) {
-    double tab[128];
     double h = std::min(std::max(p->bf16_handoff, 1e-8), 0.5);
-    table_interval(1.0 - h, R, tab);
-    float* tcoef = w.rcoef;
-    HIPCHK(set_coef_launch(tcoef, tab, R, c.st), "refine coef");
+    table_interval(1.0 - h, R, rtab);
+    HIPCHK(set_coef_launch(w.rcoef, rtab, R, c.st), "refine coef");
+  }
+  for (int Kg = 0; Kg <= kcap; ++Kg) {
+    const int count = hist[Kg];
+    if (count == 0) continue;
+    const int K = std::max(1, Kg);
+    const int K1 = bf16 ? std::max(0, std::min(k1g[Kg], K)) : K;
+    const int* gm = w.gmask;
+    HIPCHK(group_mask_launch(B, w.ksteps, Kg, w.gmask, c.st), "group mask");
+    // steps [0, K1) in FP32 while small singular values are still small
+    // (BF16 rounding would rotate their singular vectors), [K1, K) in BF16
+    // iterate after step k lives in X[k % 2] (FP32) or Y[k % 2] (BF16)
+    auto buf = [&](int k, int isbf) -> void* {
+      return isbf ? ((k & 1) ? w.Y1 : w.Y0) : (void*)((k & 1) ? w.X1 : w.X0);
+    };
+    HIPCHK(scale_copy_launch(c.A, c.lda, c.sA, B, m, n, w.scale, buf(0, K1 == 0), K1 == 0 ? 1 : 0, gm, c.st),
+           "normalise");
+    for (int k = 0; k < K; ++k) {
+      const int prec = k < K1 ? PREC_F32 : PREC_BF16;
+      const int in_bf = k >= K1;
+      const int out_bf = (k + 1 >= K1) && (k + 1 < K);
+      HIPCHK(cans_step(c, prec, buf(k, in_bf), buf(k + 1, out_bf), in_bf, out_bf, w.coef, kcap, k, gm, nullptr,
+                       count), "cans step");
+    }
     for (int r = 0; r < R; ++r) {
       const int k = K + r;
       const float* Xc = (k & 1) ? w.X1 : w.X0;
       float* Xn = (k & 1) ? w.X0 : w.X1;
-      HIPCHK(cans_step(c, PREC_F32, Xc, Xn, 0, 0, tcoef, 0, r, nullptr, nullptr), "refine step");
+      HIPCHK(cans_step(c, PREC_F32, Xc, Xn, 0, 0, w.rcoef, 0, r, gm, nullptr, count), "refine step");
     }
+    HIPCHK(fill_masked_launch(w.where, (K + R) & 1, B, gm, c.st), "where");
+    HIPCHK(fill_masked_launch(w.iters, K + R, B, gm, c.st), "iters");
   }
-  HIPCHK(fill_i32(w.where, (K + R) & 1, B, c.st), "where");
-  HIPCHK(fill_i32(w.iters, K + R, B, c.st), "iters");
   return SVDP_OK;
 }
 
@@ -484,7 +498,7 @@ svdp_status svdp_create(svdp_handle** out) {
   if (!out) return fail(SVDP_ERR_INVALID_ARG, "null handle pointer");
   svdp_handle* h = new svdp_handle();
   hipError_t e = hipMalloc((void**)&h->model, SVDP_MODEL_FLOATS * sizeof(float));
-  if (e == hipSuccess) e = hipHostMalloc((void**)&h->host_word, 64, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&h->host_word, 4096, hipHostMallocDefault);
   if (e != hipSuccess) {
     if (h->model) (void)hipFree(h->model);
     delete h;

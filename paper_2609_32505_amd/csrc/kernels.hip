@@ -592,7 +592,8 @@ __global__ void k_bounds(int batch, int mode, const float* mlp_out, const float*
     if (K == kcap && fmax(1.0 - a, hb - 1.0) <= handoff) K = k + 1;
     if (K1 == kcap && a >= bf16_from) K1 = k + 1;
   }
-  ksteps[b] = K;
+  ksteps[2 * b] = K;
+  ksteps[2 * b + 1] = K1;
   atomicMax(kmax, K);
   atomicMax(kmax + 1, K1);
 }
@@ -858,5 +859,35 @@ __global__ void k_count_mask(int batch, const int* mask, int* counter) {
 
 hipError_t count_mask_launch(int batch, const int* mask, int* counter, hipStream_t st) {
   hipLaunchKernelGGL(k_count_mask, dim3(1), dim3(1024), 0, st, batch, mask, counter);
+  LAUNCH_CHECK();
+}
+
+namespace {
+// hist[K] = matrices whose schedule has K steps; k1[K] = their largest FP32
+// step count (K1); both arrays have kcap + 1 entries, cleared here first.
+__global__ void k_step_hist(int batch, const int* ksteps, int kcap, int* hist, int* k1) {
+  __shared__ int h[65], m1[65];
+  for (int i = threadIdx.x; i <= kcap; i += blockDim.x) { h[i] = 0; m1[i] = 0; }
+  __syncthreads();
+  for (int b = threadIdx.x; b < batch; b += blockDim.x) {
+    int K = min(max(ksteps[2 * b], 0), kcap);
+    atomicAdd(&h[K], 1);
+    atomicMax(&m1[K], ksteps[2 * b + 1]);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i <= kcap; i += blockDim.x) { hist[i] = h[i]; k1[i] = m1[i]; }
+}
+__global__ void k_group_mask(int batch, const int* ksteps, int K, int* mask) {
+  int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < batch) mask[b] = ksteps[2 * b] == K;
+}
+}  // namespace
+
+hipError_t step_hist_launch(int batch, const int* ksteps, int kcap, int* hist, int* k1, hipStream_t st) {
+  hipLaunchKernelGGL(k_step_hist, dim3(1), dim3(1024), 0, st, batch, ksteps, kcap, hist, k1);
+  LAUNCH_CHECK();
+}
+hipError_t group_mask_launch(int batch, const int* ksteps, int K, int* mask, hipStream_t st) {
+  hipLaunchKernelGGL(k_group_mask, dim3(cdiv(batch, 256)), dim3(256), 0, st, batch, ksteps, K, mask);
   LAUNCH_CHECK();
 }

@@ -79,8 +79,9 @@ hipError_t adam_launch(float* p, float* m, float* v, const float* g, int64_t n, 
                        float b2, float eps, int t, hipStream_t st);
 // Learned / user bounds -> per-matrix scale, interval-optimal coefficient
 // table and BF16 step count (FP64 scalar recursion); *kmax = max count.
-// kmax[0] = max steps to the hand-off, kmax[1] = max FP32 steps before the
-// interval's lower end reaches bf16_from.
+// ksteps[2b] = steps of matrix b to the hand-off (K), ksteps[2b+1] = FP32
+// steps before its interval's lower end reaches bf16_from (K1); kmax[0..1]
+// the batch maxima.
 hipError_t bounds_launch(int batch, int mode, const float* mlp_out, const float* aux,
                          const float* user_bounds, double margin_max, double margin_min,
                          double handoff, double bf16_from, int kcap, float* scale, float* coef,
@@ -97,3 +98,7 @@ hipError_t or_flags_launch(int batch, int* flags, int bits, const int* mask, hip
 hipError_t fill_masked_launch(int* p, int v, int n, const int* mask, hipStream_t st);
 // *counter = number of nonzero mask entries
 hipError_t count_mask_launch(int batch, const int* mask, int* counter, hipStream_t st);
+// hist[K] = number of matrices with K steps, k1[K] = their largest K1 (kcap <= 64)
+hipError_t step_hist_launch(int batch, const int* ksteps, int kcap, int* hist, int* k1, hipStream_t st);
+// mask[b] = (K of matrix b == K)
+hipError_t group_mask_launch(int batch, const int* ksteps, int K, int* mask, hipStream_t st);
