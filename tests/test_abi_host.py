@@ -1,0 +1,112 @@
+"""Host-side checks of the C ABI (no GPU): the library loads, exports every
+function include/svdp.h declares, and its host-only entry points (defaults,
+workspace sizing, argument validation, the CANS coefficient scheduler) behave
+as documented.  The scheduler is compared with the oracle's."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    from paper_2609_32505_amd import _lib as L
+    return L, L.load()
+
+
+def _declared():
+    with open(os.path.join(ROOT, "include", "svdp.h")) as f:
+        src = f.read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = set(re.findall(r"\b([a-z_][a-z0-9_]*)\s*\(", src))
+    keywords = {"if", "for", "while", "sizeof", "return", "defined"}
+    return sorted(n for n in names if n not in keywords and (n.startswith("svd") or n.startswith("polar")))
+
+
+def test_header_functions_are_exported():
+    L, lib = _lib()
+    names = _declared()
+    assert "svd_polar_fwd" in names and "polar_bwd" in names and len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), f"{n} declared in svdp.h but not exported"
+        assert n in L.SIGNATURES, f"{n} has no ctypes signature in the binding"
+
+
+def test_params_struct_matches_header_layout():
+    L, lib = _lib()
+    # the binding's struct must have the header's field order: defaults land
+    # in the right fields
+    p = L.default_params(3, 20, 10)
+    assert (p.batch, p.m, p.n) == (3, 20, 10)
+    assert (p.max_iters, p.pre_iters, p.refine_steps) == (50, 2, 2)
+    assert p.delta == 0.99 and p.tol == 1e-5 and p.eps_qr == 1e-5
+    assert p.jacobi_tol == 1e-3 and p.bf16_from == 0.1
+    assert p.margin_max == 1.1 and p.margin_min == 0.5
+    assert p.eps_K == 0.0 and p.user_bounds is None and p.probe is None
+
+
+def _ws(p, op):
+    L, lib = _lib()
+    out = ctypes.c_size_t()
+    st = lib.svdp_workspace_size(ctypes.byref(p), op, ctypes.byref(out))
+    return st, out.value
+
+
+def test_workspace_size_and_shape_validation():
+    L, _ = _lib()
+    st, nb = _ws(L.default_params(256, 512, 512), L.OP_SVD_FWD)
+    assert st == 0 and nb > 4 * 256 * 512 * 512 * 4
+    st2, nb2 = _ws(L.default_params(256, 512, 512), L.OP_SVD_BWD)
+    assert st2 == 0 and 0 < nb2 < nb
+    assert _ws(L.default_params(1, 4, 8), L.OP_SVD_FWD)[0] == 2          # m < n
+    assert _ws(L.default_params(1, 8, 0), L.OP_SVD_FWD)[0] == 2          # n < 1
+    assert _ws(L.default_params(70000, 8, 8), L.OP_SVD_FWD)[0] == 2      # batch too large
+    assert _ws(L.default_params(1, 9000, 8193), L.OP_SVD_FWD)[0] == 2    # n too large
+    assert _ws(L.default_params(1, 8, 8), 99)[0] == 1                    # unknown op
+    assert _ws(L.default_params(1, 8, 8, max_iters=65), 0)[0] == 1
+    assert _ws(L.default_params(1, 8, 8, delta=1.5), 0)[0] == 1
+    assert _ws(L.default_params(1, 8, 8, precision=7), 0)[0] == 1
+    assert _ws(L.default_params(0, 8, 8), L.OP_SVD_FWD)[0] == 0
+
+
+def test_status_strings():
+    L, lib = _lib()
+    for code in range(6):
+        assert lib.svdp_status_string(code).decode() == L.STATUS[code]
+
+
+def test_null_handle_is_rejected_before_any_launch():
+    L, lib = _lib()
+    p = L.default_params(1, 8, 8)
+    st = lib.svd_polar_fwd(None, ctypes.byref(p), 0, 8, 64, 0, 8, 64, 0, 8, 0, 8, 64, None, None, 0, None)
+    assert st == 1
+    assert "null" in lib.svdp_last_error().decode()
+
+
+@pytest.mark.parametrize("delta,pre", [(0.99, 2), (0.9, 2), (0.999, 1)])
+def test_conservative_schedule_matches_oracle(orc, delta, pre):
+    from paper_2609_32505_amd import api
+    tab, t = api.cans_table(0, 50, delta=delta, pre_iters=pre)
+    ref = orc.cans_schedule_conservative(delta, pre, 50)
+    np.testing.assert_allclose(tab, ref, rtol=1e-13, atol=1e-13)
+    assert t == pytest.approx(orc.cans_preprocess_t(delta, pre), rel=1e-12)
+
+
+@pytest.mark.parametrize("lo", [1e-6, 1e-3, 0.2, 1.0])
+def test_interval_schedule_matches_oracle(orc, lo):
+    from paper_2609_32505_amd import api
+    tab, _ = api.cans_table(1, 30, lo=lo)
+    ref, _ = orc.cans_schedule_interval(lo, 30)
+    np.testing.assert_allclose(tab, ref, rtol=1e-13, atol=1e-13)
+
+
+def test_schedule_argument_errors():
+    L, lib = _lib()
+    tab = (ctypes.c_double * 8)()
+    assert lib.svdp_cans_table(0, 1.5, 2, 0.0, 4, tab, None) == 1
+    assert lib.svdp_cans_table(1, 0.99, 2, 0.0, 4, tab, None) == 1
+    assert lib.svdp_cans_table(2, 0.99, 2, 0.1, 4, tab, None) == 1
+    assert lib.svdp_cans_table(1, 0.99, 2, 0.1, 4, None, None) == 1

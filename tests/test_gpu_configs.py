@@ -1,0 +1,241 @@
+"""GPU parity at the workloads' full sizes, in the launch configuration the
+benchmark times: sampled outputs against the FP64 oracle, every output
+against properties that hold at any size (Weyl bound to the generating
+spectrum, reconstruction, orthogonality, flags)."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2609_32505_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+# |U^T U - I|, |V^T V - I| bound: CANS stops at a relative change of 1e-5, which
+# leaves |W^T W - I| of that order (the paper reports 2-4e-6 in FP32 at 4096^2)
+ORTH_TOL = 1e-5
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def api():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2609_32505_amd import api as _api
+    return _api
+
+
+@pytest.fixture(scope="module")
+def handle(api):
+    from paper_2609_32505_amd import predictor
+    h = api.Handle()
+    h.set_model(predictor.load())
+    return h
+
+
+def _weyl_slack(A32, s):
+    """|sigma_i(A32) - s_i| <= |A32 - A64|_2 <= |A32 - A64|_F for the FP32
+    rounding of A64 = Q1 diag(s) Q2^T; A64 is rebuilt from its seed by the
+    caller, here the slack is bounded by the FP32 unit roundoff times |A|_F."""
+    return 2.0 ** -24 * np.linalg.norm(A32.astype(np.float64), axis=(1, 2)) * 2
+
+
+def _gpu_checks(U, S, V, A, label, tol_orth):
+    import torch
+    Ad = torch.from_numpy(A).cuda()
+    rec = torch.linalg.norm(U @ torch.diag_embed(S) @ V.transpose(-1, -2) - Ad, dim=(1, 2)) / torch.linalg.norm(Ad, dim=(1, 2))
+    n = S.shape[1]
+    eye = torch.eye(n, device="cuda")
+    ou = (U.transpose(-1, -2) @ U - eye).abs().amax(dim=(1, 2))
+    ov = (V.transpose(-1, -2) @ V - eye).abs().amax(dim=(1, 2))
+    rec, ou, ov = rec.cpu().numpy(), ou.cpu().numpy(), ov.cpu().numpy()
+    _say(f"  {label}: recon max {rec.max():.2e}, |U^T U - I| max {ou.max():.2e}, |V^T V - I| max {ov.max():.2e}")
+    assert ou.max() < tol_orth and ov.max() < tol_orth
+    return rec
+
+
+def _sampled_oracle(A, U, S, V, idx, tol_s, tol_w, label):
+    for i in idx:
+        t0 = time.time()
+        Uo, So, Vo, _ = oracle.svd(A[i].astype(np.float64))
+        serr = np.abs(S[i] - So).max() / So[0]
+        Wo, Ho = oracle.polar_from_svd(Uo, So, Vo)
+        werr = np.abs(U[i] @ V[i].T - Wo).max()
+        _say(f"  {label} sample {i}: s_err {serr:.2e} W_err {werr:.2e} ({time.time() - t0:.1f}s oracle)")
+        assert serr < tol_s
+        assert werr < tol_w
+
+
+def test_square_512_batch256_both_paths(api, handle):
+    import torch
+    _say("256 x 512^2: plain FP32 and learned BF16 (benchmark configuration)")
+    A, s = inputs.square_loguniform(seed=2, batch=256, n=512)
+    Ad = torch.from_numpy(A).cuda()
+    probe = torch.from_numpy(inputs.probe(13, 256, 512)).cuda()
+    slack = _weyl_slack(A, s)
+    res = {}
+    for label, kw, tol_s, tol_w, tol_o in [
+            ("plain-fp32", {}, 1e-5, 1e-4, ORTH_TOL),
+            ("learned-bf16", dict(precision=1, bound=1, probe=probe), 1e-3, 5e-2, ORTH_TOL)]:
+        U, S, V, info = api.svd_fwd(Ad, handle=handle, **kw)
+        torch.cuda.synchronize()
+        inf = api.info_to_numpy(info)
+        Sh = S.cpu().double().numpy()
+        # Weyl: every matrix within tol * s_1 + rounding slack of its generating spectrum
+        dev = (np.abs(Sh - s).max(axis=1) - slack) / s[:, 0]
+        _say(f"  {label}: max normwise sigma deviation beyond rounding {dev.max():.2e}; iters "
+             f"{inf['iters'].min()}-{inf['iters'].max()}, sweeps {inf['sweeps'].min()}-{inf['sweeps'].max()}, "
+             f"fallbacks {int(((inf['flags'] & 2) != 0).sum())}")
+        assert dev.max() < tol_s
+        assert not np.any(inf["flags"] & (16 | 32))
+        _gpu_checks(U, S, V, A, label, tol_o)
+        Uh, Vh = U.cpu().double().numpy(), V.cpu().double().numpy()
+        _sampled_oracle(A, Uh, Sh, Vh, [0, 255], tol_s, tol_w, label)
+        res[label] = Sh
+    # the learned path agrees with the plain path on every matrix
+    assert (np.abs(res["learned-bf16"] - res["plain-fp32"]).max(axis=1) / res["plain-fp32"][:, 0]).max() < 1e-3
+
+
+def test_tall_4096x1024_batch16(api, handle):
+    import torch
+    _say("16 x 4096 x 1024, sigma log-uniform [1e-4, 1]: learned BF16 and plain FP32")
+    t0 = time.time()
+    A, s = inputs.tall_loguniform(seed=3, batch=16)
+    _say(f"  generated in {time.time() - t0:.1f}s")
+    Ad = torch.from_numpy(A).cuda()
+    probe = torch.from_numpy(inputs.probe(14, 16, 1024)).cuda()
+    slack = _weyl_slack(A, s)
+    for label, kw, tol_s in [("plain-fp32", {}, 1e-5), ("learned-bf16", dict(precision=1, bound=1, probe=probe), 1e-3)]:
+        t0 = time.time()
+        U, S, V, info = api.svd_fwd(Ad, handle=handle, **kw)
+        torch.cuda.synchronize()
+        inf = api.info_to_numpy(info)
+        Sh = S.cpu().double().numpy()
+        dev = (np.abs(Sh - s).max(axis=1) - slack) / s[:, 0]
+        _say(f"  {label}: {time.time() - t0:.2f}s, sigma deviation {dev.max():.2e}, iters {inf['iters'].max()}, "
+             f"sweeps {inf['sweeps'].max()}, flags {np.unique(inf['flags'])}")
+        assert dev.max() < tol_s
+        assert not np.any(inf["flags"] & (16 | 32))
+        _gpu_checks(U, S, V, A, label, ORTH_TOL)
+
+
+def test_tall_low_rank_plus_noise(api, handle):
+    import torch
+    _say("16 x 4096 x 1024 rank-64 signal + 1e-3 noise")
+    A, s_sig = inputs.low_rank_plus_noise(seed=4, batch=16)
+    Ad = torch.from_numpy(A).cuda()
+    probe = torch.from_numpy(inputs.probe(15, 16, 1024)).cuda()
+    U, S, V, info = api.svd_fwd(Ad, handle=handle, precision=1, bound=1, probe=probe)
+    Up, Sp, Vp, infop = api.svd_fwd(Ad, handle=handle)
+    torch.cuda.synchronize()
+    Sh, Sph = S.cpu().double().numpy(), Sp.cpu().double().numpy()
+    inf = api.info_to_numpy(info)
+    _say(f"  learned iters {inf['iters'].max()}, fallbacks {int(((inf['flags'] & 2) != 0).sum())}, "
+         f"plain iters {api.info_to_numpy(infop)['iters'].max()}")
+    assert (np.abs(Sh - Sph).max(axis=1) / Sph[:, 0]).max() < 1e-3
+    # an independent library SVD (LAPACK) on two sampled matrices
+    for i in (0, 15):
+        ref = np.linalg.svd(A[i].astype(np.float64), compute_uv=False)
+        err = np.abs(Sph[i] - ref).max() / ref[0]
+        _say(f"  sample {i}: plain vs LAPACK {err:.2e}; top-64 vs signal+noise {np.abs(ref[:64] - s_sig[i]).max():.2e}")
+        assert err < 1e-5
+    _gpu_checks(Up, Sp, Vp, A, "plain-fp32", ORTH_TOL)
+
+
+def test_backward_256_batch64_clustered(api):
+    import torch
+    _say("64 x 256^2 with exact and 1e-6 pairs: backward vs oracle and finite differences")
+    A, s, dU, dS, dV = inputs.clustered_backward(seed=5, batch=64, n=256)
+    Ad = torch.from_numpy(A).cuda()
+    U, S, V, info = api.svd_fwd(Ad)
+    assert not np.any(api.info_to_numpy(info)["flags"] & (16 | 32))
+    eK, eR, eT = oracle.paper_eps(1e-8)
+    dA = api.svd_bwd(U, S, V, *(torch.from_numpy(x).cuda() for x in (dU, dS, dV)), eps_K=eK, eps_R=eR, eps_T=eT)
+    dA = dA.cpu().double().numpy()
+    assert np.all(np.isfinite(dA))
+    Uh, Sh, Vh = (t.cpu().double().numpy() for t in (U, S, V))
+    # (1) Algorithm 4 on the same factors, literal, FP64, every matrix
+    M = np.einsum("bij,bj,bkj->bik", Uh, Sh, Vh)
+    ref = oracle.svd_bwd_batch(M, Uh, Sh, Vh, dU, dS, dV, eK, eR, eT, threads=8)
+    rel = np.linalg.norm(dA - ref, axis=(1, 2)) / np.linalg.norm(ref, axis=(1, 2))
+    _say(f"  vs oracle Algorithm 4: max rel {rel.max():.2e}, |dA| {np.linalg.norm(dA, axis=(1, 2)).max():.2e}")
+    assert rel.max() < 1e-3
+    # (2) finite differences of a loss that is smooth at repeated values:
+    # L = <G1, U V^T> + <g, sigma> with g constant on the pairs
+    i = 0
+    rng = inputs.rng_for(77, 0)
+    G1 = rng.standard_normal((256, 256))
+    g = rng.standard_normal(256)
+    for k in range(7, 255, 16):
+        g[k + 1] = g[k]
+    # (FP32 splits the exact pairs by ~1e-7; a tiny eps_K damps 1/(s_i - s_j)
+    # times rounding noise there, and cannot matter elsewhere because the
+    # skew part of U^T dU + V^T dV vanishes for this loss)
+    Ui, Si, Vi = Uh[i], Sh[i], Vh[i]
+    dUi = G1 @ Vi
+    dVi = G1.T @ Ui
+    gd = api.svd_bwd(torch.from_numpy(Ui[None].astype(np.float32)).cuda(),
+                     torch.from_numpy(Si[None].astype(np.float32)).cuda(),
+                     torch.from_numpy(Vi[None].astype(np.float32)).cuda(),
+                     torch.from_numpy(dUi[None].astype(np.float32)).cuda(),
+                     torch.from_numpy(g[None].astype(np.float32)).cuda(),
+                     torch.from_numpy(dVi[None].astype(np.float32)).cuda(),
+                     eps_K=1e-10).cpu().double().numpy()[0]
+    A64 = A[i].astype(np.float64)
+
+    def loss(X):
+        Uu, Ss, Vv, _ = oracle.svd(X)
+        return np.sum(G1 * (Uu @ Vv.T)) + np.sum(g * Ss)
+
+    h = 1e-4
+    for d in range(4):
+        E = rng.standard_normal((256, 256))
+        E /= np.linalg.norm(E)
+        fd = (loss(A64 + h * E) - loss(A64 - h * E)) / (2 * h)
+        an = np.sum(gd * E)
+        _say(f"  FD direction {d}: analytic {an:.6e} fd {fd:.6e} rel {abs(an - fd) / abs(fd):.2e}")
+        assert abs(an - fd) <= 1e-3 * abs(fd) + 1e-6 * np.linalg.norm(gd)
+
+
+def test_learned_predictor_gain_2048(api, handle):
+    """What the trained network gains: on 32 matrices of 2048^2 from the three
+    training families, the learned BF16 path takes fewer CANS steps than the
+    conservative FP32 path and agrees with it to 1e-3 in sigma."""
+    import torch
+    _say("32 x 2048^2 from the predictor's three families: learned vs conservative")
+    t0 = time.time()
+    mats = []
+    for i in range(32):
+        rng = inputs.rng_for(31, i)
+        kind, payload, m = inputs.predictor_spectrum(rng, 2048, i % 3)
+        if kind == "s":
+            mats.append(inputs.matrix_with_spectrum(rng, 2048, 2048, payload).astype(np.float32))
+        else:
+            mats.append(payload[:2048].astype(np.float32) if payload.shape[0] >= 2048 else payload.astype(np.float32))
+    A = np.stack(mats)
+    _say(f"  generated in {time.time() - t0:.1f}s")
+    Ad = torch.from_numpy(A).cuda()
+    probe = torch.from_numpy(inputs.probe(32, 32, 2048)).cuda()
+    out = {}
+    for label, kw in [("conservative-fp32", {}), ("learned-bf16", dict(precision=1, bound=1, probe=probe))]:
+        api.svd_fwd(Ad[:2], handle=handle, **kw)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        U, S, V, info = api.svd_fwd(Ad, handle=handle, **kw)
+        torch.cuda.synchronize()
+        inf = api.info_to_numpy(info)
+        out[label] = (S.cpu().double().numpy(), inf, time.time() - t0)
+        _say(f"  {label}: {out[label][2]:.2f}s, CANS steps mean {inf['iters'].mean():.1f} max {inf['iters'].max()}, "
+             f"fallbacks {int(((inf['flags'] & 2) != 0).sum())}, residual max {inf['residual'].max():.1e}")
+    Sc, ic, _ = out["conservative-fp32"]
+    Sl, il, _ = out["learned-bf16"]
+    err = (np.abs(Sl - Sc).max(axis=1) / Sc[:, 0]).max()
+    _say(f"  sigma learned vs conservative {err:.2e}")
+    assert err < 1e-3
+    assert il["iters"].mean() < ic["iters"].mean()

@@ -1,0 +1,137 @@
+"""Edge cases, error paths and the autograd wrappers on the GPU."""
+import ctypes
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2609_32505_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def api():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2609_32505_amd import api as _api
+    return _api
+
+
+def dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).cuda()
+
+
+def test_tiny_shapes(api):
+    _say("tiny shapes: 1x1, 7x1, 5x5 batch 3")
+    for b, m, n in [(1, 1, 1), (2, 7, 1), (3, 5, 5), (1, 33, 32)]:
+        A = inputs.rng_for(90, m * n).standard_normal((b, m, n)).astype(np.float32)
+        U, S, V, info = api.svd_fwd(dev(A))
+        Sh, Uh, Vh = (t.cpu().double().numpy() for t in (S, U, V))
+        for i in range(b):
+            _, So, _, _ = oracle.svd(A[i].astype(np.float64))
+            np.testing.assert_allclose(Sh[i], So, rtol=1e-5, atol=1e-6 * So[0])
+            np.testing.assert_allclose((Uh[i] * Sh[i]) @ Vh[i].T, A[i], atol=2e-5 * np.abs(A[i]).max())
+
+
+def test_empty_batch_is_noop(api):
+    import torch
+    from paper_2609_32505_amd import _lib as L
+    h = api.Handle()
+    p = L.default_params(0, 8, 8)
+    st = L.load().svd_polar_fwd(h.ptr, ctypes.byref(p), None, 8, 64, None, 8, 64, None, 8, None, 8, 64,
+                                None, None, 0, None)
+    assert st == 0
+
+
+def test_rank_deficient_is_flagged(api):
+    # exactly rank-deficient in FP32: the last 28 columns are zero, so CANS
+    # leaves those columns of W at zero (a partial isometry) and the column
+    # norms of U = W V expose it
+    _say("rank-deficient 64x48, rank 20 (zero columns)")
+    rng = inputs.rng_for(91, 0)
+    B = inputs.matrix_with_spectrum(rng, 64, 20, inputs.geometric(20, 10.0))
+    A = np.concatenate([B, np.zeros((64, 28))], axis=1).astype(np.float32)
+    s = np.concatenate([inputs.geometric(20, 10.0), np.zeros(28)])
+    U, S, V, info = api.svd_fwd(dev(A[None]))
+    inf = api.info_to_numpy(info)
+    Sh = S.cpu().double().numpy()[0]
+    np.testing.assert_allclose(Sh[:20], s[:20], atol=1e-5)
+    assert np.abs(Sh[20:]).max() < 1e-5
+    assert inf["flags"][0] & 8, "rank deficiency must be reported"
+
+
+def test_workspace_and_argument_errors(api):
+    import torch
+    from paper_2609_32505_amd import _lib as L
+    h = api.Handle()
+    A = torch.zeros((2, 16, 8), device="cuda")
+    out = [torch.empty((2, 16, 8), device="cuda"), torch.empty((2, 8), device="cuda"),
+           torch.empty((2, 8, 8), device="cuda")]
+    p = L.default_params(2, 16, 8)
+    ws = torch.empty(16, dtype=torch.uint8, device="cuda")
+    st = L.load().svd_polar_fwd(h.ptr, ctypes.byref(p), A.data_ptr(), 8, 128, out[0].data_ptr(), 8, 128,
+                                out[1].data_ptr(), 8, out[2].data_ptr(), 8, 64, None, ws.data_ptr(), 16, None)
+    assert st == 3
+    p2 = L.default_params(2, 16, 8, bound=1)
+    h.set_model(np.zeros(L.MODEL_FLOATS, np.float32))
+    st = L.load().svd_polar_fwd(h.ptr, ctypes.byref(p2), A.data_ptr(), 8, 128, out[0].data_ptr(), 8, 128,
+                                out[1].data_ptr(), 8, out[2].data_ptr(), 8, 64, None, ws.data_ptr(), 16, None)
+    assert st == 1 and "probe" in L.load().svdp_last_error().decode()
+    st = L.load().svd_polar_fwd(h.ptr, ctypes.byref(p), A.data_ptr(), 4, 128, out[0].data_ptr(), 8, 128,
+                                out[1].data_ptr(), 8, out[2].data_ptr(), 8, 64, None, ws.data_ptr(), 16, None)
+    assert st == 1  # lda < n
+
+
+def test_user_bound_too_small_falls_back(api):
+    _say("user bound sigma_max at half the true value: fallback to conservative CANS")
+    A, s = inputs.batch_with_spectra(92, 2, 96, 64, lambda r: inputs.log_uniform(r, 64, 1e-2, 1.0))
+    ub = dev(np.stack([s[:, -1], 0.5 * s[:, 0]], axis=1))
+    U, S, V, info = api.svd_fwd(dev(A), precision=1, bound=2, user_bounds=ub, margin_max=1.0)
+    inf = api.info_to_numpy(info)
+    assert np.all(inf["flags"] & 2), "fallback must be used"
+    Sh = S.cpu().double().numpy()
+    assert (np.abs(Sh - s).max(axis=1) / s[:, 0]).max() < 1e-5
+
+
+def test_repeatable(api):
+    A, _ = inputs.batch_with_spectra(93, 4, 100, 70, lambda r: inputs.log_uniform(r, 70, 1e-3, 1.0))
+    r1 = [t.cpu().numpy() for t in api.svd_fwd(dev(A))[:3]]
+    r2 = [t.cpu().numpy() for t in api.svd_fwd(dev(A))[:3]]
+    for a, b in zip(r1, r2):
+        np.testing.assert_array_equal(a, b)
+
+
+def test_autograd_svd_and_polar(api):
+    import torch
+    from paper_2609_32505_amd import autograd
+    _say("autograd wrappers")
+    A, _ = inputs.batch_with_spectra(94, 2, 40, 24, lambda r: inputs.log_uniform(r, 24, 1e-1, 1.0))
+    At = dev(A).requires_grad_(True)
+    U, S, Vh = autograd.svd(At)
+    rng = np.random.default_rng(3)
+    gU, gS, gV = dev(rng.standard_normal(U.shape)), dev(rng.standard_normal(S.shape)), dev(rng.standard_normal(Vh.shape))
+    loss = (U * gU).sum() + (S * gS).sum() + (Vh * gV).sum()
+    loss.backward()
+    ref = api.svd_bwd(U.detach(), S.detach(), Vh.detach().transpose(-1, -2).contiguous(), gU, gS,
+                      gV.transpose(-1, -2).contiguous())
+    np.testing.assert_allclose(At.grad.cpu().numpy(), ref.cpu().numpy(), rtol=1e-5, atol=1e-5)
+    # polar: gradient of <G, W> + <K, H> against the oracle (Algorithm 2, eps = 0)
+    A2 = dev(A).requires_grad_(True)
+    W, H = autograd.polar(A2)
+    G = rng.standard_normal(W.shape)
+    K = rng.standard_normal(H.shape)
+    ((W * dev(G)).sum() + (H * dev(K)).sum()).backward()
+    g = A2.grad.cpu().double().numpy()
+    for i in range(2):
+        Uo, So, Vo, _ = oracle.svd(A[i].astype(np.float64))
+        _, Ho = oracle.polar_from_svd(Uo, So, Vo)
+        ref = oracle.polar_bwd(A[i], Ho, G[i], K[i])
+        assert np.linalg.norm(g[i] - ref) / np.linalg.norm(ref) < 1e-4
