@@ -75,18 +75,24 @@ typedef struct {
   int32_t bound;           /* svdp_bound */
   int32_t max_iters;       /* CANS step cap, preprocessing included (50) */
   int32_t pre_iters;       /* conservative preprocessing steps (2) */
-  int32_t refine_steps;    /* FP32 steps after the BF16 phase (2) */
+  int32_t refine_steps;    /* bounded paths: FP32 refinement steps taken unconditionally (2); the
+                              refinement then continues per matrix until the relative change is
+                              <= tol, for at most refine_steps + 8 steps, else NOT_CONVERGED and
+                              the conservative fallback */
   int32_t max_sweeps;      /* Jacobi sweep cap (20) */
-  int32_t inner_sweeps;    /* scalar sweeps per 64 x 64 Jacobi subproblem (1) */
+  int32_t inner_sweeps;    /* repetitions of a block step's scalar rounds per 32 x 32 Jacobi
+                              subproblem (1) */
   int32_t fp64_sweeps;     /* final Jacobi sweeps with FP64 subproblem solves (1) */
   double delta;            /* CANS preprocessing target [1-delta, 1+delta] (0.99) */
   double tol;              /* CANS stop: |X_k+1 - X_k|_F <= tol |X_k+1|_F (1e-5) */
   double eps_qr;           /* column-norm tolerance of U (1e-5) */
   double bf16_handoff;     /* BF16 phase ends when the interval error <= this (1e-2) */
-  double refine_tol;       /* learned path falls back when the refinement residual exceeds this (1e-2) */
+  double refine_tol;       /* bounded paths fall back when |W^T W - I|_F / sqrt(n) after the
+                              refinement exceeds this (1e-2) */
   double jacobi_tol;       /* Jacobi stops after a sweep whose largest rotated |h_pq| is
-                              <= jacobi_tol sqrt(|h_pp h_qq|); the final FP64 sweep then
-                              leaves about jacobi_tol^2 (quadratic convergence) (1e-3) */
+                              <= jacobi_tol sqrt(|h_pp h_qq|); by quadratic convergence that
+                              sweep leaves about jacobi_tol^2 and the final FP64 sweep about
+                              its square; tightly clustered spectra need the margin (3e-3) */
   double jacobi_abs;       /* entries below jacobi_abs |H|_F are ignored by that test (1e-9) */
   double bf16_from;        /* bounded paths: FP32 steps until the interval's lower end
                               reaches this value, BF16 steps after it (0.1) */

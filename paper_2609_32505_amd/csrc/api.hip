@@ -136,6 +136,10 @@ EighOpts eigh_opts(const svdp_params* p) {
 
 // ---------------------------------------------------------------- forward workspace
 
+// Refinement steps allowed beyond refine_steps before a bounded-path matrix
+// is declared unconverged (and rerun with conservative CANS).
+constexpr int kRefineExtra = 8;
+
 struct FwdWs {
   float *X0, *X1, *G;
   void *Y0, *Y1;  // BF16 iterates (never aliasing the FP32 ones)
@@ -267,7 +271,8 @@ svdp_status conservative_fp32(Ctx& c, const int* mask) {
     const float* Xc = (k & 1) ? w.X1 : w.X0;
     float* Xn = (k & 1) ? w.X0 : w.X1;
     HIPCHK(cans_step(c, PREC_F32, Xc, Xn, 0, 0, w.coef, 0, k, w.active, w.conv, remaining), "cans step");
-    HIPCHK(cans_check_launch(B, w.conv, (float)p->tol, k, w.active, w.where, w.iters, w.flags, w.counter, c.st),
+    HIPCHK(cans_check_launch(B, w.conv, (float)p->tol, k, w.active, w.where, w.iters, nullptr, 0, w.flags,
+                             w.counter, c.st),
            "cans check");
     // poll the device for stragglers once the schedule can have converged
     if (k >= p->pre_iters + 4 || k == p->max_iters - 1) {
@@ -282,9 +287,9 @@ svdp_status conservative_fp32(Ctx& c, const int* mask) {
 }
 
 // Bounded path: learned (sketch features -> MLP) or user bounds give a
-// per-matrix scale and interval [lo, 1]; K interval-optimal steps (batch
-// maximum of the per-matrix counts to the BF16 hand-off) in `prec`, then
-// refine_steps FP32 steps.  Result in X0 / X1 with a uniform where[].
+// per-matrix scale and interval [lo, 1]; each matrix takes its own number K
+// of interval-optimal steps (to the BF16 hand-off error) in `prec`, then FP32
+// refinement with the stop test.  Result in X0 / X1 as where[] says.
 svdp_status bounded(Ctx& c) {
   const svdp_params* p = c.p;
   FwdWs& w = c.w;
@@ -324,13 +329,6 @@ svdp_status bounded(Ctx& c) {
   int hist[65], k1g[65];
   for (int i = 0; i <= kcap; ++i) { hist[i] = c.h->host_word[i]; k1g[i] = c.h->host_word[65 + i]; }
   const int bf16 = p->precision == SVDP_PREC_BF16;
-  const int R = p->refine_steps;
-  double rtab[128];
-  if (R > 0) {
-    double h = std::min(std::max(p->bf16_handoff, 1e-8), 0.5);
-    table_interval(1.0 - h, R, rtab);
-    HIPCHK(set_coef_launch(w.rcoef, rtab, R, c.st), "refine coef");
-  }
   for (int Kg = 0; Kg <= kcap; ++Kg) {
     const int count = hist[Kg];
     if (count == 0) continue;
@@ -339,10 +337,12 @@ svdp_status bounded(Ctx& c) {
     const int* gm = w.gmask;
     HIPCHK(group_mask_launch(B, w.ksteps, Kg, w.gmask, c.st), "group mask");
     // steps [0, K1) in FP32 while small singular values are still small
-    // (BF16 rounding would rotate their singular vectors), [K1, K) in BF16
-    // iterate after step k lives in X[k % 2] (FP32) or Y[k % 2] (BF16)
+    // (BF16 rounding would rotate their singular vectors), [K1, K) in BF16.
+    // The iterate after step k lives in X[(k + K) % 2] (FP32) or
+    // Y[(k + K) % 2] (BF16), so every group ends in X0.
     auto buf = [&](int k, int isbf) -> void* {
-      return isbf ? ((k & 1) ? w.Y1 : w.Y0) : (void*)((k & 1) ? w.X1 : w.X0);
+      const int odd = (k + K) & 1;
+      return isbf ? (odd ? w.Y1 : w.Y0) : (void*)(odd ? w.X1 : w.X0);
     };
     HIPCHK(scale_copy_launch(c.A, c.lda, c.sA, B, m, n, w.scale, buf(0, K1 == 0), K1 == 0 ? 1 : 0, gm, c.st),
            "normalise");
@@ -353,15 +353,43 @@ svdp_status bounded(Ctx& c) {
       HIPCHK(cans_step(c, prec, buf(k, in_bf), buf(k + 1, out_bf), in_bf, out_bf, w.coef, kcap, k, gm, nullptr,
                        count), "cans step");
     }
-    for (int r = 0; r < R; ++r) {
-      const int k = K + r;
-      const float* Xc = (k & 1) ? w.X1 : w.X0;
-      float* Xn = (k & 1) ? w.X0 : w.X1;
-      HIPCHK(cans_step(c, PREC_F32, Xc, Xn, 0, 0, w.rcoef, 0, r, gm, nullptr, count), "refine step");
-    }
-    HIPCHK(fill_masked_launch(w.where, (K + R) & 1, B, gm, c.st), "where");
-    HIPCHK(fill_masked_launch(w.iters, K + R, B, gm, c.st), "iters");
+    // iterations so far, the base of the refinement's count
+    HIPCHK(fill_masked_launch(w.iters, K, B, gm, c.st), "iters");
   }
+  // FP32 refinement of the whole batch from X0: interval-optimal steps from
+  // the hand-off interval (tending to the Newton-Schulz cubic), at least
+  // refine_steps of them, then per matrix until the relative change is below
+  // tol.  A matrix whose predicted interval missed part of its spectrum is
+  // still caught here; one that has not converged within refine_steps +
+  // kRefineExtra steps is flagged and falls back to conservative CANS.
+  const int R = p->refine_steps;
+  const int Rmax = std::min(R + kRefineExtra, 64);
+  double rtab[128];
+  const double hoff = std::min(std::max(p->bf16_handoff, 1e-8), 0.5);
+  table_interval(1.0 - hoff, Rmax, rtab);
+  HIPCHK(set_coef_launch(w.rcoef, rtab, Rmax, c.st), "refine coef");
+  HIPCHK(fill_i32(w.active, 1, B, c.st), "active");
+  HIPCHK(fill_i32(w.where, 0, B, c.st), "where");
+  HIPCHK(fill_f32(w.conv, 0.f, 2 * B, c.st), "conv");
+  // the reported count adds the refinement steps to each matrix's K (mask
+  // is free until the fallback test)
+  HIPCHK(copy_i32(w.mask, w.iters, B, c.st), "iteration base");
+  int remaining = B;
+  for (int r = 0; r < Rmax; ++r) {
+    const float* Xc = (r & 1) ? w.X1 : w.X0;
+    float* Xn = (r & 1) ? w.X0 : w.X1;
+    // the first R - 1 steps are unconditional: no change sums, no check
+    float* conv = r + 1 >= R ? w.conv : nullptr;
+    HIPCHK(cans_step(c, PREC_F32, Xc, Xn, 0, 0, w.rcoef, 0, r, w.active, conv, remaining), "refine step");
+    if (!conv) continue;
+    HIPCHK(cans_check_launch(B, w.conv, (float)p->tol, r, w.active, w.where, w.iters, w.mask, 1, w.flags,
+                             w.counter, c.st), "refine check");
+    svdp_status s = read_counter(c, w.counter, &remaining);
+    if (s) return s;
+    if (remaining == 0) break;
+  }
+  if (remaining > 0)
+    HIPCHK(or_flags_launch(B, w.flags, SVDP_FLAG_NOT_CONVERGED, w.active, c.st), "flags");
   return SVDP_OK;
 }
 
@@ -441,10 +469,12 @@ svdp_status check_model(svdp_handle* h, const svdp_params* p) {
 }
 
 // Fallback of the bounded paths: matrices with a residual above refine_tol,
-// a negative eigenvalue of H or non-finite values rerun conservative CANS.
+// an unconverged refinement, a negative eigenvalue of H or non-finite
+// values rerun conservative CANS.
 svdp_status fallback_mask(Ctx& c, int* count) {
   FwdWs& w = c.w;
-  HIPCHK(fallback_mask_launch(c.batch, w.flags, SVDP_FLAG_NEG_EIGENVALUE | SVDP_FLAG_NONFINITE, w.resid,
+  HIPCHK(fallback_mask_launch(c.batch, w.flags,
+                              SVDP_FLAG_NEG_EIGENVALUE | SVDP_FLAG_NONFINITE | SVDP_FLAG_NOT_CONVERGED, w.resid,
                               (float)c.p->refine_tol, w.mask, w.counter, c.st), "fallback mask");
   return read_counter(c, w.counter, count);
 }
@@ -473,7 +503,7 @@ void svdp_default_params(svdp_params* p, int64_t batch, int64_t m, int64_t n) {
   p->eps_qr = 1e-5;
   p->bf16_handoff = 1e-2;
   p->refine_tol = 1e-2;
-  p->jacobi_tol = 1e-3;
+  p->jacobi_tol = 3e-3;
   p->jacobi_abs = 1e-9;
   p->bf16_from = 0.1;
   p->margin_max = 1.1;

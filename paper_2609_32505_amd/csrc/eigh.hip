@@ -1,50 +1,79 @@
 // Batched symmetric eigendecomposition H = V diag(lam) V^T by block Jacobi
 // (the EVD step of the SVD-via-polar algorithm, Algorithm 1).
 //
-// The (padded) index range is cut into 16-wide blocks; a parallel step pairs
-// the blocks round-robin, and each pair (P, Q) owns the 32 x 32 subproblem
-// H[P u Q, P u Q].
-//   * k_jac_solve: one WAVEFRONT per pair runs a cyclic scalar Jacobi sweep on
-//     the subproblem held in its own slice of LDS (16 disjoint rotations per
-//     inner step; each 2 x 2 block of the subproblem is updated independently),
-//     accumulates the 32 x 32 orthogonal J in FP64, writes the rotated
-//     diagonal block back into H and J to a per-pair buffer.  The wave works
-//     alone on its data, so its inner steps need no workgroup barrier: LDS
-//     operations of one wave complete in program order.  FP32 subproblem
-//     arithmetic, or FP64 for the final sweep.
-//   * k_jac_apply: every off-diagonal pair block H[P, R] <- J_P^T H[P, R] J_R
-//     (upper triangle, mirrored) and every 32-row slab V[:, P] <- V[:, P] J_P,
-//     one wavefront per 32 x 32 x 32 product on FP32 MFMA (32x32x2).
-// A sweep is nb - 1 steps.  Convergence is tested per matrix on the largest
-// relative off-diagonal entry rotated during a sweep; converged matrices are
-// skipped by later launches.
+// Layout.  The index range is padded to np = 16 nb with nb a power of two
+// (at least 4).  Padding rows and columns of H are zero and those of V the
+// identity; a zero off-diagonal entry is never rotated, so padding stays
+// inert.  H and V are stored as 16 x 16 tiles (tile (I, J) is 1 KB,
+// contiguous, row-major inside); H keeps only the tiles with I <= J.
+//
+// Block ordering.  Step s (s = 1 .. nb - 1) of a sweep pairs block B with
+// B ^ s.  Two steps (sA, sB) form a phase: the blocks fall into groups
+// {B, B^sA, B^sB, B^sA^sB} that both pairings leave closed, so the rotations
+// of the two steps compose to one 64 x 64 orthogonal M_G per group, and H
+// and V are read and written once per two steps.
+//   * k_jac_solve: one workgroup (two wavefronts) per group holds H[G, G] in
+//     LDS.  Step A: wave w owns pair w, a 32 x 32 subproblem, and runs scalar
+//     Jacobi rounds on it (16 disjoint rotations per round, rotation
+//     accumulation in FP64); wave 0 then rotates the block between the two
+//     pairs with MFMA.  Step B likewise on the other pairing.  It writes
+//     H[G, G] and M_G = J_A J_B.
+//   * k_jac_apply: H[G1, G2] <- M_G1^T H[G1, G2] M_G2 for every pair of
+//     groups and V[slab, G] <- V[slab, G] M_G for every 64-row slab of V, each
+//     a 64 x 64 x 64 product pair on FP32 MFMA (32x32x2).
+// Inner rounds.  Round t of a pair subproblem rotates local indices a and
+// a ^ t: t < 16 pairs indices inside each 16-block, t >= 16 across the two
+// blocks.  The first step of a sweep runs all 31 rounds, the others the 16
+// cross rounds only, so every index pair is rotated once per sweep (a cyclic
+// Jacobi ordering).
+// Convergence is tested per matrix on the largest relative off-diagonal
+// entry rotated during a sweep; converged matrices are skipped by later
+// launches.
 #include <algorithm>
 #include <cstring>
+#include <vector>
 #include "common.hpp"
 #include "eigh.hpp"
 #include "prof.hpp"
 
 namespace {
 
-constexpr int BS = 16;       // block width
-constexpr int PB = 2 * BS;   // pair subproblem size (32)
-constexpr int NPP = PB / 2;  // disjoint rotations per inner step (16)
-constexpr int LP = PB + 1;   // LDS row pitch
+constexpr int BS = 16;      // block width
+constexpr int PB = 32;      // pair subproblem size
+constexpr int GS = 64;      // group size (four blocks)
+constexpr int LP = PB + 1;  // LDS pitch of 32-wide arrays
+constexpr int GP = GS + 1;  // LDS pitch of 64-wide arrays
 
-// Round-robin (circle method) pairing of `players` (even) in `round`:
-// position 0 is fixed, the others rotate; pair k joins positions k and
-// players - 1 - k.
-SVDP_DEV int rr_player(int pos, int round, int players) {
-  return pos == 0 ? 0 : 1 + (pos - 1 + round) % (players - 1);
-}
-SVDP_DEV void rr_pair(int k, int round, int players, int& x, int& y) {
-  int a = rr_player(k, round, players), c = rr_player(players - 1 - k, round, players);
-  x = a < c ? a : c;
-  y = a < c ? c : a;
+SVDP_DEV int insert0(int x, int p) { return ((x >> p) << (p + 1)) | (x & ((1 << p) - 1)); }
+
+// the four blocks of group gi in a phase, in local order
+// [B0, B0 ^ sA, B0 ^ sB, B0 ^ sA ^ sB]: step A pairs local blocks (0, 1) and
+// (2, 3), step B pairs (0, 2) and (1, 3).  B0 is the member with bits lo and
+// hi clear (each group has exactly one).
+SVDP_DEV void group_members(const EighPhase& ph, int gi, int* g) {
+  const int b0 = insert0(insert0(gi, ph.lo), ph.hi);
+  g[0] = b0;
+  g[1] = b0 ^ ph.sA;
+  g[2] = b0 ^ ph.sB;
+  g[3] = b0 ^ ph.sA ^ ph.sB;
 }
 
-// local index (0..31) of a pair subproblem -> global index
-SVDP_DEV int gidx(int a, int p, int q) { return a < BS ? p * BS + a : q * BS + (a - BS); }
+SVDP_DEV int64_t tile_off(int I, int J, int nb) { return ((int64_t)I * nb + J) * (BS * BS); }
+
+// position in the 64-index group of element a (0..31) of pair w: step A
+// pairs are contiguous halves, step B pairs interleave 16-blocks
+SVDP_DEV int lmap(int stepB, int w, int a) { return stepB ? a + 16 * w + (a & 16) : 32 * w + a; }
+
+// rotation k (0..15) of inner round t (1..31): the pair (x, x ^ t), x < x ^ t
+SVDP_DEV void inner_pair(int t, int k, int& x, int& y) {
+  if (t >= 16) {
+    x = k;
+  } else {
+    const int hb = 31 - __clz(t);
+    x = ((k >> 3) << 4) | insert0(k & 7, hb);
+  }
+  y = x ^ t;
+}
 
 // orders the wave's own LDS traffic: no instruction is moved across it, and
 // LDS operations of one wave complete in issue order
@@ -63,84 +92,86 @@ SVDP_DEV void rotation(R app, R aqq, R apq, R& c, R& s) {
   s = t * c;
 }
 
+SVDP_DEV f16v mfma(float a, float b, f16v acc) { return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0); }
+
+SVDP_DEV f16v zero16() {
+  f16v z;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) z[i] = 0.f;
+  return z;
+}
+
 template <typename R>
-__global__ __launch_bounds__(256) void k_jac_solve(EighWs e, int step, int inner_sweeps,
-                                                   float abs_tol, int* rotmax) {
-  __shared__ R Sall[4][PB][LP];
-  __shared__ double Jall[4][PB][LP];
-  __shared__ R csall[4][2][NPP];
-  __shared__ unsigned char ptab[PB - 1][NPP][2];
-  const int t = threadIdx.x;
-  for (int i = t; i < (PB - 1) * NPP; i += 256) {
-    int x, y;
-    rr_pair(i % NPP, i / NPP, PB, x, y);
-    ptab[i / NPP][i % NPP][0] = (unsigned char)x;
-    ptab[i / NPP][i % NPP][1] = (unsigned char)y;
-  }
-  __syncthreads();
-  const int wave = t >> 6, lane = t & 63;
-  const int npairs = e.nb / 2;
-  const int task = blockIdx.x * 4 + wave;
-  const int b = task / npairs, k = task - b * npairs;
-  if (b >= e.batch) return;
-  if (e.active && !e.active[b]) return;
-  R (*S)[LP] = Sall[wave];
-  double (*J)[LP] = Jall[wave];
-  R* cs_c = csall[wave][0];
-  R* cs_s = csall[wave][1];
-  int p, q;
-  rr_pair(k, step, e.nb, p, q);
-  float* H = e.Hw + (int64_t)b * e.np * e.np;
-  for (int idx = lane; idx < PB * PB; idx += 64) {
-    int a = idx / PB, c = idx % PB;
-    S[a][c] = (R)H[(int64_t)gidx(a, p, q) * e.np + gidx(c, p, q)];
-    J[a][c] = a == c ? 1.0 : 0.0;
-  }
-  const R floor_abs = (R)abs_tol * (R)sqrtf(e.hnorm2[b]);
-  float mrel = 0.f;
+struct SolveLds {
+  R X[GS][GP];           // H[G, G]
+  double J[2][PB][LP];   // per-wave rotation accumulation
+  float JA[2][PB][LP];   // step A rotations of the two pairs
+  float JB[2][PB][LP];   // step B rotations
+  R cs[2][2][16];        // per-wave (c, s) of the current round
+};
+
+// Scalar Jacobi rounds t0 .. 31 (repeated inner_sweeps times) on pair w of
+// the given step; J accumulates the rotations.  One wavefront, no workgroup
+// barrier.
+template <typename R>
+SVDP_DEV void pair_solve(SolveLds<R>& L, int stepB, int w, int lane, int t0, int inner_sweeps,
+                         R floor_abs, float& mrel) {
+  R (*X)[GP] = L.X;
+  double (*J)[LP] = L.J[w];
+  R* cc = L.cs[w][0];
+  R* ss = L.cs[w][1];
+  for (int idx = lane; idx < PB * PB; idx += 64) J[idx >> 5][idx & 31] = (idx >> 5) == (idx & 31) ? 1.0 : 0.0;
   wave_sync();
   for (int sw = 0; sw < inner_sweeps; ++sw) {
     int any = 0;
-    for (int s = 0; s < PB - 1; ++s) {
-      if (lane < NPP) {
-        const int x = ptab[s][lane][0], y = ptab[s][lane][1];
-        R app = S[x][x], aqq = S[y][y], apq = S[y][x] * R(0.5) + S[x][y] * R(0.5);
+    for (int t = t0; t < PB; ++t) {
+      if (lane < 16) {
+        int x, y;
+        inner_pair(t, lane, x, y);
+        const int gx = lmap(stepB, w, x), gy = lmap(stepB, w, y);
+        const R app = X[gx][gx], aqq = X[gy][gy], apq = R(0.5) * (X[gx][gy] + X[gy][gx]);
         R c = 1, sn = 0;
         if (apq != R(0) && isfinite((float)apq)) {
           rotation(app, aqq, apq, c, sn);
           any = 1;
           if (fabs(apq) > floor_abs) {
-            R den = sqrt(fabs(app * aqq));
+            const R den = sqrt(fabs(app * aqq));
             mrel = fmaxf(mrel, den > R(0) ? (float)(fabs(apq) / den) : 1e30f);
           }
         }
-        cs_c[lane] = c;
-        cs_s[lane] = sn;
+        cc[lane] = c;
+        ss[lane] = sn;
       }
       wave_sync();
-      // 16 x 16 blocks of 2 x 2, four per lane
+      // 16 x 16 blocks of 2 x 2: row pair kx, column pairs ky
+      const int kx = lane & 15;
+      int x1, y1;
+      inner_pair(t, kx, x1, y1);
+      const int gx1 = lmap(stepB, w, x1), gy1 = lmap(stepB, w, y1);
+      const R c1 = cc[kx], s1 = ss[kx];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const int blk = lane + 64 * u;
-        const int kx = blk >> 4, ky = blk & 15;
-        const int x1 = ptab[s][kx][0], y1 = ptab[s][kx][1];
-        const int x2 = ptab[s][ky][0], y2 = ptab[s][ky][1];
-        const R c1 = cs_c[kx], s1 = cs_s[kx], c2 = cs_c[ky], s2 = cs_s[ky];
-        const R a = S[x1][x2], bq = S[x1][y2], cq = S[y1][x2], d = S[y1][y2];
+        const int ky = (lane >> 4) + 4 * u;
+        int x2, y2;
+        inner_pair(t, ky, x2, y2);
+        const int gx2 = lmap(stepB, w, x2), gy2 = lmap(stepB, w, y2);
+        const R c2 = cc[ky], s2 = ss[ky];
+        const R a = X[gx1][gx2], bq = X[gx1][gy2], cq = X[gy1][gx2], d = X[gy1][gy2];
         const R t00 = c1 * a - s1 * cq, t01 = c1 * bq - s1 * d;
         const R t10 = s1 * a + c1 * cq, t11 = s1 * bq + c1 * d;
         R y00 = c2 * t00 - s2 * t01, y01 = s2 * t00 + c2 * t01;
         R y10 = c2 * t10 - s2 * t11, y11 = s2 * t10 + c2 * t11;
         if (kx == ky && s1 != R(0)) { y01 = 0; y10 = 0; }
-        S[x1][x2] = y00; S[x1][y2] = y01; S[y1][x2] = y10; S[y1][y2] = y11;
+        X[gx1][gx2] = y00; X[gx1][gy2] = y01; X[gy1][gx2] = y10; X[gy1][gy2] = y11;
       }
-      // rotation accumulation: 32 rows x 16 pairs, eight per lane
+      // rotation accumulation J <- J R: 32 rows x 16 pairs, eight per lane
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int it = lane + 64 * u;
         const int r = it >> 4, kk = it & 15;
-        const int x = ptab[s][kk][0], y = ptab[s][kk][1];
-        const double c = cs_c[kk], sn = cs_s[kk];
+        int x, y;
+        inner_pair(t, kk, x, y);
+        const double c = cc[kk], sn = ss[kk];
         const double jx = J[r][x], jy = J[r][y];
         J[r][x] = c * jx - sn * jy;
         J[r][y] = sn * jx + c * jy;
@@ -150,10 +181,116 @@ __global__ __launch_bounds__(256) void k_jac_solve(EighWs e, int step, int inner
     // every lane of the wave takes the same exit
     if (!__any(any)) break;
   }
-  for (int idx = lane; idx < PB * PB; idx += 64) {
-    int a = idx / PB, c = idx % PB;
-    H[(int64_t)gidx(a, p, q) * e.np + gidx(c, p, q)] = (float)S[a][c];
-    e.Qw[((int64_t)b * npairs + k) * (PB * PB) + idx] = (float)J[a][c];
+}
+
+// The block of H[G, G] between the two pairs of a step, B = X[P0, P1]:
+// B <- J0^T B J1, and its mirror X[P1, P0] = B^T.  One wavefront.
+template <typename R>
+SVDP_DEV void cross_update(SolveLds<R>& L, int stepB, const float (*J0)[LP], const float (*J1)[LP], int lane) {
+  R (*X)[GP] = L.X;
+  const int kh = lane >> 5, ic = lane & 31;
+  f16v acc = zero16();
+#pragma unroll 4
+  for (int kk = 0; kk < PB; kk += 2)
+    acc = mfma(J0[kk + kh][ic], (float)X[lmap(stepB, 0, kk + kh)][lmap(stepB, 1, ic)], acc);
+  wave_sync();
+#pragma unroll
+  for (int g = 0; g < 4; ++g)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) X[lmap(stepB, 0, 8 * g + 4 * kh + r)][lmap(stepB, 1, ic)] = (R)acc[4 * g + r];
+  wave_sync();
+  acc = zero16();
+#pragma unroll 4
+  for (int kk = 0; kk < PB; kk += 2)
+    acc = mfma((float)X[lmap(stepB, 0, ic)][lmap(stepB, 1, kk + kh)], J1[kk + kh][ic], acc);
+  wave_sync();
+#pragma unroll
+  for (int g = 0; g < 4; ++g)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = lmap(stepB, 0, 8 * g + 4 * kh + r), j = lmap(stepB, 1, ic);
+      X[i][j] = (R)acc[4 * g + r];
+      X[j][i] = (R)acc[4 * g + r];
+    }
+  wave_sync();
+}
+
+template <typename R>
+__global__ __launch_bounds__(128) void k_jac_solve(EighWs e, EighPhase ph, int inner_sweeps, float abs_tol,
+                                                   int* rotmax) {
+  __shared__ SolveLds<R> L;
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+  const int ng = e.nb / 4;
+  const int b = blockIdx.x / ng, gi = blockIdx.x - b * ng;
+  if (b >= e.batch) return;
+  if (e.active && !e.active[b]) return;
+  int g[4];
+  group_members(ph, gi, g);
+  float* H = e.Hw + (int64_t)b * e.np * e.np;
+  // H[G, G]: 16 tiles, the ones below the diagonal read transposed
+  for (int idx = t; idx < 16 * 64; idx += 128) {
+    const int tile = idx >> 6, qd = idx & 63, k1 = tile >> 2, k2 = tile & 3;
+    const int I = g[k1], Jb = g[k2];
+    const bool tr = I > Jb;
+    const f4v v = *(const f4v*)(H + tile_off(tr ? Jb : I, tr ? I : Jb, e.nb) + qd * 4);
+    const int r = qd >> 2, c = (qd & 3) * 4;
+#pragma unroll
+    for (int w2 = 0; w2 < 4; ++w2) {
+      if (tr) L.X[k1 * 16 + c + w2][k2 * 16 + r] = (R)v[w2];
+      else L.X[k1 * 16 + r][k2 * 16 + c + w2] = (R)v[w2];
+    }
+  }
+  __syncthreads();
+  const R floor_abs = (R)abs_tol * (R)sqrtf(e.hnorm2[b]);
+  float mrel = 0.f;
+  // step A
+  pair_solve<R>(L, 0, w, lane, ph.fullA ? 1 : 16, inner_sweeps, floor_abs, mrel);
+  for (int idx = lane; idx < PB * PB; idx += 64) L.JA[w][idx >> 5][idx & 31] = (float)L.J[w][idx >> 5][idx & 31];
+  __syncthreads();
+  if (w == 0) cross_update<R>(L, 0, L.JA[0], L.JA[1], lane);
+  __syncthreads();
+  // step B
+  if (!ph.skipB) {
+    pair_solve<R>(L, 1, w, lane, 16, inner_sweeps, floor_abs, mrel);
+    for (int idx = lane; idx < PB * PB; idx += 64) L.JB[w][idx >> 5][idx & 31] = (float)L.J[w][idx >> 5][idx & 31];
+    __syncthreads();
+  }
+  // M_G = J_A J_B (64 x 64, local order) to the group's slot; wave 0 also
+  // rotates the cross block of step B
+  float* M = e.Qw + ((int64_t)b * ng + gi) * (GS * GS);
+  const int kh = lane >> 5, ic = lane & 31;
+  if (ph.skipB) {
+    for (int idx = t; idx < GS * GS; idx += 128) {
+      const int p = idx >> 6, q = idx & 63;
+      M[idx] = (p >> 5) == (q >> 5) ? L.JA[p >> 5][p & 31][q & 31] : 0.f;
+    }
+  } else {
+    if (w == 0) cross_update<R>(L, 1, L.JB[0], L.JB[1], lane);
+    // block (wa, wb): rows of step-A pair wa, columns of step-B pair wb;
+    // the shared indices are local 32 wa + 16 wb + k, k < 16
+    for (int blk = w; blk < 4; blk += 2) {
+      const int wa = blk >> 1, wb = blk & 1;
+      f16v acc = zero16();
+#pragma unroll
+      for (int kk = 0; kk < 16; kk += 2)
+        acc = mfma(L.JA[wa][ic][16 * wb + kk + kh], L.JB[wb][16 * wa + kk + kh][ic], acc);
+#pragma unroll
+      for (int gg = 0; gg < 4; ++gg)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          M[(32 * wa + 8 * gg + 4 * kh + r) * GS + lmap(1, wb, ic)] = acc[4 * gg + r];
+    }
+  }
+  __syncthreads();
+  // H[G, G] back: the tiles on and above the diagonal
+  for (int idx = t; idx < 16 * 64; idx += 128) {
+    const int tile = idx >> 6, qd = idx & 63, k1 = tile >> 2, k2 = tile & 3;
+    if (g[k1] > g[k2]) continue;
+    const int r = qd >> 2, c = (qd & 3) * 4;
+    f4v v;
+#pragma unroll
+    for (int w2 = 0; w2 < 4; ++w2) v[w2] = (float)L.X[k1 * 16 + r][k2 * 16 + c + w2];
+    *(f4v*)(H + tile_off(g[k1], g[k2], e.nb) + qd * 4) = v;
   }
   // largest relative off-diagonal entry rotated by this wave (float bits)
 #pragma unroll
@@ -161,135 +298,163 @@ __global__ __launch_bounds__(256) void k_jac_solve(EighWs e, int step, int inner
   if (lane == 0 && rotmax) atomicMax(rotmax + b, __float_as_int(mrel));
 }
 
-// 32 x 32 x 32 product on one wavefront: A read as A[i][k] (or A[k][i] when
-// a_trans), B as B[k][j]; returns the 32 x 32 MFMA accumulator (lane l,
-// slot 4g + r -> row 8g + 4(l / 32) + r, column l % 32).
-SVDP_DEV f16v mm32(const float (*A)[LP], bool a_trans, const float (*Bm)[LP], int lane) {
-  f16v acc;
-#pragma unroll
-  for (int e2 = 0; e2 < 16; ++e2) acc[e2] = 0.f;
+// 64 x 64 quadrant product helpers on one wavefront (32 x 32 output block
+// (qi, qj)); LDS arrays have pitch GP.
+// acc = sum_k A^T[32 qi + i][k] B[k][32 qj + j]   (A read transposed)
+SVDP_DEV f16v mm_tn(const float (*A)[GP], const float (*B)[GP], int qi, int qj, int lane) {
   const int kh = lane >> 5, ic = lane & 31;
-#pragma unroll
-  for (int kk = 0; kk < PB; kk += 2) {
-    float av = a_trans ? A[kk + kh][ic] : A[ic][kk + kh];
-    float bv = Bm[kk + kh][ic];
-    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
-  }
+  f16v acc = zero16();
+#pragma unroll 8
+  for (int kk = 0; kk < GS; kk += 2) acc = mfma(A[kk + kh][32 * qi + ic], B[kk + kh][32 * qj + ic], acc);
   return acc;
 }
+// acc = sum_k A[32 qi + i][k] B[k][32 qj + j]
+SVDP_DEV f16v mm_nn(const float (*A)[GP], const float (*B)[GP], int qi, int qj, int lane) {
+  const int kh = lane >> 5, ic = lane & 31;
+  f16v acc = zero16();
+#pragma unroll 8
+  for (int kk = 0; kk < GS; kk += 2) acc = mfma(A[32 * qi + ic][kk + kh], B[kk + kh][32 * qj + ic], acc);
+  return acc;
+}
+SVDP_DEV void put_quadrant(float (*X)[GP], const f16v& acc, int qi, int qj, int lane) {
+  const int kh = lane >> 5, ic = lane & 31;
+#pragma unroll
+  for (int g = 0; g < 4; ++g)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) X[32 * qi + 8 * g + 4 * kh + r][32 * qj + ic] = acc[4 * g + r];
+}
 
-__global__ __launch_bounds__(256) void k_jac_apply(EighWs e, int step) {
-  __shared__ float Xall[4][PB][LP];
-  __shared__ float JLall[4][PB][LP];
-  __shared__ float JRall[4][PB][LP];
-  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
-  const int npairs = e.nb / 2;
-  const int nh = npairs * (npairs - 1) / 2;
-  const int nrs = e.np / PB;
-  const int ntask = nh + nrs * npairs;
-  const int gt = blockIdx.x * 4 + wave;
-  const int b = gt / ntask, task = gt - b * ntask;
+__global__ __launch_bounds__(256) void k_jac_apply(EighWs e, EighPhase ph) {
+  __shared__ float Xs[GS][GP];
+  __shared__ float M1[GS][GP];
+  __shared__ float M2[GS][GP];
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+  const int ng = e.nb / 4;
+  const int nH = ng * (ng - 1) / 2;
+  const int ntask = nH + ng * ng;
+  // matrix b runs on XCD b % 8: its group rotations stay in one L2
+  const int L = blockIdx.x, x8 = L & 7, q = L >> 3;
+  const int grp = q / ntask, task = q - grp * ntask;
+  const int b = grp * 8 + x8;
   if (b >= e.batch) return;
   if (e.active && !e.active[b]) return;
-  float (*X)[LP] = Xall[wave];
-  float (*JL)[LP] = JLall[wave];
-  float (*JR)[LP] = JRall[wave];
-  float* H = e.Hw + (int64_t)b * e.np * e.np;
-  float* V = e.Vw + (int64_t)b * e.np * e.np;
-  const float* Q = e.Qw + (int64_t)b * npairs * (PB * PB);
-  const int jc = lane & 31;
-  if (task < nh) {
-    // upper-triangular pair index (kp < kr)
-    int tt = task, kp = 0;
-    while (tt >= npairs - 1 - kp) { tt -= npairs - 1 - kp; ++kp; }
-    const int kr = kp + 1 + tt;
-    int p1, q1, p2, q2;
-    rr_pair(kp, step, e.nb, p1, q1);
-    rr_pair(kr, step, e.nb, p2, q2);
+  const int qi = w >> 1, qj = w & 1;
+  const float* Qb = e.Qw + (int64_t)b * ng * (GS * GS);
+  if (task < nH) {
+    int tt = task, G1 = 0;
+    while (tt >= ng - 1 - G1) { tt -= ng - 1 - G1; ++G1; }
+    const int G2 = G1 + 1 + tt;
+    int g1[4], g2[4];
+    group_members(ph, G1, g1);
+    group_members(ph, G2, g2);
+    float* H = e.Hw + (int64_t)b * e.np * e.np;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int idx = lane + 64 * u;  // 32 rows x 8 float4
-      const int a = idx >> 3, c = (idx & 7) * 4;
-      const f4v v = *(const f4v*)&H[(int64_t)gidx(a, p1, q1) * e.np + gidx(c, p2, q2)];
-      const f4v jl = *(const f4v*)&Q[(int64_t)kp * (PB * PB) + a * PB + c];
-      const f4v jr = *(const f4v*)&Q[(int64_t)kr * (PB * PB) + a * PB + c];
+      const int idx = t + 256 * u;
+      const int tile = idx >> 6, qd = idx & 63, k1 = tile >> 2, k2 = tile & 3;
+      const int I = g1[k1], Jb = g2[k2];
+      const bool tr = I > Jb;
+      const f4v v = *(const f4v*)(H + tile_off(tr ? Jb : I, tr ? I : Jb, e.nb) + qd * 4);
+      const int r = qd >> 2, c = (qd & 3) * 4;
 #pragma unroll
-      for (int w2 = 0; w2 < 4; ++w2) { X[a][c + w2] = v[w2]; JL[a][c + w2] = jl[w2]; JR[a][c + w2] = jr[w2]; }
-    }
-    wave_sync();
-    const f16v T = mm32(JL, true, X, lane);  // J_P^T X
-    wave_sync();
-#pragma unroll
-    for (int g = 0; g < 4; ++g)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) X[8 * g + 4 * (lane >> 5) + r][jc] = T[4 * g + r];
-    wave_sync();
-    const f16v Y = mm32(X, false, JR, lane);  // (J_P^T X) J_R
-    const int gj = gidx(jc, p2, q2);
-#pragma unroll
-    for (int g = 0; g < 4; ++g) {
-      const int i0 = 8 * g + 4 * (lane >> 5);
-      f4v col;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        H[(int64_t)gidx(i0 + r, p1, q1) * e.np + gj] = Y[4 * g + r];
-        col[r] = Y[4 * g + r];
+      for (int w2 = 0; w2 < 4; ++w2) {
+        if (tr) Xs[k1 * 16 + c + w2][k2 * 16 + r] = v[w2];
+        else Xs[k1 * 16 + r][k2 * 16 + c + w2] = v[w2];
       }
-      // mirror: row gj, columns gidx(i0 .. i0+3) are contiguous (one 16-block)
-      *(f4v*)&H[(int64_t)gj * e.np + gidx(i0, p1, q1)] = col;
+      const int row = idx >> 4, col = (idx & 15) * 4;
+      const f4v m1 = *(const f4v*)(Qb + (int64_t)G1 * (GS * GS) + row * GS + col);
+      const f4v m2 = *(const f4v*)(Qb + (int64_t)G2 * (GS * GS) + row * GS + col);
+#pragma unroll
+      for (int w2 = 0; w2 < 4; ++w2) { M1[row][col + w2] = m1[w2]; M2[row][col + w2] = m2[w2]; }
+    }
+    __syncthreads();
+    const f16v T = mm_tn(M1, Xs, qi, qj, lane);  // M1^T X
+    __syncthreads();
+    put_quadrant(Xs, T, qi, qj, lane);
+    __syncthreads();
+    const f16v Y = mm_nn(Xs, M2, qi, qj, lane);  // (M1^T X) M2
+    __syncthreads();
+    put_quadrant(Xs, Y, qi, qj, lane);
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int idx = t + 256 * u;
+      const int tile = idx >> 6, qd = idx & 63, k1 = tile >> 2, k2 = tile & 3;
+      const int I = g1[k1], Jb = g2[k2];
+      const bool tr = I > Jb;
+      const int r = qd >> 2, c = (qd & 3) * 4;
+      f4v v;
+#pragma unroll
+      for (int w2 = 0; w2 < 4; ++w2) v[w2] = tr ? Xs[k1 * 16 + c + w2][k2 * 16 + r] : Xs[k1 * 16 + r][k2 * 16 + c + w2];
+      *(f4v*)(H + tile_off(tr ? Jb : I, tr ? I : Jb, e.nb) + qd * 4) = v;
     }
   } else {
-    const int v = task - nh, rs = v / npairs, kp = v - rs * npairs;
-    int p1, q1;
-    rr_pair(kp, step, e.nb, p1, q1);
+    const int v = task - nH, slab = v / ng, G = v - slab * ng;
+    int gm[4];
+    group_members(ph, G, gm);
+    float* V = e.Vw + (int64_t)b * e.np * e.np;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int idx = lane + 64 * u;
-      const int a = idx >> 3, c = (idx & 7) * 4;
-      const f4v x = *(const f4v*)&V[(int64_t)(rs * PB + a) * e.np + gidx(c, p1, q1)];
-      const f4v jl = *(const f4v*)&Q[(int64_t)kp * (PB * PB) + a * PB + c];
+      const int idx = t + 256 * u;
+      const int tile = idx >> 6, qd = idx & 63, k1 = tile >> 2, k2 = tile & 3;
+      const f4v x = *(const f4v*)(V + tile_off(4 * slab + k1, gm[k2], e.nb) + qd * 4);
+      const int r = qd >> 2, c = (qd & 3) * 4;
 #pragma unroll
-      for (int w2 = 0; w2 < 4; ++w2) { X[a][c + w2] = x[w2]; JL[a][c + w2] = jl[w2]; }
+      for (int w2 = 0; w2 < 4; ++w2) Xs[k1 * 16 + r][k2 * 16 + c + w2] = x[w2];
+      const int row = idx >> 4, col = (idx & 15) * 4;
+      const f4v m = *(const f4v*)(Qb + (int64_t)G * (GS * GS) + row * GS + col);
+#pragma unroll
+      for (int w2 = 0; w2 < 4; ++w2) M1[row][col + w2] = m[w2];
     }
-    wave_sync();
-    const f16v Y = mm32(X, false, JL, lane);
-    const int gj = gidx(jc, p1, q1);
+    __syncthreads();
+    const f16v Y = mm_nn(Xs, M1, qi, qj, lane);
+    __syncthreads();
+    put_quadrant(Xs, Y, qi, qj, lane);
+    __syncthreads();
 #pragma unroll
-    for (int g = 0; g < 4; ++g)
+    for (int u = 0; u < 4; ++u) {
+      const int idx = t + 256 * u;
+      const int tile = idx >> 6, qd = idx & 63, k1 = tile >> 2, k2 = tile & 3;
+      const int r = qd >> 2, c = (qd & 3) * 4;
+      f4v y;
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
-        V[(int64_t)(rs * PB + 8 * g + 4 * (lane >> 5) + r) * e.np + gj] = Y[4 * g + r];
+      for (int w2 = 0; w2 < 4; ++w2) y[w2] = Xs[k1 * 16 + r][k2 * 16 + c + w2];
+      *(f4v*)(V + tile_off(4 * slab + k1, gm[k2], e.nb) + qd * 4) = y;
+    }
   }
 }
 
-// Copy (and symmetrise) H into the padded work matrix, V = I, |H|_F^2.
-// One 32 x 32 tile per workgroup; the transposed partner tile goes through
-// LDS so that every global access is row-contiguous.
+// Tiled working copies: H (tiles on and above the diagonal, symmetrised,
+// zero padding), V = I, |H|_F^2.  One tile per workgroup.
 __global__ void k_eigh_setup(EighWs e, const float* Hin, int64_t ldh, int64_t sH, const int* mask) {
-  const int b = blockIdx.z;
+  const int b = blockIdx.y;
   if (mask && !mask[b]) return;
-  __shared__ float tt[32][33];
-  const int I0 = blockIdx.y * 32, J0 = blockIdx.x * 32;
-  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const int I = blockIdx.x / e.nb, Jb = blockIdx.x - I * e.nb;
+  const int r = threadIdx.x >> 4, c = threadIdx.x & 15;
+  const int i = I * BS + r, j = Jb * BS + c;
+  const int64_t base = (int64_t)b * e.np * e.np + tile_off(I, Jb, e.nb) + r * BS + c;
+  e.Vw[base] = i == j ? 1.f : 0.f;
+  if (I > Jb) return;  // whole workgroup
   const float* Hb = Hin + b * sH;
-  for (int r = ty; r < 32; r += 8) {
-    int i = J0 + r, j = I0 + tx;  // partner tile (J, I)
-    tt[r][tx] = (i < e.n && j < e.n) ? Hb[(int64_t)i * ldh + j] : 0.f;
-  }
-  __syncthreads();
-  float* Hw = e.Hw + (int64_t)b * e.np * e.np;
-  float* Vw = e.Vw + (int64_t)b * e.np * e.np;
-  float acc = 0.f;
-  for (int r = ty; r < 32; r += 8) {
-    int i = I0 + r, j = J0 + tx;
-    float v = 0.f;
-    if (i < e.n && j < e.n) v = 0.5f * (Hb[(int64_t)i * ldh + j] + tt[tx][r]);
-    Hw[(int64_t)i * e.np + j] = v;
-    Vw[(int64_t)i * e.np + j] = i == j ? 1.f : 0.f;
-    acc += v * v;
-  }
+  float v = 0.f;
+  if (i < e.n && j < e.n) v = 0.5f * (Hb[(int64_t)i * ldh + j] + Hb[(int64_t)j * ldh + i]);
+  e.Hw[base] = v;
+  float acc = v * v * (I == Jb ? 1.f : 2.f);
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
   if ((threadIdx.x & 63) == 0) atomicAdd(e.hnorm2 + b, acc);
+}
+
+// row-major copy of a tiled np x np matrix (one float4 per thread)
+__global__ void k_untile(const float* src, float* dst, int np, int nb, const int* mask) {
+  const int b = blockIdx.y;
+  if (mask && !mask[b]) return;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t per_row = np / 4;
+  if (idx >= (int64_t)np * per_row) return;
+  const int row = (int)(idx / per_row), c4 = (int)(idx - row * per_row) * 4;
+  const int64_t off = (int64_t)b * np * np;
+  const f4v v = *(const f4v*)(src + off + tile_off(row >> 4, c4 >> 4, nb) + (row & 15) * BS + (c4 & 15));
+  *(f4v*)(dst + off + (int64_t)row * np + c4) = v;
 }
 
 // Mark matrices whose sweep made no significant rotation as converged and
@@ -302,20 +467,15 @@ __global__ void k_eigh_check(EighWs e, const int* rotcnt, float tol, int sweep, 
   int mine = 0;
   for (int b = threadIdx.x; b < e.batch; b += blockDim.x) {
     if (e.active[b]) {
-      if (__int_as_float(rotcnt[b]) <= tol) {
-        e.active[b] = 0;
-        sweeps_out[b] = sweep + 1;
-      } else {
-        sweeps_out[b] = sweep + 1;
-        ++mine;
-      }
+      sweeps_out[b] = sweep + 1;
+      if (__int_as_float(rotcnt[b]) <= tol) e.active[b] = 0;
+      else ++mine;
     }
   }
   atomicAdd(&cnt, mine);
   __syncthreads();
   if (threadIdx.x == 0) *n_active = cnt;
 }
-
 // Sort the diagonal (eigenvalues) descending -- by value (mode 0) or by
 // magnitude (mode 1, singular values of H = W^T A with sign kept apart) --
 // with a bitonic sort in LDS; write lam, the permutation and the signs, and
@@ -442,33 +602,38 @@ hipError_t fill_f32(float* p, float v, int64_t n, hipStream_t st) {
   return hipGetLastError();
 }
 
+int eigh_blocks(int64_t n) {
+  int nb = 4;
+  while ((int64_t)nb * BS < n) nb <<= 1;
+  return nb;
+}
+
 size_t eigh_ws_bytes(int64_t batch, int64_t n, int max_sweeps) {
-  int64_t np = (n + 31) / 32 * 32;
-  int64_t npairs = np / 32;
+  const int64_t nb = eigh_blocks(n), np = nb * BS, ng = nb / 4;
   size_t f = 0;
   f += 3 * batch * np * np;          // Hw, Vw, V2
   f += batch * n;                    // lamr
-  f += batch * npairs * 1024;        // Qw
+  f += batch * ng * GS * GS;         // Qw
   f += batch;                        // hnorm2
   f += 2 * batch * n;                // sign, (perm as int)
   size_t i = batch * (size_t)(max_sweeps + 2) + batch + 16;  // rotcnt, active, counters
-  return (f + i) * 4 + 8 * 256;
+  return (f + i) * 4 + 12 * 256;
 }
 
 EighWs eigh_ws_carve(void* ws, int64_t batch, int64_t n, int max_sweeps) {
   EighWs e;
   e.batch = (int)batch;
   e.n = (int)n;
-  e.np = (int)((n + 31) / 32 * 32);
-  e.nb = e.np / 16;
-  int64_t np = e.np, npairs = np / 32;
+  e.nb = eigh_blocks(n);
+  e.np = e.nb * BS;
+  const int64_t np = e.np, ng = e.nb / 4;
   char* p = (char*)ws;
   auto take = [&](size_t bytes) { char* r = p; p += (bytes + 255) / 256 * 256; return (void*)r; };
   e.Hw = (float*)take(batch * np * np * 4);
   e.Vw = (float*)take(batch * np * np * 4);
   e.V2 = (float*)take(batch * np * np * 4);
   e.lamr = (float*)take(batch * n * 4);
-  e.Qw = (float*)take(batch * npairs * 1024 * 4);
+  e.Qw = (float*)take(batch * ng * GS * GS * 4);
   e.hnorm2 = (float*)take(batch * 4);
   e.sgn = (float*)take(batch * n * 4);
   e.perm = (int*)take(batch * n * 4);
@@ -477,6 +642,30 @@ EighWs eigh_ws_carve(void* ws, int64_t batch, int64_t n, int max_sweeps) {
   e.counter = (int*)take(64);
   e.max_sweeps = max_sweeps;
   return e;
+}
+
+// The phases of one sweep over nb blocks: (1, -) with the full inner rounds,
+// then (2, 3), (4, 5), ..., (nb - 2, nb - 1) with cross rounds.  The first
+// phase has one step; its grouping uses sB = 2 (any other partner works).
+std::vector<EighPhase> eigh_phases(int nb) {
+  std::vector<EighPhase> out;
+  auto make = [](int sA, int sB, int fullA, int skipB) {
+    EighPhase ph;
+    ph.sA = sA;
+    ph.sB = sB;
+    ph.fullA = fullA;
+    ph.skipB = skipB;
+    int u = sA, v = sB;
+    const int p1 = 31 - __builtin_clz((unsigned)u);
+    if ((v >> p1) & 1) v ^= u;
+    const int p2 = 31 - __builtin_clz((unsigned)v);
+    ph.lo = std::min(p1, p2);
+    ph.hi = std::max(p1, p2);
+    return ph;
+  };
+  out.push_back(make(1, 2, 1, 1));
+  for (int s = 2; s + 1 < nb; s += 2) out.push_back(make(s, s + 1, 0, 0));
+  return out;
 }
 
 // Full eigendecomposition of a batch of symmetric n x n matrices.
@@ -490,55 +679,51 @@ hipError_t eigh_run(EighWs e, const float* H, int64_t ldh, int64_t sH, int mode,
   if ((err = fill_i32(e.rotcnt, 0, (int64_t)batch * (e.max_sweeps + 2), st))) return err;
   if (mask) { if ((err = copy_i32(e.active, mask, batch, st))) return err; }
   else if ((err = fill_i32(e.active, 1, batch, st))) return err;
-  {
-    const int tiles = e.np / 32;
-    hipLaunchKernelGGL(k_eigh_setup, dim3(tiles, tiles, batch), dim3(256), 0, st, e, H, ldh, sH, mask);
-    if ((err = hipGetLastError())) return err;
-  }
-  const int npairs = e.nb / 2;
-  const int nh = npairs * (npairs - 1) / 2;
-  const int ntask = nh + (e.np / 32) * npairs;
-  const int steps = e.nb - 1;
-  const unsigned solve_blocks = (unsigned)cdiv((int64_t)batch * npairs, 4);
-  const unsigned apply_blocks = (unsigned)cdiv((int64_t)batch * ntask, 4);
-  // algorithmic flops per matrix and step: pair solves (2 x 2 block updates,
-  // 24 flops each, and rotation accumulation, 6 per entry pair) and the
-  // block rotations (two 32^3 products per off-diagonal pair block, one per
-  // 32-row slab of V)
-  const double solve_work = (double)npairs * 31.0 * (256.0 * 24.0 + 512.0 * 6.0);
-  const double apply_work = (double)nh * 4.0 * 32768.0 + (double)(e.np / 32) * npairs * 2.0 * 32768.0;
+  hipLaunchKernelGGL(k_eigh_setup, dim3(e.nb * e.nb, batch), dim3(256), 0, st, e, H, ldh, sH, mask);
+  if ((err = hipGetLastError())) return err;
+  const int ng = e.nb / 4;
+  const int nH = ng * (ng - 1) / 2;
+  const int ntask = nH + ng * ng;
+  const std::vector<EighPhase> phases = eigh_phases(e.nb);
+  const unsigned solve_blocks = (unsigned)(batch * ng);
+  const unsigned apply_blocks = (unsigned)((int64_t)cdiv(batch, 8) * 8 * ntask);
+  // algorithmic flops per matrix: a pair round updates 256 2 x 2 blocks
+  // (24 flops each) and 512 rotation-accumulator pairs (6 each); the apply
+  // does two 64^3 products per pair of groups and one per slab of V
+  const double round_work = 256.0 * 24.0 + 512.0 * 6.0;
+  const double apply_work = (double)nH * 4.0 * GS * GS * GS + (double)ng * ng * 2.0 * GS * GS * GS;
+  auto solve_work = [&](const EighPhase& ph, int reps) {
+    const int rounds = (ph.fullA ? 31 : 16) + (ph.skipB ? 0 : 16);
+    return (double)ng * 2.0 * rounds * round_work * reps;
+  };
   int n_active = batch;
-  if (mask) {  // active count of a masked run is only needed for the work tally
-    n_active = batch;
-  }
   int sweep = 0;
   for (; sweep < e.max_sweeps; ++sweep) {
     int* rc = e.rotcnt + (int64_t)batch * sweep;
-    for (int s = 0; s < steps; ++s) {
+    for (const EighPhase& ph : phases) {
       {
-        ProfScope ps(PROF_JAC_SOLVE_F32, st, solve_work * o.inner_sweeps * n_active);
-        hipLaunchKernelGGL(k_jac_solve<float>, dim3(solve_blocks), dim3(256), 0, st, e, s,
-                           o.inner_sweeps, o.abs_tol, rc);
+        ProfScope ps(PROF_JAC_SOLVE_F32, st, solve_work(ph, o.inner_sweeps) * n_active);
+        hipLaunchKernelGGL(k_jac_solve<float>, dim3(solve_blocks), dim3(128), 0, st, e, ph, o.inner_sweeps,
+                           o.abs_tol, rc);
       }
       if ((err = hipGetLastError())) return err;
-      if (ntask > 0) {
+      {
         ProfScope ps(PROF_JAC_APPLY, st, apply_work * n_active);
-        hipLaunchKernelGGL(k_jac_apply, dim3(apply_blocks), dim3(256), 0, st, e, s);
-        if ((err = hipGetLastError())) return err;
+        hipLaunchKernelGGL(k_jac_apply, dim3(apply_blocks), dim3(256), 0, st, e, ph);
       }
+      if ((err = hipGetLastError())) return err;
     }
     hipLaunchKernelGGL(k_eigh_check, dim3(1), dim3(1024), 0, st, e, rc, o.tol, sweep, sweeps_out, e.counter);
     if ((err = hipGetLastError())) return err;
     if ((err = hipMemcpyAsync(host_counter, e.counter, sizeof(int), hipMemcpyDeviceToHost, st))) return err;
     if ((err = hipStreamSynchronize(st))) return err;
     n_active = *host_counter;
-    if (*host_counter == 0) break;
+    if (n_active == 0) break;
   }
   // matrices still active after max_sweeps did not converge
   if (sweep == e.max_sweeps) {
-    // flag them: active[b] == 1
-    hipLaunchKernelGGL(k_flag_active, dim3(cdiv(batch, 256)), dim3(256), 0, st, e.active, batch,
-                       flags, (int)SVDP_FLAG_EIGH_NOT_CONVERGED);
+    hipLaunchKernelGGL(k_flag_active, dim3(cdiv(batch, 256)), dim3(256), 0, st, e.active, batch, flags,
+                       (int)SVDP_FLAG_EIGH_NOT_CONVERGED);
     if ((err = hipGetLastError())) return err;
   }
   // final sweep(s) with FP64 pair solves on every matrix
@@ -546,40 +731,43 @@ hipError_t eigh_run(EighWs e, const float* H, int64_t ldh, int64_t sH, int mode,
     if (mask) { if ((err = copy_i32(e.active, mask, batch, st))) return err; }
     else if ((err = fill_i32(e.active, 1, batch, st))) return err;
     for (int f = 0; f < o.fp64_sweeps; ++f)
-      for (int s = 0; s < steps; ++s) {
+      for (const EighPhase& ph : phases) {
         {
-          ProfScope ps(PROF_JAC_SOLVE_F64, st, solve_work * o.fp64_inner * batch);
-          hipLaunchKernelGGL(k_jac_solve<double>, dim3(solve_blocks), dim3(256), 0, st, e, s,
-                             o.fp64_inner, o.abs_tol, (int*)nullptr);
+          ProfScope ps(PROF_JAC_SOLVE_F64, st, solve_work(ph, o.fp64_inner) * batch);
+          hipLaunchKernelGGL(k_jac_solve<double>, dim3(solve_blocks), dim3(128), 0, st, e, ph, o.fp64_inner,
+                             o.abs_tol, (int*)nullptr);
         }
         if ((err = hipGetLastError())) return err;
-        if (ntask > 0) {
+        {
           ProfScope ps(PROF_JAC_APPLY, st, apply_work * batch);
-          hipLaunchKernelGGL(k_jac_apply, dim3(apply_blocks), dim3(256), 0, st, e, s);
-          if ((err = hipGetLastError())) return err;
+          hipLaunchKernelGGL(k_jac_apply, dim3(apply_blocks), dim3(256), 0, st, e, ph);
         }
+        if ((err = hipGetLastError())) return err;
       }
   }
-  // One Newton-Schulz step re-orthonormalises the accumulated rotations,
-  // V2 = V (3 I - V^T V) / 2, then the eigenvalues are the Rayleigh
-  // quotients v_i^T H v_i against the input matrix.
+  // V (tiled) -> row-major in Hw; one Newton-Schulz step re-orthonormalises
+  // it, V2 = V (3 I - V^T V) / 2 (V^T V in Vw); the eigenvalues are the
+  // Rayleigh quotients v_i^T H v_i against the input matrix (H V2 in Hw).
   {
     const int np = e.np;
+    const int64_t nq = (int64_t)np * np / 4;
+    hipLaunchKernelGGL(k_untile, dim3(cdiv(nq, 256), batch), dim3(256), 0, st, e.Vw, e.Hw, np, e.nb, mask);
+    if ((err = hipGetLastError())) return err;
     GemmArgs g;
     memset(&g, 0, sizeof(g));
     g.M = np; g.N = np; g.K = np; g.batch = batch;
-    g.A = e.Vw; g.lda = np; g.sA = (int64_t)np * np;
-    g.B = e.Vw; g.ldb = np; g.sB = (int64_t)np * np;
-    g.C = e.Hw; g.ldc = np; g.sC = (int64_t)np * np;
+    g.A = e.Hw; g.lda = np; g.sA = (int64_t)np * np;
+    g.B = e.Hw; g.ldb = np; g.sB = (int64_t)np * np;
+    g.C = e.Vw; g.ldc = np; g.sC = (int64_t)np * np;
     g.alpha = 1.f; g.sym = 1; g.active = mask;
     if ((err = gemm_launch(g, PREC_F32, 1, 0, st))) return err;
     GemmArgs u;
     memset(&u, 0, sizeof(u));
     u.M = np; u.N = np; u.K = np; u.batch = batch;
-    u.A = e.Vw; u.lda = np; u.sA = (int64_t)np * np;
-    u.B = e.Hw; u.ldb = np; u.sB = (int64_t)np * np;
+    u.A = e.Hw; u.lda = np; u.sA = (int64_t)np * np;
+    u.B = e.Vw; u.ldb = np; u.sB = (int64_t)np * np;
     u.C = e.V2; u.ldc = np; u.sC = (int64_t)np * np;
-    u.Cin = e.Vw; u.ldcin = np; u.sCin = (int64_t)np * np;
+    u.Cin = e.Hw; u.ldcin = np; u.sCin = (int64_t)np * np;
     u.alpha = -0.5f; u.beta = 1.5f; u.active = mask;
     if ((err = gemm_launch(u, PREC_F32, 0, 0, st))) return err;
     GemmArgs r;

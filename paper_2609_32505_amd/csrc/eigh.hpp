@@ -4,12 +4,12 @@
 #include "svdp.h"
 
 struct EighWs {
-  int batch, n, np, nb, max_sweeps;
-  float* Hw;      // batch x np x np working matrix
-  float* Vw;      // batch x np x np accumulated rotations
-  float* V2;      // batch x np x np re-orthonormalised eigenvectors
+  int batch, n, np, nb, max_sweeps;  // np = 16 nb, nb a power of two >= 4
+  float* Hw;      // batch x np x np: H as 16 x 16 tiles (those on and above the diagonal)
+  float* Vw;      // batch x np x np: accumulated rotations as 16 x 16 tiles
+  float* V2;      // batch x np x np re-orthonormalised eigenvectors (row-major)
   float* lamr;    // batch x n Rayleigh-quotient eigenvalues
-  float* Qw;      // batch x (nb/2) x 64 x 64 block rotations of the current step
+  float* Qw;      // batch x (nb/4) x 64 x 64 group rotations of the current phase
   float* hnorm2;  // batch: |H|_F^2
   float* sgn;     // batch x n: sign of each sorted eigenvalue
   int* perm;      // batch x n: sorted position -> working column
@@ -18,10 +18,20 @@ struct EighWs {
   int* counter;   // device scalar: active matrices after a sweep
 };
 
+// Two fused block-Jacobi steps: block B is paired with B ^ sA, then with
+// B ^ sB; groups {B, B^sA, B^sB, B^sA^sB} are indexed by the member whose
+// bits lo and hi are clear.
+struct EighPhase {
+  int sA, sB;
+  int lo, hi;
+  int fullA;  // the first step also runs the intra-block rounds
+  int skipB;  // the phase has a single step
+};
+
 struct EighOpts {
-  int inner_sweeps;  // scalar sweeps per 64 x 64 pair subproblem (FP32)
+  int inner_sweeps;  // repetitions of a step's scalar rounds per pair subproblem (FP32)
   int fp64_sweeps;   // final block sweeps with FP64 pair solves
-  int fp64_inner;    // scalar sweeps per pair subproblem in those
+  int fp64_inner;    // repetitions in those
   float tol;         // converged after a sweep whose largest rotated |h_pq| is
                      // <= tol sqrt(|h_pp h_qq|) (quadratic convergence: the next
                      // sweep, the FP64 one, leaves ~tol^2)
@@ -29,6 +39,7 @@ struct EighOpts {
   float neg_tol;     // NEG_EIGENVALUE when lam_min < -neg_tol max|lam| (mode 1)
 };
 
+int eigh_blocks(int64_t n);
 size_t eigh_ws_bytes(int64_t batch, int64_t n, int max_sweeps);
 EighWs eigh_ws_carve(void* ws, int64_t batch, int64_t n, int max_sweeps);
 hipError_t eigh_run(EighWs e, const float* H, int64_t ldh, int64_t sH, int mode,

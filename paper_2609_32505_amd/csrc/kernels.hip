@@ -113,7 +113,7 @@ __global__ void k_set_coef(float* coef, CoefTab t, int steps) {
 }
 
 __global__ void k_cans_check(int batch, float* conv, float tol, int k, int* active, int* where,
-                             int* iters, int* flags, int* counter) {
+                             int* iters, const int* iter_base, int base_stride, int* flags, int* counter) {
   __shared__ int cnt;
   if (threadIdx.x == 0) cnt = 0;
   __syncthreads();
@@ -123,7 +123,7 @@ __global__ void k_cans_check(int batch, float* conv, float tol, int k, int* acti
     float d2 = conv[2 * b], o2 = conv[2 * b + 1];
     conv[2 * b] = 0.f;
     conv[2 * b + 1] = 0.f;
-    iters[b] = k + 1;
+    iters[b] = (iter_base ? iter_base[(int64_t)b * base_stride] : 0) + k + 1;
     where[b] = (k + 1) & 1;
     if (!isfinite(d2) || !isfinite(o2)) {
       active[b] = 0;
@@ -683,9 +683,10 @@ hipError_t set_coef_launch(float* coef, const double* tab, int steps, hipStream_
 }
 
 hipError_t cans_check_launch(int batch, float* conv, float tol, int k, int* active, int* where,
-                             int* iters, int* flags, int* counter, hipStream_t st) {
+                             int* iters, const int* iter_base, int base_stride, int* flags,
+                             int* counter, hipStream_t st) {
   hipLaunchKernelGGL(k_cans_check, dim3(1), dim3(1024), 0, st, batch, conv, tol, k, active, where,
-                     iters, flags, counter);
+                     iters, iter_base, base_stride, flags, counter);
   LAUNCH_CHECK();
 }
 

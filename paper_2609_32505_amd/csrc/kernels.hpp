@@ -20,10 +20,12 @@ hipError_t scale_copy_launch(const float* A, int64_t lda, int64_t sA, int batch,
 // Broadcast a coefficient table of up to 64 steps into coef (kcap x 2 floats).
 hipError_t set_coef_launch(float* coef, const double* tab, int steps, hipStream_t st);
 // After step k: matrices whose relative change is <= tol stop (active = 0),
-// where[b] = parity of the buffer holding their last iterate; iters[b] = k+1;
-// conv sums are cleared; *counter = number still active.
-hipError_t cans_check_launch(int batch, float* conv, float tol, int k, int* active,
-                             int* where, int* iters, int* flags, int* counter, hipStream_t st);
+// where[b] = parity of the buffer holding their last iterate;
+// iters[b] = iter_base[b * base_stride] + k + 1 (base 0 when iter_base is
+// null); conv sums are cleared; *counter = number still active.
+hipError_t cans_check_launch(int batch, float* conv, float tol, int k, int* active, int* where,
+                             int* iters, const int* iter_base, int base_stride, int* flags,
+                             int* counter, hipStream_t st);
 // residual[b] = |G - I|_F / sqrt(n) from a Gram matrix G (FP32 or BF16)
 hipError_t residual_launch(const void* G, int gbf16, int batch, int n, float* resid,
                            const int* mask, hipStream_t st);
