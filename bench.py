@@ -93,7 +93,12 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-only", action="store_true",
-                    help="run warmup + steps of the learned path only (for rocprofv3)")
+                    help="run warmup + steps of one path only (for rocprofv3)")
+    ap.add_argument("--path", choices=("learned", "plain"), default="learned",
+                    help="the path --profile-only runs")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="with --profile-only: first copy a 256 MiB buffer (a kernel of known traffic "
+                         "for scaling HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
@@ -151,12 +156,20 @@ def main():
             prof = kernel_profile(L)
         return ms, out, prof
 
+    if args.profile_only:
+        if args.calibrate_copy:
+            src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+            dst = torch.empty_like(src)
+            dst.copy_(src)
+            torch.cuda.synchronize()
+            log("calibration copy: 268435456 bytes read, 268435456 bytes written")
+        ms, _, _ = timed(args.path == "learned", False)
+        log(f"{args.path}: {ms:.2f} ms/step")
+        print(json.dumps({"profile_only": True, "path": args.path, "ms_per_step": ms}))
+        return
     ms_l, (S_l, info_l, _), prof = timed(True, True)
     log(f"learned: {ms_l:.2f} ms/step")
-    if args.profile_only:
-        print(json.dumps({"profile_only": True, "ms_per_step": ms_l}))
-        return
-    ms_p, (S_p, info_p, _), _ = timed(False, False)
+    ms_p, (S_p, info_p, _), prof_p = timed(False, True)
     log(f"plain fp32: {ms_p:.2f} ms/step")
 
     il, ip = api.info_to_numpy(info_l), api.info_to_numpy(info_p)
@@ -184,11 +197,14 @@ def main():
         "config": {"workload": f"{B} x {n} x {n} FP32, sigma log-uniform [1e-3,1], svd_polar_fwd + "
                                f"svd_polar_bwd, learned-bound BF16 CANS", "batch": B, "m": n, "n": n},
         "plain_fp32": {"value": round(B / (ms_p * 1e-3), 3), "ms_per_step": round(ms_p, 3),
-                       "iters": [int(il["iters"].max()), int(ip["iters"].max())]},
+                       "iters_max": int(ip["iters"].max()), "iters_mean": round(float(ip["iters"].mean()), 2),
+                       "kernels": {k2: {"ms_per_step": round(v["ms"] / args.steps, 3), "launches": v["launches"]}
+                                   for k2, v in prof_p.items()}},
         "speedup_learned_vs_plain": round(ms_p / ms_l, 4),
         "sigma_err": {"learned_vs_plain_max": err_lp, "plain_vs_oracle_sampled": err_po,
                       "learned_vs_oracle_sampled": err_lo, "valid": bool(valid)},
-        "learned_info": {"iters_max": int(il["iters"].max()), "sweeps_max": int(il["sweeps"].max()),
+        "learned_info": {"iters_max": int(il["iters"].max()), "iters_mean": round(float(il["iters"].mean()), 2),
+                         "sweeps_max": int(il["sweeps"].max()),
                          "fallbacks": int(((il["flags"] & L.FLAG_FALLBACK_USED) != 0).sum())},
         "roofline": roof,
         "kernels": {k2: {"ms_per_step": round(v["ms"] / args.steps, 3), "launches": v["launches"]}

@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "common.hpp"
 #include "eigh.hpp"
@@ -16,6 +17,7 @@ struct svdp_handle {
   float* model = nullptr;  // device: SVDP_MODEL_FLOATS
   bool has_model = false;
   int* host_word = nullptr;  // pinned: counter read-back
+  EighAux aux{nullptr, nullptr, nullptr, nullptr};  // second stream of the eigensolver
 };
 
 namespace {
@@ -182,7 +184,7 @@ FwdWs carve_fwd(void* base, const svdp_params* p, size_t* total) {
   w.counter = c.take<int>(16);
   w.ksteps = c.take<int>(2 * b);
   w.kmax = c.take<int>(16);
-  w.hist = c.take<int>(2 * 65);
+  w.hist = c.take<int>(4 * 64 + 8);
   if (total) *total = c.off;
   return w;
 }
@@ -213,9 +215,12 @@ svdp_status read_counter(Ctx& c, const int* dev, int* out) {
 }
 
 // One CANS step on buffers (Xc -> Xn): G = Xc^T Xc, Xn = alpha Xc + beta Xc G.
+// With ksched, matrix b takes part only if its step kidx has category kcat
+// (sched_cat over the per-matrix counts (K, K1)).
 hipError_t cans_step(Ctx& c, int prec, const void* Xc, void* Xn, int in_bf16, int out_bf16,
                      const float* coef, int64_t coef_bstride, int kidx, const int* active,
-                     float* conv, int n_active = 0) {
+                     float* conv, int n_active = 0, const int* ksched = nullptr, int kcat = 0,
+                     int kbf16 = 0) {
   const int m = c.m, n = c.n, B = c.batch;
   GemmArgs g = gemm_base(n, n, m, B);
   g.work_batch = n_active;
@@ -224,6 +229,7 @@ hipError_t cans_step(Ctx& c, int prec, const void* Xc, void* Xn, int in_bf16, in
   g.C = c.w.G; g.ldc = n; g.sC = (int64_t)n * n;
   g.sym = 1;
   g.active = active;
+  g.ksched = ksched; g.kstep = kidx; g.kcat = kcat; g.kbf16 = kbf16;
   g.in_bf16 = in_bf16;
   g.out_bf16 = prec == PREC_BF16 ? 1 : 0;
   hipError_t e = gemm_launch(g, prec, 1, 0, c.st);
@@ -236,6 +242,7 @@ hipError_t cans_step(Ctx& c, int prec, const void* Xc, void* Xn, int in_bf16, in
   u.Cin = Xc; u.ldcin = n; u.sCin = (int64_t)m * n; u.cin_bf16 = in_bf16;
   u.coef = coef; u.coef_bstride = coef_bstride; u.coef_idx = kidx;
   u.active = active;
+  u.ksched = ksched; u.kstep = kidx; u.kcat = kcat; u.kbf16 = kbf16;
   u.work_batch = n_active;
   u.conv = conv;
   u.in_bf16 = in_bf16;
@@ -319,43 +326,40 @@ svdp_status bounded(Ctx& c) {
     HIPCHK(bounds_launch(B, 1, nullptr, nullptr, p->user_bounds, p->margin_max, p->margin_min, p->bf16_handoff,
                          p->bf16_from, kcap, w.scale, w.coef, w.ksteps, w.kmax, nullptr, c.st), "bounds");
   }
-  // Matrices are grouped by their own step count K (to the BF16 hand-off);
-  // each group runs its schedule under a mask: FP32 steps [0, K1), BF16
-  // steps [K1, K) with K1 the group's largest FP32 count, then the FP32
-  // refinement.  The host reads the histogram of K (one synchronisation).
-  HIPCHK(step_hist_launch(B, w.ksteps, kcap, w.hist, w.hist + 65, c.st), "step hist");
-  HIPCHK(hipMemcpyAsync(c.h->host_word, w.hist, 130 * sizeof(int), hipMemcpyDeviceToHost, c.st), "hist copy");
-  HIPCHK(hipStreamSynchronize(c.st), "hist sync");
-  int hist[65], k1g[65];
-  for (int i = 0; i <= kcap; ++i) { hist[i] = c.h->host_word[i]; k1g[i] = c.h->host_word[65 + i]; }
+  // Every matrix runs its own schedule: K interval-optimal steps, the first
+  // K1 in FP32 (while small singular values are still small: BF16 rounding
+  // would rotate their singular vectors), the rest in BF16.  Step k runs as
+  // one batch-wide launch per category of step (FP32 or BF16 in, FP32 or
+  // BF16 out); the GEMMs skip the matrices of other categories.  The
+  // iterate after step k lives in X[k % 2] (FP32) or Y[k % 2] (BF16).  The
+  // host reads the per-step category counts (one synchronisation).
   const int bf16 = p->precision == SVDP_PREC_BF16;
-  for (int Kg = 0; Kg <= kcap; ++Kg) {
-    const int count = hist[Kg];
-    if (count == 0) continue;
-    const int K = std::max(1, Kg);
-    const int K1 = bf16 ? std::max(0, std::min(k1g[Kg], K)) : K;
-    const int* gm = w.gmask;
-    HIPCHK(group_mask_launch(B, w.ksteps, Kg, w.gmask, c.st), "group mask");
-    // steps [0, K1) in FP32 while small singular values are still small
-    // (BF16 rounding would rotate their singular vectors), [K1, K) in BF16.
-    // The iterate after step k lives in X[(k + K) % 2] (FP32) or
-    // Y[(k + K) % 2] (BF16), so every group ends in X0.
-    auto buf = [&](int k, int isbf) -> void* {
-      const int odd = (k + K) & 1;
-      return isbf ? (odd ? w.Y1 : w.Y0) : (void*)(odd ? w.X1 : w.X0);
-    };
-    HIPCHK(scale_copy_launch(c.A, c.lda, c.sA, B, m, n, w.scale, buf(0, K1 == 0), K1 == 0 ? 1 : 0, gm, c.st),
-           "normalise");
-    for (int k = 0; k < K; ++k) {
-      const int prec = k < K1 ? PREC_F32 : PREC_BF16;
-      const int in_bf = k >= K1;
-      const int out_bf = (k + 1 >= K1) && (k + 1 < K);
-      HIPCHK(cans_step(c, prec, buf(k, in_bf), buf(k + 1, out_bf), in_bf, out_bf, w.coef, kcap, k, gm, nullptr,
-                       count), "cans step");
-    }
-    // iterations so far, the base of the refinement's count
-    HIPCHK(fill_masked_launch(w.iters, K, B, gm, c.st), "iters");
+  HIPCHK(sched_counts_launch(B, w.ksteps, kcap, bf16, w.hist, c.st), "schedule counts");
+  HIPCHK(hipMemcpyAsync(c.h->host_word, w.hist, (4 * kcap + 2) * sizeof(int), hipMemcpyDeviceToHost, c.st),
+         "schedule copy");
+  HIPCHK(hipStreamSynchronize(c.st), "schedule sync");
+  std::vector<int> cnt(c.h->host_word, c.h->host_word + 4 * kcap + 2);
+  const int n_bf_start = cnt[4 * kcap], kmax = cnt[4 * kcap + 1];
+  HIPCHK(sched_mask_launch(B, w.ksteps, bf16, 0, w.gmask, c.st), "fp32 start");
+  HIPCHK(scale_copy_launch(c.A, c.lda, c.sA, B, m, n, w.scale, w.X0, 0, w.gmask, c.st), "normalise");
+  if (n_bf_start > 0) {
+    HIPCHK(sched_mask_launch(B, w.ksteps, bf16, 1, w.gmask, c.st), "bf16 start");
+    HIPCHK(scale_copy_launch(c.A, c.lda, c.sA, B, m, n, w.scale, w.Y0, 1, w.gmask, c.st), "normalise");
   }
+  for (int k = 0; k < kmax; ++k)
+    for (int cat = 0; cat < 4; ++cat) {
+      const int count = cnt[4 * k + cat];
+      if (count == 0) continue;
+      const int in_bf = cat >= 2, out_bf = cat == 1 || cat == 2;
+      const void* Xc = in_bf ? ((k & 1) ? w.Y1 : w.Y0) : (const void*)((k & 1) ? w.X1 : w.X0);
+      void* Xn = out_bf ? (((k + 1) & 1) ? w.Y1 : w.Y0) : (void*)(((k + 1) & 1) ? w.X1 : w.X0);
+      HIPCHK(cans_step(c, in_bf ? PREC_BF16 : PREC_F32, Xc, Xn, in_bf, out_bf, w.coef, kcap, k, nullptr, nullptr,
+                       count, w.ksteps, cat, bf16), "cans step");
+    }
+  // the last iterate of a matrix with K odd is in X1: move it to X0
+  HIPCHK(sched_mask_launch(B, w.ksteps, bf16, 2, w.gmask, c.st), "odd mask");
+  HIPCHK(copy_masked_launch(w.X1, w.X0, B, (int64_t)m * n, w.gmask, c.st), "to X0");
+  HIPCHK(sched_iters_launch(B, w.ksteps, w.iters, c.st), "iters");
   // FP32 refinement of the whole batch from X0: interval-optimal steps from
   // the hand-off interval (tending to the Newton-Schulz cubic), at least
   // refine_steps of them, then per matrix until the relative change is below
@@ -446,7 +450,7 @@ svdp_status svd_tail(Ctx& c, float* U, int64_t ldu, int64_t sU, float* S, int64_
   if (s) return s;
   EighWs e = eigh_ws_carve(w.eigh, B, n, p->max_sweeps);
   HIPCHK(eigh_run(e, w.G, n, (int64_t)n * n, 1, eigh_opts(p), S, sS, V, ldv, sV, w.sweeps, w.flags,
-                  c.h->host_word, mask, c.st), "eigh");
+                  c.h->host_word, mask, &c.h->aux, c.st), "eigh");
   GemmArgs g = gemm_base(m, n, n, B);
   g.A = w.X0; g.A_alt = w.X1; g.a_sel = w.where; g.lda = n; g.sA = (int64_t)m * n;
   g.B = V; g.ldb = ldv; g.sB = sV;
@@ -529,9 +533,12 @@ svdp_status svdp_create(svdp_handle** out) {
   svdp_handle* h = new svdp_handle();
   hipError_t e = hipMalloc((void**)&h->model, SVDP_MODEL_FLOATS * sizeof(float));
   if (e == hipSuccess) e = hipHostMalloc((void**)&h->host_word, 4096, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&h->aux.st2, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&h->aux.fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&h->aux.join, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&h->aux.skew, hipEventDisableTiming);
   if (e != hipSuccess) {
-    if (h->model) (void)hipFree(h->model);
-    delete h;
+    (void)svdp_destroy(h);
     return hip_fail(e, "svdp_create");
   }
   *out = h;
@@ -540,6 +547,11 @@ svdp_status svdp_create(svdp_handle** out) {
 
 svdp_status svdp_destroy(svdp_handle* h) {
   if (!h) return SVDP_OK;
+  if (h->aux.st2) (void)hipStreamSynchronize(h->aux.st2);
+  if (h->aux.skew) (void)hipEventDestroy(h->aux.skew);
+  if (h->aux.join) (void)hipEventDestroy(h->aux.join);
+  if (h->aux.fork) (void)hipEventDestroy(h->aux.fork);
+  if (h->aux.st2) (void)hipStreamDestroy(h->aux.st2);
   if (h->model) (void)hipFree(h->model);
   if (h->host_word) (void)hipHostFree(h->host_word);
   delete h;
@@ -666,7 +678,7 @@ svdp_status polar_fwd(svdp_handle* h, const svdp_params* p, const float* A, int6
     if (V_cache) {
       EighWs e = eigh_ws_carve(c.w.eigh, B, n, p->max_sweeps);
       HIPCHK(eigh_run(e, c.w.G, n, (int64_t)n * n, 0, eigh_opts(p), S_cache, sS, V_cache, ldv, sV, c.w.sweeps,
-                      c.w.flags, h->host_word, mask, c.st), "eigh");
+                      c.w.flags, h->host_word, mask, &h->aux, c.st), "eigh");
     }
     return SVDP_OK;
   };
@@ -795,7 +807,7 @@ svdp_status polar_bwd(svdp_handle* h, const svdp_params* p, const float* A, int6
     EighWs e = eigh_ws_carve(ews, B, n, p->max_sweeps);
     HIPCHK(fill_i32(flags, 0, B, st), "flags");
     HIPCHK(eigh_run(e, H, ldh, sH, 0, eigh_opts(p), Sown, n, Vown, n, (int64_t)n * n, sweeps, flags, h->host_word,
-                    nullptr, st), "eigh");
+                    nullptr, &h->aux, st), "eigh");
     Sx = Sown; Vx = Vown; sSx = n; ldvx = n; sVx = (int64_t)n * n;
   }
   {  // MV = A V
@@ -877,8 +889,8 @@ svdp_status svdp_eigh(svdp_handle* h, const svdp_params* p, const float* H, int6
   EighWs e = eigh_ws_carve(ews, B, n, p->max_sweeps);
   HIPCHK(fill_i32(flags, 0, B, st), "flags");
   HIPCHK(fill_i32(sweeps, 0, B, st), "sweeps");
-  HIPCHK(eigh_run(e, H, ldh, sH, 0, eigh_opts(p), lam, slam, V, ldv, sV, sweeps, flags, h->host_word, nullptr, st),
-         "eigh");
+  HIPCHK(eigh_run(e, H, ldh, sH, 0, eigh_opts(p), lam, slam, V, ldv, sV, sweeps, flags, h->host_word, nullptr,
+                  &h->aux, st), "eigh");
   if (info) HIPCHK(info_pack_launch(B, nullptr, sweeps, flags, nullptr, info, nullptr, st), "info");
   return SVDP_OK;
 }

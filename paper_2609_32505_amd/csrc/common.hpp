@@ -32,6 +32,9 @@ struct GemmArgs {
   const float* colscale; int64_t cs_stride;
   const float* colscale_in; int64_t csin_stride;
   const int* active;   // matrix b is skipped when active[b] == 0
+  const int* ksched;   // bounded CANS schedule: per-matrix (K, K1); when set,
+  int kstep, kcat;     // matrix b runs only if sched_cat(ksched, b, kstep,
+  int kbf16;           // kbf16) == kcat
   float* conv;         // per matrix: += sum (out - Cin)^2, += sum out^2
   int sym;             // output symmetric: upper tiles computed, mirrored
   int work_batch;      // matrices actually computed (for work accounting; 0 = batch)
@@ -43,6 +46,19 @@ enum { PREC_F32 = 0, PREC_BF16 = 1 };
 // Launch a batched GEMM.  prec selects FP32 MFMA (inputs FP32) or BF16 MFMA
 // (inputs FP32 or BF16 per in_bf16, rounded to BF16, FP32 accumulation).
 hipError_t gemm_launch(const GemmArgs& g, int prec, int ta, int tb, hipStream_t st);
+
+// Category of step k of matrix b in the bounded CANS schedule, from its step
+// counts (K, K1): K steps in all, the first K1 in FP32 (all of them when
+// bf16 == 0).  -1: no step; 0: FP32 in, FP32 out; 1: FP32 in, BF16 out (the
+// last FP32 step before BF16 ones); 2: BF16 in and out; 3: BF16 in, FP32
+// out (the last step).
+SVDP_DEV int sched_cat(const int* ks, int b, int k, int bf16) {
+  const int K = max(ks[2 * b], 1);
+  const int K1 = bf16 ? min(max(ks[2 * b + 1], 0), K) : K;
+  if (k >= K) return -1;
+  if (k < K1) return (k + 1 >= K1 && k + 1 < K) ? 1 : 0;
+  return k + 1 < K ? 2 : 3;
+}
 
 SVDP_DEV float bf2f(bf16_t x) { return (float)x; }
 SVDP_DEV bf16_t f2bf(float x) { return (bf16_t)x; }

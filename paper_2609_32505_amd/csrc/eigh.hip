@@ -43,6 +43,8 @@ constexpr int PB = 32;      // pair subproblem size
 constexpr int GS = 64;      // group size (four blocks)
 constexpr int LP = PB + 1;  // LDS pitch of 32-wide arrays
 constexpr int GP = GS + 1;  // LDS pitch of 64-wide arrays
+// per group: M_G (64 x 64) and the step-A rotations (2 x 32 x 32), FP32
+constexpr int QSTRIDE = GS * GS + 2 * PB * PB;
 
 SVDP_DEV int insert0(int x, int p) { return ((x >> p) << (p + 1)) | (x & ((1 << p) - 1)); }
 
@@ -59,21 +61,6 @@ SVDP_DEV void group_members(const EighPhase& ph, int gi, int* g) {
 }
 
 SVDP_DEV int64_t tile_off(int I, int J, int nb) { return ((int64_t)I * nb + J) * (BS * BS); }
-
-// position in the 64-index group of element a (0..31) of pair w: step A
-// pairs are contiguous halves, step B pairs interleave 16-blocks
-SVDP_DEV int lmap(int stepB, int w, int a) { return stepB ? a + 16 * w + (a & 16) : 32 * w + a; }
-
-// rotation k (0..15) of inner round t (1..31): the pair (x, x ^ t), x < x ^ t
-SVDP_DEV void inner_pair(int t, int k, int& x, int& y) {
-  if (t >= 16) {
-    x = k;
-  } else {
-    const int hb = 31 - __clz(t);
-    x = ((k >> 3) << 4) | insert0(k & 7, hb);
-  }
-  y = x ^ t;
-}
 
 // orders the wave's own LDS traffic: no instruction is moved across it, and
 // LDS operations of one wave complete in issue order
@@ -101,80 +88,106 @@ SVDP_DEV f16v zero16() {
   return z;
 }
 
+template <typename R> struct RotPair { R c, s; };
+template <typename R> struct XPitch { static constexpr int v = 66; };  // FP32: row stride 2 mod 32 banks
+template <> struct XPitch<double> { static constexpr int v = 65; };
+
 template <typename R>
 struct SolveLds {
-  R X[GS][GP];           // H[G, G]
-  double J[2][PB][LP];   // per-wave rotation accumulation
-  float JA[2][PB][LP];   // step A rotations of the two pairs
-  float JB[2][PB][LP];   // step B rotations
-  R cs[2][2][16];        // per-wave (c, s) of the current round
+  R X[GS][XPitch<R>::v];  // H[G, G]
+  double J[2][PB][LP];    // per-wave rotation accumulation; after a step, its FP32 copy in place
+  RotPair<R> cs[2][16];   // per-wave (c, s) of the current round
 };
 
-// Scalar Jacobi rounds t0 .. 31 (repeated inner_sweeps times) on pair w of
-// the given step; J accumulates the rotations.  One wavefront, no workgroup
-// barrier.
+// FP32 view of wave w's accumulator space (pitch LP)
 template <typename R>
-SVDP_DEV void pair_solve(SolveLds<R>& L, int stepB, int w, int lane, int t0, int inner_sweeps,
-                         R floor_abs, float& mrel) {
-  R (*X)[GP] = L.X;
+SVDP_DEV float (*jf(SolveLds<R>& L, int w))[LP] { return reinterpret_cast<float (*)[LP]>(&L.J[w][0][0]); }
+
+// position in the 64-index group of local index a (0..31) of pair w: step A
+// pairs are contiguous halves, step B pairs interleave 16-blocks
+template <int STEPB>
+SVDP_DEV int gpos(int w, int a) {
+  const int lo = STEPB ? 16 * w : 32 * w, hi = STEPB ? 32 + 16 * w : 32 * w + 16;
+  return a < 16 ? lo + a : hi + (a - 16);
+}
+
+SVDP_DEV void rotation_fast(float app, float aqq, float apq, float& c, float& s) {
+  const float tau = (aqq - app) * __builtin_amdgcn_rcpf(2.f * apq);
+  float t;
+  if (fabsf(tau) > 1e10f) t = 0.5f * __builtin_amdgcn_rcpf(tau);
+  else t = copysignf(__builtin_amdgcn_rcpf(fabsf(tau) + __builtin_amdgcn_sqrtf(1.f + tau * tau)), tau);
+  c = __builtin_amdgcn_rsqf(1.f + t * t);
+  s = t * c;
+}
+SVDP_DEV void rotation_fast(double app, double aqq, double apq, double& c, double& s) {
+  rotation(app, aqq, apq, c, s);
+}
+
+// Scalar Jacobi rounds t0 .. 31 (repeated inner_sweeps times) on pair w of
+// the step; J accumulates the rotations.  One wavefront, no workgroup
+// barrier.  Lane l owns rotation pair kx = l % 16 for its row updates and
+// its accumulator updates (rows l / 16 + 4 u of J), and the 2 x 2 blocks
+// (kx, l / 16 + 4 u) of the subproblem.
+template <typename R, int STEPB>
+SVDP_DEV void pair_solve(SolveLds<R>& L, int w, int lane, int t0, int inner_sweeps, R floor_abs, float& mrel) {
+  constexpr int XP = XPitch<R>::v;
+  R (*X)[XP] = L.X;
   double (*J)[LP] = L.J[w];
-  R* cc = L.cs[w][0];
-  R* ss = L.cs[w][1];
+  RotPair<R>* cs = L.cs[w];
   for (int idx = lane; idx < PB * PB; idx += 64) J[idx >> 5][idx & 31] = (idx >> 5) == (idx & 31) ? 1.0 : 0.0;
   wave_sync();
+  const int kx = lane & 15, q = lane >> 4;
   for (int sw = 0; sw < inner_sweeps; ++sw) {
     int any = 0;
     for (int t = t0; t < PB; ++t) {
+      const int hb = 31 - __builtin_clz(t);
+      auto pair_of = [&](int k, int& x, int& y) {
+        x = t >= 16 ? k : (((k >> 3) << 4) | insert0(k & 7, hb));
+        y = x ^ t;
+      };
+      int x1, y1;
+      pair_of(kx, x1, y1);
+      const int gx1 = gpos<STEPB>(w, x1), gy1 = gpos<STEPB>(w, y1);
       if (lane < 16) {
-        int x, y;
-        inner_pair(t, lane, x, y);
-        const int gx = lmap(stepB, w, x), gy = lmap(stepB, w, y);
-        const R app = X[gx][gx], aqq = X[gy][gy], apq = R(0.5) * (X[gx][gy] + X[gy][gx]);
-        R c = 1, sn = 0;
+        const R app = X[gx1][gx1], aqq = X[gy1][gy1], apq = R(0.5) * (X[gx1][gy1] + X[gy1][gx1]);
+        RotPair<R> r{R(1), R(0)};
         if (apq != R(0) && isfinite((float)apq)) {
-          rotation(app, aqq, apq, c, sn);
+          rotation_fast(app, aqq, apq, r.c, r.s);
           any = 1;
           if (fabs(apq) > floor_abs) {
             const R den = sqrt(fabs(app * aqq));
             mrel = fmaxf(mrel, den > R(0) ? (float)(fabs(apq) / den) : 1e30f);
           }
         }
-        cc[lane] = c;
-        ss[lane] = sn;
+        cs[lane] = r;
       }
       wave_sync();
-      // 16 x 16 blocks of 2 x 2: row pair kx, column pairs ky
-      const int kx = lane & 15;
-      int x1, y1;
-      inner_pair(t, kx, x1, y1);
-      const int gx1 = lmap(stepB, w, x1), gy1 = lmap(stepB, w, y1);
-      const R c1 = cc[kx], s1 = ss[kx];
+      const RotPair<R> r1 = cs[kx];
+      R* rowx = X[gx1];
+      R* rowy = X[gy1];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const int ky = (lane >> 4) + 4 * u;
+        const int ky = q + 4 * u;
         int x2, y2;
-        inner_pair(t, ky, x2, y2);
-        const int gx2 = lmap(stepB, w, x2), gy2 = lmap(stepB, w, y2);
-        const R c2 = cc[ky], s2 = ss[ky];
-        const R a = X[gx1][gx2], bq = X[gx1][gy2], cq = X[gy1][gx2], d = X[gy1][gy2];
-        const R t00 = c1 * a - s1 * cq, t01 = c1 * bq - s1 * d;
-        const R t10 = s1 * a + c1 * cq, t11 = s1 * bq + c1 * d;
-        R y00 = c2 * t00 - s2 * t01, y01 = s2 * t00 + c2 * t01;
-        R y10 = c2 * t10 - s2 * t11, y11 = s2 * t10 + c2 * t11;
-        if (kx == ky && s1 != R(0)) { y01 = 0; y10 = 0; }
-        X[gx1][gx2] = y00; X[gx1][gy2] = y01; X[gy1][gx2] = y10; X[gy1][gy2] = y11;
+        pair_of(ky, x2, y2);
+        const int gx2 = gpos<STEPB>(w, x2), gy2 = gpos<STEPB>(w, y2);
+        const RotPair<R> r2 = cs[ky];
+        const R a = rowx[gx2], bq = rowx[gy2], cq = rowy[gx2], d = rowy[gy2];
+        const R t00 = r1.c * a - r1.s * cq, t01 = r1.c * bq - r1.s * d;
+        const R t10 = r1.s * a + r1.c * cq, t11 = r1.s * bq + r1.c * d;
+        R y00 = r2.c * t00 - r2.s * t01, y01 = r2.s * t00 + r2.c * t01;
+        R y10 = r2.c * t10 - r2.s * t11, y11 = r2.s * t10 + r2.c * t11;
+        if (kx == ky && r1.s != R(0)) { y01 = 0; y10 = 0; }
+        rowx[gx2] = y00; rowx[gy2] = y01; rowy[gx2] = y10; rowy[gy2] = y11;
       }
-      // rotation accumulation J <- J R: 32 rows x 16 pairs, eight per lane
+      // J <- J R on columns (x1, y1), rows q + 4 u
+      const double c = r1.c, sn = r1.s;
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        const int it = lane + 64 * u;
-        const int r = it >> 4, kk = it & 15;
-        int x, y;
-        inner_pair(t, kk, x, y);
-        const double c = cc[kk], sn = ss[kk];
-        const double jx = J[r][x], jy = J[r][y];
-        J[r][x] = c * jx - sn * jy;
-        J[r][y] = sn * jx + c * jy;
+        const int r = q + 4 * u;
+        const double jx = J[r][x1], jy = J[r][y1];
+        J[r][x1] = c * jx - sn * jy;
+        J[r][y1] = sn * jx + c * jy;
       }
       wave_sync();
     }
@@ -183,32 +196,52 @@ SVDP_DEV void pair_solve(SolveLds<R>& L, int stepB, int w, int lane, int t0, int
   }
 }
 
+// wave w's accumulator (FP64) -> its FP32 copy in the same LDS space
+template <typename R>
+SVDP_DEV void acc_to_float(SolveLds<R>& L, int w, int lane) {
+  double v[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int idx = lane + 64 * u;
+    v[u] = L.J[w][idx >> 5][idx & 31];
+  }
+  wave_sync();
+  float (*F)[LP] = jf(L, w);
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int idx = lane + 64 * u;
+    F[idx >> 5][idx & 31] = (float)v[u];
+  }
+  wave_sync();
+}
+
 // The block of H[G, G] between the two pairs of a step, B = X[P0, P1]:
 // B <- J0^T B J1, and its mirror X[P1, P0] = B^T.  One wavefront.
-template <typename R>
-SVDP_DEV void cross_update(SolveLds<R>& L, int stepB, const float (*J0)[LP], const float (*J1)[LP], int lane) {
-  R (*X)[GP] = L.X;
+template <typename R, int STEPB>
+SVDP_DEV void cross_update(SolveLds<R>& L, const float (*J0)[LP], const float (*J1)[LP], int lane) {
+  constexpr int XP = XPitch<R>::v;
+  R (*X)[XP] = L.X;
   const int kh = lane >> 5, ic = lane & 31;
   f16v acc = zero16();
 #pragma unroll 4
   for (int kk = 0; kk < PB; kk += 2)
-    acc = mfma(J0[kk + kh][ic], (float)X[lmap(stepB, 0, kk + kh)][lmap(stepB, 1, ic)], acc);
+    acc = mfma(J0[kk + kh][ic], (float)X[gpos<STEPB>(0, kk + kh)][gpos<STEPB>(1, ic)], acc);
   wave_sync();
 #pragma unroll
   for (int g = 0; g < 4; ++g)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) X[lmap(stepB, 0, 8 * g + 4 * kh + r)][lmap(stepB, 1, ic)] = (R)acc[4 * g + r];
+    for (int r = 0; r < 4; ++r) X[gpos<STEPB>(0, 8 * g + 4 * kh + r)][gpos<STEPB>(1, ic)] = (R)acc[4 * g + r];
   wave_sync();
   acc = zero16();
 #pragma unroll 4
   for (int kk = 0; kk < PB; kk += 2)
-    acc = mfma((float)X[lmap(stepB, 0, ic)][lmap(stepB, 1, kk + kh)], J1[kk + kh][ic], acc);
+    acc = mfma((float)X[gpos<STEPB>(0, ic)][gpos<STEPB>(1, kk + kh)], J1[kk + kh][ic], acc);
   wave_sync();
 #pragma unroll
   for (int g = 0; g < 4; ++g)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int i = lmap(stepB, 0, 8 * g + 4 * kh + r), j = lmap(stepB, 1, ic);
+      const int i = gpos<STEPB>(0, 8 * g + 4 * kh + r), j = gpos<STEPB>(1, ic);
       X[i][j] = (R)acc[4 * g + r];
       X[j][i] = (R)acc[4 * g + r];
     }
@@ -219,6 +252,7 @@ template <typename R>
 __global__ __launch_bounds__(128) void k_jac_solve(EighWs e, EighPhase ph, int inner_sweeps, float abs_tol,
                                                    int* rotmax) {
   __shared__ SolveLds<R> L;
+  constexpr int XP = XPitch<R>::v;
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
   const int ng = e.nb / 4;
   const int b = blockIdx.x / ng, gi = blockIdx.x - b * ng;
@@ -243,42 +277,41 @@ __global__ __launch_bounds__(128) void k_jac_solve(EighWs e, EighPhase ph, int i
   __syncthreads();
   const R floor_abs = (R)abs_tol * (R)sqrtf(e.hnorm2[b]);
   float mrel = 0.f;
+  float* M = e.Qw + ((int64_t)b * ng + gi) * QSTRIDE;
+  float* JAg = M + GS * GS;  // step-A rotations (FP32), read back for M_G
   // step A
-  pair_solve<R>(L, 0, w, lane, ph.fullA ? 1 : 16, inner_sweeps, floor_abs, mrel);
-  for (int idx = lane; idx < PB * PB; idx += 64) L.JA[w][idx >> 5][idx & 31] = (float)L.J[w][idx >> 5][idx & 31];
+  pair_solve<R, 0>(L, w, lane, ph.fullA ? 1 : 16, inner_sweeps, floor_abs, mrel);
+  acc_to_float(L, w, lane);
+  for (int idx = lane; idx < PB * PB; idx += 64) JAg[w * PB * PB + idx] = jf(L, w)[idx >> 5][idx & 31];
   __syncthreads();
-  if (w == 0) cross_update<R>(L, 0, L.JA[0], L.JA[1], lane);
+  if (w == 0) cross_update<R, 0>(L, jf(L, 0), jf(L, 1), lane);
   __syncthreads();
-  // step B
-  if (!ph.skipB) {
-    pair_solve<R>(L, 1, w, lane, 16, inner_sweeps, floor_abs, mrel);
-    for (int idx = lane; idx < PB * PB; idx += 64) L.JB[w][idx >> 5][idx & 31] = (float)L.J[w][idx >> 5][idx & 31];
-    __syncthreads();
-  }
-  // M_G = J_A J_B (64 x 64, local order) to the group's slot; wave 0 also
-  // rotates the cross block of step B
-  float* M = e.Qw + ((int64_t)b * ng + gi) * (GS * GS);
   const int kh = lane >> 5, ic = lane & 31;
   if (ph.skipB) {
+    // M_G = J_A (block diagonal)
     for (int idx = t; idx < GS * GS; idx += 128) {
-      const int p = idx >> 6, q = idx & 63;
-      M[idx] = (p >> 5) == (q >> 5) ? L.JA[p >> 5][p & 31][q & 31] : 0.f;
+      const int p = idx >> 6, qq = idx & 63;
+      M[idx] = (p >> 5) == (qq >> 5) ? jf(L, p >> 5)[p & 31][qq & 31] : 0.f;
     }
   } else {
-    if (w == 0) cross_update<R>(L, 1, L.JB[0], L.JB[1], lane);
-    // block (wa, wb): rows of step-A pair wa, columns of step-B pair wb;
-    // the shared indices are local 32 wa + 16 wb + k, k < 16
+    // step B
+    pair_solve<R, 1>(L, w, lane, 16, inner_sweeps, floor_abs, mrel);
+    acc_to_float(L, w, lane);
+    __syncthreads();
+    if (w == 0) cross_update<R, 1>(L, jf(L, 0), jf(L, 1), lane);
+    // M_G = J_A J_B, block (wa, wb): rows of step-A pair wa, columns of
+    // step-B pair wb; the shared indices are local 32 wa + 16 wb + k, k < 16
     for (int blk = w; blk < 4; blk += 2) {
       const int wa = blk >> 1, wb = blk & 1;
       f16v acc = zero16();
 #pragma unroll
       for (int kk = 0; kk < 16; kk += 2)
-        acc = mfma(L.JA[wa][ic][16 * wb + kk + kh], L.JB[wb][16 * wa + kk + kh][ic], acc);
+        acc = mfma(JAg[wa * PB * PB + ic * PB + 16 * wb + kk + kh], jf(L, wb)[16 * wa + kk + kh][ic], acc);
 #pragma unroll
       for (int gg = 0; gg < 4; ++gg)
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-          M[(32 * wa + 8 * gg + 4 * kh + r) * GS + lmap(1, wb, ic)] = acc[4 * gg + r];
+          M[(32 * wa + 8 * gg + 4 * kh + r) * GS + gpos<1>(wb, ic)] = acc[4 * gg + r];
     }
   }
   __syncthreads();
@@ -298,22 +331,27 @@ __global__ __launch_bounds__(128) void k_jac_solve(EighWs e, EighPhase ph, int i
   if (lane == 0 && rotmax) atomicMax(rotmax + b, __float_as_int(mrel));
 }
 
-// 64 x 64 quadrant product helpers on one wavefront (32 x 32 output block
-// (qi, qj)); LDS arrays have pitch GP.
-// acc = sum_k A^T[32 qi + i][k] B[k][32 qj + j]   (A read transposed)
-SVDP_DEV f16v mm_tn(const float (*A)[GP], const float (*B)[GP], int qi, int qj, int lane) {
+// 64 x 64 quadrant products on one wavefront (32 x 32 output block (qi, qj)),
+// K = 64 in 32 MFMA steps; step s contracts index 2 s + (lane / 32).
+// MFMA operand layout (32x32x2 f32): lane l supplies A[l % 32][k] and
+// B[k][l % 32]; the accumulator's slot 4 g + r is row 8 g + 4 (l / 32) + r,
+// column l % 32.
+// acc[i][j] = sum_k a_k[i] B[k][32 qj + j]: the left factor's operands in
+// registers (a[s] for k = 2 s + lane / 32), the right factor from LDS
+SVDP_DEV f16v mm_rl(const float (&a)[32], const float (*B)[GP], int qj, int lane) {
   const int kh = lane >> 5, ic = lane & 31;
   f16v acc = zero16();
-#pragma unroll 8
-  for (int kk = 0; kk < GS; kk += 2) acc = mfma(A[kk + kh][32 * qi + ic], B[kk + kh][32 * qj + ic], acc);
+#pragma unroll
+  for (int s2 = 0; s2 < 32; ++s2) acc = mfma(a[s2], B[2 * s2 + kh][32 * qj + ic], acc);
   return acc;
 }
-// acc = sum_k A[32 qi + i][k] B[k][32 qj + j]
-SVDP_DEV f16v mm_nn(const float (*A)[GP], const float (*B)[GP], int qi, int qj, int lane) {
+// acc[i][j] = sum_k A[32 qi + i][k] b_k[j]: the left factor from LDS, the
+// right factor's operands in registers
+SVDP_DEV f16v mm_lr(const float (*A)[GP], const float (&b)[32], int qi, int lane) {
   const int kh = lane >> 5, ic = lane & 31;
   f16v acc = zero16();
-#pragma unroll 8
-  for (int kk = 0; kk < GS; kk += 2) acc = mfma(A[32 * qi + ic][kk + kh], B[kk + kh][32 * qj + ic], acc);
+#pragma unroll
+  for (int s2 = 0; s2 < 32; ++s2) acc = mfma(A[32 * qi + ic][2 * s2 + kh], b[s2], acc);
   return acc;
 }
 SVDP_DEV void put_quadrant(float (*X)[GP], const f16v& acc, int qi, int qj, int lane) {
@@ -323,11 +361,19 @@ SVDP_DEV void put_quadrant(float (*X)[GP], const f16v& acc, int qi, int qj, int 
 #pragma unroll
     for (int r = 0; r < 4; ++r) X[32 * qi + 8 * g + 4 * kh + r][32 * qj + ic] = acc[4 * g + r];
 }
+// column c0 + (lane % 32) of rows 2 s + (lane / 32) of a 64 x 64 row-major M
+SVDP_DEV void load_mcol(const float* M, int c0, int lane, float (&v)[32]) {
+  const int kh = lane >> 5, ic = lane & 31;
+#pragma unroll
+  for (int s2 = 0; s2 < 32; ++s2) v[s2] = M[(2 * s2 + kh) * GS + c0 + ic];
+}
 
+// One workgroup (four wavefronts, wave w owns output quadrant (w / 2, w % 2))
+// per task.  The 64 x 64 data block goes through LDS; the group rotations
+// (small, shared by many tasks of the matrix, L2-resident) are read straight
+// into MFMA operand registers.
 __global__ __launch_bounds__(256) void k_jac_apply(EighWs e, EighPhase ph) {
   __shared__ float Xs[GS][GP];
-  __shared__ float M1[GS][GP];
-  __shared__ float M2[GS][GP];
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
   const int ng = e.nb / 4;
   const int nH = ng * (ng - 1) / 2;
@@ -339,7 +385,7 @@ __global__ __launch_bounds__(256) void k_jac_apply(EighWs e, EighPhase ph) {
   if (b >= e.batch) return;
   if (e.active && !e.active[b]) return;
   const int qi = w >> 1, qj = w & 1;
-  const float* Qb = e.Qw + (int64_t)b * ng * (GS * GS);
+  const float* Qb = e.Qw + (int64_t)b * ng * QSTRIDE;
   if (task < nH) {
     int tt = task, G1 = 0;
     while (tt >= ng - 1 - G1) { tt -= ng - 1 - G1; ++G1; }
@@ -348,6 +394,10 @@ __global__ __launch_bounds__(256) void k_jac_apply(EighWs e, EighPhase ph) {
     group_members(ph, G1, g1);
     group_members(ph, G2, g2);
     float* H = e.Hw + (int64_t)b * e.np * e.np;
+    // T = M1^T X needs M1[k][32 qi + i]; Y = T M2 needs M2[k][32 qj + j]
+    float a1[32], b2[32];
+    load_mcol(Qb + (int64_t)G1 * QSTRIDE, 32 * qi, lane, a1);
+    load_mcol(Qb + (int64_t)G2 * QSTRIDE, 32 * qj, lane, b2);
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int idx = t + 256 * u;
@@ -361,18 +411,13 @@ __global__ __launch_bounds__(256) void k_jac_apply(EighWs e, EighPhase ph) {
         if (tr) Xs[k1 * 16 + c + w2][k2 * 16 + r] = v[w2];
         else Xs[k1 * 16 + r][k2 * 16 + c + w2] = v[w2];
       }
-      const int row = idx >> 4, col = (idx & 15) * 4;
-      const f4v m1 = *(const f4v*)(Qb + (int64_t)G1 * (GS * GS) + row * GS + col);
-      const f4v m2 = *(const f4v*)(Qb + (int64_t)G2 * (GS * GS) + row * GS + col);
-#pragma unroll
-      for (int w2 = 0; w2 < 4; ++w2) { M1[row][col + w2] = m1[w2]; M2[row][col + w2] = m2[w2]; }
     }
     __syncthreads();
-    const f16v T = mm_tn(M1, Xs, qi, qj, lane);  // M1^T X
+    const f16v T = mm_rl(a1, Xs, qj, lane);  // M1^T X
     __syncthreads();
     put_quadrant(Xs, T, qi, qj, lane);
     __syncthreads();
-    const f16v Y = mm_nn(Xs, M2, qi, qj, lane);  // (M1^T X) M2
+    const f16v Y = mm_lr(Xs, b2, qi, lane);  // (M1^T X) M2
     __syncthreads();
     put_quadrant(Xs, Y, qi, qj, lane);
     __syncthreads();
@@ -393,6 +438,8 @@ __global__ __launch_bounds__(256) void k_jac_apply(EighWs e, EighPhase ph) {
     int gm[4];
     group_members(ph, G, gm);
     float* V = e.Vw + (int64_t)b * e.np * e.np;
+    float bm[32];
+    load_mcol(Qb + (int64_t)G * QSTRIDE, 32 * qj, lane, bm);
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int idx = t + 256 * u;
@@ -401,13 +448,9 @@ __global__ __launch_bounds__(256) void k_jac_apply(EighWs e, EighPhase ph) {
       const int r = qd >> 2, c = (qd & 3) * 4;
 #pragma unroll
       for (int w2 = 0; w2 < 4; ++w2) Xs[k1 * 16 + r][k2 * 16 + c + w2] = x[w2];
-      const int row = idx >> 4, col = (idx & 15) * 4;
-      const f4v m = *(const f4v*)(Qb + (int64_t)G * (GS * GS) + row * GS + col);
-#pragma unroll
-      for (int w2 = 0; w2 < 4; ++w2) M1[row][col + w2] = m[w2];
     }
     __syncthreads();
-    const f16v Y = mm_nn(Xs, M1, qi, qj, lane);
+    const f16v Y = mm_lr(Xs, bm, qi, lane);  // X M
     __syncthreads();
     put_quadrant(Xs, Y, qi, qj, lane);
     __syncthreads();
@@ -425,23 +468,54 @@ __global__ __launch_bounds__(256) void k_jac_apply(EighWs e, EighPhase ph) {
 }
 
 // Tiled working copies: H (tiles on and above the diagonal, symmetrised,
-// zero padding), V = I, |H|_F^2.  One tile per workgroup.
-__global__ void k_eigh_setup(EighWs e, const float* Hin, int64_t ldh, int64_t sH, const int* mask) {
+// zero padding), V = I, |H|_F^2.  One 64 x 64 block (Ib, Jb) of tiles per
+// workgroup: the block and its mirror are read row-contiguous into LDS.
+__global__ __launch_bounds__(256) void k_eigh_setup(EighWs e, const float* Hin, int64_t ldh, int64_t sH,
+                                                    const int* mask) {
   const int b = blockIdx.y;
   if (mask && !mask[b]) return;
-  const int I = blockIdx.x / e.nb, Jb = blockIdx.x - I * e.nb;
-  const int r = threadIdx.x >> 4, c = threadIdx.x & 15;
-  const int i = I * BS + r, j = Jb * BS + c;
-  const int64_t base = (int64_t)b * e.np * e.np + tile_off(I, Jb, e.nb) + r * BS + c;
-  e.Vw[base] = i == j ? 1.f : 0.f;
-  if (I > Jb) return;  // whole workgroup
+  __shared__ float Ablk[GS][GP];
+  __shared__ float Tblk[GS][GP];
+  const int nq = e.nb / 4;
+  const int Ib = blockIdx.x / nq, Jb = blockIdx.x - Ib * nq;
+  const int t = threadIdx.x;
+  float* Vb = e.Vw + (int64_t)b * e.np * e.np;
+  for (int idx = t; idx < 16 * 64; idx += 256) {
+    const int tile = idx >> 6, qd = idx & 63, I = 4 * Ib + (tile >> 2), J = 4 * Jb + (tile & 3);
+    const int r = qd >> 2, c = (qd & 3) * 4;
+    f4v v;
+#pragma unroll
+    for (int w2 = 0; w2 < 4; ++w2) v[w2] = (I == J && r == c + w2) ? 1.f : 0.f;
+    *(f4v*)(Vb + tile_off(I, J, e.nb) + qd * 4) = v;
+  }
+  if (Ib > Jb) return;  // whole workgroup: H keeps the upper tiles only
   const float* Hb = Hin + b * sH;
-  float v = 0.f;
-  if (i < e.n && j < e.n) v = 0.5f * (Hb[(int64_t)i * ldh + j] + Hb[(int64_t)j * ldh + i]);
-  e.Hw[base] = v;
-  float acc = v * v * (I == Jb ? 1.f : 2.f);
+  for (int idx = t; idx < GS * GS; idx += 256) {
+    const int r = idx >> 6, c = idx & 63;
+    const int i = GS * Ib + r, j = GS * Jb + c;
+    Ablk[r][c] = (i < e.n && j < e.n) ? Hb[(int64_t)i * ldh + j] : 0.f;
+    const int i2 = GS * Jb + r, j2 = GS * Ib + c;
+    Tblk[r][c] = (i2 < e.n && j2 < e.n) ? Hb[(int64_t)i2 * ldh + j2] : 0.f;
+  }
+  __syncthreads();
+  float* Hw = e.Hw + (int64_t)b * e.np * e.np;
+  float acc = 0.f;
+  for (int idx = t; idx < 16 * 64; idx += 256) {
+    const int tile = idx >> 6, qd = idx & 63, k1 = tile >> 2, k2 = tile & 3;
+    const int I = 4 * Ib + k1, J = 4 * Jb + k2;
+    if (I > J) continue;  // below the diagonal of a diagonal block
+    const int r = qd >> 2, c = (qd & 3) * 4;
+    f4v v;
+#pragma unroll
+    for (int w2 = 0; w2 < 4; ++w2) {
+      const int rr = 16 * k1 + r, cc = 16 * k2 + c + w2;
+      v[w2] = 0.5f * (Ablk[rr][cc] + Tblk[cc][rr]);
+      acc += v[w2] * v[w2] * (I == J ? 1.f : 2.f);
+    }
+    *(f4v*)(Hw + tile_off(I, J, e.nb) + qd * 4) = v;
+  }
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-  if ((threadIdx.x & 63) == 0) atomicAdd(e.hnorm2 + b, acc);
+  if ((t & 63) == 0) atomicAdd(e.hnorm2 + b, acc);
 }
 
 // row-major copy of a tiled np x np matrix (one float4 per thread)
@@ -613,7 +687,7 @@ size_t eigh_ws_bytes(int64_t batch, int64_t n, int max_sweeps) {
   size_t f = 0;
   f += 3 * batch * np * np;          // Hw, Vw, V2
   f += batch * n;                    // lamr
-  f += batch * ng * GS * GS;         // Qw
+  f += batch * ng * QSTRIDE;         // Qw
   f += batch;                        // hnorm2
   f += 2 * batch * n;                // sign, (perm as int)
   size_t i = batch * (size_t)(max_sweeps + 2) + batch + 16;  // rotcnt, active, counters
@@ -633,7 +707,7 @@ EighWs eigh_ws_carve(void* ws, int64_t batch, int64_t n, int max_sweeps) {
   e.Vw = (float*)take(batch * np * np * 4);
   e.V2 = (float*)take(batch * np * np * 4);
   e.lamr = (float*)take(batch * n * 4);
-  e.Qw = (float*)take(batch * ng * GS * GS * 4);
+  e.Qw = (float*)take(batch * ng * QSTRIDE * 4);
   e.hnorm2 = (float*)take(batch * 4);
   e.sgn = (float*)take(batch * n * 4);
   e.perm = (int*)take(batch * n * 4);
@@ -668,25 +742,42 @@ std::vector<EighPhase> eigh_phases(int nb) {
   return out;
 }
 
+// View of matrices [b0, b0 + cnt) of a workspace; half h uses its own
+// device counter.
+static EighWs eigh_sub(const EighWs& e, int b0, int cnt, int h) {
+  EighWs s = e;
+  const int64_t m2 = (int64_t)e.np * e.np, ng = e.nb / 4;
+  s.batch = cnt;
+  s.Hw += b0 * m2;
+  s.Vw += b0 * m2;
+  s.V2 += b0 * m2;
+  s.lamr += (int64_t)b0 * e.n;
+  s.Qw += b0 * ng * QSTRIDE;
+  s.hnorm2 += b0;
+  s.sgn += (int64_t)b0 * e.n;
+  s.perm += (int64_t)b0 * e.n;
+  s.active += b0;
+  s.counter += 8 * h;
+  return s;
+}
+
 // Full eigendecomposition of a batch of symmetric n x n matrices.
 hipError_t eigh_run(EighWs e, const float* H, int64_t ldh, int64_t sH, int mode,
                     const EighOpts& o, float* lam, int64_t slam, float* Vout, int64_t ldv,
                     int64_t sV, int* sweeps_out, int* flags, int* host_counter, const int* mask,
-                    hipStream_t st) {
+                    const EighAux* aux, hipStream_t st) {
   hipError_t err;
   const int batch = e.batch;
   if ((err = fill_f32(e.hnorm2, 0.f, batch, st))) return err;
   if ((err = fill_i32(e.rotcnt, 0, (int64_t)batch * (e.max_sweeps + 2), st))) return err;
   if (mask) { if ((err = copy_i32(e.active, mask, batch, st))) return err; }
   else if ((err = fill_i32(e.active, 1, batch, st))) return err;
-  hipLaunchKernelGGL(k_eigh_setup, dim3(e.nb * e.nb, batch), dim3(256), 0, st, e, H, ldh, sH, mask);
+  hipLaunchKernelGGL(k_eigh_setup, dim3((e.nb / 4) * (e.nb / 4), batch), dim3(256), 0, st, e, H, ldh, sH, mask);
   if ((err = hipGetLastError())) return err;
   const int ng = e.nb / 4;
   const int nH = ng * (ng - 1) / 2;
   const int ntask = nH + ng * ng;
   const std::vector<EighPhase> phases = eigh_phases(e.nb);
-  const unsigned solve_blocks = (unsigned)(batch * ng);
-  const unsigned apply_blocks = (unsigned)((int64_t)cdiv(batch, 8) * 8 * ntask);
   // algorithmic flops per matrix: a pair round updates 256 2 x 2 blocks
   // (24 flops each) and 512 rotation-accumulator pairs (6 each); the apply
   // does two 64^3 products per pair of groups and one per slab of V
@@ -696,54 +787,101 @@ hipError_t eigh_run(EighWs e, const float* H, int64_t ldh, int64_t sH, int mode,
     const int rounds = (ph.fullA ? 31 : 16) + (ph.skipB ? 0 : 16);
     return (double)ng * 2.0 * rounds * round_work * reps;
   };
-  int n_active = batch;
+  // Two halves of the batch on two streams (when a second stream is given):
+  // the LDS/VALU-bound pair solves of one half run beside the MFMA/HBM-bound
+  // rotations of the other.
+  const int halves = (aux && batch >= 2) ? 2 : 1;
+  int b0[2] = {0, batch / 2}, bc[2] = {batch / 2, batch - batch / 2};
+  if (halves == 1) bc[0] = batch;
+  hipStream_t ss[2] = {st, halves == 2 ? aux->st2 : st};
+  EighWs eh[2];
+  for (int h = 0; h < halves; ++h) eh[h] = eigh_sub(e, b0[h], bc[h], h);
+  if (halves == 2) {
+    if ((err = hipEventRecord(aux->fork, st))) return err;
+    if ((err = hipStreamWaitEvent(aux->st2, aux->fork, 0))) return err;
+  }
+  auto phase_launches = [&](int h, const EighPhase& ph, bool fp64, int* rc, int n_act,
+                            bool mark_skew = false) -> hipError_t {
+    const EighWs& E = eh[h];
+    const unsigned sblocks = (unsigned)(E.batch * ng);
+    const unsigned ablocks = (unsigned)((int64_t)cdiv(E.batch, 8) * 8 * ntask);
+    if (fp64) {
+      ProfScope ps(PROF_JAC_SOLVE_F64, ss[h], solve_work(ph, o.fp64_inner) * n_act);
+      hipLaunchKernelGGL(k_jac_solve<double>, dim3(sblocks), dim3(128), 0, ss[h], E, ph, o.fp64_inner, o.abs_tol,
+                         (int*)nullptr);
+    } else {
+      ProfScope ps(PROF_JAC_SOLVE_F32, ss[h], solve_work(ph, o.inner_sweeps) * n_act);
+      hipLaunchKernelGGL(k_jac_solve<float>, dim3(sblocks), dim3(128), 0, ss[h], E, ph, o.inner_sweeps, o.abs_tol,
+                         rc);
+    }
+    hipError_t e2 = hipGetLastError();
+    if (e2) return e2;
+    if (mark_skew && (e2 = hipEventRecord(aux->skew, ss[h]))) return e2;
+    {
+      ProfScope ps(PROF_JAC_APPLY, ss[h], apply_work * n_act);
+      hipLaunchKernelGGL(k_jac_apply, dim3(ablocks), dim3(256), 0, ss[h], E, ph);
+    }
+    return hipGetLastError();
+  };
+  int n_act[2] = {bc[0], bc[1]};
   int sweep = 0;
   for (; sweep < e.max_sweeps; ++sweep) {
     int* rc = e.rotcnt + (int64_t)batch * sweep;
+    bool first = true;
     for (const EighPhase& ph : phases) {
-      {
-        ProfScope ps(PROF_JAC_SOLVE_F32, st, solve_work(ph, o.inner_sweeps) * n_active);
-        hipLaunchKernelGGL(k_jac_solve<float>, dim3(solve_blocks), dim3(128), 0, st, e, ph, o.inner_sweeps,
-                           o.abs_tol, rc);
+      for (int h = 0; h < halves; ++h) {
+        if (n_act[h] == 0) continue;
+        // the second half waits for the first half's first pair solve of the
+        // sweep, so that the two streams alternate solve and rotation
+        if (h == 1 && first && n_act[0] > 0 && (err = hipStreamWaitEvent(ss[1], aux->skew, 0))) return err;
+        if ((err = phase_launches(h, ph, false, rc + b0[h], n_act[h], h == 0 && first && halves == 2))) return err;
       }
-      if ((err = hipGetLastError())) return err;
-      {
-        ProfScope ps(PROF_JAC_APPLY, st, apply_work * n_active);
-        hipLaunchKernelGGL(k_jac_apply, dim3(apply_blocks), dim3(256), 0, st, e, ph);
-      }
-      if ((err = hipGetLastError())) return err;
+      first = false;
     }
-    hipLaunchKernelGGL(k_eigh_check, dim3(1), dim3(1024), 0, st, e, rc, o.tol, sweep, sweeps_out, e.counter);
-    if ((err = hipGetLastError())) return err;
-    if ((err = hipMemcpyAsync(host_counter, e.counter, sizeof(int), hipMemcpyDeviceToHost, st))) return err;
-    if ((err = hipStreamSynchronize(st))) return err;
-    n_active = *host_counter;
-    if (n_active == 0) break;
+    for (int h = 0; h < halves; ++h) {
+      if (n_act[h] == 0) continue;
+      hipLaunchKernelGGL(k_eigh_check, dim3(1), dim3(1024), 0, ss[h], eh[h], rc + b0[h], o.tol, sweep,
+                         sweeps_out + b0[h], eh[h].counter);
+      if ((err = hipGetLastError())) return err;
+      if ((err = hipMemcpyAsync(host_counter + h, eh[h].counter, sizeof(int), hipMemcpyDeviceToHost, ss[h])))
+        return err;
+    }
+    int total = 0;
+    for (int h = 0; h < halves; ++h) {
+      if (n_act[h] == 0) continue;
+      if ((err = hipStreamSynchronize(ss[h]))) return err;
+      n_act[h] = host_counter[h];
+      total += n_act[h];
+    }
+    if (total == 0) break;
   }
   // matrices still active after max_sweeps did not converge
-  if (sweep == e.max_sweeps) {
-    hipLaunchKernelGGL(k_flag_active, dim3(cdiv(batch, 256)), dim3(256), 0, st, e.active, batch, flags,
-                       (int)SVDP_FLAG_EIGH_NOT_CONVERGED);
-    if ((err = hipGetLastError())) return err;
-  }
+  if (sweep == e.max_sweeps)
+    for (int h = 0; h < halves; ++h) {
+      hipLaunchKernelGGL(k_flag_active, dim3(cdiv(bc[h], 256)), dim3(256), 0, ss[h], eh[h].active, bc[h],
+                         flags + b0[h], (int)SVDP_FLAG_EIGH_NOT_CONVERGED);
+      if ((err = hipGetLastError())) return err;
+    }
   // final sweep(s) with FP64 pair solves on every matrix
   if (o.fp64_sweeps > 0) {
-    if (mask) { if ((err = copy_i32(e.active, mask, batch, st))) return err; }
-    else if ((err = fill_i32(e.active, 1, batch, st))) return err;
-    for (int f = 0; f < o.fp64_sweeps; ++f)
+    for (int h = 0; h < halves; ++h) {
+      if (mask) { if ((err = copy_i32(eh[h].active, mask + b0[h], bc[h], ss[h]))) return err; }
+      else if ((err = fill_i32(eh[h].active, 1, bc[h], ss[h]))) return err;
+    }
+    for (int f = 0; f < o.fp64_sweeps; ++f) {
+      bool first = true;
       for (const EighPhase& ph : phases) {
-        {
-          ProfScope ps(PROF_JAC_SOLVE_F64, st, solve_work(ph, o.fp64_inner) * batch);
-          hipLaunchKernelGGL(k_jac_solve<double>, dim3(solve_blocks), dim3(128), 0, st, e, ph, o.fp64_inner,
-                             o.abs_tol, (int*)nullptr);
+        for (int h = 0; h < halves; ++h) {
+          if (h == 1 && first && (err = hipStreamWaitEvent(ss[1], aux->skew, 0))) return err;
+          if ((err = phase_launches(h, ph, true, nullptr, bc[h], h == 0 && first && halves == 2))) return err;
         }
-        if ((err = hipGetLastError())) return err;
-        {
-          ProfScope ps(PROF_JAC_APPLY, st, apply_work * batch);
-          hipLaunchKernelGGL(k_jac_apply, dim3(apply_blocks), dim3(256), 0, st, e, ph);
-        }
-        if ((err = hipGetLastError())) return err;
+        first = false;
       }
+    }
+  }
+  if (halves == 2) {
+    if ((err = hipEventRecord(aux->join, aux->st2))) return err;
+    if ((err = hipStreamWaitEvent(st, aux->join, 0))) return err;
   }
   // V (tiled) -> row-major in Hw; one Newton-Schulz step re-orthonormalises
   // it, V2 = V (3 I - V^T V) / 2 (V^T V in Vw); the eigenvalues are the

@@ -9,7 +9,7 @@ struct EighWs {
   float* Vw;      // batch x np x np: accumulated rotations as 16 x 16 tiles
   float* V2;      // batch x np x np re-orthonormalised eigenvectors (row-major)
   float* lamr;    // batch x n Rayleigh-quotient eigenvalues
-  float* Qw;      // batch x (nb/4) x 64 x 64 group rotations of the current phase
+  float* Qw;      // batch x (nb/4) x (64 x 64 group rotation + 2 x 32 x 32 step-A rotations)
   float* hnorm2;  // batch: |H|_F^2
   float* sgn;     // batch x n: sign of each sorted eigenvalue
   int* perm;      // batch x n: sorted position -> working column
@@ -39,13 +39,22 @@ struct EighOpts {
   float neg_tol;     // NEG_EIGENVALUE when lam_min < -neg_tol max|lam| (mode 1)
 };
 
+// A second stream and three events: the sweeps run the two halves of the
+// batch on the caller's stream and on st2, the second half starting one
+// pair solve later, so that the pair solves of one half overlap the block
+// rotations of the other.
+struct EighAux {
+  hipStream_t st2;
+  hipEvent_t fork, join, skew;
+};
+
 int eigh_blocks(int64_t n);
 size_t eigh_ws_bytes(int64_t batch, int64_t n, int max_sweeps);
 EighWs eigh_ws_carve(void* ws, int64_t batch, int64_t n, int max_sweeps);
 hipError_t eigh_run(EighWs e, const float* H, int64_t ldh, int64_t sH, int mode,
                     const EighOpts& o, float* lam, int64_t slam, float* Vout, int64_t ldv,
                     int64_t sV, int* sweeps_out, int* flags, int* host_counter, const int* mask,
-                    hipStream_t st);
+                    const EighAux* aux, hipStream_t st);
 hipError_t copy_i32(int* dst, const int* src, int64_t n, hipStream_t st);
 hipError_t fill_i32(int* p, int v, int64_t n, hipStream_t st);
 hipError_t fill_f32(float* p, float v, int64_t n, hipStream_t st);

@@ -125,6 +125,7 @@ __global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs g, int tiles_m, int t
   int b, tile;
   if (!map_block(ntiles, g.batch, remap, b, tile)) return;
   if (g.active && !g.active[b]) return;
+  if (g.ksched && sched_cat(g.ksched, b, g.kstep, g.kbf16) != g.kcat) return;
   int tm, tn;
   if (g.sym) sym_tile(tile, tiles_m, tm, tn);
   else { tm = tile / tiles_n; tn = tile - tm * tiles_n; }
@@ -261,6 +262,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g, int tiles_m, int 
   int b, tile;
   if (!map_block(ntiles, g.batch, remap, b, tile)) return;
   if (g.active && !g.active[b]) return;
+  if (g.ksched && sched_cat(g.ksched, b, g.kstep, g.kbf16) != g.kcat) return;
   int tm, tn;
   if (g.sym) sym_tile(tile, tiles_m, tm, tn);
   else { tm = tile / tiles_n; tn = tile - tm * tiles_n; }

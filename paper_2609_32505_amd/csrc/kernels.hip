@@ -864,31 +864,64 @@ hipError_t count_mask_launch(int batch, const int* mask, int* counter, hipStream
 }
 
 namespace {
-// hist[K] = matrices whose schedule has K steps; k1[K] = their largest FP32
-// step count (K1); both arrays have kcap + 1 entries, cleared here first.
-__global__ void k_step_hist(int batch, const int* ksteps, int kcap, int* hist, int* k1) {
-  __shared__ int h[65], m1[65];
-  for (int i = threadIdx.x; i <= kcap; i += blockDim.x) { h[i] = 0; m1[i] = 0; }
+// counts[4 k + c] = matrices whose step k has category c (sched_cat), for
+// k < kcap; counts[4 kcap] = matrices starting in BF16 (K1 = 0);
+// counts[4 kcap + 1] = the largest step count.
+__global__ void k_sched_counts(int batch, const int* ksteps, int kcap, int bf16, int* counts) {
+  __shared__ int h[4 * 64 + 2];
+  for (int i = threadIdx.x; i < 4 * kcap + 2; i += blockDim.x) h[i] = 0;
   __syncthreads();
   for (int b = threadIdx.x; b < batch; b += blockDim.x) {
-    int K = min(max(ksteps[2 * b], 0), kcap);
-    atomicAdd(&h[K], 1);
-    atomicMax(&m1[K], ksteps[2 * b + 1]);
+    const int K = min(max(ksteps[2 * b], 1), kcap);
+    for (int k = 0; k < K; ++k) atomicAdd(&h[4 * k + sched_cat(ksteps, b, k, bf16)], 1);
+    if (sched_cat(ksteps, b, 0, bf16) >= 2) atomicAdd(&h[4 * kcap], 1);
+    atomicMax(&h[4 * kcap + 1], K);
   }
   __syncthreads();
-  for (int i = threadIdx.x; i <= kcap; i += blockDim.x) { hist[i] = h[i]; k1[i] = m1[i]; }
+  for (int i = threadIdx.x; i < 4 * kcap + 2; i += blockDim.x) counts[i] = h[i];
 }
-__global__ void k_group_mask(int batch, const int* ksteps, int K, int* mask) {
-  int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b < batch) mask[b] = ksteps[2 * b] == K;
+// what = 0: the schedule starts in FP32; 1: it starts in BF16; 2: the last
+// iterate is in the odd buffer (K odd)
+__global__ void k_sched_mask(int batch, const int* ksteps, int bf16, int what, int* mask) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= batch) return;
+  const int start_bf = sched_cat(ksteps, b, 0, bf16) >= 2;
+  const int K = max(ksteps[2 * b], 1);
+  mask[b] = what == 0 ? !start_bf : what == 1 ? start_bf : (K & 1);
+}
+__global__ void k_sched_iters(int batch, const int* ksteps, int* iters) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < batch) iters[b] = max(ksteps[2 * b], 1);
+}
+// dst[b] = src[b] (per_matrix floats, a multiple of 4) for the masked matrices
+__global__ void k_copy_masked(const float* src, float* dst, int64_t per_matrix, const int* mask) {
+  const int b = blockIdx.y;
+  if (!mask[b]) return;
+  const f4v* s4 = (const f4v*)(src + b * per_matrix);
+  f4v* d4 = (f4v*)(dst + b * per_matrix);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < per_matrix / 4;
+       i += (int64_t)gridDim.x * blockDim.x)
+    d4[i] = s4[i];
 }
 }  // namespace
 
-hipError_t step_hist_launch(int batch, const int* ksteps, int kcap, int* hist, int* k1, hipStream_t st) {
-  hipLaunchKernelGGL(k_step_hist, dim3(1), dim3(1024), 0, st, batch, ksteps, kcap, hist, k1);
+hipError_t sched_counts_launch(int batch, const int* ksteps, int kcap, int bf16, int* counts, hipStream_t st) {
+  if (kcap > 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_sched_counts, dim3(1), dim3(1024), 0, st, batch, ksteps, kcap, bf16, counts);
   LAUNCH_CHECK();
 }
-hipError_t group_mask_launch(int batch, const int* ksteps, int K, int* mask, hipStream_t st) {
-  hipLaunchKernelGGL(k_group_mask, dim3(cdiv(batch, 256)), dim3(256), 0, st, batch, ksteps, K, mask);
+hipError_t sched_mask_launch(int batch, const int* ksteps, int bf16, int what, int* mask, hipStream_t st) {
+  hipLaunchKernelGGL(k_sched_mask, dim3(cdiv(batch, 256)), dim3(256), 0, st, batch, ksteps, bf16, what, mask);
+  LAUNCH_CHECK();
+}
+hipError_t sched_iters_launch(int batch, const int* ksteps, int* iters, hipStream_t st) {
+  hipLaunchKernelGGL(k_sched_iters, dim3(cdiv(batch, 256)), dim3(256), 0, st, batch, ksteps, iters);
+  LAUNCH_CHECK();
+}
+hipError_t copy_masked_launch(const float* src, float* dst, int batch, int64_t per_matrix, const int* mask,
+                              hipStream_t st) {
+  if (per_matrix % 4) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_copy_masked, dim3(grid1(per_matrix / 4, 256), batch), dim3(256), 0, st, src, dst,
+                     per_matrix, mask);
   LAUNCH_CHECK();
 }

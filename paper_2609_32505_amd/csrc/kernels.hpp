@@ -100,7 +100,15 @@ hipError_t or_flags_launch(int batch, int* flags, int bits, const int* mask, hip
 hipError_t fill_masked_launch(int* p, int v, int n, const int* mask, hipStream_t st);
 // *counter = number of nonzero mask entries
 hipError_t count_mask_launch(int batch, const int* mask, int* counter, hipStream_t st);
-// hist[K] = number of matrices with K steps, k1[K] = their largest K1 (kcap <= 64)
-hipError_t step_hist_launch(int batch, const int* ksteps, int kcap, int* hist, int* k1, hipStream_t st);
-// mask[b] = (K of matrix b == K)
-hipError_t group_mask_launch(int batch, const int* ksteps, int K, int* mask, hipStream_t st);
+// Bounded CANS schedule from the per-matrix step counts ksteps = (K, K1):
+// counts[4 k + c] = matrices whose step k has category c (sched_cat, k <
+// kcap <= 64), counts[4 kcap] = matrices starting in BF16, counts[4 kcap +
+// 1] = the largest K.
+hipError_t sched_counts_launch(int batch, const int* ksteps, int kcap, int bf16, int* counts, hipStream_t st);
+// mask[b] = schedule starts in FP32 (what 0), in BF16 (1), or K is odd (2)
+hipError_t sched_mask_launch(int batch, const int* ksteps, int bf16, int what, int* mask, hipStream_t st);
+// iters[b] = K
+hipError_t sched_iters_launch(int batch, const int* ksteps, int* iters, hipStream_t st);
+// dst[b] = src[b] (per_matrix floats, a multiple of 4) where mask[b] != 0
+hipError_t copy_masked_launch(const float* src, float* dst, int batch, int64_t per_matrix, const int* mask,
+                              hipStream_t st);
