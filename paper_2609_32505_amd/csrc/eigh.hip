@@ -92,17 +92,6 @@ template <typename R> struct RotPair { R c, s; };
 template <typename R> struct XPitch { static constexpr int v = 66; };  // FP32: row stride 2 mod 32 banks
 template <> struct XPitch<double> { static constexpr int v = 65; };
 
-template <typename R>
-struct SolveLds {
-  R X[GS][XPitch<R>::v];  // H[G, G]
-  double J[2][PB][LP];    // per-wave rotation accumulation; after a step, its FP32 copy in place
-  RotPair<R> cs[2][16];   // per-wave (c, s) of the current round
-};
-
-// FP32 view of wave w's accumulator space (pitch LP)
-template <typename R>
-SVDP_DEV float (*jf(SolveLds<R>& L, int w))[LP] { return reinterpret_cast<float (*)[LP]>(&L.J[w][0][0]); }
-
 // position in the 64-index group of local index a (0..31) of pair w: step A
 // pairs are contiguous halves, step B pairs interleave 16-blocks
 template <int STEPB>
@@ -123,20 +112,49 @@ SVDP_DEV void rotation_fast(double app, double aqq, double apq, double& c, doubl
   rotation(app, aqq, apq, c, s);
 }
 
+template <typename R>
+struct SolveLds {
+  R X[GS][XPitch<R>::v];    // H[G, G]
+  float Jf[2][PB][LP];      // per-wave FP32 copy of the step's rotations
+  RotPair<R> cs[2][16];     // per-wave (c, s) of the current round
+};
+
+// remove bit p of x
+SVDP_DEV int compress(int x, int p) { return ((x >> (p + 1)) << p) | (x & ((1 << p) - 1)); }
+
+template <typename T>
+SVDP_DEV T lane_xor(T v, int lane, int m);
+template <>
+SVDP_DEV float lane_xor<float>(float v, int lane, int m) {
+  return __int_as_float(__builtin_amdgcn_ds_bpermute((lane ^ m) << 2, __float_as_int(v)));
+}
+template <>
+SVDP_DEV double lane_xor<double>(double v, int lane, int m) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  return __hiloint2double(__builtin_amdgcn_ds_bpermute((lane ^ m) << 2, hi),
+                          __builtin_amdgcn_ds_bpermute((lane ^ m) << 2, lo));
+}
+
 // Scalar Jacobi rounds t0 .. 31 (repeated inner_sweeps times) on pair w of
-// the step; J accumulates the rotations.  One wavefront, no workgroup
-// barrier.  Lane l owns rotation pair kx = l % 16 for its row updates and
-// its accumulator updates (rows l / 16 + 4 u of J), and the 2 x 2 blocks
-// (kx, l / 16 + 4 u) of the subproblem.
+// the step.  One wavefront, no workgroup barrier.  Lane l (q = l / 16,
+// kx = l % 16) updates, per round, the 2 x 2 blocks (rotation kx) x
+// (rotations q + 4 u) of the subproblem, and holds rows q + 4 u of columns
+// kx and 16 + kx of the accumulated rotation J in registers (jp, jq): a
+// round rotates column pairs (a, a ^ t), which lives in lanes l and l ^ t
+// (t < 16) or l ^ (t - 16) (t >= 16), so one register exchange per entry
+// replaces LDS traffic.
 template <typename R, int STEPB>
-SVDP_DEV void pair_solve(SolveLds<R>& L, int w, int lane, int t0, int inner_sweeps, R floor_abs, float& mrel) {
+SVDP_DEV void pair_solve(SolveLds<R>& L, int w, int lane, int t0, int inner_sweeps, R floor_abs, float& mrel,
+                         R (&jp)[8], R (&jq)[8]) {
   constexpr int XP = XPitch<R>::v;
   R (*X)[XP] = L.X;
-  double (*J)[LP] = L.J[w];
   RotPair<R>* cs = L.cs[w];
-  for (int idx = lane; idx < PB * PB; idx += 64) J[idx >> 5][idx & 31] = (idx >> 5) == (idx & 31) ? 1.0 : 0.0;
-  wave_sync();
   const int kx = lane & 15, q = lane >> 4;
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    jp[u] = (q + 4 * u == kx) ? R(1) : R(0);
+    jq[u] = (q + 4 * u == 16 + kx) ? R(1) : R(0);
+  }
   for (int sw = 0; sw < inner_sweeps; ++sw) {
     int any = 0;
     for (int t = t0; t < PB; ++t) {
@@ -155,8 +173,9 @@ SVDP_DEV void pair_solve(SolveLds<R>& L, int w, int lane, int t0, int inner_swee
           rotation_fast(app, aqq, apq, r.c, r.s);
           any = 1;
           if (fabs(apq) > floor_abs) {
-            const R den = sqrt(fabs(app * aqq));
-            mrel = fmaxf(mrel, den > R(0) ? (float)(fabs(apq) / den) : 1e30f);
+            // |apq| / sqrt(|app aqq|), a convergence statistic (no IEEE rounding needed)
+            const float den2 = fabsf((float)app * (float)aqq);
+            mrel = fmaxf(mrel, den2 > 0.f ? fabsf((float)apq) * __builtin_amdgcn_rsqf(den2) : 1e30f);
           }
         }
         cs[lane] = r;
@@ -165,29 +184,56 @@ SVDP_DEV void pair_solve(SolveLds<R>& L, int w, int lane, int t0, int inner_swee
       const RotPair<R> r1 = cs[kx];
       R* rowx = X[gx1];
       R* rowy = X[gy1];
+      // the lane's four 2 x 2 blocks are disjoint from every other lane's:
+      // all loads first, then all stores (one LDS round trip)
+      int cx[4], cy[4];
+      RotPair<R> r2[4];
+      R a[4], bq[4], cq[4], d[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const int ky = q + 4 * u;
         int x2, y2;
-        pair_of(ky, x2, y2);
-        const int gx2 = gpos<STEPB>(w, x2), gy2 = gpos<STEPB>(w, y2);
-        const RotPair<R> r2 = cs[ky];
-        const R a = rowx[gx2], bq = rowx[gy2], cq = rowy[gx2], d = rowy[gy2];
-        const R t00 = r1.c * a - r1.s * cq, t01 = r1.c * bq - r1.s * d;
-        const R t10 = r1.s * a + r1.c * cq, t11 = r1.s * bq + r1.c * d;
-        R y00 = r2.c * t00 - r2.s * t01, y01 = r2.s * t00 + r2.c * t01;
-        R y10 = r2.c * t10 - r2.s * t11, y11 = r2.s * t10 + r2.c * t11;
-        if (kx == ky && r1.s != R(0)) { y01 = 0; y10 = 0; }
-        rowx[gx2] = y00; rowx[gy2] = y01; rowy[gx2] = y10; rowy[gy2] = y11;
+        pair_of(q + 4 * u, x2, y2);
+        cx[u] = gpos<STEPB>(w, x2);
+        cy[u] = gpos<STEPB>(w, y2);
+        r2[u] = cs[q + 4 * u];
+        a[u] = rowx[cx[u]]; bq[u] = rowx[cy[u]]; cq[u] = rowy[cx[u]]; d[u] = rowy[cy[u]];
       }
-      // J <- J R on columns (x1, y1), rows q + 4 u
-      const double c = r1.c, sn = r1.s;
+      // rotations of the lane's two J columns: column kx pairs with the
+      // partner lane's column (t >= 16: 16 + (kx ^ u), t < 16: kx ^ t), and
+      // column 16 + kx with the partner's (kx ^ u, resp. 16 + (kx ^ t))
+      const int m = t & 15;
+      RotPair<R> rp, rq;
+      bool px, qx;  // the lane's column is the first of its pair
+      if (t >= 16) {
+        rp = cs[kx];
+        rq = cs[kx ^ m];
+        px = true;
+        qx = false;
+      } else {
+        const int xs = (kx >> hb) & 1 ? kx ^ t : kx;
+        rp = cs[compress(xs, hb)];
+        rq = cs[8 + compress(xs, hb)];
+        px = qx = ((kx >> hb) & 1) == 0;
+      }
+      wave_sync();
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const R t00 = r1.c * a[u] - r1.s * cq[u], t01 = r1.c * bq[u] - r1.s * d[u];
+        const R t10 = r1.s * a[u] + r1.c * cq[u], t11 = r1.s * bq[u] + r1.c * d[u];
+        R y00 = r2[u].c * t00 - r2[u].s * t01, y01 = r2[u].s * t00 + r2[u].c * t01;
+        R y10 = r2[u].c * t10 - r2[u].s * t11, y11 = r2[u].s * t10 + r2[u].c * t11;
+        if (kx == q + 4 * u && r1.s != R(0)) { y01 = 0; y10 = 0; }
+        rowx[cx[u]] = y00; rowx[cy[u]] = y01; rowy[cx[u]] = y10; rowy[cy[u]] = y11;
+      }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        const int r = q + 4 * u;
-        const double jx = J[r][x1], jy = J[r][y1];
-        J[r][x1] = c * jx - sn * jy;
-        J[r][y1] = sn * jx + c * jy;
+        const R op = lane_xor<R>(jp[u], lane, m);  // partner's column kx ^ m
+        const R oq = lane_xor<R>(jq[u], lane, m);  // partner's column 16 + (kx ^ m)
+        // partner column of kx: 16 + (kx ^ m) (cross) or kx ^ t (intra)
+        const R pp = t >= 16 ? oq : op;
+        const R pq = t >= 16 ? op : oq;
+        jp[u] = px ? rp.c * jp[u] - rp.s * pp : rp.s * pp + rp.c * jp[u];
+        jq[u] = qx ? rq.c * jq[u] - rq.s * pq : rq.s * pq + rq.c * jq[u];
       }
       wave_sync();
     }
@@ -196,21 +242,14 @@ SVDP_DEV void pair_solve(SolveLds<R>& L, int w, int lane, int t0, int inner_swee
   }
 }
 
-// wave w's accumulator (FP64) -> its FP32 copy in the same LDS space
+// the step's rotations (registers) -> wave w's FP32 LDS copy
 template <typename R>
-SVDP_DEV void acc_to_float(SolveLds<R>& L, int w, int lane) {
-  double v[16];
+SVDP_DEV void j_to_lds(SolveLds<R>& L, int w, int lane, const R (&jp)[8], const R (&jq)[8]) {
+  const int kx = lane & 15, q = lane >> 4;
 #pragma unroll
-  for (int u = 0; u < 16; ++u) {
-    const int idx = lane + 64 * u;
-    v[u] = L.J[w][idx >> 5][idx & 31];
-  }
-  wave_sync();
-  float (*F)[LP] = jf(L, w);
-#pragma unroll
-  for (int u = 0; u < 16; ++u) {
-    const int idx = lane + 64 * u;
-    F[idx >> 5][idx & 31] = (float)v[u];
+  for (int u = 0; u < 8; ++u) {
+    L.Jf[w][q + 4 * u][kx] = (float)jp[u];
+    L.Jf[w][q + 4 * u][16 + kx] = (float)jq[u];
   }
   wave_sync();
 }
@@ -279,26 +318,27 @@ __global__ __launch_bounds__(128) void k_jac_solve(EighWs e, EighPhase ph, int i
   float mrel = 0.f;
   float* M = e.Qw + ((int64_t)b * ng + gi) * QSTRIDE;
   float* JAg = M + GS * GS;  // step-A rotations (FP32), read back for M_G
+  R jp[8], jq[8];
   // step A
-  pair_solve<R, 0>(L, w, lane, ph.fullA ? 1 : 16, inner_sweeps, floor_abs, mrel);
-  acc_to_float(L, w, lane);
-  for (int idx = lane; idx < PB * PB; idx += 64) JAg[w * PB * PB + idx] = jf(L, w)[idx >> 5][idx & 31];
+  pair_solve<R, 0>(L, w, lane, ph.fullA ? 1 : 16, inner_sweeps, floor_abs, mrel, jp, jq);
+  j_to_lds(L, w, lane, jp, jq);
+  for (int idx = lane; idx < PB * PB; idx += 64) JAg[w * PB * PB + idx] = L.Jf[w][idx >> 5][idx & 31];
   __syncthreads();
-  if (w == 0) cross_update<R, 0>(L, jf(L, 0), jf(L, 1), lane);
+  if (w == 0) cross_update<R, 0>(L, L.Jf[0], L.Jf[1], lane);
   __syncthreads();
   const int kh = lane >> 5, ic = lane & 31;
   if (ph.skipB) {
     // M_G = J_A (block diagonal)
     for (int idx = t; idx < GS * GS; idx += 128) {
       const int p = idx >> 6, qq = idx & 63;
-      M[idx] = (p >> 5) == (qq >> 5) ? jf(L, p >> 5)[p & 31][qq & 31] : 0.f;
+      M[idx] = (p >> 5) == (qq >> 5) ? L.Jf[p >> 5][p & 31][qq & 31] : 0.f;
     }
   } else {
     // step B
-    pair_solve<R, 1>(L, w, lane, 16, inner_sweeps, floor_abs, mrel);
-    acc_to_float(L, w, lane);
+    pair_solve<R, 1>(L, w, lane, 16, inner_sweeps, floor_abs, mrel, jp, jq);
+    j_to_lds(L, w, lane, jp, jq);
     __syncthreads();
-    if (w == 0) cross_update<R, 1>(L, jf(L, 0), jf(L, 1), lane);
+    if (w == 0) cross_update<R, 1>(L, L.Jf[0], L.Jf[1], lane);
     // M_G = J_A J_B, block (wa, wb): rows of step-A pair wa, columns of
     // step-B pair wb; the shared indices are local 32 wa + 16 wb + k, k < 16
     for (int blk = w; blk < 4; blk += 2) {
@@ -306,7 +346,7 @@ __global__ __launch_bounds__(128) void k_jac_solve(EighWs e, EighPhase ph, int i
       f16v acc = zero16();
 #pragma unroll
       for (int kk = 0; kk < 16; kk += 2)
-        acc = mfma(JAg[wa * PB * PB + ic * PB + 16 * wb + kk + kh], jf(L, wb)[16 * wa + kk + kh][ic], acc);
+        acc = mfma(JAg[wa * PB * PB + ic * PB + 16 * wb + kk + kh], L.Jf[wb][16 * wa + kk + kh][ic], acc);
 #pragma unroll
       for (int gg = 0; gg < 4; ++gg)
 #pragma unroll

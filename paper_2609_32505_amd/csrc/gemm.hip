@@ -257,8 +257,15 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g, int tiles_m, int 
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int FM = WM / 32, FN = WN / 32;
   constexpr int LDK = BK + 8;  // row stride (bf16) of the k-contiguous LDS tiles
-  __shared__ bf16_t As[2][BM][LDK];
-  __shared__ bf16_t Bs[2][BN][LDK];
+  // An operand stored with the contraction index strided (A when TA, B when
+  // !TB) stays k-major in LDS (rows of k, 16-byte vector stores); its MFMA
+  // operands (8 consecutive k per lane) are then gathered with 2-byte reads
+  // that are contiguous across lanes.  Transposing it on the way in would
+  // make every store an 8-row-stride scatter (16-way bank conflicts).
+  constexpr int LDA = TA ? BM + 8 : LDK;
+  constexpr int LDB = TB ? LDK : BN + 8;
+  __shared__ bf16_t As[2][TA ? BK : BM][LDA];
+  __shared__ bf16_t Bs[2][TB ? BN : BK][LDB];
   int b, tile;
   if (!map_block(ntiles, g.batch, remap, b, tile)) return;
   if (g.active && !g.active[b]) return;
@@ -332,7 +339,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g, int tiles_m, int 
       int idx = t + 256 * u;
       if (TA) {
         int k = idx / (BM / 8), i = (idx % (BM / 8)) * 8;
-        for (int c = 0; c < 8; ++c) As[buf][i + c][k] = ra[u][c];
+        *(bf8v*)&As[buf][k][i] = ra[u];
       } else {
         int i = idx / (BK / 8), k = (idx % (BK / 8)) * 8;
         *(bf8v*)&As[buf][i][k] = ra[u];
@@ -343,7 +350,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g, int tiles_m, int 
       int idx = t + 256 * u;
       if (!TB) {
         int k = idx / (BN / 8), j = (idx % (BN / 8)) * 8;
-        for (int c = 0; c < 8; ++c) Bs[buf][j + c][k] = rb[u][c];
+        *(bf8v*)&Bs[buf][k][j] = rb[u];
       } else {
         int j = idx / (BK / 8), k = (idx % (BK / 8)) * 8;
         *(bf8v*)&Bs[buf][j][k] = rb[u];
@@ -369,12 +376,27 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g, int tiles_m, int 
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 16) {
       bf8v av[FM], bv[FN];
+      const int k8 = kk + (lane >> 5) * 8;
 #pragma unroll
-      for (int mi = 0; mi < FM; ++mi)
-        av[mi] = *(const bf8v*)&As[cur][wm * WM + mi * 32 + (lane & 31)][kk + (lane >> 5) * 8];
+      for (int mi = 0; mi < FM; ++mi) {
+        const int i = wm * WM + mi * 32 + (lane & 31);
+        if (TA) {
 #pragma unroll
-      for (int ni = 0; ni < FN; ++ni)
-        bv[ni] = *(const bf8v*)&Bs[cur][wn * WN + ni * 32 + (lane & 31)][kk + (lane >> 5) * 8];
+          for (int c = 0; c < 8; ++c) av[mi][c] = As[cur][k8 + c][i];
+        } else {
+          av[mi] = *(const bf8v*)&As[cur][i][k8];
+        }
+      }
+#pragma unroll
+      for (int ni = 0; ni < FN; ++ni) {
+        const int j = wn * WN + ni * 32 + (lane & 31);
+        if (!TB) {
+#pragma unroll
+          for (int c = 0; c < 8; ++c) bv[ni][c] = Bs[cur][k8 + c][j];
+        } else {
+          bv[ni] = *(const bf8v*)&Bs[cur][j][k8];
+        }
+      }
 #pragma unroll
       for (int mi = 0; mi < FM; ++mi)
 #pragma unroll
