@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -17,7 +18,7 @@ struct svdp_handle {
   float* model = nullptr;  // device: SVDP_MODEL_FLOATS
   bool has_model = false;
   int* host_word = nullptr;  // pinned: counter read-back
-  EighAux aux{nullptr, nullptr, nullptr, nullptr};  // second stream of the eigensolver
+  EighAux aux{};  // extra streams of the eigensolver
 };
 
 namespace {
@@ -533,10 +534,21 @@ svdp_status svdp_create(svdp_handle** out) {
   svdp_handle* h = new svdp_handle();
   hipError_t e = hipMalloc((void**)&h->model, SVDP_MODEL_FLOATS * sizeof(float));
   if (e == hipSuccess) e = hipHostMalloc((void**)&h->host_word, 4096, hipHostMallocDefault);
-  if (e == hipSuccess) e = hipStreamCreateWithFlags(&h->aux.st2, hipStreamNonBlocking);
+  // parts of the batch the eigensolver runs on parallel streams (1 .. 4);
+  // SVDP_EIGH_PARTS overrides the default of 2 (more parts measured no
+  // faster: the sweeps are then throughput-bound)
+  h->aux.parts = 2;
+  if (const char* env = std::getenv("SVDP_EIGH_PARTS")) {
+    const int v = std::atoi(env);
+    if (v >= 1 && v <= kEighParts) h->aux.parts = v;
+  }
+  for (int i = 0; i < kEighParts - 1 && e == hipSuccess; ++i)
+    e = hipStreamCreateWithFlags(&h->aux.st[i], hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&h->aux.fork, hipEventDisableTiming);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&h->aux.join, hipEventDisableTiming);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&h->aux.skew, hipEventDisableTiming);
+  for (int i = 0; i < kEighParts && e == hipSuccess; ++i) {
+    e = hipEventCreateWithFlags(&h->aux.skew[i], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->aux.join[i], hipEventDisableTiming);
+  }
   if (e != hipSuccess) {
     (void)svdp_destroy(h);
     return hip_fail(e, "svdp_create");
@@ -547,11 +559,15 @@ svdp_status svdp_create(svdp_handle** out) {
 
 svdp_status svdp_destroy(svdp_handle* h) {
   if (!h) return SVDP_OK;
-  if (h->aux.st2) (void)hipStreamSynchronize(h->aux.st2);
-  if (h->aux.skew) (void)hipEventDestroy(h->aux.skew);
-  if (h->aux.join) (void)hipEventDestroy(h->aux.join);
+  for (int i = 0; i < kEighParts - 1; ++i)
+    if (h->aux.st[i]) (void)hipStreamSynchronize(h->aux.st[i]);
+  for (int i = 0; i < kEighParts; ++i) {
+    if (h->aux.skew[i]) (void)hipEventDestroy(h->aux.skew[i]);
+    if (h->aux.join[i]) (void)hipEventDestroy(h->aux.join[i]);
+  }
   if (h->aux.fork) (void)hipEventDestroy(h->aux.fork);
-  if (h->aux.st2) (void)hipStreamDestroy(h->aux.st2);
+  for (int i = 0; i < kEighParts - 1; ++i)
+    if (h->aux.st[i]) (void)hipStreamDestroy(h->aux.st[i]);
   if (h->model) (void)hipFree(h->model);
   if (h->host_word) (void)hipHostFree(h->host_word);
   delete h;

@@ -782,7 +782,7 @@ std::vector<EighPhase> eigh_phases(int nb) {
   return out;
 }
 
-// View of matrices [b0, b0 + cnt) of a workspace; half h uses its own
+// View of matrices [b0, b0 + cnt) of a workspace; part h uses its own
 // device counter.
 static EighWs eigh_sub(const EighWs& e, int b0, int cnt, int h) {
   EighWs s = e;
@@ -797,7 +797,7 @@ static EighWs eigh_sub(const EighWs& e, int b0, int cnt, int h) {
   s.sgn += (int64_t)b0 * e.n;
   s.perm += (int64_t)b0 * e.n;
   s.active += b0;
-  s.counter += 8 * h;
+  s.counter += 4 * h;
   return s;
 }
 
@@ -827,21 +827,27 @@ hipError_t eigh_run(EighWs e, const float* H, int64_t ldh, int64_t sH, int mode,
     const int rounds = (ph.fullA ? 31 : 16) + (ph.skipB ? 0 : 16);
     return (double)ng * 2.0 * rounds * round_work * reps;
   };
-  // Two halves of the batch on two streams (when a second stream is given):
-  // the LDS/VALU-bound pair solves of one half run beside the MFMA/HBM-bound
-  // rotations of the other.
-  const int halves = (aux && batch >= 2) ? 2 : 1;
-  int b0[2] = {0, batch / 2}, bc[2] = {batch / 2, batch - batch / 2};
-  if (halves == 1) bc[0] = batch;
-  hipStream_t ss[2] = {st, halves == 2 ? aux->st2 : st};
-  EighWs eh[2];
-  for (int h = 0; h < halves; ++h) eh[h] = eigh_sub(e, b0[h], bc[h], h);
-  if (halves == 2) {
+  // Parts of the batch on parallel streams (when extra streams are given):
+  // the LDS/VALU-bound pair solves of one part run beside the MFMA/HBM-bound
+  // rotations of the others.
+  int P = aux ? std::min(std::max(aux->parts, 1), kEighParts) : 1;
+  P = std::min(P, batch);
+  int b0[kEighParts], bc[kEighParts];
+  hipStream_t ss[kEighParts];
+  EighWs eh[kEighParts];
+  for (int h = 0; h < P; ++h) {
+    b0[h] = (int)((int64_t)batch * h / P);
+    bc[h] = (int)((int64_t)batch * (h + 1) / P) - b0[h];
+    ss[h] = h == 0 ? st : aux->st[h - 1];
+    eh[h] = eigh_sub(e, b0[h], bc[h], h);
+  }
+  if (P > 1) {
     if ((err = hipEventRecord(aux->fork, st))) return err;
-    if ((err = hipStreamWaitEvent(aux->st2, aux->fork, 0))) return err;
+    for (int h = 1; h < P; ++h)
+      if ((err = hipStreamWaitEvent(ss[h], aux->fork, 0))) return err;
   }
   auto phase_launches = [&](int h, const EighPhase& ph, bool fp64, int* rc, int n_act,
-                            bool mark_skew = false) -> hipError_t {
+                            bool mark_skew) -> hipError_t {
     const EighWs& E = eh[h];
     const unsigned sblocks = (unsigned)(E.batch * ng);
     const unsigned ablocks = (unsigned)((int64_t)cdiv(E.batch, 8) * 8 * ntask);
@@ -856,29 +862,37 @@ hipError_t eigh_run(EighWs e, const float* H, int64_t ldh, int64_t sH, int mode,
     }
     hipError_t e2 = hipGetLastError();
     if (e2) return e2;
-    if (mark_skew && (e2 = hipEventRecord(aux->skew, ss[h]))) return e2;
+    if (mark_skew && (e2 = hipEventRecord(aux->skew[h], ss[h]))) return e2;
     {
       ProfScope ps(PROF_JAC_APPLY, ss[h], apply_work * n_act);
       hipLaunchKernelGGL(k_jac_apply, dim3(ablocks), dim3(256), 0, ss[h], E, ph);
     }
     return hipGetLastError();
   };
-  int n_act[2] = {bc[0], bc[1]};
-  int sweep = 0;
-  for (; sweep < e.max_sweeps; ++sweep) {
-    int* rc = e.rotcnt + (int64_t)batch * sweep;
+  // one pass over the phases for every part; part h starts after part
+  // h - 1's first pair solve
+  auto sweep_launches = [&](bool fp64, int* rc, const int* n_act) -> hipError_t {
     bool first = true;
     for (const EighPhase& ph : phases) {
-      for (int h = 0; h < halves; ++h) {
+      int prev = -1;
+      for (int h = 0; h < P; ++h) {
         if (n_act[h] == 0) continue;
-        // the second half waits for the first half's first pair solve of the
-        // sweep, so that the two streams alternate solve and rotation
-        if (h == 1 && first && n_act[0] > 0 && (err = hipStreamWaitEvent(ss[1], aux->skew, 0))) return err;
-        if ((err = phase_launches(h, ph, false, rc + b0[h], n_act[h], h == 0 && first && halves == 2))) return err;
+        hipError_t e2;
+        if (first && prev >= 0 && (e2 = hipStreamWaitEvent(ss[h], aux->skew[prev], 0))) return e2;
+        if ((e2 = phase_launches(h, ph, fp64, rc ? rc + b0[h] : nullptr, n_act[h], first && P > 1))) return e2;
+        prev = h;
       }
       first = false;
     }
-    for (int h = 0; h < halves; ++h) {
+    return hipSuccess;
+  };
+  int n_act[kEighParts];
+  for (int h = 0; h < P; ++h) n_act[h] = bc[h];
+  int sweep = 0;
+  for (; sweep < e.max_sweeps; ++sweep) {
+    int* rc = e.rotcnt + (int64_t)batch * sweep;
+    if ((err = sweep_launches(false, rc, n_act))) return err;
+    for (int h = 0; h < P; ++h) {
       if (n_act[h] == 0) continue;
       hipLaunchKernelGGL(k_eigh_check, dim3(1), dim3(1024), 0, ss[h], eh[h], rc + b0[h], o.tol, sweep,
                          sweeps_out + b0[h], eh[h].counter);
@@ -887,7 +901,7 @@ hipError_t eigh_run(EighWs e, const float* H, int64_t ldh, int64_t sH, int mode,
         return err;
     }
     int total = 0;
-    for (int h = 0; h < halves; ++h) {
+    for (int h = 0; h < P; ++h) {
       if (n_act[h] == 0) continue;
       if ((err = hipStreamSynchronize(ss[h]))) return err;
       n_act[h] = host_counter[h];
@@ -897,32 +911,25 @@ hipError_t eigh_run(EighWs e, const float* H, int64_t ldh, int64_t sH, int mode,
   }
   // matrices still active after max_sweeps did not converge
   if (sweep == e.max_sweeps)
-    for (int h = 0; h < halves; ++h) {
+    for (int h = 0; h < P; ++h) {
       hipLaunchKernelGGL(k_flag_active, dim3(cdiv(bc[h], 256)), dim3(256), 0, ss[h], eh[h].active, bc[h],
                          flags + b0[h], (int)SVDP_FLAG_EIGH_NOT_CONVERGED);
       if ((err = hipGetLastError())) return err;
     }
   // final sweep(s) with FP64 pair solves on every matrix
   if (o.fp64_sweeps > 0) {
-    for (int h = 0; h < halves; ++h) {
+    for (int h = 0; h < P; ++h) {
       if (mask) { if ((err = copy_i32(eh[h].active, mask + b0[h], bc[h], ss[h]))) return err; }
       else if ((err = fill_i32(eh[h].active, 1, bc[h], ss[h]))) return err;
     }
-    for (int f = 0; f < o.fp64_sweeps; ++f) {
-      bool first = true;
-      for (const EighPhase& ph : phases) {
-        for (int h = 0; h < halves; ++h) {
-          if (h == 1 && first && (err = hipStreamWaitEvent(ss[1], aux->skew, 0))) return err;
-          if ((err = phase_launches(h, ph, true, nullptr, bc[h], h == 0 && first && halves == 2))) return err;
-        }
-        first = false;
-      }
+    for (int f = 0; f < o.fp64_sweeps; ++f)
+      if ((err = sweep_launches(true, nullptr, bc))) return err;
+  }
+  if (P > 1)
+    for (int h = 1; h < P; ++h) {
+      if ((err = hipEventRecord(aux->join[h], ss[h]))) return err;
+      if ((err = hipStreamWaitEvent(st, aux->join[h], 0))) return err;
     }
-  }
-  if (halves == 2) {
-    if ((err = hipEventRecord(aux->join, aux->st2))) return err;
-    if ((err = hipStreamWaitEvent(st, aux->join, 0))) return err;
-  }
   // V (tiled) -> row-major in Hw; one Newton-Schulz step re-orthonormalises
   // it, V2 = V (3 I - V^T V) / 2 (V^T V in Vw); the eigenvalues are the
   // Rayleigh quotients v_i^T H v_i against the input matrix (H V2 in Hw).

@@ -39,13 +39,18 @@ struct EighOpts {
   float neg_tol;     // NEG_EIGENVALUE when lam_min < -neg_tol max|lam| (mode 1)
 };
 
-// A second stream and three events: the sweeps run the two halves of the
-// batch on the caller's stream and on st2, the second half starting one
-// pair solve later, so that the pair solves of one half overlap the block
-// rotations of the other.
+// Extra streams and events: the sweeps run parts of the batch on the
+// caller's stream and on up to kEighParts - 1 more streams, each part
+// starting one pair solve after the previous one, so that the
+// latency-bound pair solves of some parts overlap the block rotations of
+// the others.
+constexpr int kEighParts = 4;
 struct EighAux {
-  hipStream_t st2;
-  hipEvent_t fork, join, skew;
+  int parts;                         // 1 .. kEighParts
+  hipStream_t st[kEighParts - 1];    // streams of parts 1 .. parts - 1
+  hipEvent_t fork;
+  hipEvent_t skew[kEighParts];
+  hipEvent_t join[kEighParts];
 };
 
 int eigh_blocks(int64_t n);
