@@ -95,14 +95,17 @@ typedef struct {
                               its square; tightly clustered spectra need the margin (3e-3) */
   double jacobi_abs;       /* entries below jacobi_abs |H|_F are ignored by that test (1e-9) */
   double bf16_from;        /* bounded paths: FP32 steps until the interval's lower end
-                              reaches this value, BF16 steps after it (0.1) */
+                              reaches this value, BF16 steps after it (0.05); lower values
+                              trade sigma accuracy of the smallest values for speed */
   double eps_K, eps_R, eps_T; /* backward regularisers (absolute, units of sigma^2):
                               K_ij = (s_i - s_j)/((s_i - s_j)^2 + eps_K),
                               R = V S (S^2 + eps_R)^-1 V^T,
                               T_ij = (s_i + s_j)/((s_i + s_j)^2 + eps_T).
                               Algorithm 4 takes (eps^1/2, eps^1/2, eps^1/4). */
   double margin_max;       /* learned/user sigma_max is multiplied by this (1.1) */
-  double margin_min;       /* learned/user sigma_min is multiplied by this (0.5) */
+  double margin_min;       /* learned/user sigma_min is multiplied by this (1.0: the learned
+                              bound is already a 0.98 quantile; values it overestimates are
+                              finished by the refinement's stop test) */
   const float* user_bounds; /* device, batch x 2 (sigma_min, sigma_max), bound == USER */
   const float* probe;      /* device, batch x n Gaussian probe vectors, bound == LEARNED */
 } svdp_params;
