@@ -135,3 +135,49 @@ def test_autograd_svd_and_polar(api):
         _, Ho = oracle.polar_from_svd(Uo, So, Vo)
         ref = oracle.polar_bwd(A[i], Ho, G[i], K[i])
         assert np.linalg.norm(g[i] - ref) / np.linalg.norm(ref) < 1e-4
+
+
+def test_eigh_results_do_not_depend_on_stream_parts(api):
+    # the eigensolver splits the batch over parallel streams; every matrix
+    # runs the same kernels on its own data, so results are bitwise equal
+    import os
+    import torch
+    _say("eigh 5 x 100^2 with 1, 2 and 4 stream parts")
+    rng = inputs.rng_for(95, 0)
+    lam0 = inputs.log_uniform(rng, 100, 1e-3, 1.0)
+    Hs = np.stack([inputs.matrix_with_spectrum(inputs.rng_for(95, i + 1), 100, 100, lam0) for i in range(5)])
+    Hs = 0.5 * (Hs + Hs.transpose(0, 2, 1))
+    Hd = dev(Hs)
+    out = []
+    old = os.environ.get("SVDP_EIGH_PARTS")
+    try:
+        for parts in ("1", "2", "4"):
+            os.environ["SVDP_EIGH_PARTS"] = parts
+            h = api.Handle()
+            lam, V, info = api.eigh(Hd, handle=h)
+            torch.cuda.synchronize()
+            out.append((lam.cpu().numpy(), V.cpu().numpy(), api.info_to_numpy(info)["sweeps"]))
+    finally:
+        if old is None:
+            os.environ.pop("SVDP_EIGH_PARTS", None)
+        else:
+            os.environ["SVDP_EIGH_PARTS"] = old
+    for lam, V, sw in out[1:]:
+        np.testing.assert_array_equal(lam, out[0][0])
+        np.testing.assert_array_equal(V, out[0][1])
+        np.testing.assert_array_equal(sw, out[0][2])
+
+
+def test_bound_far_too_narrow_hits_refinement_cap_and_falls_back(api):
+    # user bounds claim kappa = 2 for matrices with kappa = 1e3: the bounded
+    # schedule leaves the small singular values far from 1, the refinement
+    # stop test does not pass within its cap, and conservative CANS reruns
+    _say("user bounds with kappa 2 for kappa 1e3: refinement cap, fallback")
+    A, s = inputs.batch_with_spectra(96, 3, 80, 64, lambda r: inputs.log_uniform(r, 64, 1e-3, 1.0))
+    ub = dev(np.stack([0.5 * s[:, 0], s[:, 0]], axis=1))
+    U, S, V, info = api.svd_fwd(dev(A), precision=1, bound=2, user_bounds=ub)
+    inf = api.info_to_numpy(info)
+    assert np.all(inf["flags"] & 2), "fallback must be used"
+    assert not np.any(inf["flags"] & 1), "the conservative rerun converges"
+    Sh = S.cpu().double().numpy()
+    assert (np.abs(Sh - s).max(axis=1) / s[:, 0]).max() < 1e-5
