@@ -251,7 +251,7 @@ __global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs g, int tiles_m, int t
 // ------------------------------------------------------------------ BF16
 
 template <int BM, int BN, bool TA, bool TB, bool INBF, bool VEC>
-__global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g, int tiles_m, int tiles_n,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 4))) void k_gemm_bf16(GemmArgs g, int tiles_m, int tiles_n,
                                                    int ntiles, int remap) {
   constexpr int BK = 64;
   constexpr int WM = BM / 2, WN = BN / 2;
@@ -264,8 +264,10 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g, int tiles_m, int 
   // make every store an 8-row-stride scatter (16-way bank conflicts).
   constexpr int LDA = TA ? BM + 8 : LDK;
   constexpr int LDB = TB ? LDK : BN + 8;
-  __shared__ bf16_t As[2][TA ? BK : BM][LDA];
-  __shared__ bf16_t Bs[2][TB ? BN : BK][LDB];
+  // one LDS buffer (37 KB at 128 x 128): the next K slice waits in
+  // registers during the MFMAs, so four workgroups fit a CU
+  __shared__ bf16_t As[1][TA ? BK : BM][LDA];
+  __shared__ bf16_t Bs[1][TB ? BN : BK][LDB];
   int b, tile;
   if (!map_block(ntiles, g.batch, remap, b, tile)) return;
   if (g.active && !g.active[b]) return;
@@ -371,7 +373,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g, int tiles_m, int 
   store(0);
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
-    const int cur = kt & 1;
+    const int cur = 0;
     if (kt + 1 < nk) load((kt + 1) * BK);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 16) {
@@ -403,7 +405,10 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g, int tiles_m, int 
         for (int ni = 0; ni < FN; ++ni)
           acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[mi], bv[ni], acc[mi][ni], 0, 0, 0);
     }
-    if (kt + 1 < nk) store(cur ^ 1);
+    if (kt + 1 < nk) {
+      __syncthreads();  // every wave is done with this slice
+      store(0);
+    }
     __syncthreads();
   }
   epilogue<FM, FN>(g, b, m0 + wm * WM, n0 + wn * WN, tm, tn, acc);
