@@ -119,8 +119,8 @@ def cpu_baseline(A, dU, dS, dV, sample: int):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--cpu-sample", type=int, default=16)
@@ -174,15 +174,16 @@ def main():
         if profile:
             L.load().svdp_profile_reset()
             L.load().svdp_profile_enable(1)
-        ev0 = torch.cuda.Event(enable_timing=True)
-        ev1 = torch.cuda.Event(enable_timing=True)
-        ev0.record()
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+        evs[0].record()
         out = None
-        for _ in range(args.steps):
+        for i in range(args.steps):
             out = step(learned)
-        ev1.record()
+            evs[i + 1].record()
         torch.cuda.synchronize()
-        ms = ev0.elapsed_time(ev1) / args.steps
+        per = [evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)]
+        ms = evs[0].elapsed_time(evs[-1]) / args.steps
+        timed.per_step = per
         prof = None
         if profile:
             L.load().svdp_profile_enable(0)
@@ -200,10 +201,13 @@ def main():
         log(f"{args.path}: {ms:.2f} ms/step")
         print(json.dumps({"profile_only": True, "path": args.path, "ms_per_step": ms}))
         return
+    import statistics
     ms_l, (S_l, info_l, _), prof = timed(True, True)
-    log(f"learned: {ms_l:.2f} ms/step")
+    sd_l = statistics.pstdev(timed.per_step)
+    log(f"learned: {ms_l:.2f} +- {sd_l:.2f} ms/step")
     ms_p, (S_p, info_p, _), prof_p = timed(False, True)
-    log(f"plain fp32: {ms_p:.2f} ms/step")
+    sd_p = statistics.pstdev(timed.per_step)
+    log(f"plain fp32: {ms_p:.2f} +- {sd_p:.2f} ms/step")
 
     il, ip = api.info_to_numpy(info_l), api.info_to_numpy(info_p)
     Sl, Sp = S_l.cpu().double().numpy(), S_p.cpu().double().numpy()
@@ -220,22 +224,44 @@ def main():
     err_lo = float((np.abs(Sl[:k] - S_or).max(axis=1) / S_or[:, 0]).max())
     valid = err_lp + err_po <= 1e-3 and err_lo <= 1e-3
 
+    def recon_orth(U, S, V):
+        # |U diag(S) V^T - A|_F / |A|_F and max |U^T U - I| per matrix (FP32 on the GPU)
+        rec, orth = [], []
+        eye = torch.eye(n, device=dev)
+        for c0 in range(0, B, 32):
+            u, s, v = U[c0:c0 + 32], S[c0:c0 + 32], V[c0:c0 + 32]
+            a = Ad[c0:c0 + 32]
+            r = torch.bmm(u * s[:, None, :], v.transpose(1, 2).contiguous()) - a
+            rec.append((torch.linalg.norm(r, dim=(1, 2)) / torch.linalg.norm(a, dim=(1, 2))).cpu())
+            g = torch.bmm(u.transpose(1, 2).contiguous(), u) - eye
+            orth.append(g.abs().amax(dim=(1, 2)).cpu())
+        return float(torch.cat(rec).max()), float(torch.cat(orth).max())
+
+    U_l, _, V_l, _ = api.svd_fwd(Ad, handle=h, precision=L.PREC_BF16, bound=L.BOUND_LEARNED, probe=pd)
+    U_p, _, V_p, _ = api.svd_fwd(Ad, handle=h)
+    rec_l, orth_l = recon_orth(U_l, S_l, V_l)
+    rec_p, orth_p = recon_orth(U_p, S_p, V_p)
+
     name, roof = roofline_of(prof)
     value = B / (ms_l * 1e-3)
     rec = {
         "metric": "SVD fwd+bwd matrices/s, 512^2 batch, sigma err<=1e-3; learned BF16 vs plain FP32 CANS",
         "value": round(value, 3), "unit": "matrices/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(ms_l, 3), "higher_is_better": True, "scaling": "weak",
+        "warmup": args.warmup, "ms_per_step": round(ms_l, 3), "ms_per_step_std": round(sd_l, 3),
+        "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "bf16+fp32", "data": "synthetic",
         "config": {"workload": f"{B} x {n} x {n} FP32, sigma log-uniform [1e-3,1], svd_polar_fwd + "
                                f"svd_polar_bwd, learned-bound BF16 CANS", "batch": B, "m": n, "n": n},
         "plain_fp32": {"value": round(B / (ms_p * 1e-3), 3), "ms_per_step": round(ms_p, 3),
+                       "ms_per_step_std": round(sd_p, 3),
                        "iters_max": int(ip["iters"].max()), "iters_mean": round(float(ip["iters"].mean()), 2),
                        "kernels": {k2: {"ms_per_step": round(v["ms"] / args.steps, 3), "launches": v["launches"]}
                                    for k2, v in prof_p.items()}},
         "speedup_learned_vs_plain": round(ms_p / ms_l, 4),
         "sigma_err": {"learned_vs_plain_max": err_lp, "plain_vs_oracle_sampled": err_po,
                       "learned_vs_oracle_sampled": err_lo, "valid": bool(valid)},
+        "factor_err": {"recon_learned_max": rec_l, "orth_U_learned_max": orth_l,
+                       "recon_plain_max": rec_p, "orth_U_plain_max": orth_p},
         "learned_info": {"iters_max": int(il["iters"].max()), "iters_mean": round(float(il["iters"].mean()), 2),
                          "sweeps_max": int(il["sweeps"].max()),
                          "fallbacks": int(((il["flags"] & L.FLAG_FALLBACK_USED) != 0).sum())},

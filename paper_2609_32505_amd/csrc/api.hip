@@ -148,6 +148,7 @@ struct FwdWs {
   void *Y0, *Y1;  // BF16 iterates (never aliasing the FP32 ones)
   void* eigh;
   float *scale, *conv, *resid, *colsum, *rowmax, *fro2, *coef, *rcoef, *F, *aux, *mlpout, *nrm, *y0, *y1;
+  float* qr;  // QR completion scratch: 2 m per matrix
   int *active, *where, *iters, *flags, *sweeps, *mask, *counter, *ksteps, *kmax, *hist, *gmask;
 };
 
@@ -175,6 +176,7 @@ FwdWs carve_fwd(void* base, const svdp_params* p, size_t* total) {
   w.nrm = c.take<float>(b * 8);
   w.y0 = c.take<float>(b * m);
   w.y1 = c.take<float>(b * m);
+  w.qr = c.take<float>(b * 2 * m);
   w.active = c.take<int>(b);
   w.where = c.take<int>(b);
   w.iters = c.take<int>(b);
@@ -460,6 +462,9 @@ svdp_status svd_tail(Ctx& c, float* U, int64_t ldu, int64_t sU, float* S, int64_
   g.active = mask;
   HIPCHK(gemm_launch(g, PREC_F32, 0, 0, c.st), "U = W V");
   HIPCHK(colnorm_check_launch(U, ldu, sU, B, m, n, w.colsum, (float)p->eps_qr, w.flags, mask, c.st), "colnorm");
+  // Algorithm 1: a column norm off by more than eps_qr (rank deficiency)
+  // -> orthogonalise U by QR
+  HIPCHK(qr_complete_launch(U, ldu, sU, B, m, n, (float)p->eps_qr, w.flags, w.qr, mask, c.st), "qr");
   return SVDP_OK;
 }
 
@@ -510,7 +515,7 @@ void svdp_default_params(svdp_params* p, int64_t batch, int64_t m, int64_t n) {
   p->refine_tol = 1e-2;
   p->jacobi_tol = 3e-3;
   p->jacobi_abs = 1e-9;
-  p->bf16_from = 0.05;
+  p->bf16_from = 0.1;
   p->margin_max = 1.1;
   p->margin_min = 1.0;
 }

@@ -191,6 +191,91 @@ __global__ void k_colnorm_flag(const float* cn2, int n, float eps_qr, int* flags
   if (__any(nonfin)) if ((threadIdx.x & 63) == 0) atomicOr(flags + b, SVDP_FLAG_NONFINITE);
 }
 
+// Algorithm 1's orthogonalisation of U, for the matrices flagged
+// RANK_DEFICIENT: U <- Q of U = QR with R_ii >= 0, by classical Gram-Schmidt
+// applied twice per column, left to right, against the finished columns
+// (R_ii is the residual norm).  A column whose residual is below eps_qr (a
+// zero singular value: CANS leaves that column of W V near zero) is replaced
+// by the unit vector of the coordinate the finished columns cover least --
+// its residual is at least sqrt(1 - i / m) > 0 -- and orthogonalised the
+// same way.  One workgroup per matrix; scratch holds v (m) and the coverage
+// (m) per matrix; LDS holds the n projection coefficients.
+SVDP_DEV float block_sum256(float x, float* red) {
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
+  __syncthreads();
+  return red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ __launch_bounds__(256) void k_qr_complete(float* U, int64_t ldu, int64_t sU, int m, int n, float eps_qr,
+                                                     const int* flags, float* scratch, const int* mask) {
+  const int b = blockIdx.x;
+  if (skip(mask, b) || !(flags[b] & SVDP_FLAG_RANK_DEFICIENT)) return;
+  extern __shared__ float rco[];  // n projection coefficients
+  __shared__ float red[4];
+  __shared__ float redv[4];
+  __shared__ int redk[4];
+  float* Ub = U + b * sU;
+  float* v = scratch + (int64_t)b * 2 * m;
+  float* cov = v + m;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  for (int k = t; k < m; k += 256) cov[k] = 0.f;
+  for (int i = 0; i < n; ++i) {
+    for (int k = t; k < m; k += 256) v[k] = Ub[(int64_t)k * ldu + i];
+    __syncthreads();
+    float nrm = 0.f;
+    for (int attempt = 0; attempt < 2; ++attempt) {
+      for (int pass = 0; pass < 2; ++pass) {
+        // coefficients against the finished columns j < i (rows read coalesced)
+        for (int j = t; j < i; j += 256) {
+          float s2 = 0.f;
+          for (int k = 0; k < m; ++k) s2 += Ub[(int64_t)k * ldu + j] * v[k];
+          rco[j] = s2;
+        }
+        __syncthreads();
+        // v -= sum_j rco_j U_j: one wave per row
+        for (int k = w; k < m; k += 4) {
+          float s2 = 0.f;
+          for (int j = lane; j < i; j += 64) s2 += rco[j] * Ub[(int64_t)k * ldu + j];
+          for (int off = 32; off > 0; off >>= 1) s2 += __shfl_xor(s2, off);
+          if (lane == 0) v[k] -= s2;
+        }
+        __syncthreads();
+      }
+      float s2 = 0.f;
+      for (int k = t; k < m; k += 256) s2 += v[k] * v[k];
+      nrm = sqrtf(block_sum256(s2, red));
+      if (nrm >= eps_qr || attempt == 1) break;
+      // zero column: start again from the least covered coordinate
+      float best = INFINITY;
+      int bk = 0;
+      for (int k = t; k < m; k += 256)
+        if (cov[k] < best) { best = cov[k]; bk = k; }
+      for (int off = 32; off > 0; off >>= 1) {
+        const float ob = __shfl_xor(best, off);
+        const int ok = __shfl_xor(bk, off);
+        if (ob < best || (ob == best && ok < bk)) { best = ob; bk = ok; }
+      }
+      if (lane == 0) { redv[w] = best; redk[w] = bk; }
+      __syncthreads();
+      int kstar = redk[0];
+      float vbest = redv[0];
+      for (int q = 1; q < 4; ++q)
+        if (redv[q] < vbest || (redv[q] == vbest && redk[q] < kstar)) { vbest = redv[q]; kstar = redk[q]; }
+      for (int k = t; k < m; k += 256) v[k] = k == kstar ? 1.f : 0.f;
+      __syncthreads();
+    }
+    const float inv = nrm > 0.f ? 1.f / nrm : 0.f;
+    for (int k = t; k < m; k += 256) {
+      const float qv = v[k] * inv;
+      Ub[(int64_t)k * ldu + i] = qv;
+      cov[k] += qv * qv;
+    }
+    __syncthreads();
+  }
+}
+
 // ------------------------------------------------------------ backward
 
 __global__ void k_dvec(const float* S, int64_t sS, int n, double eR, float* D) {
@@ -711,6 +796,14 @@ hipError_t colnorm_check_launch(const float* U, int64_t ldu, int64_t sU, int bat
                      sU, m, n, rows_per, colnorm2, mask);
   if ((e = hipGetLastError())) return e;
   hipLaunchKernelGGL(k_colnorm_flag, dim3(batch), dim3(256), 0, st, colnorm2, n, eps_qr, flags, mask);
+  LAUNCH_CHECK();
+}
+
+hipError_t qr_complete_launch(float* U, int64_t ldu, int64_t sU, int batch, int m, int n, float eps_qr,
+                              const int* flags, float* scratch, const int* mask, hipStream_t st) {
+  if (batch <= 0 || n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_qr_complete, dim3(batch), dim3(256), (size_t)n * sizeof(float), st, U, ldu, sU, m, n, eps_qr,
+                     flags, scratch, mask);
   LAUNCH_CHECK();
 }
 

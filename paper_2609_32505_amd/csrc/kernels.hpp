@@ -34,6 +34,11 @@ hipError_t residual_launch(const void* G, int gbf16, int batch, int n, float* re
 hipError_t colnorm_check_launch(const float* U, int64_t ldu, int64_t sU, int batch, int m, int n,
                                 float* colnorm2, float eps_qr, int* flags, const int* mask,
                                 hipStream_t st);
+// Algorithm 1's QR orthogonalisation of U for the matrices flagged
+// RANK_DEFICIENT (R_ii >= 0; zero columns completed); scratch: 2 m floats
+// per matrix.
+hipError_t qr_complete_launch(float* U, int64_t ldu, int64_t sU, int batch, int m, int n, float eps_qr,
+                              const int* flags, float* scratch, const int* mask, hipStream_t st);
 
 // ---- backward element-wise steps -------------------------------------------
 // D[b, j] = s_j / (s_j^2 + eR) in FP64

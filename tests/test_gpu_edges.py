@@ -51,10 +51,13 @@ def test_empty_batch_is_noop(api):
     assert st == 0
 
 
-def test_rank_deficient_is_flagged(api):
+def test_rank_deficient_is_flagged_and_completed(api):
     # exactly rank-deficient in FP32: the last 28 columns are zero, so CANS
-    # leaves those columns of W at zero (a partial isometry) and the column
-    # norms of U = W V expose it
+    # leaves those columns of W at zero (a partial isometry); the column
+    # norms of U = W V expose it and Algorithm 1's QR step completes U to an
+    # orthonormal matrix.  The completion is not unique: compared are the
+    # singular values, the leading 20 singular vectors (against the FP64
+    # oracle, up to sign) and the orthonormality of the whole U.
     _say("rank-deficient 64x48, rank 20 (zero columns)")
     rng = inputs.rng_for(91, 0)
     B = inputs.matrix_with_spectrum(rng, 64, 20, inputs.geometric(20, 10.0))
@@ -63,9 +66,34 @@ def test_rank_deficient_is_flagged(api):
     U, S, V, info = api.svd_fwd(dev(A[None]))
     inf = api.info_to_numpy(info)
     Sh = S.cpu().double().numpy()[0]
+    Uh, Vh = U.cpu().double().numpy()[0], V.cpu().double().numpy()[0]
     np.testing.assert_allclose(Sh[:20], s[:20], atol=1e-5)
     assert np.abs(Sh[20:]).max() < 1e-5
     assert inf["flags"][0] & 8, "rank deficiency must be reported"
+    orth = np.abs(Uh.T @ Uh - np.eye(48)).max()
+    _say(f"  |U^T U - I| = {orth:.2e}")
+    assert orth < 1e-5
+    Uo, So, Vo, _ = oracle.svd(A.astype(np.float64))
+    sg = np.sign(np.sum(Uh[:, :20] * Uo[:, :20], axis=0))
+    assert np.abs(Uh[:, :20] * sg - Uo[:, :20]).max() < 1e-4
+    rec = np.linalg.norm((Uh * Sh) @ Vh.T - A) / np.linalg.norm(A)
+    assert rec < 1e-5
+
+
+def test_numerically_rank_deficient_is_completed(api):
+    # sigma down to 1e-9 relative: the smallest directions of W stay far
+    # from unit norm after CANS, so U is orthogonalised by QR
+    _say("96 x 64, sigma geometric 1 .. 1e-9")
+    A, s = inputs.batch_with_spectra(97, 3, 96, 64, lambda r: inputs.geometric(64, 1e9))
+    U, S, V, info = api.svd_fwd(dev(A))
+    inf = api.info_to_numpy(info)
+    Sh, Uh, Vh = (t.cpu().double().numpy() for t in (S, U, V))
+    for i in range(3):
+        orth = np.abs(Uh[i].T @ Uh[i] - np.eye(64)).max()
+        serr = np.abs(Sh[i] - s[i]).max() / s[i][0]
+        rec = np.linalg.norm((Uh[i] * Sh[i]) @ Vh[i].T - A[i]) / np.linalg.norm(A[i])
+        _say(f"  b={i} flags={inf['flags'][i]} |U^T U - I|={orth:.2e} s_err={serr:.2e} recon={rec:.2e}")
+        assert orth < 1e-5 and serr < 1e-5 and rec < 1e-5
 
 
 def test_workspace_and_argument_errors(api):
