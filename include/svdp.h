@@ -146,6 +146,7 @@ svdp_status svdp_set_model(svdp_handle* h, const float* host_model);
 #define SVDP_OP_POLAR_BWD 3
 #define SVDP_OP_EIGH 4
 #define SVDP_OP_FEATURES 5
+#define SVDP_OP_EIGH_BWD 6
 svdp_status svdp_workspace_size(const svdp_params* p, int32_t op, size_t* bytes);
 
 const char* svdp_status_string(svdp_status s);
@@ -216,6 +217,23 @@ svdp_status svdp_eigh(svdp_handle* h, const svdp_params* p,
                       float* lam, int64_t slam,
                       float* V, int64_t ldv, int64_t sV,
                       svdp_info* info, void* ws, size_t ws_bytes, void* stream);
+
+/* Backward of the symmetric eigendecomposition: the EVD pseudo-gradient
+ * (theorem on the EVD backward, Section 4.2) with the regularised K of the
+ * same section, K_ij = (l_i - l_j) / ((l_i - l_j)^2 + eps_K):
+ *   dH = V (S + diag(dlam)) V^T,  S = K^T o (V^T dV - dV^T V) / 2.
+ * eps_K = 0 gives K_ij = 1 / (l_i - l_j), and 0 for equal eigenvalues
+ * (rotations inside an eigenspace do not contribute).  lam, V: the forward
+ * eigenpairs (any order, as svdp_eigh returns them); dlam (batch x n) and
+ * dV (n x n) may be null (zero).  dH: n x n, symmetric.  Uses p->batch,
+ * p->n (m ignored), eps_K; workspace op SVDP_OP_EIGH_BWD. */
+svdp_status svdp_eigh_bwd(svdp_handle* h, const svdp_params* p,
+                          const float* lam, int64_t slam,
+                          const float* V, int64_t ldv, int64_t sV,
+                          const float* dlam, int64_t sdlam,
+                          const float* dV, int64_t lddv, int64_t sdV,
+                          float* dH, int64_t lddh, int64_t sdH,
+                          void* ws, size_t ws_bytes, void* stream);
 
 /* Sketch features of each matrix (the learned interval predictor's input).
  * probe: batch x n.  With y0 = probe, y1 = A y0, y2 = A^T y1, ... up to y7

@@ -11,9 +11,9 @@ Contents (each function cites the passage of the paper it follows):
   Algorithm 2 (polar backward), the classical full-rank SVD backward.
 * numpy part (FP64): the normalisation of the appendix on Newton-Schulz
   initialisation (Algorithm 3), the degree-3 CANS polynomial and its
-  interval recursion, the CANS polar iteration, the sketch features and the
-  small MLP (forward, backward, pinball loss, Adam) of the learned interval
-  predictor.
+  interval recursion, the CANS polar iteration, the symmetric EVD backward
+  (the EVD pseudo-gradient theorem), the sketch features and the small MLP
+  (forward, backward, pinball loss, Adam) of the learned interval predictor.
 
 Parity status: every function here is pinned by a ``-m "not gpu"`` test in
 ``tests/test_oracle_*.py`` against closed forms, invariants, brute force or
@@ -126,6 +126,31 @@ def polar_from_svd(U, S, V):
 # --------------------------------------------------------------------------
 # backward passes
 # --------------------------------------------------------------------------
+
+def eigh_bwd(lam, V, dlam=None, dV=None, eps_K: float = 0.0):
+    """Backward of the symmetric EVD H = V diag(lam) V^T: the EVD
+    pseudo-gradient theorem (Section 4.2), literal, in FP64.
+    K_ij = 1 / (lam_i - lam_j) when lam_i != lam_j and 0 otherwise; with
+    eps_K > 0 the regularised K_ij = (lam_i - lam_j) / ((lam_i - lam_j)^2 + eps_K)
+    of the same section (eps_K plays the role of eps^2).  Then
+    S = K^T o (V^T dV - dV^T V) / 2 and dH = V (S + diag(dlam)) V^T."""
+    lam = np.asarray(lam, dtype=np.float64)
+    V = np.asarray(V, dtype=np.float64)
+    n = lam.shape[0]
+    d = lam[:, None] - lam[None, :]
+    if eps_K > 0:
+        K = d / (d * d + eps_K)
+    else:
+        K = np.zeros((n, n))
+        nz = d != 0
+        K[nz] = 1.0 / d[nz]
+    np.fill_diagonal(K, 0.0)
+    P = np.zeros((n, n)) if dV is None else V.T @ np.asarray(dV, dtype=np.float64)
+    S = 0.5 * K.T * (P - P.T)
+    if dlam is not None:
+        S = S + np.diag(np.asarray(dlam, dtype=np.float64))
+    return V @ S @ V.T
+
 
 def paper_eps(eps: float, k_exponent: str = "alg4"):
     """Map the paper's single eps to the three absolute regularisers.

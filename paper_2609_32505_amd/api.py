@@ -204,6 +204,27 @@ def eigh(H, p=None, handle=None, **kw):
     return lam, V, info
 
 
+def eigh_bwd(lam, V, dlam=None, dV=None, p=None, handle=None, **kw):
+    """dH of the symmetric EVD H = V diag(lam) V^T (the EVD pseudo-gradient
+    theorem, regularised K with eps_K)."""
+    V = _batched(_req(V, "V"))
+    lam = _req(lam, "lam")
+    lam = lam if lam.dim() == 2 else lam.unsqueeze(0)
+    b, n, _ = V.shape
+    dlam = None if dlam is None else _req(dlam, "dlam")
+    if dlam is not None and dlam.dim() == 1:
+        dlam = dlam.unsqueeze(0)
+    dV = None if dV is None else _batched(_req(dV, "dV"))
+    h = handle or default_handle()
+    p = _prep_params(p, kw, b, n, n)
+    dH = torch.empty((b, n, n), device=V.device)
+    ws = _workspace(p, _lib.OP_EIGH_BWD, V.device)
+    check(load().svdp_eigh_bwd(h.ptr, ctypes.byref(p), lam.data_ptr(), n, V.data_ptr(), n, n * n,
+                               _p(dlam), n, _p(dV), n, n * n, dH.data_ptr(), n, n * n, ws.data_ptr(),
+                               ws.numel(), _stream()), "svdp_eigh_bwd")
+    return dH
+
+
 # ------------------------------------------------------------------ predictor
 
 def bound_features(A, probe, handle=None):

@@ -1,5 +1,6 @@
 """torch.autograd.Function wrappers: the forward and the backward both run
-in the library (Algorithm 4 for the SVD, Algorithm 2 for the polar factors).
+in the library (Algorithm 4 for the SVD, Algorithm 2 for the polar factors,
+the EVD pseudo-gradient theorem for the symmetric eigendecomposition).
 """
 from __future__ import annotations
 
@@ -59,6 +60,30 @@ class Polar(torch.autograd.Function):
         return (dA[0] if sq else dA), None
 
 
+class Eigh(torch.autograd.Function):
+    """(lam, V) with H = V diag(lam) V^T, lam descending."""
+
+    @staticmethod
+    def forward(ctx, H, opts):
+        H = H.contiguous()
+        lam, V, info = api.eigh(H, **opts)
+        ctx.save_for_backward(lam, V)
+        ctx.opts = {k: v for k, v in opts.items() if k == "eps_K"}
+        ctx.squeeze = H.dim() == 2
+        if ctx.squeeze:
+            return lam[0], V[0]
+        return lam, V
+
+    @staticmethod
+    def backward(ctx, dlam, dV):
+        lam, V = ctx.saved_tensors
+        sq = ctx.squeeze
+        def bat(t):
+            return None if t is None else (t.unsqueeze(0) if sq else t).contiguous()
+        dH = api.eigh_bwd(lam, V, bat(dlam), bat(dV), **ctx.opts)
+        return (dH[0] if sq else dH), None
+
+
 def svd(A, **opts):
     """Differentiable thin SVD of A (m >= n): returns (U, S, Vh)."""
     return SVD.apply(A, opts)
@@ -67,3 +92,8 @@ def svd(A, **opts):
 def polar(A, **opts):
     """Differentiable polar decomposition A = W H: returns (W, H)."""
     return Polar.apply(A, opts)
+
+
+def eigh(H, **opts):
+    """Differentiable symmetric eigendecomposition: returns (lam, V)."""
+    return Eigh.apply(H, opts)

@@ -617,6 +617,12 @@ svdp_status svdp_workspace_size(const svdp_params* p, int32_t op, size_t* bytes)
     case SVDP_OP_POLAR_FWD:
     case SVDP_OP_FEATURES: carve_fwd(nullptr, p, &total); break;
     case SVDP_OP_SVD_BWD: total = bwd_bytes(p, 0); break;
+    case SVDP_OP_EIGH_BWD: {
+      Carver c(nullptr);
+      c.take<float>((size_t)p->batch * p->n * p->n * 3);
+      total = c.off;
+      break;
+    }
     case SVDP_OP_POLAR_BWD: total = bwd_bytes(p, 1); break;
     case SVDP_OP_EIGH: {
       Carver c(nullptr);
@@ -718,6 +724,54 @@ svdp_status polar_fwd(svdp_handle* h, const svdp_params* p, const float* A, int6
   HIPCHK(symmetrize_launch(c.w.G, B, n, H, ldh, sH, c.st), "H out");
   HIPCHK(copy_launch(c.w.X0, n, (int64_t)m * n, c.w.where, c.w.X1, W, ldw, sW, B, m, n, c.st), "W out");
   if (info) HIPCHK(info_pack_launch(B, c.w.iters, c.w.sweeps, c.w.flags, c.w.resid, info, nullptr, c.st), "info");
+  return SVDP_OK;
+}
+
+svdp_status svdp_eigh_bwd(svdp_handle* h, const svdp_params* p, const float* lam, int64_t slam, const float* V,
+                          int64_t ldv, int64_t sV, const float* dlam, int64_t sdlam, const float* dV, int64_t lddv,
+                          int64_t sdV, float* dH, int64_t lddh, int64_t sdH, void* ws, size_t ws_bytes, void* stream) {
+  REQ(h);
+  svdp_params q = *p;
+  q.m = q.n;
+  svdp_status s = check_common(&q);
+  if (s) return s;
+  if (q.batch == 0) return SVDP_OK;
+  REQ(lam); REQ(V); REQ(dH);
+  const int B = (int)q.batch, n = (int)q.n;
+  LDCHK(ldv, n, B > 1 ? sV : 0, n);
+  LDCHK(lddh, n, B > 1 ? sdH : 0, n);
+  if (dV) LDCHK(lddv, n, B > 1 ? sdV : 0, n);
+  size_t need = 0;
+  svdp_workspace_size(&q, SVDP_OP_EIGH_BWD, &need);
+  if (!ws || ws_bytes < need) return fail(SVDP_ERR_WORKSPACE, "workspace too small");
+  hipStream_t st = (hipStream_t)stream;
+  Carver c(ws);
+  float* P = c.take<float>((size_t)B * n * n);
+  float* C = c.take<float>((size_t)B * n * n);
+  float* T = c.take<float>((size_t)B * n * n);
+  if (dV) {  // P = V^T dV
+    GemmArgs g = gemm_base(n, n, n, B);
+    g.A = V; g.lda = ldv; g.sA = sV;
+    g.B = dV; g.ldb = lddv; g.sB = sdV;
+    g.C = P; g.ldc = n; g.sC = (int64_t)n * n;
+    HIPCHK(gemm_launch(g, PREC_F32, 1, 0, st), "V^T dV");
+  }
+  HIPCHK(sylvester_launch(2, nullptr, dV ? P : nullptr, lam, slam, dlam, sdlam, nullptr, B, n, q.eps_K, 0.0, C, st),
+         "eigh bwd scaling");
+  {  // T = V C
+    GemmArgs g = gemm_base(n, n, n, B);
+    g.A = V; g.lda = ldv; g.sA = sV;
+    g.B = C; g.ldb = n; g.sB = (int64_t)n * n;
+    g.C = T; g.ldc = n; g.sC = (int64_t)n * n;
+    HIPCHK(gemm_launch(g, PREC_F32, 0, 0, st), "V C");
+  }
+  {  // dH = T V^T
+    GemmArgs g = gemm_base(n, n, n, B);
+    g.A = T; g.lda = n; g.sA = (int64_t)n * n;
+    g.B = V; g.ldb = ldv; g.sB = sV;
+    g.C = dH; g.ldc = lddh; g.sC = sdH;
+    HIPCHK(gemm_launch(g, PREC_F32, 0, 1, st), "T V^T");
+  }
   return SVDP_OK;
 }
 

@@ -295,6 +295,9 @@ SVDP_DEV double reg_ratio(double x, double e) {
 // 32 x 32 output tile per workgroup (256 threads, 4 entries each); the tile
 // at (I, J) and its transpose partner (J, I) of both inputs go through LDS so
 // all global reads are row-contiguous.
+// mode 0: SVD (Algorithm 4 in the eigenbasis); mode 1: polar (Algorithm 2);
+// mode 2: symmetric EVD (the EVD pseudo-gradient theorem, regularised K),
+// S = sigma (the eigenvalues), dS = their incoming gradient.
 __global__ void k_sylvester(int mode, const float* X1, const float* X2, const float* S, int64_t sS,
                             const float* dS, int64_t sdS, const float* D, int n, double eK,
                             double eT, float* out) {
@@ -317,7 +320,7 @@ __global__ void k_sylvester(int mode, const float* X1, const float* X2, const fl
     const int i = I0 + r, j = J0 + tx;
     if (i >= n || j >= n) continue;
     const double si = S[b * sS + i], sj = S[b * sS + j];
-    const double Di = D[(int64_t)b * n + i], Dj = D[(int64_t)b * n + j];
+    const double Di = D ? D[(int64_t)b * n + i] : 0.0, Dj = D ? D[(int64_t)b * n + j] : 0.0;  // null in mode 2
     // element (i, j) of input X is *_ij[r][tx]; element (j, i) is *_ji[tx][r]
     const double x1ij = a_ij[r][tx], x1ji = a_ji[tx][r];
     const double x2ij = p_ij[r][tx], x2ji = p_ji[tx][r];
@@ -330,11 +333,16 @@ __global__ void k_sylvester(int mode, const float* X1, const float* X2, const fl
       if (i == j && dS) c += dS[b * sdS + i];
       double t = reg_ratio(si + sj, eT);
       out[base + (int64_t)i * n + j] = (float)(si * t * c);
-    } else {
+    } else if (mode == 1) {
       // X1 = V^T dH V, X2 = (M V)^T (dW V)
       c = 0.5 * (x1ij + x1ji) - 0.5 * Di * Dj * (x2ij + x2ji);
       double t = reg_ratio(si + sj, eT);
       out[base + (int64_t)i * n + j] = (float)(t * c);
+    } else {
+      // EVD: X2 = V^T dV; S = K^T o (P - P^T) / 2 + diag(dlam)
+      c = 0.5 * reg_ratio(sj - si, eK) * (x2ij - x2ji);
+      if (i == j && dS) c += dS[b * sdS + i];
+      out[base + (int64_t)i * n + j] = (float)c;
     }
   }
 }

@@ -251,3 +251,94 @@ def test_lyapunov_identity_on_oracle_solution(orc):
     np.testing.assert_allclose(H @ X + X @ H, B, atol=1e-12)
     np.testing.assert_allclose(H @ Y + Y @ H, A, atol=1e-12)
     assert np.sum(A * X) == pytest.approx(np.sum(Y * B), rel=1e-12)
+
+
+# ---------------------------------------------------------------- EVD backward
+
+def _sym(rng, n):
+    X = rng.standard_normal((n, n))
+    return 0.5 * (X + X.T)
+
+
+def test_eigh_bwd_eigenvalue_gradient_closed_form_and_fd(orc):
+    # d lambda_k / dH = v_k v_k^T; checked against central differences of
+    # LAPACK eigenvalues along random symmetric directions
+    rng = np.random.default_rng(41)
+    H = _sym(rng, 7)
+    lam, V = np.linalg.eigh(H)
+    for k in (0, 3, 6):
+        e = np.zeros(7); e[k] = 1.0
+        g = orc.eigh_bwd(lam, V, dlam=e)
+        np.testing.assert_allclose(g, np.outer(V[:, k], V[:, k]), atol=1e-14)
+        for _ in range(3):
+            E = _sym(rng, 7)
+            h = 1e-6
+            fd = (np.linalg.eigvalsh(H + h * E)[k] - np.linalg.eigvalsh(H - h * E)[k]) / (2 * h)
+            assert abs(fd - np.sum(g * E)) < 1e-7
+
+
+def test_eigh_bwd_sign_invariant_loss_vs_fd(orc):
+    # L = sum_i w_i (v_i^T a)^2 + sum_i g_i lambda_i, distinct eigenvalues:
+    # dL/dv_i = 2 w_i (v_i^T a) a, dL/dlambda = g
+    rng = np.random.default_rng(42)
+    n = 6
+    H = _sym(rng, n)
+    a, w, g = rng.standard_normal(n), rng.standard_normal(n), rng.standard_normal(n)
+
+    def loss(M):
+        l, Q = np.linalg.eigh(M)
+        return np.sum(w * (Q.T @ a) ** 2) + np.sum(g * l)
+
+    lam, V = np.linalg.eigh(H)
+    dV = 2.0 * a[:, None] * (w * (V.T @ a))[None, :]
+    G = orc.eigh_bwd(lam, V, dlam=g, dV=dV)
+    np.testing.assert_allclose(G, G.T, atol=1e-13)
+    for _ in range(6):
+        E = _sym(rng, n)
+        E /= np.linalg.norm(E)
+        h = 1e-5
+        fd = (loss(H + h * E) - loss(H - h * E)) / (2 * h)
+        assert abs(fd - np.sum(G * E)) < 1e-6 * max(1.0, abs(fd))
+
+
+def test_eigh_bwd_regularised_tends_to_exact(orc):
+    rng = np.random.default_rng(43)
+    H = _sym(rng, 8)
+    lam, V = np.linalg.eigh(H)
+    dV, dl = rng.standard_normal((8, 8)), rng.standard_normal(8)
+    g0 = orc.eigh_bwd(lam, V, dl, dV)
+    g1 = orc.eigh_bwd(lam, V, dl, dV, eps_K=1e-16)
+    np.testing.assert_allclose(g1, g0, rtol=1e-6, atol=1e-9)
+    # a large regulariser damps the rotation part: K -> d / eps for eps >> d^2
+    g2 = orc.eigh_bwd(lam, V, dl, dV, eps_K=1e6)
+    np.testing.assert_allclose(g2, V @ np.diag(dl) @ V.T, atol=1e-4)
+
+
+def test_eigh_bwd_repeated_eigenvalue_invariant_loss_vs_fd(orc):
+    # lambda_1 = lambda_2: L = sum over the cluster of (v_i^T a)^2 (the
+    # projector onto the eigenspace, rotation invariant) + the third
+    # eigenvector's term; the pseudo-gradient (K = 0 inside the cluster) is
+    # the true gradient of such a loss
+    rng = np.random.default_rng(44)
+    Q, _ = np.linalg.qr(rng.standard_normal((5, 5)))
+    lam0 = np.array([-1.0, 0.5, 0.5, 2.0, 3.0])
+    H = (Q * lam0) @ Q.T
+    a = rng.standard_normal(5)
+
+    def loss(M):
+        l, V = np.linalg.eigh(M)
+        c = V[:, 1:3].T @ a
+        return np.sum(c ** 2) + 0.3 * (V[:, 3] @ a) ** 2
+
+    lam, V = np.linalg.eigh(H)
+    lam[1:3] = 0.5  # exactly repeated in the factors handed to the backward
+    dV = np.zeros((5, 5))
+    dV[:, 1:3] = 2.0 * a[:, None] * (V[:, 1:3].T @ a)[None, :]
+    dV[:, 3] = 0.6 * a * (V[:, 3] @ a)
+    G = orc.eigh_bwd(lam, V, None, dV)
+    for _ in range(5):
+        E = _sym(rng, 5)
+        E /= np.linalg.norm(E)
+        h = 1e-6
+        fd = (loss(H + h * E) - loss(H - h * E)) / (2 * h)
+        assert abs(fd - np.sum(G * E)) < 1e-6
