@@ -83,7 +83,8 @@ typedef struct {
   int32_t max_sweeps;      /* Jacobi sweep cap (20) */
   int32_t inner_sweeps;    /* repetitions of a block step's scalar rounds per 32 x 32 Jacobi
                               subproblem (1) */
-  int32_t fp64_sweeps;     /* final Jacobi sweeps with FP64 subproblem solves (1) */
+  int32_t fp64_sweeps;     /* final Jacobi sweeps with FP64 subproblem solves, and the sweeps of
+                              each restart (1) */
   double delta;            /* CANS preprocessing target [1-delta, 1+delta] (0.99) */
   double tol;              /* CANS stop: |X_k+1 - X_k|_F <= tol |X_k+1|_F (1e-5) */
   double eps_qr;           /* column-norm tolerance of U (1e-5) */
@@ -111,6 +112,10 @@ typedef struct {
                               finished by the refinement's stop test) */
   const float* user_bounds; /* device, batch x 2 (sigma_min, sigma_max), bound == USER */
   const float* probe;      /* device, batch x n Gaussian probe vectors, bound == LEARNED */
+  double eigh_off_tol;     /* eigensolver restarts: T = V^T H V is re-formed from the input and
+                              swept again from V' = I (V <- V V') while |off(T)|_F > eigh_off_tol
+                              |H|_F; the last T gives the eigenvalues (1e-5) */
+  int32_t eigh_restarts;   /* cap on those restarts (2) */
 } svdp_params;
 
 /* per-matrix diagnostics, device array of `batch` records */
@@ -211,7 +216,7 @@ svdp_status polar_bwd(svdp_handle* h, const svdp_params* p,
 /* Symmetric eigendecomposition H = V diag(lam) V^T (the EVD step of
  * Algorithm 1) by batched block Jacobi; lam descending (signed), V n x n.
  * Uses p->batch, p->n (m ignored), max_sweeps, inner_sweeps, fp64_sweeps,
- * jacobi_tol, jacobi_abs.  info: sweeps and flags (may be null). */
+ * jacobi_tol, jacobi_abs, eigh_off_tol, eigh_restarts.  info: sweeps and flags (may be null). */
 svdp_status svdp_eigh(svdp_handle* h, const svdp_params* p,
                       const float* H, int64_t ldh, int64_t sH,
                       float* lam, int64_t slam,

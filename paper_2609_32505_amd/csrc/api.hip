@@ -120,6 +120,9 @@ svdp_status check_common(const svdp_params* p) {
   if (p->max_sweeps < 1 || p->max_sweeps > 100) return fail(SVDP_ERR_INVALID_ARG, "max_sweeps must be in [1, 100]");
   if (p->inner_sweeps < 1 || p->inner_sweeps > 16) return fail(SVDP_ERR_INVALID_ARG, "inner_sweeps must be in [1, 16]");
   if (p->fp64_sweeps < 0 || p->fp64_sweeps > 4) return fail(SVDP_ERR_INVALID_ARG, "fp64_sweeps must be in [0, 4]");
+  if (p->eigh_restarts < 0 || p->eigh_restarts > 8)
+    return fail(SVDP_ERR_INVALID_ARG, "eigh_restarts must be in [0, 8]");
+  if (!(p->eigh_off_tol >= 0)) return fail(SVDP_ERR_INVALID_ARG, "eigh_off_tol must be >= 0");
   if (!(p->delta > 0 && p->delta < 1)) return fail(SVDP_ERR_INVALID_ARG, "delta must be in (0, 1)");
   if (!(p->tol > 0)) return fail(SVDP_ERR_INVALID_ARG, "tol must be > 0");
   if (p->eps_K < 0 || p->eps_R < 0 || p->eps_T < 0) return fail(SVDP_ERR_INVALID_ARG, "eps must be >= 0");
@@ -134,6 +137,8 @@ EighOpts eigh_opts(const svdp_params* p) {
   o.tol = (float)p->jacobi_tol;
   o.abs_tol = (float)p->jacobi_abs;
   o.neg_tol = 1e-4f;
+  o.off_tol = (float)p->eigh_off_tol;
+  o.restarts = p->eigh_restarts;
   return o;
 }
 
@@ -518,6 +523,8 @@ void svdp_default_params(svdp_params* p, int64_t batch, int64_t m, int64_t n) {
   p->bf16_from = 0.1;
   p->margin_max = 1.1;
   p->margin_min = 1.0;
+  p->eigh_off_tol = 1e-5;
+  p->eigh_restarts = 2;
 }
 
 const char* svdp_status_string(svdp_status s) {

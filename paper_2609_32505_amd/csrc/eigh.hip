@@ -29,6 +29,12 @@
 // Convergence is tested per matrix on the largest relative off-diagonal
 // entry rotated during a sweep; converged matrices are skipped by later
 // launches.
+// Restarts.  Every block rotation rounds H and V separately, so after many
+// sweeps V no longer diagonalises the input to FP32 accuracy (the backward
+// error grows with the number of rotations, i.e. with n).  T = V^T H V is
+// therefore re-formed from the input by two GEMMs and measured; if its
+// off-diagonal part is too large, T is swept again from V' = I, whose
+// rotations are small, and V <- V V'.
 #include <algorithm>
 #include <cstring>
 #include <vector>
@@ -507,11 +513,14 @@ __global__ __launch_bounds__(256) void k_jac_apply(EighWs e, EighPhase ph) {
   }
 }
 
+// what k_eigh_setup writes: V = I (tiled), the upper tiles of sym(H), |H|_F^2
+constexpr int kSetupV = 1, kSetupH = 2, kSetupNorm = 4;
+
 // Tiled working copies: H (tiles on and above the diagonal, symmetrised,
 // zero padding), V = I, |H|_F^2.  One 64 x 64 block (Ib, Jb) of tiles per
 // workgroup: the block and its mirror are read row-contiguous into LDS.
 __global__ __launch_bounds__(256) void k_eigh_setup(EighWs e, const float* Hin, int64_t ldh, int64_t sH,
-                                                    const int* mask) {
+                                                    const int* mask, int what) {
   const int b = blockIdx.y;
   if (mask && !mask[b]) return;
   __shared__ float Ablk[GS][GP];
@@ -520,15 +529,16 @@ __global__ __launch_bounds__(256) void k_eigh_setup(EighWs e, const float* Hin, 
   const int Ib = blockIdx.x / nq, Jb = blockIdx.x - Ib * nq;
   const int t = threadIdx.x;
   float* Vb = e.Vw + (int64_t)b * e.np * e.np;
-  for (int idx = t; idx < 16 * 64; idx += 256) {
-    const int tile = idx >> 6, qd = idx & 63, I = 4 * Ib + (tile >> 2), J = 4 * Jb + (tile & 3);
-    const int r = qd >> 2, c = (qd & 3) * 4;
-    f4v v;
+  if (what & kSetupV)
+    for (int idx = t; idx < 16 * 64; idx += 256) {
+      const int tile = idx >> 6, qd = idx & 63, I = 4 * Ib + (tile >> 2), J = 4 * Jb + (tile & 3);
+      const int r = qd >> 2, c = (qd & 3) * 4;
+      f4v v;
 #pragma unroll
-    for (int w2 = 0; w2 < 4; ++w2) v[w2] = (I == J && r == c + w2) ? 1.f : 0.f;
-    *(f4v*)(Vb + tile_off(I, J, e.nb) + qd * 4) = v;
-  }
-  if (Ib > Jb) return;  // whole workgroup: H keeps the upper tiles only
+      for (int w2 = 0; w2 < 4; ++w2) v[w2] = (I == J && r == c + w2) ? 1.f : 0.f;
+      *(f4v*)(Vb + tile_off(I, J, e.nb) + qd * 4) = v;
+    }
+  if (!(what & kSetupH) || Ib > Jb) return;  // whole workgroup: H keeps the upper tiles only
   const float* Hb = Hin + b * sH;
   for (int idx = t; idx < GS * GS; idx += 256) {
     const int r = idx >> 6, c = idx & 63;
@@ -554,6 +564,7 @@ __global__ __launch_bounds__(256) void k_eigh_setup(EighWs e, const float* Hin, 
     }
     *(f4v*)(Hw + tile_off(I, J, e.nb) + qd * 4) = v;
   }
+  if (!(what & kSetupNorm)) return;
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
   if ((t & 63) == 0) atomicAdd(e.hnorm2 + b, acc);
 }
@@ -666,17 +677,70 @@ __global__ void k_eigh_permute(EighWs e, const int* perm, float* Vout, int64_t l
   for (int c = threadIdx.x; c < e.n; c += blockDim.x) out[c] = Vw[pb[c]];
 }
 
-// lamr[b, i] = v_i^T (H0 v_i) with T = H0 V in Hw (FP64 accumulation)
-__global__ void k_rayleigh(EighWs e, const int* mask) {
+// Restart measure of T = V^T H0 V (row-major, leading dimension np) for the
+// matrices of `proc`.  H0 may be unsymmetric (H = W^T A); the measure uses
+// the symmetric part S = (T + T^T) / 2: off2[b] += sum_{i != j} S_ij^2 (FP64)
+// over the 32 x 32 tile pairs (I <= J) this workgroup takes, and the
+// diagonal tiles give lamr = diag(T), the Rayleigh quotients of V's columns.
+__global__ __launch_bounds__(256) void k_restart_offnorm(EighWs e, const float* T, const int* proc) {
   const int b = blockIdx.y;
-  if (mask && !mask[b]) return;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= e.n) return;
-  const float* V = e.V2 + (int64_t)b * e.np * e.np;
-  const float* T = e.Hw + (int64_t)b * e.np * e.np;
-  double s = 0.0;
-  for (int j = 0; j < e.n; ++j) s += (double)V[(int64_t)j * e.np + i] * (double)T[(int64_t)j * e.np + i];
-  e.lamr[(int64_t)b * e.n + i] = (float)s;
+  if (proc && !proc[b]) return;
+  __shared__ float X[32][33], Y[32][33];
+  __shared__ double red[4];
+  const int n = e.n, nt = (n + 31) / 32, npairs = nt * (nt + 1) / 2;
+  const float* Tb = T + (int64_t)b * e.np * e.np;
+  const int t = threadIdx.x, r = t >> 3, c0 = (t & 7) * 4;
+  double acc = 0.0;
+  for (int p = blockIdx.x; p < npairs; p += gridDim.x) {
+    int I = 0, rem = p;  // p -> (I, J), I <= J, row by row over the upper triangle
+    while (rem >= nt - I) { rem -= nt - I; ++I; }
+    const int J = I + rem;
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      const int c = c0 + w;
+      const int i1 = 32 * I + r, j1 = 32 * J + c, i2 = 32 * J + r, j2 = 32 * I + c;
+      X[r][c] = (i1 < n && j1 < n) ? Tb[(int64_t)i1 * e.np + j1] : 0.f;
+      Y[r][c] = (i2 < n && j2 < n) ? Tb[(int64_t)i2 * e.np + j2] : 0.f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      const int c = c0 + w;
+      const double sv = 0.5 * ((double)X[r][c] + (double)Y[c][r]);
+      if (I != J) acc += 2.0 * sv * sv;
+      else if (r != c) acc += sv * sv;
+      else if (32 * I + r < n) e.lamr[(int64_t)b * n + 32 * I + r] = X[r][c];
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  if ((t & 63) == 0) red[t >> 6] = acc;
+  __syncthreads();
+  if (t == 0) atomicAdd(e.off2 + b, red[0] + red[1] + red[2] + red[3]);
+}
+
+// After a restart measure: a matrix of `proc` stays active for another sweep
+// of T when off2 > off_tol2 |H0|_F^2 and `last` is 0 (the others leave the
+// active set); *counter gains the number of active matrices.
+__global__ void k_restart_decide(EighWs e, const int* proc, float off_tol2, int last, int* counter) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= e.batch) return;
+  int act = 0;
+  if (!proc || proc[b]) act = !last && e.off2[b] > (double)off_tol2 * (double)e.hnorm2[b];
+  e.active[b] = act;
+  if (act) atomicAdd(counter, 1);
+}
+
+// dst[b][:n, :n] = src[b][:n, :n] (leading dimension np) for the active matrices
+__global__ void k_copy_active(const float* src, float* dst, int n, int np, const int* active) {
+  const int b = blockIdx.y;
+  if (!active[b]) return;
+  const int64_t off = (int64_t)b * np * np;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < (int64_t)n * n;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = k / n, j = k - i * n;
+    dst[off + i * np + j] = src[off + i * np + j];
+  }
 }
 
 __global__ void k_flag_active(const int* active, int batch, int* flags, int f) {
@@ -729,9 +793,10 @@ size_t eigh_ws_bytes(int64_t batch, int64_t n, int max_sweeps) {
   f += batch * n;                    // lamr
   f += batch * ng * QSTRIDE;         // Qw
   f += batch;                        // hnorm2
+  f += 2 * batch;                    // off2 (FP64)
   f += 2 * batch * n;                // sign, (perm as int)
   size_t i = batch * (size_t)(max_sweeps + 2) + batch + 16;  // rotcnt, active, counters
-  return (f + i) * 4 + 12 * 256;
+  return (f + i) * 4 + 16 * 256;
 }
 
 EighWs eigh_ws_carve(void* ws, int64_t batch, int64_t n, int max_sweeps) {
@@ -749,6 +814,7 @@ EighWs eigh_ws_carve(void* ws, int64_t batch, int64_t n, int max_sweeps) {
   e.lamr = (float*)take(batch * n * 4);
   e.Qw = (float*)take(batch * ng * QSTRIDE * 4);
   e.hnorm2 = (float*)take(batch * 4);
+  e.off2 = (double*)take(batch * 8);
   e.sgn = (float*)take(batch * n * 4);
   e.perm = (int*)take(batch * n * 4);
   e.rotcnt = (int*)take(batch * (size_t)(max_sweeps + 2) * 4);
@@ -794,6 +860,7 @@ static EighWs eigh_sub(const EighWs& e, int b0, int cnt, int h) {
   s.lamr += (int64_t)b0 * e.n;
   s.Qw += b0 * ng * QSTRIDE;
   s.hnorm2 += b0;
+  s.off2 += b0;
   s.sgn += (int64_t)b0 * e.n;
   s.perm += (int64_t)b0 * e.n;
   s.active += b0;
@@ -812,7 +879,8 @@ hipError_t eigh_run(EighWs e, const float* H, int64_t ldh, int64_t sH, int mode,
   if ((err = fill_i32(e.rotcnt, 0, (int64_t)batch * (e.max_sweeps + 2), st))) return err;
   if (mask) { if ((err = copy_i32(e.active, mask, batch, st))) return err; }
   else if ((err = fill_i32(e.active, 1, batch, st))) return err;
-  hipLaunchKernelGGL(k_eigh_setup, dim3((e.nb / 4) * (e.nb / 4), batch), dim3(256), 0, st, e, H, ldh, sH, mask);
+  hipLaunchKernelGGL(k_eigh_setup, dim3((e.nb / 4) * (e.nb / 4), batch), dim3(256), 0, st, e, H, ldh, sH, mask,
+                     kSetupV | kSetupH | kSetupNorm);
   if ((err = hipGetLastError())) return err;
   const int ng = e.nb / 4;
   const int nH = ng * (ng - 1) / 2;
@@ -925,46 +993,110 @@ hipError_t eigh_run(EighWs e, const float* H, int64_t ldh, int64_t sH, int mode,
     for (int f = 0; f < o.fp64_sweeps; ++f)
       if ((err = sweep_launches(true, nullptr, bc))) return err;
   }
-  if (P > 1)
+  auto join = [&]() -> hipError_t {
+    hipError_t e2;
     for (int h = 1; h < P; ++h) {
-      if ((err = hipEventRecord(aux->join[h], ss[h]))) return err;
-      if ((err = hipStreamWaitEvent(st, aux->join[h], 0))) return err;
+      if ((e2 = hipEventRecord(aux->join[h], ss[h]))) return e2;
+      if ((e2 = hipStreamWaitEvent(st, aux->join[h], 0))) return e2;
     }
+    return hipSuccess;
+  };
+  if ((err = join())) return err;
+  const int np = e.np;
+  const int64_t m2 = (int64_t)np * np;
   // V (tiled) -> row-major in Hw; one Newton-Schulz step re-orthonormalises
-  // it, V2 = V (3 I - V^T V) / 2 (V^T V in Vw); the eigenvalues are the
-  // Rayleigh quotients v_i^T H v_i against the input matrix (H V2 in Hw).
+  // it, V2 = V (3 I - V^T V) / 2 (V^T V in Vw)
   {
-    const int np = e.np;
-    const int64_t nq = (int64_t)np * np / 4;
+    const int64_t nq = m2 / 4;
     hipLaunchKernelGGL(k_untile, dim3(cdiv(nq, 256), batch), dim3(256), 0, st, e.Vw, e.Hw, np, e.nb, mask);
     if ((err = hipGetLastError())) return err;
     GemmArgs g;
     memset(&g, 0, sizeof(g));
     g.M = np; g.N = np; g.K = np; g.batch = batch;
-    g.A = e.Hw; g.lda = np; g.sA = (int64_t)np * np;
-    g.B = e.Hw; g.ldb = np; g.sB = (int64_t)np * np;
-    g.C = e.Vw; g.ldc = np; g.sC = (int64_t)np * np;
+    g.A = e.Hw; g.lda = np; g.sA = m2;
+    g.B = e.Hw; g.ldb = np; g.sB = m2;
+    g.C = e.Vw; g.ldc = np; g.sC = m2;
     g.alpha = 1.f; g.sym = 1; g.active = mask;
     if ((err = gemm_launch(g, PREC_F32, 1, 0, st))) return err;
     GemmArgs u;
     memset(&u, 0, sizeof(u));
     u.M = np; u.N = np; u.K = np; u.batch = batch;
-    u.A = e.Hw; u.lda = np; u.sA = (int64_t)np * np;
-    u.B = e.Vw; u.ldb = np; u.sB = (int64_t)np * np;
-    u.C = e.V2; u.ldc = np; u.sC = (int64_t)np * np;
-    u.Cin = e.Hw; u.ldcin = np; u.sCin = (int64_t)np * np;
+    u.A = e.Hw; u.lda = np; u.sA = m2;
+    u.B = e.Vw; u.ldb = np; u.sB = m2;
+    u.C = e.V2; u.ldc = np; u.sC = m2;
+    u.Cin = e.Hw; u.ldcin = np; u.sCin = m2;
     u.alpha = -0.5f; u.beta = 1.5f; u.active = mask;
     if ((err = gemm_launch(u, PREC_F32, 0, 0, st))) return err;
-    GemmArgs r;
-    memset(&r, 0, sizeof(r));
-    r.M = e.n; r.N = e.n; r.K = e.n; r.batch = batch;
-    r.A = H; r.lda = ldh; r.sA = sH;
-    r.B = e.V2; r.ldb = np; r.sB = (int64_t)np * np;
-    r.C = e.Hw; r.ldc = np; r.sC = (int64_t)np * np;
-    r.alpha = 1.f; r.active = mask;
-    if ((err = gemm_launch(r, PREC_F32, 0, 0, st))) return err;
-    hipLaunchKernelGGL(k_rayleigh, dim3(cdiv(e.n, 256), batch), dim3(256), 0, st, e, mask);
-    if ((err = hipGetLastError())) return err;
+  }
+  // Restarts.  T = V^T H V is formed from the input (H V in Hw, T in Vw):
+  // its diagonal holds the eigenvalues (Rayleigh quotients) and its
+  // off-diagonal norm the backward error of the decomposition, which the
+  // rounding of many FP32 block rotations raises with n.  While that norm
+  // exceeds off_tol |H|_F, T itself is swept from V' = I -- its rotations are
+  // small, so they add little rounding -- and V <- V V'.
+  {
+    const int* proc = mask;
+    const int nt = (e.n + 31) / 32, npairs = nt * (nt + 1) / 2;
+    const int chunks = std::max(1, std::min(npairs, cdiv(2048, batch)));
+    const float tol2 = o.off_tol * o.off_tol;
+    for (int r = 0;; ++r) {
+      const int last = r >= o.restarts;
+      GemmArgs y;
+      memset(&y, 0, sizeof(y));
+      y.M = e.n; y.N = e.n; y.K = e.n; y.batch = batch;
+      y.A = H; y.lda = ldh; y.sA = sH;
+      y.B = e.V2; y.ldb = np; y.sB = m2;
+      y.C = e.Hw; y.ldc = np; y.sC = m2;
+      y.alpha = 1.f; y.active = proc;
+      if ((err = gemm_launch(y, PREC_F32, 0, 0, st))) return err;
+      GemmArgs tt;
+      memset(&tt, 0, sizeof(tt));
+      tt.M = e.n; tt.N = e.n; tt.K = e.n; tt.batch = batch;
+      tt.A = e.V2; tt.lda = np; tt.sA = m2;
+      tt.B = e.Hw; tt.ldb = np; tt.sB = m2;
+      tt.C = e.Vw; tt.ldc = np; tt.sC = m2;
+      tt.alpha = 1.f; tt.active = proc;
+      if ((err = gemm_launch(tt, PREC_F32, 1, 0, st))) return err;
+      if ((err = fill_f32((float*)e.off2, 0.f, 2 * (int64_t)batch, st))) return err;
+      if ((err = fill_i32(e.counter, 0, 1, st))) return err;
+      hipLaunchKernelGGL(k_restart_offnorm, dim3(chunks, batch), dim3(256), 0, st, e, e.Vw, proc);
+      if ((err = hipGetLastError())) return err;
+      hipLaunchKernelGGL(k_restart_decide, dim3(cdiv(batch, 256)), dim3(256), 0, st, e, proc, tol2, last,
+                         e.counter);
+      if ((err = hipGetLastError())) return err;
+      if (last) break;
+      if ((err = hipMemcpyAsync(host_counter, e.counter, sizeof(int), hipMemcpyDeviceToHost, st))) return err;
+      if ((err = hipStreamSynchronize(st))) return err;
+      if (host_counter[0] == 0) break;
+      proc = e.active;
+      const dim3 sgrid((e.nb / 4) * (e.nb / 4), batch);
+      hipLaunchKernelGGL(k_eigh_setup, sgrid, dim3(256), 0, st, e, e.Vw, (int64_t)np, m2, proc, kSetupH);
+      if ((err = hipGetLastError())) return err;
+      hipLaunchKernelGGL(k_eigh_setup, sgrid, dim3(256), 0, st, e, (const float*)nullptr, (int64_t)0, (int64_t)0,
+                         proc, kSetupV);
+      if ((err = hipGetLastError())) return err;
+      if (P > 1) {
+        if ((err = hipEventRecord(aux->fork, st))) return err;
+        for (int h = 1; h < P; ++h)
+          if ((err = hipStreamWaitEvent(ss[h], aux->fork, 0))) return err;
+      }
+      for (int f = 0; f < std::max(1, o.fp64_sweeps); ++f)
+        if ((err = sweep_launches(o.fp64_sweeps > 0, nullptr, bc))) return err;
+      if ((err = join())) return err;
+      hipLaunchKernelGGL(k_untile, dim3(cdiv(m2 / 4, 256), batch), dim3(256), 0, st, e.Vw, e.Hw, np, e.nb, proc);
+      if ((err = hipGetLastError())) return err;
+      GemmArgs v;
+      memset(&v, 0, sizeof(v));
+      v.M = e.n; v.N = e.n; v.K = e.n; v.batch = batch;
+      v.A = e.V2; v.lda = np; v.sA = m2;
+      v.B = e.Hw; v.ldb = np; v.sB = m2;
+      v.C = e.Vw; v.ldc = np; v.sC = m2;
+      v.alpha = 1.f; v.active = proc;
+      if ((err = gemm_launch(v, PREC_F32, 0, 0, st))) return err;
+      const unsigned cgrid = (unsigned)std::min<int64_t>(cdiv((int64_t)e.n * e.n, 256), 1024);
+      hipLaunchKernelGGL(k_copy_active, dim3(cgrid, batch), dim3(256), 0, st, e.Vw, e.V2, e.n, np, proc);
+      if ((err = hipGetLastError())) return err;
+    }
   }
   {
     int P2 = 1;

@@ -11,6 +11,7 @@ struct EighWs {
   float* lamr;    // batch x n Rayleigh-quotient eigenvalues
   float* Qw;      // batch x (nb/4) x (64 x 64 group rotation + 2 x 32 x 32 step-A rotations)
   float* hnorm2;  // batch: |H|_F^2
+  double* off2;   // batch: |off(sym(V^T H V))|_F^2 of the last restart measure
   float* sgn;     // batch x n: sign of each sorted eigenvalue
   int* perm;      // batch x n: sorted position -> working column
   int* rotcnt;    // batch x (max_sweeps + 2): largest relative entry rotated (float bits)
@@ -37,6 +38,8 @@ struct EighOpts {
                      // sweep, the FP64 one, leaves ~tol^2)
   float abs_tol;     // entries below abs_tol |H|_F do not count
   float neg_tol;     // NEG_EIGENVALUE when lam_min < -neg_tol max|lam| (mode 1)
+  float off_tol;     // restarts end once |off(V^T H V)|_F <= off_tol |H|_F
+  int restarts;      // cap on restarts (re-formed V^T H V swept again from I)
 };
 
 // Extra streams and events: the sweeps run parts of the batch on the

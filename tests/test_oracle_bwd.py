@@ -231,6 +231,34 @@ def test_tikhonov_keeps_gradient_finite_at_tiny_gap(orc):
     assert norms[1e-12][1] < 1e5
 
 
+def test_gradient_norm_matches_closed_form_expectation(orc):
+    # Table 3's loss <A, U> + <B, Sigma> + <C, V> with i.i.d. N(0, 1) A, B, C:
+    # at a square full-rank M the classical gradient is
+    # U [F o (X - X^T) S + diag(B) + S F o (Y - Y^T)] V^T, F_ij = 1/(s_j^2 - s_i^2),
+    # X = U^T A and Y = V^T C i.i.d. Gaussian again, so
+    # E |dM|_F^2 = n + sum_{i != j} 2 (s_i^2 + s_j^2) / (s_i^2 - s_j^2)^2.
+    # A Monte-Carlo mean of the oracle's Algorithm 4 must reach it.
+    n = 24
+    s = np.arange(1.0, n + 1.0)
+    s[-1] = n - 1 + 0.5  # the spectral-gap scheme, gap 0.5
+    M = inputs.matrix_with_spectrum(inputs.rng_for(31, 0), n, n, s)
+    U, S, V, _ = orc.svd(M)
+    s2 = S ** 2
+    d = s2[:, None] - s2[None, :]
+    np.fill_diagonal(d, 1.0)
+    t = 2.0 * (s2[:, None] + s2[None, :]) / d ** 2
+    np.fill_diagonal(t, 0.0)
+    expect = n + t.sum()
+    rng = inputs.rng_for(31, 1)
+    acc = []
+    for _ in range(300):
+        dU = rng.standard_normal((n, n)); dV = rng.standard_normal((n, n)); dS = rng.standard_normal(n)
+        acc.append(np.sum(orc.svd_bwd(M, U, S, V, dU, dS, dV) ** 2))
+    acc = np.array(acc)
+    # the Monte-Carlo mean within 4 standard errors
+    assert abs(acc.mean() - expect) < 4 * acc.std() / np.sqrt(len(acc))
+
+
 def test_lyapunov_identity_on_oracle_solution(orc):
     # Lyapunov identity lemma: with HY + YH = A and HX + XH = B,
     # <A, X> = <Y, B>; the eigenbasis solution of the proposition on solving
