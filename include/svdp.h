@@ -114,14 +114,19 @@ typedef struct {
   const float* probe;      /* device, batch x n Gaussian probe vectors, bound == LEARNED */
   double eigh_off_tol;     /* eigensolver restarts: T = V^T H V is re-formed from the input and
                               swept again from V' = I (V <- V V') while |off(T)|_F > eigh_off_tol
-                              |H|_F; the last T gives the eigenvalues (1e-5) */
+                              |H|_F; the last T gives the eigenvalues (6e-6: about the FP32
+                              floor of a restart at n = 4096) */
   int32_t eigh_restarts;   /* cap on those restarts (2) */
+  double jacobi_fro_tol;   /* Jacobi also stops after a sweep whose rotated entries have
+                              sqrt(sum h_pq^2) <= jacobi_fro_tol |H|_F: a normwise test, met
+                              sweeps before the relative one when small eigenvalues need many
+                              sweeps for relative accuracy (3e-4; 0 disables it) */
 } svdp_params;
 
 /* per-matrix diagnostics, device array of `batch` records */
 typedef struct {
   int32_t iters;    /* CANS steps taken (BF16 + FP32) */
-  int32_t sweeps;   /* Jacobi sweeps (FP32 phase) */
+  int32_t sweeps;   /* Jacobi sweeps: the FP32 phase plus the sweeps of eigensolver restarts */
   int32_t flags;    /* SVDP_FLAG_* */
   float residual;   /* |X^T X - I|_F / sqrt(n) of the iterate entering the last CANS step */
 } svdp_info;
@@ -216,7 +221,7 @@ svdp_status polar_bwd(svdp_handle* h, const svdp_params* p,
 /* Symmetric eigendecomposition H = V diag(lam) V^T (the EVD step of
  * Algorithm 1) by batched block Jacobi; lam descending (signed), V n x n.
  * Uses p->batch, p->n (m ignored), max_sweeps, inner_sweeps, fp64_sweeps,
- * jacobi_tol, jacobi_abs, eigh_off_tol, eigh_restarts.  info: sweeps and flags (may be null). */
+ * jacobi_tol, jacobi_abs, jacobi_fro_tol, eigh_off_tol, eigh_restarts.  info: sweeps and flags (may be null). */
 svdp_status svdp_eigh(svdp_handle* h, const svdp_params* p,
                       const float* H, int64_t ldh, int64_t sH,
                       float* lam, int64_t slam,

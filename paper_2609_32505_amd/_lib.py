@@ -43,7 +43,7 @@ class Params(ctypes.Structure):
         ("eps_K", c_dbl), ("eps_R", c_dbl), ("eps_T", c_dbl),
         ("margin_max", c_dbl), ("margin_min", c_dbl),
         ("user_bounds", c_vp), ("probe", c_vp),
-        ("eigh_off_tol", c_dbl), ("eigh_restarts", c_i32),
+        ("eigh_off_tol", c_dbl), ("eigh_restarts", c_i32), ("jacobi_fro_tol", c_dbl),
     ]
 
 

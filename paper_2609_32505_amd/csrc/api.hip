@@ -123,6 +123,7 @@ svdp_status check_common(const svdp_params* p) {
   if (p->eigh_restarts < 0 || p->eigh_restarts > 8)
     return fail(SVDP_ERR_INVALID_ARG, "eigh_restarts must be in [0, 8]");
   if (!(p->eigh_off_tol >= 0)) return fail(SVDP_ERR_INVALID_ARG, "eigh_off_tol must be >= 0");
+  if (!(p->jacobi_fro_tol >= 0)) return fail(SVDP_ERR_INVALID_ARG, "jacobi_fro_tol must be >= 0");
   if (!(p->delta > 0 && p->delta < 1)) return fail(SVDP_ERR_INVALID_ARG, "delta must be in (0, 1)");
   if (!(p->tol > 0)) return fail(SVDP_ERR_INVALID_ARG, "tol must be > 0");
   if (p->eps_K < 0 || p->eps_R < 0 || p->eps_T < 0) return fail(SVDP_ERR_INVALID_ARG, "eps must be >= 0");
@@ -136,6 +137,7 @@ EighOpts eigh_opts(const svdp_params* p) {
   o.fp64_inner = p->inner_sweeps;
   o.tol = (float)p->jacobi_tol;
   o.abs_tol = (float)p->jacobi_abs;
+  o.fro_tol = (float)p->jacobi_fro_tol;
   o.neg_tol = 1e-4f;
   o.off_tol = (float)p->eigh_off_tol;
   o.restarts = p->eigh_restarts;
@@ -523,8 +525,9 @@ void svdp_default_params(svdp_params* p, int64_t batch, int64_t m, int64_t n) {
   p->bf16_from = 0.1;
   p->margin_max = 1.1;
   p->margin_min = 1.0;
-  p->eigh_off_tol = 1e-5;
+  p->eigh_off_tol = 6e-6;
   p->eigh_restarts = 2;
+  p->jacobi_fro_tol = 3e-4;
 }
 
 const char* svdp_status_string(svdp_status s) {

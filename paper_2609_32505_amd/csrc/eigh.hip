@@ -26,9 +26,9 @@
 // blocks.  The first step of a sweep runs all 31 rounds, the others the 16
 // cross rounds only, so every index pair is rotated once per sweep (a cyclic
 // Jacobi ordering).
-// Convergence is tested per matrix on the largest relative off-diagonal
-// entry rotated during a sweep; converged matrices are skipped by later
-// launches.
+// Convergence is tested per matrix after each sweep, on the largest relative
+// off-diagonal entry rotated and on the sum of squares of the rotated entries
+// (normwise); converged matrices are skipped by later launches.
 // Restarts.  Every block rotation rounds H and V separately, so after many
 // sweeps V no longer diagonalises the input to FP32 accuracy (the backward
 // error grows with the number of rotations, i.e. with n).  T = V^T H V is
@@ -151,7 +151,7 @@ SVDP_DEV double lane_xor<double>(double v, int lane, int m) {
 // replaces LDS traffic.
 template <typename R, int STEPB>
 SVDP_DEV void pair_solve(SolveLds<R>& L, int w, int lane, int t0, int inner_sweeps, R floor_abs, float& mrel,
-                         R (&jp)[8], R (&jq)[8]) {
+                         float& vsum, R (&jp)[8], R (&jq)[8]) {
   constexpr int XP = XPitch<R>::v;
   R (*X)[XP] = L.X;
   RotPair<R>* cs = L.cs[w];
@@ -178,6 +178,7 @@ SVDP_DEV void pair_solve(SolveLds<R>& L, int w, int lane, int t0, int inner_swee
         if (apq != R(0) && isfinite((float)apq)) {
           rotation_fast(app, aqq, apq, r.c, r.s);
           any = 1;
+          vsum += (float)apq * (float)apq;
           if (fabs(apq) > floor_abs) {
             // |apq| / sqrt(|app aqq|), a convergence statistic (no IEEE rounding needed)
             const float den2 = fabsf((float)app * (float)aqq);
@@ -295,7 +296,7 @@ SVDP_DEV void cross_update(SolveLds<R>& L, const float (*J0)[LP], const float (*
 
 template <typename R>
 __global__ __launch_bounds__(128) void k_jac_solve(EighWs e, EighPhase ph, int inner_sweeps, float abs_tol,
-                                                   int* rotmax) {
+                                                   int* rotmax, float* rotsq) {
   __shared__ SolveLds<R> L;
   constexpr int XP = XPitch<R>::v;
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
@@ -321,12 +322,12 @@ __global__ __launch_bounds__(128) void k_jac_solve(EighWs e, EighPhase ph, int i
   }
   __syncthreads();
   const R floor_abs = (R)abs_tol * (R)sqrtf(e.hnorm2[b]);
-  float mrel = 0.f;
+  float mrel = 0.f, vsum = 0.f;
   float* M = e.Qw + ((int64_t)b * ng + gi) * QSTRIDE;
   float* JAg = M + GS * GS;  // step-A rotations (FP32), read back for M_G
   R jp[8], jq[8];
   // step A
-  pair_solve<R, 0>(L, w, lane, ph.fullA ? 1 : 16, inner_sweeps, floor_abs, mrel, jp, jq);
+  pair_solve<R, 0>(L, w, lane, ph.fullA ? 1 : 16, inner_sweeps, floor_abs, mrel, vsum, jp, jq);
   j_to_lds(L, w, lane, jp, jq);
   for (int idx = lane; idx < PB * PB; idx += 64) JAg[w * PB * PB + idx] = L.Jf[w][idx >> 5][idx & 31];
   __syncthreads();
@@ -341,7 +342,7 @@ __global__ __launch_bounds__(128) void k_jac_solve(EighWs e, EighPhase ph, int i
     }
   } else {
     // step B
-    pair_solve<R, 1>(L, w, lane, 16, inner_sweeps, floor_abs, mrel, jp, jq);
+    pair_solve<R, 1>(L, w, lane, 16, inner_sweeps, floor_abs, mrel, vsum, jp, jq);
     j_to_lds(L, w, lane, jp, jq);
     __syncthreads();
     if (w == 0) cross_update<R, 1>(L, L.Jf[0], L.Jf[1], lane);
@@ -371,10 +372,15 @@ __global__ __launch_bounds__(128) void k_jac_solve(EighWs e, EighPhase ph, int i
     for (int w2 = 0; w2 < 4; ++w2) v[w2] = (float)L.X[k1 * 16 + r][k2 * 16 + c + w2];
     *(f4v*)(H + tile_off(g[k1], g[k2], e.nb) + qd * 4) = v;
   }
-  // largest relative off-diagonal entry rotated by this wave (float bits)
+  // largest relative off-diagonal entry rotated by this wave (float bits),
+  // and the sum of squares of the entries it rotated
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) mrel = fmaxf(mrel, __shfl_xor(mrel, off));
+  for (int off = 32; off > 0; off >>= 1) {
+    mrel = fmaxf(mrel, __shfl_xor(mrel, off));
+    vsum += __shfl_xor(vsum, off);
+  }
   if (lane == 0 && rotmax) atomicMax(rotmax + b, __float_as_int(mrel));
+  if (lane == 0 && rotsq) atomicAdd(rotsq + b, vsum);
 }
 
 // 64 x 64 quadrant products on one wavefront (32 x 32 output block (qi, qj)),
@@ -582,10 +588,12 @@ __global__ void k_untile(const float* src, float* dst, int np, int nb, const int
   *(f4v*)(dst + off + (int64_t)row * np + c4) = v;
 }
 
-// Mark matrices whose sweep made no significant rotation as converged and
+// Mark matrices as converged after a sweep whose largest rotated relative
+// entry was <= tol, or whose rotated entries had a sum of squares <=
+// fro_tol2 |H|_F^2 (a normwise test: the next sweep leaves far less), and
 // count the ones still active (single workgroup).
-__global__ void k_eigh_check(EighWs e, const int* rotcnt, float tol, int sweep, int* sweeps_out,
-                             int* n_active) {
+__global__ void k_eigh_check(EighWs e, const int* rotcnt, const float* rotsq, float tol, float fro_tol2, int sweep,
+                             int* sweeps_out, int* n_active) {
   __shared__ int cnt;
   if (threadIdx.x == 0) cnt = 0;
   __syncthreads();
@@ -593,7 +601,7 @@ __global__ void k_eigh_check(EighWs e, const int* rotcnt, float tol, int sweep, 
   for (int b = threadIdx.x; b < e.batch; b += blockDim.x) {
     if (e.active[b]) {
       sweeps_out[b] = sweep + 1;
-      if (__int_as_float(rotcnt[b]) <= tol) e.active[b] = 0;
+      if (__int_as_float(rotcnt[b]) <= tol || rotsq[b] <= fro_tol2 * e.hnorm2[b]) e.active[b] = 0;
       else ++mine;
     }
   }
@@ -721,14 +729,19 @@ __global__ __launch_bounds__(256) void k_restart_offnorm(EighWs e, const float* 
 
 // After a restart measure: a matrix of `proc` stays active for another sweep
 // of T when off2 > off_tol2 |H0|_F^2 and `last` is 0 (the others leave the
-// active set); *counter gains the number of active matrices.
-__global__ void k_restart_decide(EighWs e, const int* proc, float off_tol2, int last, int* counter) {
+// active set); *counter gains the number of active matrices, and their sweep
+// counts the nsweeps sweeps of the restart.
+__global__ void k_restart_decide(EighWs e, const int* proc, float off_tol2, int last, int* counter,
+                                 int* sweeps_out, int nsweeps) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= e.batch) return;
   int act = 0;
   if (!proc || proc[b]) act = !last && e.off2[b] > (double)off_tol2 * (double)e.hnorm2[b];
   e.active[b] = act;
-  if (act) atomicAdd(counter, 1);
+  if (act) {
+    atomicAdd(counter, 1);
+    sweeps_out[b] += nsweeps;
+  }
 }
 
 // dst[b][:n, :n] = src[b][:n, :n] (leading dimension np) for the active matrices
@@ -795,7 +808,7 @@ size_t eigh_ws_bytes(int64_t batch, int64_t n, int max_sweeps) {
   f += batch;                        // hnorm2
   f += 2 * batch;                    // off2 (FP64)
   f += 2 * batch * n;                // sign, (perm as int)
-  size_t i = batch * (size_t)(max_sweeps + 2) + batch + 16;  // rotcnt, active, counters
+  size_t i = 2 * batch * (size_t)(max_sweeps + 2) + batch + 16;  // rotcnt, rotsq, active, counters
   return (f + i) * 4 + 16 * 256;
 }
 
@@ -818,6 +831,7 @@ EighWs eigh_ws_carve(void* ws, int64_t batch, int64_t n, int max_sweeps) {
   e.sgn = (float*)take(batch * n * 4);
   e.perm = (int*)take(batch * n * 4);
   e.rotcnt = (int*)take(batch * (size_t)(max_sweeps + 2) * 4);
+  e.rotsq = (float*)take(batch * (size_t)(max_sweeps + 2) * 4);
   e.active = (int*)take(batch * 4);
   e.counter = (int*)take(64);
   e.max_sweeps = max_sweeps;
@@ -877,6 +891,7 @@ hipError_t eigh_run(EighWs e, const float* H, int64_t ldh, int64_t sH, int mode,
   const int batch = e.batch;
   if ((err = fill_f32(e.hnorm2, 0.f, batch, st))) return err;
   if ((err = fill_i32(e.rotcnt, 0, (int64_t)batch * (e.max_sweeps + 2), st))) return err;
+  if ((err = fill_f32(e.rotsq, 0.f, (int64_t)batch * (e.max_sweeps + 2), st))) return err;
   if (mask) { if ((err = copy_i32(e.active, mask, batch, st))) return err; }
   else if ((err = fill_i32(e.active, 1, batch, st))) return err;
   hipLaunchKernelGGL(k_eigh_setup, dim3((e.nb / 4) * (e.nb / 4), batch), dim3(256), 0, st, e, H, ldh, sH, mask,
@@ -914,7 +929,7 @@ hipError_t eigh_run(EighWs e, const float* H, int64_t ldh, int64_t sH, int mode,
     for (int h = 1; h < P; ++h)
       if ((err = hipStreamWaitEvent(ss[h], aux->fork, 0))) return err;
   }
-  auto phase_launches = [&](int h, const EighPhase& ph, bool fp64, int* rc, int n_act,
+  auto phase_launches = [&](int h, const EighPhase& ph, bool fp64, int* rc, float* vs, int n_act,
                             bool mark_skew) -> hipError_t {
     const EighWs& E = eh[h];
     const unsigned sblocks = (unsigned)(E.batch * ng);
@@ -922,11 +937,11 @@ hipError_t eigh_run(EighWs e, const float* H, int64_t ldh, int64_t sH, int mode,
     if (fp64) {
       ProfScope ps(PROF_JAC_SOLVE_F64, ss[h], solve_work(ph, o.fp64_inner) * n_act);
       hipLaunchKernelGGL(k_jac_solve<double>, dim3(sblocks), dim3(128), 0, ss[h], E, ph, o.fp64_inner, o.abs_tol,
-                         (int*)nullptr);
+                         (int*)nullptr, (float*)nullptr);
     } else {
       ProfScope ps(PROF_JAC_SOLVE_F32, ss[h], solve_work(ph, o.inner_sweeps) * n_act);
       hipLaunchKernelGGL(k_jac_solve<float>, dim3(sblocks), dim3(128), 0, ss[h], E, ph, o.inner_sweeps, o.abs_tol,
-                         rc);
+                         rc, vs);
     }
     hipError_t e2 = hipGetLastError();
     if (e2) return e2;
@@ -939,7 +954,7 @@ hipError_t eigh_run(EighWs e, const float* H, int64_t ldh, int64_t sH, int mode,
   };
   // one pass over the phases for every part; part h starts after part
   // h - 1's first pair solve
-  auto sweep_launches = [&](bool fp64, int* rc, const int* n_act) -> hipError_t {
+  auto sweep_launches = [&](bool fp64, int* rc, float* vs, const int* n_act) -> hipError_t {
     bool first = true;
     for (const EighPhase& ph : phases) {
       int prev = -1;
@@ -947,7 +962,8 @@ hipError_t eigh_run(EighWs e, const float* H, int64_t ldh, int64_t sH, int mode,
         if (n_act[h] == 0) continue;
         hipError_t e2;
         if (first && prev >= 0 && (e2 = hipStreamWaitEvent(ss[h], aux->skew[prev], 0))) return e2;
-        if ((e2 = phase_launches(h, ph, fp64, rc ? rc + b0[h] : nullptr, n_act[h], first && P > 1))) return e2;
+        if ((e2 = phase_launches(h, ph, fp64, rc ? rc + b0[h] : nullptr, vs ? vs + b0[h] : nullptr, n_act[h],
+                                  first && P > 1))) return e2;
         prev = h;
       }
       first = false;
@@ -959,11 +975,12 @@ hipError_t eigh_run(EighWs e, const float* H, int64_t ldh, int64_t sH, int mode,
   int sweep = 0;
   for (; sweep < e.max_sweeps; ++sweep) {
     int* rc = e.rotcnt + (int64_t)batch * sweep;
-    if ((err = sweep_launches(false, rc, n_act))) return err;
+    float* vs = e.rotsq + (int64_t)batch * sweep;
+    if ((err = sweep_launches(false, rc, vs, n_act))) return err;
     for (int h = 0; h < P; ++h) {
       if (n_act[h] == 0) continue;
-      hipLaunchKernelGGL(k_eigh_check, dim3(1), dim3(1024), 0, ss[h], eh[h], rc + b0[h], o.tol, sweep,
-                         sweeps_out + b0[h], eh[h].counter);
+      hipLaunchKernelGGL(k_eigh_check, dim3(1), dim3(1024), 0, ss[h], eh[h], rc + b0[h], vs + b0[h], o.tol,
+                         o.fro_tol * o.fro_tol, sweep, sweeps_out + b0[h], eh[h].counter);
       if ((err = hipGetLastError())) return err;
       if ((err = hipMemcpyAsync(host_counter + h, eh[h].counter, sizeof(int), hipMemcpyDeviceToHost, ss[h])))
         return err;
@@ -991,7 +1008,7 @@ hipError_t eigh_run(EighWs e, const float* H, int64_t ldh, int64_t sH, int mode,
       else if ((err = fill_i32(eh[h].active, 1, bc[h], ss[h]))) return err;
     }
     for (int f = 0; f < o.fp64_sweeps; ++f)
-      if ((err = sweep_launches(true, nullptr, bc))) return err;
+      if ((err = sweep_launches(true, nullptr, nullptr, bc))) return err;
   }
   auto join = [&]() -> hipError_t {
     hipError_t e2;
@@ -1062,7 +1079,7 @@ hipError_t eigh_run(EighWs e, const float* H, int64_t ldh, int64_t sH, int mode,
       hipLaunchKernelGGL(k_restart_offnorm, dim3(chunks, batch), dim3(256), 0, st, e, e.Vw, proc);
       if ((err = hipGetLastError())) return err;
       hipLaunchKernelGGL(k_restart_decide, dim3(cdiv(batch, 256)), dim3(256), 0, st, e, proc, tol2, last,
-                         e.counter);
+                         e.counter, sweeps_out, std::max(1, o.fp64_sweeps));
       if ((err = hipGetLastError())) return err;
       if (last) break;
       if ((err = hipMemcpyAsync(host_counter, e.counter, sizeof(int), hipMemcpyDeviceToHost, st))) return err;
@@ -1081,7 +1098,7 @@ hipError_t eigh_run(EighWs e, const float* H, int64_t ldh, int64_t sH, int mode,
           if ((err = hipStreamWaitEvent(ss[h], aux->fork, 0))) return err;
       }
       for (int f = 0; f < std::max(1, o.fp64_sweeps); ++f)
-        if ((err = sweep_launches(o.fp64_sweeps > 0, nullptr, bc))) return err;
+        if ((err = sweep_launches(o.fp64_sweeps > 0, nullptr, nullptr, bc))) return err;
       if ((err = join())) return err;
       hipLaunchKernelGGL(k_untile, dim3(cdiv(m2 / 4, 256), batch), dim3(256), 0, st, e.Vw, e.Hw, np, e.nb, proc);
       if ((err = hipGetLastError())) return err;

@@ -15,6 +15,7 @@ struct EighWs {
   float* sgn;     // batch x n: sign of each sorted eigenvalue
   int* perm;      // batch x n: sorted position -> working column
   int* rotcnt;    // batch x (max_sweeps + 2): largest relative entry rotated (float bits)
+  float* rotsq;   // batch x (max_sweeps + 2): sum of squares of the entries rotated
   int* active;    // batch: 1 while not converged
   int* counter;   // device scalar: active matrices after a sweep
 };
@@ -37,6 +38,8 @@ struct EighOpts {
                      // <= tol sqrt(|h_pp h_qq|) (quadratic convergence: the next
                      // sweep, the FP64 one, leaves ~tol^2)
   float abs_tol;     // entries below abs_tol |H|_F do not count
+  float fro_tol;     // ... or after a sweep whose rotated entries have a sum of squares
+                     // <= fro_tol^2 |H|_F^2 (normwise)
   float neg_tol;     // NEG_EIGENVALUE when lam_min < -neg_tol max|lam| (mode 1)
   float off_tol;     // restarts end once |off(V^T H V)|_F <= off_tol |H|_F
   int restarts;      // cap on restarts (re-formed V^T H V swept again from I)

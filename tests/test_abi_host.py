@@ -46,7 +46,7 @@ def test_params_struct_matches_header_layout():
     assert p.jacobi_tol == 3e-3 and p.bf16_from == 0.1
     assert p.margin_max == 1.1 and p.margin_min == 1.0
     assert p.eps_K == 0.0 and p.user_bounds is None and p.probe is None
-    assert p.eigh_off_tol == 1e-5 and p.eigh_restarts == 2
+    assert p.eigh_off_tol == 6e-6 and p.eigh_restarts == 2 and p.jacobi_fro_tol == 3e-4
 
 
 def _ws(p, op):
@@ -72,6 +72,7 @@ def test_workspace_size_and_shape_validation():
     assert _ws(L.default_params(1, 8, 8, precision=7), 0)[0] == 1
     assert _ws(L.default_params(1, 8, 8, eigh_restarts=9), 0)[0] == 1
     assert _ws(L.default_params(1, 8, 8, eigh_off_tol=-1.0), 0)[0] == 1
+    assert _ws(L.default_params(1, 8, 8, jacobi_fro_tol=-1.0), 0)[0] == 1
     assert _ws(L.default_params(0, 8, 8), L.OP_SVD_FWD)[0] == 0
 
 
