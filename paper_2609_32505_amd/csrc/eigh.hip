@@ -36,6 +36,7 @@
 // off-diagonal part is too large, T is swept again from V' = I, whose
 // rotations are small, and V <- V V'.
 #include <algorithm>
+#include <type_traits>
 #include <cstring>
 #include <vector>
 #include "common.hpp"
@@ -161,89 +162,97 @@ SVDP_DEV void pair_solve(SolveLds<R>& L, int w, int lane, int t0, int inner_swee
     jp[u] = (q + 4 * u == kx) ? R(1) : R(0);
     jq[u] = (q + 4 * u == 16 + kx) ? R(1) : R(0);
   }
+  // One round t.  CROSS (t >= 16) pairs index k of the first 16-block with
+  // 16 + (k ^ (t - 16)); otherwise indices inside each 16-block are paired.
+  // The two kinds are separate instantiations, so their index maps are
+  // resolved at compile time.
+  auto round = [&](auto cross_c, int t, int& any) {
+    constexpr bool CROSS = decltype(cross_c)::value;
+    const int hb = 31 - __builtin_clz(t);
+    auto pair_of = [&](int k, int& x, int& y) {
+      x = CROSS ? k : (((k >> 3) << 4) | insert0(k & 7, hb));
+      y = x ^ t;
+    };
+    int x1, y1;
+    pair_of(kx, x1, y1);
+    const int gx1 = gpos<STEPB>(w, x1), gy1 = gpos<STEPB>(w, y1);
+    if (lane < 16) {
+      const R app = X[gx1][gx1], aqq = X[gy1][gy1], apq = R(0.5) * (X[gx1][gy1] + X[gy1][gx1]);
+      RotPair<R> r{R(1), R(0)};
+      if (apq != R(0) && isfinite((float)apq)) {
+        rotation_fast(app, aqq, apq, r.c, r.s);
+        any = 1;
+        vsum += (float)apq * (float)apq;
+        if (fabs(apq) > floor_abs) {
+          // |apq| / sqrt(|app aqq|), a convergence statistic (no IEEE rounding needed)
+          const float den2 = fabsf((float)app * (float)aqq);
+          mrel = fmaxf(mrel, den2 > 0.f ? fabsf((float)apq) * __builtin_amdgcn_rsqf(den2) : 1e30f);
+        }
+      }
+      cs[lane] = r;
+    }
+    wave_sync();
+    const RotPair<R> r1 = cs[kx];
+    R* rowx = X[gx1];
+    R* rowy = X[gy1];
+    // the lane's four 2 x 2 blocks are disjoint from every other lane's:
+    // all loads first, then all stores (one LDS round trip)
+    int cx[4], cy[4];
+    RotPair<R> r2[4];
+    R a[4], bq[4], cq[4], d[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      int x2, y2;
+      pair_of(q + 4 * u, x2, y2);
+      cx[u] = gpos<STEPB>(w, x2);
+      cy[u] = gpos<STEPB>(w, y2);
+      r2[u] = cs[q + 4 * u];
+      a[u] = rowx[cx[u]]; bq[u] = rowx[cy[u]]; cq[u] = rowy[cx[u]]; d[u] = rowy[cy[u]];
+    }
+    // rotations of the lane's two J columns: column kx pairs with the
+    // partner lane's column (cross: 16 + (kx ^ m), intra: kx ^ t), and column
+    // 16 + kx with the partner's (kx ^ m, resp. 16 + (kx ^ t)).  A column
+    // that is the first of its pair becomes c x - s y, the second c x + s y:
+    // the sign goes into s once per round.
+    const int m = t & 15;
+    RotPair<R> rp, rq;
+    R sp, sq;
+    if (CROSS) {
+      rp = cs[kx];
+      rq = cs[kx ^ m];
+      sp = -rp.s;
+      sq = rq.s;
+    } else {
+      const bool first = ((kx >> hb) & 1) == 0;
+      const int xs = first ? kx : kx ^ t;
+      rp = cs[compress(xs, hb)];
+      rq = cs[8 + compress(xs, hb)];
+      sp = first ? -rp.s : rp.s;
+      sq = first ? -rq.s : rq.s;
+    }
+    wave_sync();
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const R t00 = r1.c * a[u] - r1.s * cq[u], t01 = r1.c * bq[u] - r1.s * d[u];
+      const R t10 = r1.s * a[u] + r1.c * cq[u], t11 = r1.s * bq[u] + r1.c * d[u];
+      R y00 = r2[u].c * t00 - r2[u].s * t01, y01 = r2[u].s * t00 + r2[u].c * t01;
+      R y10 = r2[u].c * t10 - r2[u].s * t11, y11 = r2[u].s * t10 + r2[u].c * t11;
+      if (kx == q + 4 * u && r1.s != R(0)) { y01 = 0; y10 = 0; }
+      rowx[cx[u]] = y00; rowx[cy[u]] = y01; rowy[cx[u]] = y10; rowy[cy[u]] = y11;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const R op = lane_xor<R>(jp[u], lane, m);  // partner's column kx ^ m
+      const R oq = lane_xor<R>(jq[u], lane, m);  // partner's column 16 + (kx ^ m)
+      jp[u] = rp.c * jp[u] + sp * (CROSS ? oq : op);
+      jq[u] = rq.c * jq[u] + sq * (CROSS ? op : oq);
+    }
+    wave_sync();
+  };
   for (int sw = 0; sw < inner_sweeps; ++sw) {
     int any = 0;
-    for (int t = t0; t < PB; ++t) {
-      const int hb = 31 - __builtin_clz(t);
-      auto pair_of = [&](int k, int& x, int& y) {
-        x = t >= 16 ? k : (((k >> 3) << 4) | insert0(k & 7, hb));
-        y = x ^ t;
-      };
-      int x1, y1;
-      pair_of(kx, x1, y1);
-      const int gx1 = gpos<STEPB>(w, x1), gy1 = gpos<STEPB>(w, y1);
-      if (lane < 16) {
-        const R app = X[gx1][gx1], aqq = X[gy1][gy1], apq = R(0.5) * (X[gx1][gy1] + X[gy1][gx1]);
-        RotPair<R> r{R(1), R(0)};
-        if (apq != R(0) && isfinite((float)apq)) {
-          rotation_fast(app, aqq, apq, r.c, r.s);
-          any = 1;
-          vsum += (float)apq * (float)apq;
-          if (fabs(apq) > floor_abs) {
-            // |apq| / sqrt(|app aqq|), a convergence statistic (no IEEE rounding needed)
-            const float den2 = fabsf((float)app * (float)aqq);
-            mrel = fmaxf(mrel, den2 > 0.f ? fabsf((float)apq) * __builtin_amdgcn_rsqf(den2) : 1e30f);
-          }
-        }
-        cs[lane] = r;
-      }
-      wave_sync();
-      const RotPair<R> r1 = cs[kx];
-      R* rowx = X[gx1];
-      R* rowy = X[gy1];
-      // the lane's four 2 x 2 blocks are disjoint from every other lane's:
-      // all loads first, then all stores (one LDS round trip)
-      int cx[4], cy[4];
-      RotPair<R> r2[4];
-      R a[4], bq[4], cq[4], d[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        int x2, y2;
-        pair_of(q + 4 * u, x2, y2);
-        cx[u] = gpos<STEPB>(w, x2);
-        cy[u] = gpos<STEPB>(w, y2);
-        r2[u] = cs[q + 4 * u];
-        a[u] = rowx[cx[u]]; bq[u] = rowx[cy[u]]; cq[u] = rowy[cx[u]]; d[u] = rowy[cy[u]];
-      }
-      // rotations of the lane's two J columns: column kx pairs with the
-      // partner lane's column (t >= 16: 16 + (kx ^ u), t < 16: kx ^ t), and
-      // column 16 + kx with the partner's (kx ^ u, resp. 16 + (kx ^ t))
-      const int m = t & 15;
-      RotPair<R> rp, rq;
-      bool px, qx;  // the lane's column is the first of its pair
-      if (t >= 16) {
-        rp = cs[kx];
-        rq = cs[kx ^ m];
-        px = true;
-        qx = false;
-      } else {
-        const int xs = (kx >> hb) & 1 ? kx ^ t : kx;
-        rp = cs[compress(xs, hb)];
-        rq = cs[8 + compress(xs, hb)];
-        px = qx = ((kx >> hb) & 1) == 0;
-      }
-      wave_sync();
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const R t00 = r1.c * a[u] - r1.s * cq[u], t01 = r1.c * bq[u] - r1.s * d[u];
-        const R t10 = r1.s * a[u] + r1.c * cq[u], t11 = r1.s * bq[u] + r1.c * d[u];
-        R y00 = r2[u].c * t00 - r2[u].s * t01, y01 = r2[u].s * t00 + r2[u].c * t01;
-        R y10 = r2[u].c * t10 - r2[u].s * t11, y11 = r2[u].s * t10 + r2[u].c * t11;
-        if (kx == q + 4 * u && r1.s != R(0)) { y01 = 0; y10 = 0; }
-        rowx[cx[u]] = y00; rowx[cy[u]] = y01; rowy[cx[u]] = y10; rowy[cy[u]] = y11;
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const R op = lane_xor<R>(jp[u], lane, m);  // partner's column kx ^ m
-        const R oq = lane_xor<R>(jq[u], lane, m);  // partner's column 16 + (kx ^ m)
-        // partner column of kx: 16 + (kx ^ m) (cross) or kx ^ t (intra)
-        const R pp = t >= 16 ? oq : op;
-        const R pq = t >= 16 ? op : oq;
-        jp[u] = px ? rp.c * jp[u] - rp.s * pp : rp.s * pp + rp.c * jp[u];
-        jq[u] = qx ? rq.c * jq[u] - rq.s * pq : rq.s * pq + rq.c * jq[u];
-      }
-      wave_sync();
-    }
+    for (int t = t0; t < 16; ++t) round(std::false_type{}, t, any);
+    for (int t = t0 > 16 ? t0 : 16; t < PB; ++t) round(std::true_type{}, t, any);
     // every lane of the wave takes the same exit
     if (!__any(any)) break;
   }
