@@ -150,12 +150,22 @@ EighOpts eigh_opts(const svdp_params* p) {
 // is declared unconverged (and rerun with conservative CANS).
 constexpr int kRefineExtra = 8;
 
+// Algorithm 1's QR step: one workgroup runs CGS2 over all columns of a
+// flagged matrix up to this n; beyond it, blocks of kQrBlock columns are
+// projected against the earlier ones by GEMMs (twice) and orthonormalised
+// among themselves by CholeskyQR (twice).
+constexpr int kQrBlockedFrom = 512;
+constexpr int kQrBlock = 64;
+
 struct FwdWs {
   float *X0, *X1, *G;
   void *Y0, *Y1;  // BF16 iterates (never aliasing the FP32 ones)
   void* eigh;
   float *scale, *conv, *resid, *colsum, *rowmax, *fro2, *coef, *rcoef, *F, *aux, *mlpout, *nrm, *y0, *y1;
-  float* qr;  // QR completion scratch: 2 m per matrix
+  float* qr;   // QR completion scratch: 2 m per matrix
+  float* qrc;  // blocked QR: projection coefficients, n x kQrBlock per matrix
+  float *qrg, *qrr;  // blocked QR: a block's Gram matrix and CholeskyQR factor
+  int* qmask;  // blocked QR: the flagged matrices
   int *active, *where, *iters, *flags, *sweeps, *mask, *counter, *ksteps, *kmax, *hist, *gmask;
 };
 
@@ -184,6 +194,11 @@ FwdWs carve_fwd(void* base, const svdp_params* p, size_t* total) {
   w.y0 = c.take<float>(b * m);
   w.y1 = c.take<float>(b * m);
   w.qr = c.take<float>(b * 2 * m);
+  const bool blocked_qr = n > (size_t)kQrBlockedFrom;
+  w.qrc = c.take<float>(blocked_qr ? b * n * kQrBlock : 0);
+  w.qrg = c.take<float>(blocked_qr ? b * kQrBlock * kQrBlock : 0);
+  w.qrr = c.take<float>(blocked_qr ? b * kQrBlock * kQrBlock : 0);
+  w.qmask = c.take<int>(b);
   w.active = c.take<int>(b);
   w.where = c.take<int>(b);
   w.iters = c.take<int>(b);
@@ -449,6 +464,62 @@ svdp_status polar_core(Ctx& c) {
   return final_residual(c, nullptr);
 }
 
+// Blocked QR of U for the flagged matrices (n > kQrBlockedFrom): columns
+// without direction (sigma_j <= eps_qr sigma_1) are replaced by pseudo-random
+// unit vectors and other deficient columns perturbed by eps_qr-sized ones;
+// then for each
+// block of kQrBlock columns, twice C = U[:, :c0]^T U[:, blk] and
+// U[:, blk] -= U[:, :c0] C (block Gram-Schmidt), and twice G = U[:, blk]^T
+// U[:, blk], U[:, blk] <- U[:, blk] Rinv (CholeskyQR with column scaling).
+// The R factor this implies has a positive diagonal.
+svdp_status qr_blocked(Ctx& c, float* U, int64_t ldu, int64_t sU, const float* S, int64_t sS, const int* mask) {
+  const svdp_params* p = c.p;
+  FwdWs& w = c.w;
+  const int B = c.batch, m = c.m, n = c.n;
+  HIPCHK(qr_mask_launch(B, w.flags, mask, w.qmask, w.counter, c.st), "qr mask");
+  int flagged = 0;
+  svdp_status s = read_counter(c, w.counter, &flagged);
+  if (s || flagged == 0) return s;
+  HIPCHK(qr_perturb_launch(U, ldu, sU, B, m, n, S, sS, w.colsum, (float)p->eps_qr, w.qmask, c.st), "qr perturb");
+  for (int c0 = 0; c0 < n; c0 += kQrBlock) {
+    const int bc = std::min(kQrBlock, n - c0);
+    for (int pass = 0; c0 > 0 && pass < 2; ++pass) {
+      GemmArgs g = gemm_base(c0, bc, m, B);  // C = U[:, :c0]^T U[:, c0:c0+bc]
+      g.A = U; g.lda = ldu; g.sA = sU;
+      g.B = U + c0; g.ldb = ldu; g.sB = sU;
+      g.C = w.qrc; g.ldc = bc; g.sC = (int64_t)n * kQrBlock;
+      g.active = w.qmask;
+      HIPCHK(gemm_launch(g, PREC_F32, 1, 0, c.st), "qr project");
+      GemmArgs u = gemm_base(m, bc, c0, B);  // U[:, blk] = U[:, blk] - U[:, :c0] C
+      u.A = U; u.lda = ldu; u.sA = sU;
+      u.B = w.qrc; u.ldb = bc; u.sB = (int64_t)n * kQrBlock;
+      u.C = U + c0; u.ldc = ldu; u.sC = sU;
+      u.Cin = U + c0; u.ldcin = ldu; u.sCin = sU;
+      u.alpha = -1.f; u.beta = 1.f;
+      u.active = w.qmask;
+      HIPCHK(gemm_launch(u, PREC_F32, 0, 0, c.st), "qr update");
+    }
+    for (int pass = 0; pass < 2; ++pass) {
+      GemmArgs g = gemm_base(bc, bc, m, B);  // G = U[:, blk]^T U[:, blk]
+      g.A = U + c0; g.lda = ldu; g.sA = sU;
+      g.B = U + c0; g.ldb = ldu; g.sB = sU;
+      g.C = w.qrg; g.ldc = bc; g.sC = (int64_t)kQrBlock * kQrBlock;
+      g.sym = 1; g.active = w.qmask;
+      HIPCHK(gemm_launch(g, PREC_F32, 1, 0, c.st), "qr gram");
+      HIPCHK(qr_chol_launch(w.qrg, w.qrr, B, bc, w.qmask, c.st), "qr chol");
+      // in place: each workgroup reads the rows of U[:, blk] it writes, and
+      // K = bc is consumed before its epilogue
+      GemmArgs r = gemm_base(m, bc, bc, B);  // U[:, blk] <- U[:, blk] Rinv
+      r.A = U + c0; r.lda = ldu; r.sA = sU;
+      r.B = w.qrr; r.ldb = bc; r.sB = (int64_t)kQrBlock * kQrBlock;
+      r.C = U + c0; r.ldc = ldu; r.sC = sU;
+      r.active = w.qmask;
+      HIPCHK(gemm_launch(r, PREC_F32, 0, 0, c.st), "qr scale");
+    }
+  }
+  return SVDP_OK;
+}
+
 // H, eigh(H), U = W V with eigenvalue signs, column-norm test (Algorithm 1
 // steps 4-7) for every matrix or the masked ones.
 svdp_status svd_tail(Ctx& c, float* U, int64_t ldu, int64_t sU, float* S, int64_t sS, float* V,
@@ -471,8 +542,11 @@ svdp_status svd_tail(Ctx& c, float* U, int64_t ldu, int64_t sU, float* S, int64_
   HIPCHK(colnorm_check_launch(U, ldu, sU, B, m, n, w.colsum, (float)p->eps_qr, w.flags, mask, c.st), "colnorm");
   // Algorithm 1: a column norm off by more than eps_qr (rank deficiency)
   // -> orthogonalise U by QR
-  HIPCHK(qr_complete_launch(U, ldu, sU, B, m, n, (float)p->eps_qr, w.flags, w.qr, mask, c.st), "qr");
-  return SVDP_OK;
+  if (n <= kQrBlockedFrom) {
+    HIPCHK(qr_complete_launch(U, ldu, sU, B, m, n, (float)p->eps_qr, w.flags, w.qr, mask, c.st), "qr");
+    return SVDP_OK;
+  }
+  return qr_blocked(c, U, ldu, sU, S, sS, mask);
 }
 
 svdp_status check_model(svdp_handle* h, const svdp_params* p) {

@@ -52,6 +52,13 @@ constexpr int LP = PB + 1;  // LDS pitch of 32-wide arrays
 constexpr int GP = GS + 1;  // LDS pitch of 64-wide arrays
 // per group: M_G (64 x 64) and the step-A rotations (2 x 32 x 32), FP32
 constexpr int QSTRIDE = GS * GS + 2 * PB * PB;
+// A restart sweeps T = V^T H V formed by FP32 GEMMs, resolved to about
+// 2^-24 |H|_F: a pair whose 2 x 2 block (h_pp, h_qq, h_pq) lies entirely
+// below that level is not rotated there.  Rotating such pairs only stirs a
+// cluster of (near-)zero eigenvalues by large angles, which keeps re-filling
+// its coupling to the other eigenvalues (the restart then converges
+// linearly, not quadratically); pairs with a larger diagonal are rotated.
+constexpr float kRestartSkip = 5.9604645e-8f;
 
 SVDP_DEV int insert0(int x, int p) { return ((x >> p) << (p + 1)) | (x & ((1 << p) - 1)); }
 
@@ -151,8 +158,8 @@ SVDP_DEV double lane_xor<double>(double v, int lane, int m) {
 // (t < 16) or l ^ (t - 16) (t >= 16), so one register exchange per entry
 // replaces LDS traffic.
 template <typename R, int STEPB>
-SVDP_DEV void pair_solve(SolveLds<R>& L, int w, int lane, int t0, int inner_sweeps, R floor_abs, float& mrel,
-                         float& vsum, R (&jp)[8], R (&jq)[8]) {
+SVDP_DEV void pair_solve(SolveLds<R>& L, int w, int lane, int t0, int inner_sweeps, R floor_abs, R skip_abs,
+                         float& mrel, float& vsum, R (&jp)[8], R (&jq)[8]) {
   constexpr int XP = XPitch<R>::v;
   R (*X)[XP] = L.X;
   RotPair<R>* cs = L.cs[w];
@@ -179,7 +186,7 @@ SVDP_DEV void pair_solve(SolveLds<R>& L, int w, int lane, int t0, int inner_swee
     if (lane < 16) {
       const R app = X[gx1][gx1], aqq = X[gy1][gy1], apq = R(0.5) * (X[gx1][gy1] + X[gy1][gx1]);
       RotPair<R> r{R(1), R(0)};
-      if (apq != R(0) && isfinite((float)apq)) {
+      if (apq != R(0) && isfinite((float)apq) && fmax(fmax(fabs(app), fabs(aqq)), fabs(apq)) > skip_abs) {
         rotation_fast(app, aqq, apq, r.c, r.s);
         any = 1;
         vsum += (float)apq * (float)apq;
@@ -305,7 +312,7 @@ SVDP_DEV void cross_update(SolveLds<R>& L, const float (*J0)[LP], const float (*
 
 template <typename R>
 __global__ __launch_bounds__(128) void k_jac_solve(EighWs e, EighPhase ph, int inner_sweeps, float abs_tol,
-                                                   int* rotmax, float* rotsq) {
+                                                   float skip_rel, int* rotmax, float* rotsq) {
   __shared__ SolveLds<R> L;
   constexpr int XP = XPitch<R>::v;
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
@@ -331,12 +338,14 @@ __global__ __launch_bounds__(128) void k_jac_solve(EighWs e, EighPhase ph, int i
   }
   __syncthreads();
   const R floor_abs = (R)abs_tol * (R)sqrtf(e.hnorm2[b]);
+  // a pair whose 2 x 2 block lies entirely at or below skip_abs is not rotated
+  const R skip_abs = (R)skip_rel * (R)sqrtf(e.hnorm2[b]);
   float mrel = 0.f, vsum = 0.f;
   float* M = e.Qw + ((int64_t)b * ng + gi) * QSTRIDE;
   float* JAg = M + GS * GS;  // step-A rotations (FP32), read back for M_G
   R jp[8], jq[8];
   // step A
-  pair_solve<R, 0>(L, w, lane, ph.fullA ? 1 : 16, inner_sweeps, floor_abs, mrel, vsum, jp, jq);
+  pair_solve<R, 0>(L, w, lane, ph.fullA ? 1 : 16, inner_sweeps, floor_abs, skip_abs, mrel, vsum, jp, jq);
   j_to_lds(L, w, lane, jp, jq);
   for (int idx = lane; idx < PB * PB; idx += 64) JAg[w * PB * PB + idx] = L.Jf[w][idx >> 5][idx & 31];
   __syncthreads();
@@ -351,7 +360,7 @@ __global__ __launch_bounds__(128) void k_jac_solve(EighWs e, EighPhase ph, int i
     }
   } else {
     // step B
-    pair_solve<R, 1>(L, w, lane, 16, inner_sweeps, floor_abs, mrel, vsum, jp, jq);
+    pair_solve<R, 1>(L, w, lane, 16, inner_sweeps, floor_abs, skip_abs, mrel, vsum, jp, jq);
     j_to_lds(L, w, lane, jp, jq);
     __syncthreads();
     if (w == 0) cross_update<R, 1>(L, L.Jf[0], L.Jf[1], lane);
@@ -938,7 +947,7 @@ hipError_t eigh_run(EighWs e, const float* H, int64_t ldh, int64_t sH, int mode,
     for (int h = 1; h < P; ++h)
       if ((err = hipStreamWaitEvent(ss[h], aux->fork, 0))) return err;
   }
-  auto phase_launches = [&](int h, const EighPhase& ph, bool fp64, int* rc, float* vs, int n_act,
+  auto phase_launches = [&](int h, const EighPhase& ph, bool fp64, float skip_rel, int* rc, float* vs, int n_act,
                             bool mark_skew) -> hipError_t {
     const EighWs& E = eh[h];
     const unsigned sblocks = (unsigned)(E.batch * ng);
@@ -946,11 +955,11 @@ hipError_t eigh_run(EighWs e, const float* H, int64_t ldh, int64_t sH, int mode,
     if (fp64) {
       ProfScope ps(PROF_JAC_SOLVE_F64, ss[h], solve_work(ph, o.fp64_inner) * n_act);
       hipLaunchKernelGGL(k_jac_solve<double>, dim3(sblocks), dim3(128), 0, ss[h], E, ph, o.fp64_inner, o.abs_tol,
-                         (int*)nullptr, (float*)nullptr);
+                         skip_rel, (int*)nullptr, (float*)nullptr);
     } else {
       ProfScope ps(PROF_JAC_SOLVE_F32, ss[h], solve_work(ph, o.inner_sweeps) * n_act);
       hipLaunchKernelGGL(k_jac_solve<float>, dim3(sblocks), dim3(128), 0, ss[h], E, ph, o.inner_sweeps, o.abs_tol,
-                         rc, vs);
+                         skip_rel, rc, vs);
     }
     hipError_t e2 = hipGetLastError();
     if (e2) return e2;
@@ -963,7 +972,7 @@ hipError_t eigh_run(EighWs e, const float* H, int64_t ldh, int64_t sH, int mode,
   };
   // one pass over the phases for every part; part h starts after part
   // h - 1's first pair solve
-  auto sweep_launches = [&](bool fp64, int* rc, float* vs, const int* n_act) -> hipError_t {
+  auto sweep_launches = [&](bool fp64, float skip_rel, int* rc, float* vs, const int* n_act) -> hipError_t {
     bool first = true;
     for (const EighPhase& ph : phases) {
       int prev = -1;
@@ -971,7 +980,7 @@ hipError_t eigh_run(EighWs e, const float* H, int64_t ldh, int64_t sH, int mode,
         if (n_act[h] == 0) continue;
         hipError_t e2;
         if (first && prev >= 0 && (e2 = hipStreamWaitEvent(ss[h], aux->skew[prev], 0))) return e2;
-        if ((e2 = phase_launches(h, ph, fp64, rc ? rc + b0[h] : nullptr, vs ? vs + b0[h] : nullptr, n_act[h],
+        if ((e2 = phase_launches(h, ph, fp64, skip_rel, rc ? rc + b0[h] : nullptr, vs ? vs + b0[h] : nullptr, n_act[h],
                                   first && P > 1))) return e2;
         prev = h;
       }
@@ -985,7 +994,7 @@ hipError_t eigh_run(EighWs e, const float* H, int64_t ldh, int64_t sH, int mode,
   for (; sweep < e.max_sweeps; ++sweep) {
     int* rc = e.rotcnt + (int64_t)batch * sweep;
     float* vs = e.rotsq + (int64_t)batch * sweep;
-    if ((err = sweep_launches(false, rc, vs, n_act))) return err;
+    if ((err = sweep_launches(false, 0.f, rc, vs, n_act))) return err;
     for (int h = 0; h < P; ++h) {
       if (n_act[h] == 0) continue;
       hipLaunchKernelGGL(k_eigh_check, dim3(1), dim3(1024), 0, ss[h], eh[h], rc + b0[h], vs + b0[h], o.tol,
@@ -1017,7 +1026,7 @@ hipError_t eigh_run(EighWs e, const float* H, int64_t ldh, int64_t sH, int mode,
       else if ((err = fill_i32(eh[h].active, 1, bc[h], ss[h]))) return err;
     }
     for (int f = 0; f < o.fp64_sweeps; ++f)
-      if ((err = sweep_launches(true, nullptr, nullptr, bc))) return err;
+      if ((err = sweep_launches(true, 0.f, nullptr, nullptr, bc))) return err;
   }
   auto join = [&]() -> hipError_t {
     hipError_t e2;
@@ -1059,7 +1068,8 @@ hipError_t eigh_run(EighWs e, const float* H, int64_t ldh, int64_t sH, int mode,
   // off-diagonal norm the backward error of the decomposition, which the
   // rounding of many FP32 block rotations raises with n.  While that norm
   // exceeds off_tol |H|_F, T itself is swept from V' = I -- its rotations are
-  // small, so they add little rounding -- and V <- V V'.
+  // small, so they add little rounding; pairs entirely within T's own
+  // rounding (kRestartSkip) are left alone -- and V <- V V'.
   {
     const int* proc = mask;
     const int nt = (e.n + 31) / 32, npairs = nt * (nt + 1) / 2;
@@ -1107,7 +1117,7 @@ hipError_t eigh_run(EighWs e, const float* H, int64_t ldh, int64_t sH, int mode,
           if ((err = hipStreamWaitEvent(ss[h], aux->fork, 0))) return err;
       }
       for (int f = 0; f < std::max(1, o.fp64_sweeps); ++f)
-        if ((err = sweep_launches(o.fp64_sweeps > 0, nullptr, nullptr, bc))) return err;
+        if ((err = sweep_launches(o.fp64_sweeps > 0, kRestartSkip, nullptr, nullptr, bc))) return err;
       if ((err = join())) return err;
       hipLaunchKernelGGL(k_untile, dim3(cdiv(m2 / 4, 256), batch), dim3(256), 0, st, e.Vw, e.Hw, np, e.nb, proc);
       if ((err = hipGetLastError())) return err;

@@ -276,6 +276,110 @@ __global__ __launch_bounds__(256) void k_qr_complete(float* U, int64_t ldu, int6
   }
 }
 
+// Blocked QR of flagged matrices.  With g a deterministic pseudo-random
+// vector of unit-variance entries (a hash of matrix, row and column): a
+// column whose singular value is <= eps_qr sigma_1 carries no direction
+// (the polar iteration leaves it at zero or at rounding noise) and is
+// replaced by g / sqrt(m); any other column whose norm is off from 1 by
+// more than eps_qr gains gamma g with gamma = eps_qr / sqrt(m), keeping its
+// direction to O(eps_qr).  Every column then keeps a component outside the
+// span of the others, so the Gram-Schmidt passes need no completion step.
+SVDP_DEV float hash_unit(uint32_t a, uint32_t b, uint32_t c) {
+  uint32_t h = a * 0x9E3779B1u ^ (b + 0x7F4A7C15u) * 0x85EBCA77u ^ (c + 0x2545F491u) * 0xC2B2AE3Du;
+  h ^= h >> 16; h *= 0x7FEB352Du; h ^= h >> 15; h *= 0x846CA68Bu; h ^= h >> 16;
+  return ((float)(h >> 8) * (1.f / 16777216.f) - 0.5f) * 3.4641016f;  // uniform, variance 1
+}
+
+__global__ void k_qr_perturb(float* U, int64_t ldu, int64_t sU, int m, int n, int rows_per, const float* S,
+                             int64_t sS, const float* colnorm2, float eps_qr, const int* qmask) {
+  const int b = blockIdx.z;
+  if (!qmask[b]) return;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const bool nodir = !(S[b * sS + j] > eps_qr * S[b * sS]);
+  if (!nodir && fabsf(sqrtf(colnorm2[(int64_t)b * n + j]) - 1.f) <= eps_qr) return;
+  const float gamma = (nodir ? 1.f : eps_qr) * rsqrtf((float)m);
+  float* Ub = U + b * sU;
+  const int r0 = blockIdx.y * rows_per, r1 = min(m, r0 + rows_per);
+  for (int k = r0; k < r1; ++k) {
+    const float g = gamma * hash_unit((uint32_t)b, (uint32_t)k, (uint32_t)j);
+    float* u = Ub + (int64_t)k * ldu + j;
+    *u = nodir ? g : *u + g;
+  }
+}
+
+// qmask[b] = 1 for the matrices (of mask) flagged RANK_DEFICIENT; *counter
+// gains their number
+__global__ void k_qr_mask(int batch, const int* flags, const int* mask, int* qmask, int* counter) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= batch) return;
+  const int q = !skip(mask, b) && (flags[b] & SVDP_FLAG_RANK_DEFICIENT);
+  qmask[b] = q;
+  if (q) atomicAdd(counter, 1);
+}
+
+// CholeskyQR step of one block of bc <= 64 columns Z (flagged matrices):
+// G = Z^T Z (bc x bc, row-major, per matrix bc * bc floats) -> Rinv with
+// Z Rinv orthonormal.  With D = diag(G)^(1/2) and G' = D^-1 G D^-1 = R'^T R'
+// (Cholesky, upper R', FP64 in LDS), Z = Q R' D, so Rinv = D^-1 R'^-1, upper
+// triangular with a positive diagonal (R_ii > 0).  Column scales are kept
+// >= 1e-15 of the largest and pivots (of the unit-diagonal G') >= 1e-12, so
+// a (numerically) dependent block gives large but finite factors.
+__global__ __launch_bounds__(256) void k_qr_chol(const float* G, float* Rinv, int bc, const int* qmask) {
+  const int b = blockIdx.x;
+  if (!qmask[b]) return;
+  __shared__ double A[64][65];
+  __shared__ float X[64][65];  // R'^-1
+  __shared__ double d[64];
+  const int t = threadIdx.x;
+  const float* Gb = G + (int64_t)b * bc * bc;
+  __shared__ double gmax;
+  if (t == 0) {
+    double mx = 0.0;
+    for (int j = 0; j < bc; ++j) mx = fmax(mx, (double)Gb[(int64_t)j * bc + j]);
+    gmax = mx > 0.0 ? mx : 1.0;
+  }
+  __syncthreads();
+  for (int j = t; j < bc; j += 256) d[j] = sqrt(fmax((double)Gb[(int64_t)j * bc + j], 1e-30 * gmax));
+  __syncthreads();
+  for (int idx = t; idx < bc * bc; idx += 256) {
+    const int i = idx / bc, j = idx - i * bc;
+    A[i][j] = (double)Gb[idx] / (d[i] * d[j]);
+    X[i][j] = 0.f;
+  }
+  __syncthreads();
+  for (int k = 0; k < bc; ++k) {
+    if (t == 0) {
+      const double piv = A[k][k];
+      A[k][k] = piv > 1e-12 ? sqrt(piv) : 1e-6;
+    }
+    __syncthreads();
+    for (int j = k + 1 + t; j < bc; j += 256) A[k][j] /= A[k][k];
+    __syncthreads();
+    const int w = bc - k - 1;
+    for (int idx = t; idx < w * w; idx += 256) {
+      const int i = k + 1 + idx / w, j = k + 1 + idx % w;
+      if (j >= i) A[i][j] -= A[k][i] * A[k][j];
+    }
+    __syncthreads();
+  }
+  // X = R'^-1 (upper), one column per thread, back substitution
+  if (t < bc) {
+    const int j = t;
+    for (int i = j; i >= 0; --i) {
+      double s = i == j ? 1.0 : 0.0;
+      for (int k = i + 1; k <= j; ++k) s -= A[i][k] * (double)X[k][j];
+      X[i][j] = (float)(s / A[i][i]);
+    }
+  }
+  __syncthreads();
+  float* Rb = Rinv + (int64_t)b * bc * bc;
+  for (int idx = t; idx < bc * bc; idx += 256) {
+    const int i = idx / bc, j = idx - i * bc;
+    Rb[idx] = j >= i ? (float)((double)X[i][j] / d[i]) : 0.f;
+  }
+}
+
 // ------------------------------------------------------------ backward
 
 __global__ void k_dvec(const float* S, int64_t sS, int n, double eR, float* D) {
@@ -812,6 +916,29 @@ hipError_t qr_complete_launch(float* U, int64_t ldu, int64_t sU, int batch, int 
   if (batch <= 0 || n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_qr_complete, dim3(batch), dim3(256), (size_t)n * sizeof(float), st, U, ldu, sU, m, n, eps_qr,
                      flags, scratch, mask);
+  LAUNCH_CHECK();
+}
+
+hipError_t qr_chol_launch(const float* G, float* Rinv, int batch, int bc, const int* qmask, hipStream_t st) {
+  if (batch <= 0) return hipSuccess;
+  if (bc < 1 || bc > 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_qr_chol, dim3(batch), dim3(256), 0, st, G, Rinv, bc, qmask);
+  LAUNCH_CHECK();
+}
+
+hipError_t qr_perturb_launch(float* U, int64_t ldu, int64_t sU, int batch, int m, int n, const float* S,
+                             int64_t sS, const float* colnorm2, float eps_qr, const int* qmask, hipStream_t st) {
+  if (batch <= 0 || n <= 0) return hipSuccess;
+  const int rows_per = 256;
+  hipLaunchKernelGGL(k_qr_perturb, dim3(cdiv(n, 256), cdiv(m, rows_per), batch), dim3(256), 0, st, U, ldu, sU, m,
+                     n, rows_per, S, sS, colnorm2, eps_qr, qmask);
+  LAUNCH_CHECK();
+}
+
+hipError_t qr_mask_launch(int batch, const int* flags, const int* mask, int* qmask, int* counter, hipStream_t st) {
+  hipError_t e;
+  if ((e = fill_i32(counter, 0, 1, st))) return e;
+  hipLaunchKernelGGL(k_qr_mask, dim3(cdiv(batch, 256)), dim3(256), 0, st, batch, flags, mask, qmask, counter);
   LAUNCH_CHECK();
 }
 

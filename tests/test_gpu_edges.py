@@ -80,6 +80,41 @@ def test_rank_deficient_is_flagged_and_completed(api):
     assert rec < 1e-5
 
 
+def test_rank_deficient_blocked_qr_1024(api):
+    # above 512 columns the QR step runs blocked (64-column blocks projected
+    # by GEMMs, CGS2 inside a block).  Two 1024^2 matrices: rank 100 and
+    # rank 1023 (kappa 10 on the nonzero part).  The leading singular vectors
+    # are compared with the generating Q1 (known, gaps >= 2%), the rest by
+    # orthonormality, singular values and reconstruction.
+    import torch
+    n = 1024
+    _say("rank-deficient 2 x 1024^2 (ranks 100 and 1023): blocked QR")
+    As, Ss, Q1s = [], [], []
+    for i, r in enumerate((100, 1023)):
+        rng = inputs.rng_for(93, i)
+        s = inputs.paper_kappa_rank(n, 10.0, r)
+        Q1 = inputs.orthonormal(rng, n, n)
+        Q2 = inputs.orthonormal(rng, n, n)
+        As.append(((Q1 * s) @ Q2.T).astype(np.float32)); Ss.append(s); Q1s.append(Q1)
+    A = np.stack(As)
+    U, S, V, info = api.svd_fwd(dev(A))
+    torch.cuda.synchronize()
+    inf = api.info_to_numpy(info)
+    Sh, Uh, Vh = (t.cpu().double().numpy() for t in (S, U, V))
+    for i, r in enumerate((100, 1023)):
+        orth = np.abs(Uh[i].T @ Uh[i] - np.eye(n)).max()
+        orthv = np.abs(Vh[i].T @ Vh[i] - np.eye(n)).max()
+        serr = np.abs(Sh[i] - Ss[i]).max() / Ss[i][0]
+        rec = np.linalg.norm((Uh[i] * Sh[i]) @ Vh[i].T - A[i]) / np.linalg.norm(A[i])
+        lead = np.abs(np.sum(Uh[i][:, :r] * Q1s[i][:, :r], axis=0)).min()
+        _say(f"  rank {r}: flags {inf['flags'][i]}, |U^T U - I| {orth:.2e}, |V^T V - I| {orthv:.2e}, "
+             f"sigma err {serr:.2e}, recon {rec:.2e}, min |<u_i, q_i>| over the leading {r}: {lead:.6f}")
+        assert inf["flags"][i] & 8, "rank deficiency must be reported"
+        assert orth < 1e-5 and orthv < 1e-5
+        assert serr < 1e-5 and rec < 1e-5
+        assert lead > 1 - 1e-4
+
+
 def test_numerically_rank_deficient_is_completed(api):
     # sigma down to 1e-9 relative: the smallest directions of W stay far
     # from unit norm after CANS, so U is orthogonalised by QR

@@ -5,9 +5,10 @@ kappa scheme s_i = kappa^((n - i)/(n - 1)).  The paper's two measures:
   reconstruction  |M - U Sigma V^T|_F / |M|_F
   orthogonality   max(|U^T U - I|_F, |V^T V - I|_F) / |I|_F
 
-are evaluated in FP64 and held to the FP32 stop tolerance of CANS (1e-5),
-with the values printed in Tables 1 and 2 (mean of 100 matrices on another
-GPU) reported beside them as context.  The learned BF16 path runs on the same
+are evaluated in FP64 and held to REC_TOL (the reconstruction adds CANS's
+stop tolerance of 1e-5 on the relative step, the eigensolver's 6e-6 and
+FP32 GEMM rounding) and ORTH_TOL, with the values printed in Tables 1 and 2
+(mean of 100 matrices on another GPU) reported beside them as context.  The learned BF16 path runs on the same
 matrices with its own bound: a normwise singular-value error of 1e-3."""
 import json
 import os
@@ -23,6 +24,8 @@ pytestmark = pytest.mark.gpu
 
 N = 4096
 KAPPAS = [10.0, 1e3, 1e6]
+REC_TOL = 1.5e-5
+ORTH_TOL = 1e-5
 GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_hyperparameters.json")))
 
 
@@ -95,7 +98,7 @@ def test_paper_tables_4096(api, handle, haar, kappa):
          f"reconstruction {rec:.2e} (paper {_paper_value('table1_reconstruction_fp32', kappa):.1e}), "
          f"orthogonality {orth:.2e} (paper {_paper_value('table2_orthogonality_fp32', kappa):.1e})")
     assert not np.any(inf["flags"] & (16 | 32))
-    assert rec < 1e-5 and orth < 1e-5
+    assert rec < REC_TOL and orth < ORTH_TOL
     Sh = S[0].cpu().double().numpy()
     sig = np.abs(Sh - s).max() / s[0]
     _say(f"  plain-fp32 normwise sigma error {sig:.2e}")
@@ -110,7 +113,39 @@ def test_paper_tables_4096(api, handle, haar, kappa):
     _say(f"  learned-bf16 (iters {inf['iters'][0]}, flags {inf['flags'][0]}): sigma error {sig_l:.2e}, "
          f"reconstruction {rec_l:.2e}, orthogonality {orth_l:.2e}")
     assert not np.any(inf["flags"] & (16 | 32))
-    assert sig_l < 1e-3 and orth_l < 1e-5
+    assert sig_l < 1e-3 and orth_l < ORTH_TOL
+
+
+@pytest.mark.parametrize("rank", [1, 64, 1024, 4095, 4096])
+def test_paper_lowrank_tables_4096(api, handle, haar, rank):
+    """Appendix tables of low-rank 4096^2 matrices (Tables 5 and 6):
+    s_i = kappa^((r - i)/(r - 1)) for i <= r, zero beyond, kappa = 10 (the
+    tables leave kappa unstated; 10 is the paper's square-matrix setting).
+    Below full rank CANS returns a partial isometry, the column-norm test
+    flags it, and Algorithm 1's QR step (blocked at this size) completes U."""
+    import torch
+    Q1, Q2 = haar
+    s = inputs.paper_kappa_rank(N, 10.0, rank)
+    Md = torch.from_numpy(((Q1 * s) @ Q2.T).astype(np.float32)).cuda()
+    t0 = time.time()
+    U, S, V, info = api.svd_fwd(Md[None], handle=handle)
+    torch.cuda.synchronize()
+    dt = time.time() - t0
+    inf = api.info_to_numpy(info)
+    rec, orth = _measures(Md, U[0], S[0], V[0])
+    sig = np.abs(S[0].cpu().double().numpy() - s).max() / s[0]
+    _say(f"  rank {rank}: {dt * 1e3:.0f} ms, flags {inf['flags'][0]}, sigma error {sig:.2e}, "
+         f"reconstruction {rec:.2e} (paper {_paper_value_r('table5_reconstruction_lowrank_fp32', rank):.1e}), "
+         f"orthogonality {orth:.2e} (paper {_paper_value_r('table6_orthogonality_lowrank_fp32', rank):.1e})")
+    assert not np.any(inf["flags"] & (16 | 32))
+    if rank < N:
+        assert inf["flags"][0] & 8, "rank deficiency must be reported"
+    assert rec < REC_TOL and orth < ORTH_TOL and sig < 1e-5
+
+
+def _paper_value_r(table, rank):
+    t = GOLDEN[table]
+    return t["err"][t["rank"].index(rank)]
 
 
 def _expected_grad_norm(s):
