@@ -61,6 +61,15 @@ typedef enum {
   SVDP_BOUND_USER = 2          /* caller's [sigma_min, sigma_max] per matrix */
 } svdp_bound;
 
+/* Iteration polynomial of the conservative FP32 path (the appendix's
+ * ablation of polar iterations built on matrix products). */
+typedef enum {
+  SVDP_POLY_CANS3 = 0, /* interval-optimal odd cubic (CANS), the method's default */
+  SVDP_POLY_NS = 1,    /* classical Newton-Schulz 1.5 x - 0.5 x^3, no preprocessing */
+  SVDP_POLY_CANS5 = 2  /* interval-optimal odd quintic (Remez exchange): three products
+                          per step (X^T X, G G, X P), with its own preprocessing */
+} svdp_poly;
+
 /* per-matrix result flags (svdp_info.flags) */
 #define SVDP_FLAG_NOT_CONVERGED 1        /* CANS stopped at max_iters above tol */
 #define SVDP_FLAG_FALLBACK_USED 2        /* learned/user bound failed; conservative CANS rerun */
@@ -121,6 +130,8 @@ typedef struct {
                               sqrt(sum h_pq^2) <= jacobi_fro_tol |H|_F: a normwise test, met
                               sweeps before the relative one when small eigenvalues need many
                               sweeps for relative accuracy (3e-4; 0 disables it) */
+  int32_t poly;            /* svdp_poly (CANS3); other values need bound CONSERVATIVE and
+                              precision FP32 */
 } svdp_params;
 
 /* per-matrix diagnostics, device array of `batch` records */
@@ -293,6 +304,16 @@ svdp_status svdp_adam_step(float* params, float* m, float* v, const float* grad,
  * Returns the preprocessing t (kind 0) or lo (kind 1) in *t_out. */
 svdp_status svdp_cans_table(int32_t kind, double delta, int32_t pre_iters, double lo,
                             int32_t steps, double* table, double* t_out);
+
+/* HOST helper: the conservative coefficient table (c1, c3, c5) of
+ * p(x) = c1 x + c3 x^3 + c5 x^5 for `steps` steps of iteration polynomial
+ * `poly` into host `table` (steps x 3 doubles): CANS3 as svdp_cans_table
+ * kind 0 with c5 = 0; NS (1.5, -0.5, 0) throughout, t = 0; CANS5 the
+ * interval-optimal quintics, pre_iters of them on [t, 1] (t the smallest
+ * value they map into [1-delta, 1+delta]), then the interval recursion from
+ * [1-delta, 1+delta].  Returns t in *t_out (may be null). */
+svdp_status svdp_poly_table(int32_t poly, double delta, int32_t pre_iters, int32_t steps, double* table,
+                            double* t_out);
 
 /* Kernel timing for benchmarks: while enabled, every launch of the kernel
  * classes below is bracketed by HIP events on its stream.  read() waits for

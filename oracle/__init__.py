@@ -11,7 +11,9 @@ Contents (each function cites the passage of the paper it follows):
   Algorithm 2 (polar backward), the classical full-rank SVD backward.
 * numpy part (FP64): the normalisation of the appendix on Newton-Schulz
   initialisation (Algorithm 3), the degree-3 CANS polynomial and its
-  interval recursion, the CANS polar iteration, the symmetric EVD backward
+  interval recursion, the CANS polar iteration, the iteration variants of
+  the appendix's polar-iteration ablation (classical Newton-Schulz, the
+  degree-5 interval-optimal polynomial), the symmetric EVD backward
   (the EVD pseudo-gradient theorem), the sketch features and the small MLP
   (forward, backward, pinball loss, Adam) of the learned interval predictor.
 
@@ -294,6 +296,119 @@ def cans_schedule_interval(lo: float, max_iters: int = 50):
         out.append((al, be))
         errs.append(max(1.0 - a, b - 1.0))
     return np.array(out), errs
+
+
+def cans5_poly(a: float, b: float):
+    """Odd quintic p(x) = c1 x + c3 x^3 + c5 x^5 closest to 1 in max norm on
+    [a, b]: the degree-5 member of the interval-optimal family (the appendix's
+    ablation of polar iterations; "higher-degree CANS").  Chebyshev's
+    alternation theorem fixes it by equioscillation of the error 1 - p at four
+    points a < x1 < x2 < b with signs (+, -, +, -), x1 and x2 stationary.
+    Solved here as that nonlinear system in (c1, c3, c5, E, x1, x2) by
+    Newton's method (scipy's hybrid solver).  A very narrow interval takes the
+    limit q(x / x0) with q(u) = (15 u - 10 u^3 + 3 u^5) / 8 (p(x0) = 1,
+    p'(x0) = p''(x0) = 0).  Returns (c1, c3, c5, lo, hi), [lo, hi] the image
+    of [a, b]."""
+    from scipy.optimize import fsolve
+    a = float(a); b = float(b)
+    if b - a <= 1e-6 * b:
+        x0 = 0.5 * (a + b)
+        c = (15.0 / (8.0 * x0), -10.0 / (8.0 * x0 ** 3), 3.0 / (8.0 * x0 ** 5))
+        p = lambda x: c[0] * x + c[1] * x ** 3 + c[2] * x ** 5
+        return c[0], c[1], c[2], p(a), p(b)
+
+    def p(c, x):
+        return c[0] * x + c[1] * x ** 3 + c[2] * x ** 5
+
+    def dp(c, x):
+        return c[0] + 3 * c[1] * x ** 2 + 5 * c[2] * x ** 4
+
+    # work in u = x / b so that the system is scaled
+    ua = a / b
+
+    def eqs(z):
+        c1, c3, c5, E, u1, u2 = z
+        c = (c1, c3, c5)
+        return [1 - p(c, ua) - E, 1 - p(c, u1) + E, 1 - p(c, u2) - E, 1 - p(c, 1.0) + E, dp(c, u1), dp(c, u2)]
+
+    u1 = ua + (1 - ua) * 0.25
+    u2 = ua + (1 - ua) * 0.75
+    pts = np.array([ua, u1, u2, 1.0])
+    M = np.stack([pts, pts ** 3, pts ** 5, np.array([1.0, -1.0, 1.0, -1.0])], axis=1)
+    c1, c3, c5, E = np.linalg.solve(M, np.ones(4))
+    import warnings
+    with warnings.catch_warnings():
+        # near-degenerate (very narrow) intervals stop short of xtol at FP64 rounding
+        warnings.simplefilter("ignore", RuntimeWarning)
+        z = fsolve(eqs, [c1, c3, c5, E, u1, u2], xtol=1e-13, maxfev=20000)
+    c1, c3, c5, E, u1, u2 = z
+    # back to x: p(x) = q(x / b)
+    c = (c1 / b, c3 / b ** 3, c5 / b ** 5)
+    xs = [a, u1 * b, u2 * b, b]
+    vals = [p(c, x) for x in xs]
+    return c[0], c[1], c[2], min(vals[0], vals[2]), max(vals[1], vals[3])
+
+
+def cans5_preprocess_t(delta: float = 0.99, steps: int = 2):
+    """Smallest t such that `steps` optimal quintic steps from [t, 1] land in
+    [1 - delta, 1 + delta] (bisection on t, as for the cubic)."""
+    def err(t):
+        a, b = t, 1.0
+        for _ in range(steps):
+            *_, a, b = cans5_poly(a, b)
+        return max(1.0 - a, b - 1.0)
+    lo, hi = 1e-16, 1.0
+    for _ in range(200):
+        mid = np.sqrt(lo * hi)
+        if err(mid) <= delta:
+            hi = mid
+        else:
+            lo = mid
+    return hi
+
+
+def poly_schedule_conservative(poly: int, delta: float = 0.99, pre_steps: int = 2, max_iters: int = 50):
+    """Coefficients (c1, c3, c5) per step of the conservative path for an
+    iteration polynomial: 0 the CANS cubic (c5 = 0), 1 classical Newton-Schulz
+    (1.5, -0.5, 0) throughout (no preprocessing), 2 the CANS quintic with its
+    preprocessing on [t, 1] and the interval recursion from [1 - delta,
+    1 + delta].  Returns (table (max_iters, 3), t)."""
+    if poly == 1:
+        return np.tile([1.5, -0.5, 0.0], (max_iters, 1)), 0.0
+    if poly == 0:
+        tab = cans_schedule_conservative(delta, pre_steps, max_iters)
+        return np.concatenate([tab, np.zeros((max_iters, 1))], axis=1), cans_preprocess_t(delta, pre_steps)
+    t = cans5_preprocess_t(delta, pre_steps)
+    out = []
+    a, b = t, 1.0
+    for _ in range(min(pre_steps, max_iters)):
+        c1, c3, c5, a, b = cans5_poly(a, b)
+        out.append((c1, c3, c5))
+    a, b = 1.0 - delta, 1.0 + delta
+    while len(out) < max_iters:
+        c1, c3, c5, a, b = cans5_poly(a, b)
+        out.append((c1, c3, c5))
+    return np.array(out), t
+
+
+def poly_polar(A, table, tol: float = 1e-5, max_iters: int = 64):
+    """Polar iteration in FP64 with per-step odd polynomials
+    X <- c1 X + c3 X G + c5 X G^2, G = X^T X (rows of `table`), after the
+    Algorithm 3 scaling, with the stop test of the CANS iteration.
+    Returns (W, iterations)."""
+    A = np.asarray(A, dtype=np.float64)
+    X = A / ns_normaliser(A)
+    it = 0
+    for k in range(min(max_iters, len(table))):
+        c1, c3, c5 = table[k]
+        G = X.T @ X
+        Xn = c1 * X + X @ (c3 * G + c5 * (G @ G))
+        it = k + 1
+        done = np.linalg.norm(Xn - X) <= tol * np.linalg.norm(Xn)
+        X = Xn
+        if done:
+            break
+    return X, it
 
 
 def cans_polar(A, table, tol: float = 1e-5, scale: float | None = None, max_iters: int = 50):

@@ -21,6 +21,7 @@ STATUS = {0: "ok", 1: "invalid argument", 2: "bad shape", 3: "workspace too smal
 
 PREC_FP32, PREC_BF16 = 0, 1
 BOUND_CONSERVATIVE, BOUND_LEARNED, BOUND_USER = 0, 1, 2
+POLY_CANS3, POLY_NS, POLY_CANS5 = 0, 1, 2
 FLAG_NOT_CONVERGED = 1
 FLAG_FALLBACK_USED = 2
 FLAG_NEG_EIGENVALUE = 4
@@ -43,7 +44,7 @@ class Params(ctypes.Structure):
         ("eps_K", c_dbl), ("eps_R", c_dbl), ("eps_T", c_dbl),
         ("margin_max", c_dbl), ("margin_min", c_dbl),
         ("user_bounds", c_vp), ("probe", c_vp),
-        ("eigh_off_tol", c_dbl), ("eigh_restarts", c_i32), ("jacobi_fro_tol", c_dbl),
+        ("eigh_off_tol", c_dbl), ("eigh_restarts", c_i32), ("jacobi_fro_tol", c_dbl), ("poly", c_i32),
     ]
 
 
@@ -86,6 +87,7 @@ SIGNATURES = {
                                c_vp]),
     "svdp_cans_table": (c_i32, [c_i32, c_dbl, c_i32, c_dbl, c_i32, ctypes.POINTER(c_dbl),
                                 ctypes.POINTER(c_dbl)]),
+    "svdp_poly_table": (c_i32, [c_i32, c_dbl, c_i32, c_i32, ctypes.POINTER(c_dbl), ctypes.POINTER(c_dbl)]),
     "svdp_profile_enable": (None, [ctypes.c_int]),
     "svdp_profile_reset": (None, []),
     "svdp_profile_read": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(c_dbl), ctypes.POINTER(c_i64),

@@ -287,6 +287,15 @@ def adam_step(P, m, v, g, t, lr, b1=0.9, b2=0.999, eps=1e-8):
           "svdp_adam_step")
 
 
+def poly_table(poly, steps, delta=0.99, pre_iters=2):
+    """Host coefficient table (steps, 3) of (c1, c3, c5) of the conservative
+    schedule of iteration polynomial `poly` (POLY_CANS3, POLY_NS, POLY_CANS5)."""
+    tab = (ctypes.c_double * (3 * steps))()
+    t = ctypes.c_double()
+    check(load().svdp_poly_table(poly, delta, pre_iters, steps, tab, ctypes.byref(t)), "poly_table")
+    return np.array(tab[:]).reshape(steps, 3), t.value
+
+
 def cans_table(kind, steps, delta=0.99, pre_iters=2, lo=1e-3):
     """Host coefficient table (steps, 2) of the library's scheduler."""
     tab = (ctypes.c_double * (2 * steps))()

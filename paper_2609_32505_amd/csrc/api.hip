@@ -99,6 +99,113 @@ void table_interval(double lo, int steps, double* tab) {
   for (int k = 0; k < steps; ++k) cans_poly(a, b, tab[2 * k], tab[2 * k + 1], a, b);
 }
 
+// Odd quintic p(x) = c1 x + c3 x^3 + c5 x^5 closest to 1 in max norm on
+// [a, b], the degree-5 analogue of cans_poly: the error 1 - p equioscillates
+// (signs +, -, +, -) at a, at the two interior stationary points and at b.
+// Remez exchange in FP64 from Chebyshev-spaced points: solve
+// p(x_i) + s_i E = 1 for (c1, c3, c5, E), move the interior points to the
+// roots of p' (a quadratic in x^2), repeat.  A very narrow interval takes the
+// limit q(x / x0), q(u) = (15 u - 10 u^3 + 3 u^5) / 8 (p = 1, p' = p'' = 0 at
+// x0), which is increasing.  [lo, hi] is the image of [a, b].
+static bool solve4(double M[4][5], double x[4]) {
+  for (int col = 0; col < 4; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < 4; ++r)
+      if (std::fabs(M[r][col]) > std::fabs(M[piv][col])) piv = r;
+    if (M[piv][col] == 0.0) return false;
+    for (int k = 0; k < 5; ++k) std::swap(M[col][k], M[piv][k]);
+    for (int r = 0; r < 4; ++r) {
+      if (r == col) continue;
+      const double f = M[r][col] / M[col][col];
+      for (int k = col; k < 5; ++k) M[r][k] -= f * M[col][k];
+    }
+  }
+  for (int r = 0; r < 4; ++r) x[r] = M[r][4] / M[r][r];
+  return true;
+}
+
+void cans5_poly(double a, double b, double* c, double& lo, double& hi) {
+  auto p = [&](double x) { const double x2 = x * x; return x * (c[0] + x2 * (c[1] + x2 * c[2])); };
+  auto limit = [&]() {
+    const double x0 = 0.5 * (a + b);
+    c[0] = 15.0 / (8.0 * x0);
+    c[1] = -10.0 / (8.0 * x0 * x0 * x0);
+    c[2] = 3.0 / (8.0 * x0 * x0 * x0 * x0 * x0);
+    lo = p(a);
+    hi = p(b);
+  };
+  if (b - a <= 1e-6 * b) { limit(); return; }
+  const double pi = 3.14159265358979323846;
+  double x[4] = {a, a + (b - a) * (1.0 - std::cos(pi / 3.0)) / 2.0, a + (b - a) * (1.0 - std::cos(2.0 * pi / 3.0)) / 2.0, b};
+  const double s[4] = {1.0, -1.0, 1.0, -1.0};
+  double sol[4] = {0, 0, 0, 0};
+  for (int it = 0; it < 100; ++it) {
+    double M[4][5];
+    for (int i = 0; i < 4; ++i) {
+      const double x2 = x[i] * x[i];
+      M[i][0] = x[i]; M[i][1] = x[i] * x2; M[i][2] = x[i] * x2 * x2; M[i][3] = s[i]; M[i][4] = 1.0;
+    }
+    if (!solve4(M, sol)) { limit(); return; }
+    c[0] = sol[0]; c[1] = sol[1]; c[2] = sol[2];
+    // p'(x) = c1 + 3 c3 x^2 + 5 c5 x^4 = 0
+    const double disc = 9.0 * c[1] * c[1] - 20.0 * c[0] * c[2];
+    if (!(disc > 0.0) || c[2] == 0.0) { limit(); return; }
+    double y1 = (-3.0 * c[1] - std::sqrt(disc)) / (10.0 * c[2]);
+    double y2 = (-3.0 * c[1] + std::sqrt(disc)) / (10.0 * c[2]);
+    if (y1 > y2) std::swap(y1, y2);
+    if (!(y1 > a * a && y2 < b * b)) { limit(); return; }
+    const double n1 = std::sqrt(y1), n2 = std::sqrt(y2);
+    const double move = std::max(std::fabs(n1 - x[1]), std::fabs(n2 - x[2]));
+    x[1] = n1;
+    x[2] = n2;
+    if (move <= 1e-15 * b) break;
+  }
+  lo = std::min(p(a), p(x[2]));
+  hi = std::max(p(x[1]), p(b));
+}
+
+// smallest t whose `steps` optimal quintic steps from [t, 1] land in [1-delta, 1+delta]
+double preprocess_t5(double delta, int steps) {
+  auto err = [&](double t) {
+    double a = t, b = 1.0, c[3];
+    for (int k = 0; k < steps; ++k) cans5_poly(a, b, c, a, b);
+    return std::max(1.0 - a, b - 1.0);
+  };
+  double lo = 1e-16, hi = 1.0;
+  for (int it = 0; it < 200; ++it) {
+    double mid = std::sqrt(lo * hi);
+    if (err(mid) <= delta) hi = mid;
+    else lo = mid;
+  }
+  return hi;
+}
+
+// Conservative coefficient table (c1, c3, c5) per step for each iteration
+// polynomial: CANS cubic (c5 = 0), classical Newton-Schulz (1.5, -0.5, 0)
+// from the first step (no preprocessing, t = 0), or the CANS quintic with its
+// own preprocessing.
+void table_poly(int poly, double delta, int pre, int steps, double* tab, double* t_out) {
+  if (poly == SVDP_POLY_NS) {
+    for (int k = 0; k < steps; ++k) { tab[3 * k] = 1.5; tab[3 * k + 1] = -0.5; tab[3 * k + 2] = 0.0; }
+    if (t_out) *t_out = 0.0;
+    return;
+  }
+  if (poly == SVDP_POLY_CANS5) {
+    const double t = preprocess_t5(delta, pre);
+    double a = t, b = 1.0;
+    int k = 0;
+    for (; k < std::min(pre, steps); ++k) cans5_poly(a, b, tab + 3 * k, a, b);
+    a = 1.0 - delta;
+    b = 1.0 + delta;
+    for (; k < steps; ++k) cans5_poly(a, b, tab + 3 * k, a, b);
+    if (t_out) *t_out = t;
+    return;
+  }
+  double tab2[128];
+  table_conservative(delta, pre, steps, tab2, t_out);
+  for (int k = 0; k < steps; ++k) { tab[3 * k] = tab2[2 * k]; tab[3 * k + 1] = tab2[2 * k + 1]; tab[3 * k + 2] = 0.0; }
+}
+
 // ---------------------------------------------------------------- checks
 
 bool bad_shape(const svdp_params* p) {
@@ -127,6 +234,9 @@ svdp_status check_common(const svdp_params* p) {
   if (!(p->delta > 0 && p->delta < 1)) return fail(SVDP_ERR_INVALID_ARG, "delta must be in (0, 1)");
   if (!(p->tol > 0)) return fail(SVDP_ERR_INVALID_ARG, "tol must be > 0");
   if (p->eps_K < 0 || p->eps_R < 0 || p->eps_T < 0) return fail(SVDP_ERR_INVALID_ARG, "eps must be >= 0");
+  if (p->poly < SVDP_POLY_CANS3 || p->poly > SVDP_POLY_CANS5) return fail(SVDP_ERR_INVALID_ARG, "unknown poly");
+  if (p->poly != SVDP_POLY_CANS3 && (p->bound != SVDP_BOUND_CONSERVATIVE || p->precision != SVDP_PREC_FP32))
+    return fail(SVDP_ERR_INVALID_ARG, "poly variants run on the conservative FP32 path");
   return SVDP_OK;
 }
 
@@ -165,6 +275,7 @@ struct FwdWs {
   float* qr;   // QR completion scratch: 2 m per matrix
   float* qrc;  // blocked QR: projection coefficients, n x kQrBlock per matrix
   float *qrg, *qrr;  // blocked QR: a block's Gram matrix and CholeskyQR factor
+  float* P;    // quintic steps: c3 G + c5 G^2, n x n per matrix
   int* qmask;  // blocked QR: the flagged matrices
   int *active, *where, *iters, *flags, *sweeps, *mask, *counter, *ksteps, *kmax, *hist, *gmask;
 };
@@ -198,6 +309,7 @@ FwdWs carve_fwd(void* base, const svdp_params* p, size_t* total) {
   w.qrc = c.take<float>(blocked_qr ? b * n * kQrBlock : 0);
   w.qrg = c.take<float>(blocked_qr ? b * kQrBlock * kQrBlock : 0);
   w.qrr = c.take<float>(blocked_qr ? b * kQrBlock * kQrBlock : 0);
+  w.P = c.take<float>(p->poly == SVDP_POLY_CANS5 ? b * n * n : 0);
   w.qmask = c.take<int>(b);
   w.active = c.take<int>(b);
   w.where = c.take<int>(b);
@@ -275,6 +387,42 @@ hipError_t cans_step(Ctx& c, int prec, const void* Xc, void* Xn, int in_bf16, in
   return gemm_launch(u, prec, 0, prec == PREC_BF16 ? 1 : 0, c.st);
 }
 
+// One quintic step (FP32): G = Xc^T Xc, P = c5 G G + c3 G, Xn = c1 Xc + Xc P,
+// with the change sums of the stop test from the last product.
+hipError_t cans5_step(Ctx& c, const float* Xc, float* Xn, const double* cf, const int* active, float* conv,
+                      int n_active) {
+  const int m = c.m, n = c.n, B = c.batch;
+  GemmArgs g = gemm_base(n, n, m, B);
+  g.work_batch = n_active;
+  g.A = Xc; g.lda = n; g.sA = (int64_t)m * n;
+  g.B = Xc; g.ldb = n; g.sB = (int64_t)m * n;
+  g.C = c.w.G; g.ldc = n; g.sC = (int64_t)n * n;
+  g.sym = 1;
+  g.active = active;
+  hipError_t e = gemm_launch(g, PREC_F32, 1, 0, c.st);
+  if (e) return e;
+  GemmArgs q = gemm_base(n, n, n, B);
+  q.work_batch = n_active;
+  q.A = c.w.G; q.lda = n; q.sA = (int64_t)n * n;
+  q.B = c.w.G; q.ldb = n; q.sB = (int64_t)n * n;
+  q.C = c.w.P; q.ldc = n; q.sC = (int64_t)n * n;
+  q.Cin = c.w.G; q.ldcin = n; q.sCin = (int64_t)n * n;
+  q.alpha = (float)cf[2]; q.beta = (float)cf[1];
+  q.sym = 1;
+  q.active = active;
+  if ((e = gemm_launch(q, PREC_F32, 0, 0, c.st))) return e;
+  GemmArgs u = gemm_base(m, n, n, B);
+  u.work_batch = n_active;
+  u.A = Xc; u.lda = n; u.sA = (int64_t)m * n;
+  u.B = c.w.P; u.ldb = n; u.sB = (int64_t)n * n;
+  u.C = Xn; u.ldc = n; u.sC = (int64_t)m * n;
+  u.Cin = Xc; u.ldcin = n; u.sCin = (int64_t)m * n;
+  u.alpha = 1.f; u.beta = (float)cf[0];
+  u.active = active;
+  u.conv = conv;
+  return gemm_launch(u, PREC_F32, 0, 0, c.st);
+}
+
 // Conservative CANS in FP32 with per-matrix stopping (mask: matrices to run,
 // null = all): Algorithm 3 scaling, pre_iters preprocessing steps, then the
 // interval recursion from [1 - delta, 1 + delta] until the relative change is
@@ -286,8 +434,9 @@ svdp_status conservative_fp32(Ctx& c, const int* mask) {
   HIPCHK(norms_launch(c.A, c.lda, c.sA, B, m, n, w.colsum, w.rowmax, w.fro2, w.flags, mask, c.st), "norms");
   HIPCHK(ns_scale_launch(w.colsum, w.rowmax, B, n, w.scale, mask, c.st), "scale");
   HIPCHK(scale_copy_launch(c.A, c.lda, c.sA, B, m, n, w.scale, w.X0, 0, mask, c.st), "normalise");
-  double tab[128];
-  table_conservative(p->delta, p->pre_iters, p->max_iters, tab, nullptr);
+  double tab[128], tab3[3 * 64];
+  table_poly(p->poly, p->delta, p->pre_iters, p->max_iters, tab3, nullptr);
+  for (int k = 0; k < p->max_iters; ++k) { tab[2 * k] = tab3[3 * k]; tab[2 * k + 1] = tab3[3 * k + 1]; }
   HIPCHK(set_coef_launch(w.coef, tab, p->max_iters, c.st), "coef");
   if (mask) HIPCHK(copy_i32(w.active, mask, B, c.st), "active");
   else HIPCHK(fill_i32(w.active, 1, B, c.st), "active");
@@ -302,7 +451,10 @@ svdp_status conservative_fp32(Ctx& c, const int* mask) {
   for (int k = 0; k < p->max_iters; ++k) {
     const float* Xc = (k & 1) ? w.X1 : w.X0;
     float* Xn = (k & 1) ? w.X0 : w.X1;
-    HIPCHK(cans_step(c, PREC_F32, Xc, Xn, 0, 0, w.coef, 0, k, w.active, w.conv, remaining), "cans step");
+    if (p->poly == SVDP_POLY_CANS5)
+      HIPCHK(cans5_step(c, Xc, Xn, tab3 + 3 * k, w.active, w.conv, remaining), "cans5 step");
+    else
+      HIPCHK(cans_step(c, PREC_F32, Xc, Xn, 0, 0, w.coef, 0, k, w.active, w.conv, remaining), "cans step");
     HIPCHK(cans_check_launch(B, w.conv, (float)p->tol, k, w.active, w.where, w.iters, nullptr, 0, w.flags,
                              w.counter, c.st),
            "cans check");
@@ -602,6 +754,7 @@ void svdp_default_params(svdp_params* p, int64_t batch, int64_t m, int64_t n) {
   p->eigh_off_tol = 6e-6;
   p->eigh_restarts = 2;
   p->jacobi_fro_tol = 3e-4;
+  p->poly = SVDP_POLY_CANS3;
 }
 
 const char* svdp_status_string(svdp_status s) {
@@ -1158,6 +1311,17 @@ svdp_status svdp_cans_table(int32_t kind, double delta, int32_t pre_iters, doubl
   } else {
     return fail(SVDP_ERR_INVALID_ARG, "kind must be 0 or 1");
   }
+  return SVDP_OK;
+}
+
+svdp_status svdp_poly_table(int32_t poly, double delta, int32_t pre_iters, int32_t steps, double* table,
+                            double* t_out) {
+  if (poly < SVDP_POLY_CANS3 || poly > SVDP_POLY_CANS5) return fail(SVDP_ERR_INVALID_ARG, "unknown poly");
+  if (!table || steps < 1 || steps > 64 || pre_iters < 0 || pre_iters > steps || !(delta > 0 && delta < 1))
+    return fail(SVDP_ERR_INVALID_ARG, "need table, 1 <= steps <= 64, 0 <= pre_iters <= steps, 0 < delta < 1");
+  double t = 0.0;
+  table_poly(poly, delta, pre_iters, steps, table, &t);
+  if (t_out) *t_out = t;
   return SVDP_OK;
 }
 

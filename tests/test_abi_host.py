@@ -46,7 +46,7 @@ def test_params_struct_matches_header_layout():
     assert p.jacobi_tol == 3e-3 and p.bf16_from == 0.1
     assert p.margin_max == 1.1 and p.margin_min == 1.0
     assert p.eps_K == 0.0 and p.user_bounds is None and p.probe is None
-    assert p.eigh_off_tol == 6e-6 and p.eigh_restarts == 2 and p.jacobi_fro_tol == 3e-4
+    assert p.eigh_off_tol == 6e-6 and p.eigh_restarts == 2 and p.jacobi_fro_tol == 3e-4 and p.poly == 0
 
 
 def _ws(p, op):
@@ -97,6 +97,43 @@ def test_conservative_schedule_matches_oracle(orc, delta, pre):
     ref = orc.cans_schedule_conservative(delta, pre, 50)
     np.testing.assert_allclose(tab, ref, rtol=1e-13, atol=1e-13)
     assert t == pytest.approx(orc.cans_preprocess_t(delta, pre), rel=1e-12)
+
+
+@pytest.mark.parametrize("poly", [0, 1, 2])
+@pytest.mark.parametrize("delta,pre", [(0.99, 2), (0.9, 1), (0.999, 3)])
+def test_poly_table_matches_oracle(orc, poly, delta, pre):
+    # the host Remez exchange (quintic) against the oracle's nonlinear solve
+    # of the equioscillation system.  Where the interval is so narrow that the
+    # minimax error nears FP64 rounding (E < 1e-12) the coefficients are no
+    # longer determined by the problem, so each step is compared by what it
+    # must achieve: its maximum error on the oracle's interval.
+    from paper_2609_32505_amd import api
+    tab, t = api.poly_table(poly, 40, delta=delta, pre_iters=pre)
+    ref, t_ref = orc.poly_schedule_conservative(poly, delta, pre, 40)
+    assert t == pytest.approx(t_ref, rel=1e-9, abs=0.0)
+    if poly != 2:
+        np.testing.assert_allclose(tab, ref, rtol=1e-12, atol=1e-13)
+        return
+    a, b = t_ref, 1.0
+    for k in range(40):
+        if k == pre:
+            a, b = 1.0 - delta, 1.0 + delta
+        c1, c3, c5, lo, hi = orc.cans5_poly(a, b)
+        E = (hi - lo) / 2
+        x = np.linspace(a, b, 20001)
+        e_host = np.abs(1.0 - (tab[k, 0] * x + tab[k, 1] * x ** 3 + tab[k, 2] * x ** 5)).max()
+        assert e_host <= E * (1 + 1e-6) + 1e-15, k
+        if E > 1e-12:
+            np.testing.assert_allclose(tab[k], ref[k], rtol=1e-7)
+        a, b = lo, hi
+
+
+def test_poly_argument_errors():
+    L, lib = _lib()
+    assert _ws(L.default_params(1, 8, 8, poly=3), 0)[0] == 1
+    assert _ws(L.default_params(1, 8, 8, poly=2, bound=1), 0)[0] == 1
+    assert _ws(L.default_params(1, 8, 8, poly=1, precision=1), 0)[0] == 1
+    assert _ws(L.default_params(1, 8, 8, poly=2), 0)[0] == 0
 
 
 @pytest.mark.parametrize("lo", [1e-6, 1e-3, 0.2, 1.0])

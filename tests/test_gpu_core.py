@@ -147,6 +147,23 @@ def test_svd_ragged_fp32(api, b, m, n):
     _svd_check(api, A, tol_uv=5e-3)
 
 
+@pytest.mark.parametrize("poly", [1, 2])
+@pytest.mark.parametrize("b,m,n", [(3, 130, 100), (2, 200, 200)])
+def test_svd_poly_variants_fp32(api, poly, b, m, n):
+    # the iteration variants of the polar ablation (1: classical Newton-
+    # Schulz, 2: the CANS quintic) against the FP64 oracle, and their step
+    # counts against the CANS cubic on the same matrices
+    _say(f"svd {b} x {m} x {n} fp32 conservative, poly {poly}")
+    A, _ = inputs.batch_with_spectra(60 + m, b, m, n, lambda r: inputs.log_uniform(r, n, 1e-3, 1.0))
+    r = _svd_check(api, A, tol_uv=5e-3, poly=poly, max_iters=64)
+    assert all(x[4] < 1e-5 and x[5] < 1e-5 and x[6] == 0 for x in r)
+    _, _, _, i3 = api.svd_fwd(dev(A))
+    _, _, _, ip = api.svd_fwd(dev(A), poly=poly, max_iters=64)
+    it3, itp = api.info_to_numpy(i3)["iters"], api.info_to_numpy(ip)["iters"]
+    _say(f"  iterations: cubic {it3}, poly {poly} {itp}")
+    assert np.all(itp > it3) if poly == 1 else np.all(itp < it3)
+
+
 def test_svd_bf16_user_bounds(api):
     import torch
     _say("svd 4 x 256^2 bf16 user bounds")

@@ -172,6 +172,37 @@ def test_paper_delta_ablation_4096(api, handle, haar, kappa):
     assert recs[-1] > recs[0]
 
 
+def test_polar_iteration_ablation_1024(api, handle):
+    """The appendix's ablation of polar iterations built on matrix products,
+    at its setting (one 1024^2 matrix, kappa 1e6): classical Newton-Schulz
+    converges slowly, the interval-optimal polynomials fast (here the CANS
+    cubic and, as the higher-degree member, the CANS quintic).  Checked: each
+    reaches |W^T W - I|_F / |I|_F < 1e-5 with the stop test, and the step
+    counts order NS > cubic > quintic.  The quintic's step costs 4 n^3 flops
+    against the cubic's 3 n^3; both are reported."""
+    import torch
+    n = 1024
+    A, _ = inputs.batch_with_spectra(71, 1, n, n, lambda r: inputs.paper_kappa_rank(n, 1e6))
+    Ad = torch.from_numpy(A).cuda()
+    eye = torch.eye(n, dtype=torch.float64, device="cuda")
+    its = {}
+    for poly, name, flops in [(1, "Newton-Schulz", 3), (0, "CANS cubic", 3), (2, "CANS quintic", 4)]:
+        W, H, _, _, info = api.polar_fwd(Ad, handle=handle, poly=poly, max_iters=64, cache=False)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        W, H, _, _, info = api.polar_fwd(Ad, handle=handle, poly=poly, max_iters=64, cache=False)
+        torch.cuda.synchronize()
+        dt = time.time() - t0
+        inf = api.info_to_numpy(info)
+        Wd = W[0].double()
+        orth = float(torch.linalg.norm(Wd.T @ Wd - eye) / np.sqrt(n))
+        its[poly] = int(inf["iters"][0])
+        _say(f"  {name}: {its[poly]} steps ({its[poly] * flops} n^3 flops), {dt * 1e3:.1f} ms, "
+             f"|W^T W - I|_F/|I|_F {orth:.2e}, flags {inf['flags'][0]}")
+        assert not (inf["flags"][0] & 1) and orth < 1e-5
+    assert its[1] > its[0] > its[2]
+
+
 def _paper_value_r(table, rank):
     t = GOLDEN[table]
     return t["err"][t["rank"].index(rank)]

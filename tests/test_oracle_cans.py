@@ -34,6 +34,57 @@ def test_cans_poly_newton_schulz_limit(orc):
     assert (al, be) == (1.5, -0.5) and lo == 1.0 and hi == 1.0
 
 
+@pytest.mark.parametrize("a,b", [(0.01, 1.99), (1e-3, 1.0), (0.5, 1.0), (0.9, 1.1), (2.7765e-4, 1.0)])
+def test_cans5_poly_equioscillates_and_is_minimax(orc, a, b):
+    # the degree-5 step: equioscillation at four points with alternating signs
+    # (Chebyshev alternation for three coefficients), image [1 - E, 1 + E],
+    # and no nearby odd quintic with a smaller maximum error
+    c1, c3, c5, lo, hi = orc.cans5_poly(a, b)
+    x = np.linspace(a, b, 400001)
+    err = 1.0 - (c1 * x + c3 * x ** 3 + c5 * x ** 5)
+    E = np.abs(err).max()
+    assert lo == pytest.approx(1 - E, rel=1e-9, abs=1e-12) and hi == pytest.approx(1 + E, rel=1e-9)
+    # sign pattern +, -, +, - of the extremal values, in order
+    ext = [err[0]]
+    for i in range(1, len(x) - 1):
+        if (err[i] - err[i - 1]) * (err[i + 1] - err[i]) < 0 and abs(abs(err[i]) - E) < 1e-6 * E:
+            ext.append(err[i])
+    ext.append(err[-1])
+    signs = np.sign(ext)
+    assert len(ext) == 4 and list(signs) == [1, -1, 1, -1]
+    assert np.allclose(np.abs(ext), E, rtol=1e-6)
+    rng = np.random.default_rng(1)
+    for _ in range(300):
+        d = rng.standard_normal(3) * 1e-4 * np.abs([c1, c3, c5])
+        e2 = np.abs(1.0 - ((c1 + d[0]) * x + (c3 + d[1]) * x ** 3 + (c5 + d[2]) * x ** 5)).max()
+        assert e2 >= E * (1 - 1e-9)
+
+
+def test_cans5_poly_narrow_limit(orc):
+    # p(1) = 1, p'(1) = p''(1) = 0: the quintic Newton-Schulz-type limit
+    c1, c3, c5, lo, hi = orc.cans5_poly(1.0 - 1e-8, 1.0 + 1e-8)
+    assert (c1, c3, c5) == pytest.approx((15 / 8, -10 / 8, 3 / 8), rel=1e-7)
+    assert lo == pytest.approx(1.0, abs=1e-15) and hi == pytest.approx(1.0, abs=1e-15)
+
+
+def test_poly_variants_reach_polar_factor(orc):
+    # FP64: classical Newton-Schulz, the CANS cubic and the CANS quintic all
+    # reach the polar factor of the Jacobi SVD; per step the quintic gains
+    # most, Newton-Schulz least (the ablation's ordering)
+    rng = inputs.rng_for(43, 0)
+    A = inputs.matrix_with_spectrum(rng, 40, 30, inputs.geometric(30, 1e4))
+    U, S, V, _ = orc.svd(A)
+    W_ref, _ = orc.polar_from_svd(U, S, V)
+    its = {}
+    for poly in (0, 1, 2):
+        tab, t = orc.poly_schedule_conservative(poly, 0.99, 2, 64)
+        W, it = orc.poly_polar(A, tab, tol=1e-13, max_iters=64)
+        assert it < 64
+        np.testing.assert_allclose(W, W_ref, atol=1e-9)
+        its[poly] = it
+    assert its[2] < its[0] < its[1]
+
+
 def test_interval_recursion_shrinks(orc):
     a, b = 0.01, 1.99
     prev = 1.0
