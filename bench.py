@@ -158,10 +158,16 @@ def main():
     h = api.Handle()
     h.set_model(predictor.load())
     eps = dict(eps_K=1e-12, eps_R=0.0, eps_T=0.0)
+    # The learned BF16 path's polar factor is accurate to about 1e-3 (its
+    # reconstruction error); its eigensolver is held to a backward error of
+    # 1e-4 (restart tolerance, no FP64 final sweep) instead of the FP32
+    # path's 6e-6, an order of magnitude below the factor it decomposes.
+    learned_eigh = dict(fp64_sweeps=0, eigh_off_tol=1e-4, jacobi_fro_tol=1e-3)
 
     def step(learned: bool):
         if learned:
-            U, S, V, info = api.svd_fwd(Ad, handle=h, precision=L.PREC_BF16, bound=L.BOUND_LEARNED, probe=pd)
+            U, S, V, info = api.svd_fwd(Ad, handle=h, precision=L.PREC_BF16, bound=L.BOUND_LEARNED, probe=pd,
+                                        **learned_eigh)
         else:
             U, S, V, info = api.svd_fwd(Ad, handle=h)
         dA = api.svd_bwd(U, S, V, dUd, dSd, dVd, handle=h, **eps)
@@ -237,7 +243,8 @@ def main():
             orth.append(g.abs().amax(dim=(1, 2)).cpu())
         return float(torch.cat(rec).max()), float(torch.cat(orth).max())
 
-    U_l, _, V_l, _ = api.svd_fwd(Ad, handle=h, precision=L.PREC_BF16, bound=L.BOUND_LEARNED, probe=pd)
+    U_l, _, V_l, _ = api.svd_fwd(Ad, handle=h, precision=L.PREC_BF16, bound=L.BOUND_LEARNED, probe=pd,
+                                 **learned_eigh)
     U_p, _, V_p, _ = api.svd_fwd(Ad, handle=h)
     rec_l, orth_l = recon_orth(U_l, S_l, V_l)
     rec_p, orth_p = recon_orth(U_p, S_p, V_p)
@@ -251,7 +258,8 @@ def main():
         "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "bf16+fp32", "data": "synthetic",
         "config": {"workload": f"{B} x {n} x {n} FP32, sigma log-uniform [1e-3,1], svd_polar_fwd + "
-                               f"svd_polar_bwd, learned-bound BF16 CANS", "batch": B, "m": n, "n": n},
+                               f"svd_polar_bwd, learned-bound BF16 CANS", "batch": B, "m": n, "n": n,
+                   "learned_eigh": learned_eigh},
         "plain_fp32": {"value": round(B / (ms_p * 1e-3), 3), "ms_per_step": round(ms_p, 3),
                        "ms_per_step_std": round(sd_p, 3),
                        "iters_max": int(ip["iters"].max()), "iters_mean": round(float(ip["iters"].mean()), 2),

@@ -16,6 +16,9 @@ pytestmark = pytest.mark.gpu
 # |U^T U - I|, |V^T V - I| bound: CANS stops at a relative change of 1e-5, which
 # leaves |W^T W - I| of that order (the paper reports 2-4e-6 in FP32 at 4096^2)
 ORTH_TOL = 1e-5
+# the benchmark's learned-path eigensolver settings (backward error 1e-4, no
+# FP64 final sweep: an order of magnitude below the BF16 polar factor's error)
+LEARNED_EIGH = dict(fp64_sweeps=0, eigh_off_tol=1e-4, jacobi_fro_tol=1e-3)
 
 
 def _say(*a):
@@ -82,7 +85,7 @@ def test_square_512_batch256_both_paths(api, handle):
     res = {}
     for label, kw, tol_s, tol_w, tol_o in [
             ("plain-fp32", {}, 1e-5, 1e-4, ORTH_TOL),
-            ("learned-bf16", dict(precision=1, bound=1, probe=probe), 1e-3, 5e-2, ORTH_TOL)]:
+            ("learned-bf16", dict(precision=1, bound=1, probe=probe, **LEARNED_EIGH), 1e-3, 5e-2, ORTH_TOL)]:
         U, S, V, info = api.svd_fwd(Ad, handle=handle, **kw)
         torch.cuda.synchronize()
         inf = api.info_to_numpy(info)
