@@ -128,6 +128,14 @@ def test_poly_table_matches_oracle(orc, poly, delta, pre):
         a, b = lo, hi
 
 
+def test_workspace_covers_quintic_buffer():
+    # the quintic step needs one n x n buffer per matrix (P = c3 G + c5 G^2)
+    L, _ = _lib()
+    st0, nb0 = _ws(L.default_params(4, 300, 200), L.OP_SVD_FWD)
+    st2, nb2 = _ws(L.default_params(4, 300, 200, poly=2), L.OP_SVD_FWD)
+    assert st0 == 0 and st2 == 0 and nb2 - nb0 >= 0.99 * 4 * 200 * 200 * 4
+
+
 def test_poly_argument_errors():
     L, lib = _lib()
     assert _ws(L.default_params(1, 8, 8, poly=3), 0)[0] == 1
