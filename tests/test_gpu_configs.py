@@ -234,8 +234,15 @@ def test_learned_predictor_gain_2048(api, handle):
         torch.cuda.synchronize()
         inf = api.info_to_numpy(info)
         out[label] = (S.cpu().double().numpy(), inf, time.time() - t0)
-        _say(f"  {label}: {out[label][2]:.2f}s, CANS steps mean {inf['iters'].mean():.1f} max {inf['iters'].max()}, "
-             f"fallbacks {int(((inf['flags'] & 2) != 0).sum())}, residual max {inf['residual'].max():.1e}")
+        # the CANS phase alone: the polar factor without the eigendecomposition
+        torch.cuda.synchronize()
+        t1 = time.time()
+        api.polar_fwd(Ad, handle=handle, cache=False, **kw)
+        torch.cuda.synchronize()
+        t_cans = time.time() - t1
+        _say(f"  {label}: {out[label][2]:.2f}s SVD, CANS phase {t_cans * 1e3:.0f} ms, CANS steps mean "
+             f"{inf['iters'].mean():.1f} max {inf['iters'].max()}, fallbacks {int(((inf['flags'] & 2) != 0).sum())}, "
+             f"residual max {inf['residual'].max():.1e}")
     Sc, ic, _ = out["conservative-fp32"]
     Sl, il, _ = out["learned-bf16"]
     err = (np.abs(Sl - Sc).max(axis=1) / Sc[:, 0]).max()
