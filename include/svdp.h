@@ -21,7 +21,8 @@
  *   - Work is enqueued on `stream` (a hipStream_t passed as void*; null =
  *     the default stream).  Calls return after enqueueing, except that the
  *     forward passes read a few device counters back to the host (iteration
- *     control of CANS and Jacobi), which synchronises `stream`.
+ *     control of CANS and Jacobi, eigensolver restarts, the blocked QR step),
+ *     which synchronises `stream`.
  *   - Errors: arguments are checked before anything is launched; a non-OK
  *     status means no work was enqueued, except SVDP_ERR_HIP, which reports
  *     a failed launch or copy (svdp_last_error() gives the HIP message).
