@@ -109,6 +109,39 @@ def test_preprocess_boundary(orc):
     assert 7e-4 < t < 8e-4
 
 
+@pytest.mark.parametrize("delta", [0.9, 0.99])
+def test_cans5_preprocess_boundary(orc, delta):
+    # two quintic steps map [t, 1] exactly onto the edge of [1 - delta, 1 + delta],
+    # and a slightly smaller t falls outside; the quintic reaches further down
+    # than the cubic
+    t = orc.cans5_preprocess_t(delta)
+    def two(t0):
+        a, b = t0, 1.0
+        for _ in range(2):
+            *_, a, b = orc.cans5_poly(a, b)
+        return max(1 - a, b - 1)
+    assert two(t) == pytest.approx(delta, abs=1e-9)
+    assert two(t * 0.999) > delta and two(t * 1.001) < delta
+    assert t < orc.cans_preprocess_t(delta)
+
+
+def test_poly_schedule_layout(orc):
+    # Newton-Schulz rows are (1.5, -0.5, 0); cubic rows carry c5 = 0 and equal
+    # the cubic table; quintic rows after the preprocessing follow the
+    # interval recursion from [1 - delta, 1 + delta]
+    ns, t_ns = orc.poly_schedule_conservative(1, 0.99, 2, 10)
+    assert t_ns == 0.0 and np.all(ns == np.array([1.5, -0.5, 0.0]))
+    c3, _ = orc.poly_schedule_conservative(0, 0.99, 2, 10)
+    np.testing.assert_array_equal(c3[:, :2], orc.cans_schedule_conservative(0.99, 2, 10))
+    assert np.all(c3[:, 2] == 0.0)
+    c5, _ = orc.poly_schedule_conservative(2, 0.99, 2, 6)
+    a, b = 0.01, 1.99
+    for k in range(2, 6):
+        r = orc.cans5_poly(a, b)
+        np.testing.assert_allclose(c5[k], r[:3], rtol=1e-12)
+        a, b = r[3], r[4]
+
+
 def test_conservative_table_layout(orc):
     tab = orc.cans_schedule_conservative()
     assert tab.shape == (50, 2)
