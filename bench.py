@@ -134,7 +134,8 @@ def main():
                          "for scaling HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU only (a batch shards by matrix across "
+                                   "GPUs); run with --gpus 1"}))
         sys.exit(2)
 
     import numpy as np

@@ -159,3 +159,15 @@ def test_schedule_argument_errors():
     assert lib.svdp_cans_table(1, 0.99, 2, 0.0, 4, tab, None) == 1
     assert lib.svdp_cans_table(2, 0.99, 2, 0.1, 4, tab, None) == 1
     assert lib.svdp_cans_table(1, 0.99, 2, 0.1, 4, None, None) == 1
+
+
+def test_bench_refuses_more_than_one_gpu():
+    # one GPU per box: --gpus N > 1 exits with a message before touching a GPU
+    import json
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in json.loads(r.stdout.strip().splitlines()[-1])["error"]
