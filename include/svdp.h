@@ -233,7 +233,8 @@ svdp_status polar_bwd(svdp_handle* h, const svdp_params* p,
 /* Symmetric eigendecomposition H = V diag(lam) V^T (the EVD step of
  * Algorithm 1) by batched block Jacobi; lam descending (signed), V n x n.
  * Uses p->batch, p->n (m ignored), max_sweeps, inner_sweeps, fp64_sweeps,
- * jacobi_tol, jacobi_abs, jacobi_fro_tol, eigh_off_tol, eigh_restarts.  info: sweeps and flags (may be null). */
+ * jacobi_tol, jacobi_abs, jacobi_fro_tol, eigh_off_tol, eigh_restarts.
+ * info: sweeps and flags (may be null). */
 svdp_status svdp_eigh(svdp_handle* h, const svdp_params* p,
                       const float* H, int64_t ldh, int64_t sH,
                       float* lam, int64_t slam,
