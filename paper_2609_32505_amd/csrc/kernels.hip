@@ -28,33 +28,43 @@ SVDP_DEV bool skip(const int* mask, int b) { return mask && !mask[b]; }
 // ------------------------------------------------------------ normalisation
 
 // one wave per row: row abs sum -> rowmax, squares -> fro2, non-finite flag
-__global__ void k_rownorms(const float* A, int64_t lda, int64_t sA, int m, int n, float* rowmax,
+// Row sums of |A| (their maximum, the infinity norm), |A|_F^2 and the
+// non-finite flag: a workgroup reduces rows_per rows (a wave per row at a
+// time), then adds one atomic per quantity.
+__global__ void k_rownorms(const float* A, int64_t lda, int64_t sA, int m, int n, int rows_per, float* rowmax,
                            float* fro2, int* flags, const int* mask) {
   const int b = blockIdx.y;
   if (skip(mask, b)) return;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int i = blockIdx.x * 4 + w;
-  if (i >= m) return;
-  const float* r = A + b * sA + (int64_t)i * lda;
-  float s = 0.f, q = 0.f;
+  const int r0 = blockIdx.x * rows_per, r1 = min(m, r0 + rows_per);
+  float mx = 0.f, q = 0.f;
   bool bad = false;
-  for (int j = lane; j < n; j += 64) {
-    float v = r[j];
-    bad |= !isfinite(v);
-    s += fabsf(v);
-    q += v * v;
+  for (int i = r0 + w; i < r1; i += 4) {
+    const float* r = A + b * sA + (int64_t)i * lda;
+    float s = 0.f;
+    for (int j = lane; j < n; j += 64) {
+      const float v = r[j];
+      bad |= !isfinite(v);
+      s += fabsf(v);
+      q += v * v;
+    }
+    s = wave_sum(s);
+    mx = fmaxf(mx, isfinite(s) ? s : 0.f);
   }
-  s = wave_sum(s);
   q = wave_sum(q);
-  unsigned long long anybad = __ballot(bad);
-  if (lane == 0) {
-    atomic_max_pos(rowmax + b, isfinite(s) ? s : 0.f);
-    atomicAdd(fro2 + b, q);
-    if (anybad) atomicOr(flags + b, SVDP_FLAG_NONFINITE);
+  const int anybad = __ballot(bad) != 0ull;
+  __shared__ float smx[4], sq[4];
+  __shared__ int sbad[4];
+  if (lane == 0) { smx[w] = mx; sq[w] = q; sbad[w] = anybad; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const float m4 = fmaxf(fmaxf(smx[0], smx[1]), fmaxf(smx[2], smx[3]));
+    atomic_max_pos(rowmax + b, m4);
+    atomicAdd(fro2 + b, sq[0] + sq[1] + sq[2] + sq[3]);
+    if (sbad[0] | sbad[1] | sbad[2] | sbad[3]) atomicOr(flags + b, SVDP_FLAG_NONFINITE);
   }
 }
 
-// column abs sums over a chunk of rows (coalesced across threads)
 __global__ void k_colsums(const float* A, int64_t lda, int64_t sA, int m, int n, int rows_per,
                           float* colsum, const int* mask) {
   const int b = blockIdx.z;
@@ -849,8 +859,9 @@ hipError_t norms_launch(const float* A, int64_t lda, int64_t sA, int batch, int 
   if ((e = fill_f32(colsum, 0.f, (int64_t)batch * n, st))) return e;
   if ((e = fill_f32(rowmax, 0.f, batch, st))) return e;
   if ((e = fill_f32(fro2, 0.f, batch, st))) return e;
-  hipLaunchKernelGGL(k_rownorms, dim3(cdiv(m, 4), batch), dim3(256), 0, st, A, lda, sA, m, n, rowmax,
-                     fro2, flags, mask);
+  const int rows_wg = 64;
+  hipLaunchKernelGGL(k_rownorms, dim3(cdiv(m, rows_wg), batch), dim3(256), 0, st, A, lda, sA, m, n, rows_wg,
+                     rowmax, fro2, flags, mask);
   if ((e = hipGetLastError())) return e;
   const int rows_per = 256;
   hipLaunchKernelGGL(k_colsums, dim3(cdiv(n, 256), cdiv(m, rows_per), batch), dim3(256), 0, st, A, lda,

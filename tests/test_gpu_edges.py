@@ -115,6 +115,55 @@ def test_rank_deficient_blocked_qr_1024(api):
         assert lead > 1 - 1e-4
 
 
+def _eigh_backward_error(api, H, **kw):
+    import torch
+    lam, V, info = api.eigh(H, **kw)
+    torch.cuda.synchronize()
+    Hd = (0.5 * (H + H.transpose(-1, -2))).double()
+    Vd, Ld = V.double(), lam.double()
+    rec = torch.linalg.norm(Hd - (Vd * Ld[:, None, :]) @ Vd.transpose(-1, -2), dim=(1, 2)) / torch.linalg.norm(Hd, dim=(1, 2))
+    return rec.cpu().numpy(), api.info_to_numpy(info)
+
+
+def test_eigh_restarts_reach_fp32_floor_at_2048(api):
+    # many FP32 block rotations leave a backward error that grows with n, and
+    # one FP64 sweep does not finish a dense spectrum (kappa 10: 2048 values
+    # in [1, 10]); the restarts (T = V^T H V re-formed and swept) must bring
+    # |H - V diag(lam) V^T|_F / |H|_F to the 6e-6 tolerance
+    import torch
+    n = 2048
+    _say("eigh 2048^2, eigenvalues geometric 10 .. 1: restarts off vs on")
+    rng = inputs.rng_for(95, 0)
+    Q = inputs.orthonormal(rng, n, n)
+    H = torch.from_numpy(((Q * inputs.paper_kappa_rank(n, 10.0)) @ Q.T).astype(np.float32)[None]).cuda()
+    r0, i0 = _eigh_backward_error(api, H, eigh_restarts=0)
+    r2, i2 = _eigh_backward_error(api, H)
+    _say(f"  no restart: {r0[0]:.2e} ({i0['sweeps'][0]} sweeps); default: {r2[0]:.2e} ({i2['sweeps'][0]} sweeps)")
+    assert r2[0] < 8e-6 and r2[0] < r0[0]
+    assert i2["sweeps"][0] <= i0["sweeps"][0] + 2
+
+
+def test_eigh_restart_skips_rounding_level_cluster(api):
+    # rank 100 at n = 1024: about 924 eigenvalues at rounding level.  Rotating
+    # those pairs in a restart stirs the cluster and the restart converges only
+    # linearly; restart sweeps leave pairs entirely below 2^-24 |H|_F alone,
+    # and one restart reaches the tolerance
+    import torch
+    n = 1024
+    _say("eigh of H = sym(W^T A), A 1024^2 of rank 100")
+    rng = inputs.rng_for(93, 0)
+    s = inputs.paper_kappa_rank(n, 10.0, 100)
+    Q1 = inputs.orthonormal(rng, n, n)
+    Q2 = inputs.orthonormal(rng, n, n)
+    A = torch.from_numpy(((Q1 * s) @ Q2.T).astype(np.float32)[None]).cuda()
+    W, H, _, _, _ = api.polar_fwd(A, cache=False)
+    r0, i0 = _eigh_backward_error(api, H, eigh_restarts=0)
+    r, inf = _eigh_backward_error(api, H)
+    _say(f"  no restart: {r0[0]:.2e} ({i0['sweeps'][0]} sweeps); default: {r[0]:.2e} ({inf['sweeps'][0]} sweeps)")
+    assert r[0] < 6e-6
+    assert inf["sweeps"][0] <= i0["sweeps"][0] + 1
+
+
 def test_numerically_rank_deficient_is_completed(api):
     # sigma down to 1e-9 relative: the smallest directions of W stay far
     # from unit norm after CANS, so U is orthogonalised by QR
