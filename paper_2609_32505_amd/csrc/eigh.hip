@@ -593,17 +593,17 @@ __global__ __launch_bounds__(256) void k_eigh_setup(EighWs e, const float* Hin, 
   if ((t & 63) == 0) atomicAdd(e.hnorm2 + b, acc);
 }
 
-// row-major copy of a tiled np x np matrix (one float4 per thread)
+// row-major copy of a tiled np x np matrix: one row per workgroup, a float4
+// per thread and step
 __global__ void k_untile(const float* src, float* dst, int np, int nb, const int* mask) {
   const int b = blockIdx.y;
   if (mask && !mask[b]) return;
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t per_row = np / 4;
-  if (idx >= (int64_t)np * per_row) return;
-  const int row = (int)(idx / per_row), c4 = (int)(idx - row * per_row) * 4;
+  const int row = blockIdx.x;
   const int64_t off = (int64_t)b * np * np;
-  const f4v v = *(const f4v*)(src + off + tile_off(row >> 4, c4 >> 4, nb) + (row & 15) * BS + (c4 & 15));
-  *(f4v*)(dst + off + (int64_t)row * np + c4) = v;
+  for (int c4 = 4 * threadIdx.x; c4 < np; c4 += 4 * blockDim.x) {
+    const f4v v = *(const f4v*)(src + off + tile_off(row >> 4, c4 >> 4, nb) + (row & 15) * BS + (c4 & 15));
+    *(f4v*)(dst + off + (int64_t)row * np + c4) = v;
+  }
 }
 
 // Mark matrices as converged after a sweep whose largest rotated relative
@@ -767,11 +767,8 @@ __global__ void k_copy_active(const float* src, float* dst, int n, int np, const
   const int b = blockIdx.y;
   if (!active[b]) return;
   const int64_t off = (int64_t)b * np * np;
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < (int64_t)n * n;
-       k += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t i = k / n, j = k - i * n;
-    dst[off + i * np + j] = src[off + i * np + j];
-  }
+  for (int i = blockIdx.x; i < n; i += gridDim.x)
+    for (int j = threadIdx.x; j < n; j += blockDim.x) dst[off + (int64_t)i * np + j] = src[off + (int64_t)i * np + j];
 }
 
 __global__ void k_flag_active(const int* active, int batch, int* flags, int f) {
@@ -1042,8 +1039,7 @@ hipError_t eigh_run(EighWs e, const float* H, int64_t ldh, int64_t sH, int mode,
   // V (tiled) -> row-major in Hw; one Newton-Schulz step re-orthonormalises
   // it, V2 = V (3 I - V^T V) / 2 (V^T V in Vw)
   {
-    const int64_t nq = m2 / 4;
-    hipLaunchKernelGGL(k_untile, dim3(cdiv(nq, 256), batch), dim3(256), 0, st, e.Vw, e.Hw, np, e.nb, mask);
+    hipLaunchKernelGGL(k_untile, dim3(np, batch), dim3(256), 0, st, e.Vw, e.Hw, np, e.nb, mask);
     if ((err = hipGetLastError())) return err;
     GemmArgs g;
     memset(&g, 0, sizeof(g));
@@ -1119,7 +1115,7 @@ hipError_t eigh_run(EighWs e, const float* H, int64_t ldh, int64_t sH, int mode,
       for (int f = 0; f < std::max(1, o.fp64_sweeps); ++f)
         if ((err = sweep_launches(o.fp64_sweeps > 0, kRestartSkip, nullptr, nullptr, bc))) return err;
       if ((err = join())) return err;
-      hipLaunchKernelGGL(k_untile, dim3(cdiv(m2 / 4, 256), batch), dim3(256), 0, st, e.Vw, e.Hw, np, e.nb, proc);
+      hipLaunchKernelGGL(k_untile, dim3(np, batch), dim3(256), 0, st, e.Vw, e.Hw, np, e.nb, proc);
       if ((err = hipGetLastError())) return err;
       GemmArgs v;
       memset(&v, 0, sizeof(v));
@@ -1129,8 +1125,8 @@ hipError_t eigh_run(EighWs e, const float* H, int64_t ldh, int64_t sH, int mode,
       v.C = e.Vw; v.ldc = np; v.sC = m2;
       v.alpha = 1.f; v.active = proc;
       if ((err = gemm_launch(v, PREC_F32, 0, 0, st))) return err;
-      const unsigned cgrid = (unsigned)std::min<int64_t>(cdiv((int64_t)e.n * e.n, 256), 1024);
-      hipLaunchKernelGGL(k_copy_active, dim3(cgrid, batch), dim3(256), 0, st, e.Vw, e.V2, e.n, np, proc);
+      hipLaunchKernelGGL(k_copy_active, dim3(std::min(e.n, 512), batch), dim3(256), 0, st, e.Vw, e.V2, e.n, np,
+                         proc);
       if ((err = hipGetLastError())) return err;
     }
   }

@@ -105,12 +105,15 @@ __global__ void k_scale_copy(const float* A, int64_t lda, int64_t sA, int m, int
   if (skip(mask, b)) return;
   const float inv = 1.f / scale[b];
   const int64_t total = (int64_t)m * n;
-  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    int i = (int)(idx / n), j = (int)(idx - (int64_t)i * n);
-    float v = A[b * sA + (int64_t)i * lda + j] * inv;
-    if (out_bf16) ((bf16_t*)X)[b * total + idx] = f2bf(v);
-    else ((float*)X)[b * total + idx] = v;
+  // rows over workgroups, columns over threads (no per-element division)
+  for (int i = blockIdx.x; i < m; i += gridDim.x) {
+    const float* a = A + b * sA + (int64_t)i * lda;
+    const int64_t o = b * total + (int64_t)i * n;
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+      const float v = a[j] * inv;
+      if (out_bf16) ((bf16_t*)X)[o + j] = f2bf(v);
+      else ((float*)X)[o + j] = v;
+    }
   }
 }
 
@@ -154,12 +157,13 @@ __global__ void k_residual(const void* G, int gbf16, int n, float* resid, const 
   if (skip(mask, b)) return;
   const int64_t total = (int64_t)n * n;
   float s = 0.f;
-  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    int i = (int)(idx / n), j = (int)(idx - (int64_t)i * n);
-    float g = gbf16 ? bf2f(((const bf16_t*)G)[b * total + idx]) : ((const float*)G)[b * total + idx];
-    float d = g - (i == j ? 1.f : 0.f);
-    s += d * d;
+  for (int i = blockIdx.x; i < n; i += gridDim.x) {
+    const int64_t o = b * total + (int64_t)i * n;
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+      const float g = gbf16 ? bf2f(((const bf16_t*)G)[o + j]) : ((const float*)G)[o + j];
+      const float d = g - (i == j ? 1.f : 0.f);
+      s += d * d;
+    }
   }
   s = wave_sum(s);
   if ((threadIdx.x & 63) == 0) atomicAdd(resid + b, s);
@@ -464,23 +468,19 @@ __global__ void k_sylvester(int mode, const float* X1, const float* X2, const fl
 __global__ void k_symmetrize(const float* in, int n, float* out, int64_t ldo, int64_t so) {
   const int b = blockIdx.y;
   const int64_t total = (int64_t)n * n;
-  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    int i = (int)(idx / n), j = (int)(idx - (int64_t)i * n);
-    out[b * so + (int64_t)i * ldo + j] = 0.5f * (in[b * total + idx] + in[b * total + (int64_t)j * n + i]);
-  }
+  for (int i = blockIdx.x; i < n; i += gridDim.x)
+    for (int j = threadIdx.x; j < n; j += blockDim.x)
+      out[b * so + (int64_t)i * ldo + j] =
+          0.5f * (in[b * total + (int64_t)i * n + j] + in[b * total + (int64_t)j * n + i]);
 }
 
 __global__ void k_copy(const float* src, int64_t lds, int64_t ss, const int* sel, const float* src_alt,
                        float* dst, int64_t ldd, int64_t sd, int m, int n) {
   const int b = blockIdx.y;
   const float* s = (sel && sel[b]) ? src_alt : src;
-  const int64_t total = (int64_t)m * n;
-  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    int i = (int)(idx / n), j = (int)(idx - (int64_t)i * n);
-    dst[b * sd + (int64_t)i * ldd + j] = s[b * ss + (int64_t)i * lds + j];
-  }
+  for (int i = blockIdx.x; i < m; i += gridDim.x)
+    for (int j = threadIdx.x; j < n; j += blockDim.x)
+      dst[b * sd + (int64_t)i * ldd + j] = s[b * ss + (int64_t)i * lds + j];
 }
 
 // ------------------------------------------------------------ features
@@ -877,7 +877,7 @@ hipError_t ns_scale_launch(const float* colsum, const float* rowmax, int batch, 
 
 hipError_t scale_copy_launch(const float* A, int64_t lda, int64_t sA, int batch, int m, int n,
                              const float* scale, void* X, int out_bf16, const int* mask, hipStream_t st) {
-  hipLaunchKernelGGL(k_scale_copy, dim3(grid1((int64_t)m * n), batch), dim3(256), 0, st, A, lda, sA, m,
+  hipLaunchKernelGGL(k_scale_copy, dim3(std::min(m, 512), batch), dim3(256), 0, st, A, lda, sA, m,
                      n, scale, X, out_bf16, mask);
   LAUNCH_CHECK();
 }
@@ -902,7 +902,7 @@ hipError_t residual_launch(const void* G, int gbf16, int batch, int n, float* re
                            hipStream_t st) {
   hipError_t e;
   if ((e = fill_f32(resid, 0.f, batch, st))) return e;
-  hipLaunchKernelGGL(k_residual, dim3(grid1((int64_t)n * n, 64), batch), dim3(256), 0, st, G, gbf16, n,
+  hipLaunchKernelGGL(k_residual, dim3(std::min(n, 64), batch), dim3(256), 0, st, G, gbf16, n,
                      resid, mask);
   if ((e = hipGetLastError())) return e;
   hipLaunchKernelGGL(k_residual_finish, dim3(cdiv(batch, 256)), dim3(256), 0, st, batch, n, resid, mask);
@@ -968,14 +968,14 @@ hipError_t sylvester_launch(int mode, const float* X1, const float* X2, const fl
 
 hipError_t symmetrize_launch(const float* in, int batch, int n, float* out, int64_t ldo, int64_t so,
                              hipStream_t st) {
-  hipLaunchKernelGGL(k_symmetrize, dim3(grid1((int64_t)n * n), batch), dim3(256), 0, st, in, n, out, ldo,
+  hipLaunchKernelGGL(k_symmetrize, dim3(std::min(n, 512), batch), dim3(256), 0, st, in, n, out, ldo,
                      so);
   LAUNCH_CHECK();
 }
 
 hipError_t copy_launch(const float* src, int64_t lds, int64_t ss, const int* sel, const float* src_alt,
                        float* dst, int64_t ldd, int64_t sd, int batch, int m, int n, hipStream_t st) {
-  hipLaunchKernelGGL(k_copy, dim3(grid1((int64_t)m * n), batch), dim3(256), 0, st, src, lds, ss, sel,
+  hipLaunchKernelGGL(k_copy, dim3(std::min(m, 512), batch), dim3(256), 0, st, src, lds, ss, sel,
                      src_alt, dst, ldd, sd, m, n);
   LAUNCH_CHECK();
 }
