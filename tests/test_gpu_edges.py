@@ -115,6 +115,45 @@ def test_rank_deficient_blocked_qr_1024(api):
         assert lead > 1 - 1e-4
 
 
+def test_rank_deficient_blocked_qr_tall_and_learned(api):
+    # the blocked QR step on a tall, exactly rank-deficient matrix: 1536 x 768
+    # whose last 668 columns are zero (rank 100, kappa 10), on the
+    # conservative path and on the learned BF16 path (a predictor model loaded;
+    # a failed bound falls back to conservative CANS).  CANS leaves the zero
+    # directions of W at zero, the column-norm test flags U and the QR step
+    # completes it: U orthonormal, sigma against the generating spectrum, the
+    # leading vectors against the generating Q1
+    import torch
+    from paper_2609_32505_amd import predictor
+    m, n, r = 1536, 768, 100
+    _say("1536 x 768 with 668 zero columns (rank 100): blocked QR, conservative and learned")
+    rng = inputs.rng_for(94, 0)
+    sr = inputs.paper_kappa_rank(r, 10.0)
+    Q1 = inputs.orthonormal(rng, m, r)
+    Q2 = inputs.orthonormal(rng, r, r)
+    A = np.zeros((1, m, n), np.float32)
+    A[0, :, :r] = (Q1 * sr) @ Q2.T
+    s = np.concatenate([sr, np.zeros(n - r)])
+    h = api.Handle()
+    h.set_model(predictor.load())
+    probe = torch.from_numpy(inputs.probe(17, 1, n)).cuda()
+    for label, kw, tol_s in [("conservative", {}, 1e-5),
+                             ("learned-bf16", dict(precision=1, bound=1, probe=probe), 1e-3)]:
+        U, S, V, info = api.svd_fwd(dev(A), handle=h, **kw)
+        torch.cuda.synchronize()
+        inf = api.info_to_numpy(info)
+        Uh, Sh, Vh = (t.cpu().double().numpy()[0] for t in (U, S, V))
+        orth = np.abs(Uh.T @ Uh - np.eye(n)).max()
+        serr = np.abs(Sh - s).max() / s[0]
+        lead = np.abs(np.sum(Uh[:, :r] * Q1, axis=0)).min()
+        rec = np.linalg.norm((Uh * Sh) @ Vh.T - A[0]) / np.linalg.norm(A[0])
+        _say(f"  {label}: flags {inf['flags'][0]}, |U^T U - I| {orth:.2e}, sigma err {serr:.2e}, recon {rec:.2e}, "
+             f"min |<u_i, q_i>| {lead:.6f}")
+        assert inf["flags"][0] & 8
+        assert orth < 1e-5 and serr < tol_s
+        assert lead > 1 - (1e-4 if label == "conservative" else 1e-2)
+
+
 def _eigh_backward_error(api, H, **kw):
     import torch
     lam, V, info = api.eigh(H, **kw)
