@@ -230,6 +230,10 @@ def main():
     err_po = float((np.abs(Sp[:k] - S_or).max(axis=1) / S_or[:, 0]).max())
     err_lo = float((np.abs(Sl[:k] - S_or).max(axis=1) / S_or[:, 0]).max())
     valid = err_lp + err_po <= 1e-3 and err_lo <= 1e-3
+    # also per singular value, max_i |s_i - t_i| / t_i (reported, not the validity test)
+    rel_lp = float((np.abs(Sl - Sp) / Sp).max())
+    rel_po = float((np.abs(Sp[:k] - S_or) / S_or).max())
+    rel_lo = float((np.abs(Sl[:k] - S_or) / S_or).max())
 
     def recon_orth(U, S, V):
         # |U diag(S) V^T - A|_F / |A|_F and max |U^T U - I| per matrix (FP32 on the GPU)
@@ -268,7 +272,9 @@ def main():
                                    for k2, v in prof_p.items()}},
         "speedup_learned_vs_plain": round(ms_p / ms_l, 4),
         "sigma_err": {"learned_vs_plain_max": err_lp, "plain_vs_oracle_sampled": err_po,
-                      "learned_vs_oracle_sampled": err_lo, "valid": bool(valid)},
+                      "learned_vs_oracle_sampled": err_lo, "valid": bool(valid),
+                      "relative": {"learned_vs_plain_max": rel_lp, "plain_vs_oracle_sampled": rel_po,
+                                   "learned_vs_oracle_sampled": rel_lo}},
         "factor_err": {"recon_learned_max": rec_l, "orth_U_learned_max": orth_l,
                        "recon_plain_max": rec_p, "orth_U_plain_max": orth_p},
         "learned_info": {"iters_max": int(il["iters"].max()), "iters_mean": round(float(il["iters"].mean()), 2),
