@@ -79,17 +79,32 @@ def recorded_traffic(kind: str):
     return float(rec["hbm_bytes_per_dispatch"])
 
 
+def kind_peak(name):
+    if name in ("gemm_f32", "jac_apply"):
+        return PEAKS["mfma_fp32"]
+    if name == "gemm_bf16":
+        return PEAKS["mfma_bf16"]
+    if name == "jac_solve_f64":
+        return PEAKS["alu_fp64"]
+    return PEAKS["alu_fp32"]
+
+
+def kernel_table(prof, steps):
+    # per kernel class: time per step, launches, and the algorithmic rate
+    # over the event-timed launches against that class's own peak
+    out = {}
+    for k2, v in prof.items():
+        tf = v["flops"] / (v["ms"] * 1e-3) / 1e12 if v["ms"] > 0 else 0.0
+        out[k2] = {"ms_per_step": round(v["ms"] / steps, 3), "launches": v["launches"],
+                   "tflops": round(tf, 2), "frac_of_peak": round(tf / kind_peak(k2), 4)}
+    return out
+
+
 def roofline_of(prof):
     name = max(prof, key=lambda k: prof[k]["ms"])
     rec = prof[name]
-    if name in ("gemm_f32", "jac_apply"):
-        bound, peak = "mfma", PEAKS["mfma_fp32"]
-    elif name == "gemm_bf16":
-        bound, peak = "mfma", PEAKS["mfma_bf16"]
-    elif name == "jac_solve_f64":
-        bound, peak = "alu", PEAKS["alu_fp64"]
-    else:
-        bound, peak = "alu", PEAKS["alu_fp32"]
+    bound = "mfma" if name in ("gemm_f32", "gemm_bf16", "jac_apply") else "alu"
+    peak = kind_peak(name)
     avg_ms = rec["ms"] / max(rec["launches"], 1)
     per_launch = rec["flops"] / max(rec["launches"], 1)
     achieved = per_launch / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
@@ -268,8 +283,7 @@ def main():
         "plain_fp32": {"value": round(B / (ms_p * 1e-3), 3), "ms_per_step": round(ms_p, 3),
                        "ms_per_step_std": round(sd_p, 3),
                        "iters_max": int(ip["iters"].max()), "iters_mean": round(float(ip["iters"].mean()), 2),
-                       "kernels": {k2: {"ms_per_step": round(v["ms"] / args.steps, 3), "launches": v["launches"]}
-                                   for k2, v in prof_p.items()}},
+                       "kernels": kernel_table(prof_p, args.steps)},
         "speedup_learned_vs_plain": round(ms_p / ms_l, 4),
         "sigma_err": {"learned_vs_plain_max": err_lp, "plain_vs_oracle_sampled": err_po,
                       "learned_vs_oracle_sampled": err_lo, "valid": bool(valid),
@@ -281,8 +295,7 @@ def main():
                          "sweeps_max": int(il["sweeps"].max()),
                          "fallbacks": int(((il["flags"] & L.FLAG_FALLBACK_USED) != 0).sum())},
         "roofline": roof,
-        "kernels": {k2: {"ms_per_step": round(v["ms"] / args.steps, 3), "launches": v["launches"]}
-                    for k2, v in prof.items()},
+        "kernels": kernel_table(prof, args.steps),
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)
