@@ -176,9 +176,10 @@ def main():
     eps = dict(eps_K=1e-12, eps_R=0.0, eps_T=0.0)
     # The learned BF16 path's polar factor is accurate to about 1e-3 (its
     # reconstruction error); its eigensolver is held to a backward error of
-    # 1e-4 (restart tolerance, no FP64 final sweep) instead of the FP32
-    # path's 6e-6, an order of magnitude below the factor it decomposes.
-    learned_eigh = dict(fp64_sweeps=0, eigh_off_tol=1e-4, jacobi_fro_tol=1e-3)
+    # 1e-4 (restart tolerance) instead of the FP32 path's 6e-6, an order of
+    # magnitude below the factor it decomposes.  The FP64 final sweep stays:
+    # without it the smallest singular values lose 1e-3 relative accuracy.
+    learned_eigh = dict(fp64_sweeps=1, eigh_off_tol=1e-4, jacobi_fro_tol=1e-3)
 
     def step(learned: bool):
         if learned:
@@ -244,11 +245,14 @@ def main():
     k = S_or.shape[0]
     err_po = float((np.abs(Sp[:k] - S_or).max(axis=1) / S_or[:, 0]).max())
     err_lo = float((np.abs(Sl[:k] - S_or).max(axis=1) / S_or[:, 0]).max())
-    valid = err_lp + err_po <= 1e-3 and err_lo <= 1e-3
-    # also per singular value, max_i |s_i - t_i| / t_i (reported, not the validity test)
+    # also per singular value, max_i |s_i - t_i| / t_i
     rel_lp = float((np.abs(Sl - Sp) / Sp).max())
     rel_po = float((np.abs(Sp[:k] - S_or) / S_or).max())
     rel_lo = float((np.abs(Sl[:k] - S_or) / S_or).max())
+    # valid under both readings of "sigma error <= 1e-3": normwise (relative to
+    # sigma_1) and per singular value
+    valid = (err_lp + err_po <= 1e-3 and err_lo <= 1e-3 and rel_lp + rel_po <= 1e-3
+             and rel_lo <= 1e-3)
 
     def recon_orth(U, S, V):
         # |U diag(S) V^T - A|_F / |A|_F and max |U^T U - I| per matrix (FP32 on the GPU)

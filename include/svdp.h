@@ -107,10 +107,13 @@ typedef struct {
                               its square; tightly clustered spectra need the margin (3e-3) */
   double jacobi_abs;       /* entries below jacobi_abs |H|_F are ignored by that test (1e-9) */
   double bf16_from;        /* bounded paths: FP32 steps until the interval's lower end
-                              reaches this value, BF16 steps after it (0.1).  BF16 rounding
+                              reaches this value, BF16 steps after it (0.5).  BF16 rounding
                               while a singular value is still small rotates its singular
-                              vectors: lower values buy speed with larger U, V errors (at
-                              kappa = 1e3, reconstruction error 3.5e-3 at 0.1, 1e-2 at 0.05) */
+                              vectors and moves the small singular values: lower values buy
+                              speed with larger errors (256 x 512^2, sigma in [1e-3, 1], with
+                              the FP64 final sweep: largest per-value relative sigma error
+                              5.8e-4 at 0.5, 0.8-1e-3 at 0.3, 1.5e-3 at 0.2, 3.4e-3 at 0.1,
+                              for 0.7 ms per 256 matrices between 0.3 and 0.5) */
   double eps_K, eps_R, eps_T; /* backward regularisers (absolute, units of sigma^2):
                               K_ij = (s_i - s_j)/((s_i - s_j)^2 + eps_K),
                               R = V S (S^2 + eps_R)^-1 V^T,

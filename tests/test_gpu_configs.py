@@ -16,9 +16,11 @@ pytestmark = pytest.mark.gpu
 # |U^T U - I|, |V^T V - I| bound: CANS stops at a relative change of 1e-5, which
 # leaves |W^T W - I| of that order (the paper reports 2-4e-6 in FP32 at 4096^2)
 ORTH_TOL = 1e-5
-# the benchmark's learned-path eigensolver settings (backward error 1e-4, no
-# FP64 final sweep: an order of magnitude below the BF16 polar factor's error)
-LEARNED_EIGH = dict(fp64_sweeps=0, eigh_off_tol=1e-4, jacobi_fro_tol=1e-3)
+# the benchmark's learned-path eigensolver settings: backward error 1e-4 (an
+# order of magnitude below the BF16 polar factor's error), with the FP64
+# final sweep, which the smallest singular values need for 1e-3 relative
+# accuracy
+LEARNED_EIGH = dict(fp64_sweeps=1, eigh_off_tol=1e-4, jacobi_fro_tol=1e-3)
 
 
 def _say(*a):
@@ -101,8 +103,14 @@ def test_square_512_batch256_both_paths(api, handle):
         Uh, Vh = U.cpu().double().numpy(), V.cpu().double().numpy()
         _sampled_oracle(A, Uh, Sh, Vh, [0, 255], tol_s, tol_w, label)
         res[label] = Sh
-    # the learned path agrees with the plain path on every matrix
-    assert (np.abs(res["learned-bf16"] - res["plain-fp32"]).max(axis=1) / res["plain-fp32"][:, 0]).max() < 1e-3
+    # the learned path agrees with the plain path on every matrix, normwise and
+    # per singular value
+    d = np.abs(res["learned-bf16"] - res["plain-fp32"])
+    rel = (d / res["plain-fp32"]).max()
+    _say(f"  learned vs plain: normwise {(d.max(axis=1) / res['plain-fp32'][:, 0]).max():.2e}, "
+         f"per-value relative {rel:.2e}")
+    assert (d.max(axis=1) / res["plain-fp32"][:, 0]).max() < 1e-3
+    assert rel < 1e-3
 
 
 def test_tall_4096x1024_batch16(api, handle):
