@@ -489,7 +489,7 @@ svdp_status bounded(Ctx& c) {
       float* y = (k & 1) ? w.y0 : w.y1;
       int trans = (k & 1) ? 0 : 1;
       int len = trans ? n : m;
-      HIPCHK(matvec_launch(c.A, c.lda, c.sA, B, m, n, x, sx, y, m, trans, c.st), "matvec");
+      HIPCHK(matvec_launch(c.A, c.lda, c.sA, B, m, n, x, sx, y, m, trans, w.fro2, c.st), "matvec");
       HIPCHK(vnorm_launch(y, m, B, len, w.nrm, k, c.st), "vnorm");
       x = y;
       sx = m;
@@ -1230,7 +1230,7 @@ svdp_status svdp_bound_features(svdp_handle* h, const svdp_params* p, const floa
   for (int k = 1; k <= 7; ++k) {
     float* y = (k & 1) ? w.y0 : w.y1;
     int trans = (k & 1) ? 0 : 1;
-    HIPCHK(matvec_launch(A, lda, sA, B, m, n, x, sx, y, m, trans, st), "matvec");
+    HIPCHK(matvec_launch(A, lda, sA, B, m, n, x, sx, y, m, trans, w.fro2, st), "matvec");
     HIPCHK(vnorm_launch(y, m, B, trans ? n : m, w.nrm, k, st), "vnorm");
     x = y;
     sx = m;

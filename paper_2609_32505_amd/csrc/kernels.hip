@@ -486,8 +486,13 @@ __global__ void k_copy(const float* src, int64_t lds, int64_t ss, const int* sel
 // ------------------------------------------------------------ features
 
 // y = A x: one wave per row
+// 1 / |A[b]|_F when fro2 is given (the power sequence runs on A / |A|_F, so
+// its norms stay below |x| whatever the scale of A), else 1
+SVDP_DEV float matvec_scale(const float* fro2, int b) {
+  return (fro2 && fro2[b] > 0.f) ? 1.f / sqrtf(fro2[b]) : 1.f;
+}
 __global__ void k_matvec_n(const float* A, int64_t lda, int64_t sA, int m, int n, const float* x,
-                           int64_t sx, float* y, int64_t sy) {
+                           int64_t sx, float* y, int64_t sy, const float* fro2) {
   const int b = blockIdx.y;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int i = blockIdx.x * 4 + w;
@@ -497,11 +502,11 @@ __global__ void k_matvec_n(const float* A, int64_t lda, int64_t sA, int m, int n
   float s = 0.f;
   for (int j = lane; j < n; j += 64) s += r[j] * xb[j];
   s = wave_sum(s);
-  if (lane == 0) y[b * sy + i] = s;
+  if (lane == 0) y[b * sy + i] = s * matvec_scale(fro2, b);
 }
 // y = A^T x: thread per column over a chunk of rows, atomics into cleared y
 __global__ void k_matvec_t(const float* A, int64_t lda, int64_t sA, int m, int n, int rows_per,
-                           const float* x, int64_t sx, float* y, int64_t sy) {
+                           const float* x, int64_t sx, float* y, int64_t sy, const float* fro2) {
   const int b = blockIdx.z;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
@@ -510,24 +515,25 @@ __global__ void k_matvec_t(const float* A, int64_t lda, int64_t sA, int m, int n
   const float* xb = x + b * sx;
   float s = 0.f;
   for (int i = i0; i < i1; ++i) s += p[(int64_t)i * lda] * xb[i];
-  atomicAdd(y + b * sy + j, s);
+  atomicAdd(y + b * sy + j, s * matvec_scale(fro2, b));
 }
 
+// sum of squares in FP64: no overflow before the square root
 __global__ void k_vnorm(const float* v, int64_t sv, int len, float* nrm, int slot) {
   const int b = blockIdx.x;
-  float s = 0.f;
+  double s = 0.0;
   for (int j = threadIdx.x; j < len; j += blockDim.x) {
-    float x = v[b * sv + j];
+    const double x = v[b * sv + j];
     s += x * x;
   }
-  s = wave_sum(s);
-  __shared__ float part[16];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  __shared__ double part[16];
   if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
   __syncthreads();
   if (threadIdx.x == 0) {
-    float t = 0.f;
+    double t = 0.0;
     for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += part[w];
-    nrm[b * 8 + slot] = sqrtf(t);
+    nrm[b * 8 + slot] = (float)sqrt(t);
   }
 }
 
@@ -547,9 +553,15 @@ __global__ void k_features(const float* fro2, const float* nrm, int batch, int m
                            float* aux) {
   int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= batch) return;
+  // nrm holds the norms of the sequence on A / |A|_F: its ratios are those of
+  // A divided by |A|_F, so the features see |A|_F = 1 and the sigma_max
+  // estimate aux[0] is scaled back
   double nr[8];
   for (int k = 0; k < 8; ++k) nr[k] = nrm[b * 8 + k];
-  features_from(sqrt((double)fro2[b]), nr, (double)n, (double)m / (double)n, F + b * 8, aux + b * 2);
+  const double fro = sqrt((double)fro2[b]);
+  features_from(1.0, nr, (double)n, (double)m / (double)n, F + b * 8, aux + b * 2);
+  aux[b * 2] = (float)((double)aux[b * 2] * fro);
+  aux[b * 2 + 1] = (float)fro;
 }
 
 // one wave per row: |s^k z| for k = 0..7 and |s|
@@ -981,10 +993,10 @@ hipError_t copy_launch(const float* src, int64_t lds, int64_t ss, const int* sel
 }
 
 hipError_t matvec_launch(const float* A, int64_t lda, int64_t sA, int batch, int m, int n, const float* x,
-                         int64_t sx, float* y, int64_t sy, int trans, hipStream_t st) {
+                         int64_t sx, float* y, int64_t sy, int trans, const float* fro2, hipStream_t st) {
   if (!trans) {
     hipLaunchKernelGGL(k_matvec_n, dim3(cdiv(m, 4), batch), dim3(256), 0, st, A, lda, sA, m, n, x, sx, y,
-                       sy);
+                       sy, fro2);
     LAUNCH_CHECK();
   }
   hipError_t e;
@@ -992,7 +1004,7 @@ hipError_t matvec_launch(const float* A, int64_t lda, int64_t sA, int batch, int
   if ((e = fill_f32(y, 0.f, (int64_t)(batch - 1) * sy + n, st))) return e;
   const int rows_per = 256;
   hipLaunchKernelGGL(k_matvec_t, dim3(cdiv(n, 256), cdiv(m, rows_per), batch), dim3(256), 0, st, A, lda,
-                     sA, m, n, rows_per, x, sx, y, sy);
+                     sA, m, n, rows_per, x, sx, y, sy, fro2);
   LAUNCH_CHECK();
 }
 

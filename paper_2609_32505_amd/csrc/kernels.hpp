@@ -69,10 +69,11 @@ hipError_t copy_launch(const float* src, int64_t lds, int64_t ss, const int* sel
                        int n, hipStream_t st);
 
 // ---- sketch features and the interval predictor ---------------------------
-// y[b] = A[b] x[b] (trans = 0, length m) or A[b]^T x[b] (trans = 1, length n)
+// y[b] = c A[b] x[b] (trans = 0, length m) or c A[b]^T x[b] (trans = 1, length n),
+// c = 1 / sqrt(fro2[b]) when fro2 is given, else 1
 hipError_t matvec_launch(const float* A, int64_t lda, int64_t sA, int batch, int m, int n,
                          const float* x, int64_t sx, float* y, int64_t sy, int trans,
-                         hipStream_t st);
+                         const float* fro2, hipStream_t st);
 // nrm[b * 8 + slot] = |v[b]|_2 (v length len, stride sv)
 hipError_t vnorm_launch(const float* v, int64_t sv, int batch, int len, float* nrm, int slot,
                         hipStream_t st);

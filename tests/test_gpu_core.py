@@ -248,6 +248,52 @@ def test_features_match_oracle(api):
         np.testing.assert_allclose(aux[i], [r7, fro], rtol=1e-5)
 
 
+@pytest.mark.parametrize("scale", [1e-3, 1e3, 1e5])
+def test_features_scale_equivariant(api, scale):
+    """The power sequence (A^T A)^k A g grows as sigma_1^(2k+1): at sigma_1 ~ 1e3
+    and n = 2048 its squared norms exceed the FP32 range.  The features are
+    ratios, so they must not depend on the scale of A; the sigma_max estimate
+    and |A|_F scale with it.  Checked against the FP64 oracle at each scale."""
+    _say(f"features 2 x 300 x 256 at scale {scale:g}")
+    b, m, n = 2, 300, 256
+    A, _ = inputs.batch_with_spectra(81, b, m, n, lambda r: inputs.log_uniform(r, n, 1e-3, 1.0))
+    As = (A.astype(np.float64) * scale).astype(np.float32)
+    g = inputs.probe(81, b, n)
+    F, aux = api.bound_features(dev(As), dev(g))
+    F, aux = host(F), host(aux)
+    for i in range(b):
+        f, r7, fro = oracle.sketch_features(As[i].astype(np.float64), g[i])
+        _say(f"  b={i} f_err={np.abs(F[i] - f).max():.2e} aux {aux[i]} oracle {[r7, fro]}")
+        assert np.all(np.isfinite(F[i])) and np.all(np.isfinite(aux[i]))
+        np.testing.assert_allclose(F[i], f, atol=2e-4)
+        np.testing.assert_allclose(aux[i], [r7, fro], rtol=1e-5)
+
+
+def test_learned_path_large_scale_no_fallback(api):
+    """A learned-path SVD of 1024 A equals 1024 times that of A, with the same
+    schedule and no fallback: the features that pick the schedule are
+    scale-free (a power-of-two scale keeps every FP32 value exactly scaled;
+    before the power sequence was normalised its squared norms overflowed
+    here)."""
+    import torch
+    from paper_2609_32505_amd import predictor
+    _say("learned BF16 SVD of A and 1024 A, 4 x 512^2")
+    A, s = inputs.square_loguniform(seed=82, batch=4, n=512)
+    probe = dev(inputs.probe(82, 4, 512))
+    h = api.Handle()
+    h.set_model(predictor.load())
+    out = []
+    for c in (1.0, 1024.0):
+        U, S, V, info = api.svd_fwd(dev(A * np.float32(c)), handle=h, precision=1, bound=1, probe=probe)
+        torch.cuda.synchronize()
+        inf = api.info_to_numpy(info)
+        _say(f"  scale {c:g}: flags {inf['flags']}, iters {inf['iters']}")
+        assert not np.any(inf["flags"] & 2)
+        out.append((host(S) / c, inf["iters"]))
+    np.testing.assert_array_equal(out[0][1], out[1][1])
+    assert (np.abs(out[0][0] - out[1][0]).max(axis=1) / out[0][0][:, 0]).max() < 1e-5
+
+
 def test_mlp_fwd_bwd_adam_match_oracle(api):
     import torch
     _say("mlp fwd/bwd/pinball/adam")
