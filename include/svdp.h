@@ -265,7 +265,9 @@ svdp_status svdp_eigh_bwd(svdp_handle* h, const svdp_params* p,
  * probe: batch x n.  With y0 = probe, y1 = A y0, y2 = A^T y1, ... up to y7
  * and r_k = |y_k| / |y_(k-1)|:  F[b] = (log(|A|_F / r_7),
  * log(r_2 / r_3), ..., log(r_6 / r_7), log(n), log(m / n)) (8 floats);
- * aux[b] = (r_7, |A|_F).  F: batch x 8, aux: batch x 2. */
+ * aux[b] = (r_7, |A|_F).  F: batch x 8, aux: batch x 2.  The sequence is
+ * computed on A / |A|_F (the ratios scale back exactly), so no norm
+ * overflows FP32 whatever the scale of A. */
 svdp_status svdp_bound_features(svdp_handle* h, const svdp_params* p,
                                 const float* A, int64_t lda, int64_t sA,
                                 const float* probe, float* F, float* aux,
