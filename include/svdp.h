@@ -136,6 +136,15 @@ typedef struct {
                               sweeps for relative accuracy (3e-4; 0 disables it) */
   int32_t poly;            /* svdp_poly (CANS3); other values need bound CONSERVATIVE and
                               precision FP32 */
+  int32_t bf16_correct;    /* svd_polar_fwd, precision BF16: correct U, V and S for the BF16
+                              rounding of the polar iterate (1; 0 = off).  That rounding
+                              leaves W = W_t (I + S) with S skew of order 2^-9 / sigma_min of
+                              the iterate, which the FP32 refinement cannot remove.  With
+                              (lam, V) = eig(sym(W^T A)) and P = V^T W^T A V, S~ = V^T S V
+                              solves S~ L + L S~ = -(P - P^T) elementwise; U = W V (I - S~/2)
+                              and V (I + S~/2) are then right to second order, and
+                              sigma_i = diag((I + S~/2) P (I + S~/2)) to third.  Four n^3
+                              GEMMs and one element-wise pass */
 } svdp_params;
 
 /* per-matrix diagnostics, device array of `batch` records */

@@ -45,6 +45,7 @@ class Params(ctypes.Structure):
         ("margin_max", c_dbl), ("margin_min", c_dbl),
         ("user_bounds", c_vp), ("probe", c_vp),
         ("eigh_off_tol", c_dbl), ("eigh_restarts", c_i32), ("jacobi_fro_tol", c_dbl), ("poly", c_i32),
+        ("bf16_correct", c_i32),
     ]
 
 

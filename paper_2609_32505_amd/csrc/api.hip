@@ -235,6 +235,7 @@ svdp_status check_common(const svdp_params* p) {
   if (!(p->tol > 0)) return fail(SVDP_ERR_INVALID_ARG, "tol must be > 0");
   if (p->eps_K < 0 || p->eps_R < 0 || p->eps_T < 0) return fail(SVDP_ERR_INVALID_ARG, "eps must be >= 0");
   if (p->poly < SVDP_POLY_CANS3 || p->poly > SVDP_POLY_CANS5) return fail(SVDP_ERR_INVALID_ARG, "unknown poly");
+  if (p->bf16_correct != 0 && p->bf16_correct != 1) return fail(SVDP_ERR_INVALID_ARG, "bf16_correct must be 0 or 1");
   if (p->poly != SVDP_POLY_CANS3 && (p->bound != SVDP_BOUND_CONSERVATIVE || p->precision != SVDP_PREC_FP32))
     return fail(SVDP_ERR_INVALID_ARG, "poly variants run on the conservative FP32 path");
   return SVDP_OK;
@@ -684,9 +685,31 @@ svdp_status svd_tail(Ctx& c, float* U, int64_t ldu, int64_t sU, float* S, int64_
   EighWs e = eigh_ws_carve(w.eigh, B, n, p->max_sweeps);
   HIPCHK(eigh_run(e, w.G, n, (int64_t)n * n, 1, eigh_opts(p), S, sS, V, ldv, sV, w.sweeps, w.flags,
                   c.h->host_word, mask, &c.h->aux, c.st), "eigh");
+  // B operand of U = W V: V, or V Mu after the BF16 correction
+  const float* Vb = V;
+  int64_t ldvb = ldv, svb = sV;
+  if (p->bf16_correct && p->precision == SVDP_PREC_BF16 && !mask) {
+    // First-order correction of the BF16-rounded polar factor (the bounded
+    // path's first pass; its fallback reruns are FP32).  P = V^T (W^T A) V is
+    // the eigensolver's last restart measure T (in Vw, working order, read
+    // through perm); polar_fix gives Mu and the corrected singular values;
+    // U = W (V Mu) and V <- V (2 I - Mu) = 2 V - V Mu.  Scratch: the
+    // eigensolver's other working copies (np >= n), free once it returned.
+    const int64_t n2 = (int64_t)n * n, np2 = (int64_t)e.np * e.np;
+    HIPCHK(polar_fix_launch(e.Vw, e.np, np2, e.perm, S, sS, e.sgn, B, n, e.V2, w.colsum, nullptr, c.st),
+           "polar fix");
+    GemmArgs vu = gemm_base(n, n, n, B);  // V Mu
+    vu.A = V; vu.lda = ldv; vu.sA = sV;
+    vu.B = e.V2; vu.ldb = n; vu.sB = n2;
+    vu.C = e.Hw; vu.ldc = n; vu.sC = n2;
+    HIPCHK(gemm_launch(vu, PREC_F32, 0, 0, c.st), "V Mu");
+    HIPCHK(vcorr_launch(V, ldv, sV, e.Hw, B, n, c.st), "V");
+    HIPCHK(sigma_store_launch(w.colsum, n, S, sS, B, nullptr, c.st), "sigma");
+    Vb = e.Hw; ldvb = n; svb = n2;
+  }
   GemmArgs g = gemm_base(m, n, n, B);
   g.A = w.X0; g.A_alt = w.X1; g.a_sel = w.where; g.lda = n; g.sA = (int64_t)m * n;
-  g.B = V; g.ldb = ldv; g.sB = sV;
+  g.B = Vb; g.ldb = ldvb; g.sB = svb;
   g.C = U; g.ldc = ldu; g.sC = sU;
   g.colscale = e.sgn; g.cs_stride = n;
   g.active = mask;
@@ -755,6 +778,7 @@ void svdp_default_params(svdp_params* p, int64_t batch, int64_t m, int64_t n) {
   p->eigh_restarts = 2;
   p->jacobi_fro_tol = 3e-4;
   p->poly = SVDP_POLY_CANS3;
+  p->bf16_correct = 1;
 }
 
 const char* svdp_status_string(svdp_status s) {

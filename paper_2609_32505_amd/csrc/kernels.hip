@@ -483,14 +483,111 @@ __global__ void k_copy(const float* src, int64_t lds, int64_t ss, const int* sel
       dst[b * sd + (int64_t)i * ldd + j] = s[b * ss + (int64_t)i * lds + j];
 }
 
+// ------------------------------------------------------------ polar factor correction
+
+// First-order correction of a polar factor W = W_t (I + S) (S skew, small:
+// the rounding of a BF16 iterate) from P = V^T (W^T A) V, with (lam, V) the
+// eigenpairs of sym(W^T A) (lam_i = sgn_i s_i).  P is read from the
+// eigensolver's last T = V_w^T (W^T A) V_w (working column order, leading
+// dimension ldt) through the sort permutation: P_ij = T[perm_i, perm_j].  In that basis S~ = V^T S V
+// solves S~ L + L S~ = -(P - P^T), so S~_ij = -2 skew(P)_ij t_ij with
+// t_ij = 1 / (lam_i + lam_j), regularised as s / (s^2 + (2^-10 lam_max)^2),
+// s = lam_i + lam_j: the FP32 rounding of W^T A and P (about 1e-7 lam_max)
+// over a smaller s would swamp the signal, and a noisy S~ changes column
+// norms at second order.  U = W V
+// carries U_t (I + S~/2) and V carries V_t (I - S~/2), hence Mu = I - S~/2
+// and Mv = I + S~/2 = 2 I - Mu (only Mu is written).  The singular value of the corrected pair is
+// diag((I + S~/2) P (I + S~/2)) = P_ii + 2 sum_j skew(P)_ij^2 t_ij
+// - 1/4 sum_j S~_ij^2 lam_j + O(S^3) (P ~ L in the last term).  The
+// symmetric off-diagonal part e = sym(P)_ij that the eigensolver's stop
+// test left adds, pair by pair, the exact 2 x 2 eigenvalue shift
+// sign(d) e^2 / (sqrt(d^2/4 + e^2) + |d|/2), d = P_ii - P_jj (e^2 / d for a
+// wide gap, at most |e| for a close pair).  The result goes to snew as a
+// magnitude.  One workgroup per row; FP64 arithmetic.
+__global__ void k_polar_fix(const float* T, int ldt, int64_t sT, const int* perm, const float* S, int64_t sS,
+                            const float* sgn, int n, float* Mu, float* snew, const int* mask) {
+  const int b = blockIdx.y;
+  if (mask && !mask[b]) return;
+  const int64_t off = (int64_t)b * n * n;
+  const float* Tb = T + b * sT;
+  const int* pb = perm + (int64_t)b * n;
+  auto Pij = [&](int i, int j) -> double { return (double)Tb[(int64_t)pb[i] * ldt + pb[j]]; };
+  const float* sb = S + b * sS;
+  const float* gb = sgn + (int64_t)b * n;
+  const double lmax = fabs((double)sb[0]);
+  const double reg = ldexp(lmax, -10) * ldexp(lmax, -10);
+  __shared__ double red[2][4];
+  for (int i = blockIdx.x; i < n; i += gridDim.x) {
+    const double li = (double)gb[i] * (double)sb[i];
+    const double pii = Pij(i, i);
+    double a1 = 0.0, a2 = 0.0;
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+      const double lj = (double)gb[j] * (double)sb[j];
+      const double s = li + lj;
+      const double t = s / (s * s + reg);
+      const double pij = Pij(i, j), pji = Pij(j, i);
+      const double sk = 0.5 * (pij - pji);
+      const double st = -2.0 * sk * t;
+      Mu[off + (int64_t)i * n + j] = (float)((i == j ? 1.0 : 0.0) - 0.5 * st);
+      a1 += 2.0 * sk * sk * t;
+      a2 += st * st * lj;
+      if (j != i) {
+        const double e = 0.5 * (pij + pji);
+        const double dd = pii - Pij(j, j);
+        const double hh = sqrt(0.25 * dd * dd + e * e) + 0.5 * fabs(dd);
+        if (hh > 0.0) a1 += (dd >= 0.0 ? 1.0 : -1.0) * e * e / hh;
+      }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      a1 += __shfl_xor(a1, o);
+      a2 += __shfl_xor(a2, o);
+    }
+    if ((threadIdx.x & 63) == 0) {
+      red[0][threadIdx.x >> 6] = a1;
+      red[1][threadIdx.x >> 6] = a2;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double s1 = 0.0, s2 = 0.0;
+      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) { s1 += red[0][w]; s2 += red[1][w]; }
+      snew[(int64_t)b * n + i] = (float)fabs(pii + s1 - 0.25 * s2);
+    }
+    __syncthreads();
+  }
+}
+
+// V <- 2 V - Vu (V Mv from V Mu, Mv = 2 I - Mu); Vu contiguous n x n
+__global__ void k_vcorr(float* V, int64_t ldv, int64_t sV, const float* Vu, int n) {
+  const int b = blockIdx.y;
+  for (int i = blockIdx.x; i < n; i += gridDim.x)
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+      float* v = V + b * sV + (int64_t)i * ldv + j;
+      *v = 2.f * *v - Vu[((int64_t)b * n + i) * n + j];
+    }
+}
+
+// S[b] = snew[b] made non-increasing (a corrected value may cross its
+// neighbour by its correction only, where the two are already equal to that
+// accuracy); one thread per matrix
+__global__ void k_sigma_store(const float* snew, int n, float* S, int64_t sS, int batch, const int* mask) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= batch || (mask && !mask[b])) return;
+  float prev = snew[(int64_t)b * n];
+  S[b * sS] = prev;
+  for (int i = 1; i < n; ++i) {
+    prev = fminf(prev, snew[(int64_t)b * n + i]);
+    S[b * sS + i] = prev;
+  }
+}
+
 // ------------------------------------------------------------ features
 
-// y = A x: one wave per row
 // 1 / |A[b]|_F when fro2 is given (the power sequence runs on A / |A|_F, so
 // its norms stay below |x| whatever the scale of A), else 1
 SVDP_DEV float matvec_scale(const float* fro2, int b) {
   return (fro2 && fro2[b] > 0.f) ? 1.f / sqrtf(fro2[b]) : 1.f;
 }
+// y = A x: one wave per row
 __global__ void k_matvec_n(const float* A, int64_t lda, int64_t sA, int m, int n, const float* x,
                            int64_t sx, float* y, int64_t sy, const float* fro2) {
   const int b = blockIdx.y;
@@ -982,6 +1079,25 @@ hipError_t symmetrize_launch(const float* in, int batch, int n, float* out, int6
                              hipStream_t st) {
   hipLaunchKernelGGL(k_symmetrize, dim3(std::min(n, 512), batch), dim3(256), 0, st, in, n, out, ldo,
                      so);
+  LAUNCH_CHECK();
+}
+
+hipError_t polar_fix_launch(const float* T, int ldt, int64_t sT, const int* perm, const float* S, int64_t sS,
+                            const float* sgn, int batch, int n, float* Mu, float* snew, const int* mask,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(k_polar_fix, dim3(std::min(n, 1024), batch), dim3(256), 0, st, T, ldt, sT, perm, S, sS, sgn,
+                     n, Mu, snew, mask);
+  LAUNCH_CHECK();
+}
+
+hipError_t vcorr_launch(float* V, int64_t ldv, int64_t sV, const float* Vu, int batch, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_vcorr, dim3(std::min(n, 512), batch), dim3(256), 0, st, V, ldv, sV, Vu, n);
+  LAUNCH_CHECK();
+}
+
+hipError_t sigma_store_launch(const float* snew, int n, float* S, int64_t sS, int batch, const int* mask,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_sigma_store, dim3(cdiv(batch, 64)), dim3(64), 0, st, snew, n, S, sS, batch, mask);
   LAUNCH_CHECK();
 }
 

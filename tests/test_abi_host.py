@@ -47,6 +47,7 @@ def test_params_struct_matches_header_layout():
     assert p.margin_max == 1.1 and p.margin_min == 1.0
     assert p.eps_K == 0.0 and p.user_bounds is None and p.probe is None
     assert p.eigh_off_tol == 6e-6 and p.eigh_restarts == 2 and p.jacobi_fro_tol == 3e-4 and p.poly == 0
+    assert p.bf16_correct == 1
 
 
 def _ws(p, op):
@@ -142,6 +143,12 @@ def test_poly_argument_errors():
     assert _ws(L.default_params(1, 8, 8, poly=2, bound=1), 0)[0] == 1
     assert _ws(L.default_params(1, 8, 8, poly=1, precision=1), 0)[0] == 1
     assert _ws(L.default_params(1, 8, 8, poly=2), 0)[0] == 0
+
+
+def test_bf16_correct_argument():
+    L, lib = _lib()
+    assert _ws(L.default_params(1, 8, 8, bf16_correct=2), 0)[0] == 1
+    assert _ws(L.default_params(1, 8, 8, bf16_correct=0), 0)[0] == 0
 
 
 @pytest.mark.parametrize("lo", [1e-6, 1e-3, 0.2, 1.0])
