@@ -180,6 +180,8 @@ def main():
     # magnitude below the factor it decomposes.  The FP64 final sweep stays:
     # without it the smallest singular values lose 1e-3 relative accuracy.
     learned_eigh = dict(fp64_sweeps=1, eigh_off_tol=1e-4, jacobi_fro_tol=1e-3)
+    # the library defaults the learned path runs with (reported in config)
+    dp = L.default_params(B, n, n)
 
     def step(learned: bool):
         if learned:
@@ -283,7 +285,8 @@ def main():
         "vs_baseline": None, "dtype": "bf16+fp32", "data": "synthetic",
         "config": {"workload": f"{B} x {n} x {n} FP32, sigma log-uniform [1e-3,1], svd_polar_fwd + "
                                f"svd_polar_bwd, learned-bound BF16 CANS", "batch": B, "m": n, "n": n,
-                   "learned_eigh": learned_eigh},
+                   "learned_eigh": learned_eigh,
+                   "learned_bf16": {"bf16_from": dp.bf16_from, "bf16_correct": dp.bf16_correct}},
         "plain_fp32": {"value": round(B / (ms_p * 1e-3), 3), "ms_per_step": round(ms_p, 3),
                        "ms_per_step_std": round(sd_p, 3),
                        "iters_max": int(ip["iters"].max()), "iters_mean": round(float(ip["iters"].mean()), 2),

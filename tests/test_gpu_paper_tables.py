@@ -26,6 +26,11 @@ N = 4096
 KAPPAS = [10.0, 1e3, 1e6]
 REC_TOL = 1.5e-5
 ORTH_TOL = 1e-5
+# the learned BF16 rows are reduced precision: their orthogonality measures
+# 4e-6 to 1.5e-5 at kappa = 1e6 from run to run (the predictor's atomic sums
+# are not bitwise reproducible); the paper's reduced-precision (TF32) rows of
+# Table 2 are at 6.2e-4
+ORTH_TOL_BF16 = 1e-4
 GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_hyperparameters.json")))
 
 
@@ -113,7 +118,7 @@ def test_paper_tables_4096(api, handle, haar, kappa):
     _say(f"  learned-bf16 (iters {inf['iters'][0]}, flags {inf['flags'][0]}): sigma error {sig_l:.2e}, "
          f"reconstruction {rec_l:.2e}, orthogonality {orth_l:.2e}")
     assert not np.any(inf["flags"] & (16 | 32))
-    assert sig_l < 1e-3 and orth_l < ORTH_TOL
+    assert sig_l < 1e-3 and orth_l < ORTH_TOL_BF16
 
 
 @pytest.mark.parametrize("rank", [1, 64, 1024, 4095, 4096])
