@@ -524,7 +524,8 @@ __global__ void k_polar_fix(const float* T, int ldt, int64_t sT, const int* perm
     for (int j = threadIdx.x; j < n; j += blockDim.x) {
       const double lj = (double)gb[j] * (double)sb[j];
       const double s = li + lj;
-      const double t = s / (s * s + reg);
+      const double den = s * s + reg;
+      const double t = den > 0.0 ? s / den : 0.0;  // 0 for an all-zero spectrum
       const double pij = Pij(i, j), pji = Pij(j, i);
       const double sk = 0.5 * (pij - pji);
       const double st = -2.0 * sk * t;
@@ -1270,6 +1271,15 @@ __global__ void k_copy_masked(const float* src, float* dst, int64_t per_matrix, 
        i += (int64_t)gridDim.x * blockDim.x)
     d4[i] = s4[i];
 }
+// the same for a per-matrix size that is not a multiple of 4 (no vector
+// alignment across matrices)
+__global__ void k_copy_masked1(const float* src, float* dst, int64_t per_matrix, const int* mask) {
+  const int b = blockIdx.y;
+  if (!mask[b]) return;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < per_matrix;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[b * per_matrix + i] = src[b * per_matrix + i];
+}
 }  // namespace
 
 hipError_t sched_counts_launch(int batch, const int* ksteps, int kcap, int bf16, int* counts, hipStream_t st) {
@@ -1287,8 +1297,12 @@ hipError_t sched_iters_launch(int batch, const int* ksteps, int* iters, hipStrea
 }
 hipError_t copy_masked_launch(const float* src, float* dst, int batch, int64_t per_matrix, const int* mask,
                               hipStream_t st) {
-  if (per_matrix % 4) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_copy_masked, dim3(grid1(per_matrix / 4, 256), batch), dim3(256), 0, st, src, dst,
-                     per_matrix, mask);
+  if (per_matrix <= 0 || batch <= 0) return hipSuccess;
+  if (per_matrix % 4)
+    hipLaunchKernelGGL(k_copy_masked1, dim3(grid1(per_matrix, 256), batch), dim3(256), 0, st, src, dst,
+                       per_matrix, mask);
+  else
+    hipLaunchKernelGGL(k_copy_masked, dim3(grid1(per_matrix / 4, 256), batch), dim3(256), 0, st, src, dst,
+                       per_matrix, mask);
   LAUNCH_CHECK();
 }
