@@ -143,8 +143,12 @@ typedef struct {
                               (lam, V) = eig(sym(W^T A)) and P = V^T W^T A V, S~ = V^T S V
                               solves S~ L + L S~ = -(P - P^T) elementwise; U = W V (I - S~/2)
                               and V (I + S~/2) are then right to second order, and
-                              sigma_i = diag((I + S~/2) P (I + S~/2)) to third.  Four n^3
-                              GEMMs and one element-wise pass */
+                              sigma_i = diag((I + S~/2) P (I + S~/2)) to third, plus the
+                              2 x 2 shift of the coupling the eigensolver's stop leaves in
+                              P.  P is the eigensolver's last restart measure; the cost is
+                              one n^3 GEMM and two element-wise passes.  polar_fwd's W and H
+                              are not corrected; tall matrices keep W's error outside A's
+                              column space */
 } svdp_params;
 
 /* per-matrix diagnostics, device array of `batch` records */
