@@ -696,16 +696,17 @@ svdp_status svd_tail(Ctx& c, float* U, int64_t ldu, int64_t sU, float* S, int64_
     // U = W (V Mu) and V <- V (2 I - Mu) = 2 V - V Mu.  Scratch: the
     // eigensolver's other working copies (np >= n), free once it returned.
     const int64_t n2 = (int64_t)n * n, np2 = (int64_t)e.np * e.np;
-    HIPCHK(polar_fix_launch(e.Vw, e.np, np2, e.perm, S, sS, e.sgn, B, n, e.V2, w.colsum, nullptr, c.st),
-           "polar fix");
+    // P and then Mu in Hw, P^T in V2, diag(P) in y0 (batch x m >= n)
+    HIPCHK(polar_fix_launch(e.Vw, e.np, np2, e.perm, S, sS, e.sgn, B, n, e.Hw, e.V2, w.y0, w.colsum, nullptr,
+                            c.st), "polar fix");
     GemmArgs vu = gemm_base(n, n, n, B);  // V Mu
     vu.A = V; vu.lda = ldv; vu.sA = sV;
-    vu.B = e.V2; vu.ldb = n; vu.sB = n2;
-    vu.C = e.Hw; vu.ldc = n; vu.sC = n2;
+    vu.B = e.Hw; vu.ldb = n; vu.sB = n2;
+    vu.C = e.V2; vu.ldc = n; vu.sC = n2;
     HIPCHK(gemm_launch(vu, PREC_F32, 0, 0, c.st), "V Mu");
-    HIPCHK(vcorr_launch(V, ldv, sV, e.Hw, B, n, c.st), "V");
+    HIPCHK(vcorr_launch(V, ldv, sV, e.V2, B, n, c.st), "V");
     HIPCHK(sigma_store_launch(w.colsum, n, S, sS, B, nullptr, c.st), "sigma");
-    Vb = e.Hw; ldvb = n; svb = n2;
+    Vb = e.V2; ldvb = n; svb = n2;
   }
   GemmArgs g = gemm_base(m, n, n, B);
   g.A = w.X0; g.A_alt = w.X1; g.a_sel = w.where; g.lda = n; g.sA = (int64_t)m * n;

@@ -487,57 +487,100 @@ __global__ void k_copy(const float* src, int64_t lds, int64_t ss, const int* sel
 
 // First-order correction of a polar factor W = W_t (I + S) (S skew, small:
 // the rounding of a BF16 iterate) from P = V^T (W^T A) V, with (lam, V) the
-// eigenpairs of sym(W^T A) (lam_i = sgn_i s_i).  P is read from the
-// eigensolver's last T = V_w^T (W^T A) V_w (working column order, leading
-// dimension ldt) through the sort permutation: P_ij = T[perm_i, perm_j].  In that basis S~ = V^T S V
-// solves S~ L + L S~ = -(P - P^T), so S~_ij = -2 skew(P)_ij t_ij with
+// eigenpairs of sym(W^T A) (lam_i = sgn_i s_i).  P is the eigensolver's last
+// T = V_w^T (W^T A) V_w (working column order) in sorted order:
+// P_ij = T[perm_i, perm_j].  In that basis S~ = V^T S V solves
+// S~ L + L S~ = -(P - P^T), so S~_ij = -2 skew(P)_ij t_ij with
 // t_ij = 1 / (lam_i + lam_j), regularised as s / (s^2 + (2^-10 lam_max)^2),
 // s = lam_i + lam_j: the FP32 rounding of W^T A and P (about 1e-7 lam_max)
 // over a smaller s would swamp the signal, and a noisy S~ changes column
-// norms at second order.  U = W V
-// carries U_t (I + S~/2) and V carries V_t (I - S~/2), hence Mu = I - S~/2
-// and Mv = I + S~/2 = 2 I - Mu (only Mu is written).  The singular value of the corrected pair is
+// norms at second order.  U = W V carries U_t (I + S~/2) and V carries
+// V_t (I - S~/2), hence Mu = I - S~/2 and Mv = I + S~/2 = 2 I - Mu (only Mu
+// is written).  The singular value of the corrected pair is
 // diag((I + S~/2) P (I + S~/2)) = P_ii + 2 sum_j skew(P)_ij^2 t_ij
 // - 1/4 sum_j S~_ij^2 lam_j + O(S^3) (P ~ L in the last term).  The
 // symmetric off-diagonal part e = sym(P)_ij that the eigensolver's stop
 // test left adds, pair by pair, the exact 2 x 2 eigenvalue shift
 // sign(d) e^2 / (sqrt(d^2/4 + e^2) + |d|/2), d = P_ii - P_jj (e^2 / d for a
 // wide gap, at most |e| for a close pair).  The result goes to snew as a
-// magnitude.  One workgroup per row; FP64 arithmetic.
-__global__ void k_polar_fix(const float* T, int ldt, int64_t sT, const int* perm, const float* S, int64_t sS,
+// magnitude.
+// Three passes, all row-contiguous: k_polar_gather stages row perm_i of T
+// in LDS and writes row i of P (and its diagonal entry), k_transpose32
+// forms P^T, and k_polar_fix reads rows i of P and P^T.
+
+// P[i, :] = T[perm_i, perm[:]] and dP[i] = P_ii; one workgroup per row, the
+// row of T (n floats) in dynamic LDS
+__global__ void k_polar_gather(const float* T, int ldt, int64_t sT, const int* perm, int n, float* P, float* dP,
+                               const int* mask) {
+  extern __shared__ float trow[];
+  const int b = blockIdx.y;
+  if (mask && !mask[b]) return;
+  const float* Tb = T + b * sT;
+  const int* pb = perm + (int64_t)b * n;
+  float* Pb = P + (int64_t)b * n * n;
+  for (int i = blockIdx.x; i < n; i += gridDim.x) {
+    const float* tr = Tb + (int64_t)pb[i] * ldt;
+    for (int j = threadIdx.x; j < n; j += blockDim.x) trow[j] = tr[j];
+    __syncthreads();
+    for (int j = threadIdx.x; j < n; j += blockDim.x) Pb[(int64_t)i * n + j] = trow[pb[j]];
+    if (threadIdx.x == 0) dP[(int64_t)b * n + i] = trow[pb[i]];
+    __syncthreads();
+  }
+}
+
+// Pt = P^T per matrix (n x n contiguous), 32 x 32 tiles through LDS
+__global__ void k_transpose32(const float* P, int n, float* Pt, const int* mask) {
+  __shared__ float tile[32][33];
+  const int b = blockIdx.z;
+  if (mask && !mask[b]) return;
+  const int64_t off = (int64_t)b * n * n;
+  const int i0 = blockIdx.y * 32, j0 = blockIdx.x * 32;
+  for (int r = threadIdx.y; r < 32; r += blockDim.y) {
+    const int i = i0 + r, j = j0 + threadIdx.x;
+    if (i < n && j < n) tile[r][threadIdx.x] = P[off + (int64_t)i * n + j];
+  }
+  __syncthreads();
+  for (int r = threadIdx.y; r < 32; r += blockDim.y) {
+    const int i = j0 + r, j = i0 + threadIdx.x;  // Pt[i][j] = P[j][i]
+    if (i < n && j < n) Pt[off + (int64_t)i * n + j] = tile[threadIdx.x][r];
+  }
+}
+
+// Mu and snew from P, Pt = P^T and dP = diag(P); one workgroup per row, FP64
+// arithmetic.  Mu may be P itself: each element is read before the same
+// thread overwrites it, and no other row reads it.
+__global__ void k_polar_fix(const float* P, const float* Pt, const float* dP, const float* S, int64_t sS,
                             const float* sgn, int n, float* Mu, float* snew, const int* mask) {
   const int b = blockIdx.y;
   if (mask && !mask[b]) return;
   const int64_t off = (int64_t)b * n * n;
-  const float* Tb = T + b * sT;
-  const int* pb = perm + (int64_t)b * n;
-  auto Pij = [&](int i, int j) -> double { return (double)Tb[(int64_t)pb[i] * ldt + pb[j]]; };
   const float* sb = S + b * sS;
   const float* gb = sgn + (int64_t)b * n;
+  const float* db = dP + (int64_t)b * n;
   const double lmax = fabs((double)sb[0]);
   const double reg = ldexp(lmax, -10) * ldexp(lmax, -10);
   __shared__ double red[2][4];
   for (int i = blockIdx.x; i < n; i += gridDim.x) {
     const double li = (double)gb[i] * (double)sb[i];
-    const double pii = Pij(i, i);
+    const double pii = db[i];
     double a1 = 0.0, a2 = 0.0;
     for (int j = threadIdx.x; j < n; j += blockDim.x) {
       const double lj = (double)gb[j] * (double)sb[j];
       const double s = li + lj;
       const double den = s * s + reg;
       const double t = den > 0.0 ? s / den : 0.0;  // 0 for an all-zero spectrum
-      const double pij = Pij(i, j), pji = Pij(j, i);
+      const double pij = P[off + (int64_t)i * n + j], pji = Pt[off + (int64_t)i * n + j];
       const double sk = 0.5 * (pij - pji);
       const double st = -2.0 * sk * t;
-      Mu[off + (int64_t)i * n + j] = (float)((i == j ? 1.0 : 0.0) - 0.5 * st);
       a1 += 2.0 * sk * sk * t;
       a2 += st * st * lj;
       if (j != i) {
         const double e = 0.5 * (pij + pji);
-        const double dd = pii - Pij(j, j);
+        const double dd = pii - (double)db[j];
         const double hh = sqrt(0.25 * dd * dd + e * e) + 0.5 * fabs(dd);
         if (hh > 0.0) a1 += (dd >= 0.0 ? 1.0 : -1.0) * e * e / hh;
       }
+      Mu[off + (int64_t)i * n + j] = (float)((i == j ? 1.0 : 0.0) - 0.5 * st);
     }
     for (int o = 32; o > 0; o >>= 1) {
       a1 += __shfl_xor(a1, o);
@@ -1084,10 +1127,16 @@ hipError_t symmetrize_launch(const float* in, int batch, int n, float* out, int6
 }
 
 hipError_t polar_fix_launch(const float* T, int ldt, int64_t sT, const int* perm, const float* S, int64_t sS,
-                            const float* sgn, int batch, int n, float* Mu, float* snew, const int* mask,
-                            hipStream_t st) {
-  hipLaunchKernelGGL(k_polar_fix, dim3(std::min(n, 1024), batch), dim3(256), 0, st, T, ldt, sT, perm, S, sS, sgn,
-                     n, Mu, snew, mask);
+                            const float* sgn, int batch, int n, float* P, float* Pt, float* dP, float* snew,
+                            const int* mask, hipStream_t st) {
+  hipError_t e;
+  hipLaunchKernelGGL(k_polar_gather, dim3(std::min(n, 1024), batch), dim3(256), (size_t)n * sizeof(float), st, T,
+                     ldt, sT, perm, n, P, dP, mask);
+  if ((e = hipGetLastError())) return e;
+  hipLaunchKernelGGL(k_transpose32, dim3(cdiv(n, 32), cdiv(n, 32), batch), dim3(32, 8), 0, st, P, n, Pt, mask);
+  if ((e = hipGetLastError())) return e;
+  hipLaunchKernelGGL(k_polar_fix, dim3(std::min(n, 1024), batch), dim3(256), 0, st, P, Pt, dP, S, sS, sgn, n, P,
+                     snew, mask);
   LAUNCH_CHECK();
 }
 

@@ -64,14 +64,15 @@ hipError_t sylvester_launch(int mode, const float* X1, const float* X2, const fl
 hipError_t symmetrize_launch(const float* in, int batch, int n, float* out, int64_t ldo,
                              int64_t so, hipStream_t st);
 // First-order correction of a BF16-rounded polar factor from
-// P = V^T (W^T A) V, read as T[perm_i, perm_j] from the eigensolver's last
-// T (working order, leading dimension ldt, batch stride sT), and the
-// eigenpairs (sgn * S, V) of sym(W^T A): Mu = I - S~/2 (n x n, contiguous)
-// with S~_ij = -2 skew(P)_ij / (lam_i + lam_j), and the corrected singular
-// values snew (batch x n).  U = W V Mu and V (2 I - Mu) replace W V and V.
+// P = V^T (W^T A) V, gathered as T[perm_i, perm_j] from the eigensolver's
+// last T (working order, leading dimension ldt, batch stride sT), and the
+// eigenpairs (sgn * S, V) of sym(W^T A).  Scratch P, Pt: n x n contiguous per
+// matrix; dP: batch x n.  Leaves Mu = I - S~/2 in P (S~_ij = -2 skew(P)_ij /
+// (lam_i + lam_j)) and the corrected singular values in snew (batch x n).
+// U = W V Mu and V (2 I - Mu) replace W V and V.
 hipError_t polar_fix_launch(const float* T, int ldt, int64_t sT, const int* perm, const float* S, int64_t sS,
-                            const float* sgn, int batch, int n, float* Mu, float* snew, const int* mask,
-                            hipStream_t st);
+                            const float* sgn, int batch, int n, float* P, float* Pt, float* dP, float* snew,
+                            const int* mask, hipStream_t st);
 // V <- 2 V - Vu (Vu contiguous n x n per matrix)
 hipError_t vcorr_launch(float* V, int64_t ldv, int64_t sV, const float* Vu, int batch, int n, hipStream_t st);
 // S = snew, made non-increasing per matrix
