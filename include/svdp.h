@@ -136,7 +136,8 @@ typedef struct {
                               sweeps for relative accuracy (3e-4; 0 disables it) */
   int32_t poly;            /* svdp_poly (CANS3); other values need bound CONSERVATIVE and
                               precision FP32 */
-  int32_t bf16_correct;    /* svd_polar_fwd, precision BF16: correct U, V and S for the BF16
+  int32_t bf16_correct;    /* precision BF16: correct svd_polar_fwd's U, V and S, and polar_fwd's
+                              W, H and cached (S, V) when the cache is requested, for the BF16
                               rounding of the polar iterate (1; 0 = off).  That rounding
                               leaves W = W_t (I + S) with S skew of order 2^-9 / sigma_min of
                               the iterate, which the FP32 refinement cannot remove.  With
@@ -146,9 +147,10 @@ typedef struct {
                               sigma_i = diag((I + S~/2) P (I + S~/2)) to third, plus the
                               2 x 2 shift of the coupling the eigensolver's stop leaves in
                               P.  P is the eigensolver's last restart measure; the cost is
-                              one n^3 GEMM and two element-wise passes.  polar_fwd's W and H
-                              are not corrected; tall matrices keep W's error outside A's
-                              column space */
+                              one n^3 GEMM and two element-wise passes (polar_fwd: three more
+                              GEMMs, W <- W (V Mu) V^T and H = sym(W^T A)).  polar_fwd without
+                              the cache is not corrected; tall matrices keep W's error outside
+                              A's column space */
 } svdp_params;
 
 /* per-matrix diagnostics, device array of `batch` records */

@@ -697,8 +697,8 @@ svdp_status svd_tail(Ctx& c, float* U, int64_t ldu, int64_t sU, float* S, int64_
     // eigensolver's other working copies (np >= n), free once it returned.
     const int64_t n2 = (int64_t)n * n, np2 = (int64_t)e.np * e.np;
     // P and then Mu in Hw, P^T in V2, diag(P) in y0 (batch x m >= n)
-    HIPCHK(polar_fix_launch(e.Vw, e.np, np2, e.perm, S, sS, e.sgn, B, n, e.Hw, e.V2, w.y0, w.colsum, nullptr,
-                            c.st), "polar fix");
+    HIPCHK(polar_fix_launch(e.Vw, e.np, np2, e.perm, S, sS, e.sgn, 0, B, n, e.Hw, e.V2, w.y0, w.colsum,
+                            nullptr, c.st), "polar fix");
     GemmArgs vu = gemm_base(n, n, n, B);  // V Mu
     vu.A = V; vu.lda = ldv; vu.sA = sV;
     vu.B = e.Hw; vu.ldb = n; vu.sB = n2;
@@ -961,6 +961,11 @@ svdp_status polar_fwd(svdp_handle* h, const svdp_params* p, const float* A, int6
   Ctx c{h, p, carve_fwd(ws, p, nullptr), (hipStream_t)stream, (int)p->batch, (int)p->m, (int)p->n, A, lda, sA};
   const int B = c.batch, m = c.m, n = c.n;
   if ((s = polar_core(c))) return s;
+  // the BF16 correction (bf16_correct) of W, H and the eigenpairs, when the
+  // eigenpairs are requested: W is then written by the first pass, and only
+  // the fallback reruns copy their iterate at the end
+  const bool correct = V_cache && p->bf16_correct && p->precision == SVDP_PREC_BF16 &&
+                       p->bound != SVDP_BOUND_CONSERVATIVE;
   auto tail = [&](const int* mask) -> svdp_status {
     svdp_status s2 = form_h(c, mask);
     if (s2) return s2;
@@ -968,6 +973,36 @@ svdp_status polar_fwd(svdp_handle* h, const svdp_params* p, const float* A, int6
       EighWs e = eigh_ws_carve(c.w.eigh, B, n, p->max_sweeps);
       HIPCHK(eigh_run(e, c.w.G, n, (int64_t)n * n, 0, eigh_opts(p), S_cache, sS, V_cache, ldv, sV, c.w.sweeps,
                       c.w.flags, h->host_word, mask, &h->aux, c.st), "eigh");
+      if (correct && !mask) {
+        // as in svd_tail, with signed eigenvalues: Mu in Hw, V Mu in V2,
+        // V <- 2 V - V Mu, S corrected; then W <- W (V Mu) V^T (the new V)
+        // and G = W^T A for H = sym(G)
+        const int64_t n2 = (int64_t)n * n, np2 = (int64_t)e.np * e.np;
+        HIPCHK(polar_fix_launch(e.Vw, e.np, np2, e.perm, S_cache, sS, e.sgn, 1, B, n, e.Hw, e.V2, c.w.y0,
+                                c.w.colsum, nullptr, c.st), "polar fix");
+        GemmArgs vu = gemm_base(n, n, n, B);  // V Mu
+        vu.A = V_cache; vu.lda = ldv; vu.sA = sV;
+        vu.B = e.Hw; vu.ldb = n; vu.sB = n2;
+        vu.C = e.V2; vu.ldc = n; vu.sC = n2;
+        HIPCHK(gemm_launch(vu, PREC_F32, 0, 0, c.st), "V Mu");
+        HIPCHK(vcorr_launch(V_cache, ldv, sV, e.V2, B, n, c.st), "V");
+        HIPCHK(sigma_store_launch(c.w.colsum, n, S_cache, sS, B, nullptr, c.st), "eigenvalues");
+        GemmArgs r = gemm_base(n, n, n, B);  // R = (V Mu) V^T
+        r.A = e.V2; r.lda = n; r.sA = n2;
+        r.B = V_cache; r.ldb = ldv; r.sB = sV;
+        r.C = e.Hw; r.ldc = n; r.sC = n2;
+        HIPCHK(gemm_launch(r, PREC_F32, 0, 1, c.st), "R");
+        GemmArgs wc = gemm_base(m, n, n, B);  // W out = W R
+        wc.A = c.w.X0; wc.A_alt = c.w.X1; wc.a_sel = c.w.where; wc.lda = n; wc.sA = (int64_t)m * n;
+        wc.B = e.Hw; wc.ldb = n; wc.sB = n2;
+        wc.C = W; wc.ldc = ldw; wc.sC = sW;
+        HIPCHK(gemm_launch(wc, PREC_F32, 0, 0, c.st), "W R");
+        GemmArgs g = gemm_base(n, n, m, B);  // G = W^T A
+        g.A = W; g.lda = ldw; g.sA = sW;
+        g.B = c.A; g.ldb = c.lda; g.sB = c.sA;
+        g.C = c.w.G; g.ldc = n; g.sC = n2;
+        HIPCHK(gemm_launch(g, PREC_F32, 1, 0, c.st), "W^T A");
+      }
     }
     return SVDP_OK;
   };
@@ -984,7 +1019,8 @@ svdp_status polar_fwd(svdp_handle* h, const svdp_params* p, const float* A, int6
     }
   }
   HIPCHK(symmetrize_launch(c.w.G, B, n, H, ldh, sH, c.st), "H out");
-  HIPCHK(copy_launch(c.w.X0, n, (int64_t)m * n, c.w.where, c.w.X1, W, ldw, sW, B, m, n, c.st), "W out");
+  HIPCHK(copy_launch(c.w.X0, n, (int64_t)m * n, c.w.where, c.w.X1, W, ldw, sW, B, m, n, c.st,
+                     correct ? c.w.mask : nullptr), "W out");
   if (info) HIPCHK(info_pack_launch(B, c.w.iters, c.w.sweeps, c.w.flags, c.w.resid, info, nullptr, c.st), "info");
   return SVDP_OK;
 }

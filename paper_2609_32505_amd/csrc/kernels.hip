@@ -475,8 +475,9 @@ __global__ void k_symmetrize(const float* in, int n, float* out, int64_t ldo, in
 }
 
 __global__ void k_copy(const float* src, int64_t lds, int64_t ss, const int* sel, const float* src_alt,
-                       float* dst, int64_t ldd, int64_t sd, int m, int n) {
+                       float* dst, int64_t ldd, int64_t sd, int m, int n, const int* mask) {
   const int b = blockIdx.y;
+  if (mask && !mask[b]) return;
   const float* s = (sel && sel[b]) ? src_alt : src;
   for (int i = blockIdx.x; i < m; i += gridDim.x)
     for (int j = threadIdx.x; j < n; j += blockDim.x)
@@ -548,24 +549,27 @@ __global__ void k_transpose32(const float* P, int n, float* Pt, const int* mask)
 
 // Mu and snew from P, Pt = P^T and dP = diag(P); one workgroup per row, FP64
 // arithmetic.  Mu may be P itself: each element is read before the same
-// thread overwrites it, and no other row reads it.
+// thread overwrites it, and no other row reads it.  S holds magnitudes with
+// their signs in sgn (lam = sgn S, snew a magnitude), or with signed_lam the
+// signed eigenvalues themselves (lam = S, snew signed).
 __global__ void k_polar_fix(const float* P, const float* Pt, const float* dP, const float* S, int64_t sS,
-                            const float* sgn, int n, float* Mu, float* snew, const int* mask) {
+                            const float* sgn, int signed_lam, int n, float* Mu, float* snew, const int* mask) {
   const int b = blockIdx.y;
   if (mask && !mask[b]) return;
   const int64_t off = (int64_t)b * n * n;
   const float* sb = S + b * sS;
   const float* gb = sgn + (int64_t)b * n;
   const float* db = dP + (int64_t)b * n;
-  const double lmax = fabs((double)sb[0]);
+  const double lmax = signed_lam ? fmax(fabs((double)sb[0]), fabs((double)sb[n - 1])) : fabs((double)sb[0]);
+  auto lam = [&](int i) -> double { return signed_lam ? (double)sb[i] : (double)gb[i] * (double)sb[i]; };
   const double reg = ldexp(lmax, -10) * ldexp(lmax, -10);
   __shared__ double red[2][4];
   for (int i = blockIdx.x; i < n; i += gridDim.x) {
-    const double li = (double)gb[i] * (double)sb[i];
+    const double li = lam(i);
     const double pii = db[i];
     double a1 = 0.0, a2 = 0.0;
     for (int j = threadIdx.x; j < n; j += blockDim.x) {
-      const double lj = (double)gb[j] * (double)sb[j];
+      const double lj = lam(j);
       const double s = li + lj;
       const double den = s * s + reg;
       const double t = den > 0.0 ? s / den : 0.0;  // 0 for an all-zero spectrum
@@ -594,7 +598,8 @@ __global__ void k_polar_fix(const float* P, const float* Pt, const float* dP, co
     if (threadIdx.x == 0) {
       double s1 = 0.0, s2 = 0.0;
       for (int w = 0; w < (int)(blockDim.x >> 6); ++w) { s1 += red[0][w]; s2 += red[1][w]; }
-      snew[(int64_t)b * n + i] = (float)fabs(pii + s1 - 0.25 * s2);
+      const double v = pii + s1 - 0.25 * s2;
+      snew[(int64_t)b * n + i] = (float)(signed_lam ? v : fabs(v));
     }
     __syncthreads();
   }
@@ -1127,16 +1132,16 @@ hipError_t symmetrize_launch(const float* in, int batch, int n, float* out, int6
 }
 
 hipError_t polar_fix_launch(const float* T, int ldt, int64_t sT, const int* perm, const float* S, int64_t sS,
-                            const float* sgn, int batch, int n, float* P, float* Pt, float* dP, float* snew,
-                            const int* mask, hipStream_t st) {
+                            const float* sgn, int signed_lam, int batch, int n, float* P, float* Pt, float* dP,
+                            float* snew, const int* mask, hipStream_t st) {
   hipError_t e;
   hipLaunchKernelGGL(k_polar_gather, dim3(std::min(n, 1024), batch), dim3(256), (size_t)n * sizeof(float), st, T,
                      ldt, sT, perm, n, P, dP, mask);
   if ((e = hipGetLastError())) return e;
   hipLaunchKernelGGL(k_transpose32, dim3(cdiv(n, 32), cdiv(n, 32), batch), dim3(32, 8), 0, st, P, n, Pt, mask);
   if ((e = hipGetLastError())) return e;
-  hipLaunchKernelGGL(k_polar_fix, dim3(std::min(n, 1024), batch), dim3(256), 0, st, P, Pt, dP, S, sS, sgn, n, P,
-                     snew, mask);
+  hipLaunchKernelGGL(k_polar_fix, dim3(std::min(n, 1024), batch), dim3(256), 0, st, P, Pt, dP, S, sS, sgn,
+                     signed_lam, n, P, snew, mask);
   LAUNCH_CHECK();
 }
 
@@ -1152,9 +1157,10 @@ hipError_t sigma_store_launch(const float* snew, int n, float* S, int64_t sS, in
 }
 
 hipError_t copy_launch(const float* src, int64_t lds, int64_t ss, const int* sel, const float* src_alt,
-                       float* dst, int64_t ldd, int64_t sd, int batch, int m, int n, hipStream_t st) {
+                       float* dst, int64_t ldd, int64_t sd, int batch, int m, int n, hipStream_t st,
+                       const int* mask) {
   hipLaunchKernelGGL(k_copy, dim3(std::min(m, 512), batch), dim3(256), 0, st, src, lds, ss, sel,
-                     src_alt, dst, ldd, sd, m, n);
+                     src_alt, dst, ldd, sd, m, n, mask);
   LAUNCH_CHECK();
 }
 

@@ -66,22 +66,24 @@ hipError_t symmetrize_launch(const float* in, int batch, int n, float* out, int6
 // First-order correction of a BF16-rounded polar factor from
 // P = V^T (W^T A) V, gathered as T[perm_i, perm_j] from the eigensolver's
 // last T (working order, leading dimension ldt, batch stride sT), and the
-// eigenpairs (sgn * S, V) of sym(W^T A).  Scratch P, Pt: n x n contiguous per
+// eigenpairs (lam, V) of sym(W^T A): lam = sgn * S (S magnitudes, snew a
+// magnitude) or, with signed_lam, lam = S (snew signed).  Scratch P, Pt: n x n contiguous per
 // matrix; dP: batch x n.  Leaves Mu = I - S~/2 in P (S~_ij = -2 skew(P)_ij /
 // (lam_i + lam_j)) and the corrected singular values in snew (batch x n).
 // U = W V Mu and V (2 I - Mu) replace W V and V.
 hipError_t polar_fix_launch(const float* T, int ldt, int64_t sT, const int* perm, const float* S, int64_t sS,
-                            const float* sgn, int batch, int n, float* P, float* Pt, float* dP, float* snew,
-                            const int* mask, hipStream_t st);
+                            const float* sgn, int signed_lam, int batch, int n, float* P, float* Pt, float* dP,
+                            float* snew, const int* mask, hipStream_t st);
 // V <- 2 V - Vu (Vu contiguous n x n per matrix)
 hipError_t vcorr_launch(float* V, int64_t ldv, int64_t sV, const float* Vu, int batch, int n, hipStream_t st);
 // S = snew, made non-increasing per matrix
 hipError_t sigma_store_launch(const float* snew, int n, float* S, int64_t sS, int batch, const int* mask,
                               hipStream_t st);
-// strided batch copy (m x n)
+// strided batch copy (m x n); matrix b reads src_alt when sel[b], and is
+// skipped when mask is given and mask[b] == 0
 hipError_t copy_launch(const float* src, int64_t lds, int64_t ss, const int* sel,
                        const float* src_alt, float* dst, int64_t ldd, int64_t sd, int batch, int m,
-                       int n, hipStream_t st);
+                       int n, hipStream_t st, const int* mask = nullptr);
 
 // ---- sketch features and the interval predictor ---------------------------
 // y[b] = c A[b] x[b] (trans = 0, length m) or c A[b]^T x[b] (trans = 1, length n),

@@ -262,6 +262,57 @@ def test_backward_learned_bf16_vs_finite_differences(api, handle):
     assert rel < 1e-3
 
 
+def test_polar_learned_bf16_corrected(api, handle):
+    """polar_fwd on the learned BF16 path with the eigenpairs requested (default
+    eigensolver settings): W, H and (S, V) carry the BF16 correction.  W and
+    H against the FP64 oracle's polar factors, beside the uncorrected W of the
+    same path; polar_bwd (epsilon = 0) from the cached eigenpairs against the
+    oracle's Algorithm 2, held to 2x the plain FP32 path's error on the same
+    matrix.  That backward amplifies V's error by 1 / (s_i + s_j): 6.9e-4 on
+    the plain path at this spectrum, 0.2 on the learned path without the
+    correction, 3e-3 with the benchmark's relaxed eigensolver stop."""
+    import torch
+    _say("learned BF16 polar_fwd, 4 x 512^2: corrected W, H against the oracle")
+    A, s = inputs.square_loguniform(seed=6, batch=4, n=512)
+    Ad = torch.from_numpy(A).cuda()
+    probe = torch.from_numpy(inputs.probe(17, 4, 512)).cuda()
+    kw = dict(precision=1, bound=1, probe=probe)
+    W, H, S, V, info = api.polar_fwd(Ad, handle=handle, cache=True, **kw)
+    W0, _, _, _, _ = api.polar_fwd(Ad, handle=handle, cache=True, bf16_correct=0, **kw)
+    torch.cuda.synchronize()
+    inf = api.info_to_numpy(info)
+    assert not np.any(inf["flags"] & (2 | 16 | 32))
+    Wh, Hh, Sh, Vh, W0h = (t.cpu().double().numpy() for t in (W, H, S, V, W0))
+    for i in (0, 3):
+        Uo, So, Vo, _ = oracle.svd(A[i].astype(np.float64))
+        Wo, Ho = oracle.polar_from_svd(Uo, So, Vo)
+        werr = np.abs(Wh[i] - Wo).max()
+        werr0 = np.abs(W0h[i] - Wo).max()
+        herr = np.abs(Hh[i] - Ho).max() / So[0]
+        rec = np.abs((Vh[i] * Sh[i]) @ Vh[i].T - Hh[i]).max() / So[0]
+        _say(f"  matrix {i}: W err {werr:.2e} (uncorrected {werr0:.2e}), H err {herr:.2e}, "
+             f"|V S V^T - H| {rec:.2e}")
+        assert werr < 0.1 * werr0 and werr < 2e-4
+        assert herr < 1e-5 and rec < 1e-5
+    # the polar backward from the cached (corrected) eigenpairs against
+    # Algorithm 2 in FP64 on the oracle's H
+    rng = inputs.rng_for(18, 0)
+    dW = rng.standard_normal((4, 512, 512)).astype(np.float32)
+    dH = rng.standard_normal((4, 512, 512)).astype(np.float32)
+    _, _, Sp, Vp, _ = api.polar_fwd(Ad, handle=handle, cache=True)
+    dWd, dHd = torch.from_numpy(dW).cuda(), torch.from_numpy(dH).cuda()
+    dA = api.polar_bwd(Ad, None, S, V, dWd, dHd, handle=handle).cpu().double().numpy()
+    dAp = api.polar_bwd(Ad, None, Sp, Vp, dWd, dHd, handle=handle).cpu().double().numpy()
+    for i in (0,):
+        Uo, So, Vo, _ = oracle.svd(A[i].astype(np.float64))
+        Ho = oracle.polar_from_svd(Uo, So, Vo)[1]
+        ref = oracle.polar_bwd(A[i], Ho, dW[i], dH[i], 0.0, 0.0)
+        rel = np.linalg.norm(dA[i] - ref) / np.linalg.norm(ref)
+        relp = np.linalg.norm(dAp[i] - ref) / np.linalg.norm(ref)
+        _say(f"  polar_bwd from the cached eigenpairs, matrix {i}: relative error {rel:.2e} (plain FP32 {relp:.2e})")
+        assert rel < 2 * relp
+
+
 def test_learned_predictor_gain_2048(api, handle):
     """What the trained network gains: on 32 matrices of 2048^2 from the three
     training families, the learned BF16 path takes fewer CANS steps than the
