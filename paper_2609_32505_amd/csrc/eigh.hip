@@ -14,10 +14,11 @@
 // and V are read and written once per two steps.
 //   * k_jac_solve: one workgroup (two wavefronts) per group holds H[G, G] in
 //     LDS.  Step A: wave w owns pair w, a 32 x 32 subproblem, and runs scalar
-//     Jacobi rounds on it (16 disjoint rotations per round, rotation
-//     accumulation in FP64); wave 0 then rotates the block between the two
-//     pairs with MFMA.  Step B likewise on the other pairing.  It writes
-//     H[G, G] and M_G = J_A J_B.
+//     Jacobi rounds on it (16 disjoint rotations per round, the step's
+//     rotation accumulated in registers in the solve's precision: FP32 in
+//     the main sweeps, FP64 in the final sweep); wave 0 then rotates the
+//     block between the two pairs with MFMA.  Step B likewise on the other
+//     pairing.  It writes H[G, G] and M_G = J_A J_B.
 //   * k_jac_apply: H[G1, G2] <- M_G1^T H[G1, G2] M_G2 for every pair of
 //     groups and V[slab, G] <- V[slab, G] M_G for every 64-row slab of V, each
 //     a 64 x 64 x 64 product pair on FP32 MFMA (32x32x2).

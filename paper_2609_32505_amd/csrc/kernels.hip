@@ -547,11 +547,18 @@ __global__ void k_transpose32(const float* P, int n, float* Pt, const int* mask)
   }
 }
 
-// Mu and snew from P, Pt = P^T and dP = diag(P); one workgroup per row, FP64
-// arithmetic.  Mu may be P itself: each element is read before the same
-// thread overwrites it, and no other row reads it.  S holds magnitudes with
-// their signs in sgn (lam = sgn S, snew a magnitude), or with signed_lam the
-// signed eigenvalues themselves (lam = S, snew signed).
+// Mu and snew from P, Pt = P^T and dP = diag(P); one workgroup per row, FP32
+// arithmetic on values scaled by 1 / lam_max (so that e^2 and the
+// regularisation stay far from the FP32 range limits at any scale of A).
+// Every term is formed from differences and products of FP32 inputs whose
+// rounding (about 2^-24 lam_max) is already below what the correction
+// resolves; the row sums only add second-order terms to P_ii.  Mu may be P
+// itself: each element is read before the same thread overwrites it, and no
+// other row reads it.  S holds magnitudes with their signs in sgn (lam =
+// sgn S, snew a magnitude), or with signed_lam the signed eigenvalues
+// themselves (lam = S, snew signed).  An exactly tied pair (d = 0) takes the
+// 2 x 2 eigenvalues a + |e| and a - |e| in index order, the smaller index
+// the larger value, as the descending sort would.
 __global__ void k_polar_fix(const float* P, const float* Pt, const float* dP, const float* S, int64_t sS,
                             const float* sgn, int signed_lam, int n, float* Mu, float* snew, const int* mask) {
   const int b = blockIdx.y;
@@ -560,31 +567,33 @@ __global__ void k_polar_fix(const float* P, const float* Pt, const float* dP, co
   const float* sb = S + b * sS;
   const float* gb = sgn + (int64_t)b * n;
   const float* db = dP + (int64_t)b * n;
-  const double lmax = signed_lam ? fmax(fabs((double)sb[0]), fabs((double)sb[n - 1])) : fabs((double)sb[0]);
-  auto lam = [&](int i) -> double { return signed_lam ? (double)sb[i] : (double)gb[i] * (double)sb[i]; };
-  const double reg = ldexp(lmax, -10) * ldexp(lmax, -10);
-  __shared__ double red[2][4];
+  const float lmax = signed_lam ? fmaxf(fabsf(sb[0]), fabsf(sb[n - 1])) : fabsf(sb[0]);
+  // all-zero spectrum: nothing to correct (t = 0, e = 0)
+  const float inv = lmax > 0.f ? 1.f / lmax : 0.f;
+  auto lam = [&](int i) -> float { return (signed_lam ? sb[i] : gb[i] * sb[i]) * inv; };
+  const float reg = 0x1p-20f;  // (2^-10 lam_max)^2 in units of lam_max
+  __shared__ float red[2][4];
   for (int i = blockIdx.x; i < n; i += gridDim.x) {
-    const double li = lam(i);
-    const double pii = db[i];
-    double a1 = 0.0, a2 = 0.0;
+    const float li = lam(i);
+    const float pii = db[i] * inv;
+    float a1 = 0.f, a2 = 0.f;
     for (int j = threadIdx.x; j < n; j += blockDim.x) {
-      const double lj = lam(j);
-      const double s = li + lj;
-      const double den = s * s + reg;
-      const double t = den > 0.0 ? s / den : 0.0;  // 0 for an all-zero spectrum
-      const double pij = P[off + (int64_t)i * n + j], pji = Pt[off + (int64_t)i * n + j];
-      const double sk = 0.5 * (pij - pji);
-      const double st = -2.0 * sk * t;
-      a1 += 2.0 * sk * sk * t;
+      const float lj = lam(j);
+      const float s = li + lj;
+      const float t = s / (s * s + reg);
+      const float pij = P[off + (int64_t)i * n + j] * inv, pji = Pt[off + (int64_t)i * n + j] * inv;
+      const float sk = 0.5f * (pij - pji);
+      const float st = -2.f * sk * t;
+      a1 += 2.f * sk * sk * t;
       a2 += st * st * lj;
       if (j != i) {
-        const double e = 0.5 * (pij + pji);
-        const double dd = pii - (double)db[j];
-        const double hh = sqrt(0.25 * dd * dd + e * e) + 0.5 * fabs(dd);
-        if (hh > 0.0) a1 += (dd >= 0.0 ? 1.0 : -1.0) * e * e / hh;
+        const float e = 0.5f * (pij + pji);
+        const float dd = pii - db[j] * inv;
+        const float hh = sqrtf(0.25f * dd * dd + e * e) + 0.5f * fabsf(dd);
+        const float sgn_d = dd > 0.f ? 1.f : (dd < 0.f ? -1.f : (i < j ? 1.f : -1.f));
+        if (hh > 0.f) a1 += sgn_d * e * e / hh;
       }
-      Mu[off + (int64_t)i * n + j] = (float)((i == j ? 1.0 : 0.0) - 0.5 * st);
+      Mu[off + (int64_t)i * n + j] = (i == j ? 1.f : 0.f) - 0.5f * st;
     }
     for (int o = 32; o > 0; o >>= 1) {
       a1 += __shfl_xor(a1, o);
@@ -596,10 +605,10 @@ __global__ void k_polar_fix(const float* P, const float* Pt, const float* dP, co
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-      double s1 = 0.0, s2 = 0.0;
+      float s1 = 0.f, s2 = 0.f;
       for (int w = 0; w < (int)(blockDim.x >> 6); ++w) { s1 += red[0][w]; s2 += red[1][w]; }
-      const double v = pii + s1 - 0.25 * s2;
-      snew[(int64_t)b * n + i] = (float)(signed_lam ? v : fabs(v));
+      const float v = (pii + (s1 - 0.25f * s2)) * lmax;
+      snew[(int64_t)b * n + i] = signed_lam ? v : fabsf(v);
     }
     __syncthreads();
   }
