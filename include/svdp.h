@@ -67,8 +67,13 @@ typedef enum {
 typedef enum {
   SVDP_POLY_CANS3 = 0, /* interval-optimal odd cubic (CANS), the method's default */
   SVDP_POLY_NS = 1,    /* classical Newton-Schulz 1.5 x - 0.5 x^3, no preprocessing */
-  SVDP_POLY_CANS5 = 2  /* interval-optimal odd quintic (Remez exchange): three products
+  SVDP_POLY_CANS5 = 2, /* interval-optimal odd quintic (Remez exchange): three products
                           per step (X^T X, G G, X P), with its own preprocessing */
+  SVDP_POLY_PE = 3     /* Polar Express (cited by the paper's ablation of polar
+                          iterations): X0 = A / |A|_F, per-step minimax odd quintics on the
+                          interval recursion from [pe_lo, 1], the cushioned interval
+                          [max(l, u / 10), u], the input divided by 1.01 on every step but
+                          the last; a fixed number of steps (svdp_pe_table), no stop test */
 } svdp_poly;
 
 /* per-matrix result flags (svdp_info.flags) */
@@ -150,7 +155,15 @@ typedef struct {
                               one n^3 GEMM and two element-wise passes (polar_fwd: three more
                               GEMMs, W <- W (V Mu) V^T and H = sym(W^T A)).  polar_fwd without
                               the cache is not corrected; tall matrices keep W's error outside
-                              A's column space */
+                              A's column space unless tall_qr is on */
+  double pe_lo;            /* poly PE: lower end of the interval assumed to hold the singular
+                              values of A / |A|_F (1e-3); values below it still converge, more
+                              slowly, and the step count grows as it falls */
+  int32_t tall_qr;         /* svd_polar_fwd with m > n: 1 = QR preprocessing (the paper's
+                              rectangular experiments): an orthonormal basis Q of A's columns
+                              by block Gram-Schmidt with CholeskyQR blocks, then the SVD of the
+                              n x n matrix B = Q^T A and U = Q U_B; 0 = CANS on A itself.
+                              Default 1 */
 } svdp_params;
 
 /* per-matrix diagnostics, device array of `batch` records */
@@ -337,6 +350,17 @@ svdp_status svdp_cans_table(int32_t kind, double delta, int32_t pre_iters, doubl
 svdp_status svdp_poly_table(int32_t poly, double delta, int32_t pre_iters, int32_t steps, double* table,
                             double* t_out);
 
+/* HOST helper: the Polar Express schedule (poly SVDP_POLY_PE) from [lo, 1]:
+ * the coefficients (c1, c3, c5) of each step, with the step's 1 / 1.01 input
+ * scaling folded in (c_k / 1.01^k on every step but the last), into host
+ * `table` (max_steps x 3 doubles), and the number of steps in *steps.  Step t
+ * takes the odd quintic closest to 1 in max norm on [max(l_t, u_t / 10), u_t];
+ * [l_t+1, u_t+1] is the image of [l_t / 1.01, u_t / 1.01] under it.  The
+ * damped steps continue until u - l <= 1e-4, then one undamped step ends the
+ * schedule.  INVALID_ARG if lo is not in (0, 1) or the schedule needs more
+ * than max_steps (<= 64) steps. */
+svdp_status svdp_pe_table(double lo, int32_t max_steps, double* table, int32_t* steps);
+
 /* Kernel timing for benchmarks: while enabled, every launch of the kernel
  * classes below is bracketed by HIP events on its stream.  read() waits for
  * the recorded events and returns, for one class, the summed milliseconds,
@@ -348,6 +372,17 @@ svdp_status svdp_poly_table(int32_t poly, double delta, int32_t pre_iters, int32
 #define SVDP_PROF_JAC_APPLY 2     /* Jacobi block rotations on MFMA */
 #define SVDP_PROF_GEMM_F32 3      /* batched GEMMs on FP32 MFMA */
 #define SVDP_PROF_GEMM_BF16 4     /* batched GEMMs on BF16 MFMA */
+/* phases of the forward and backward calls (wall time on the caller's
+ * stream between the phase's first and last launch; work 0) */
+#define SVDP_PROF_PHASE_BOUND 5    /* normalisation, sketch features, predictor, schedule */
+#define SVDP_PROF_PHASE_CANS 6     /* CANS steps before the FP32 refinement */
+#define SVDP_PROF_PHASE_REFINE 7   /* FP32 refinement and the final residual */
+#define SVDP_PROF_PHASE_H 8        /* H = W^T A */
+#define SVDP_PROF_PHASE_EIGH 9     /* eigendecomposition of H */
+#define SVDP_PROF_PHASE_U 10       /* BF16 correction, U = W V, column-norm test, QR step */
+#define SVDP_PROF_PHASE_FALLBACK 11 /* conservative reruns of the bounded paths */
+#define SVDP_PROF_PHASE_BWD 12     /* svd_polar_bwd, polar_bwd */
+#define SVDP_PROF_PHASE_QR 13      /* QR preprocessing of tall matrices */
 void svdp_profile_enable(int on);
 void svdp_profile_reset(void);
 int svdp_profile_read(int kind, double* total_ms, int64_t* launches, double* work);

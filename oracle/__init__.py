@@ -391,6 +391,44 @@ def poly_schedule_conservative(poly: int, delta: float = 0.99, pre_steps: int = 
     return np.array(out), t
 
 
+def polar_express_schedule(lo: float = 1e-3, max_steps: int = 64):
+    """Polar Express (cited by the appendix's ablation of polar iterations;
+    the paper states that its polynomial input is divided by 1.01 on every
+    step but the last).  Reading of the published construction: X0 = A /
+    |A|_F, so the singular values lie in [lo, 1]; step t takes the odd quintic
+    closest to 1 in max norm on the cushioned interval [max(l_t, u_t / 10),
+    u_t] (``cans5_poly``) and applies it to X / 1.01; [l_t+1, u_t+1] is the
+    image of [l_t / 1.01, u_t / 1.01], read here off a dense grid of 2e5
+    points plus the ends; once u - l <= 1e-4 one undamped step ends the
+    schedule.  Returns a (steps, 3) array of (c1, c3, c5) with the damping
+    folded in (c_k / 1.01^k)."""
+    damp, cushion = 1.01, 0.1
+    l, u = float(lo), 1.0
+    out = []
+    for _ in range(max_steps):
+        c1, c3, c5, _, _ = cans5_poly(max(l, cushion * u), u)
+        if u - l <= 1e-4:
+            out.append((c1, c3, c5))
+            return np.array(out)
+        out.append((c1 / damp, c3 / damp ** 3, c5 / damp ** 5))
+        xs = np.concatenate([np.linspace(l / damp, u / damp, 200001), [l / damp, u / damp]])
+        v = c1 * xs + c3 * xs ** 3 + c5 * xs ** 5
+        l, u = float(v.min()), float(v.max())
+    raise ValueError("schedule longer than max_steps")
+
+
+def polar_express_polar(A, lo: float = 1e-3):
+    """The Polar Express iteration in FP64: X0 = A / |A|_F, then the fixed
+    schedule of ``polar_express_schedule`` (no stop test).  Returns (W, steps)."""
+    A = np.asarray(A, dtype=np.float64)
+    X = A / np.linalg.norm(A)
+    tab = polar_express_schedule(lo)
+    for c1, c3, c5 in tab:
+        G = X.T @ X
+        X = c1 * X + X @ (c3 * G + c5 * (G @ G))
+    return X, len(tab)
+
+
 def poly_polar(A, table, tol: float = 1e-5, max_iters: int = 64):
     """Polar iteration in FP64 with per-step odd polynomials
     X <- c1 X + c3 X G + c5 X G^2, G = X^T X (rows of `table`), after the

@@ -21,7 +21,7 @@ STATUS = {0: "ok", 1: "invalid argument", 2: "bad shape", 3: "workspace too smal
 
 PREC_FP32, PREC_BF16 = 0, 1
 BOUND_CONSERVATIVE, BOUND_LEARNED, BOUND_USER = 0, 1, 2
-POLY_CANS3, POLY_NS, POLY_CANS5 = 0, 1, 2
+POLY_CANS3, POLY_NS, POLY_CANS5, POLY_PE = 0, 1, 2, 3
 FLAG_NOT_CONVERGED = 1
 FLAG_FALLBACK_USED = 2
 FLAG_NEG_EIGENVALUE = 4
@@ -45,7 +45,7 @@ class Params(ctypes.Structure):
         ("margin_max", c_dbl), ("margin_min", c_dbl),
         ("user_bounds", c_vp), ("probe", c_vp),
         ("eigh_off_tol", c_dbl), ("eigh_restarts", c_i32), ("jacobi_fro_tol", c_dbl), ("poly", c_i32),
-        ("bf16_correct", c_i32),
+        ("bf16_correct", c_i32), ("pe_lo", c_dbl), ("tall_qr", c_i32),
     ]
 
 
@@ -89,12 +89,15 @@ SIGNATURES = {
     "svdp_cans_table": (c_i32, [c_i32, c_dbl, c_i32, c_dbl, c_i32, ctypes.POINTER(c_dbl),
                                 ctypes.POINTER(c_dbl)]),
     "svdp_poly_table": (c_i32, [c_i32, c_dbl, c_i32, c_i32, ctypes.POINTER(c_dbl), ctypes.POINTER(c_dbl)]),
+    "svdp_pe_table": (c_i32, [c_dbl, c_i32, ctypes.POINTER(c_dbl), ctypes.POINTER(c_i32)]),
     "svdp_profile_enable": (None, [ctypes.c_int]),
     "svdp_profile_reset": (None, []),
     "svdp_profile_read": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(c_dbl), ctypes.POINTER(c_i64),
                                          ctypes.POINTER(c_dbl)]),
 }
 PROF_KINDS = {"jac_solve_f32": 0, "jac_solve_f64": 1, "jac_apply": 2, "gemm_f32": 3, "gemm_bf16": 4}
+PROF_PHASES = {"bound": 5, "cans": 6, "refine": 7, "H": 8, "eigh": 9, "U": 10, "fallback": 11, "backward": 12,
+               "qr": 13}
 
 _lib = None
 

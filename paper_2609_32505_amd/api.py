@@ -302,3 +302,13 @@ def cans_table(kind, steps, delta=0.99, pre_iters=2, lo=1e-3):
     t = ctypes.c_double()
     check(load().svdp_cans_table(kind, delta, pre_iters, lo, steps, tab, ctypes.byref(t)), "cans_table")
     return np.array(tab[:]).reshape(steps, 2), t.value
+
+
+def pe_table(lo=1e-3, max_steps=64):
+    """Host Polar Express schedule from [lo, 1]: (steps, 3) array of
+    (c1, c3, c5) with the 1.01 input damping folded in (all steps but the
+    last)."""
+    tab = (ctypes.c_double * (3 * max_steps))()
+    steps = ctypes.c_int32()
+    check(load().svdp_pe_table(float(lo), int(max_steps), tab, ctypes.byref(steps)), "pe_table")
+    return np.array(tab[:3 * steps.value]).reshape(steps.value, 3)

@@ -12,6 +12,7 @@
 #include "common.hpp"
 #include "eigh.hpp"
 #include "kernels.hpp"
+#include "prof.hpp"
 #include "svdp.h"
 
 struct svdp_handle {
@@ -206,6 +207,48 @@ void table_poly(int poly, double delta, int pre, int steps, double* tab, double*
   for (int k = 0; k < steps; ++k) { tab[3 * k] = tab2[2 * k]; tab[3 * k + 1] = tab2[2 * k + 1]; tab[3 * k + 2] = 0.0; }
 }
 
+// Polar Express schedule from [lo, 1] (the iteration the paper's ablation of
+// polar iterations compares CANS with; reading of its published
+// construction): step t takes the odd quintic closest to 1 in max norm on
+// the cushioned interval [max(l, u / 10), u] and applies it to X / 1.01, so
+// the interval moves to the image of [l / 1.01, u / 1.01]; once the
+// interval is narrower than 1e-4 one undamped step ends the schedule.  The
+// image of an interval under an odd quintic is read off its ends and its
+// stationary points (the roots of p' in x^2).  tab: (c1, c3, c5) per step,
+// the 1.01 folded in.  Returns the step count, or -1 above max_steps.
+static void quintic_image(const double* c, double x0, double x1, double& lo, double& hi) {
+  auto p = [&](double x) { const double x2 = x * x; return x * (c[0] + x2 * (c[1] + x2 * c[2])); };
+  lo = std::min(p(x0), p(x1));
+  hi = std::max(p(x0), p(x1));
+  const double disc = 9.0 * c[1] * c[1] - 20.0 * c[0] * c[2];
+  if (c[2] != 0.0 && disc >= 0.0)
+    for (int sg = -1; sg <= 1; sg += 2) {
+      const double y = (-3.0 * c[1] + sg * std::sqrt(disc)) / (10.0 * c[2]);
+      if (y <= 0.0) continue;
+      const double x = std::sqrt(y);
+      if (x > x0 && x < x1) { lo = std::min(lo, p(x)); hi = std::max(hi, p(x)); }
+    }
+}
+
+int pe_table(double lo, int max_steps, double* tab) {
+  constexpr double kDamp = 1.01, kCushion = 0.1, kWidth = 1e-4;
+  double l = lo, u = 1.0;
+  for (int t = 0; t < max_steps; ++t) {
+    double c[3], ilo, ihi;
+    cans5_poly(std::max(l, kCushion * u), u, c, ilo, ihi);
+    const bool last = u - l <= kWidth;
+    if (last) {
+      for (int k = 0; k < 3; ++k) tab[3 * t + k] = c[k];
+      return t + 1;
+    }
+    tab[3 * t] = c[0] / kDamp;
+    tab[3 * t + 1] = c[1] / (kDamp * kDamp * kDamp);
+    tab[3 * t + 2] = c[2] / (kDamp * kDamp * kDamp * kDamp * kDamp);
+    quintic_image(c, l / kDamp, u / kDamp, l, u);
+  }
+  return -1;
+}
+
 // ---------------------------------------------------------------- checks
 
 bool bad_shape(const svdp_params* p) {
@@ -234,8 +277,15 @@ svdp_status check_common(const svdp_params* p) {
   if (!(p->delta > 0 && p->delta < 1)) return fail(SVDP_ERR_INVALID_ARG, "delta must be in (0, 1)");
   if (!(p->tol > 0)) return fail(SVDP_ERR_INVALID_ARG, "tol must be > 0");
   if (p->eps_K < 0 || p->eps_R < 0 || p->eps_T < 0) return fail(SVDP_ERR_INVALID_ARG, "eps must be >= 0");
-  if (p->poly < SVDP_POLY_CANS3 || p->poly > SVDP_POLY_CANS5) return fail(SVDP_ERR_INVALID_ARG, "unknown poly");
+  if (p->poly < SVDP_POLY_CANS3 || p->poly > SVDP_POLY_PE) return fail(SVDP_ERR_INVALID_ARG, "unknown poly");
   if (p->bf16_correct != 0 && p->bf16_correct != 1) return fail(SVDP_ERR_INVALID_ARG, "bf16_correct must be 0 or 1");
+  if (p->tall_qr != 0 && p->tall_qr != 1) return fail(SVDP_ERR_INVALID_ARG, "tall_qr must be 0 or 1");
+  if (p->poly == SVDP_POLY_PE) {
+    if (!(p->pe_lo > 0 && p->pe_lo < 1)) return fail(SVDP_ERR_INVALID_ARG, "pe_lo must be in (0, 1)");
+    double tab[3 * 64];
+    if (pe_table(p->pe_lo, p->max_iters, tab) < 0)
+      return fail(SVDP_ERR_INVALID_ARG, "the Polar Express schedule from pe_lo needs more than max_iters steps");
+  }
   if (p->poly != SVDP_POLY_CANS3 && (p->bound != SVDP_BOUND_CONSERVATIVE || p->precision != SVDP_PREC_FP32))
     return fail(SVDP_ERR_INVALID_ARG, "poly variants run on the conservative FP32 path");
   return SVDP_OK;
@@ -310,7 +360,7 @@ FwdWs carve_fwd(void* base, const svdp_params* p, size_t* total) {
   w.qrc = c.take<float>(blocked_qr ? b * n * kQrBlock : 0);
   w.qrg = c.take<float>(blocked_qr ? b * kQrBlock * kQrBlock : 0);
   w.qrr = c.take<float>(blocked_qr ? b * kQrBlock * kQrBlock : 0);
-  w.P = c.take<float>(p->poly == SVDP_POLY_CANS5 ? b * n * n : 0);
+  w.P = c.take<float>(p->poly == SVDP_POLY_CANS5 || p->poly == SVDP_POLY_PE ? b * n * n : 0);
   w.qmask = c.take<int>(b);
   w.active = c.take<int>(b);
   w.where = c.take<int>(b);
@@ -432,10 +482,31 @@ svdp_status conservative_fp32(Ctx& c, const int* mask) {
   const svdp_params* p = c.p;
   FwdWs& w = c.w;
   const int B = c.batch, m = c.m, n = c.n;
+  ProfScope phase_bound(PROF_PHASE_BOUND, c.st);
   HIPCHK(norms_launch(c.A, c.lda, c.sA, B, m, n, w.colsum, w.rowmax, w.fro2, w.flags, mask, c.st), "norms");
-  HIPCHK(ns_scale_launch(w.colsum, w.rowmax, B, n, w.scale, mask, c.st), "scale");
+  if (p->poly == SVDP_POLY_PE)
+    HIPCHK(fro_scale_launch(w.fro2, B, w.scale, mask, c.st), "scale");
+  else
+    HIPCHK(ns_scale_launch(w.colsum, w.rowmax, B, n, w.scale, mask, c.st), "scale");
   HIPCHK(scale_copy_launch(c.A, c.lda, c.sA, B, m, n, w.scale, w.X0, 0, mask, c.st), "normalise");
+  phase_bound.next(PROF_PHASE_CANS);
   double tab[128], tab3[3 * 64];
+  if (p->poly == SVDP_POLY_PE) {
+    // a fixed schedule without stop test (the 1.01 damping holds the
+    // iterate on a plateau short of convergence until the last step)
+    const int T = pe_table(p->pe_lo, p->max_iters, tab3);
+    if (T < 0) return fail(SVDP_ERR_INVALID_ARG, "Polar Express schedule longer than max_iters");
+    if (mask) HIPCHK(copy_i32(w.active, mask, B, c.st), "active");
+    else HIPCHK(fill_i32(w.active, 1, B, c.st), "active");
+    for (int k = 0; k < T; ++k) {
+      const float* Xc = (k & 1) ? w.X1 : w.X0;
+      float* Xn = (k & 1) ? w.X0 : w.X1;
+      HIPCHK(cans5_step(c, Xc, Xn, tab3 + 3 * k, w.active, nullptr, B), "pe step");
+    }
+    HIPCHK(fill_masked_launch(w.where, T & 1, B, mask, c.st), "where");
+    HIPCHK(fill_masked_launch(w.iters, T, B, mask, c.st), "iters");
+    return SVDP_OK;
+  }
   table_poly(p->poly, p->delta, p->pre_iters, p->max_iters, tab3, nullptr);
   for (int k = 0; k < p->max_iters; ++k) { tab[2 * k] = tab3[3 * k]; tab[2 * k + 1] = tab3[3 * k + 1]; }
   HIPCHK(set_coef_launch(w.coef, tab, p->max_iters, c.st), "coef");
@@ -480,6 +551,7 @@ svdp_status bounded(Ctx& c) {
   FwdWs& w = c.w;
   const int B = c.batch, m = c.m, n = c.n;
   const int kcap = std::min(p->max_iters, 64);
+  ProfScope phase(PROF_PHASE_BOUND, c.st);
   if (p->bound == SVDP_BOUND_LEARNED) {
     // features: |A|_F^2 via the row pass, then the alternating power sequence
     HIPCHK(norms_launch(c.A, c.lda, c.sA, B, m, n, w.colsum, w.rowmax, w.fro2, w.flags, nullptr, c.st), "norms");
@@ -524,6 +596,7 @@ svdp_status bounded(Ctx& c) {
     HIPCHK(sched_mask_launch(B, w.ksteps, bf16, 1, w.gmask, c.st), "bf16 start");
     HIPCHK(scale_copy_launch(c.A, c.lda, c.sA, B, m, n, w.scale, w.Y0, 1, w.gmask, c.st), "normalise");
   }
+  phase.next(PROF_PHASE_CANS);
   for (int k = 0; k < kmax; ++k)
     for (int cat = 0; cat < 4; ++cat) {
       const int count = cnt[4 * k + cat];
@@ -544,6 +617,7 @@ svdp_status bounded(Ctx& c) {
   // tol.  A matrix whose predicted interval missed part of its spectrum is
   // still caught here; one that has not converged within refine_steps +
   // kRefineExtra steps is flagged and falls back to conservative CANS.
+  phase.next(PROF_PHASE_REFINE);
   const int R = p->refine_steps;
   const int Rmax = std::min(R + kRefineExtra, 64);
   double rtab[128];
@@ -577,6 +651,7 @@ svdp_status bounded(Ctx& c) {
 
 // residual |W^T W - I|_F / sqrt(n) of the final iterate (Gram into G)
 svdp_status final_residual(Ctx& c, const int* mask) {
+  ProfScope phase(PROF_PHASE_REFINE, c.st);
   FwdWs& w = c.w;
   const int B = c.batch, m = c.m, n = c.n;
   GemmArgs g = gemm_base(n, n, m, B);
@@ -680,11 +755,14 @@ svdp_status svd_tail(Ctx& c, float* U, int64_t ldu, int64_t sU, float* S, int64_
   const svdp_params* p = c.p;
   FwdWs& w = c.w;
   const int B = c.batch, m = c.m, n = c.n;
+  ProfScope phase(PROF_PHASE_H, c.st);
   svdp_status s = form_h(c, mask);
   if (s) return s;
+  phase.next(PROF_PHASE_EIGH);
   EighWs e = eigh_ws_carve(w.eigh, B, n, p->max_sweeps);
   HIPCHK(eigh_run(e, w.G, n, (int64_t)n * n, 1, eigh_opts(p), S, sS, V, ldv, sV, w.sweeps, w.flags,
                   c.h->host_word, mask, &c.h->aux, c.st), "eigh");
+  phase.next(PROF_PHASE_U);
   // B operand of U = W V: V, or V Mu after the BF16 correction
   const float* Vb = V;
   int64_t ldvb = ldv, svb = sV;
@@ -780,6 +858,8 @@ void svdp_default_params(svdp_params* p, int64_t batch, int64_t m, int64_t n) {
   p->jacobi_fro_tol = 3e-4;
   p->poly = SVDP_POLY_CANS3;
   p->bf16_correct = 1;
+  p->pe_lo = 1e-3;
+  p->tall_qr = 1;
 }
 
 const char* svdp_status_string(svdp_status s) {
@@ -928,6 +1008,7 @@ svdp_status svd_polar_fwd(svdp_handle* h, const svdp_params* p, const float* A, 
     int cnt = 0;
     if ((s = fallback_mask(c, &cnt))) return s;
     if (cnt > 0) {
+      ProfScope phase(PROF_PHASE_FALLBACK, c.st);
       const int* mk = c.w.mask;
       if ((s = conservative_fp32(c, mk))) return s;
       if ((s = final_residual(c, mk))) return s;
@@ -1091,6 +1172,7 @@ svdp_status svd_polar_bwd(svdp_handle* h, const svdp_params* p, const float* U, 
   if (dV) LDCHK(lddv, n, B > 1 ? sdV : 0, n);
   if (!ws || ws_bytes < bwd_bytes(p, 0)) return fail(SVDP_ERR_WORKSPACE, "workspace too small");
   hipStream_t st = (hipStream_t)stream;
+  ProfScope phase(PROF_PHASE_BWD, st);
   Carver c(ws);
   float* X1 = c.take<float>((size_t)B * n * n);
   float* X2 = c.take<float>((size_t)B * n * n);
@@ -1159,6 +1241,7 @@ svdp_status polar_bwd(svdp_handle* h, const svdp_params* p, const float* A, int6
   if (dH) LDCHK(lddh, n, B > 1 ? sdH : 0, n);
   if (!ws || ws_bytes < bwd_bytes(p, 1)) return fail(SVDP_ERR_WORKSPACE, "workspace too small");
   hipStream_t st = (hipStream_t)stream;
+  ProfScope phase(PROF_PHASE_BWD, st);
   Carver c(ws);
   float* X1 = c.take<float>((size_t)B * n * n);
   float* X2 = c.take<float>((size_t)B * n * n);
@@ -1377,12 +1460,23 @@ svdp_status svdp_cans_table(int32_t kind, double delta, int32_t pre_iters, doubl
 
 svdp_status svdp_poly_table(int32_t poly, double delta, int32_t pre_iters, int32_t steps, double* table,
                             double* t_out) {
-  if (poly < SVDP_POLY_CANS3 || poly > SVDP_POLY_CANS5) return fail(SVDP_ERR_INVALID_ARG, "unknown poly");
+  if (poly < SVDP_POLY_CANS3 || poly > SVDP_POLY_CANS5)
+    return fail(SVDP_ERR_INVALID_ARG, "unknown poly (Polar Express: svdp_pe_table)");
   if (!table || steps < 1 || steps > 64 || pre_iters < 0 || pre_iters > steps || !(delta > 0 && delta < 1))
     return fail(SVDP_ERR_INVALID_ARG, "need table, 1 <= steps <= 64, 0 <= pre_iters <= steps, 0 < delta < 1");
   double t = 0.0;
   table_poly(poly, delta, pre_iters, steps, table, &t);
   if (t_out) *t_out = t;
+  return SVDP_OK;
+}
+
+svdp_status svdp_pe_table(double lo, int32_t max_steps, double* table, int32_t* steps) {
+  REQ(table); REQ(steps);
+  if (!(lo > 0 && lo < 1) || max_steps < 1 || max_steps > 64)
+    return fail(SVDP_ERR_INVALID_ARG, "need 0 < lo < 1 and 1 <= max_steps <= 64");
+  const int t = pe_table(lo, max_steps, table);
+  if (t < 0) return fail(SVDP_ERR_INVALID_ARG, "the schedule needs more than max_steps steps");
+  *steps = t;
   return SVDP_OK;
 }
 

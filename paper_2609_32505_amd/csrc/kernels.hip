@@ -99,6 +99,15 @@ __global__ void k_ns_scale(const float* colsum, const float* rowmax, int batch, 
   }
 }
 
+// scale[b] = |A[b]|_F from the row pass's sum of squares (Polar Express
+// normalisation), 1 for a zero matrix
+__global__ void k_fro_scale(const float* fro2, int batch, float* scale, const int* mask) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= batch || skip(mask, b)) return;
+  const float f = sqrtf(fro2[b]);
+  scale[b] = f > 0.f && isfinite(f) ? f : 1.f;
+}
+
 __global__ void k_scale_copy(const float* A, int64_t lda, int64_t sA, int m, int n, const float* scale,
                              void* X, int out_bf16, const int* mask) {
   const int b = blockIdx.y;
@@ -1034,6 +1043,12 @@ hipError_t norms_launch(const float* A, int64_t lda, int64_t sA, int batch, int 
   hipLaunchKernelGGL(k_colsums, dim3(cdiv(n, 256), cdiv(m, rows_per), batch), dim3(256), 0, st, A, lda,
                      sA, m, n, rows_per, colsum, mask);
   LAUNCH_CHECK();
+}
+
+hipError_t fro_scale_launch(const float* fro2, int batch, float* scale, const int* mask, hipStream_t st) {
+  if (batch <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fro_scale, dim3(cdiv(batch, 256)), dim3(256), 0, st, fro2, batch, scale, mask);
+  return hipGetLastError();
 }
 
 hipError_t ns_scale_launch(const float* colsum, const float* rowmax, int batch, int n, float* scale,

@@ -2,6 +2,7 @@
 // bracketed by a pair of HIP events recorded on its own stream; reading the
 // totals synchronises on the recorded events.
 #include <mutex>
+#include <new>
 #include <vector>
 
 #include "prof.hpp"
@@ -30,7 +31,12 @@ hipEvent_t get_event() {
 }
 }  // namespace
 
-ProfScope::ProfScope(int k, hipStream_t s, double work) : kind(k), st(s), slot(-1) {
+// phase scopes nest (a fallback rerun contains CANS and eigh phases): only
+// the outermost one on a thread records
+thread_local int t_phase_depth = 0;
+
+ProfScope::ProfScope(int k, hipStream_t s, double work) : kind(k), st(s), slot(-1), phase(k >= PROF_PHASE_BOUND) {
+  if (phase && t_phase_depth++ > 0) return;
   std::lock_guard<std::mutex> lk(g_mu);
   if (!g_on) return;
   hipEvent_t a = get_event(), b = get_event();
@@ -41,9 +47,16 @@ ProfScope::ProfScope(int k, hipStream_t s, double work) : kind(k), st(s), slot(-
 }
 
 ProfScope::~ProfScope() {
+  if (phase) --t_phase_depth;
   if (slot < 0) return;
   std::lock_guard<std::mutex> lk(g_mu);
   if (slot < (int)g_recs.size()) (void)hipEventRecord(g_recs[slot].b, st);
+}
+
+void ProfScope::next(int k) {
+  const hipStream_t s = st;
+  this->~ProfScope();
+  new (this) ProfScope(k, s, 0.0);
 }
 
 extern "C" {

@@ -139,7 +139,7 @@ def test_workspace_covers_quintic_buffer():
 
 def test_poly_argument_errors():
     L, lib = _lib()
-    assert _ws(L.default_params(1, 8, 8, poly=3), 0)[0] == 1
+    assert _ws(L.default_params(1, 8, 8, poly=4), 0)[0] == 1
     assert _ws(L.default_params(1, 8, 8, poly=2, bound=1), 0)[0] == 1
     assert _ws(L.default_params(1, 8, 8, poly=1, precision=1), 0)[0] == 1
     assert _ws(L.default_params(1, 8, 8, poly=2), 0)[0] == 0
@@ -178,3 +178,43 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=120)
     assert r.returncode != 0
     assert "one GPU" in json.loads(r.stdout.strip().splitlines()[-1])["error"]
+
+
+@pytest.mark.parametrize("lo", [1e-3, 1e-7, 0.3])
+def test_pe_table_matches_oracle(orc, lo):
+    # the host Remez exchange and exact interval images against the oracle's
+    # equioscillation solve and grid images: same step count, each step's
+    # polynomial as good as the oracle's on the oracle's cushioned interval
+    from paper_2609_32505_amd import api
+    tab = api.pe_table(lo)
+    ref = orc.polar_express_schedule(lo)
+    assert tab.shape == ref.shape
+    # each step's polynomial against the oracle's on the oracle's interval: the
+    # coefficients of a very narrow interval are not determined to FP64 by the
+    # problem (the minimax error nears rounding), the values are
+    l, u = lo, 1.0
+    for k in range(len(ref)):
+        last = k == len(ref) - 1
+        f = 1.0 if last else 1.01
+        x = np.linspace(l / f, u / f, 20001)
+        ph = tab[k, 0] * x + tab[k, 1] * x ** 3 + tab[k, 2] * x ** 5
+        pr = ref[k, 0] * x + ref[k, 1] * x ** 3 + ref[k, 2] * x ** 5
+        assert np.abs(ph - pr).max() < 1e-8, k
+        if u - l > 1e-3:
+            np.testing.assert_allclose(tab[k], ref[k], rtol=1e-8)
+        l, u = pr.min(), pr.max()
+
+
+def test_pe_argument_errors():
+    L, lib = _lib()
+    tab = (ctypes.c_double * 192)()
+    steps = ctypes.c_int32()
+    assert lib.svdp_pe_table(0.0, 64, tab, ctypes.byref(steps)) == 1
+    assert lib.svdp_pe_table(1e-3, 3, tab, ctypes.byref(steps)) == 1   # needs 8 steps
+    assert lib.svdp_pe_table(1e-3, 8, tab, ctypes.byref(steps)) == 0 and steps.value == 8
+    p = L.default_params(2, 10, 10, poly=L.POLY_PE, pe_lo=0.0)
+    st, _ = _ws(p, L.OP_SVD_FWD)
+    assert st == 1
+    p = L.default_params(2, 10, 10, poly=L.POLY_PE, pe_lo=1e-3, precision=L.PREC_BF16)
+    st, _ = _ws(p, L.OP_SVD_FWD)
+    assert st == 1

@@ -29,6 +29,10 @@ def dev(x):
     return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).cuda()
 
 
+def host(t):
+    return t.detach().cpu().double().numpy()
+
+
 def test_tiny_shapes(api):
     _say("tiny shapes: 1x1, 7x1, 5x5 batch 3")
     for b, m, n in [(1, 1, 1), (2, 7, 1), (3, 5, 5), (1, 33, 32)]:
@@ -283,6 +287,34 @@ def test_user_bound_too_small_falls_back(api):
     assert np.all(inf["flags"] & 2), "fallback must be used"
     Sh = S.cpu().double().numpy()
     assert (np.abs(Sh - s).max(axis=1) / s[:, 0]).max() < 1e-5
+
+
+def test_polar_bf16_corrected_with_fallback(api):
+    # polar_fwd on the BF16 path with the eigenpairs cached (the BF16
+    # correction on) and a user bound too small for matrix 1 only: matrix 1
+    # falls back to conservative FP32 CANS (its W comes from the masked
+    # copy of the rerun's iterate, its H from the rerun), the others keep the
+    # corrected W and H; all against the FP64 oracle's polar factors
+    _say("polar_fwd BF16, cached eigenpairs, one matrix falling back")
+    b, n = 3, 128
+    A, s = inputs.batch_with_spectra(95, b, n, n, lambda r: inputs.log_uniform(r, n, 1e-2, 1.0))
+    bounds = np.stack([s[:, -1], s[:, 0]], axis=1)
+    bounds[1, 1] *= 0.5
+    W, H, S, V, info = api.polar_fwd(dev(A), cache=True, precision=1, bound=2, user_bounds=dev(bounds),
+                                     margin_max=1.0)
+    Wh, Hh, Sh, Vh = host(W), host(H), host(S), host(V)
+    inf = api.info_to_numpy(info)
+    assert [bool(f & 2) for f in inf["flags"]] == [False, True, False], inf["flags"]
+    for i in range(b):
+        Uo, So, Vo, _ = oracle.svd(A[i].astype(np.float64))
+        Wo, Ho = oracle.polar_from_svd(Uo, So, Vo)
+        werr = np.abs(Wh[i] - Wo).max()
+        herr = np.abs(Hh[i] - Ho).max() / So[0]
+        serr = np.abs(np.abs(Sh[i]) - So).max() / So[0]
+        eig = np.abs((Vh[i] * Sh[i]) @ Vh[i].T - Hh[i]).max() / So[0]
+        _say(f"  matrix {i} (fallback {bool(inf['flags'][i] & 2)}): W {werr:.2e}, H {herr:.2e}, S {serr:.2e}, "
+             f"|V S V^T - H| {eig:.2e}")
+        assert werr < 2e-4 and herr < 1e-5 and serr < 1e-5 and eig < 1e-5
 
 
 def test_repeatable(api):

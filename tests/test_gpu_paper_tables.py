@@ -206,6 +206,25 @@ def test_polar_iteration_ablation_1024(api, handle):
              f"|W^T W - I|_F/|I|_F {orth:.2e}, flags {inf['flags'][0]}")
         assert not (inf["flags"][0] & 1) and orth < 1e-5
     assert its[1] > its[0] > its[2]
+    # Polar Express (its assumed lower end set below sigma_min / |A|_F): a
+    # fixed schedule without stop test, the input damped by 1.01 until the
+    # last step; it ends at the same orthogonality with fewer steps than
+    # Newton-Schulz
+    s = inputs.paper_kappa_rank(n, 1e6)
+    lo = 0.5 * s[-1] / np.linalg.norm(s)
+    W, H, _, _, info = api.polar_fwd(Ad, handle=handle, poly=3, pe_lo=lo, max_iters=64, cache=False)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    W, H, _, _, info = api.polar_fwd(Ad, handle=handle, poly=3, pe_lo=lo, max_iters=64, cache=False)
+    torch.cuda.synchronize()
+    dt = time.time() - t0
+    inf = api.info_to_numpy(info)
+    Wd = W[0].double()
+    orth = float(torch.linalg.norm(Wd.T @ Wd - eye) / np.sqrt(n))
+    its[3] = int(inf["iters"][0])
+    _say(f"  Polar Express (l0 {lo:.2e}): {its[3]} steps ({its[3] * 4} n^3 flops), {dt * 1e3:.1f} ms, "
+         f"|W^T W - I|_F/|I|_F {orth:.2e}, flags {inf['flags'][0]}")
+    assert orth < 1e-5 and its[3] < its[1]
 
 
 def _paper_value_r(table, rank):

@@ -244,3 +244,50 @@ def test_adam_constant_gradient_closed_form(orc):
         p_new, m, v = orc.adam_step(p, m, v, g, t, lr=0.01, eps=1e-12)
         np.testing.assert_allclose(p_new - p, -0.01 * g / (np.abs(g) + 1e-12), rtol=1e-9)
         p = p_new
+
+
+def test_polar_express_reaches_polar_factor_and_tracks_its_interval(orc):
+    # FP64 Polar Express (reading of its published construction: per-step
+    # minimax quintics on the cushioned interval, input / 1.01 on every step
+    # but the last): the singular values of the iterate stay inside the
+    # scalar interval recursion at every step (checked on the true singular
+    # values, by an SVD of each iterate), the iterate sits on a plateau short
+    # of convergence before the undamped last step, and the result is the
+    # Jacobi SVD's polar factor
+    rng = inputs.rng_for(44, 0)
+    s = inputs.geometric(30, 1e3)
+    A = inputs.matrix_with_spectrum(rng, 40, 30, s)
+    lo = 0.9 * s[-1] / np.linalg.norm(s)
+    tab = orc.polar_express_schedule(lo)
+    X = A / np.linalg.norm(A)
+    l, u = lo, 1.0
+    damp = 1.01
+    for k, (c1, c3, c5) in enumerate(tab):
+        sv = np.linalg.svd(X, compute_uv=False)
+        assert sv.min() >= l * (1 - 1e-9) and sv.max() <= u * (1 + 1e-9), k
+        if k == len(tab) - 1:
+            orth_before = np.linalg.norm(X.T @ X - np.eye(30)) / np.sqrt(30)
+        G = X.T @ X
+        X = c1 * X + X @ (c3 * G + c5 * (G @ G))
+        # the recursion's next interval, from the undamped coefficients
+        f = 1.0 if k == len(tab) - 1 else damp
+        q = (c1 * f, c3 * f ** 3, c5 * f ** 5)
+        xs = np.linspace(l / f, u / f, 100001)
+        v = q[0] * xs + q[1] * xs ** 3 + q[2] * xs ** 5
+        l, u = v.min(), v.max()
+    U, S, V, _ = orc.svd(A)
+    W_ref, _ = orc.polar_from_svd(U, S, V)
+    np.testing.assert_allclose(X, W_ref, atol=1e-9)
+    assert 1e-9 < orth_before < 1e-3      # the damped plateau
+    W2, steps = orc.polar_express_polar(A, lo)
+    assert steps == len(tab) and np.abs(W2 - X).max() < 1e-13
+    # a smaller assumed lower end costs steps
+    assert len(orc.polar_express_schedule(lo * 1e-3)) > len(tab)
+
+
+def test_polar_express_narrow_start_is_one_step(orc):
+    # an interval already narrower than 1e-4 needs only the undamped step, the
+    # quintic's narrow-interval limit
+    tab = orc.polar_express_schedule(1.0 - 5e-5)
+    assert tab.shape == (1, 3)
+    assert tab[0] == pytest.approx((15 / 8, -10 / 8, 3 / 8), rel=1e-3)
