@@ -383,6 +383,8 @@ svdp_status svdp_pe_table(double lo, int32_t max_steps, double* table, int32_t* 
 #define SVDP_PROF_PHASE_FALLBACK 11 /* conservative reruns of the bounded paths */
 #define SVDP_PROF_PHASE_BWD 12     /* svd_polar_bwd, polar_bwd */
 #define SVDP_PROF_PHASE_QR 13      /* QR preprocessing of tall matrices */
+#define SVDP_PROF_JAC_VSWEEP 14    /* Jacobi: the once-per-sweep update of V from every phase's
+                                      group rotations (n <= 1024) */
 void svdp_profile_enable(int on);
 void svdp_profile_reset(void);
 int svdp_profile_read(int kind, double* total_ms, int64_t* launches, double* work);

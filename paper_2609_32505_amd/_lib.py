@@ -95,7 +95,8 @@ SIGNATURES = {
     "svdp_profile_read": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(c_dbl), ctypes.POINTER(c_i64),
                                          ctypes.POINTER(c_dbl)]),
 }
-PROF_KINDS = {"jac_solve_f32": 0, "jac_solve_f64": 1, "jac_apply": 2, "gemm_f32": 3, "gemm_bf16": 4}
+PROF_KINDS = {"jac_solve_f32": 0, "jac_solve_f64": 1, "jac_apply": 2, "gemm_f32": 3, "gemm_bf16": 4,
+              "jac_vsweep": 14}
 PROF_PHASES = {"bound": 5, "cans": 6, "refine": 7, "H": 8, "eigh": 9, "U": 10, "fallback": 11, "backward": 12,
                "qr": 13}
 

@@ -327,6 +327,7 @@ struct FwdWs {
   float* qrc;  // blocked QR: projection coefficients, n x kQrBlock per matrix
   float *qrg, *qrr;  // blocked QR: a block's Gram matrix and CholeskyQR factor
   float* P;    // quintic steps: c3 G + c5 G^2, n x n per matrix
+  float *Qt, *Bq, *UBq;  // QR preprocessing of tall matrices: Q (m x n), B = Q^T A and U_B (n x n)
   int* qmask;  // blocked QR: the flagged matrices
   int *active, *where, *iters, *flags, *sweeps, *mask, *counter, *ksteps, *kmax, *hist, *gmask;
 };
@@ -356,7 +357,8 @@ FwdWs carve_fwd(void* base, const svdp_params* p, size_t* total) {
   w.y0 = c.take<float>(b * m);
   w.y1 = c.take<float>(b * m);
   w.qr = c.take<float>(b * 2 * m);
-  const bool blocked_qr = n > (size_t)kQrBlockedFrom;
+  const bool tall_qr = p->tall_qr && m > n;
+  const bool blocked_qr = n > (size_t)kQrBlockedFrom || tall_qr;
   w.qrc = c.take<float>(blocked_qr ? b * n * kQrBlock : 0);
   w.qrg = c.take<float>(blocked_qr ? b * kQrBlock * kQrBlock : 0);
   w.qrr = c.take<float>(blocked_qr ? b * kQrBlock * kQrBlock : 0);
@@ -373,6 +375,9 @@ FwdWs carve_fwd(void* base, const svdp_params* p, size_t* total) {
   w.ksteps = c.take<int>(2 * b);
   w.kmax = c.take<int>(16);
   w.hist = c.take<int>(4 * 64 + 8);
+  w.Qt = c.take<float>(tall_qr ? b * m * n : 0);
+  w.Bq = c.take<float>(tall_qr ? b * n * n : 0);
+  w.UBq = c.take<float>(tall_qr ? b * n * n : 0);
   if (total) *total = c.off;
   return w;
 }
@@ -700,6 +705,58 @@ svdp_status polar_core(Ctx& c) {
 // U[:, blk] -= U[:, :c0] C (block Gram-Schmidt), and twice G = U[:, blk]^T
 // U[:, blk], U[:, blk] <- U[:, blk] Rinv (CholeskyQR with column scaling).
 // The R factor this implies has a positive diagonal.
+// The block loop of the blocked QR on the matrices of qmask: for each block
+// of kQrBlock columns, twice C = U[:, :c0]^T U[:, blk] and U[:, blk] -=
+// U[:, :c0] C (block Gram-Schmidt), and twice G = U[:, blk]^T U[:, blk],
+// U[:, blk] <- U[:, blk] Rinv (CholeskyQR with column scaling).  With
+// zero_dep, columns dependent on the earlier ones come out as zero columns.
+svdp_status qr_blocks(Ctx& c, float* U, int64_t ldu, int64_t sU, const int* qmask, int zero_dep) {
+  FwdWs& w = c.w;
+  const int B = c.batch, m = c.m, n = c.n;
+  for (int c0 = 0; c0 < n; c0 += kQrBlock) {
+    const int bc = std::min(kQrBlock, n - c0);
+    for (int pass = 0; c0 > 0 && pass < 2; ++pass) {
+      GemmArgs g = gemm_base(c0, bc, m, B);  // C = U[:, :c0]^T U[:, c0:c0+bc]
+      g.A = U; g.lda = ldu; g.sA = sU;
+      g.B = U + c0; g.ldb = ldu; g.sB = sU;
+      g.C = w.qrc; g.ldc = bc; g.sC = (int64_t)n * kQrBlock;
+      g.active = qmask;
+      HIPCHK(gemm_launch(g, PREC_F32, 1, 0, c.st), "qr project");
+      GemmArgs u = gemm_base(m, bc, c0, B);  // U[:, blk] = U[:, blk] - U[:, :c0] C
+      u.A = U; u.lda = ldu; u.sA = sU;
+      u.B = w.qrc; u.ldb = bc; u.sB = (int64_t)n * kQrBlock;
+      u.C = U + c0; u.ldc = ldu; u.sC = sU;
+      u.Cin = U + c0; u.ldcin = ldu; u.sCin = sU;
+      u.alpha = -1.f; u.beta = 1.f;
+      u.active = qmask;
+      HIPCHK(gemm_launch(u, PREC_F32, 0, 0, c.st), "qr update");
+    }
+    for (int pass = 0; pass < 2; ++pass) {
+      GemmArgs g = gemm_base(bc, bc, m, B);  // G = U[:, blk]^T U[:, blk]
+      g.A = U + c0; g.lda = ldu; g.sA = sU;
+      g.B = U + c0; g.ldb = ldu; g.sB = sU;
+      g.C = w.qrg; g.ldc = bc; g.sC = (int64_t)kQrBlock * kQrBlock;
+      g.sym = 1; g.active = qmask;
+      HIPCHK(gemm_launch(g, PREC_F32, 1, 0, c.st), "qr gram");
+      HIPCHK(qr_chol_launch(w.qrg, w.qrr, B, bc, qmask, zero_dep, c.st), "qr chol");
+      // in place: each workgroup reads the rows of U[:, blk] it writes, and
+      // K = bc is consumed before its epilogue
+      GemmArgs r = gemm_base(m, bc, bc, B);  // U[:, blk] <- U[:, blk] Rinv
+      r.A = U + c0; r.lda = ldu; r.sA = sU;
+      r.B = w.qrr; r.ldb = bc; r.sB = (int64_t)kQrBlock * kQrBlock;
+      r.C = U + c0; r.ldc = ldu; r.sC = sU;
+      r.active = qmask;
+      HIPCHK(gemm_launch(r, PREC_F32, 0, 0, c.st), "qr scale");
+    }
+  }
+  return SVDP_OK;
+}
+
+// Blocked QR of U for the flagged matrices (n > kQrBlockedFrom): columns
+// without direction (sigma_j <= eps_qr sigma_1) are replaced by pseudo-random
+// unit vectors and other deficient columns perturbed by eps_qr-sized ones;
+// then the block loop of qr_blocks.  The R factor this implies has a
+// positive diagonal.
 svdp_status qr_blocked(Ctx& c, float* U, int64_t ldu, int64_t sU, const float* S, int64_t sS, const int* mask) {
   const svdp_params* p = c.p;
   FwdWs& w = c.w;
@@ -709,43 +766,21 @@ svdp_status qr_blocked(Ctx& c, float* U, int64_t ldu, int64_t sU, const float* S
   svdp_status s = read_counter(c, w.counter, &flagged);
   if (s || flagged == 0) return s;
   HIPCHK(qr_perturb_launch(U, ldu, sU, B, m, n, S, sS, w.colsum, (float)p->eps_qr, w.qmask, c.st), "qr perturb");
-  for (int c0 = 0; c0 < n; c0 += kQrBlock) {
-    const int bc = std::min(kQrBlock, n - c0);
-    for (int pass = 0; c0 > 0 && pass < 2; ++pass) {
-      GemmArgs g = gemm_base(c0, bc, m, B);  // C = U[:, :c0]^T U[:, c0:c0+bc]
-      g.A = U; g.lda = ldu; g.sA = sU;
-      g.B = U + c0; g.ldb = ldu; g.sB = sU;
-      g.C = w.qrc; g.ldc = bc; g.sC = (int64_t)n * kQrBlock;
-      g.active = w.qmask;
-      HIPCHK(gemm_launch(g, PREC_F32, 1, 0, c.st), "qr project");
-      GemmArgs u = gemm_base(m, bc, c0, B);  // U[:, blk] = U[:, blk] - U[:, :c0] C
-      u.A = U; u.lda = ldu; u.sA = sU;
-      u.B = w.qrc; u.ldb = bc; u.sB = (int64_t)n * kQrBlock;
-      u.C = U + c0; u.ldc = ldu; u.sC = sU;
-      u.Cin = U + c0; u.ldcin = ldu; u.sCin = sU;
-      u.alpha = -1.f; u.beta = 1.f;
-      u.active = w.qmask;
-      HIPCHK(gemm_launch(u, PREC_F32, 0, 0, c.st), "qr update");
-    }
-    for (int pass = 0; pass < 2; ++pass) {
-      GemmArgs g = gemm_base(bc, bc, m, B);  // G = U[:, blk]^T U[:, blk]
-      g.A = U + c0; g.lda = ldu; g.sA = sU;
-      g.B = U + c0; g.ldb = ldu; g.sB = sU;
-      g.C = w.qrg; g.ldc = bc; g.sC = (int64_t)kQrBlock * kQrBlock;
-      g.sym = 1; g.active = w.qmask;
-      HIPCHK(gemm_launch(g, PREC_F32, 1, 0, c.st), "qr gram");
-      HIPCHK(qr_chol_launch(w.qrg, w.qrr, B, bc, w.qmask, c.st), "qr chol");
-      // in place: each workgroup reads the rows of U[:, blk] it writes, and
-      // K = bc is consumed before its epilogue
-      GemmArgs r = gemm_base(m, bc, bc, B);  // U[:, blk] <- U[:, blk] Rinv
-      r.A = U + c0; r.lda = ldu; r.sA = sU;
-      r.B = w.qrr; r.ldb = bc; r.sB = (int64_t)kQrBlock * kQrBlock;
-      r.C = U + c0; r.ldc = ldu; r.sC = sU;
-      r.active = w.qmask;
-      HIPCHK(gemm_launch(r, PREC_F32, 0, 0, c.st), "qr scale");
-    }
+  return qr_blocks(c, U, ldu, sU, w.qmask, 0);
+}
+
+// Algorithm 1's column-norm test on U and its QR step for the flagged
+// matrices (one workgroup per matrix up to kQrBlockedFrom columns, blocked
+// above).
+svdp_status u_qr_step(Ctx& c, float* U, int64_t ldu, int64_t sU, const float* S, int64_t sS, const int* mask) {
+  FwdWs& w = c.w;
+  const int B = c.batch, m = c.m, n = c.n;
+  HIPCHK(colnorm_check_launch(U, ldu, sU, B, m, n, w.colsum, (float)c.p->eps_qr, w.flags, mask, c.st), "colnorm");
+  if (n <= kQrBlockedFrom) {
+    HIPCHK(qr_complete_launch(U, ldu, sU, B, m, n, (float)c.p->eps_qr, w.flags, w.qr, mask, c.st), "qr");
+    return SVDP_OK;
   }
-  return SVDP_OK;
+  return qr_blocked(c, U, ldu, sU, S, sS, mask);
 }
 
 // H, eigh(H), U = W V with eigenvalue signs, column-norm test (Algorithm 1
@@ -793,14 +828,9 @@ svdp_status svd_tail(Ctx& c, float* U, int64_t ldu, int64_t sU, float* S, int64_
   g.colscale = e.sgn; g.cs_stride = n;
   g.active = mask;
   HIPCHK(gemm_launch(g, PREC_F32, 0, 0, c.st), "U = W V");
-  HIPCHK(colnorm_check_launch(U, ldu, sU, B, m, n, w.colsum, (float)p->eps_qr, w.flags, mask, c.st), "colnorm");
   // Algorithm 1: a column norm off by more than eps_qr (rank deficiency)
   // -> orthogonalise U by QR
-  if (n <= kQrBlockedFrom) {
-    HIPCHK(qr_complete_launch(U, ldu, sU, B, m, n, (float)p->eps_qr, w.flags, w.qr, mask, c.st), "qr");
-    return SVDP_OK;
-  }
-  return qr_blocked(c, U, ldu, sU, S, sS, mask);
+  return u_qr_step(c, U, ldu, sU, S, sS, mask);
 }
 
 svdp_status check_model(svdp_handle* h, const svdp_params* p) {
@@ -822,6 +852,71 @@ svdp_status fallback_mask(Ctx& c, int* count) {
                               SVDP_FLAG_NEG_EIGENVALUE | SVDP_FLAG_NONFINITE | SVDP_FLAG_NOT_CONVERGED, w.resid,
                               (float)c.p->refine_tol, w.mask, w.counter, c.st), "fallback mask");
   return read_counter(c, w.counter, count);
+}
+
+// Algorithm 1 on the matrices of the context: the polar factor, H, eigh, U,
+// and the conservative reruns of the bounded paths.
+svdp_status svd_core(Ctx& c, float* U, int64_t ldu, int64_t sU, float* S, int64_t sS, float* V, int64_t ldv,
+                     int64_t sV) {
+  svdp_status s;
+  if ((s = polar_core(c))) return s;
+  if ((s = svd_tail(c, U, ldu, sU, S, sS, V, ldv, sV, nullptr))) return s;
+  if (c.p->bound != SVDP_BOUND_CONSERVATIVE) {
+    int cnt = 0;
+    if ((s = fallback_mask(c, &cnt))) return s;
+    if (cnt > 0) {
+      ProfScope phase(PROF_PHASE_FALLBACK, c.st);
+      const int* mk = c.w.mask;
+      if ((s = conservative_fp32(c, mk))) return s;
+      if ((s = final_residual(c, mk))) return s;
+      if ((s = svd_tail(c, U, ldu, sU, S, sS, V, ldv, sV, mk))) return s;
+      HIPCHK(or_flags_launch(c.batch, c.w.flags, SVDP_FLAG_FALLBACK_USED, mk, c.st), "flags");
+    }
+  }
+  return SVDP_OK;
+}
+
+// QR preprocessing of tall matrices (the paper's rectangular experiments):
+// Q, an orthonormal basis of A's columns (block Gram-Schmidt with CholeskyQR
+// blocks, dependent columns dropped as zero columns), B = Q^T A (n x n, with
+// A = Q B since Q Q^T A = A), the SVD B = U_B S V^T by svd_core on the square
+// B, and U = Q U_B.  Zero columns of Q (a rank-deficient A) can leave
+// columns of U off unit norm; Algorithm 1's column-norm test and QR step on
+// U repair them.
+svdp_status svd_tall_qr(Ctx& c, float* U, int64_t ldu, int64_t sU, float* S, int64_t sS, float* V, int64_t ldv,
+                        int64_t sV) {
+  FwdWs& w = c.w;
+  const int B = c.batch, m = c.m, n = c.n;
+  const int64_t mn = (int64_t)m * n, nn = (int64_t)n * n;
+  {
+    ProfScope phase(PROF_PHASE_QR, c.st);
+    HIPCHK(copy_launch(c.A, c.lda, c.sA, nullptr, nullptr, w.Qt, n, mn, B, m, n, c.st, nullptr), "Q = A");
+    HIPCHK(fill_i32(w.qmask, 1, B, c.st), "qr mask");
+    svdp_status s = qr_blocks(c, w.Qt, n, mn, w.qmask, 1);
+    if (s) return s;
+    GemmArgs g = gemm_base(n, n, m, B);  // B = Q^T A
+    g.A = w.Qt; g.lda = n; g.sA = mn;
+    g.B = c.A; g.ldb = c.lda; g.sB = c.sA;
+    g.C = w.Bq; g.ldc = n; g.sC = nn;
+    HIPCHK(gemm_launch(g, PREC_F32, 1, 0, c.st), "Q^T A");
+  }
+  svdp_params p2 = *c.p;
+  p2.m = n;
+  Ctx c2 = c;
+  c2.p = &p2;
+  c2.m = n;
+  c2.A = w.Bq;
+  c2.lda = n;
+  c2.sA = nn;
+  svdp_status s = svd_core(c2, w.UBq, n, nn, S, sS, V, ldv, sV);
+  if (s) return s;
+  ProfScope phase(PROF_PHASE_QR, c.st);
+  GemmArgs g = gemm_base(m, n, n, B);  // U = Q U_B
+  g.A = w.Qt; g.lda = n; g.sA = mn;
+  g.B = w.UBq; g.ldb = n; g.sB = nn;
+  g.C = U; g.ldc = ldu; g.sC = sU;
+  HIPCHK(gemm_launch(g, PREC_F32, 0, 0, c.st), "Q U_B");
+  return u_qr_step(c, U, ldu, sU, S, sS, nullptr);
 }
 
 }  // namespace
@@ -1002,19 +1097,10 @@ svdp_status svd_polar_fwd(svdp_handle* h, const svdp_params* p, const float* A, 
   carve_fwd(nullptr, p, &need);
   if (!ws || ws_bytes < need) return fail(SVDP_ERR_WORKSPACE, "workspace too small");
   Ctx c{h, p, carve_fwd(ws, p, nullptr), (hipStream_t)stream, (int)p->batch, (int)p->m, (int)p->n, A, lda, sA};
-  if ((s = polar_core(c))) return s;
-  if ((s = svd_tail(c, U, ldu, sU, S, sS, V, ldv, sV, nullptr))) return s;
-  if (p->bound != SVDP_BOUND_CONSERVATIVE) {
-    int cnt = 0;
-    if ((s = fallback_mask(c, &cnt))) return s;
-    if (cnt > 0) {
-      ProfScope phase(PROF_PHASE_FALLBACK, c.st);
-      const int* mk = c.w.mask;
-      if ((s = conservative_fp32(c, mk))) return s;
-      if ((s = final_residual(c, mk))) return s;
-      if ((s = svd_tail(c, U, ldu, sU, S, sS, V, ldv, sV, mk))) return s;
-      HIPCHK(or_flags_launch(c.batch, c.w.flags, SVDP_FLAG_FALLBACK_USED, mk, c.st), "flags");
-    }
+  if (p->tall_qr && p->m > p->n) {
+    if ((s = svd_tall_qr(c, U, ldu, sU, S, sS, V, ldv, sV))) return s;
+  } else if ((s = svd_core(c, U, ldu, sU, S, sS, V, ldv, sV))) {
+    return s;
   }
   if (info) HIPCHK(info_pack_launch(c.batch, c.w.iters, c.w.sweeps, c.w.flags, c.w.resid, info, nullptr, c.st), "info");
   return SVDP_OK;

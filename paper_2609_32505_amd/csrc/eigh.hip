@@ -77,6 +77,11 @@ SVDP_DEV void group_members(const EighPhase& ph, int gi, int* g) {
 
 SVDP_DEV int64_t tile_off(int I, int J, int nb) { return ((int64_t)I * nb + J) * (BS * BS); }
 
+// group rotations of phase slot `slot` of matrix b (nb / 4 groups of QSTRIDE floats)
+SVDP_DEV float* qslot(const EighWs& e, int b, int slot) {
+  return e.Qw + ((int64_t)b * e.nph_store + slot) * (e.nb / 4) * QSTRIDE;
+}
+
 // orders the wave's own LDS traffic: no instruction is moved across it, and
 // LDS operations of one wave complete in issue order
 SVDP_DEV void wave_sync() {
@@ -342,7 +347,7 @@ __global__ __launch_bounds__(128) void k_jac_solve(EighWs e, EighPhase ph, int i
   // a pair whose 2 x 2 block lies entirely at or below skip_abs is not rotated
   const R skip_abs = (R)skip_rel * (R)sqrtf(e.hnorm2[b]);
   float mrel = 0.f, vsum = 0.f;
-  float* M = e.Qw + ((int64_t)b * ng + gi) * QSTRIDE;
+  float* M = qslot(e, b, e.deferred ? ph.idx : 0) + (int64_t)gi * QSTRIDE;
   float* JAg = M + GS * GS;  // step-A rotations (FP32), read back for M_G
   R jp[8], jq[8];
   // step A
@@ -448,7 +453,8 @@ __global__ __launch_bounds__(256) void k_jac_apply(EighWs e, EighPhase ph) {
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
   const int ng = e.nb / 4;
   const int nH = ng * (ng - 1) / 2;
-  const int ntask = nH + ng * ng;
+  // with V deferred to the end of the sweep only the H tasks run here
+  const int ntask = e.deferred ? nH : nH + ng * ng;
   // matrix b runs on XCD b % 8: its group rotations stay in one L2
   const int L = blockIdx.x, x8 = L & 7, q = L >> 3;
   const int grp = q / ntask, task = q - grp * ntask;
@@ -456,7 +462,7 @@ __global__ __launch_bounds__(256) void k_jac_apply(EighWs e, EighPhase ph) {
   if (b >= e.batch) return;
   if (e.active && !e.active[b]) return;
   const int qi = w >> 1, qj = w & 1;
-  const float* Qb = e.Qw + (int64_t)b * ng * QSTRIDE;
+  const float* Qb = qslot(e, b, e.deferred ? ph.idx : 0);
   if (task < nH) {
     int tt = task, G1 = 0;
     while (tt >= ng - 1 - G1) { tt -= ng - 1 - G1; ++G1; }
@@ -538,6 +544,83 @@ __global__ __launch_bounds__(256) void k_jac_apply(EighWs e, EighPhase ph) {
   }
 }
 
+// Deferred V update: V[slab, :] <- V[slab, :] M_1 M_2 ... M_P with the group
+// rotations of every phase of the sweep (block diagonal in that phase's
+// grouping, one 64 x 64 orthogonal M per group of four blocks).  One
+// workgroup (four wavefronts) per slab of R rows of one matrix; the slab
+// (R x NP FP32, row pitch NP + 1 so that the 32 rows an MFMA operand reads
+// start in 32 different banks) stays in LDS for the whole sweep, and each
+// phase's rotations are read from L2 straight into MFMA operand registers.
+// Per phase the R x 64 block of each group is multiplied by its M: (R / 32)
+// x ng x 2 output blocks of 32 x 32, dealt to the four waves; each wave keeps
+// its blocks' accumulators until every wave has read the phase's input (one
+// barrier), then writes them back (another).  Matrices that were not active
+// in the sweep are skipped (their rotation slots hold an earlier sweep's).
+template <int R, int NP>
+__global__ __launch_bounds__(256) void k_jac_vsweep(EighWs e) {
+  constexpr int PITCH = NP + 1;
+  constexpr int NBK = NP / BS, NG = NBK / 4;
+  constexpr int NBLK = (R / 32) * NG * 2;
+  constexpr int BPW = NBLK / 4;
+  static_assert(NBLK % 4 == 0 && BPW >= 1, "output blocks must split over four waves");
+  constexpr int SLABS = NP / R;
+  __shared__ float Vs[R * PITCH];
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+  // matrix b on XCD b % 8: its rotations are read into one L2
+  const int L = blockIdx.x, x8 = L & 7, q = L >> 3;
+  const int grp = q / SLABS, slab = q - grp * SLABS;
+  const int b = grp * 8 + x8;
+  if (b >= e.batch) return;
+  if (e.active && !e.active[b]) return;
+  float* V = e.Vw + (int64_t)b * NP * NP + (int64_t)slab * R * NP;
+  for (int idx = t; idx < R * NP / 4; idx += 256) {
+    const int r = idx / (NP / 4), c = (idx - r * (NP / 4)) * 4;
+    const f4v v = *(const f4v*)(V + (int64_t)r * NP + c);
+#pragma unroll
+    for (int w2 = 0; w2 < 4; ++w2) Vs[r * PITCH + c + w2] = v[w2];
+  }
+  __syncthreads();
+  const int kh = lane >> 5, ic = lane & 31;
+  for (int p = 0; p < NBK / 2; ++p) {
+    const EighPhase ph = eigh_phase(p);
+    const float* Q = qslot(e, b, p);
+    f16v acc[BPW];
+#pragma unroll
+    for (int j = 0; j < BPW; ++j) {
+      const int bi = w + 4 * j, ch = bi & 1, G = (bi >> 1) % NG, rb = (bi >> 1) / NG;
+      int gm[4];
+      group_members(ph, G, gm);
+      float bm[32];
+      load_mcol(Q + (int64_t)G * QSTRIDE, 32 * ch, lane, bm);
+      const float* row = Vs + (32 * rb + ic) * PITCH;
+      f16v a = zero16();
+#pragma unroll
+      for (int s2 = 0; s2 < 32; ++s2) a = mfma(row[16 * gm[s2 >> 3] + 2 * (s2 & 7) + kh], bm[s2], a);
+      acc[j] = a;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < BPW; ++j) {
+      const int bi = w + 4 * j, ch = bi & 1, G = (bi >> 1) % NG, rb = (bi >> 1) / NG;
+      int gm[4];
+      group_members(ph, G, gm);
+      const int col = 16 * gm[2 * ch + (ic >> 4)] + (ic & 15);
+#pragma unroll
+      for (int g4 = 0; g4 < 4; ++g4)
+#pragma unroll
+        for (int r4 = 0; r4 < 4; ++r4) Vs[(32 * rb + 8 * g4 + 4 * kh + r4) * PITCH + col] = acc[j][4 * g4 + r4];
+    }
+    __syncthreads();
+  }
+  for (int idx = t; idx < R * NP / 4; idx += 256) {
+    const int r = idx / (NP / 4), c = (idx - r * (NP / 4)) * 4;
+    f4v v;
+#pragma unroll
+    for (int w2 = 0; w2 < 4; ++w2) v[w2] = Vs[r * PITCH + c + w2];
+    *(f4v*)(V + (int64_t)r * NP + c) = v;
+  }
+}
+
 // what k_eigh_setup writes: V = I (tiled), the upper tiles of sym(H), |H|_F^2
 constexpr int kSetupV = 1, kSetupH = 2, kSetupNorm = 4;
 
@@ -561,7 +644,9 @@ __global__ __launch_bounds__(256) void k_eigh_setup(EighWs e, const float* Hin, 
       f4v v;
 #pragma unroll
       for (int w2 = 0; w2 < 4; ++w2) v[w2] = (I == J && r == c + w2) ? 1.f : 0.f;
-      *(f4v*)(Vb + tile_off(I, J, e.nb) + qd * 4) = v;
+      // deferred V is row-major, otherwise tiled
+      const int64_t off = e.deferred ? (int64_t)(16 * I + r) * e.np + 16 * J + c : tile_off(I, J, e.nb) + qd * 4;
+      *(f4v*)(Vb + off) = v;
     }
   if (!(what & kSetupH) || Ib > Jb) return;  // whole workgroup: H keeps the upper tiles only
   const float* Hb = Hin + b * sH;
@@ -815,12 +900,17 @@ int eigh_blocks(int64_t n) {
   return nb;
 }
 
+// V is deferred (updated once per sweep by k_jac_vsweep) when a slab of it
+// fits in LDS: np <= 1024
+static bool eigh_deferred(int64_t np) { return np <= 1024; }
+
 size_t eigh_ws_bytes(int64_t batch, int64_t n, int max_sweeps) {
   const int64_t nb = eigh_blocks(n), np = nb * BS, ng = nb / 4;
+  const int64_t nph = eigh_deferred(np) ? nb / 2 : 1;
   size_t f = 0;
   f += 3 * batch * np * np;          // Hw, Vw, V2
   f += batch * n;                    // lamr
-  f += batch * ng * QSTRIDE;         // Qw
+  f += batch * nph * ng * QSTRIDE;   // Qw
   f += batch;                        // hnorm2
   f += 2 * batch;                    // off2 (FP64)
   f += 2 * batch * n;                // sign, (perm as int)
@@ -835,13 +925,15 @@ EighWs eigh_ws_carve(void* ws, int64_t batch, int64_t n, int max_sweeps) {
   e.nb = eigh_blocks(n);
   e.np = e.nb * BS;
   const int64_t np = e.np, ng = e.nb / 4;
+  e.deferred = eigh_deferred(np) ? 1 : 0;
+  e.nph_store = e.deferred ? e.nb / 2 : 1;
   char* p = (char*)ws;
   auto take = [&](size_t bytes) { char* r = p; p += (bytes + 255) / 256 * 256; return (void*)r; };
   e.Hw = (float*)take(batch * np * np * 4);
   e.Vw = (float*)take(batch * np * np * 4);
   e.V2 = (float*)take(batch * np * np * 4);
   e.lamr = (float*)take(batch * n * 4);
-  e.Qw = (float*)take(batch * ng * QSTRIDE * 4);
+  e.Qw = (float*)take(batch * e.nph_store * ng * QSTRIDE * 4);
   e.hnorm2 = (float*)take(batch * 4);
   e.off2 = (double*)take(batch * 8);
   e.sgn = (float*)take(batch * n * 4);
@@ -854,28 +946,27 @@ EighWs eigh_ws_carve(void* ws, int64_t batch, int64_t n, int max_sweeps) {
   return e;
 }
 
-// The phases of one sweep over nb blocks: (1, -) with the full inner rounds,
-// then (2, 3), (4, 5), ..., (nb - 2, nb - 1) with cross rounds.  The first
-// phase has one step; its grouping uses sB = 2 (any other partner works).
+static int phases_per_sweep_of(int nb) { return nb / 2; }
+
 std::vector<EighPhase> eigh_phases(int nb) {
   std::vector<EighPhase> out;
-  auto make = [](int sA, int sB, int fullA, int skipB) {
-    EighPhase ph;
-    ph.sA = sA;
-    ph.sB = sB;
-    ph.fullA = fullA;
-    ph.skipB = skipB;
-    int u = sA, v = sB;
-    const int p1 = 31 - __builtin_clz((unsigned)u);
-    if ((v >> p1) & 1) v ^= u;
-    const int p2 = 31 - __builtin_clz((unsigned)v);
-    ph.lo = std::min(p1, p2);
-    ph.hi = std::max(p1, p2);
-    return ph;
-  };
-  out.push_back(make(1, 2, 1, 1));
-  for (int s = 2; s + 1 < nb; s += 2) out.push_back(make(s, s + 1, 0, 0));
+  for (int p = 0; p < nb / 2; ++p) out.push_back(eigh_phase(p));
   return out;
+}
+
+// The deferred V update of one sweep for the matrices of E (V row-major).
+static hipError_t vsweep_launch(const EighWs& E, double work, hipStream_t st) {
+  ProfScope ps(PROF_JAC_VSWEEP, st, work);
+  const unsigned groups8 = (unsigned)cdiv(E.batch, 8) * 8;
+  switch (E.np) {
+    case 64: hipLaunchKernelGGL((k_jac_vsweep<64, 64>), dim3(groups8 * 1), dim3(256), 0, st, E); break;
+    case 128: hipLaunchKernelGGL((k_jac_vsweep<64, 128>), dim3(groups8 * 2), dim3(256), 0, st, E); break;
+    case 256: hipLaunchKernelGGL((k_jac_vsweep<64, 256>), dim3(groups8 * 4), dim3(256), 0, st, E); break;
+    case 512: hipLaunchKernelGGL((k_jac_vsweep<64, 512>), dim3(groups8 * 8), dim3(256), 0, st, E); break;
+    case 1024: hipLaunchKernelGGL((k_jac_vsweep<32, 1024>), dim3(groups8 * 32), dim3(256), 0, st, E); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 // View of matrices [b0, b0 + cnt) of a workspace; part h uses its own
@@ -888,7 +979,7 @@ static EighWs eigh_sub(const EighWs& e, int b0, int cnt, int h) {
   s.Vw += b0 * m2;
   s.V2 += b0 * m2;
   s.lamr += (int64_t)b0 * e.n;
-  s.Qw += b0 * ng * QSTRIDE;
+  s.Qw += b0 * e.nph_store * ng * QSTRIDE;
   s.hnorm2 += b0;
   s.off2 += b0;
   s.sgn += (int64_t)b0 * e.n;
@@ -921,7 +1012,9 @@ hipError_t eigh_run(EighWs e, const float* H, int64_t ldh, int64_t sH, int mode,
   // (24 flops each) and 512 rotation-accumulator pairs (6 each); the apply
   // does two 64^3 products per pair of groups and one per slab of V
   const double round_work = 256.0 * 24.0 + 512.0 * 6.0;
-  const double apply_work = (double)nH * 4.0 * GS * GS * GS + (double)ng * ng * 2.0 * GS * GS * GS;
+  const double apply_work = (double)nH * 4.0 * GS * GS * GS + (e.deferred ? 0.0 : (double)ng * ng * 2.0 * GS * GS * GS);
+  // the deferred V update: every phase's 64 x 64 group products over all rows
+  const double vsweep_work = (double)phases_per_sweep_of(e.nb) * ng * 2.0 * e.np * GS * GS;
   auto solve_work = [&](const EighPhase& ph, int reps) {
     const int rounds = (ph.fullA ? 31 : 16) + (ph.skipB ? 0 : 16);
     return (double)ng * 2.0 * rounds * round_work * reps;
@@ -949,7 +1042,7 @@ hipError_t eigh_run(EighWs e, const float* H, int64_t ldh, int64_t sH, int mode,
                             bool mark_skew) -> hipError_t {
     const EighWs& E = eh[h];
     const unsigned sblocks = (unsigned)(E.batch * ng);
-    const unsigned ablocks = (unsigned)((int64_t)cdiv(E.batch, 8) * 8 * ntask);
+    const unsigned ablocks = (unsigned)((int64_t)cdiv(E.batch, 8) * 8 * (e.deferred ? nH : ntask));
     if (fp64) {
       ProfScope ps(PROF_JAC_SOLVE_F64, ss[h], solve_work(ph, o.fp64_inner) * n_act);
       hipLaunchKernelGGL(k_jac_solve<double>, dim3(sblocks), dim3(128), 0, ss[h], E, ph, o.fp64_inner, o.abs_tol,
@@ -962,7 +1055,7 @@ hipError_t eigh_run(EighWs e, const float* H, int64_t ldh, int64_t sH, int mode,
     hipError_t e2 = hipGetLastError();
     if (e2) return e2;
     if (mark_skew && (e2 = hipEventRecord(aux->skew[h], ss[h]))) return e2;
-    {
+    if (ablocks > 0) {
       ProfScope ps(PROF_JAC_APPLY, ss[h], apply_work * n_act);
       hipLaunchKernelGGL(k_jac_apply, dim3(ablocks), dim3(256), 0, ss[h], E, ph);
     }
@@ -984,6 +1077,12 @@ hipError_t eigh_run(EighWs e, const float* H, int64_t ldh, int64_t sH, int mode,
       }
       first = false;
     }
+    if (e.deferred)
+      for (int h = 0; h < P; ++h) {
+        if (n_act[h] == 0) continue;
+        hipError_t e2 = vsweep_launch(eh[h], vsweep_work * n_act[h], ss[h]);
+        if (e2) return e2;
+      }
     return hipSuccess;
   };
   int n_act[kEighParts];
@@ -1037,26 +1136,33 @@ hipError_t eigh_run(EighWs e, const float* H, int64_t ldh, int64_t sH, int mode,
   if ((err = join())) return err;
   const int np = e.np;
   const int64_t m2 = (int64_t)np * np;
-  // V (tiled) -> row-major in Hw; one Newton-Schulz step re-orthonormalises
-  // it, V2 = V (3 I - V^T V) / 2 (V^T V in Vw)
+  // V row-major: Vw itself when deferred, else untiled into Hw; one
+  // Newton-Schulz step re-orthonormalises it, V2 = V (3 I - V^T V) / 2 (V^T V
+  // in the other of Hw / Vw; H is no longer needed)
   {
-    hipLaunchKernelGGL(k_untile, dim3(np, batch), dim3(256), 0, st, e.Vw, e.Hw, np, e.nb, mask);
-    if ((err = hipGetLastError())) return err;
+    float* Vrow = e.Vw;
+    float* Gram = e.Hw;
+    if (!e.deferred) {
+      hipLaunchKernelGGL(k_untile, dim3(np, batch), dim3(256), 0, st, e.Vw, e.Hw, np, e.nb, mask);
+      if ((err = hipGetLastError())) return err;
+      Vrow = e.Hw;
+      Gram = e.Vw;
+    }
     GemmArgs g;
     memset(&g, 0, sizeof(g));
     g.M = np; g.N = np; g.K = np; g.batch = batch;
-    g.A = e.Hw; g.lda = np; g.sA = m2;
-    g.B = e.Hw; g.ldb = np; g.sB = m2;
-    g.C = e.Vw; g.ldc = np; g.sC = m2;
+    g.A = Vrow; g.lda = np; g.sA = m2;
+    g.B = Vrow; g.ldb = np; g.sB = m2;
+    g.C = Gram; g.ldc = np; g.sC = m2;
     g.alpha = 1.f; g.sym = 1; g.active = mask;
     if ((err = gemm_launch(g, PREC_F32, 1, 0, st))) return err;
     GemmArgs u;
     memset(&u, 0, sizeof(u));
     u.M = np; u.N = np; u.K = np; u.batch = batch;
-    u.A = e.Hw; u.lda = np; u.sA = m2;
-    u.B = e.Vw; u.ldb = np; u.sB = m2;
+    u.A = Vrow; u.lda = np; u.sA = m2;
+    u.B = Gram; u.ldb = np; u.sB = m2;
     u.C = e.V2; u.ldc = np; u.sC = m2;
-    u.Cin = e.Hw; u.ldcin = np; u.sCin = m2;
+    u.Cin = Vrow; u.ldcin = np; u.sCin = m2;
     u.alpha = -0.5f; u.beta = 1.5f; u.active = mask;
     if ((err = gemm_launch(u, PREC_F32, 0, 0, st))) return err;
   }
@@ -1116,17 +1222,25 @@ hipError_t eigh_run(EighWs e, const float* H, int64_t ldh, int64_t sH, int mode,
       for (int f = 0; f < std::max(1, o.fp64_sweeps); ++f)
         if ((err = sweep_launches(o.fp64_sweeps > 0, kRestartSkip, nullptr, nullptr, bc))) return err;
       if ((err = join())) return err;
-      hipLaunchKernelGGL(k_untile, dim3(np, batch), dim3(256), 0, st, e.Vw, e.Hw, np, e.nb, proc);
-      if ((err = hipGetLastError())) return err;
+      // V' row-major (Vw itself when deferred, else untiled into Hw); V2 V'
+      // into the other buffer, then copied to V2 for the restarted matrices
+      const float* Vp = e.Vw;
+      float* VV = e.Hw;
+      if (!e.deferred) {
+        hipLaunchKernelGGL(k_untile, dim3(np, batch), dim3(256), 0, st, e.Vw, e.Hw, np, e.nb, proc);
+        if ((err = hipGetLastError())) return err;
+        Vp = e.Hw;
+        VV = e.Vw;
+      }
       GemmArgs v;
       memset(&v, 0, sizeof(v));
       v.M = e.n; v.N = e.n; v.K = e.n; v.batch = batch;
       v.A = e.V2; v.lda = np; v.sA = m2;
-      v.B = e.Hw; v.ldb = np; v.sB = m2;
-      v.C = e.Vw; v.ldc = np; v.sC = m2;
+      v.B = Vp; v.ldb = np; v.sB = m2;
+      v.C = VV; v.ldc = np; v.sC = m2;
       v.alpha = 1.f; v.active = proc;
       if ((err = gemm_launch(v, PREC_F32, 0, 0, st))) return err;
-      hipLaunchKernelGGL(k_copy_active, dim3(std::min(e.n, 512), batch), dim3(256), 0, st, e.Vw, e.V2, e.n, np,
+      hipLaunchKernelGGL(k_copy_active, dim3(std::min(e.n, 512), batch), dim3(256), 0, st, VV, e.V2, e.n, np,
                          proc);
       if ((err = hipGetLastError())) return err;
     }

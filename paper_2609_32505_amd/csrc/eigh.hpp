@@ -18,6 +18,9 @@ struct EighWs {
   float* rotsq;   // batch x (max_sweeps + 2): sum of squares of the entries rotated
   int* active;    // batch: 1 while not converged
   int* counter;   // device scalar: active matrices after a sweep
+  int deferred;   // 1: V row-major, updated once per sweep from every phase's group
+                  // rotations (np <= 1024); 0: V tiled, updated by every phase's apply
+  int nph_store;  // group-rotation slots per matrix in Qw: the phases of a sweep (deferred), else 1
 };
 
 // Two fused block-Jacobi steps: block B is paired with B ^ sA, then with
@@ -28,7 +31,29 @@ struct EighPhase {
   int lo, hi;
   int fullA;  // the first step also runs the intra-block rounds
   int skipB;  // the phase has a single step
+  int idx;    // position in the sweep (slot of its group rotations when V is deferred)
 };
+
+// Phase p of a sweep over nb blocks: (1, -) with the full inner rounds, then
+// (2, 3), (4, 5), ..., (nb - 2, nb - 1) with cross rounds.  The first phase
+// has one step; its grouping uses sB = 2 (any other partner works).  lo, hi:
+// the pivot bits of span{sA, sB} in echelon form.
+__host__ __device__ inline EighPhase eigh_phase(int p) {
+  EighPhase ph;
+  ph.sA = p == 0 ? 1 : 2 * p;
+  ph.sB = p == 0 ? 2 : 2 * p + 1;
+  ph.fullA = p == 0;
+  ph.skipB = p == 0;
+  ph.idx = p;
+  const int u = ph.sA;
+  int v = ph.sB;
+  const int p1 = 31 - __builtin_clz((unsigned)u);
+  if ((v >> p1) & 1) v ^= u;
+  const int p2 = 31 - __builtin_clz((unsigned)v);
+  ph.lo = p1 < p2 ? p1 : p2;
+  ph.hi = p1 < p2 ? p2 : p1;
+  return ph;
+}
 
 struct EighOpts {
   int inner_sweeps;  // repetitions of a step's scalar rounds per pair subproblem (FP32)

@@ -347,8 +347,14 @@ __global__ void k_qr_mask(int batch, const int* flags, const int* mask, int* qma
 // (Cholesky, upper R', FP64 in LDS), Z = Q R' D, so Rinv = D^-1 R'^-1, upper
 // triangular with a positive diagonal (R_ii > 0).  Column scales are kept
 // >= 1e-15 of the largest and pivots (of the unit-diagonal G') >= 1e-12, so
-// a (numerically) dependent block gives large but finite factors.
-__global__ __launch_bounds__(256) void k_qr_chol(const float* G, float* Rinv, int bc, const int* qmask) {
+// a (numerically) dependent block gives large but finite factors.  With
+// zero_dep, a column whose pivot is <= 1e-10 (its angle to the block's
+// earlier columns below 1e-5: dependent to FP32 resolution) is dropped
+// instead: its row of R' is taken as e_k (no trailing update) and its column
+// of Rinv as zero, so Z Rinv has a zero column there and the other columns
+// stay orthonormal and independent of it.
+__global__ __launch_bounds__(256) void k_qr_chol(const float* G, float* Rinv, int bc, const int* qmask,
+                                                 int zero_dep) {
   const int b = blockIdx.x;
   if (!qmask[b]) return;
   __shared__ double A[64][65];
@@ -371,13 +377,21 @@ __global__ __launch_bounds__(256) void k_qr_chol(const float* G, float* Rinv, in
     X[i][j] = 0.f;
   }
   __syncthreads();
+  __shared__ int dep[64];
+  for (int k = t; k < 64; k += 256) dep[k] = 0;
+  __syncthreads();
   for (int k = 0; k < bc; ++k) {
     if (t == 0) {
       const double piv = A[k][k];
-      A[k][k] = piv > 1e-12 ? sqrt(piv) : 1e-6;
+      if (zero_dep && !(piv > 1e-10)) {
+        dep[k] = 1;
+        A[k][k] = 1.0;
+      } else {
+        A[k][k] = piv > 1e-12 ? sqrt(piv) : 1e-6;
+      }
     }
     __syncthreads();
-    for (int j = k + 1 + t; j < bc; j += 256) A[k][j] /= A[k][k];
+    for (int j = k + 1 + t; j < bc; j += 256) A[k][j] = dep[k] ? 0.0 : A[k][j] / A[k][k];
     __syncthreads();
     const int w = bc - k - 1;
     for (int idx = t; idx < w * w; idx += 256) {
@@ -399,7 +413,7 @@ __global__ __launch_bounds__(256) void k_qr_chol(const float* G, float* Rinv, in
   float* Rb = Rinv + (int64_t)b * bc * bc;
   for (int idx = t; idx < bc * bc; idx += 256) {
     const int i = idx / bc, j = idx - i * bc;
-    Rb[idx] = j >= i ? (float)((double)X[i][j] / d[i]) : 0.f;
+    Rb[idx] = (j >= i && !dep[j]) ? (float)((double)X[i][j] / d[i]) : 0.f;
   }
 }
 
@@ -1112,10 +1126,11 @@ hipError_t qr_complete_launch(float* U, int64_t ldu, int64_t sU, int batch, int 
   LAUNCH_CHECK();
 }
 
-hipError_t qr_chol_launch(const float* G, float* Rinv, int batch, int bc, const int* qmask, hipStream_t st) {
+hipError_t qr_chol_launch(const float* G, float* Rinv, int batch, int bc, const int* qmask, int zero_dep,
+                          hipStream_t st) {
   if (batch <= 0) return hipSuccess;
   if (bc < 1 || bc > 64) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_qr_chol, dim3(batch), dim3(256), 0, st, G, Rinv, bc, qmask);
+  hipLaunchKernelGGL(k_qr_chol, dim3(batch), dim3(256), 0, st, G, Rinv, bc, qmask, zero_dep);
   LAUNCH_CHECK();
 }
 

@@ -44,7 +44,8 @@ hipError_t qr_complete_launch(float* U, int64_t ldu, int64_t sU, int batch, int 
 // block of bc <= 64 columns from its Gram matrix, the replacement of columns
 // without direction (sigma_j <= eps_qr sigma_1) and the eps_qr perturbation
 // of other deficient columns, and the mask (and count) of the flagged matrices
-hipError_t qr_chol_launch(const float* G, float* Rinv, int batch, int bc, const int* qmask, hipStream_t st);
+hipError_t qr_chol_launch(const float* G, float* Rinv, int batch, int bc, const int* qmask, int zero_dep,
+                          hipStream_t st);
 hipError_t qr_perturb_launch(float* U, int64_t ldu, int64_t sU, int batch, int m, int n, const float* S,
                              int64_t sS, const float* colnorm2, float eps_qr, const int* qmask, hipStream_t st);
 hipError_t qr_mask_launch(int batch, const int* flags, const int* mask, int* qmask, int* counter, hipStream_t st);

@@ -35,7 +35,8 @@ hipEvent_t get_event() {
 // the outermost one on a thread records
 thread_local int t_phase_depth = 0;
 
-ProfScope::ProfScope(int k, hipStream_t s, double work) : kind(k), st(s), slot(-1), phase(k >= PROF_PHASE_BOUND) {
+ProfScope::ProfScope(int k, hipStream_t s, double work)
+    : kind(k), st(s), slot(-1), phase(k >= PROF_PHASE_BOUND && k <= PROF_PHASE_QR) {
   if (phase && t_phase_depth++ > 0) return;
   std::lock_guard<std::mutex> lk(g_mu);
   if (!g_on) return;

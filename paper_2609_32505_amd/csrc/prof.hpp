@@ -18,7 +18,8 @@ enum ProfKind {
   PROF_PHASE_FALLBACK = 11, // conservative reruns of the bounded paths
   PROF_PHASE_BWD = 12,      // svd_polar_bwd / polar_bwd
   PROF_PHASE_QR = 13,       // QR preprocessing of tall matrices (Q, Q^T A, Q U_B)
-  PROF_KINDS = 14
+  PROF_JAC_VSWEEP = 14,     // Jacobi: once-per-sweep V update from the phases' rotations
+  PROF_KINDS = 15
 };
 
 // Brackets one launch with events when profiling is on; a no-op otherwise.

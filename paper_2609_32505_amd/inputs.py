@@ -105,6 +105,16 @@ def batch_with_spectra(seed: int, batch: int, m: int, n: int, spectrum_fn):
     return A, S
 
 
+def generating_factors(seed: int, index: int, m: int, n: int, spectrum_fn):
+    """(Q1, s, Q2) of matrix `index` of ``batch_with_spectra(seed, ...)``:
+    the same draws in the same order, FP64."""
+    rng = rng_for(seed, index)
+    s = np.asarray(spectrum_fn(rng), dtype=np.float64)
+    Q1 = orthonormal(rng, m, n)
+    Q2 = orthonormal(rng, n, n)
+    return Q1, s, Q2
+
+
 def single_64(seed: int = 1):
     """One 64 x 64 matrix, geometric spectrum from 1 to 1e-3."""
     return batch_with_spectra(seed, 1, 64, 64, lambda r: geometric(64, 1e3))

@@ -164,26 +164,54 @@ def test_square_512_batch256_both_paths(api, handle):
 
 
 def test_tall_4096x1024_batch16(api, handle):
+    """16 x 4096 x 1024, sigma log-uniform [1e-4, 1]: plain FP32 and learned
+    BF16, both with the QR preprocessing of tall matrices (the default) and
+    plain FP32 also on A itself.  Every matrix: sigma against the generating
+    spectrum (Weyl), reconstruction, orthogonality; U and V against the
+    generating Q1, Q2 on the columns whose singular value is separated from
+    its neighbours by 1e-2 s_1 (determined there to about the backward error
+    / 1e-2), after sign alignment."""
     import torch
     _say("16 x 4096 x 1024, sigma log-uniform [1e-4, 1]: learned BF16 and plain FP32")
     t0 = time.time()
     A, s = inputs.tall_loguniform(seed=3, batch=16)
     _say(f"  generated in {time.time() - t0:.1f}s")
+    spec = lambda r: inputs.log_uniform(r, 1024, 1e-4, 1.0)
+    fac = [inputs.generating_factors(3, i, 4096, 1024, spec) for i in (0, 7, 15)]
     Ad = torch.from_numpy(A).cuda()
     probe = torch.from_numpy(inputs.probe(14, 16, 1024)).cuda()
     slack = _weyl_slack(A, s)
-    for label, kw, tol_s in [("plain-fp32", {}, 1e-5), ("learned-bf16", dict(precision=1, bound=1, probe=probe), 1e-3)]:
+    for label, kw, tol_s, tol_rec, tol_uv in [
+            ("plain-fp32", {}, 1e-5, 1e-5, 1e-3),
+            ("plain-fp32-direct", dict(tall_qr=0), 1e-5, 1e-5, 1e-3),
+            ("learned-bf16", dict(precision=1, bound=1, probe=probe), 1e-3, 1e-4, 1e-2)]:
+        api.svd_fwd(Ad[:2], handle=handle, **kw)
+        torch.cuda.synchronize()
         t0 = time.time()
         U, S, V, info = api.svd_fwd(Ad, handle=handle, **kw)
         torch.cuda.synchronize()
+        dt = time.time() - t0
         inf = api.info_to_numpy(info)
         Sh = S.cpu().double().numpy()
         dev = (np.abs(Sh - s).max(axis=1) - slack) / s[:, 0]
-        _say(f"  {label}: {time.time() - t0:.2f}s, sigma deviation {dev.max():.2e}, iters {inf['iters'].max()}, "
+        _say(f"  {label}: {dt:.3f}s, sigma deviation {dev.max():.2e}, iters {inf['iters'].max()}, "
              f"sweeps {inf['sweeps'].max()}, flags {np.unique(inf['flags'])}")
         assert dev.max() < tol_s
-        assert not np.any(inf["flags"] & (16 | 32))
-        _gpu_checks(U, S, V, A, label, ORTH_TOL)
+        assert not np.any(inf["flags"] & (2 | 16 | 32))
+        rec = _gpu_checks(U, S, V, A, label, ORTH_TOL)
+        assert rec.max() < tol_rec
+        Uh, Vh = U.cpu().double().numpy(), V.cpu().double().numpy()
+        for (Q1, sg, Q2), i in zip(fac, (0, 7, 15)):
+            d = np.abs(np.diff(sg)) / sg[0]
+            sep = np.ones(len(sg), bool)
+            sep[:-1] &= d > 1e-2
+            sep[1:] &= d > 1e-2
+            al = np.sign(np.sum(Vh[i] * Q2, axis=0))
+            al[al == 0] = 1.0
+            eu = np.abs(Uh[i] * al - Q1)[:, sep].max()
+            ev = np.abs(Vh[i] * al - Q2)[:, sep].max()
+            _say(f"    matrix {i}: U vs Q1 {eu:.2e}, V vs Q2 {ev:.2e} on {int(sep.sum())} separated columns")
+            assert eu < tol_uv and ev < tol_uv
 
 
 def test_tall_low_rank_plus_noise(api, handle):
@@ -206,7 +234,9 @@ def test_tall_low_rank_plus_noise(api, handle):
         err = np.abs(Sph[i] - ref).max() / ref[0]
         _say(f"  sample {i}: plain vs LAPACK {err:.2e}; top-64 vs signal+noise {np.abs(ref[:64] - s_sig[i]).max():.2e}")
         assert err < 1e-5
-    _gpu_checks(Up, Sp, Vp, A, "plain-fp32", ORTH_TOL)
+    rec_p = _gpu_checks(Up, Sp, Vp, A, "plain-fp32", ORTH_TOL)
+    rec_l = _gpu_checks(U, S, V, A, "learned-bf16", ORTH_TOL)
+    assert rec_p.max() < 1e-5 and rec_l.max() < 1e-4
 
 
 def test_backward_256_batch64_clustered(api):
