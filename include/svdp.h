@@ -159,11 +159,12 @@ typedef struct {
   double pe_lo;            /* poly PE: lower end of the interval assumed to hold the singular
                               values of A / |A|_F (1e-3); values below it still converge, more
                               slowly, and the step count grows as it falls */
-  int32_t tall_qr;         /* svd_polar_fwd with m > n: 1 = QR preprocessing (the paper's
+  int32_t tall_qr;         /* svd_polar_fwd with m >= 2 n: 1 = QR preprocessing (the paper's
                               rectangular experiments): an orthonormal basis Q of A's columns
-                              by block Gram-Schmidt with CholeskyQR blocks, then the SVD of the
-                              n x n matrix B = Q^T A and U = Q U_B; 0 = CANS on A itself.
-                              Default 1 */
+                              by block Gram-Schmidt with CholeskyQR blocks (FP32 Grams: a
+                              64-column block of condition beyond about 1e7 loses its smallest
+                              directions; set 0 for such inputs), then the SVD of the n x n
+                              matrix B = Q^T A, U = Q U_B; 0 = CANS on A itself.  Default 1 */
 } svdp_params;
 
 /* per-matrix diagnostics, device array of `batch` records */

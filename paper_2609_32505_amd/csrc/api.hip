@@ -318,9 +318,14 @@ constexpr int kRefineExtra = 8;
 constexpr int kQrBlockedFrom = 512;
 constexpr int kQrBlock = 64;
 
+// QR preprocessing for matrices at least twice as tall as wide (below that
+// the QR costs about what it saves on the CANS steps)
+bool use_tall_qr(const svdp_params* p) { return p->tall_qr && p->m >= 2 * p->n; }
+
 struct FwdWs {
   float *X0, *X1, *G;
   void *Y0, *Y1;  // BF16 iterates (never aliasing the FP32 ones)
+  void *Yt0, *Yt1;  // their transposes (n x m, BF16): the Gram's operands, contiguous in k
   void* eigh;
   float *scale, *conv, *resid, *colsum, *rowmax, *fro2, *coef, *rcoef, *F, *aux, *mlpout, *nrm, *y0, *y1;
   float* qr;   // QR completion scratch: 2 m per matrix
@@ -340,6 +345,9 @@ FwdWs carve_fwd(void* base, const svdp_params* p, size_t* total) {
   w.X1 = c.take<float>(b * m * n);
   w.Y0 = c.take<uint16_t>(b * m * n);
   w.Y1 = c.take<uint16_t>(b * m * n);
+  const bool bf16 = p->precision == SVDP_PREC_BF16;
+  w.Yt0 = c.take<uint16_t>(bf16 ? b * m * n : 0);
+  w.Yt1 = c.take<uint16_t>(bf16 ? b * m * n : 0);
   w.G = c.take<float>(b * n * n);
   w.eigh = c.take_bytes(eigh_ws_bytes(b, n, p->max_sweeps));
   w.scale = c.take<float>(b);
@@ -357,7 +365,7 @@ FwdWs carve_fwd(void* base, const svdp_params* p, size_t* total) {
   w.y0 = c.take<float>(b * m);
   w.y1 = c.take<float>(b * m);
   w.qr = c.take<float>(b * 2 * m);
-  const bool tall_qr = p->tall_qr && m > n;
+  const bool tall_qr = use_tall_qr(p);
   const bool blocked_qr = n > (size_t)kQrBlockedFrom || tall_qr;
   w.qrc = c.take<float>(blocked_qr ? b * n * kQrBlock : 0);
   w.qrg = c.take<float>(blocked_qr ? b * kQrBlock * kQrBlock : 0);
@@ -410,22 +418,33 @@ svdp_status read_counter(Ctx& c, const int* dev, int* out) {
 // One CANS step on buffers (Xc -> Xn): G = Xc^T Xc, Xn = alpha Xc + beta Xc G.
 // With ksched, matrix b takes part only if its step kidx has category kcat
 // (sched_cat over the per-matrix counts (K, K1)).
+// Xtc / Xtn: the BF16 transposes of Xc / Xn (n x m) when the iterates are
+// BF16: the Gram reads Xc^T from Xtc with both operands contiguous in k, and
+// the update writes Xn^T beside Xn.
 hipError_t cans_step(Ctx& c, int prec, const void* Xc, void* Xn, int in_bf16, int out_bf16,
                      const float* coef, int64_t coef_bstride, int kidx, const int* active,
                      float* conv, int n_active = 0, const int* ksched = nullptr, int kcat = 0,
-                     int kbf16 = 0) {
+                     int kbf16 = 0, const void* Xtc = nullptr, void* Xtn = nullptr) {
   const int m = c.m, n = c.n, B = c.batch;
   GemmArgs g = gemm_base(n, n, m, B);
   g.work_batch = n_active;
-  g.A = Xc; g.lda = n; g.sA = (int64_t)m * n;
-  g.B = Xc; g.ldb = n; g.sB = (int64_t)m * n;
   g.C = c.w.G; g.ldc = n; g.sC = (int64_t)n * n;
   g.sym = 1;
   g.active = active;
   g.ksched = ksched; g.kstep = kidx; g.kcat = kcat; g.kbf16 = kbf16;
   g.in_bf16 = in_bf16;
   g.out_bf16 = prec == PREC_BF16 ? 1 : 0;
-  hipError_t e = gemm_launch(g, prec, 1, 0, c.st);
+  hipError_t e;
+  if (in_bf16 && Xtc) {
+    // G = (X^T)(X^T)^T: op(A) = X^T stored n x m, op(B) = X stored as X^T
+    g.A = Xtc; g.lda = m; g.sA = (int64_t)m * n;
+    g.B = Xtc; g.ldb = m; g.sB = (int64_t)m * n;
+    e = gemm_launch(g, prec, 0, 1, c.st);
+  } else {
+    g.A = Xc; g.lda = n; g.sA = (int64_t)m * n;
+    g.B = Xc; g.ldb = n; g.sB = (int64_t)m * n;
+    e = gemm_launch(g, prec, 1, 0, c.st);
+  }
   if (e) return e;
   GemmArgs u = gemm_base(m, n, n, B);
   u.A = Xc; u.lda = n; u.sA = (int64_t)m * n;
@@ -440,6 +459,7 @@ hipError_t cans_step(Ctx& c, int prec, const void* Xc, void* Xn, int in_bf16, in
   u.conv = conv;
   u.in_bf16 = in_bf16;
   u.out_bf16 = out_bf16;
+  if (out_bf16 && Xtn) { u.Ct = Xtn; u.ldct = m; u.sCt = (int64_t)m * n; }
   return gemm_launch(u, prec, 0, prec == PREC_BF16 ? 1 : 0, c.st);
 }
 
@@ -600,6 +620,7 @@ svdp_status bounded(Ctx& c) {
   if (n_bf_start > 0) {
     HIPCHK(sched_mask_launch(B, w.ksteps, bf16, 1, w.gmask, c.st), "bf16 start");
     HIPCHK(scale_copy_launch(c.A, c.lda, c.sA, B, m, n, w.scale, w.Y0, 1, w.gmask, c.st), "normalise");
+    HIPCHK(transpose_bf16_launch(w.Y0, B, m, n, w.Yt0, w.gmask, c.st), "transpose");
   }
   phase.next(PROF_PHASE_CANS);
   for (int k = 0; k < kmax; ++k)
@@ -609,8 +630,10 @@ svdp_status bounded(Ctx& c) {
       const int in_bf = cat >= 2, out_bf = cat == 1 || cat == 2;
       const void* Xc = in_bf ? ((k & 1) ? w.Y1 : w.Y0) : (const void*)((k & 1) ? w.X1 : w.X0);
       void* Xn = out_bf ? (((k + 1) & 1) ? w.Y1 : w.Y0) : (void*)(((k + 1) & 1) ? w.X1 : w.X0);
+      const void* Xtc = in_bf ? ((k & 1) ? w.Yt1 : w.Yt0) : nullptr;
+      void* Xtn = out_bf ? (((k + 1) & 1) ? w.Yt1 : w.Yt0) : nullptr;
       HIPCHK(cans_step(c, in_bf ? PREC_BF16 : PREC_F32, Xc, Xn, in_bf, out_bf, w.coef, kcap, k, nullptr, nullptr,
-                       count, w.ksteps, cat, bf16), "cans step");
+                       count, w.ksteps, cat, bf16, Xtc, Xtn), "cans step");
     }
   // the last iterate of a matrix with K odd is in X1: move it to X0
   HIPCHK(sched_mask_launch(B, w.ksteps, bf16, 2, w.gmask, c.st), "odd mask");
@@ -1097,7 +1120,7 @@ svdp_status svd_polar_fwd(svdp_handle* h, const svdp_params* p, const float* A, 
   carve_fwd(nullptr, p, &need);
   if (!ws || ws_bytes < need) return fail(SVDP_ERR_WORKSPACE, "workspace too small");
   Ctx c{h, p, carve_fwd(ws, p, nullptr), (hipStream_t)stream, (int)p->batch, (int)p->m, (int)p->n, A, lda, sA};
-  if (p->tall_qr && p->m > p->n) {
+  if (use_tall_qr(p)) {
     if ((s = svd_tall_qr(c, U, ldu, sU, S, sS, V, ldv, sV))) return s;
   } else if ((s = svd_core(c, U, ldu, sU, S, sS, V, ldv, sV))) {
     return s;

@@ -39,6 +39,7 @@ struct GemmArgs {
   int sym;             // output symmetric: upper tiles computed, mirrored
   int work_batch;      // matrices actually computed (for work accounting; 0 = batch)
   int out_bf16, in_bf16, cin_bf16;
+  void* Ct; int64_t ldct, sCt;  // out_bf16: also write the output transposed, Ct[j, i] (BF16)
 };
 
 enum { PREC_F32 = 0, PREC_BF16 = 1 };

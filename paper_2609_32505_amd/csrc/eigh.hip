@@ -547,22 +547,26 @@ __global__ __launch_bounds__(256) void k_jac_apply(EighWs e, EighPhase ph) {
 // Deferred V update: V[slab, :] <- V[slab, :] M_1 M_2 ... M_P with the group
 // rotations of every phase of the sweep (block diagonal in that phase's
 // grouping, one 64 x 64 orthogonal M per group of four blocks).  One
-// workgroup (four wavefronts) per slab of R rows of one matrix; the slab
-// (R x NP FP32, row pitch NP + 1 so that the 32 rows an MFMA operand reads
-// start in 32 different banks) stays in LDS for the whole sweep, and each
-// phase's rotations are read from L2 straight into MFMA operand registers.
-// Per phase the R x 64 block of each group is multiplied by its M: (R / 32)
-// x ng x 2 output blocks of 32 x 32, dealt to the four waves; each wave keeps
-// its blocks' accumulators until every wave has read the phase's input (one
-// barrier), then writes them back (another).  Matrices that were not active
-// in the sweep are skipped (their rotation slots hold an earlier sweep's).
-template <int R, int NP>
-__global__ __launch_bounds__(256) void k_jac_vsweep(EighWs e) {
+// workgroup of eight wavefronts per slab of R rows of one matrix (R = 64 up
+// to NP = 512, 32 at NP = 1024: the slab takes about 128 KB of LDS); the
+// slab (row pitch NP + 1, so that the 32 rows an MFMA operand reads start in
+// 32 different banks) stays in LDS for the whole sweep, and the rotations
+// are read from L2 straight into MFMA operand registers.  A phase runs over
+// sets of GPS groups (groups touch disjoint columns): wave w takes the
+// column half w % 2 of group w / 2 of the set, i.e. a 64 x 32 slice of that
+// group's M, and multiplies every 32-row block of the slab by it (R / 32
+// independent MFMA chains on the same operands); all waves have read the
+// set's input columns at the first barrier and written their outputs at the
+// second.  The next set's slice is loaded during the current set's MFMAs.
+// Matrices that were not active in the sweep are skipped (their rotation
+// slots hold an earlier sweep's).
+template <int NP, int R>
+__global__ __launch_bounds__(512) void k_jac_vsweep(EighWs e) {
   constexpr int PITCH = NP + 1;
-  constexpr int NBK = NP / BS, NG = NBK / 4;
-  constexpr int NBLK = (R / 32) * NG * 2;
-  constexpr int BPW = NBLK / 4;
-  static_assert(NBLK % 4 == 0 && BPW >= 1, "output blocks must split over four waves");
+  constexpr int NBK = NP / BS, NG = NBK / 4, NPH = NBK / 2;
+  constexpr int GPS = NG < 4 ? NG : 4;  // groups per set: 2 GPS <= 8 slices, one per wave
+  constexpr int NSET = NG / GPS;
+  constexpr int RB = R / 32;            // 32-row blocks of the slab
   constexpr int SLABS = NP / R;
   __shared__ float Vs[R * PITCH];
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
@@ -573,7 +577,7 @@ __global__ __launch_bounds__(256) void k_jac_vsweep(EighWs e) {
   if (b >= e.batch) return;
   if (e.active && !e.active[b]) return;
   float* V = e.Vw + (int64_t)b * NP * NP + (int64_t)slab * R * NP;
-  for (int idx = t; idx < R * NP / 4; idx += 256) {
+  for (int idx = t; idx < R * NP / 4; idx += 512) {
     const int r = idx / (NP / 4), c = (idx - r * (NP / 4)) * 4;
     const f4v v = *(const f4v*)(V + (int64_t)r * NP + c);
 #pragma unroll
@@ -581,38 +585,54 @@ __global__ __launch_bounds__(256) void k_jac_vsweep(EighWs e) {
   }
   __syncthreads();
   const int kh = lane >> 5, ic = lane & 31;
-  for (int p = 0; p < NBK / 2; ++p) {
+  const bool busy = w < 2 * GPS;  // waves beyond the set's slices idle (NG < 4)
+  const int ch = w & 1;
+  float cur[32], nxt[32];
+  auto load_slice = [&](int p, int set, float (&bm)[32]) {
+    if (!busy) return;
+    const int G = set * GPS + (w >> 1);
+    load_mcol(qslot(e, b, p) + (int64_t)G * QSTRIDE, 32 * ch, lane, bm);
+  };
+  load_slice(0, 0, cur);
+  for (int p = 0; p < NPH; ++p) {
     const EighPhase ph = eigh_phase(p);
-    const float* Q = qslot(e, b, p);
-    f16v acc[BPW];
+    for (int set = 0; set < NSET; ++set) {
+      if (set + 1 < NSET) load_slice(p, set + 1, nxt);
+      else if (p + 1 < NPH) load_slice(p + 1, 0, nxt);
+      f16v acc[RB];
 #pragma unroll
-    for (int j = 0; j < BPW; ++j) {
-      const int bi = w + 4 * j, ch = bi & 1, G = (bi >> 1) % NG, rb = (bi >> 1) / NG;
+      for (int rb = 0; rb < RB; ++rb) acc[rb] = zero16();
       int gm[4];
-      group_members(ph, G, gm);
-      float bm[32];
-      load_mcol(Q + (int64_t)G * QSTRIDE, 32 * ch, lane, bm);
-      const float* row = Vs + (32 * rb + ic) * PITCH;
-      f16v a = zero16();
+      group_members(ph, set * GPS + (w >> 1), gm);
+      if (busy) {
 #pragma unroll
-      for (int s2 = 0; s2 < 32; ++s2) a = mfma(row[16 * gm[s2 >> 3] + 2 * (s2 & 7) + kh], bm[s2], a);
-      acc[j] = a;
+        for (int s2 = 0; s2 < 32; ++s2) {
+          const int col = 16 * gm[s2 >> 3] + 2 * (s2 & 7) + kh;
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb) acc[rb] = mfma(Vs[(32 * rb + ic) * PITCH + col], cur[s2], acc[rb]);
+        }
+      }
+      __syncthreads();
+      if (busy) {
+        // member block of the output column 32 ch + ic (selected, not indexed:
+        // gm stays in registers)
+        const int mb = 2 * ch + (ic >> 4);
+        const int gsel = mb == 0 ? gm[0] : (mb == 1 ? gm[1] : (mb == 2 ? gm[2] : gm[3]));
+        const int col = 16 * gsel + (ic & 15);
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+          for (int g4 = 0; g4 < 4; ++g4)
+#pragma unroll
+            for (int r4 = 0; r4 < 4; ++r4)
+              Vs[(32 * rb + 8 * g4 + 4 * kh + r4) * PITCH + col] = acc[rb][4 * g4 + r4];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < 32; ++k) cur[k] = nxt[k];
     }
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < BPW; ++j) {
-      const int bi = w + 4 * j, ch = bi & 1, G = (bi >> 1) % NG, rb = (bi >> 1) / NG;
-      int gm[4];
-      group_members(ph, G, gm);
-      const int col = 16 * gm[2 * ch + (ic >> 4)] + (ic & 15);
-#pragma unroll
-      for (int g4 = 0; g4 < 4; ++g4)
-#pragma unroll
-        for (int r4 = 0; r4 < 4; ++r4) Vs[(32 * rb + 8 * g4 + 4 * kh + r4) * PITCH + col] = acc[j][4 * g4 + r4];
-    }
-    __syncthreads();
   }
-  for (int idx = t; idx < R * NP / 4; idx += 256) {
+  for (int idx = t; idx < R * NP / 4; idx += 512) {
     const int r = idx / (NP / 4), c = (idx - r * (NP / 4)) * 4;
     f4v v;
 #pragma unroll
@@ -959,11 +979,11 @@ static hipError_t vsweep_launch(const EighWs& E, double work, hipStream_t st) {
   ProfScope ps(PROF_JAC_VSWEEP, st, work);
   const unsigned groups8 = (unsigned)cdiv(E.batch, 8) * 8;
   switch (E.np) {
-    case 64: hipLaunchKernelGGL((k_jac_vsweep<64, 64>), dim3(groups8 * 1), dim3(256), 0, st, E); break;
-    case 128: hipLaunchKernelGGL((k_jac_vsweep<64, 128>), dim3(groups8 * 2), dim3(256), 0, st, E); break;
-    case 256: hipLaunchKernelGGL((k_jac_vsweep<64, 256>), dim3(groups8 * 4), dim3(256), 0, st, E); break;
-    case 512: hipLaunchKernelGGL((k_jac_vsweep<64, 512>), dim3(groups8 * 8), dim3(256), 0, st, E); break;
-    case 1024: hipLaunchKernelGGL((k_jac_vsweep<32, 1024>), dim3(groups8 * 32), dim3(256), 0, st, E); break;
+    case 64: hipLaunchKernelGGL((k_jac_vsweep<64, 64>), dim3(groups8 * 1), dim3(512), 0, st, E); break;
+    case 128: hipLaunchKernelGGL((k_jac_vsweep<128, 64>), dim3(groups8 * 2), dim3(512), 0, st, E); break;
+    case 256: hipLaunchKernelGGL((k_jac_vsweep<256, 64>), dim3(groups8 * 4), dim3(512), 0, st, E); break;
+    case 512: hipLaunchKernelGGL((k_jac_vsweep<512, 64>), dim3(groups8 * 8), dim3(512), 0, st, E); break;
+    case 1024: hipLaunchKernelGGL((k_jac_vsweep<1024, 32>), dim3(groups8 * 32), dim3(512), 0, st, E); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -66,6 +66,7 @@ SVDP_DEV void epilogue(const GemmArgs& g, int b, int rowbase, int colbase, int t
   const float* csi = g.colscale_in ? g.colscale_in + b * g.csin_stride : nullptr;
   const char* cin = g.Cin ? (const char*)g.Cin + b * g.sCin * (g.cin_bf16 ? 2 : 4) : nullptr;
   char* out = (char*)g.C + b * g.sC * (g.out_bf16 ? 2 : 4);
+  bf16_t* outt = g.Ct ? (bf16_t*)g.Ct + b * g.sCt : nullptr;
   float d2 = 0.f, o2 = 0.f;
   const bool mirror = g.sym && tm != tn;
 #pragma unroll
@@ -77,10 +78,13 @@ SVDP_DEV void epilogue(const GemmArgs& g, int b, int rowbase, int colbase, int t
       const float csj = cs ? cs[j] : 1.f;
       const float csij = csi ? csi[j] : 1.f;
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
+      for (int q = 0; q < 4; ++q) {
+        const int i0 = rowbase + mi * 32 + 8 * q + 4 * (lane >> 5);
+        bf16_t tv[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int i = rowbase + mi * 32 + 8 * q + 4 * (lane >> 5) + r;
+          const int i = i0 + r;
+          tv[r] = f2bf(0.f);
           if (i >= g.M) continue;
           float v = s_acc * acc[mi][ni][4 * q + r] * csj;
           if (cin) {
@@ -90,13 +94,28 @@ SVDP_DEV void epilogue(const GemmArgs& g, int b, int rowbase, int colbase, int t
           }
           o2 += v * v;
           if (g.out_bf16) {
-            ((bf16_t*)out)[(int64_t)i * g.ldc + j] = f2bf(v);
-            if (mirror) ((bf16_t*)out)[(int64_t)j * g.ldc + i] = f2bf(v);
+            const bf16_t h = f2bf(v);
+            tv[r] = h;
+            ((bf16_t*)out)[(int64_t)i * g.ldc + j] = h;
+            if (mirror) ((bf16_t*)out)[(int64_t)j * g.ldc + i] = h;
           } else {
             ((float*)out)[(int64_t)i * g.ldc + j] = v;
             if (mirror) ((float*)out)[(int64_t)j * g.ldc + i] = v;
           }
         }
+        // the transposed copy: rows i0 .. i0 + 3 of column j are consecutive
+        // in row j of Ct, one 8-byte store when all four are inside
+        if (outt) {
+          bf16_t* dst = outt + (int64_t)j * g.ldct + i0;
+          if (i0 + 3 < g.M && (g.ldct & 3) == 0) {
+            typedef __bf16 bf4v __attribute__((ext_vector_type(4)));
+            bf4v pk = {tv[0], tv[1], tv[2], tv[3]};
+            *(bf4v*)dst = pk;
+          } else {
+            for (int r = 0; r < 4 && i0 + r < g.M; ++r) dst[r] = tv[r];
+          }
+        }
+      }
     }
   if (g.conv) {
 #pragma unroll

@@ -342,14 +342,15 @@ __global__ void k_qr_mask(int batch, const int* flags, const int* mask, int* qma
 }
 
 // CholeskyQR step of one block of bc <= 64 columns Z (flagged matrices):
-// G = Z^T Z (bc x bc, row-major, per matrix bc * bc floats) -> Rinv with
+// G = Z^T Z (bc x bc, row-major with leading dimension bc, matrices 64 * 64
+// floats apart) -> Rinv (same layout) with
 // Z Rinv orthonormal.  With D = diag(G)^(1/2) and G' = D^-1 G D^-1 = R'^T R'
 // (Cholesky, upper R', FP64 in LDS), Z = Q R' D, so Rinv = D^-1 R'^-1, upper
 // triangular with a positive diagonal (R_ii > 0).  Column scales are kept
 // >= 1e-15 of the largest and pivots (of the unit-diagonal G') >= 1e-12, so
 // a (numerically) dependent block gives large but finite factors.  With
-// zero_dep, a column whose pivot is <= 1e-10 (its angle to the block's
-// earlier columns below 1e-5: dependent to FP32 resolution) is dropped
+// zero_dep, a column whose pivot is <= 1e-13 (its angle to the block's
+// earlier columns below 3e-7: dependent to FP32 resolution) is dropped
 // instead: its row of R' is taken as e_k (no trailing update) and its column
 // of Rinv as zero, so Z Rinv has a zero column there and the other columns
 // stay orthonormal and independent of it.
@@ -361,7 +362,8 @@ __global__ __launch_bounds__(256) void k_qr_chol(const float* G, float* Rinv, in
   __shared__ float X[64][65];  // R'^-1
   __shared__ double d[64];
   const int t = threadIdx.x;
-  const float* Gb = G + (int64_t)b * bc * bc;
+  // per-matrix stride 64 x 64 whatever bc (the layout of the block GEMMs)
+  const float* Gb = G + (int64_t)b * 64 * 64;
   __shared__ double gmax;
   if (t == 0) {
     double mx = 0.0;
@@ -383,7 +385,7 @@ __global__ __launch_bounds__(256) void k_qr_chol(const float* G, float* Rinv, in
   for (int k = 0; k < bc; ++k) {
     if (t == 0) {
       const double piv = A[k][k];
-      if (zero_dep && !(piv > 1e-10)) {
+      if (zero_dep && !(piv > 1e-13)) {
         dep[k] = 1;
         A[k][k] = 1.0;
       } else {
@@ -410,7 +412,7 @@ __global__ __launch_bounds__(256) void k_qr_chol(const float* G, float* Rinv, in
     }
   }
   __syncthreads();
-  float* Rb = Rinv + (int64_t)b * bc * bc;
+  float* Rb = Rinv + (int64_t)b * 64 * 64;
   for (int idx = t; idx < bc * bc; idx += 256) {
     const int i = idx / bc, j = idx - i * bc;
     Rb[idx] = (j >= i && !dep[j]) ? (float)((double)X[i][j] / d[i]) : 0.f;
@@ -549,6 +551,25 @@ __global__ void k_polar_gather(const float* T, int ldt, int64_t sT, const int* p
     for (int j = threadIdx.x; j < n; j += blockDim.x) Pb[(int64_t)i * n + j] = trow[pb[j]];
     if (threadIdx.x == 0) dP[(int64_t)b * n + i] = trow[pb[i]];
     __syncthreads();
+  }
+}
+
+// Xt = X^T per matrix (X m x n BF16 contiguous, Xt n x m), 32 x 32 tiles
+// through LDS; matrices outside mask are skipped
+__global__ void k_transpose_bf16(const bf16_t* X, int m, int n, bf16_t* Xt, const int* mask) {
+  __shared__ bf16_t tile[32][34];
+  const int b = blockIdx.z;
+  if (mask && !mask[b]) return;
+  const int64_t off = (int64_t)b * m * n;
+  const int i0 = blockIdx.y * 32, j0 = blockIdx.x * 32;
+  for (int r = threadIdx.y; r < 32; r += blockDim.y) {
+    const int i = i0 + r, j = j0 + threadIdx.x;
+    if (i < m && j < n) tile[r][threadIdx.x] = X[off + (int64_t)i * n + j];
+  }
+  __syncthreads();
+  for (int r = threadIdx.y; r < 32; r += blockDim.y) {
+    const int j = j0 + r, i = i0 + threadIdx.x;  // Xt[j][i] = X[i][j]
+    if (i < m && j < n) Xt[off + (int64_t)j * m + i] = tile[threadIdx.x][r];
   }
 }
 
@@ -1057,6 +1078,14 @@ hipError_t norms_launch(const float* A, int64_t lda, int64_t sA, int batch, int 
   hipLaunchKernelGGL(k_colsums, dim3(cdiv(n, 256), cdiv(m, rows_per), batch), dim3(256), 0, st, A, lda,
                      sA, m, n, rows_per, colsum, mask);
   LAUNCH_CHECK();
+}
+
+hipError_t transpose_bf16_launch(const void* X, int batch, int m, int n, void* Xt, const int* mask,
+                                 hipStream_t st) {
+  if (batch <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_transpose_bf16, dim3(cdiv(n, 32), cdiv(m, 32), batch), dim3(32, 8), 0, st,
+                     (const bf16_t*)X, m, n, (bf16_t*)Xt, mask);
+  return hipGetLastError();
 }
 
 hipError_t fro_scale_launch(const float* fro2, int batch, float* scale, const int* mask, hipStream_t st) {

@@ -9,6 +9,8 @@ hipError_t norms_launch(const float* A, int64_t lda, int64_t sA, int batch, int 
                         float* colsum, float* rowmax, float* fro2, int* flags,
                         const int* mask, hipStream_t st);
 // scale[b] = sqrt(max_j colsum[b, j] * rowmax[b]) (1 for a zero matrix)
+hipError_t transpose_bf16_launch(const void* X, int batch, int m, int n, void* Xt, const int* mask,
+                                 hipStream_t st);
 hipError_t fro_scale_launch(const float* fro2, int batch, float* scale, const int* mask, hipStream_t st);
 hipError_t ns_scale_launch(const float* colsum, const float* rowmax, int batch, int n,
                            float* scale, const int* mask, hipStream_t st);
