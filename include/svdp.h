@@ -19,10 +19,14 @@
  *     call: scratch comes from the caller's workspace `ws` of `ws_bytes`
  *     bytes, sized by svdp_workspace_size() (alignment 256 bytes).
  *   - Work is enqueued on `stream` (a hipStream_t passed as void*; null =
- *     the default stream).  Calls return after enqueueing, except that the
- *     forward passes read a few device counters back to the host (iteration
- *     control of CANS and Jacobi, eigensolver restarts, the blocked QR step),
- *     which synchronises `stream`.
+ *     the default stream).  Calls return after enqueueing: the iteration
+ *     control of CANS, of the bounded schedule and refinement, of the Jacobi
+ *     sweeps and of the eigensolver restarts runs on the device (fixed
+ *     budgets of launches whose workgroups skip converged matrices).  Two
+ *     forward steps read a device count back, which synchronises `stream`:
+ *     the bounded paths' fallback test (learned / user bounds), and the QR
+ *     step of Algorithm 1 when it runs blocked (n > 512); svdp_host_syncs()
+ *     counts them.
  *   - Errors: arguments are checked before anything is launched; a non-OK
  *     status means no work was enqueued, except SVDP_ERR_HIP, which reports
  *     a failed launch or copy (svdp_last_error() gives the HIP message).
@@ -206,6 +210,10 @@ svdp_status svdp_workspace_size(const svdp_params* p, int32_t op, size_t* bytes)
 const char* svdp_status_string(svdp_status s);
 /* message of the last failing call on this thread (static storage) */
 const char* svdp_last_error(void);
+
+/* Number of host synchronisations the library has made so far (all
+ * threads): each is one device count read back by a forward pass. */
+int64_t svdp_host_syncs(void);
 
 /* Forward SVD A = U diag(S) V^T (Algorithm 1).
  * A: m x n.  U: m x n.  S: n values, descending.  V: n x n (V, not V^T).

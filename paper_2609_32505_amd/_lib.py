@@ -62,6 +62,7 @@ SIGNATURES = {
     "svdp_workspace_size": (c_i32, [ctypes.POINTER(Params), c_i32, ctypes.POINTER(c_sz)]),
     "svdp_status_string": (ctypes.c_char_p, [c_i32]),
     "svdp_last_error": (ctypes.c_char_p, []),
+    "svdp_host_syncs": (c_i64, []),
     "svd_polar_fwd": (c_i32, [c_vp, ctypes.POINTER(Params), c_vp, c_i64, c_i64, c_vp, c_i64, c_i64,
                               c_vp, c_i64, c_vp, c_i64, c_i64, c_vp, c_vp, c_sz, c_vp]),
     "svd_polar_bwd": (c_i32, [c_vp, ctypes.POINTER(Params), c_vp, c_i64, c_i64, c_vp, c_i64,

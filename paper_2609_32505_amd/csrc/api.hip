@@ -2,6 +2,7 @@
 // orchestration of the kernels (no arithmetic of the method runs on the host
 // except the scalar CANS coefficient recursion).
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -93,6 +94,22 @@ void table_conservative(double delta, int pre, int steps, double* tab, double* t
   b = 1.0 + delta;
   for (; k < steps; ++k) cans_poly(a, b, tab[2 * k], tab[2 * k + 1], a, b);
   if (t_out) *t_out = t;
+}
+
+// The bound kernel clamps the interval's lower end at this value (a singular
+// value below 1e-9 of the largest is not resolved in FP32 anyway: such a
+// matrix misses the refinement's stop test and falls back).
+constexpr double kLoFloor = 1e-9;
+
+// Steps of the interval recursion from [kLoFloor, 1] until its error is
+// <= handoff: an upper bound of every matrix's K in the bounded schedule.
+int bounded_budget(double handoff) {
+  double a = kLoFloor, b = 1.0, al, be;
+  for (int k = 0; k < 64; ++k) {
+    cans_poly(a, b, al, be, a, b);
+    if (std::max(1.0 - a, b - 1.0) <= handoff) return k + 1;
+  }
+  return 64;
 }
 
 void table_interval(double lo, int steps, double* tab) {
@@ -408,9 +425,15 @@ struct Ctx {
   int64_t lda, sA;
 };
 
+// Host synchronisations made by the library (svdp_host_syncs): the
+// forward passes read a device count back only for the bounded paths'
+// fallback test and the blocked QR step (n > 512).
+std::atomic<int64_t> g_host_syncs{0};
+
 svdp_status read_counter(Ctx& c, const int* dev, int* out) {
   HIPCHK(hipMemcpyAsync(c.h->host_word, dev, sizeof(int), hipMemcpyDeviceToHost, c.st), "counter copy");
   HIPCHK(hipStreamSynchronize(c.st), "counter sync");
+  g_host_syncs.fetch_add(1);
   *out = *c.h->host_word;
   return SVDP_OK;
 }
@@ -418,20 +441,22 @@ svdp_status read_counter(Ctx& c, const int* dev, int* out) {
 // One CANS step on buffers (Xc -> Xn): G = Xc^T Xc, Xn = alpha Xc + beta Xc G.
 // With ksched, matrix b takes part only if its step kidx has category kcat
 // (sched_cat over the per-matrix counts (K, K1)).
-// Xtc / Xtn: the BF16 transposes of Xc / Xn (n x m) when the iterates are
-// BF16: the Gram reads Xc^T from Xtc with both operands contiguous in k, and
-// the update writes Xn^T beside Xn.
+// One CANS step on buffers (Xc -> Xn): G = Xc^T Xc, Xn = alpha Xc + beta Xc G.
+// With ksched (the bounded schedule), matrix b takes part only if the
+// category of its step kidx is in kcatmask, and its output goes to Xn_bf
+// (BF16, with its transpose in Xtn) when that category's bit is set in
+// obf_catmask, else to Xn.  Xtc: the BF16 transpose of a BF16 Xc (n x m),
+// from which the Gram reads both operands contiguous in k.
 hipError_t cans_step(Ctx& c, int prec, const void* Xc, void* Xn, int in_bf16, int out_bf16,
                      const float* coef, int64_t coef_bstride, int kidx, const int* active,
-                     float* conv, int n_active = 0, const int* ksched = nullptr, int kcat = 0,
-                     int kbf16 = 0, const void* Xtc = nullptr, void* Xtn = nullptr) {
+                     float* conv, const int* ksched = nullptr, int kcatmask = 0, int obf_catmask = 0,
+                     int kbf16 = 0, const void* Xtc = nullptr, void* Xn_bf = nullptr, void* Xtn = nullptr) {
   const int m = c.m, n = c.n, B = c.batch;
   GemmArgs g = gemm_base(n, n, m, B);
-  g.work_batch = n_active;
   g.C = c.w.G; g.ldc = n; g.sC = (int64_t)n * n;
   g.sym = 1;
   g.active = active;
-  g.ksched = ksched; g.kstep = kidx; g.kcat = kcat; g.kbf16 = kbf16;
+  g.ksched = ksched; g.kstep = kidx; g.kcatmask = kcatmask; g.kbf16 = kbf16;
   g.in_bf16 = in_bf16;
   g.out_bf16 = prec == PREC_BF16 ? 1 : 0;
   hipError_t e;
@@ -454,12 +479,12 @@ hipError_t cans_step(Ctx& c, int prec, const void* Xc, void* Xn, int in_bf16, in
   u.Cin = Xc; u.ldcin = n; u.sCin = (int64_t)m * n; u.cin_bf16 = in_bf16;
   u.coef = coef; u.coef_bstride = coef_bstride; u.coef_idx = kidx;
   u.active = active;
-  u.ksched = ksched; u.kstep = kidx; u.kcat = kcat; u.kbf16 = kbf16;
-  u.work_batch = n_active;
+  u.ksched = ksched; u.kstep = kidx; u.kcatmask = kcatmask; u.kbf16 = kbf16;
+  u.obf_catmask = obf_catmask; u.C_bf = Xn_bf;
   u.conv = conv;
   u.in_bf16 = in_bf16;
   u.out_bf16 = out_bf16;
-  if (out_bf16 && Xtn) { u.Ct = Xtn; u.ldct = m; u.sCt = (int64_t)m * n; }
+  if (Xtn) { u.Ct = Xtn; u.ldct = m; u.sCt = (int64_t)m * n; }
   return gemm_launch(u, prec, 0, prec == PREC_BF16 ? 1 : 0, c.st);
 }
 
@@ -539,31 +564,22 @@ svdp_status conservative_fp32(Ctx& c, const int* mask) {
   else HIPCHK(fill_i32(w.active, 1, B, c.st), "active");
   HIPCHK(fill_masked_launch(w.where, 0, B, mask, c.st), "where");
   HIPCHK(fill_f32(w.conv, 0.f, 2 * B, c.st), "conv");
-  int remaining = B;
-  if (mask) {
-    HIPCHK(count_mask_launch(B, mask, w.counter, c.st), "count");
-    svdp_status s0 = read_counter(c, w.counter, &remaining);
-    if (s0) return s0;
-  }
+  // The full budget of max_iters steps is enqueued without reading anything
+  // back: a matrix leaves the active set on the device at its stop test, and
+  // the later steps' workgroups of that matrix exit at once.
   for (int k = 0; k < p->max_iters; ++k) {
     const float* Xc = (k & 1) ? w.X1 : w.X0;
     float* Xn = (k & 1) ? w.X0 : w.X1;
     if (p->poly == SVDP_POLY_CANS5)
-      HIPCHK(cans5_step(c, Xc, Xn, tab3 + 3 * k, w.active, w.conv, remaining), "cans5 step");
+      HIPCHK(cans5_step(c, Xc, Xn, tab3 + 3 * k, w.active, w.conv, 0), "cans5 step");
     else
-      HIPCHK(cans_step(c, PREC_F32, Xc, Xn, 0, 0, w.coef, 0, k, w.active, w.conv, remaining), "cans step");
+      HIPCHK(cans_step(c, PREC_F32, Xc, Xn, 0, 0, w.coef, 0, k, w.active, w.conv), "cans step");
     HIPCHK(cans_check_launch(B, w.conv, (float)p->tol, k, w.active, w.where, w.iters, nullptr, 0, w.flags,
                              w.counter, c.st),
            "cans check");
-    // poll the device for stragglers once the schedule can have converged
-    if (k >= p->pre_iters + 4 || k == p->max_iters - 1) {
-      svdp_status s = read_counter(c, w.counter, &remaining);
-      if (s) return s;
-      if (remaining == 0) break;
-    }
   }
-  if (remaining > 0)
-    HIPCHK(or_flags_launch(B, w.flags, SVDP_FLAG_NOT_CONVERGED, w.active, c.st), "flags");
+  // still active after max_iters: not converged
+  HIPCHK(or_flags_launch(B, w.flags, SVDP_FLAG_NOT_CONVERGED, w.active, c.st), "flags");
   return SVDP_OK;
 }
 
@@ -608,33 +624,34 @@ svdp_status bounded(Ctx& c) {
   // BF16 out); the GEMMs skip the matrices of other categories.  The
   // iterate after step k lives in X[k % 2] (FP32) or Y[k % 2] (BF16).  The
   // host reads the per-step category counts (one synchronisation).
+  // No read-back: the host enqueues a budget of steps that covers every
+  // matrix's K -- the number of steps from the smallest interval the bound
+  // kernel produces (kLoFloor) to the hand-off -- and each launch skips the
+  // matrices whose schedule has no step of its kind at k.
   const int bf16 = p->precision == SVDP_PREC_BF16;
-  HIPCHK(sched_counts_launch(B, w.ksteps, kcap, bf16, w.hist, c.st), "schedule counts");
-  HIPCHK(hipMemcpyAsync(c.h->host_word, w.hist, (4 * kcap + 2) * sizeof(int), hipMemcpyDeviceToHost, c.st),
-         "schedule copy");
-  HIPCHK(hipStreamSynchronize(c.st), "schedule sync");
-  std::vector<int> cnt(c.h->host_word, c.h->host_word + 4 * kcap + 2);
-  const int n_bf_start = cnt[4 * kcap], kmax = cnt[4 * kcap + 1];
+  const int kbudget = std::min(kcap, bounded_budget(p->bf16_handoff));
   HIPCHK(sched_mask_launch(B, w.ksteps, bf16, 0, w.gmask, c.st), "fp32 start");
   HIPCHK(scale_copy_launch(c.A, c.lda, c.sA, B, m, n, w.scale, w.X0, 0, w.gmask, c.st), "normalise");
-  if (n_bf_start > 0) {
+  if (bf16) {
     HIPCHK(sched_mask_launch(B, w.ksteps, bf16, 1, w.gmask, c.st), "bf16 start");
     HIPCHK(scale_copy_launch(c.A, c.lda, c.sA, B, m, n, w.scale, w.Y0, 1, w.gmask, c.st), "normalise");
     HIPCHK(transpose_bf16_launch(w.Y0, B, m, n, w.Yt0, w.gmask, c.st), "transpose");
   }
   phase.next(PROF_PHASE_CANS);
-  for (int k = 0; k < kmax; ++k)
-    for (int cat = 0; cat < 4; ++cat) {
-      const int count = cnt[4 * k + cat];
-      if (count == 0) continue;
-      const int in_bf = cat >= 2, out_bf = cat == 1 || cat == 2;
-      const void* Xc = in_bf ? ((k & 1) ? w.Y1 : w.Y0) : (const void*)((k & 1) ? w.X1 : w.X0);
-      void* Xn = out_bf ? (((k + 1) & 1) ? w.Y1 : w.Y0) : (void*)(((k + 1) & 1) ? w.X1 : w.X0);
-      const void* Xtc = in_bf ? ((k & 1) ? w.Yt1 : w.Yt0) : nullptr;
-      void* Xtn = out_bf ? (((k + 1) & 1) ? w.Yt1 : w.Yt0) : nullptr;
-      HIPCHK(cans_step(c, in_bf ? PREC_BF16 : PREC_F32, Xc, Xn, in_bf, out_bf, w.coef, kcap, k, nullptr, nullptr,
-                       count, w.ksteps, cat, bf16, Xtc, Xtn), "cans step");
-    }
+  // Step k runs as one launch pair for FP32 input (categories 0: FP32 out,
+  // 1: BF16 out) and, on the BF16 path, one for BF16 input (2: BF16 out, 3:
+  // FP32 out); the iterate after step k is in X[k % 2] (FP32) or Y[k % 2]
+  // (BF16, with its transpose in Yt[k % 2]).
+  for (int k = 0; k < kbudget; ++k) {
+    void* Xn = ((k + 1) & 1) ? w.X1 : w.X0;
+    void* Yn = ((k + 1) & 1) ? w.Y1 : w.Y0;
+    void* Ytn = bf16 ? (((k + 1) & 1) ? w.Yt1 : w.Yt0) : nullptr;
+    HIPCHK(cans_step(c, PREC_F32, (k & 1) ? w.X1 : w.X0, Xn, 0, 0, w.coef, kcap, k, nullptr, nullptr, w.ksteps,
+                     (1 << 0) | (1 << 1), 1 << 1, bf16, nullptr, Yn, Ytn), "cans step");
+    if (bf16)
+      HIPCHK(cans_step(c, PREC_BF16, (k & 1) ? w.Y1 : w.Y0, Xn, 1, 0, w.coef, kcap, k, nullptr, nullptr, w.ksteps,
+                       (1 << 2) | (1 << 3), 1 << 2, bf16, (k & 1) ? w.Yt1 : w.Yt0, Yn, Ytn), "cans step");
+  }
   // the last iterate of a matrix with K odd is in X1: move it to X0
   HIPCHK(sched_mask_launch(B, w.ksteps, bf16, 2, w.gmask, c.st), "odd mask");
   HIPCHK(copy_masked_launch(w.X1, w.X0, B, (int64_t)m * n, w.gmask, c.st), "to X0");
@@ -644,7 +661,8 @@ svdp_status bounded(Ctx& c) {
   // refine_steps of them, then per matrix until the relative change is below
   // tol.  A matrix whose predicted interval missed part of its spectrum is
   // still caught here; one that has not converged within refine_steps +
-  // kRefineExtra steps is flagged and falls back to conservative CANS.
+  // kRefineExtra steps is flagged and falls back to conservative CANS.  The
+  // whole budget is enqueued; converged matrices are skipped on the device.
   phase.next(PROF_PHASE_REFINE);
   const int R = p->refine_steps;
   const int Rmax = std::min(R + kRefineExtra, 64);
@@ -658,22 +676,17 @@ svdp_status bounded(Ctx& c) {
   // the reported count adds the refinement steps to each matrix's K (mask
   // is free until the fallback test)
   HIPCHK(copy_i32(w.mask, w.iters, B, c.st), "iteration base");
-  int remaining = B;
   for (int r = 0; r < Rmax; ++r) {
     const float* Xc = (r & 1) ? w.X1 : w.X0;
     float* Xn = (r & 1) ? w.X0 : w.X1;
     // the first R - 1 steps are unconditional: no change sums, no check
     float* conv = r + 1 >= R ? w.conv : nullptr;
-    HIPCHK(cans_step(c, PREC_F32, Xc, Xn, 0, 0, w.rcoef, 0, r, w.active, conv, remaining), "refine step");
+    HIPCHK(cans_step(c, PREC_F32, Xc, Xn, 0, 0, w.rcoef, 0, r, w.active, conv), "refine step");
     if (!conv) continue;
     HIPCHK(cans_check_launch(B, w.conv, (float)p->tol, r, w.active, w.where, w.iters, w.mask, 1, w.flags,
                              w.counter, c.st), "refine check");
-    svdp_status s = read_counter(c, w.counter, &remaining);
-    if (s) return s;
-    if (remaining == 0) break;
   }
-  if (remaining > 0)
-    HIPCHK(or_flags_launch(B, w.flags, SVDP_FLAG_NOT_CONVERGED, w.active, c.st), "flags");
+  HIPCHK(or_flags_launch(B, w.flags, SVDP_FLAG_NOT_CONVERGED, w.active, c.st), "flags");
   return SVDP_OK;
 }
 
@@ -993,6 +1006,8 @@ const char* svdp_status_string(svdp_status s) {
 }
 
 const char* svdp_last_error(void) { return g_last_error.c_str(); }
+
+int64_t svdp_host_syncs(void) { return g_host_syncs.load(); }
 
 svdp_status svdp_create(svdp_handle** out) {
   if (!out) return fail(SVDP_ERR_INVALID_ARG, "null handle pointer");

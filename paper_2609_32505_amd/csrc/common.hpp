@@ -33,13 +33,16 @@ struct GemmArgs {
   const float* colscale_in; int64_t csin_stride;
   const int* active;   // matrix b is skipped when active[b] == 0
   const int* ksched;   // bounded CANS schedule: per-matrix (K, K1); when set,
-  int kstep, kcat;     // matrix b runs only if sched_cat(ksched, b, kstep,
-  int kbf16;           // kbf16) == kcat
+  int kstep, kcatmask; // matrix b runs only if bit sched_cat(ksched, b, kstep,
+  int kbf16;           // kbf16) of kcatmask is set, and writes its output in
+  int obf_catmask;     // BF16 to C_bf (and Ct) when that bit of obf_catmask is set
+  void* C_bf;          // (same leading dimension and stride as C), else to C
   float* conv;         // per matrix: += sum (out - Cin)^2, += sum out^2
   int sym;             // output symmetric: upper tiles computed, mirrored
   int work_batch;      // matrices actually computed (for work accounting; 0 = batch)
   int out_bf16, in_bf16, cin_bf16;
   void* Ct; int64_t ldct, sCt;  // out_bf16: also write the output transposed, Ct[j, i] (BF16)
+  double* work;        // profiling: += the algorithmic flops of each tile computed
 };
 
 enum { PREC_F32 = 0, PREC_BF16 = 1 };

@@ -326,6 +326,13 @@ __global__ __launch_bounds__(128) void k_jac_solve(EighWs e, EighPhase ph, int i
   const int b = blockIdx.x / ng, gi = blockIdx.x - b * ng;
   if (b >= e.batch) return;
   if (e.active && !e.active[b]) return;
+  if (e.work && t == 0) {
+    // algorithmic flops: per pair subproblem and round, 256 two-sided 2 x 2
+    // block updates (24 flops each) and 512 rotation-accumulator pairs (6)
+    const int rounds = (ph.fullA ? 31 : 16) + (ph.skipB ? 0 : 16);
+    atomicAdd(e.work + (sizeof(R) == 8 ? PROF_JAC_SOLVE_F64 : PROF_JAC_SOLVE_F32),
+              2.0 * rounds * inner_sweeps * (256.0 * 24.0 + 512.0 * 6.0));
+  }
   int g[4];
   group_members(ph, gi, g);
   float* H = e.Hw + (int64_t)b * e.np * e.np;
@@ -408,48 +415,66 @@ __global__ __launch_bounds__(128) void k_jac_solve(EighWs e, EighPhase ph, int i
 }
 
 // 64 x 64 quadrant products on one wavefront (32 x 32 output block (qi, qj)),
-// K = 64 in 32 MFMA steps; step s contracts index 2 s + (lane / 32).
-// MFMA operand layout (32x32x2 f32): lane l supplies A[l % 32][k] and
-// B[k][l % 32]; the accumulator's slot 4 g + r is row 8 g + 4 (l / 32) + r,
-// column l % 32.
-// acc[i][j] = sum_k a_k[i] B[k][32 qj + j]: the left factor's operands in
-// registers (a[s] for k = 2 s + lane / 32), the right factor from LDS
-SVDP_DEV f16v mm_rl(const float (&a)[32], const float (*B)[GP], int qj, int lane) {
+// K = 64 in 32 MFMA steps.  MFMA operand layout (32x32x2 f32): lane l
+// supplies A[l % 32][k] and B[k][l % 32]; the accumulator's slot 4 g + r is
+// row 8 g + 4 (l / 32) + r, column l % 32.  Step s contracts index
+// s + 32 (l / 32) (a permutation of the 64 indices, the same for both
+// operands), so a lane's steps 4 j .. 4 j + 3 read four consecutive entries
+// of an LDS row: one 16-byte read (row pitch AP = 68: eight rows start in
+// 32 different banks) feeds four MFMAs.
+constexpr int AP = GS + 4;
+// acc[i][j] = sum_k a_k[i] B[k][32 qj + j] with B given transposed in LDS
+// (Bt[j][k] = B[k][j]); the left factor's operands in registers (a[s] for
+// k = s + 32 (lane / 32))
+SVDP_DEV f16v mm_rl(const float (&a)[32], const float (*Bt)[AP], int qj, int lane) {
   const int kh = lane >> 5, ic = lane & 31;
+  const float* row = Bt[32 * qj + ic] + 32 * kh;
   f16v acc = zero16();
 #pragma unroll
-  for (int s2 = 0; s2 < 32; ++s2) acc = mfma(a[s2], B[2 * s2 + kh][32 * qj + ic], acc);
+  for (int j = 0; j < 8; ++j) {
+    const f4v v = *(const f4v*)(row + 4 * j);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc = mfma(a[4 * j + u], v[u], acc);
+  }
   return acc;
 }
-// acc[i][j] = sum_k A[32 qi + i][k] b_k[j]: the left factor from LDS, the
-// right factor's operands in registers
-SVDP_DEV f16v mm_lr(const float (*A)[GP], const float (&b)[32], int qi, int lane) {
+// acc[i][j] = sum_k A[32 qi + i][k] b_k[j]: the left factor from LDS (row
+// major), the right factor's operands in registers
+SVDP_DEV f16v mm_lr(const float (*A)[AP], const float (&b)[32], int qi, int lane) {
   const int kh = lane >> 5, ic = lane & 31;
+  const float* row = A[32 * qi + ic] + 32 * kh;
   f16v acc = zero16();
 #pragma unroll
-  for (int s2 = 0; s2 < 32; ++s2) acc = mfma(A[32 * qi + ic][2 * s2 + kh], b[s2], acc);
+  for (int j = 0; j < 8; ++j) {
+    const f4v v = *(const f4v*)(row + 4 * j);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc = mfma(v[u], b[4 * j + u], acc);
+  }
   return acc;
 }
-SVDP_DEV void put_quadrant(float (*X)[GP], const f16v& acc, int qi, int qj, int lane) {
+SVDP_DEV void put_quadrant(float (*X)[AP], const f16v& acc, int qi, int qj, int lane) {
   const int kh = lane >> 5, ic = lane & 31;
 #pragma unroll
   for (int g = 0; g < 4; ++g)
 #pragma unroll
     for (int r = 0; r < 4; ++r) X[32 * qi + 8 * g + 4 * kh + r][32 * qj + ic] = acc[4 * g + r];
 }
-// column c0 + (lane % 32) of rows 2 s + (lane / 32) of a 64 x 64 row-major M
+// rows s + 32 (lane / 32) of column c0 + (lane % 32) of a 64 x 64 row-major M
 SVDP_DEV void load_mcol(const float* M, int c0, int lane, float (&v)[32]) {
   const int kh = lane >> 5, ic = lane & 31;
+  const float* p = M + 32 * kh * GS + c0 + ic;
 #pragma unroll
-  for (int s2 = 0; s2 < 32; ++s2) v[s2] = M[(2 * s2 + kh) * GS + c0 + ic];
+  for (int s2 = 0; s2 < 32; ++s2) v[s2] = p[s2 * GS];
 }
 
 // One workgroup (four wavefronts, wave w owns output quadrant (w / 2, w % 2))
 // per task.  The 64 x 64 data block goes through LDS; the group rotations
 // (small, shared by many tasks of the matrix, L2-resident) are read straight
-// into MFMA operand registers.
+// into MFMA operand registers.  An H task holds X transposed for M1^T X,
+// then the intermediate row-major for (M1^T X) M2; a V task holds X
+// row-major for X M.
 __global__ __launch_bounds__(256) void k_jac_apply(EighWs e, EighPhase ph) {
-  __shared__ float Xs[GS][GP];
+  __shared__ __attribute__((aligned(16))) float Xs[GS][AP];
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
   const int ng = e.nb / 4;
   const int nH = ng * (ng - 1) / 2;
@@ -463,6 +488,8 @@ __global__ __launch_bounds__(256) void k_jac_apply(EighWs e, EighPhase ph) {
   if (e.active && !e.active[b]) return;
   const int qi = w >> 1, qj = w & 1;
   const float* Qb = qslot(e, b, e.deferred ? ph.idx : 0);
+  // algorithmic flops: two 64^3 products per H task, one per V task
+  if (e.work && t == 0) atomicAdd(e.work + PROF_JAC_APPLY, (task < nH ? 4.0 : 2.0) * GS * GS * GS);
   if (task < nH) {
     int tt = task, G1 = 0;
     while (tt >= ng - 1 - G1) { tt -= ng - 1 - G1; ++G1; }
@@ -475,6 +502,7 @@ __global__ __launch_bounds__(256) void k_jac_apply(EighWs e, EighPhase ph) {
     float a1[32], b2[32];
     load_mcol(Qb + (int64_t)G1 * QSTRIDE, 32 * qi, lane, a1);
     load_mcol(Qb + (int64_t)G2 * QSTRIDE, 32 * qj, lane, b2);
+    // X^T into LDS: Xs[c][r] = X[r][c], X = H[G1, G2] from the upper tiles
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int idx = t + 256 * u;
@@ -483,10 +511,12 @@ __global__ __launch_bounds__(256) void k_jac_apply(EighWs e, EighPhase ph) {
       const bool tr = I > Jb;
       const f4v v = *(const f4v*)(H + tile_off(tr ? Jb : I, tr ? I : Jb, e.nb) + qd * 4);
       const int r = qd >> 2, c = (qd & 3) * 4;
+      if (tr) {
+        // the stored tile is X's block transposed: row r of it is column r of X
+        *(f4v*)&Xs[k2 * 16 + r][k1 * 16 + c] = v;
+      } else {
 #pragma unroll
-      for (int w2 = 0; w2 < 4; ++w2) {
-        if (tr) Xs[k1 * 16 + c + w2][k2 * 16 + r] = v[w2];
-        else Xs[k1 * 16 + r][k2 * 16 + c + w2] = v[w2];
+        for (int w2 = 0; w2 < 4; ++w2) Xs[k2 * 16 + c + w2][k1 * 16 + r] = v[w2];
       }
     }
     __syncthreads();
@@ -523,8 +553,7 @@ __global__ __launch_bounds__(256) void k_jac_apply(EighWs e, EighPhase ph) {
       const int tile = idx >> 6, qd = idx & 63, k1 = tile >> 2, k2 = tile & 3;
       const f4v x = *(const f4v*)(V + tile_off(4 * slab + k1, gm[k2], e.nb) + qd * 4);
       const int r = qd >> 2, c = (qd & 3) * 4;
-#pragma unroll
-      for (int w2 = 0; w2 < 4; ++w2) Xs[k1 * 16 + r][k2 * 16 + c + w2] = x[w2];
+      *(f4v*)&Xs[k1 * 16 + r][k2 * 16 + c] = x;
     }
     __syncthreads();
     const f16v Y = mm_lr(Xs, bm, qi, lane);  // X M
@@ -536,10 +565,7 @@ __global__ __launch_bounds__(256) void k_jac_apply(EighWs e, EighPhase ph) {
       const int idx = t + 256 * u;
       const int tile = idx >> 6, qd = idx & 63, k1 = tile >> 2, k2 = tile & 3;
       const int r = qd >> 2, c = (qd & 3) * 4;
-      f4v y;
-#pragma unroll
-      for (int w2 = 0; w2 < 4; ++w2) y[w2] = Xs[k1 * 16 + r][k2 * 16 + c + w2];
-      *(f4v*)(V + tile_off(4 * slab + k1, gm[k2], e.nb) + qd * 4) = y;
+      *(f4v*)(V + tile_off(4 * slab + k1, gm[k2], e.nb) + qd * 4) = *(const f4v*)&Xs[k1 * 16 + r][k2 * 16 + c];
     }
   }
 }
@@ -549,26 +575,29 @@ __global__ __launch_bounds__(256) void k_jac_apply(EighWs e, EighPhase ph) {
 // grouping, one 64 x 64 orthogonal M per group of four blocks).  One
 // workgroup of eight wavefronts per slab of R rows of one matrix (R = 64 up
 // to NP = 512, 32 at NP = 1024: the slab takes about 128 KB of LDS); the
-// slab (row pitch NP + 1, so that the 32 rows an MFMA operand reads start in
-// 32 different banks) stays in LDS for the whole sweep, and the rotations
-// are read from L2 straight into MFMA operand registers.  A phase runs over
-// sets of GPS groups (groups touch disjoint columns): wave w takes the
-// column half w % 2 of group w / 2 of the set, i.e. a 64 x 32 slice of that
-// group's M, and multiplies every 32-row block of the slab by it (R / 32
-// independent MFMA chains on the same operands); all waves have read the
-// set's input columns at the first barrier and written their outputs at the
-// second.  The next set's slice is loaded during the current set's MFMAs.
-// Matrices that were not active in the sweep are skipped (their rotation
-// slots hold an earlier sweep's).
+// slab stays in LDS for the whole sweep and the rotations are read from L2
+// straight into MFMA operand registers.  A phase runs over sets of GPS
+// groups (groups touch disjoint columns): wave w takes the column half
+// w % 2 of group w / 2 of the set, i.e. a 64 x 32 slice of that group's M,
+// and multiplies every 32-row block of the slab by it (R / 32 independent
+// MFMA chains on the same operands); all waves have read the set's input
+// columns at the first barrier and written their outputs at the second.
+// The contraction index of MFMA step s is s + 32 (lane / 32) (any order of
+// the 64 indices gives the same product), so a lane's steps 4 j .. 4 j + 3
+// read four consecutive slab columns: one 16-byte LDS read (row pitch
+// NP + 4: eight rows start in 32 different banks) feeds four MFMAs.  The
+// next set's slice is loaded during the current set's MFMAs.  Matrices that
+// were not active in the sweep are skipped (their rotation slots hold an
+// earlier sweep's).
 template <int NP, int R>
 __global__ __launch_bounds__(512) void k_jac_vsweep(EighWs e) {
-  constexpr int PITCH = NP + 1;
+  constexpr int PITCH = NP + 4;
   constexpr int NBK = NP / BS, NG = NBK / 4, NPH = NBK / 2;
   constexpr int GPS = NG < 4 ? NG : 4;  // groups per set: 2 GPS <= 8 slices, one per wave
   constexpr int NSET = NG / GPS;
   constexpr int RB = R / 32;            // 32-row blocks of the slab
   constexpr int SLABS = NP / R;
-  __shared__ float Vs[R * PITCH];
+  __shared__ __attribute__((aligned(16))) float Vs[R * PITCH];
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
   // matrix b on XCD b % 8: its rotations are read into one L2
   const int L = blockIdx.x, x8 = L & 7, q = L >> 3;
@@ -577,21 +606,22 @@ __global__ __launch_bounds__(512) void k_jac_vsweep(EighWs e) {
   if (b >= e.batch) return;
   if (e.active && !e.active[b]) return;
   float* V = e.Vw + (int64_t)b * NP * NP + (int64_t)slab * R * NP;
+  if (e.work && t == 0) atomicAdd(e.work + PROF_JAC_VSWEEP, (double)NPH * NG * 2.0 * R * GS * GS);
   for (int idx = t; idx < R * NP / 4; idx += 512) {
     const int r = idx / (NP / 4), c = (idx - r * (NP / 4)) * 4;
-    const f4v v = *(const f4v*)(V + (int64_t)r * NP + c);
-#pragma unroll
-    for (int w2 = 0; w2 < 4; ++w2) Vs[r * PITCH + c + w2] = v[w2];
+    *(f4v*)(Vs + r * PITCH + c) = *(const f4v*)(V + (int64_t)r * NP + c);
   }
   __syncthreads();
   const int kh = lane >> 5, ic = lane & 31;
   const bool busy = w < 2 * GPS;  // waves beyond the set's slices idle (NG < 4)
   const int ch = w & 1;
   float cur[32], nxt[32];
+  // B operands of the slice: rows s + 32 kh of column 32 ch + ic of M
   auto load_slice = [&](int p, int set, float (&bm)[32]) {
     if (!busy) return;
-    const int G = set * GPS + (w >> 1);
-    load_mcol(qslot(e, b, p) + (int64_t)G * QSTRIDE, 32 * ch, lane, bm);
+    const float* M = qslot(e, b, p) + (int64_t)(set * GPS + (w >> 1)) * QSTRIDE + 32 * kh * GS + 32 * ch + ic;
+#pragma unroll
+    for (int s2 = 0; s2 < 32; ++s2) bm[s2] = M[s2 * GS];
   };
   load_slice(0, 0, cur);
   for (int p = 0; p < NPH; ++p) {
@@ -605,11 +635,18 @@ __global__ __launch_bounds__(512) void k_jac_vsweep(EighWs e) {
       int gm[4];
       group_members(ph, set * GPS + (w >> 1), gm);
       if (busy) {
+        // contraction index s2 + 32 kh lies in member block 2 kh + s2 / 16
+        const int blk0 = kh ? gm[2] : gm[0], blk1 = kh ? gm[3] : gm[1];
 #pragma unroll
-        for (int s2 = 0; s2 < 32; ++s2) {
-          const int col = 16 * gm[s2 >> 3] + 2 * (s2 & 7) + kh;
+        for (int j = 0; j < 8; ++j) {
+          const int col = 16 * (j < 4 ? blk0 : blk1) + 4 * (j & 3);
+          f4v a[RB];
 #pragma unroll
-          for (int rb = 0; rb < RB; ++rb) acc[rb] = mfma(Vs[(32 * rb + ic) * PITCH + col], cur[s2], acc[rb]);
+          for (int rb = 0; rb < RB; ++rb) a[rb] = *(const f4v*)(Vs + (32 * rb + ic) * PITCH + col);
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) acc[rb] = mfma(a[rb][u], cur[4 * j + u], acc[rb]);
         }
       }
       __syncthreads();
@@ -634,10 +671,7 @@ __global__ __launch_bounds__(512) void k_jac_vsweep(EighWs e) {
   }
   for (int idx = t; idx < R * NP / 4; idx += 512) {
     const int r = idx / (NP / 4), c = (idx - r * (NP / 4)) * 4;
-    f4v v;
-#pragma unroll
-    for (int w2 = 0; w2 < 4; ++w2) v[w2] = Vs[r * PITCH + c + w2];
-    *(f4v*)(V + (int64_t)r * NP + c) = v;
+    *(f4v*)(V + (int64_t)r * NP + c) = *(const f4v*)(Vs + r * PITCH + c);
   }
 }
 
@@ -966,8 +1000,6 @@ EighWs eigh_ws_carve(void* ws, int64_t batch, int64_t n, int max_sweeps) {
   return e;
 }
 
-static int phases_per_sweep_of(int nb) { return nb / 2; }
-
 std::vector<EighPhase> eigh_phases(int nb) {
   std::vector<EighPhase> out;
   for (int p = 0; p < nb / 2; ++p) out.push_back(eigh_phase(p));
@@ -975,8 +1007,8 @@ std::vector<EighPhase> eigh_phases(int nb) {
 }
 
 // The deferred V update of one sweep for the matrices of E (V row-major).
-static hipError_t vsweep_launch(const EighWs& E, double work, hipStream_t st) {
-  ProfScope ps(PROF_JAC_VSWEEP, st, work);
+static hipError_t vsweep_launch(const EighWs& E, hipStream_t st) {
+  ProfScope ps(PROF_JAC_VSWEEP, st);
   const unsigned groups8 = (unsigned)cdiv(E.batch, 8) * 8;
   switch (E.np) {
     case 64: hipLaunchKernelGGL((k_jac_vsweep<64, 64>), dim3(groups8 * 1), dim3(512), 0, st, E); break;
@@ -1016,6 +1048,7 @@ hipError_t eigh_run(EighWs e, const float* H, int64_t ldh, int64_t sH, int mode,
                     const EighAux* aux, hipStream_t st) {
   hipError_t err;
   const int batch = e.batch;
+  e.work = prof_work_dev();
   if ((err = fill_f32(e.hnorm2, 0.f, batch, st))) return err;
   if ((err = fill_i32(e.rotcnt, 0, (int64_t)batch * (e.max_sweeps + 2), st))) return err;
   if ((err = fill_f32(e.rotsq, 0.f, (int64_t)batch * (e.max_sweeps + 2), st))) return err;
@@ -1028,17 +1061,6 @@ hipError_t eigh_run(EighWs e, const float* H, int64_t ldh, int64_t sH, int mode,
   const int nH = ng * (ng - 1) / 2;
   const int ntask = nH + ng * ng;
   const std::vector<EighPhase> phases = eigh_phases(e.nb);
-  // algorithmic flops per matrix: a pair round updates 256 2 x 2 blocks
-  // (24 flops each) and 512 rotation-accumulator pairs (6 each); the apply
-  // does two 64^3 products per pair of groups and one per slab of V
-  const double round_work = 256.0 * 24.0 + 512.0 * 6.0;
-  const double apply_work = (double)nH * 4.0 * GS * GS * GS + (e.deferred ? 0.0 : (double)ng * ng * 2.0 * GS * GS * GS);
-  // the deferred V update: every phase's 64 x 64 group products over all rows
-  const double vsweep_work = (double)phases_per_sweep_of(e.nb) * ng * 2.0 * e.np * GS * GS;
-  auto solve_work = [&](const EighPhase& ph, int reps) {
-    const int rounds = (ph.fullA ? 31 : 16) + (ph.skipB ? 0 : 16);
-    return (double)ng * 2.0 * rounds * round_work * reps;
-  };
   // Parts of the batch on parallel streams (when extra streams are given):
   // the LDS/VALU-bound pair solves of one part run beside the MFMA/HBM-bound
   // rotations of the others.
@@ -1064,11 +1086,11 @@ hipError_t eigh_run(EighWs e, const float* H, int64_t ldh, int64_t sH, int mode,
     const unsigned sblocks = (unsigned)(E.batch * ng);
     const unsigned ablocks = (unsigned)((int64_t)cdiv(E.batch, 8) * 8 * (e.deferred ? nH : ntask));
     if (fp64) {
-      ProfScope ps(PROF_JAC_SOLVE_F64, ss[h], solve_work(ph, o.fp64_inner) * n_act);
+      ProfScope ps(PROF_JAC_SOLVE_F64, ss[h]);
       hipLaunchKernelGGL(k_jac_solve<double>, dim3(sblocks), dim3(128), 0, ss[h], E, ph, o.fp64_inner, o.abs_tol,
                          skip_rel, (int*)nullptr, (float*)nullptr);
     } else {
-      ProfScope ps(PROF_JAC_SOLVE_F32, ss[h], solve_work(ph, o.inner_sweeps) * n_act);
+      ProfScope ps(PROF_JAC_SOLVE_F32, ss[h]);
       hipLaunchKernelGGL(k_jac_solve<float>, dim3(sblocks), dim3(128), 0, ss[h], E, ph, o.inner_sweeps, o.abs_tol,
                          skip_rel, rc, vs);
     }
@@ -1076,7 +1098,7 @@ hipError_t eigh_run(EighWs e, const float* H, int64_t ldh, int64_t sH, int mode,
     if (e2) return e2;
     if (mark_skew && (e2 = hipEventRecord(aux->skew[h], ss[h]))) return e2;
     if (ablocks > 0) {
-      ProfScope ps(PROF_JAC_APPLY, ss[h], apply_work * n_act);
+      ProfScope ps(PROF_JAC_APPLY, ss[h]);
       hipLaunchKernelGGL(k_jac_apply, dim3(ablocks), dim3(256), 0, ss[h], E, ph);
     }
     return hipGetLastError();
@@ -1100,42 +1122,32 @@ hipError_t eigh_run(EighWs e, const float* H, int64_t ldh, int64_t sH, int mode,
     if (e.deferred)
       for (int h = 0; h < P; ++h) {
         if (n_act[h] == 0) continue;
-        hipError_t e2 = vsweep_launch(eh[h], vsweep_work * n_act[h], ss[h]);
+        hipError_t e2 = vsweep_launch(eh[h], ss[h]);
         if (e2) return e2;
       }
     return hipSuccess;
   };
+  // The sweep loop runs its full budget without reading anything back: a
+  // matrix leaves the active set on the device after the sweep that
+  // converges it (k_eigh_check), and every later launch skips it.
   int n_act[kEighParts];
   for (int h = 0; h < P; ++h) n_act[h] = bc[h];
-  int sweep = 0;
-  for (; sweep < e.max_sweeps; ++sweep) {
+  for (int sweep = 0; sweep < e.max_sweeps; ++sweep) {
     int* rc = e.rotcnt + (int64_t)batch * sweep;
     float* vs = e.rotsq + (int64_t)batch * sweep;
     if ((err = sweep_launches(false, 0.f, rc, vs, n_act))) return err;
     for (int h = 0; h < P; ++h) {
-      if (n_act[h] == 0) continue;
       hipLaunchKernelGGL(k_eigh_check, dim3(1), dim3(1024), 0, ss[h], eh[h], rc + b0[h], vs + b0[h], o.tol,
                          o.fro_tol * o.fro_tol, sweep, sweeps_out + b0[h], eh[h].counter);
       if ((err = hipGetLastError())) return err;
-      if ((err = hipMemcpyAsync(host_counter + h, eh[h].counter, sizeof(int), hipMemcpyDeviceToHost, ss[h])))
-        return err;
     }
-    int total = 0;
-    for (int h = 0; h < P; ++h) {
-      if (n_act[h] == 0) continue;
-      if ((err = hipStreamSynchronize(ss[h]))) return err;
-      n_act[h] = host_counter[h];
-      total += n_act[h];
-    }
-    if (total == 0) break;
   }
   // matrices still active after max_sweeps did not converge
-  if (sweep == e.max_sweeps)
-    for (int h = 0; h < P; ++h) {
-      hipLaunchKernelGGL(k_flag_active, dim3(cdiv(bc[h], 256)), dim3(256), 0, ss[h], eh[h].active, bc[h],
-                         flags + b0[h], (int)SVDP_FLAG_EIGH_NOT_CONVERGED);
-      if ((err = hipGetLastError())) return err;
-    }
+  for (int h = 0; h < P; ++h) {
+    hipLaunchKernelGGL(k_flag_active, dim3(cdiv(bc[h], 256)), dim3(256), 0, ss[h], eh[h].active, bc[h],
+                       flags + b0[h], (int)SVDP_FLAG_EIGH_NOT_CONVERGED);
+    if ((err = hipGetLastError())) return err;
+  }
   // final sweep(s) with FP64 pair solves on every matrix
   if (o.fp64_sweeps > 0) {
     for (int h = 0; h < P; ++h) {
@@ -1224,9 +1236,7 @@ hipError_t eigh_run(EighWs e, const float* H, int64_t ldh, int64_t sH, int mode,
                          e.counter, sweeps_out, std::max(1, o.fp64_sweeps));
       if ((err = hipGetLastError())) return err;
       if (last) break;
-      if ((err = hipMemcpyAsync(host_counter, e.counter, sizeof(int), hipMemcpyDeviceToHost, st))) return err;
-      if ((err = hipStreamSynchronize(st))) return err;
-      if (host_counter[0] == 0) break;
+      // the restart's launches skip the matrices k_restart_decide left out
       proc = e.active;
       const dim3 sgrid((e.nb / 4) * (e.nb / 4), batch);
       hipLaunchKernelGGL(k_eigh_setup, sgrid, dim3(256), 0, st, e, e.Vw, (int64_t)np, m2, proc, kSetupH);

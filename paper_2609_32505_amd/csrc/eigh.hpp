@@ -21,6 +21,7 @@ struct EighWs {
   int deferred;   // 1: V row-major, updated once per sweep from every phase's group
                   // rotations (np <= 1024); 0: V tiled, updated by every phase's apply
   int nph_store;  // group-rotation slots per matrix in Qw: the phases of a sweep (deferred), else 1
+  double* work;   // profiling: device work counters per kind (null when profiling is off)
 };
 
 // Two fused block-Jacobi steps: block B is paired with B ^ sA, then with

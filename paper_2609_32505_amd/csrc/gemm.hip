@@ -15,7 +15,6 @@
 namespace {
 
 thread_local int g_prof_kind = PROF_GEMM_F32;
-thread_local double g_prof_batch = 0.0;
 
 // Linear block id -> (matrix, tile).  Workgroups are dealt to the 8 XCDs
 // round-robin by linear id; with remap every tile of matrix b runs on XCD
@@ -49,6 +48,14 @@ SVDP_DEV float ld_any(const void* p, int64_t i, int isbf) {
   return isbf ? (float)((const bf16_t*)p)[i] : ((const float*)p)[i];
 }
 
+// Profiling: the tile's algorithmic flops, 2 r c K (r x c the tile inside the
+// output), half of it on the diagonal of a symmetric output (its triangle)
+SVDP_DEV void count_tile(const GemmArgs& g, int m0, int n0, int BM, int BN, int tm, int tn) {
+  if (!g.work || threadIdx.x != 0) return;
+  const double r = min(BM, g.M - m0), c = min(BN, g.N - n0);
+  atomicAdd(g.work, (g.sym && tm == tn ? 1.0 : 2.0) * r * c * (double)g.K);
+}
+
 // Shared epilogue over one wave's accumulators.  acc[f] holds a 32x32 block
 // in the MFMA output layout: lane l, slot 4g + r -> row 8g + 4(l/32) + r,
 // column l % 32.
@@ -65,8 +72,13 @@ SVDP_DEV void epilogue(const GemmArgs& g, int b, int rowbase, int colbase, int t
   const float* cs = g.colscale ? g.colscale + b * g.cs_stride : nullptr;
   const float* csi = g.colscale_in ? g.colscale_in + b * g.csin_stride : nullptr;
   const char* cin = g.Cin ? (const char*)g.Cin + b * g.sCin * (g.cin_bf16 ? 2 : 4) : nullptr;
-  char* out = (char*)g.C + b * g.sC * (g.out_bf16 ? 2 : 4);
-  bf16_t* outt = g.Ct ? (bf16_t*)g.Ct + b * g.sCt : nullptr;
+  // output format: per matrix from its schedule category when a BF16
+  // destination is given (the workgroup ran, so the category is >= 0), else
+  // out_bf16
+  const bool percat = g.ksched && g.C_bf;
+  const int obf = percat ? (g.obf_catmask >> sched_cat(g.ksched, b, g.kstep, g.kbf16)) & 1 : g.out_bf16;
+  char* out = (char*)(percat && obf ? g.C_bf : g.C) + b * g.sC * (obf ? 2 : 4);
+  bf16_t* outt = (g.Ct && obf) ? (bf16_t*)g.Ct + b * g.sCt : nullptr;
   float d2 = 0.f, o2 = 0.f;
   const bool mirror = g.sym && tm != tn;
 #pragma unroll
@@ -93,7 +105,7 @@ SVDP_DEV void epilogue(const GemmArgs& g, int b, int rowbase, int colbase, int t
             d2 += (v - c) * (v - c);
           }
           o2 += v * v;
-          if (g.out_bf16) {
+          if (obf) {
             const bf16_t h = f2bf(v);
             tv[r] = h;
             ((bf16_t*)out)[(int64_t)i * g.ldc + j] = h;
@@ -144,11 +156,15 @@ __global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs g, int tiles_m, int t
   int b, tile;
   if (!map_block(ntiles, g.batch, remap, b, tile)) return;
   if (g.active && !g.active[b]) return;
-  if (g.ksched && sched_cat(g.ksched, b, g.kstep, g.kbf16) != g.kcat) return;
+  if (g.ksched) {
+    const int cat = sched_cat(g.ksched, b, g.kstep, g.kbf16);
+    if (cat < 0 || !((g.kcatmask >> cat) & 1)) return;
+  }
   int tm, tn;
   if (g.sym) sym_tile(tile, tiles_m, tm, tn);
   else { tm = tile / tiles_n; tn = tile - tm * tiles_n; }
   const int m0 = tm * BM, n0 = tn * BN;
+  count_tile(g, m0, n0, BM, BN, tm, tn);
   const float* A = (const float*)((g.a_sel && g.a_sel[b]) ? g.A_alt : g.A) + b * g.sA;
   const float* B = (const float*)((g.b_sel && g.b_sel[b]) ? g.B_alt : g.B) + b * g.sB;
   const int M = g.M, N = g.N, K = g.K;
@@ -290,11 +306,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 4))) voi
   int b, tile;
   if (!map_block(ntiles, g.batch, remap, b, tile)) return;
   if (g.active && !g.active[b]) return;
-  if (g.ksched && sched_cat(g.ksched, b, g.kstep, g.kbf16) != g.kcat) return;
+  if (g.ksched) {
+    const int cat = sched_cat(g.ksched, b, g.kstep, g.kbf16);
+    if (cat < 0 || !((g.kcatmask >> cat) & 1)) return;
+  }
   int tm, tn;
   if (g.sym) sym_tile(tile, tiles_m, tm, tn);
   else { tm = tile / tiles_n; tn = tile - tm * tiles_n; }
   const int m0 = tm * BM, n0 = tn * BN;
+  count_tile(g, m0, n0, BM, BN, tm, tn);
   const int esz = INBF ? 2 : 4;
   const char* A = (const char*)((g.a_sel && g.a_sel[b]) ? g.A_alt : g.A) + b * g.sA * esz;
   const char* B = (const char*)((g.b_sel && g.b_sel[b]) ? g.B_alt : g.B) + b * g.sB * esz;
@@ -441,9 +461,12 @@ hipError_t launch_tiles(KernelT kern, const GemmArgs& g, int BM, int BN, hipStre
   int64_t blocks = remap ? (int64_t)cdiv(g.batch, 8) * 8 * ntiles : (int64_t)g.batch * ntiles;
   if (blocks <= 0) return hipSuccess;
   if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
-  // algorithmic flops: 2 M N K per matrix, half of it for a symmetric output
-  ProfScope ps(g_prof_kind, st, (g.sym ? 1.0 : 2.0) * g.M * (double)g.N * g.K * g_prof_batch);
-  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), 0, st, g, tiles_m, tiles_n, ntiles, remap);
+  // algorithmic flops counted on the device by the tiles that run
+  ProfScope ps(g_prof_kind, st, 0.0);
+  GemmArgs ga = g;
+  double* wd = prof_work_dev();
+  ga.work = wd ? wd + g_prof_kind : nullptr;
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), 0, st, ga, tiles_m, tiles_n, ntiles, remap);
   return hipGetLastError();
 }
 
@@ -482,7 +505,6 @@ bool aligned(const void* p, int64_t ld, int64_t stride, int elems, int esz) {
 hipError_t gemm_launch(const GemmArgs& g, int prec, int ta, int tb, hipStream_t st) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
   g_prof_kind = prec == PREC_F32 ? PROF_GEMM_F32 : PROF_GEMM_BF16;
-  g_prof_batch = g.work_batch > 0 ? g.work_batch : g.batch;
   if (g.sym && g.M != g.N) return hipErrorInvalidValue;
   const bool big = g.M > 64 && g.N > 64;
   if (prec == PREC_F32) {

@@ -995,7 +995,8 @@ __global__ void k_bounds(int batch, int mode, const float* mlp_out, const float*
   smin *= margin_min;
   if (!(smax > 0.0) || !isfinite(smax)) smax = 1.0;
   double lo = smin / smax;
-  if (!(lo > 1e-12)) lo = 1e-12;
+  // the host's step budget counts the steps from this floor (kLoFloor)
+  if (!(lo > 1e-9)) lo = 1e-9;
   if (lo > 1.0) lo = 1.0;
   scale[b] = (float)smax;
   double a = lo, hb = 1.0;

@@ -16,6 +16,7 @@ struct Rec {
 };
 std::mutex g_mu;
 bool g_on = false;
+double* g_dev_work = nullptr;  // PROF_KINDS device counters, allocated on first enable
 std::vector<Rec> g_recs;
 std::vector<hipEvent_t> g_pool;
 
@@ -60,10 +61,19 @@ void ProfScope::next(int k) {
   new (this) ProfScope(k, s, 0.0);
 }
 
+double* prof_work_dev() {
+  std::lock_guard<std::mutex> lk(g_mu);
+  return g_on ? g_dev_work : nullptr;
+}
+
 extern "C" {
 
 void svdp_profile_enable(int on) {
   std::lock_guard<std::mutex> lk(g_mu);
+  if (on && !g_dev_work) {
+    if (hipMalloc((void**)&g_dev_work, PROF_KINDS * sizeof(double)) != hipSuccess) g_dev_work = nullptr;
+    else (void)hipMemset(g_dev_work, 0, PROF_KINDS * sizeof(double));
+  }
   g_on = on != 0;
 }
 
@@ -74,6 +84,10 @@ void svdp_profile_reset(void) {
     g_pool.push_back(r.b);
   }
   g_recs.clear();
+  if (g_dev_work) {
+    (void)hipDeviceSynchronize();
+    (void)hipMemset(g_dev_work, 0, PROF_KINDS * sizeof(double));
+  }
 }
 
 int svdp_profile_read(int kind, double* total_ms, int64_t* launches, double* work) {
@@ -88,6 +102,12 @@ int svdp_profile_read(int kind, double* total_ms, int64_t* launches, double* wor
     t += ms;
     wk += r.work;
     ++c;
+  }
+  if (g_dev_work && kind >= 0 && kind < PROF_KINDS) {
+    double dw = 0.0;
+    if (hipDeviceSynchronize() != hipSuccess) return SVDP_ERR_HIP;
+    if (hipMemcpy(&dw, g_dev_work + kind, sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) return SVDP_ERR_HIP;
+    wk += dw;
   }
   if (total_ms) *total_ms = t;
   if (launches) *launches = c;

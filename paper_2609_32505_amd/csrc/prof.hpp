@@ -22,8 +22,14 @@ enum ProfKind {
   PROF_KINDS = 15
 };
 
+// Device-side work counters (one double per kind) while profiling is on,
+// null otherwise: a kernel adds the algorithmic flops of each workgroup that
+// runs (workgroups of converged or masked matrices exit without adding).
+double* prof_work_dev();
+
 // Brackets one launch with events when profiling is on; a no-op otherwise.
-// `work` is the launch's algorithmic work (flops), summed per class.
+// `work` is host-side algorithmic work (flops) added to the class's total
+// (kernels that count on the device pass 0).
 struct ProfScope {
   ProfScope(int kind, hipStream_t st, double work = 0.0);
   ~ProfScope();

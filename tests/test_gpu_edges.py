@@ -397,3 +397,34 @@ def test_bound_far_too_narrow_hits_refinement_cap_and_falls_back(api):
     assert not np.any(inf["flags"] & 1), "the conservative rerun converges"
     Sh = S.cpu().double().numpy()
     assert (np.abs(Sh - s).max(axis=1) / s[:, 0]).max() < 1e-5
+
+
+def test_forward_host_syncs(api):
+    # the forward passes enqueue their iteration control on the device: no
+    # host synchronisation on the conservative path, one (the fallback test)
+    # on the learned path, at n <= 512 (the QR step runs per matrix there)
+    import torch
+    from paper_2609_32505_amd import _lib as L, predictor
+    h = api.Handle()
+    h.set_model(predictor.load())
+    A, _ = inputs.batch_with_spectra(98, 8, 256, 256, lambda r: inputs.log_uniform(r, 256, 1e-3, 1.0))
+    Ad = dev(A)
+    probe = dev(inputs.probe(99, 8, 256))
+    lib = L.load()
+    api.svd_fwd(Ad, handle=h)
+    torch.cuda.synchronize()
+    n0 = lib.svdp_host_syncs()
+    U, S, V, info = api.svd_fwd(Ad, handle=h)
+    n1 = lib.svdp_host_syncs()
+    api.svd_fwd(Ad, handle=h, precision=1, bound=1, probe=probe)
+    n2 = lib.svdp_host_syncs()
+    W, H, _, _, _ = api.polar_fwd(Ad, handle=h, cache=False)
+    n3 = lib.svdp_host_syncs()
+    torch.cuda.synchronize()
+    _say(f"  host syncs: conservative svd {n1 - n0}, learned svd {n2 - n1}, conservative polar {n3 - n2}")
+    assert n1 - n0 == 0 and n2 - n1 <= 1 and n3 - n2 == 0
+    # and the results are those of the oracle
+    Sh = S.cpu().double().numpy()
+    for i in (0, 7):
+        So = oracle.svd(A[i].astype(np.float64))[1]
+        assert np.abs(Sh[i] - So).max() / So[0] < 1e-5
