@@ -52,7 +52,8 @@ def kernel_profile(L):
 # still has the hash recorded with the counters.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_256x512.txt")
 KERNEL_SOURCES = {"jac_apply": "eigh.hip", "jac_solve_f32": "eigh.hip", "jac_solve_f64": "eigh.hip",
-                  "gemm_f32": "gemm.hip", "gemm_bf16": "gemm.hip"}
+                  "jac_vsweep": "eigh.hip", "gemm_f32": "gemm.hip", "gemm_bf16": "gemm.hip"}
+MFMA_KINDS = ("gemm_f32", "gemm_bf16", "jac_apply", "jac_vsweep")
 
 
 def recorded_traffic(kind: str):
@@ -80,7 +81,7 @@ def recorded_traffic(kind: str):
 
 
 def kind_peak(name):
-    if name in ("gemm_f32", "jac_apply"):
+    if name in ("gemm_f32", "jac_apply", "jac_vsweep"):
         return PEAKS["mfma_fp32"]
     if name == "gemm_bf16":
         return PEAKS["mfma_bf16"]
@@ -103,7 +104,7 @@ def kernel_table(prof, steps):
 def roofline_of(prof):
     name = max(prof, key=lambda k: prof[k]["ms"])
     rec = prof[name]
-    bound = "mfma" if name in ("gemm_f32", "gemm_bf16", "jac_apply") else "alu"
+    bound = "mfma" if name in MFMA_KINDS else "alu"
     peak = kind_peak(name)
     avg_ms = rec["ms"] / max(rec["launches"], 1)
     per_launch = rec["flops"] / max(rec["launches"], 1)
@@ -413,6 +414,8 @@ def main():
         "plain_fp32": {"value": round(B / (ms_p * 1e-3), 3), "ms_per_step": round(ms_p, 3),
                        "ms_per_step_std": round(sd_p, 3),
                        "iters_max": int(ip["iters"].max()), "iters_mean": round(float(ip["iters"].mean()), 2),
+                       "sweeps_max": int(ip["sweeps"].max()),
+                       "sweeps_hist": np.bincount(ip["sweeps"]).tolist(),
                        "kernels": kernel_table(prof_p, args.steps)},
         "plain_fp32_learned_eigh": {"value": round(B / (ms_ps * 1e-3), 3), "ms_per_step": round(ms_ps, 3),
                                     "note": "the plain path with the learned path's eigensolver settings"},
@@ -434,6 +437,7 @@ def main():
                                     f"Algorithm 4 on the oracle's factors, relative Frobenius, matrices {gidx}"},
         "learned_info": {"iters_max": int(il["iters"].max()), "iters_mean": round(float(il["iters"].mean()), 2),
                          "sweeps_max": int(il["sweeps"].max()),
+                         "sweeps_hist": np.bincount(il["sweeps"]).tolist(),
                          "fallbacks": int(((il["flags"] & L.FLAG_FALLBACK_USED) != 0).sum())},
         "roofline": roof,
         "kernels": kernel_table(prof, args.steps),

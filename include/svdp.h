@@ -316,6 +316,22 @@ svdp_status svdp_bound_features(svdp_handle* h, const svdp_params* p,
 svdp_status svdp_spectral_features(const float* s, const float* z, int64_t rows, int64_t n,
                                    const float* m_over_n, float* F, float* aux, void* stream);
 
+/* Training targets of the interval predictor (Section 3, learned bounds:
+ * the network predicts how far sigma_max lies above the sketch estimate r_7
+ * and the log condition number): for each row of s (rows x n, a spectrum)
+ * and aux (rows x 2 from svdp_spectral_features, aux[r][0] = r_7),
+ * T[r] = (log(max s / r_7), log(max s / min s)) (min s clamped at 1e-30).
+ * T: rows x 2, device.  rows = 0 is a no-op; SVDP_ERR_SHAPE for rows < 0,
+ * rows > 2^26 or n < 1. */
+svdp_status svdp_training_targets(const float* s, const float* aux, int64_t rows, int64_t n, float* T,
+                                  void* stream);
+/* Feature standardisation of the predictor's inputs (Section 3, learned
+ * bounds): mu[f] = mean and sd[f] = sample standard deviation (divisor
+ * rows - 1, clamped at 1e-3) of column f of F (rows x 8, device), summed in
+ * FP64 in a fixed order, so repeated calls agree bit for bit.  mu, sd: 8
+ * floats each, device.  SVDP_ERR_SHAPE unless 1 <= rows <= 2^26. */
+svdp_status svdp_feature_stats(const float* F, int64_t rows, float* mu, float* sd, void* stream);
+
 /* MLP 8 -> 64 -> 64 -> 2 with tanh hidden layers.  params (4866 floats):
  * W1 (64 x 8), b1 (64), W2 (64 x 64), b2 (64), W3 (2 x 64), b3 (2), weights
  * row-major (out x in).  Inputs are standardised as (X - mu) / sd when mu, sd

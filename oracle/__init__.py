@@ -515,6 +515,31 @@ def spectral_features(s, z, m: int):
     return _features_from_norms(np.linalg.norm(s), norms, m, n)
 
 
+def training_targets(s, r7):
+    """Regression targets of the interval predictor for a spectrum s and its
+    power-sequence estimate r_7: (log(sigma_max / r_7), log(sigma_max /
+    sigma_min)), i.e. how far the cheap estimate sits below sigma_max and the
+    log condition number; the learned bound of Section 3 is sigma_max <=
+    r_7 exp(t_1), sigma_min >= sigma_max exp(-t_2).  sigma_min is clamped at
+    1e-30 so that singular spectra give a finite target."""
+    s = np.asarray(s, dtype=np.float64)
+    smax = s.max()
+    smin = max(s.min(), 1e-30)
+    return np.array([np.log(smax / float(r7)), np.log(smax / smin)])
+
+
+def feature_stats(F):
+    """Standardisation of the predictor's inputs: per column of F (rows x 8)
+    the mean and the sample standard deviation (divisor rows - 1), the latter
+    clamped at 1e-3 so that a constant feature (log(m / n) on square-only
+    data) does not divide by zero."""
+    F = np.asarray(F, dtype=np.float64)
+    rows = F.shape[0]
+    mu = F.sum(axis=0) / rows
+    var = ((F - mu) ** 2).sum(axis=0) / max(rows - 1, 1)
+    return mu, np.maximum(np.sqrt(var), 1e-3)
+
+
 def mlp_unpack(p):
     p = np.asarray(p, dtype=np.float64)
     o = 0

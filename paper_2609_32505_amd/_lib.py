@@ -81,6 +81,8 @@ SIGNATURES = {
     "svdp_bound_features": (c_i32, [c_vp, ctypes.POINTER(Params), c_vp, c_i64, c_i64, c_vp, c_vp,
                                     c_vp, c_vp, c_sz, c_vp]),
     "svdp_spectral_features": (c_i32, [c_vp, c_vp, c_i64, c_i64, c_vp, c_vp, c_vp, c_vp]),
+    "svdp_training_targets": (c_i32, [c_vp, c_vp, c_i64, c_i64, c_vp, c_vp]),
+    "svdp_feature_stats": (c_i32, [c_vp, c_i64, c_vp, c_vp, c_vp]),
     "svdp_mlp_fwd": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_i64, c_vp, c_vp, c_vp]),
     "svdp_mlp_bwd_ws_bytes": (c_sz, [c_i64]),
     "svdp_mlp_bwd": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_i64, c_vp, c_vp, c_sz, c_vp]),

@@ -252,6 +252,27 @@ def spectral_features(s, z, m_over_n):
     return F, aux
 
 
+def training_targets(s, aux):
+    """(log(max s / r_7), log(max s / min s)) per row (svdp_training_targets)."""
+    s = _req(s, "s"); aux = _req(aux, "aux")
+    rows, n = s.shape
+    T = torch.empty((rows, 2), device=s.device)
+    check(load().svdp_training_targets(s.data_ptr(), aux.data_ptr(), rows, n, T.data_ptr(), _stream()),
+          "training_targets")
+    return T
+
+
+def feature_stats(F):
+    """Column means and sample standard deviations (clamped at 1e-3) of F
+    (rows x 8), by svdp_feature_stats."""
+    F = _req(F, "F")
+    mu = torch.empty(8, device=F.device)
+    sd = torch.empty(8, device=F.device)
+    check(load().svdp_feature_stats(F.data_ptr(), F.shape[0], mu.data_ptr(), sd.data_ptr(), _stream()),
+          "feature_stats")
+    return mu, sd
+
+
 def mlp_fwd(P, X, mu=None, sd=None, keep_act=True):
     P = _req(P, "params"); X = _req(X, "X")
     rows = X.shape[0]

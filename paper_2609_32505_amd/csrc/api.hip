@@ -344,7 +344,7 @@ struct FwdWs {
   void *Y0, *Y1;  // BF16 iterates (never aliasing the FP32 ones)
   void *Yt0, *Yt1;  // their transposes (n x m, BF16): the Gram's operands, contiguous in k
   void* eigh;
-  float *scale, *conv, *resid, *colsum, *rowmax, *fro2, *coef, *rcoef, *F, *aux, *mlpout, *nrm, *y0, *y1;
+  float *scale, *conv, *resid, *colsum, *rowmax, *fro2, *fpart, *coef, *rcoef, *F, *aux, *mlpout, *nrm, *y0, *y1;
   float* qr;   // QR completion scratch: 2 m per matrix
   float* qrc;  // blocked QR: projection coefficients, n x kQrBlock per matrix
   float *qrg, *qrr;  // blocked QR: a block's Gram matrix and CholeskyQR factor
@@ -373,6 +373,7 @@ FwdWs carve_fwd(void* base, const svdp_params* p, size_t* total) {
   w.colsum = c.take<float>(b * n);
   w.rowmax = c.take<float>(b);
   w.fro2 = c.take<float>(b);
+  w.fpart = c.take<float>(b * norms_blocks(n));
   w.coef = c.take<float>(b * 64 * 2);
   w.rcoef = c.take<float>(64 * 2);
   w.F = c.take<float>(b * 8);
@@ -533,7 +534,8 @@ svdp_status conservative_fp32(Ctx& c, const int* mask) {
   FwdWs& w = c.w;
   const int B = c.batch, m = c.m, n = c.n;
   ProfScope phase_bound(PROF_PHASE_BOUND, c.st);
-  HIPCHK(norms_launch(c.A, c.lda, c.sA, B, m, n, w.colsum, w.rowmax, w.fro2, w.flags, mask, c.st), "norms");
+  HIPCHK(norms_launch(c.A, c.lda, c.sA, B, m, n, w.colsum, w.rowmax, w.fro2, w.fpart, w.flags, mask, c.st),
+         "norms");
   if (p->poly == SVDP_POLY_PE)
     HIPCHK(fro_scale_launch(w.fro2, B, w.scale, mask, c.st), "scale");
   else
@@ -595,7 +597,8 @@ svdp_status bounded(Ctx& c) {
   ProfScope phase(PROF_PHASE_BOUND, c.st);
   if (p->bound == SVDP_BOUND_LEARNED) {
     // features: |A|_F^2 via the row pass, then the alternating power sequence
-    HIPCHK(norms_launch(c.A, c.lda, c.sA, B, m, n, w.colsum, w.rowmax, w.fro2, w.flags, nullptr, c.st), "norms");
+    HIPCHK(norms_launch(c.A, c.lda, c.sA, B, m, n, w.colsum, w.rowmax, w.fro2, w.fpart, w.flags, nullptr,
+                        c.st), "norms");
     HIPCHK(vnorm_launch(p->probe, n, B, n, w.nrm, 0, c.st), "probe norm");
     const float* x = p->probe;
     int64_t sx = n;
@@ -1491,7 +1494,7 @@ svdp_status svdp_bound_features(svdp_handle* h, const svdp_params* p, const floa
   hipStream_t st = (hipStream_t)stream;
   const int B = (int)p->batch, m = (int)p->m, n = (int)p->n;
   HIPCHK(fill_i32(w.flags, 0, B, st), "flags");
-  HIPCHK(norms_launch(A, lda, sA, B, m, n, w.colsum, w.rowmax, w.fro2, w.flags, nullptr, st), "norms");
+  HIPCHK(norms_launch(A, lda, sA, B, m, n, w.colsum, w.rowmax, w.fro2, w.fpart, w.flags, nullptr, st), "norms");
   HIPCHK(vnorm_launch(probe, n, B, n, w.nrm, 0, st), "probe norm");
   const float* x = probe;
   int64_t sx = n;
@@ -1513,6 +1516,22 @@ svdp_status svdp_spectral_features(const float* sv, const float* z, int64_t rows
   REQ(sv); REQ(z); REQ(m_over_n); REQ(F); REQ(aux);
   if (rows < 0 || n < 1 || rows > (1 << 26)) return fail(SVDP_ERR_SHAPE, "bad rows / n");
   HIPCHK(spectral_features_launch(sv, z, (int)rows, (int)n, m_over_n, F, aux, (hipStream_t)stream), "features");
+  return SVDP_OK;
+}
+
+svdp_status svdp_training_targets(const float* sv, const float* aux, int64_t rows, int64_t n, float* T,
+                                  void* stream) {
+  if (rows == 0) return SVDP_OK;
+  REQ(sv); REQ(aux); REQ(T);
+  if (rows < 0 || n < 1 || rows > (1 << 26)) return fail(SVDP_ERR_SHAPE, "bad rows / n");
+  HIPCHK(training_targets_launch(sv, aux, (int)rows, (int)n, T, (hipStream_t)stream), "training targets");
+  return SVDP_OK;
+}
+
+svdp_status svdp_feature_stats(const float* F, int64_t rows, float* mu, float* sd, void* stream) {
+  REQ(F); REQ(mu); REQ(sd);
+  if (rows < 1 || rows > (1 << 26)) return fail(SVDP_ERR_SHAPE, "need 1 <= rows <= 2^26");
+  HIPCHK(feature_stats_launch(F, (int)rows, mu, sd, (hipStream_t)stream), "feature stats");
   return SVDP_OK;
 }
 

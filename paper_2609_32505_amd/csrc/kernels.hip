@@ -27,17 +27,16 @@ SVDP_DEV bool skip(const int* mask, int b) { return mask && !mask[b]; }
 
 // ------------------------------------------------------------ normalisation
 
-// one wave per row: row abs sum -> rowmax, squares -> fro2, non-finite flag
-// Row sums of |A| (their maximum, the infinity norm), |A|_F^2 and the
-// non-finite flag: a workgroup reduces rows_per rows (a wave per row at a
-// time), then adds one atomic per quantity.
+// Row sums of |A| (their maximum, the infinity norm) and the non-finite
+// flag: a workgroup reduces rows_per rows (a wave per row at a time), then
+// takes one atomic maximum and one atomic or (both order-independent).
 __global__ void k_rownorms(const float* A, int64_t lda, int64_t sA, int m, int n, int rows_per, float* rowmax,
-                           float* fro2, int* flags, const int* mask) {
+                           int* flags, const int* mask) {
   const int b = blockIdx.y;
   if (skip(mask, b)) return;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int r0 = blockIdx.x * rows_per, r1 = min(m, r0 + rows_per);
-  float mx = 0.f, q = 0.f;
+  float mx = 0.f;
   bool bad = false;
   for (int i = r0 + w; i < r1; i += 4) {
     const float* r = A + b * sA + (int64_t)i * lda;
@@ -46,36 +45,66 @@ __global__ void k_rownorms(const float* A, int64_t lda, int64_t sA, int m, int n
       const float v = r[j];
       bad |= !isfinite(v);
       s += fabsf(v);
-      q += v * v;
     }
     s = wave_sum(s);
     mx = fmaxf(mx, isfinite(s) ? s : 0.f);
   }
-  q = wave_sum(q);
   const int anybad = __ballot(bad) != 0ull;
-  __shared__ float smx[4], sq[4];
+  __shared__ float smx[4];
   __shared__ int sbad[4];
-  if (lane == 0) { smx[w] = mx; sq[w] = q; sbad[w] = anybad; }
+  if (lane == 0) { smx[w] = mx; sbad[w] = anybad; }
   __syncthreads();
   if (threadIdx.x == 0) {
     const float m4 = fmaxf(fmaxf(smx[0], smx[1]), fmaxf(smx[2], smx[3]));
     atomic_max_pos(rowmax + b, m4);
-    atomicAdd(fro2 + b, sq[0] + sq[1] + sq[2] + sq[3]);
     if (sbad[0] | sbad[1] | sbad[2] | sbad[3]) atomicOr(flags + b, SVDP_FLAG_NONFINITE);
   }
 }
 
-__global__ void k_colsums(const float* A, int64_t lda, int64_t sA, int m, int n, int rows_per,
-                          float* colsum, const int* mask) {
-  const int b = blockIdx.z;
+// Column pass, one workgroup of 16 waves per 64 columns of one matrix:
+// colsum[j] = sum_i |a_ij| and part[blk] = the block's sum of squares.  Wave
+// w takes rows w, w + 16, ...; the 16 partial columns are added in wave order
+// and the squares by a fixed shuffle tree, so the results do not depend on
+// scheduling (no atomics).
+__global__ __launch_bounds__(1024) void k_colnorms(const float* A, int64_t lda, int64_t sA, int m, int n,
+                                                   float* colsum, float* part, int nblk, const int* mask) {
+  const int b = blockIdx.y;
   if (skip(mask, b)) return;
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
-  const int i0 = blockIdx.y * rows_per, i1 = min(m, i0 + rows_per);
-  const float* p = A + b * sA + j;
-  float s = 0.f;
-  for (int i = i0; i < i1; ++i) s += fabsf(p[(int64_t)i * lda]);
-  atomicAdd(colsum + (int64_t)b * n + j, s);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int j = blockIdx.x * 64 + lane;
+  float s = 0.f, q = 0.f;
+  if (j < n) {
+    const float* p = A + b * sA + j;
+#pragma unroll 4
+    for (int i = w; i < m; i += 16) {
+      const float v = p[(int64_t)i * lda];
+      s += fabsf(v);
+      q += v * v;
+    }
+  }
+  __shared__ float ls[16][64], lq[16][64];
+  ls[w][lane] = s;
+  lq[w][lane] = q;
+  __syncthreads();
+  if (w == 0) {
+    float cs = 0.f, cq = 0.f;
+    for (int k = 0; k < 16; ++k) {
+      cs += ls[k][lane];
+      cq += lq[k][lane];
+    }
+    if (j < n) colsum[(int64_t)b * n + j] = cs;
+    cq = wave_sum(cq);
+    if (lane == 0) part[(int64_t)b * nblk + blockIdx.x] = cq;
+  }
+}
+
+// |A[b]|_F^2 = the column blocks' sums of squares added in block order
+__global__ void k_fro_finalize(const float* part, int nblk, int batch, float* fro2, const int* mask) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= batch || skip(mask, b)) return;
+  float t = 0.f;
+  for (int k = 0; k < nblk; ++k) t += part[(int64_t)b * nblk + k];
+  fro2[b] = t;
 }
 
 __global__ void k_ns_scale(const float* colsum, const float* rowmax, int batch, int n, float* scale,
@@ -703,18 +732,29 @@ __global__ void k_matvec_n(const float* A, int64_t lda, int64_t sA, int m, int n
   s = wave_sum(s);
   if (lane == 0) y[b * sy + i] = s * matvec_scale(fro2, b);
 }
-// y = A^T x: thread per column over a chunk of rows, atomics into cleared y
-__global__ void k_matvec_t(const float* A, int64_t lda, int64_t sA, int m, int n, int rows_per,
-                           const float* x, int64_t sx, float* y, int64_t sy, const float* fro2) {
-  const int b = blockIdx.z;
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
-  const int i0 = blockIdx.y * rows_per, i1 = min(m, i0 + rows_per);
-  const float* p = A + b * sA + j;
-  const float* xb = x + b * sx;
+// y = A^T x: one workgroup of 16 waves per 64 columns, wave w over rows w,
+// w + 16, ...; the 16 partial sums are added in wave order (deterministic)
+__global__ __launch_bounds__(1024) void k_matvec_t(const float* A, int64_t lda, int64_t sA, int m, int n,
+                                                   const float* x, int64_t sx, float* y, int64_t sy,
+                                                   const float* fro2) {
+  const int b = blockIdx.y;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int j = blockIdx.x * 64 + lane;
   float s = 0.f;
-  for (int i = i0; i < i1; ++i) s += p[(int64_t)i * lda] * xb[i];
-  atomicAdd(y + b * sy + j, s * matvec_scale(fro2, b));
+  if (j < n) {
+    const float* p = A + b * sA + j;
+    const float* xb = x + b * sx;
+#pragma unroll 4
+    for (int i = w; i < m; i += 16) s += p[(int64_t)i * lda] * xb[i];
+  }
+  __shared__ float ls[16][64];
+  ls[w][lane] = s;
+  __syncthreads();
+  if (w == 0 && j < n) {
+    float t = 0.f;
+    for (int k = 0; k < 16; ++k) t += ls[k][lane];
+    y[b * sy + j] = t * matvec_scale(fro2, b);
+  }
 }
 
 // sum of squares in FP64: no overflow before the square root
@@ -787,6 +827,74 @@ __global__ void k_spectral_features(const float* s, const float* z, int rows, in
     double nr[8];
     for (int k = 0; k < 8; ++k) nr[k] = sqrt(acc[k]);
     features_from(sqrt(acc[8]), nr, (double)n, (double)m_over_n[row], F + (int64_t)row * 8, aux + (int64_t)row * 2);
+  }
+}
+
+// Training targets of the interval predictor, one wave per row: with
+// smax, smin the largest and smallest entry of the row's spectrum s and
+// r7 = aux[row][0] its power-sequence estimate, T = (log(smax / r7),
+// log(smax / smin)) (smin clamped at 1e-30).
+__global__ void k_training_targets(const float* s, const float* aux, int rows, int n, float* T) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + w;
+  if (row >= rows) return;
+  const float* sr = s + (int64_t)row * n;
+  float mx = 0.f, mn = INFINITY;
+  for (int j = lane; j < n; j += 64) {
+    mx = fmaxf(mx, sr[j]);
+    mn = fminf(mn, sr[j]);
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    mx = fmaxf(mx, __shfl_xor(mx, off));
+    mn = fminf(mn, __shfl_xor(mn, off));
+  }
+  if (lane == 0) {
+    const double smax = mx, smin = fmax((double)mn, 1e-30), r7 = aux[2 * (int64_t)row];
+    T[2 * (int64_t)row] = (float)log(smax / r7);
+    T[2 * (int64_t)row + 1] = (float)log(smax / smin);
+  }
+}
+
+// Feature standardisation of a training set, one workgroup: mu = mean of
+// each of the 8 columns of F (rows x 8), sd = its sample standard deviation
+// (divisor rows - 1), clamped at 1e-3; FP64 sums in a fixed order (each
+// thread a fixed set of rows, then a tree in LDS), so the result does not
+// depend on scheduling.
+__global__ __launch_bounds__(256) void k_feature_stats(const float* F, int rows, float* mu, float* sd) {
+  __shared__ double red[2][8][256];
+  const int t = threadIdx.x;
+  double a[8], q[8];
+  for (int f = 0; f < 8; ++f) a[f] = q[f] = 0.0;
+  for (int r = t; r < rows; r += 256)
+    for (int f = 0; f < 8; ++f) {
+      const double v = F[(int64_t)r * 8 + f];
+      a[f] += v;
+    }
+  for (int f = 0; f < 8; ++f) red[0][f][t] = a[f];
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (t < st)
+      for (int f = 0; f < 8; ++f) red[0][f][t] += red[0][f][t + st];
+    __syncthreads();
+  }
+  double mean[8];
+  for (int f = 0; f < 8; ++f) mean[f] = red[0][f][0] / fmax((double)rows, 1.0);
+  // second pass on the centred values
+  for (int r = t; r < rows; r += 256)
+    for (int f = 0; f < 8; ++f) {
+      const double v = F[(int64_t)r * 8 + f] - mean[f];
+      q[f] += v * v;
+    }
+  for (int f = 0; f < 8; ++f) red[1][f][t] = q[f];
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (t < st)
+      for (int f = 0; f < 8; ++f) red[1][f][t] += red[1][f][t + st];
+    __syncthreads();
+  }
+  if (t < 8) {
+    mu[t] = (float)mean[t];
+    sd[t] = (float)fmax(sqrt(red[1][t][0] / fmax((double)rows - 1.0, 1.0)), 1e-3);
   }
 }
 
@@ -1065,19 +1173,19 @@ inline int grid1(int64_t total, int cap = 2048) { return (int)std::max<int64_t>(
 #define LAUNCH_CHECK() return hipGetLastError()
 
 hipError_t norms_launch(const float* A, int64_t lda, int64_t sA, int batch, int m, int n,
-                        float* colsum, float* rowmax, float* fro2, int* flags, const int* mask,
+                        float* colsum, float* rowmax, float* fro2, float* part, int* flags, const int* mask,
                         hipStream_t st) {
   hipError_t e;
-  if ((e = fill_f32(colsum, 0.f, (int64_t)batch * n, st))) return e;
   if ((e = fill_f32(rowmax, 0.f, batch, st))) return e;
-  if ((e = fill_f32(fro2, 0.f, batch, st))) return e;
   const int rows_wg = 64;
   hipLaunchKernelGGL(k_rownorms, dim3(cdiv(m, rows_wg), batch), dim3(256), 0, st, A, lda, sA, m, n, rows_wg,
-                     rowmax, fro2, flags, mask);
+                     rowmax, flags, mask);
   if ((e = hipGetLastError())) return e;
-  const int rows_per = 256;
-  hipLaunchKernelGGL(k_colsums, dim3(cdiv(n, 256), cdiv(m, rows_per), batch), dim3(256), 0, st, A, lda,
-                     sA, m, n, rows_per, colsum, mask);
+  const int nblk = norms_blocks(n);
+  hipLaunchKernelGGL(k_colnorms, dim3(nblk, batch), dim3(1024), 0, st, A, lda, sA, m, n, colsum, part, nblk,
+                     mask);
+  if ((e = hipGetLastError())) return e;
+  hipLaunchKernelGGL(k_fro_finalize, dim3(cdiv(batch, 256)), dim3(256), 0, st, part, nblk, batch, fro2, mask);
   LAUNCH_CHECK();
 }
 
@@ -1086,6 +1194,17 @@ hipError_t transpose_bf16_launch(const void* X, int batch, int m, int n, void* X
   if (batch <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_transpose_bf16, dim3(cdiv(n, 32), cdiv(m, 32), batch), dim3(32, 8), 0, st,
                      (const bf16_t*)X, m, n, (bf16_t*)Xt, mask);
+  return hipGetLastError();
+}
+
+hipError_t training_targets_launch(const float* s, const float* aux, int rows, int n, float* T, hipStream_t st) {
+  if (rows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_training_targets, dim3(cdiv(rows, 4)), dim3(256), 0, st, s, aux, rows, n, T);
+  return hipGetLastError();
+}
+
+hipError_t feature_stats_launch(const float* F, int rows, float* mu, float* sd, hipStream_t st) {
+  hipLaunchKernelGGL(k_feature_stats, dim3(1), dim3(256), 0, st, F, rows, mu, sd);
   return hipGetLastError();
 }
 
@@ -1240,12 +1359,8 @@ hipError_t matvec_launch(const float* A, int64_t lda, int64_t sA, int batch, int
                        sy, fro2);
     LAUNCH_CHECK();
   }
-  hipError_t e;
-  // y cleared by a strided fill: batch rows of length n with stride sy
-  if ((e = fill_f32(y, 0.f, (int64_t)(batch - 1) * sy + n, st))) return e;
-  const int rows_per = 256;
-  hipLaunchKernelGGL(k_matvec_t, dim3(cdiv(n, 256), cdiv(m, rows_per), batch), dim3(256), 0, st, A, lda,
-                     sA, m, n, rows_per, x, sx, y, sy, fro2);
+  hipLaunchKernelGGL(k_matvec_t, dim3(cdiv(n, 64), batch), dim3(1024), 0, st, A, lda, sA, m, n, x, sx, y, sy,
+                     fro2);
   LAUNCH_CHECK();
 }
 

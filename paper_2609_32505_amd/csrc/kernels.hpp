@@ -5,12 +5,16 @@
 
 // ---- normalisation (Algorithm 3): s_b = sqrt(|A_b|_1 |A_b|_inf) ----------
 // colsum: batch x n scratch, rowmax/colmax/fro2: batch floats (all cleared here).
+// per-matrix partial sums of the column pass (norms_launch's part buffer)
+inline int norms_blocks(int64_t n) { return (int)((n + 63) / 64); }
 hipError_t norms_launch(const float* A, int64_t lda, int64_t sA, int batch, int m, int n,
-                        float* colsum, float* rowmax, float* fro2, int* flags,
-                        const int* mask, hipStream_t st);
+                        float* colsum, float* rowmax, float* fro2, float* part, int* flags, const int* mask,
+                        hipStream_t st);
 // scale[b] = sqrt(max_j colsum[b, j] * rowmax[b]) (1 for a zero matrix)
 hipError_t transpose_bf16_launch(const void* X, int batch, int m, int n, void* Xt, const int* mask,
                                  hipStream_t st);
+hipError_t training_targets_launch(const float* s, const float* aux, int rows, int n, float* T, hipStream_t st);
+hipError_t feature_stats_launch(const float* F, int rows, float* mu, float* sd, hipStream_t st);
 hipError_t fro_scale_launch(const float* fro2, int batch, float* scale, const int* mask, hipStream_t st);
 hipError_t ns_scale_launch(const float* colsum, const float* rowmax, int batch, int n,
                            float* scale, const int* mask, hipStream_t st);

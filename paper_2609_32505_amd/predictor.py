@@ -102,10 +102,7 @@ def features_targets(groups, device="cuda"):
         z = torch.from_numpy(Z).to(device)
         mn = torch.from_numpy(M).to(device)
         F, aux = api.spectral_features(s, z, mn)
-        smax = s.max(dim=1).values.double()
-        smin = s.min(dim=1).values.double().clamp_min(1e-30)
-        r7 = aux[:, 0].double()
-        T = torch.stack([torch.log(smax / r7), torch.log(smax / smin)], dim=1).float()
+        T = api.training_targets(s, aux)
         Fs.append(F)
         Ts.append(T)
     return torch.cat(Fs), torch.cat(Ts)
@@ -116,8 +113,7 @@ def train(F, T, steps: int = 3000, batch: int = 2048, lr: float = 2e-3, seed: in
     """Train the 8-64-64-2 MLP with the library's kernels.  Returns the model
     vector (params + feature means + stds) as float32 numpy, and the losses."""
     dev = F.device
-    mu = F.mean(dim=0)
-    sd = F.std(dim=0).clamp_min(1e-3)
+    mu, sd = api.feature_stats(F)
     g = torch.Generator(device="cpu").manual_seed(seed)
     P = torch.empty(4866)
     o = 0
@@ -128,7 +124,10 @@ def train(F, T, steps: int = 3000, batch: int = 2048, lr: float = 2e-3, seed: in
         o += fan_out
     P = P.to(dev)
     # start the output bias at the target means so the quantiles move from there
-    P[4864:4866] = T.mean(dim=0)
+    # (the first two columns of T padded to 8 give their means)
+    Tpad = torch.zeros((T.shape[0], 8), device=dev)
+    Tpad[:, :2] = T
+    P[4864:4866] = api.feature_stats(Tpad)[0][:2]
     m1 = torch.zeros_like(P)
     v1 = torch.zeros_like(P)
     rows = F.shape[0]

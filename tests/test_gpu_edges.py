@@ -323,6 +323,23 @@ def test_repeatable(api):
     r2 = [t.cpu().numpy() for t in api.svd_fwd(dev(A))[:3]]
     for a, b in zip(r1, r2):
         np.testing.assert_array_equal(a, b)
+    # the learned BF16 path too: its sketch features (|A|_F, column sums,
+    # A^T x) are reduced in a fixed order, so the predicted interval, the
+    # schedule and every output repeat bit for bit (ragged: 300 x 200)
+    from paper_2609_32505_amd import predictor
+    h = api.Handle()
+    h.set_model(predictor.load())
+    A, _ = inputs.batch_with_spectra(95, 6, 300, 200, lambda r: inputs.log_uniform(r, 200, 1e-4, 1.0))
+    probe = dev(inputs.probe(96, 6, 200))
+    F1, _ = api.bound_features(dev(A), probe, h)
+    F2, _ = api.bound_features(dev(A), probe, h)
+    np.testing.assert_array_equal(F1.cpu().numpy(), F2.cpu().numpy())
+    outs = []
+    for _ in range(2):
+        U, S, V, info = api.svd_fwd(dev(A), handle=h, precision=1, bound=1, probe=probe)
+        outs.append([t.cpu().numpy() for t in (U, S, V)] + [api.info_to_numpy(info)["iters"]])
+    for a, b in zip(outs[0], outs[1]):
+        np.testing.assert_array_equal(a, b)
 
 
 def test_autograd_svd_and_polar(api):

@@ -203,6 +203,49 @@ def test_features_orthogonal_invariance_and_scale(orc):
     assert f1[-1] == pytest.approx(np.log(m / n)) and f1[-2] == pytest.approx(np.log(n))
 
 
+def test_training_targets_closed_forms(orc):
+    # geometric spectrum of condition kappa: second target is log(kappa);
+    # a probe on the top singular direction makes r_7 = sigma_max exactly
+    n, kappa = 40, 1e4
+    s = inputs.geometric(n, kappa) * 3.0
+    z = np.zeros(n); z[0] = 1.0
+    f, r7, _ = orc.spectral_features(s, z, n)
+    T = orc.training_targets(s, r7)
+    assert T[0] == pytest.approx(0.0, abs=1e-12)
+    assert T[1] == pytest.approx(np.log(kappa), rel=1e-12)
+    # two equal singular values at the top, probe spread over both: still exact
+    s2 = np.array([2.0, 2.0, 0.5, 0.1]); z2 = np.array([1.0, -1.0, 0.0, 0.0])
+    T2 = orc.training_targets(s2, orc.spectral_features(s2, z2, 4)[1])
+    assert T2[0] == pytest.approx(0.0, abs=1e-12) and T2[1] == pytest.approx(np.log(20.0))
+    # a probe on the bottom direction: r_7 = sigma_min, both targets log(kappa)
+    z3 = np.zeros(n); z3[-1] = 1.0
+    T3 = orc.training_targets(s, orc.spectral_features(s, z3, n)[1])
+    np.testing.assert_allclose(T3, [np.log(kappa)] * 2, rtol=1e-12)
+    # a singular spectrum: the clamp gives a finite second target
+    T4 = orc.training_targets(np.array([1.0, 0.0]), 1.0)
+    assert T4[1] == pytest.approx(np.log(1e30))
+    # random probe: r_7 below sigma_max, so the first target is >= 0
+    z5 = np.random.default_rng(5).standard_normal(n)
+    assert orc.training_targets(s, orc.spectral_features(s, z5, n)[1])[0] >= 0.0
+
+
+def test_feature_stats_pins(orc):
+    import statistics
+    rng = np.random.default_rng(46)
+    F = rng.standard_normal((37, 8)) * np.arange(1, 9) + np.arange(8)
+    mu, sd = orc.feature_stats(F)
+    for j in range(8):
+        assert mu[j] == pytest.approx(statistics.fmean(F[:, j]), rel=1e-13)
+        assert sd[j] == pytest.approx(statistics.stdev(F[:, j]), rel=1e-12)
+    # column 0 = 1..N: mean (N + 1) / 2, sample variance N (N + 1) / 12
+    N = 101
+    G = np.zeros((N, 8)); G[:, 0] = np.arange(1, N + 1); G[:, 1] = 5.0
+    mu, sd = orc.feature_stats(G)
+    assert mu[0] == pytest.approx((N + 1) / 2) and sd[0] == pytest.approx(np.sqrt(N * (N + 1) / 12))
+    # constant column: mean exact, deviation at the clamp
+    assert mu[1] == 5.0 and sd[1] == 1e-3 and sd[2] == 1e-3
+
+
 def test_mlp_backward_vs_fd(orc):
     rng = np.random.default_rng(44)
     p = rng.standard_normal(orc.N_PARAMS) * 0.3
