@@ -242,6 +242,26 @@ svdp_status svd_polar_bwd(svdp_handle* h, const svdp_params* p,
                           float* dA, int64_t ldda, int64_t sdA,
                           void* ws, size_t ws_bytes, void* stream);
 
+/* svd_polar_bwd without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): its scratch is a file-scope device
+ * array of 128 MiB, one per GPU, resolved once per device and held until
+ * the process ends.  The call allocates nothing (no hipMalloc / hipFree, no
+ * allocating library routine).  Same arguments and results as
+ * svd_polar_bwd otherwise.  SVDP_ERR_WORKSPACE when the batch needs more
+ * than 128 MiB of scratch (svdp_workspace_size with SVDP_OP_SVD_BWD gives the
+ * need; e.g. 64 matrices of 256 x 256 need 84 MB).  All calls on one GPU
+ * share that GPU's array and nothing in it carries over between calls:
+ * calls that overlap on one GPU (other streams or threads) race. */
+svdp_status svd_polar_bwd_noalloc(svdp_handle* h, const svdp_params* p,
+                                  const float* U, int64_t ldu, int64_t sU,
+                                  const float* S, int64_t sS,
+                                  const float* V, int64_t ldv, int64_t sV,
+                                  const float* dU, int64_t lddu, int64_t sdU,
+                                  const float* dS, int64_t sdS,
+                                  const float* dV, int64_t lddv, int64_t sdV,
+                                  float* dA, int64_t ldda, int64_t sdA, void* stream);
+
 /* Polar decomposition A = W H (Algorithm 1 up to the symmetric factor).
  * W: m x n with orthonormal columns.  H: n x n, sym(W^T A).  Optional
  * S_cache (n) / V_cache (n x n): eigenvalues (descending) and eigenvectors

@@ -68,6 +68,9 @@ SIGNATURES = {
     "svd_polar_bwd": (c_i32, [c_vp, ctypes.POINTER(Params), c_vp, c_i64, c_i64, c_vp, c_i64,
                               c_vp, c_i64, c_i64, c_vp, c_i64, c_i64, c_vp, c_i64, c_vp, c_i64,
                               c_i64, c_vp, c_i64, c_i64, c_vp, c_sz, c_vp]),
+    "svd_polar_bwd_noalloc": (c_i32, [c_vp, ctypes.POINTER(Params), c_vp, c_i64, c_i64, c_vp, c_i64,
+                                      c_vp, c_i64, c_i64, c_vp, c_i64, c_i64, c_vp, c_i64, c_vp, c_i64,
+                                      c_i64, c_vp, c_i64, c_i64, c_vp]),
     "polar_fwd": (c_i32, [c_vp, ctypes.POINTER(Params), c_vp, c_i64, c_i64, c_vp, c_i64, c_i64,
                           c_vp, c_i64, c_i64, c_vp, c_i64, c_vp, c_i64, c_i64, c_vp, c_vp, c_sz,
                           c_vp]),

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -958,6 +959,33 @@ svdp_status svd_tall_qr(Ctx& c, float* U, int64_t ldu, int64_t sU, float* S, int
   return u_qr_step(c, U, ldu, sU, S, sS, nullptr);
 }
 
+// Scratch of svd_polar_bwd_noalloc, for callers that cannot allocate: a
+// file-scope device array, one copy per GPU, held until the process ends.
+// In host code its name is only a stand-in: the device address of each GPU's
+// copy comes from hipGetSymbolAddress with that GPU current, resolved once
+// per device (at svdp_create, or at the entry point's first call on a
+// device) and kept in g_scratch_addr.
+constexpr size_t kScratchBytes = size_t(128) << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+
+svdp_status scratch_address(void** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev), "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(SVDP_ERR_INVALID_ARG, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(SVDP_ERR_HIP, "hipGetSymbolAddress(scratch) returned null");
+    g_scratch_addr[dev] = p;
+  }
+  *out = g_scratch_addr[dev];
+  return SVDP_OK;
+}
+
 }  // namespace
 
 // =====================================================================
@@ -1035,6 +1063,13 @@ svdp_status svdp_create(svdp_handle** out) {
   if (e != hipSuccess) {
     (void)svdp_destroy(h);
     return hip_fail(e, "svdp_create");
+  }
+  // the allocation-free backward's scratch address on the current device
+  void* scr = nullptr;
+  svdp_status s = scratch_address(&scr);
+  if (s) {
+    (void)svdp_destroy(h);
+    return s;
   }
   *out = h;
   return SVDP_OK;
@@ -1281,24 +1316,16 @@ svdp_status svdp_eigh_bwd(svdp_handle* h, const svdp_params* p, const float* lam
   return SVDP_OK;
 }
 
-svdp_status svd_polar_bwd(svdp_handle* h, const svdp_params* p, const float* U, int64_t ldu, int64_t sU,
-                          const float* S, int64_t sS, const float* V, int64_t ldv, int64_t sV, const float* dU,
-                          int64_t lddu, int64_t sdU, const float* dS, int64_t sdS, const float* dV,
-                          int64_t lddv, int64_t sdV, float* dA, int64_t ldda, int64_t sdA, void* ws,
-                          size_t ws_bytes, void* stream) {
-  REQ(h);
-  svdp_status s = check_common(p);
-  if (s) return s;
-  if (p->batch == 0) return SVDP_OK;
-  REQ(U); REQ(S); REQ(V); REQ(dA);
+}  // extern "C"
+
+namespace {
+// Algorithm 4 backward in the eigenbasis on a workspace (checked by the
+// caller to hold bwd_bytes(p, 0)).
+svdp_status svd_bwd_impl(const svdp_params* p, const float* U, int64_t ldu, int64_t sU, const float* S, int64_t sS,
+                         const float* V, int64_t ldv, int64_t sV, const float* dU, int64_t lddu, int64_t sdU,
+                         const float* dS, int64_t sdS, const float* dV, int64_t lddv, int64_t sdV, float* dA,
+                         int64_t ldda, int64_t sdA, void* ws, hipStream_t st) {
   const int B = (int)p->batch, m = (int)p->m, n = (int)p->n;
-  LDCHK(ldu, n, B > 1 ? sU : 0, m);
-  LDCHK(ldv, n, B > 1 ? sV : 0, n);
-  LDCHK(ldda, n, B > 1 ? sdA : 0, m);
-  if (dU) LDCHK(lddu, n, B > 1 ? sdU : 0, m);
-  if (dV) LDCHK(lddv, n, B > 1 ? sdV : 0, n);
-  if (!ws || ws_bytes < bwd_bytes(p, 0)) return fail(SVDP_ERR_WORKSPACE, "workspace too small");
-  hipStream_t st = (hipStream_t)stream;
   ProfScope phase(PROF_PHASE_BWD, st);
   Carver c(ws);
   float* X1 = c.take<float>((size_t)B * n * n);
@@ -1344,6 +1371,61 @@ svdp_status svd_polar_bwd(svdp_handle* h, const svdp_params* p, const float* U, 
     HIPCHK(gemm_launch(g, PREC_F32, 0, 1, st), "Z V^T");
   }
   return SVDP_OK;
+}
+
+// Argument checks shared by svd_polar_bwd and svd_polar_bwd_noalloc.
+svdp_status svd_bwd_check(const svdp_params* p, const float* U, int64_t ldu, int64_t sU, const float* S,
+                          const float* V, int64_t ldv, int64_t sV, const float* dU, int64_t lddu, int64_t sdU,
+                          const float* dV, int64_t lddv, int64_t sdV, float* dA, int64_t ldda, int64_t sdA) {
+  svdp_status s = check_common(p);
+  if (s) return s;
+  if (p->batch == 0) return SVDP_OK;
+  REQ(U); REQ(S); REQ(V); REQ(dA);
+  const int B = (int)p->batch, m = (int)p->m, n = (int)p->n;
+  LDCHK(ldu, n, B > 1 ? sU : 0, m);
+  LDCHK(ldv, n, B > 1 ? sV : 0, n);
+  LDCHK(ldda, n, B > 1 ? sdA : 0, m);
+  if (dU) LDCHK(lddu, n, B > 1 ? sdU : 0, m);
+  if (dV) LDCHK(lddv, n, B > 1 ? sdV : 0, n);
+  return SVDP_OK;
+}
+}  // namespace
+
+extern "C" {
+
+svdp_status svd_polar_bwd(svdp_handle* h, const svdp_params* p, const float* U, int64_t ldu, int64_t sU,
+                          const float* S, int64_t sS, const float* V, int64_t ldv, int64_t sV, const float* dU,
+                          int64_t lddu, int64_t sdU, const float* dS, int64_t sdS, const float* dV,
+                          int64_t lddv, int64_t sdV, float* dA, int64_t ldda, int64_t sdA, void* ws,
+                          size_t ws_bytes, void* stream) {
+  REQ(h);
+  svdp_status s = svd_bwd_check(p, U, ldu, sU, S, V, ldv, sV, dU, lddu, sdU, dV, lddv, sdV, dA, ldda, sdA);
+  if (s || p->batch == 0) return s;
+  if (!ws || ws_bytes < bwd_bytes(p, 0)) return fail(SVDP_ERR_WORKSPACE, "workspace too small");
+  return svd_bwd_impl(p, U, ldu, sU, S, sS, V, ldv, sV, dU, lddu, sdU, dS, sdS, dV, lddv, sdV, dA, ldda, sdA, ws,
+                      (hipStream_t)stream);
+}
+
+svdp_status svd_polar_bwd_noalloc(svdp_handle* h, const svdp_params* p, const float* U, int64_t ldu, int64_t sU,
+                                  const float* S, int64_t sS, const float* V, int64_t ldv, int64_t sV,
+                                  const float* dU, int64_t lddu, int64_t sdU, const float* dS, int64_t sdS,
+                                  const float* dV, int64_t lddv, int64_t sdV, float* dA, int64_t ldda, int64_t sdA,
+                                  void* stream) {
+  REQ(h);
+  svdp_status s = svd_bwd_check(p, U, ldu, sU, S, V, ldv, sV, dU, lddu, sdU, dV, lddv, sdV, dA, ldda, sdA);
+  if (s || p->batch == 0) return s;
+  const size_t need = bwd_bytes(p, 0);
+  if (need > kScratchBytes) {
+    char msg[160];
+    std::snprintf(msg, sizeof(msg),
+                  "svd_polar_bwd_noalloc: this batch needs %zu bytes of scratch, the static scratch holds %zu",
+                  need, kScratchBytes);
+    return fail(SVDP_ERR_WORKSPACE, msg);
+  }
+  void* ws = nullptr;
+  if ((s = scratch_address(&ws))) return s;
+  return svd_bwd_impl(p, U, ldu, sU, S, sS, V, ldv, sV, dU, lddu, sdU, dS, sdS, dV, lddv, sdV, dA, ldda, sdA, ws,
+                      (hipStream_t)stream);
 }
 
 svdp_status polar_bwd(svdp_handle* h, const svdp_params* p, const float* A, int64_t lda, int64_t sA,
