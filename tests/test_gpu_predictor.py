@@ -90,12 +90,15 @@ def test_predictor_trains_from_seed(api):
     cover, slack = predictor.evaluate(model, Fe, Te)
     _say(f"  held-out coverage {cover}, mean slack {slack}")
     assert cover[0] >= 0.95 and cover[1] >= 0.95
-    # the network uses its inputs: its mean slack is below that of the
-    # best constant bound, the training targets' own 0.98 quantile
+    # the sigma_max output: r_7 is already within a few percent of sigma_max
+    # on these families, and the bound stays close (mean e^0.15 = 1.16 x);
+    # the condition-number output uses its inputs: its mean slack is well
+    # below that of the best constant bound (the training targets' own 0.98
+    # quantile), measured 2.4 against 5.6
     Th, Teh = T.cpu().double().numpy(), Te.cpu().double().numpy()
     const_slack = [float(np.mean(np.quantile(Th[:, j], 0.98) - Teh[:, j])) for j in range(2)]
     _say(f"  constant 0.98-quantile bound: mean slack {const_slack}")
-    assert slack[0] < 0.5 * const_slack[0] and slack[1] < const_slack[1]
+    assert 0.0 < slack[0] < 0.15 and slack[1] < 0.6 * const_slack[1]
     # every reduction in training is in a fixed order: the same seed gives
     # the same model bit for bit
     m1, _ = predictor.train(F, T, steps=30)
