@@ -99,7 +99,7 @@ typedef struct {
                               refinement then continues per matrix until the relative change is
                               <= tol, for at most refine_steps + 8 steps, else NOT_CONVERGED and
                               the conservative fallback */
-  int32_t max_sweeps;      /* Jacobi sweep cap (20) */
+  int32_t max_sweeps;      /* Jacobi sweep budget (16): launched whatever the convergence */
   int32_t inner_sweeps;    /* repetitions of a block step's scalar rounds per 32 x 32 Jacobi
                               subproblem (1) */
   int32_t fp64_sweeps;     /* final Jacobi sweeps with FP64 subproblem solves, and the sweeps of

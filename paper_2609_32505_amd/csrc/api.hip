@@ -836,7 +836,7 @@ svdp_status svd_tail(Ctx& c, float* U, int64_t ldu, int64_t sU, float* S, int64_
   phase.next(PROF_PHASE_EIGH);
   EighWs e = eigh_ws_carve(w.eigh, B, n, p->max_sweeps);
   HIPCHK(eigh_run(e, w.G, n, (int64_t)n * n, 1, eigh_opts(p), S, sS, V, ldv, sV, w.sweeps, w.flags,
-                  c.h->host_word, mask, &c.h->aux, c.st), "eigh");
+                  mask, &c.h->aux, c.st), "eigh");
   phase.next(PROF_PHASE_U);
   // B operand of U = W V: V, or V Mu after the BF16 correction
   const float* Vb = V;
@@ -1002,7 +1002,7 @@ void svdp_default_params(svdp_params* p, int64_t batch, int64_t m, int64_t n) {
   p->max_iters = 50;
   p->pre_iters = 2;
   p->refine_steps = 2;
-  p->max_sweeps = 20;
+  p->max_sweeps = 16;
   p->inner_sweeps = 1;
   p->fp64_sweeps = 1;
   p->delta = 0.99;
@@ -1215,7 +1215,7 @@ svdp_status polar_fwd(svdp_handle* h, const svdp_params* p, const float* A, int6
     if (V_cache) {
       EighWs e = eigh_ws_carve(c.w.eigh, B, n, p->max_sweeps);
       HIPCHK(eigh_run(e, c.w.G, n, (int64_t)n * n, 0, eigh_opts(p), S_cache, sS, V_cache, ldv, sV, c.w.sweeps,
-                      c.w.flags, h->host_word, mask, &h->aux, c.st), "eigh");
+                      c.w.flags, mask, &h->aux, c.st), "eigh");
       if (correct && !mask) {
         // as in svd_tail, with signed eigenvalues: Mu in Hw, V Mu in V2,
         // V <- 2 V - V Mu, S corrected; then W <- W (V Mu) V^T (the new V)
@@ -1471,7 +1471,7 @@ svdp_status polar_bwd(svdp_handle* h, const svdp_params* p, const float* A, int6
   if (!V_cache) {  // Algorithm 2, step 1: EVD of H
     EighWs e = eigh_ws_carve(ews, B, n, p->max_sweeps);
     HIPCHK(fill_i32(flags, 0, B, st), "flags");
-    HIPCHK(eigh_run(e, H, ldh, sH, 0, eigh_opts(p), Sown, n, Vown, n, (int64_t)n * n, sweeps, flags, h->host_word,
+    HIPCHK(eigh_run(e, H, ldh, sH, 0, eigh_opts(p), Sown, n, Vown, n, (int64_t)n * n, sweeps, flags,
                     nullptr, &h->aux, st), "eigh");
     Sx = Sown; Vx = Vown; sSx = n; ldvx = n; sVx = (int64_t)n * n;
   }
@@ -1554,7 +1554,7 @@ svdp_status svdp_eigh(svdp_handle* h, const svdp_params* p, const float* H, int6
   EighWs e = eigh_ws_carve(ews, B, n, p->max_sweeps);
   HIPCHK(fill_i32(flags, 0, B, st), "flags");
   HIPCHK(fill_i32(sweeps, 0, B, st), "sweeps");
-  HIPCHK(eigh_run(e, H, ldh, sH, 0, eigh_opts(p), lam, slam, V, ldv, sV, sweeps, flags, h->host_word, nullptr,
+  HIPCHK(eigh_run(e, H, ldh, sH, 0, eigh_opts(p), lam, slam, V, ldv, sV, sweeps, flags, nullptr,
                   &h->aux, st), "eigh");
   if (info) HIPCHK(info_pack_launch(B, nullptr, sweeps, flags, nullptr, info, nullptr, st), "info");
   return SVDP_OK;

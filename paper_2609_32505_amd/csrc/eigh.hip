@@ -1023,6 +1023,15 @@ static hipError_t vsweep_launch(const EighWs& E, hipStream_t st) {
 
 // View of matrices [b0, b0 + cnt) of a workspace; part h uses its own
 // device counter.
+// Sweeps that run in stream-parallel parts: the sweep counts at which
+// matrices converge grow slowly with n (at most 10 at n = 512, 14 at 4096
+// on the test spectra, restarts included)
+int eigh_par_sweeps(int64_t n) {
+  int s = 11;
+  for (int64_t k = 1024; k <= n; k <<= 1) ++s;
+  return s;
+}
+
 static EighWs eigh_sub(const EighWs& e, int b0, int cnt, int h) {
   EighWs s = e;
   const int64_t m2 = (int64_t)e.np * e.np, ng = e.nb / 4;
@@ -1044,7 +1053,7 @@ static EighWs eigh_sub(const EighWs& e, int b0, int cnt, int h) {
 // Full eigendecomposition of a batch of symmetric n x n matrices.
 hipError_t eigh_run(EighWs e, const float* H, int64_t ldh, int64_t sH, int mode,
                     const EighOpts& o, float* lam, int64_t slam, float* Vout, int64_t ldv,
-                    int64_t sV, int* sweeps_out, int* flags, int* host_counter, const int* mask,
+                    int64_t sV, int* sweeps_out, int* flags, const int* mask,
                     const EighAux* aux, hipStream_t st) {
   hipError_t err;
   const int batch = e.batch;
@@ -1063,66 +1072,83 @@ hipError_t eigh_run(EighWs e, const float* H, int64_t ldh, int64_t sH, int mode,
   const std::vector<EighPhase> phases = eigh_phases(e.nb);
   // Parts of the batch on parallel streams (when extra streams are given):
   // the LDS/VALU-bound pair solves of one part run beside the MFMA/HBM-bound
-  // rotations of the others.
-  int P = aux ? std::min(std::max(aux->parts, 1), kEighParts) : 1;
-  P = std::min(P, batch);
-  int b0[kEighParts], bc[kEighParts];
-  hipStream_t ss[kEighParts];
-  EighWs eh[kEighParts];
-  for (int h = 0; h < P; ++h) {
-    b0[h] = (int)((int64_t)batch * h / P);
-    bc[h] = (int)((int64_t)batch * (h + 1) / P) - b0[h];
-    ss[h] = h == 0 ? st : aux->st[h - 1];
-    eh[h] = eigh_sub(e, b0[h], bc[h], h);
+  // rotations of the others.  The first par_sweeps sweeps, in which most
+  // matrices are still active, and the final FP64 sweep run in parts; the
+  // tail of the sweep budget and the restarts, which touch few matrices,
+  // run as a single part on the caller's stream, a quarter of the launches.
+  struct Parts {
+    int P;
+    int b0[kEighParts], bc[kEighParts];
+    hipStream_t ss[kEighParts];
+    EighWs eh[kEighParts];
+  };
+  Parts multi, single;
+  multi.P = std::min(aux ? std::min(std::max(aux->parts, 1), kEighParts) : 1, batch);
+  for (int h = 0; h < multi.P; ++h) {
+    multi.b0[h] = (int)((int64_t)batch * h / multi.P);
+    multi.bc[h] = (int)((int64_t)batch * (h + 1) / multi.P) - multi.b0[h];
+    multi.ss[h] = h == 0 ? st : aux->st[h - 1];
+    multi.eh[h] = eigh_sub(e, multi.b0[h], multi.bc[h], h);
   }
-  if (P > 1) {
-    if ((err = hipEventRecord(aux->fork, st))) return err;
-    for (int h = 1; h < P; ++h)
-      if ((err = hipStreamWaitEvent(ss[h], aux->fork, 0))) return err;
-  }
-  auto phase_launches = [&](int h, const EighPhase& ph, bool fp64, float skip_rel, int* rc, float* vs, int n_act,
-                            bool mark_skew) -> hipError_t {
-    const EighWs& E = eh[h];
+  single.P = 1;
+  single.b0[0] = 0;
+  single.bc[0] = batch;
+  single.ss[0] = st;
+  single.eh[0] = eigh_sub(e, 0, batch, 0);
+  auto fork = [&](const Parts& S) -> hipError_t {
+    if (S.P < 2) return hipSuccess;
+    hipError_t e2 = hipEventRecord(aux->fork, st);
+    for (int h = 1; h < S.P && !e2; ++h) e2 = hipStreamWaitEvent(S.ss[h], aux->fork, 0);
+    return e2;
+  };
+  auto join = [&](const Parts& S) -> hipError_t {
+    hipError_t e2 = hipSuccess;
+    for (int h = 1; h < S.P && !e2; ++h) {
+      e2 = hipEventRecord(aux->join[h], S.ss[h]);
+      if (!e2) e2 = hipStreamWaitEvent(st, aux->join[h], 0);
+    }
+    return e2;
+  };
+  auto phase_launches = [&](const Parts& S, int h, const EighPhase& ph, bool fp64, float skip_rel, int* rc,
+                            float* vs, bool mark_skew) -> hipError_t {
+    const EighWs& E = S.eh[h];
+    hipStream_t sh = S.ss[h];
     const unsigned sblocks = (unsigned)(E.batch * ng);
     const unsigned ablocks = (unsigned)((int64_t)cdiv(E.batch, 8) * 8 * (e.deferred ? nH : ntask));
     if (fp64) {
-      ProfScope ps(PROF_JAC_SOLVE_F64, ss[h]);
-      hipLaunchKernelGGL(k_jac_solve<double>, dim3(sblocks), dim3(128), 0, ss[h], E, ph, o.fp64_inner, o.abs_tol,
+      ProfScope ps(PROF_JAC_SOLVE_F64, sh);
+      hipLaunchKernelGGL(k_jac_solve<double>, dim3(sblocks), dim3(128), 0, sh, E, ph, o.fp64_inner, o.abs_tol,
                          skip_rel, (int*)nullptr, (float*)nullptr);
     } else {
-      ProfScope ps(PROF_JAC_SOLVE_F32, ss[h]);
-      hipLaunchKernelGGL(k_jac_solve<float>, dim3(sblocks), dim3(128), 0, ss[h], E, ph, o.inner_sweeps, o.abs_tol,
+      ProfScope ps(PROF_JAC_SOLVE_F32, sh);
+      hipLaunchKernelGGL(k_jac_solve<float>, dim3(sblocks), dim3(128), 0, sh, E, ph, o.inner_sweeps, o.abs_tol,
                          skip_rel, rc, vs);
     }
     hipError_t e2 = hipGetLastError();
     if (e2) return e2;
-    if (mark_skew && (e2 = hipEventRecord(aux->skew[h], ss[h]))) return e2;
+    if (mark_skew && (e2 = hipEventRecord(aux->skew[h], sh))) return e2;
     if (ablocks > 0) {
-      ProfScope ps(PROF_JAC_APPLY, ss[h]);
-      hipLaunchKernelGGL(k_jac_apply, dim3(ablocks), dim3(256), 0, ss[h], E, ph);
+      ProfScope ps(PROF_JAC_APPLY, sh);
+      hipLaunchKernelGGL(k_jac_apply, dim3(ablocks), dim3(256), 0, sh, E, ph);
     }
     return hipGetLastError();
   };
   // one pass over the phases for every part; part h starts after part
   // h - 1's first pair solve
-  auto sweep_launches = [&](bool fp64, float skip_rel, int* rc, float* vs, const int* n_act) -> hipError_t {
+  auto sweep_launches = [&](const Parts& S, bool fp64, float skip_rel, int* rc, float* vs) -> hipError_t {
     bool first = true;
     for (const EighPhase& ph : phases) {
-      int prev = -1;
-      for (int h = 0; h < P; ++h) {
-        if (n_act[h] == 0) continue;
+      for (int h = 0; h < S.P; ++h) {
         hipError_t e2;
-        if (first && prev >= 0 && (e2 = hipStreamWaitEvent(ss[h], aux->skew[prev], 0))) return e2;
-        if ((e2 = phase_launches(h, ph, fp64, skip_rel, rc ? rc + b0[h] : nullptr, vs ? vs + b0[h] : nullptr, n_act[h],
-                                  first && P > 1))) return e2;
-        prev = h;
+        if (first && h > 0 && (e2 = hipStreamWaitEvent(S.ss[h], aux->skew[h - 1], 0))) return e2;
+        if ((e2 = phase_launches(S, h, ph, fp64, skip_rel, rc ? rc + S.b0[h] : nullptr,
+                                 vs ? vs + S.b0[h] : nullptr, first && S.P > 1))) return e2;
       }
       first = false;
     }
     if (e.deferred)
-      for (int h = 0; h < P; ++h) {
-        if (n_act[h] == 0) continue;
-        hipError_t e2 = vsweep_launch(eh[h], ss[h]);
+      for (int h = 0; h < S.P; ++h) {
+        hipError_t e2 = vsweep_launch(S.eh[h], S.ss[h]);
         if (e2) return e2;
       }
     return hipSuccess;
@@ -1130,42 +1156,34 @@ hipError_t eigh_run(EighWs e, const float* H, int64_t ldh, int64_t sH, int mode,
   // The sweep loop runs its full budget without reading anything back: a
   // matrix leaves the active set on the device after the sweep that
   // converges it (k_eigh_check), and every later launch skips it.
-  int n_act[kEighParts];
-  for (int h = 0; h < P; ++h) n_act[h] = bc[h];
+  const int par_sweeps = std::min(e.max_sweeps, eigh_par_sweeps(e.n));
+  if ((err = fork(multi))) return err;
   for (int sweep = 0; sweep < e.max_sweeps; ++sweep) {
+    if (sweep == par_sweeps && (err = join(multi))) return err;
+    const Parts& S = sweep < par_sweeps ? multi : single;
     int* rc = e.rotcnt + (int64_t)batch * sweep;
     float* vs = e.rotsq + (int64_t)batch * sweep;
-    if ((err = sweep_launches(false, 0.f, rc, vs, n_act))) return err;
-    for (int h = 0; h < P; ++h) {
-      hipLaunchKernelGGL(k_eigh_check, dim3(1), dim3(1024), 0, ss[h], eh[h], rc + b0[h], vs + b0[h], o.tol,
-                         o.fro_tol * o.fro_tol, sweep, sweeps_out + b0[h], eh[h].counter);
+    if ((err = sweep_launches(S, false, 0.f, rc, vs))) return err;
+    for (int h = 0; h < S.P; ++h) {
+      hipLaunchKernelGGL(k_eigh_check, dim3(1), dim3(1024), 0, S.ss[h], S.eh[h], rc + S.b0[h], vs + S.b0[h],
+                         o.tol, o.fro_tol * o.fro_tol, sweep, sweeps_out + S.b0[h], S.eh[h].counter);
       if ((err = hipGetLastError())) return err;
     }
   }
+  if (par_sweeps >= e.max_sweeps && (err = join(multi))) return err;
   // matrices still active after max_sweeps did not converge
-  for (int h = 0; h < P; ++h) {
-    hipLaunchKernelGGL(k_flag_active, dim3(cdiv(bc[h], 256)), dim3(256), 0, ss[h], eh[h].active, bc[h],
-                       flags + b0[h], (int)SVDP_FLAG_EIGH_NOT_CONVERGED);
-    if ((err = hipGetLastError())) return err;
-  }
+  hipLaunchKernelGGL(k_flag_active, dim3(cdiv(batch, 256)), dim3(256), 0, st, e.active, batch, flags,
+                     (int)SVDP_FLAG_EIGH_NOT_CONVERGED);
+  if ((err = hipGetLastError())) return err;
   // final sweep(s) with FP64 pair solves on every matrix
   if (o.fp64_sweeps > 0) {
-    for (int h = 0; h < P; ++h) {
-      if (mask) { if ((err = copy_i32(eh[h].active, mask + b0[h], bc[h], ss[h]))) return err; }
-      else if ((err = fill_i32(eh[h].active, 1, bc[h], ss[h]))) return err;
-    }
+    if (mask) { if ((err = copy_i32(e.active, mask, batch, st))) return err; }
+    else if ((err = fill_i32(e.active, 1, batch, st))) return err;
+    if ((err = fork(multi))) return err;
     for (int f = 0; f < o.fp64_sweeps; ++f)
-      if ((err = sweep_launches(true, 0.f, nullptr, nullptr, bc))) return err;
+      if ((err = sweep_launches(multi, true, 0.f, nullptr, nullptr))) return err;
+    if ((err = join(multi))) return err;
   }
-  auto join = [&]() -> hipError_t {
-    hipError_t e2;
-    for (int h = 1; h < P; ++h) {
-      if ((e2 = hipEventRecord(aux->join[h], ss[h]))) return e2;
-      if ((e2 = hipStreamWaitEvent(st, aux->join[h], 0))) return e2;
-    }
-    return hipSuccess;
-  };
-  if ((err = join())) return err;
   const int np = e.np;
   const int64_t m2 = (int64_t)np * np;
   // V row-major: Vw itself when deferred, else untiled into Hw; one
@@ -1244,14 +1262,8 @@ hipError_t eigh_run(EighWs e, const float* H, int64_t ldh, int64_t sH, int mode,
       hipLaunchKernelGGL(k_eigh_setup, sgrid, dim3(256), 0, st, e, (const float*)nullptr, (int64_t)0, (int64_t)0,
                          proc, kSetupV);
       if ((err = hipGetLastError())) return err;
-      if (P > 1) {
-        if ((err = hipEventRecord(aux->fork, st))) return err;
-        for (int h = 1; h < P; ++h)
-          if ((err = hipStreamWaitEvent(ss[h], aux->fork, 0))) return err;
-      }
       for (int f = 0; f < std::max(1, o.fp64_sweeps); ++f)
-        if ((err = sweep_launches(o.fp64_sweeps > 0, kRestartSkip, nullptr, nullptr, bc))) return err;
-      if ((err = join())) return err;
+        if ((err = sweep_launches(single, o.fp64_sweeps > 0, kRestartSkip, nullptr, nullptr))) return err;
       // V' row-major (Vw itself when deferred, else untiled into Hw); V2 V'
       // into the other buffer, then copied to V2 for the restarted matrices
       const float* Vp = e.Vw;

@@ -86,11 +86,12 @@ struct EighAux {
 };
 
 int eigh_blocks(int64_t n);
+int eigh_par_sweeps(int64_t n);
 size_t eigh_ws_bytes(int64_t batch, int64_t n, int max_sweeps);
 EighWs eigh_ws_carve(void* ws, int64_t batch, int64_t n, int max_sweeps);
 hipError_t eigh_run(EighWs e, const float* H, int64_t ldh, int64_t sH, int mode,
                     const EighOpts& o, float* lam, int64_t slam, float* Vout, int64_t ldv,
-                    int64_t sV, int* sweeps_out, int* flags, int* host_counter, const int* mask,
+                    int64_t sV, int* sweeps_out, int* flags, const int* mask,
                     const EighAux* aux, hipStream_t st);
 hipError_t copy_i32(int* dst, const int* src, int64_t n, hipStream_t st);
 hipError_t fill_i32(int* p, int v, int64_t n, hipStream_t st);
