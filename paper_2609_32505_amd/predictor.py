@@ -8,14 +8,14 @@ the library's kernels: spectral features, MLP forward/backward, the pinball
 loss and Adam.  Python only draws the seeded spectra/probes and loops.
 
 Training set: spectra of length 1024 from three families (geometric with
-kappa log-uniform in [1e2, 1e6]; Marchenko-Pastur-like, i.e. singular values
+kappa log-uniform in [1e2, 1e7]; Marchenko-Pastur-like, i.e. singular values
 of Gaussian (1024/c) x 1024 matrices computed by this library's SVD; rank-64
 signal plus N(0, 1e-3^2) noise, also through this library's SVD), each times
 a global scale log-uniform in [1e-3, 1e3].  Features depend only on the
 spectrum and a Gaussian probe (|y_k| = |s^k z| for bi-orthogonally invariant
 matrices), so each row pairs a spectrum with a fresh probe, presented at
-n = 512, 1024 or 2048 (decimated or geometrically interpolated) so that the
-network sees how the power-step ratios scale with n.
+n = 512, 1024, 2048 or 4096 (decimated or geometrically interpolated) so
+that the network sees how the power-step ratios scale with n.
 """
 from __future__ import annotations
 
@@ -68,7 +68,7 @@ def base_spectra_by_method(count_mp: int, count_lr: int, n: int, seed: int, devi
     return out
 
 
-def training_rows(rows: int, n: int = 1024, seed: int = 0, bases=None, sizes=(512, 1024, 2048)):
+def training_rows(rows: int, n: int = 1024, seed: int = 0, bases=None, sizes=(512, 1024, 2048, 4096)):
     """Seeded (spectrum, probe, m/n) rows, grouped by presentation size.
     Returns {size: (s (r, size), z (r, size), m_over_n (r,))} as float32."""
     rng = np.random.default_rng(seed)
@@ -77,7 +77,7 @@ def training_rows(rows: int, n: int = 1024, seed: int = 0, bases=None, sizes=(51
         fam = r % 3
         scale = float(np.exp(rng.uniform(np.log(1e-3), np.log(1e3))))
         if fam == 0 or not bases:
-            kappa = float(np.exp(rng.uniform(np.log(1e2), np.log(1e6))))
+            kappa = float(np.exp(rng.uniform(np.log(1e2), np.log(1e7))))
             s, mn = inputs.geometric(n, kappa), 1.0
         else:
             pool = [b for b in bases if b[2] == fam] or bases

@@ -315,7 +315,7 @@ def test_backward_learned_bf16_vs_finite_differences(api, handle):
                                    for x in (Ui, Si, Vi, G1 @ Vi, g, G1.T @ Ui)), eps_K=1e-10).cpu().double().numpy()[0])
     rel = _fd_rel_errors(A[idx], grads, G1, g, dirs)
     _say(f"  matrices {idx}: CANS steps {inf['iters'][idx]}, gradient relative error "
-         f"{np.array2string(rel, precision=2)}")
+         f"{np.array2string(rel, formatter={'float_kind': lambda x: f'{x:.2e}'})}")
     assert rel.max() < 1e-3
 
 

@@ -23,14 +23,14 @@ from paper_2609_32505_amd import inputs
 pytestmark = pytest.mark.gpu
 
 N = 4096
-KAPPAS = [10.0, 1e3, 1e6]
+KAPPAS = [10.0, 1e2, 1e3, 1e4, 1e6]
 REC_TOL = 1.5e-5
 ORTH_TOL = 1e-5
-# the learned BF16 rows are reduced precision: their orthogonality measures
-# 4e-6 to 1.5e-5 at kappa = 1e6 from run to run (the predictor's atomic sums
-# are not bitwise reproducible); the paper's reduced-precision (TF32) rows of
-# Table 2 are at 6.2e-4
-ORTH_TOL_BF16 = 1e-4
+# the learned BF16 rows end in FP32 refinement and the same FP32 eigensolver:
+# their orthogonality measures 3.6e-6 to 4.8e-6 (every reduction on the path
+# is in a fixed order, so these repeat bit for bit); the paper's
+# reduced-precision (TF32) rows of Table 2 are at 6.2e-4
+ORTH_TOL_BF16 = 1e-5
 GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_hyperparameters.json")))
 
 
