@@ -425,6 +425,8 @@ struct Ctx {
   int batch, m, n;
   const float* A;
   int64_t lda, sA;
+  int feat_m = 0;  // rows the sketch features report (0: m); the QR path's square core
+                   // reports the tall input's, whose spectrum and power sequence it shares
 };
 
 // Host synchronisations made by the library (svdp_host_syncs): the
@@ -612,7 +614,7 @@ svdp_status bounded(Ctx& c) {
       x = y;
       sx = m;
     }
-    HIPCHK(features_launch(w.fro2, w.nrm, B, m, n, w.F, w.aux, c.st), "features");
+    HIPCHK(features_launch(w.fro2, w.nrm, B, c.feat_m ? c.feat_m : m, n, w.F, w.aux, c.st), "features");
     HIPCHK(mlp_fwd_launch(c.h->model, c.h->model + SVDP_MLP_PARAMS, c.h->model + SVDP_MLP_PARAMS + 8, w.F, B,
                           w.mlpout, nullptr, c.st), "mlp");
     HIPCHK(bounds_launch(B, 0, w.mlpout, w.aux, nullptr, p->margin_max, p->margin_min, p->bf16_handoff,
@@ -948,6 +950,7 @@ svdp_status svd_tall_qr(Ctx& c, float* U, int64_t ldu, int64_t sU, float* S, int
   c2.A = w.Bq;
   c2.lda = n;
   c2.sA = nn;
+  c2.feat_m = m;
   svdp_status s = svd_core(c2, w.UBq, n, nn, S, sS, V, ldv, sV);
   if (s) return s;
   ProfScope phase(PROF_PHASE_QR, c.st);

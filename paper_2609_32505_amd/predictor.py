@@ -10,7 +10,8 @@ loss and Adam.  Python only draws the seeded spectra/probes and loops.
 Training set: spectra of length 1024 from three families (geometric with
 kappa log-uniform in [1e2, 1e7]; Marchenko-Pastur-like, i.e. singular values
 of Gaussian (1024/c) x 1024 matrices computed by this library's SVD; rank-64
-signal plus N(0, 1e-3^2) noise, also through this library's SVD), each times
+signal plus N(0, 1e-3^2) noise at m / n = 1, 2 and 4, also through this
+library's SVD), each times
 a global scale log-uniform in [1e-3, 1e3].  Features depend only on the
 spectrum and a Gaussian probe (|y_k| = |s^k z| for bi-orthogonally invariant
 matrices), so each row pairs a spectrum with a fresh probe, presented at
@@ -54,17 +55,22 @@ def base_spectra_by_method(count_mp: int, count_lr: int, n: int, seed: int, devi
         _, S, _, _ = api.svd_fwd(torch.from_numpy(G).to(device))
         for s in S.cpu().double().numpy():
             out.append((np.abs(s), m / n, 1))
-    A = []
-    for i in range(count_lr):
-        rng = inputs.rng_for(seed + 1, i)
-        sig = inputs.log_uniform(rng, 64, 0.1, 1.0)
-        Q1 = inputs.orthonormal(rng, n, 64)
-        Q2 = inputs.orthonormal(rng, n, 64)
-        A.append(((Q1 * sig) @ Q2.T + 1e-3 * rng.standard_normal((n, n))).astype(np.float32))
-    for k in range(0, len(A), 16):
-        _, S, _, _ = api.svd_fwd(torch.from_numpy(np.stack(A[k:k + 16])).to(device))
-        for s in S.cpu().double().numpy():
-            out.append((np.abs(s), 1.0, 2))
+    # rank-64 signal plus N(0, 1e-3^2) noise, square and tall (m / n = 2, 4):
+    # the noise floor of the spectrum, 1e-3 (sqrt(m) - sqrt(n)), rises with m / n
+    lr_aspect = [1.0, 0.5, 0.25]
+    for ai, c in enumerate(lr_aspect):
+        m = int(round(n / c))
+        A = []
+        for i in range(ai, count_lr, len(lr_aspect)):
+            rng = inputs.rng_for(seed + 1, i)
+            sig = inputs.log_uniform(rng, 64, 0.1, 1.0)
+            Q1 = inputs.orthonormal(rng, m, 64)
+            Q2 = inputs.orthonormal(rng, n, 64)
+            A.append(((Q1 * sig) @ Q2.T + 1e-3 * rng.standard_normal((m, n))).astype(np.float32))
+        for k in range(0, len(A), 8):
+            _, S, _, _ = api.svd_fwd(torch.from_numpy(np.stack(A[k:k + 8])).to(device))
+            for s in S.cpu().double().numpy():
+                out.append((np.abs(s), m / n, 2))
     return out
 
 
