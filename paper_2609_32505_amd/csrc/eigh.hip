@@ -336,17 +336,24 @@ __global__ __launch_bounds__(128) void k_jac_solve(EighWs e, EighPhase ph, int i
   int g[4];
   group_members(ph, gi, g);
   float* H = e.Hw + (int64_t)b * e.np * e.np;
-  // H[G, G]: 16 tiles, the ones below the diagonal read transposed
-  for (int idx = t; idx < 16 * 64; idx += 128) {
-    const int tile = idx >> 6, qd = idx & 63, k1 = tile >> 2, k2 = tile & 3;
+  // H[G, G]: 16 tiles, the ones below the diagonal read transposed; all
+  // eight of a thread's loads are issued before its first LDS store
+  f4v hv[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int idx = t + 128 * u, tile = idx >> 6, qd = idx & 63, k1 = tile >> 2, k2 = tile & 3;
     const int I = g[k1], Jb = g[k2];
-    const bool tr = I > Jb;
-    const f4v v = *(const f4v*)(H + tile_off(tr ? Jb : I, tr ? I : Jb, e.nb) + qd * 4);
+    hv[u] = *(const f4v*)(H + tile_off(I > Jb ? Jb : I, I > Jb ? I : Jb, e.nb) + qd * 4);
+  }
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int idx = t + 128 * u, tile = idx >> 6, qd = idx & 63, k1 = tile >> 2, k2 = tile & 3;
+    const bool tr = g[k1] > g[k2];
     const int r = qd >> 2, c = (qd & 3) * 4;
 #pragma unroll
     for (int w2 = 0; w2 < 4; ++w2) {
-      if (tr) L.X[k1 * 16 + c + w2][k2 * 16 + r] = (R)v[w2];
-      else L.X[k1 * 16 + r][k2 * 16 + c + w2] = (R)v[w2];
+      if (tr) L.X[k1 * 16 + c + w2][k2 * 16 + r] = (R)hv[u][w2];
+      else L.X[k1 * 16 + r][k2 * 16 + c + w2] = (R)hv[u][w2];
     }
   }
   __syncthreads();
@@ -498,19 +505,31 @@ __global__ __launch_bounds__(256) void k_jac_apply(EighWs e, EighPhase ph) {
     group_members(ph, G1, g1);
     group_members(ph, G2, g2);
     float* H = e.Hw + (int64_t)b * e.np * e.np;
+    // X = H[G1, G2] from the upper tiles.  A wave moves four 1 KB tiles; lane
+    // l takes each tile's 16-byte chunk at row r = l % 16, columns c .. c + 3
+    // with c = 4 (l / 16), so each group of 16 lanes covers 16 rows of one
+    // column chunk: its 16-byte LDS stores (a transposed stored tile) start 4
+    // banks apart and its 4-byte stores land in 64 distinct banks.  All four
+    // loads are issued before the rotations' loads and before any store, so
+    // their round trips overlap.
+    const int r = lane & 15, c = (lane >> 4) * 4;
+    f4v xv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int tile = w + 4 * u, k1 = tile >> 2, k2 = tile & 3;
+      const int I = g1[k1], Jb = g2[k2];
+      xv[u] = *(const f4v*)(H + tile_off(I > Jb ? Jb : I, I > Jb ? I : Jb, e.nb) + r * 16 + c);
+    }
     // T = M1^T X needs M1[k][32 qi + i]; Y = T M2 needs M2[k][32 qj + j]
     float a1[32], b2[32];
     load_mcol(Qb + (int64_t)G1 * QSTRIDE, 32 * qi, lane, a1);
     load_mcol(Qb + (int64_t)G2 * QSTRIDE, 32 * qj, lane, b2);
-    // X^T into LDS: Xs[c][r] = X[r][c], X = H[G1, G2] from the upper tiles
+    // X^T into LDS: Xs[c][r] = X[r][c]
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int idx = t + 256 * u;
-      const int tile = idx >> 6, qd = idx & 63, k1 = tile >> 2, k2 = tile & 3;
-      const int I = g1[k1], Jb = g2[k2];
-      const bool tr = I > Jb;
-      const f4v v = *(const f4v*)(H + tile_off(tr ? Jb : I, tr ? I : Jb, e.nb) + qd * 4);
-      const int r = qd >> 2, c = (qd & 3) * 4;
+      const int tile = w + 4 * u, k1 = tile >> 2, k2 = tile & 3;
+      const bool tr = g1[k1] > g2[k2];
+      const f4v v = xv[u];
       if (tr) {
         // the stored tile is X's block transposed: row r of it is column r of X
         *(f4v*)&Xs[k2 * 16 + r][k1 * 16 + c] = v;
@@ -528,17 +547,21 @@ __global__ __launch_bounds__(256) void k_jac_apply(EighWs e, EighPhase ph) {
     __syncthreads();
     put_quadrant(Xs, Y, qi, qj, lane);
     __syncthreads();
+    // back to the upper tiles, the same lane-to-chunk map: an untransposed
+    // tile's chunk is one 16-byte LDS read
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int idx = t + 256 * u;
-      const int tile = idx >> 6, qd = idx & 63, k1 = tile >> 2, k2 = tile & 3;
+      const int tile = w + 4 * u, k1 = tile >> 2, k2 = tile & 3;
       const int I = g1[k1], Jb = g2[k2];
       const bool tr = I > Jb;
-      const int r = qd >> 2, c = (qd & 3) * 4;
       f4v v;
+      if (tr) {
 #pragma unroll
-      for (int w2 = 0; w2 < 4; ++w2) v[w2] = tr ? Xs[k1 * 16 + c + w2][k2 * 16 + r] : Xs[k1 * 16 + r][k2 * 16 + c + w2];
-      *(f4v*)(H + tile_off(tr ? Jb : I, tr ? I : Jb, e.nb) + qd * 4) = v;
+        for (int w2 = 0; w2 < 4; ++w2) v[w2] = Xs[k1 * 16 + c + w2][k2 * 16 + r];
+      } else {
+        v = *(const f4v*)&Xs[k1 * 16 + r][k2 * 16 + c];
+      }
+      *(f4v*)(H + tile_off(tr ? Jb : I, tr ? I : Jb, e.nb) + r * 16 + c) = v;
     }
   } else {
     const int v = task - nH, slab = v / ng, G = v - slab * ng;
@@ -607,9 +630,21 @@ __global__ __launch_bounds__(512) void k_jac_vsweep(EighWs e) {
   if (e.active && !e.active[b]) return;
   float* V = e.Vw + (int64_t)b * NP * NP + (int64_t)slab * R * NP;
   if (e.work && t == 0) atomicAdd(e.work + PROF_JAC_VSWEEP, (double)NPH * NG * 2.0 * R * GS * GS);
-  for (int idx = t; idx < R * NP / 4; idx += 512) {
-    const int r = idx / (NP / 4), c = (idx - r * (NP / 4)) * 4;
-    *(f4v*)(Vs + r * PITCH + c) = *(const f4v*)(V + (int64_t)r * NP + c);
+  // the slab into LDS, up to eight 16-byte loads in flight per thread
+  constexpr int PER = R * NP / 4 / 512, NBT = PER < 8 ? PER : 8;
+  static_assert(PER % NBT == 0, "slab load batches");
+  for (int i0 = t; i0 < R * NP / 4; i0 += 512 * NBT) {
+    f4v tmp[NBT];
+#pragma unroll
+    for (int u = 0; u < NBT; ++u) {
+      const int idx = i0 + 512 * u, r = idx / (NP / 4), c = (idx - r * (NP / 4)) * 4;
+      tmp[u] = *(const f4v*)(V + (int64_t)r * NP + c);
+    }
+#pragma unroll
+    for (int u = 0; u < NBT; ++u) {
+      const int idx = i0 + 512 * u, r = idx / (NP / 4), c = (idx - r * (NP / 4)) * 4;
+      *(f4v*)(Vs + r * PITCH + c) = tmp[u];
+    }
   }
   __syncthreads();
   const int kh = lane >> 5, ic = lane & 31;
