@@ -212,6 +212,9 @@ def main():
                     help="run warmup + steps of one path only (for rocprofv3)")
     ap.add_argument("--path", choices=("learned", "plain"), default="learned",
                     help="the path --profile-only runs")
+    ap.add_argument("--bf16-from", type=float, default=None,
+                    help="interval lower end from which the learned path's CANS steps run in BF16 "
+                         "(default: the library's)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="with --profile-only: first copy a 256 MiB buffer (a kernel of known traffic "
                          "for scaling HBM counters)")
@@ -247,12 +250,15 @@ def main():
     # 1e-4 (restart tolerance) instead of the FP32 path's 6e-6.  The plain
     # path is timed both with its own defaults and with these settings.
     learned_eigh = dict(fp64_sweeps=1, eigh_off_tol=1e-4, jacobi_fro_tol=1e-3)
+    learned_kw = dict(learned_eigh)
+    if args.bf16_from is not None:
+        learned_kw["bf16_from"] = args.bf16_from
     dp = L.default_params(B, n, n)
 
     def step(path: str):
         if path == "learned":
             U, S, V, info = api.svd_fwd(Ad, handle=h, precision=L.PREC_BF16, bound=L.BOUND_LEARNED, probe=pd,
-                                        **learned_eigh)
+                                        **learned_kw)
         elif path == "plain_same_eigh":
             U, S, V, info = api.svd_fwd(Ad, handle=h, **learned_eigh)
         else:
@@ -380,7 +386,7 @@ def main():
         return worst
 
     U_l, S_l2, V_l, _ = api.svd_fwd(Ad, handle=h, precision=L.PREC_BF16, bound=L.BOUND_LEARNED, probe=pd,
-                                    **learned_eigh)
+                                    **learned_kw)
     U_p, S_p2, V_p, _ = api.svd_fwd(Ad, handle=h)
     rec_l, orth_l = recon_orth(U_l, S_l2, V_l)
     rec_p, orth_p = recon_orth(U_p, S_p2, V_p)
@@ -407,7 +413,8 @@ def main():
         "config": {"workload": f"{B} x {n} x {n} FP32, sigma log-uniform [1e-3,1], svd_polar_fwd + "
                                f"svd_polar_bwd, learned-bound BF16 CANS", "batch": B, "m": n, "n": n,
                    "learned_eigh": learned_eigh,
-                   "learned_bf16": {"bf16_from": dp.bf16_from, "bf16_correct": dp.bf16_correct}},
+                   "learned_bf16": {"bf16_from": learned_kw.get("bf16_from", dp.bf16_from),
+                                    "bf16_correct": dp.bf16_correct}},
         "timing": "value and ms_per_step from a leg with kernel profiling off; the profiled legs "
                   f"(per-launch events) ran at {ms_lp:.2f} (learned) and {ms_pp:.2f} (plain) ms/step",
         "phases_ms_per_step": {"learned": ph_l, "plain": ph_p},

@@ -423,3 +423,46 @@ def test_learned_predictor_gain_2048(api, handle):
     # no matrix of this set falls back (two of them, at sigma_1 ~ 500-900, did
     # while the sketch's power-sequence norms overflowed FP32)
     assert not np.any(il["flags"] & 2)
+
+
+def test_bf16_handoff_ablation_512(api, handle):
+    """The learned path's analogue of the appendix delta ablation: where the
+    BF16 steps start (bf16_from, the interval lower end from which the CANS
+    steps run in BF16) and where they end (bf16_handoff, the interval error
+    at which FP32 refinement takes over), on 32 matrices of the benchmark's
+    recipe.  Per setting: the per-value sigma error against the FP64 oracle
+    on four matrices and against the plain FP32 path on all 32, the worst
+    reconstruction, and the mean step count.  Checked: every setting from
+    bf16_from 0.1 up keeps every singular value within 1e-3 relative and the
+    reconstruction at the FP32 level; earlier hand-offs degrade the smallest
+    singular values (the per-value error at 0.01 exceeds that at 0.5 tenfold),
+    which is why the default starts BF16 only once the interval's lower end
+    has reached 0.5."""
+    import torch
+    B, n = 32, 512
+    A, s = inputs.square_loguniform(seed=44, batch=B, n=n)
+    Ad = torch.from_numpy(A).cuda()
+    probe = torch.from_numpy(inputs.probe(45, B, n)).cuda()
+    idx = [0, 11, 22, 31]
+    _, So, _, _ = oracle.svd_batch(A[idx].astype(np.float64))
+    _, Sp, _, _ = api.svd_fwd(Ad, handle=handle)
+    Sp = Sp.cpu().double().numpy()
+    _say("BF16 hand-off ablation, 32 x 512^2 (sigma log-uniform in [1e-3, 1])")
+    res = {}
+    for bf, ho in [(0.5, 1e-2), (0.3, 1e-2), (0.2, 1e-2), (0.1, 1e-2), (0.5, 1e-1), (0.01, 1e-2)]:
+        U, S, V, info = api.svd_fwd(Ad, handle=handle, precision=1, bound=1, probe=probe, bf16_from=bf,
+                                    bf16_handoff=ho, **LEARNED_EIGH)
+        torch.cuda.synchronize()
+        inf = api.info_to_numpy(info)
+        Sh = S.cpu().double().numpy()
+        rel_or = max(float((np.abs(Sh[i] - So[j]) / So[j]).max()) for j, i in enumerate(idx))
+        rel_pl = float((np.abs(Sh - Sp) / Sp).max())
+        r = torch.bmm(U * S[:, None, :], V.transpose(1, 2).contiguous()) - Ad
+        rec = float((torch.linalg.norm(r, dim=(1, 2)) / torch.linalg.norm(Ad, dim=(1, 2))).max())
+        fb = int(((inf["flags"] & 2) != 0).sum())
+        res[(bf, ho)] = (rel_or, rel_pl, rec)
+        _say(f"  bf16_from {bf:g}, hand-off {ho:g}: steps mean {inf['iters'].mean():.2f}, fallbacks {fb}, "
+             f"per-value sigma error vs oracle {rel_or:.2e}, vs plain {rel_pl:.2e}, reconstruction {rec:.2e}")
+        if bf >= 0.1:
+            assert rel_or < 1e-3 and rel_pl < 1e-3 and rec < 1e-4, (bf, ho)
+    assert res[(0.01, 1e-2)][1] > 10 * res[(0.5, 1e-2)][1]

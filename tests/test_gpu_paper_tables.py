@@ -258,9 +258,9 @@ def test_gradient_norm_vs_gap_4096(api, handle, haar):
     computed gap is rounding noise of that size.  Checked: at large gaps the
     regularised gradient (Algorithm 4's eps mapping of eps = 1e-8) equals
     the unregularised one and has the closed-form expected norm; at every
-    gap it stays finite and bounded.  The main text's eps^2 for K and the
-    paper's printed norms (half the closed form at large gaps) are reported
-    beside."""
+    gap it stays finite and bounded.  The main text's eps^2 for K is reported
+    beside, and at large gaps half the measured norm is checked against the
+    paper's printed one."""
     import torch
     import oracle
     Q1, Q2 = haar
@@ -291,6 +291,9 @@ def test_gradient_norm_vs_gap_4096(api, handle, haar):
         if gap >= 0.1:
             assert abs(row["alg4"] - row["none"]) < 1e-2 * row["none"]
             assert abs(row["alg4"] - expect) < 0.05 * expect
+            # the paper's printed norm is half the mean norm (the reading pinned
+            # on the CPU by the Table 3 quadrature test)
+            assert abs(row["alg4"] / 2.0 - paper_an) < 0.05 * paper_an
     # Tikhonov bounds |K_ij| = |d| / (d^2 + eps_K) by 1 / (2 sqrt(eps_K)) = 50
     # whatever the computed gap d: the pair's two entries add about 2 K^2
     # (<= 5e3) to the expected |dM|_F^2 (1.76e4 at gap 1), so the norm stays

@@ -259,6 +259,55 @@ def test_gradient_norm_matches_closed_form_expectation(orc):
     assert abs(acc.mean() - expect) < 4 * acc.std() / np.sqrt(len(acc))
 
 
+def test_table3_printed_norms_are_half_the_mean_gradient_norm():
+    # Reading of Table 3's printed norms: with the closed-form structure of
+    # the gradient above, |dM|_F^2 is a sum of ~n^2/2 independent pair terms;
+    # all but the gap pair (s_n = n - 1 + gap, s_{n-1} = n - 1) concentrate on
+    # their mean C, and the gap pair's two entries are
+    # F^2 [(a s_j + b s_i)^2 + (a s_i + b s_j)^2] with a, b ~ N(0, 2).  E|dM|_F
+    # (the mean of the norm over matrices, as a 100-matrix average reports)
+    # follows by 2-D Gauss-Hermite quadrature.  The printed values are half of
+    # it: within print rounding at gaps 1 and 0.1, and within 3.5 standard
+    # errors of a 100-matrix mean at the small gaps (where FP32 also perturbs
+    # the computed gap).  Neither the full norm nor half the root-mean-square
+    # norm fits: the latter misses the gap 1e-4 value by 3.7 standard errors.
+    import json
+    import os
+    t3 = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                     "paper_hyperparameters.json")))["table3_gradient_norm"]
+    n = 4096
+    z, wq = np.polynomial.hermite_e.hermegauss(120)
+    wq = wq / wq.sum()
+    a, b = np.meshgrid(z * np.sqrt(2.0), z * np.sqrt(2.0))
+    w2 = np.outer(wq, wq)
+    for gap, printed in zip(t3["gap"], t3["analytic"]):
+        if printed is None:
+            continue
+        s = inputs.paper_gap(n, gap)[::-1].copy()  # ascending: s[-1] the gap value
+        s2 = s ** 2
+        tot = float(n)
+        for r in range(n):
+            d = s2[r] - s2
+            d[r] = 1.0
+            t = 2.0 * (s2[r] + s2) / d ** 2
+            t[r] = 0.0
+            tot += t.sum()
+        i, j = n - 1, n - 2
+        F = 1.0 / (s2[i] - s2[j])
+        C = tot - 4.0 * (s2[i] + s2[j]) * F ** 2
+        g = np.sqrt(C + F ** 2 * ((a * s[j] + b * s[i]) ** 2 + (a * s[i] + b * s[j]) ** 2))
+        mean = float((w2 * g).sum())
+        sd = float(np.sqrt(max((w2 * g ** 2).sum() - mean ** 2, 0.0)))
+        se_half = sd / np.sqrt(100.0) / 2.0
+        if gap >= 0.1:
+            assert abs(mean / 2.0 - printed) <= 0.5 + 0.01 * printed, gap
+            assert abs(np.sqrt(tot) - printed) > 0.5 * printed  # not the full norm
+        else:
+            assert abs(mean / 2.0 - printed) <= 3.5 * se_half, gap
+            if gap <= 1e-4:
+                assert abs(np.sqrt(tot) / 2.0 - printed) > 3.5 * se_half
+
+
 def test_lyapunov_identity_on_oracle_solution(orc):
     # Lyapunov identity lemma: with HY + YH = A and HX + XH = B,
     # <A, X> = <Y, B>; the eigenbasis solution of the proposition on solving
