@@ -345,7 +345,7 @@ struct FwdWs {
   void *Y0, *Y1;  // BF16 iterates (never aliasing the FP32 ones)
   void *Yt0, *Yt1;  // their transposes (n x m, BF16): the Gram's operands, contiguous in k
   void* eigh;
-  float *scale, *conv, *resid, *colsum, *rowmax, *fro2, *fpart, *coef, *rcoef, *F, *aux, *mlpout, *nrm, *y0, *y1;
+  float *scale, *conv, *resid, *rpart, *colsum, *rowmax, *fro2, *fpart, *coef, *rcoef, *F, *aux, *mlpout, *nrm, *y0, *y1;
   float* qr;   // QR completion scratch: 2 m per matrix
   float* qrc;  // blocked QR: projection coefficients, n x kQrBlock per matrix
   float *qrg, *qrr;  // blocked QR: a block's Gram matrix and CholeskyQR factor
@@ -369,8 +369,9 @@ FwdWs carve_fwd(void* base, const svdp_params* p, size_t* total) {
   w.G = c.take<float>(b * n * n);
   w.eigh = c.take_bytes(eigh_ws_bytes(b, n, p->max_sweeps));
   w.scale = c.take<float>(b);
-  w.conv = c.take<float>(2 * b);
+  w.conv = c.take<float>(2 * b * gemm_conv_slots(m, n));
   w.resid = c.take<float>(b);
+  w.rpart = c.take<float>(residual_part_floats(b));
   w.colsum = c.take<float>(b * n);
   w.rowmax = c.take<float>(b);
   w.fro2 = c.take<float>(b);
@@ -568,7 +569,6 @@ svdp_status conservative_fp32(Ctx& c, const int* mask) {
   if (mask) HIPCHK(copy_i32(w.active, mask, B, c.st), "active");
   else HIPCHK(fill_i32(w.active, 1, B, c.st), "active");
   HIPCHK(fill_masked_launch(w.where, 0, B, mask, c.st), "where");
-  HIPCHK(fill_f32(w.conv, 0.f, 2 * B, c.st), "conv");
   // The full budget of max_iters steps is enqueued without reading anything
   // back: a matrix leaves the active set on the device at its stop test, and
   // the later steps' workgroups of that matrix exit at once.
@@ -579,7 +579,8 @@ svdp_status conservative_fp32(Ctx& c, const int* mask) {
       HIPCHK(cans5_step(c, Xc, Xn, tab3 + 3 * k, w.active, w.conv, 0), "cans5 step");
     else
       HIPCHK(cans_step(c, PREC_F32, Xc, Xn, 0, 0, w.coef, 0, k, w.active, w.conv), "cans step");
-    HIPCHK(cans_check_launch(B, w.conv, (float)p->tol, k, w.active, w.where, w.iters, nullptr, 0, w.flags,
+    HIPCHK(cans_check_launch(B, w.conv, gemm_conv_slots(m, n), (float)p->tol, k, w.active, w.where, w.iters,
+                             nullptr, 0, w.flags,
                              w.counter, c.st),
            "cans check");
   }
@@ -678,7 +679,6 @@ svdp_status bounded(Ctx& c) {
   HIPCHK(set_coef_launch(w.rcoef, rtab, Rmax, c.st), "refine coef");
   HIPCHK(fill_i32(w.active, 1, B, c.st), "active");
   HIPCHK(fill_i32(w.where, 0, B, c.st), "where");
-  HIPCHK(fill_f32(w.conv, 0.f, 2 * B, c.st), "conv");
   // the reported count adds the refinement steps to each matrix's K (mask
   // is free until the fallback test)
   HIPCHK(copy_i32(w.mask, w.iters, B, c.st), "iteration base");
@@ -689,7 +689,8 @@ svdp_status bounded(Ctx& c) {
     float* conv = r + 1 >= R ? w.conv : nullptr;
     HIPCHK(cans_step(c, PREC_F32, Xc, Xn, 0, 0, w.rcoef, 0, r, w.active, conv), "refine step");
     if (!conv) continue;
-    HIPCHK(cans_check_launch(B, w.conv, (float)p->tol, r, w.active, w.where, w.iters, w.mask, 1, w.flags,
+    HIPCHK(cans_check_launch(B, w.conv, gemm_conv_slots(m, n), (float)p->tol, r, w.active, w.where, w.iters,
+                             w.mask, 1, w.flags,
                              w.counter, c.st), "refine check");
   }
   HIPCHK(or_flags_launch(B, w.flags, SVDP_FLAG_NOT_CONVERGED, w.active, c.st), "flags");
@@ -708,7 +709,7 @@ svdp_status final_residual(Ctx& c, const int* mask) {
   g.sym = 1;
   g.active = mask;
   HIPCHK(gemm_launch(g, PREC_F32, 1, 0, c.st), "W^T W");
-  HIPCHK(residual_launch(w.G, 0, B, n, w.resid, mask, c.st), "residual");
+  HIPCHK(residual_launch(w.G, 0, B, n, w.rpart, w.resid, mask, c.st), "residual");
   return SVDP_OK;
 }
 

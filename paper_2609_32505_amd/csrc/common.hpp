@@ -37,7 +37,7 @@ struct GemmArgs {
   int kbf16;           // kbf16) of kcatmask is set, and writes its output in
   int obf_catmask;     // BF16 to C_bf (and Ct) when that bit of obf_catmask is set
   void* C_bf;          // (same leading dimension and stride as C), else to C
-  float* conv;         // per matrix: += sum (out - Cin)^2, += sum out^2
+  float* conv;         // per matrix and wave sub-tile (gemm_conv_slots slots): sum (out - Cin)^2, sum out^2
   int sym;             // output symmetric: upper tiles computed, mirrored
   int work_batch;      // matrices actually computed (for work accounting; 0 = batch)
   int out_bf16, in_bf16, cin_bf16;
@@ -50,6 +50,8 @@ enum { PREC_F32 = 0, PREC_BF16 = 1 };
 // Launch a batched GEMM.  prec selects FP32 MFMA (inputs FP32) or BF16 MFMA
 // (inputs FP32 or BF16 per in_bf16, rounded to BF16, FP32 accumulation).
 hipError_t gemm_launch(const GemmArgs& g, int prec, int ta, int tb, hipStream_t st);
+// slots per matrix of GemmArgs::conv for an M x N output (one per wave sub-tile)
+int gemm_conv_slots(int64_t M, int64_t N);
 
 // Category of step k of matrix b in the bounded CANS schedule, from its step
 // counts (K, K1): K steps in all, the first K1 in FP32 (all of them when

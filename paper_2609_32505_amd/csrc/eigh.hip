@@ -418,7 +418,9 @@ __global__ __launch_bounds__(128) void k_jac_solve(EighWs e, EighPhase ph, int i
     vsum += __shfl_xor(vsum, off);
   }
   if (lane == 0 && rotmax) atomicMax(rotmax + b, __float_as_int(mrel));
-  if (lane == 0 && rotsq) atomicAdd(rotsq + b, vsum);
+  // the rotated mass goes to this group's and wave's slot of the sweep (its
+  // only writer in every phase), added in slot order by k_eigh_check
+  if (lane == 0 && rotsq) rotsq[((int64_t)b * ng + gi) * 2 + w] += vsum;
 }
 
 // 64 x 64 quadrant products on one wavefront (32 x 32 output block (qi, qj)),
@@ -765,7 +767,19 @@ __global__ __launch_bounds__(256) void k_eigh_setup(EighWs e, const float* Hin, 
   }
   if (!(what & kSetupNorm)) return;
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-  if ((t & 63) == 0) atomicAdd(e.hnorm2 + b, acc);
+  if ((t & 63) == 0) e.hn_part[((int64_t)b * nq * nq + blockIdx.x) * 4 + (t >> 6)] = acc;
+}
+
+// |H|_F^2 = the setup workgroups' partial sums (blocks Ib <= Jb) in block order
+__global__ void k_hnorm_finalize(EighWs e, const int* mask) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= e.batch || (mask && !mask[b])) return;
+  const int nq = e.nb / 4;
+  float t = 0.f;
+  for (int Ib = 0; Ib < nq; ++Ib)
+    for (int Jb = Ib; Jb < nq; ++Jb)
+      for (int w = 0; w < 4; ++w) t += e.hn_part[((int64_t)b * nq * nq + Ib * nq + Jb) * 4 + w];
+  e.hnorm2[b] = t;
 }
 
 // row-major copy of a tiled np x np matrix: one row per workgroup, a float4
@@ -785,16 +799,23 @@ __global__ void k_untile(const float* src, float* dst, int np, int nb, const int
 // entry was <= tol, or whose rotated entries had a sum of squares <=
 // fro_tol2 |H|_F^2 (a normwise test: the next sweep leaves far less), and
 // count the ones still active (single workgroup).
-__global__ void k_eigh_check(EighWs e, const int* rotcnt, const float* rotsq, float tol, float fro_tol2, int sweep,
+__global__ void k_eigh_check(EighWs e, const int* rotcnt, float* rotsq, float tol, float fro_tol2, int sweep,
                              int* sweeps_out, int* n_active) {
   __shared__ int cnt;
   if (threadIdx.x == 0) cnt = 0;
   __syncthreads();
   int mine = 0;
+  const int slots = (e.nb / 4) * 2;
   for (int b = threadIdx.x; b < e.batch; b += blockDim.x) {
+    float* rs = rotsq + (int64_t)b * slots;
+    float vs = 0.f;
+    for (int q = 0; q < slots; ++q) {
+      vs += rs[q];
+      rs[q] = 0.f;
+    }
     if (e.active[b]) {
       sweeps_out[b] = sweep + 1;
-      if (__int_as_float(rotcnt[b]) <= tol || rotsq[b] <= fro_tol2 * e.hnorm2[b]) e.active[b] = 0;
+      if (__int_as_float(rotcnt[b]) <= tol || vs <= fro_tol2 * e.hnorm2[b]) e.active[b] = 0;
       else ++mine;
     }
   }
@@ -917,19 +938,25 @@ __global__ __launch_bounds__(256) void k_restart_offnorm(EighWs e, const float* 
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
   if ((t & 63) == 0) red[t >> 6] = acc;
   __syncthreads();
-  if (t == 0) atomicAdd(e.off2 + b, red[0] + red[1] + red[2] + red[3]);
+  if (t == 0) e.off_part[(int64_t)b * gridDim.x + blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
 // After a restart measure: a matrix of `proc` stays active for another sweep
 // of T when off2 > off_tol2 |H0|_F^2 and `last` is 0 (the others leave the
 // active set); *counter gains the number of active matrices, and their sweep
 // counts the nsweeps sweeps of the restart.
-__global__ void k_restart_decide(EighWs e, const int* proc, float off_tol2, int last, int* counter,
+__global__ void k_restart_decide(EighWs e, const int* proc, int chunks, float off_tol2, int last, int* counter,
                                  int* sweeps_out, int nsweeps) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= e.batch) return;
   int act = 0;
-  if (!proc || proc[b]) act = !last && e.off2[b] > (double)off_tol2 * (double)e.hnorm2[b];
+  if (!proc || proc[b]) {
+    // the measure's workgroup partials in order
+    double off2 = 0.0;
+    for (int q = 0; q < chunks; ++q) off2 += e.off_part[(int64_t)b * chunks + q];
+    e.off2[b] = off2;
+    act = !last && off2 > (double)off_tol2 * (double)e.hnorm2[b];
+  }
   e.active[b] = act;
   if (act) {
     atomicAdd(counter, 1);
@@ -993,6 +1020,12 @@ int eigh_blocks(int64_t n) {
 // fits in LDS: np <= 1024
 static bool eigh_deferred(int64_t np) { return np <= 1024; }
 
+// workgroups per matrix of the restart measure (each a run of 32 x 32 tile pairs)
+static int restart_chunks(int64_t n, int64_t batch) {
+  const int64_t nt = (n + 31) / 32, npairs = nt * (nt + 1) / 2;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(npairs, (2048 + batch - 1) / batch));
+}
+
 size_t eigh_ws_bytes(int64_t batch, int64_t n, int max_sweeps) {
   const int64_t nb = eigh_blocks(n), np = nb * BS, ng = nb / 4;
   const int64_t nph = eigh_deferred(np) ? nb / 2 : 1;
@@ -1003,7 +1036,10 @@ size_t eigh_ws_bytes(int64_t batch, int64_t n, int max_sweeps) {
   f += batch;                        // hnorm2
   f += 2 * batch;                    // off2 (FP64)
   f += 2 * batch * n;                // sign, (perm as int)
-  size_t i = 2 * batch * (size_t)(max_sweeps + 2) + batch + 16;  // rotcnt, rotsq, active, counters
+  f += batch * ng * 2;               // rotated-mass slots
+  f += batch * ng * ng * 4;          // |H|_F^2 slots
+  f += 2 * batch * (size_t)restart_chunks(n, batch);  // restart-measure slots (FP64)
+  size_t i = batch * (size_t)(max_sweeps + 2) + batch + 16;  // rotcnt, active, counters
   return (f + i) * 4 + 16 * 256;
 }
 
@@ -1028,7 +1064,9 @@ EighWs eigh_ws_carve(void* ws, int64_t batch, int64_t n, int max_sweeps) {
   e.sgn = (float*)take(batch * n * 4);
   e.perm = (int*)take(batch * n * 4);
   e.rotcnt = (int*)take(batch * (size_t)(max_sweeps + 2) * 4);
-  e.rotsq = (float*)take(batch * (size_t)(max_sweeps + 2) * 4);
+  e.rotsq = (float*)take(batch * ng * 2 * 4);
+  e.hn_part = (float*)take(batch * ng * ng * 4 * 4);
+  e.off_part = (double*)take(batch * (size_t)restart_chunks(n, batch) * 8);
   e.active = (int*)take(batch * 4);
   e.counter = (int*)take(64);
   e.max_sweeps = max_sweeps;
@@ -1078,6 +1116,7 @@ static EighWs eigh_sub(const EighWs& e, int b0, int cnt, int h) {
   s.Qw += b0 * e.nph_store * ng * QSTRIDE;
   s.hnorm2 += b0;
   s.off2 += b0;
+  s.rotsq += (int64_t)b0 * ng * 2;
   s.sgn += (int64_t)b0 * e.n;
   s.perm += (int64_t)b0 * e.n;
   s.active += b0;
@@ -1093,13 +1132,15 @@ hipError_t eigh_run(EighWs e, const float* H, int64_t ldh, int64_t sH, int mode,
   hipError_t err;
   const int batch = e.batch;
   e.work = prof_work_dev();
-  if ((err = fill_f32(e.hnorm2, 0.f, batch, st))) return err;
+  const int rslots = (e.nb / 4) * 2;  // rotated-mass slots per matrix (k_eigh_check clears them)
   if ((err = fill_i32(e.rotcnt, 0, (int64_t)batch * (e.max_sweeps + 2), st))) return err;
-  if ((err = fill_f32(e.rotsq, 0.f, (int64_t)batch * (e.max_sweeps + 2), st))) return err;
+  if ((err = fill_f32(e.rotsq, 0.f, (int64_t)batch * rslots, st))) return err;
   if (mask) { if ((err = copy_i32(e.active, mask, batch, st))) return err; }
   else if ((err = fill_i32(e.active, 1, batch, st))) return err;
   hipLaunchKernelGGL(k_eigh_setup, dim3((e.nb / 4) * (e.nb / 4), batch), dim3(256), 0, st, e, H, ldh, sH, mask,
                      kSetupV | kSetupH | kSetupNorm);
+  if ((err = hipGetLastError())) return err;
+  hipLaunchKernelGGL(k_hnorm_finalize, dim3(cdiv(batch, 256)), dim3(256), 0, st, e, mask);
   if ((err = hipGetLastError())) return err;
   const int ng = e.nb / 4;
   const int nH = ng * (ng - 1) / 2;
@@ -1177,7 +1218,7 @@ hipError_t eigh_run(EighWs e, const float* H, int64_t ldh, int64_t sH, int mode,
         hipError_t e2;
         if (first && h > 0 && (e2 = hipStreamWaitEvent(S.ss[h], aux->skew[h - 1], 0))) return e2;
         if ((e2 = phase_launches(S, h, ph, fp64, skip_rel, rc ? rc + S.b0[h] : nullptr,
-                                 vs ? vs + S.b0[h] : nullptr, first && S.P > 1))) return e2;
+                                 vs ? vs + (int64_t)S.b0[h] * rslots : nullptr, first && S.P > 1))) return e2;
       }
       first = false;
     }
@@ -1197,10 +1238,11 @@ hipError_t eigh_run(EighWs e, const float* H, int64_t ldh, int64_t sH, int mode,
     if (sweep == par_sweeps && (err = join(multi))) return err;
     const Parts& S = sweep < par_sweeps ? multi : single;
     int* rc = e.rotcnt + (int64_t)batch * sweep;
-    float* vs = e.rotsq + (int64_t)batch * sweep;
+    float* vs = e.rotsq;
     if ((err = sweep_launches(S, false, 0.f, rc, vs))) return err;
     for (int h = 0; h < S.P; ++h) {
-      hipLaunchKernelGGL(k_eigh_check, dim3(1), dim3(1024), 0, S.ss[h], S.eh[h], rc + S.b0[h], vs + S.b0[h],
+      hipLaunchKernelGGL(k_eigh_check, dim3(1), dim3(1024), 0, S.ss[h], S.eh[h], rc + S.b0[h],
+                         vs + (int64_t)S.b0[h] * rslots,
                          o.tol, o.fro_tol * o.fro_tol, sweep, sweeps_out + S.b0[h], S.eh[h].counter);
       if ((err = hipGetLastError())) return err;
     }
@@ -1260,8 +1302,7 @@ hipError_t eigh_run(EighWs e, const float* H, int64_t ldh, int64_t sH, int mode,
   // rounding (kRestartSkip) are left alone -- and V <- V V'.
   {
     const int* proc = mask;
-    const int nt = (e.n + 31) / 32, npairs = nt * (nt + 1) / 2;
-    const int chunks = std::max(1, std::min(npairs, cdiv(2048, batch)));
+    const int chunks = restart_chunks(e.n, batch);
     const float tol2 = o.off_tol * o.off_tol;
     for (int r = 0;; ++r) {
       const int last = r >= o.restarts;
@@ -1281,11 +1322,10 @@ hipError_t eigh_run(EighWs e, const float* H, int64_t ldh, int64_t sH, int mode,
       tt.C = e.Vw; tt.ldc = np; tt.sC = m2;
       tt.alpha = 1.f; tt.active = proc;
       if ((err = gemm_launch(tt, PREC_F32, 1, 0, st))) return err;
-      if ((err = fill_f32((float*)e.off2, 0.f, 2 * (int64_t)batch, st))) return err;
       if ((err = fill_i32(e.counter, 0, 1, st))) return err;
       hipLaunchKernelGGL(k_restart_offnorm, dim3(chunks, batch), dim3(256), 0, st, e, e.Vw, proc);
       if ((err = hipGetLastError())) return err;
-      hipLaunchKernelGGL(k_restart_decide, dim3(cdiv(batch, 256)), dim3(256), 0, st, e, proc, tol2, last,
+      hipLaunchKernelGGL(k_restart_decide, dim3(cdiv(batch, 256)), dim3(256), 0, st, e, proc, chunks, tol2, last,
                          e.counter, sweeps_out, std::max(1, o.fp64_sweeps));
       if ((err = hipGetLastError())) return err;
       if (last) break;

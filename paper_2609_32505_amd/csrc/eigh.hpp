@@ -12,10 +12,13 @@ struct EighWs {
   float* Qw;      // batch x (nb/4) x (64 x 64 group rotation + 2 x 32 x 32 step-A rotations)
   float* hnorm2;  // batch: |H|_F^2
   double* off2;   // batch: |off(sym(V^T H V))|_F^2 of the last restart measure
+  float* hn_part;    // batch x (nb/4)^2 x 4: |H|_F^2 per setup workgroup and wave
+  double* off_part;  // batch x chunks: the restart measure per workgroup
   float* sgn;     // batch x n: sign of each sorted eigenvalue
   int* perm;      // batch x n: sorted position -> working column
   int* rotcnt;    // batch x (max_sweeps + 2): largest relative entry rotated (float bits)
-  float* rotsq;   // batch x (max_sweeps + 2): sum of squares of the entries rotated
+  float* rotsq;   // batch x (nb/4) x 2: sum of squares of the entries rotated in the
+                  // current sweep, per group and wave (added in order, then cleared)
   int* active;    // batch: 1 while not converged
   int* counter;   // device scalar: active matrices after a sweep
   int deferred;   // 1: V row-major, updated once per sweep from every phase's group

@@ -129,15 +129,19 @@ SVDP_DEV void epilogue(const GemmArgs& g, int b, int rowbase, int colbase, int t
         }
       }
     }
-  if (g.conv) {
+  if (g.conv && rowbase < g.M && colbase < g.N) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
       d2 += __shfl_xor(d2, off);
       o2 += __shfl_xor(o2, off);
     }
+    // one slot per wave sub-tile (32 FM x 32 FN), added in order by the check
+    const int slots_n = (g.N + 32 * FN - 1) / (32 * FN);
+    const int slots = ((g.M + 32 * FM - 1) / (32 * FM)) * slots_n;
+    const int slot = (rowbase / (32 * FM)) * slots_n + colbase / (32 * FN);
     if (lane == 0) {
-      atomicAdd(g.conv + 2 * b, d2);
-      atomicAdd(g.conv + 2 * b + 1, o2);
+      g.conv[((int64_t)b * slots + slot) * 2] = d2;
+      g.conv[((int64_t)b * slots + slot) * 2 + 1] = o2;
     }
   }
 }
@@ -501,6 +505,13 @@ bool aligned(const void* p, int64_t ld, int64_t stride, int elems, int esz) {
 }
 
 }  // namespace
+
+int gemm_conv_slots(int64_t M, int64_t N) {
+  // the wave sub-tile of the tile size gemm_launch picks: 64 x 64 in 128 x 128
+  // tiles, 32 x 32 in 64 x 64 tiles
+  const int w = (M > 64 && N > 64) ? 64 : 32;
+  return (int)(((M + w - 1) / w) * ((N + w - 1) / w));
+}
 
 hipError_t gemm_launch(const GemmArgs& g, int prec, int ta, int tb, hipStream_t st) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;

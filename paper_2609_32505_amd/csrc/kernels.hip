@@ -163,7 +163,10 @@ __global__ void k_set_coef(float* coef, CoefTab t, int steps) {
   if (i < 2 * steps) coef[i] = t.v[i];
 }
 
-__global__ void k_cans_check(int batch, float* conv, float tol, int k, int* active, int* where,
+// conv holds, per matrix, `slots` pairs (change, output) of sums of squares,
+// one per output sub-tile of the update GEMM (gemm_conv_slots), added here in
+// slot order so that the decision does not depend on scheduling
+__global__ void k_cans_check(int batch, const float* conv, int slots, float tol, int k, int* active, int* where,
                              int* iters, const int* iter_base, int base_stride, int* flags, int* counter) {
   __shared__ int cnt;
   if (threadIdx.x == 0) cnt = 0;
@@ -171,9 +174,12 @@ __global__ void k_cans_check(int batch, float* conv, float tol, int k, int* acti
   int mine = 0;
   for (int b = threadIdx.x; b < batch; b += blockDim.x) {
     if (!active[b]) continue;
-    float d2 = conv[2 * b], o2 = conv[2 * b + 1];
-    conv[2 * b] = 0.f;
-    conv[2 * b + 1] = 0.f;
+    float d2 = 0.f, o2 = 0.f;
+    const float* cb = conv + (int64_t)b * slots * 2;
+    for (int q = 0; q < slots; ++q) {
+      d2 += cb[2 * q];
+      o2 += cb[2 * q + 1];
+    }
     iters[b] = (iter_base ? iter_base[(int64_t)b * base_stride] : 0) + k + 1;
     where[b] = (k + 1) & 1;
     if (!isfinite(d2) || !isfinite(o2)) {
@@ -190,7 +196,10 @@ __global__ void k_cans_check(int batch, float* conv, float tol, int k, int* acti
   if (threadIdx.x == 0) *counter = cnt;
 }
 
-__global__ void k_residual(const void* G, int gbf16, int n, float* resid, const int* mask) {
+// |G - I|_F^2 per matrix: workgroup x of matrix b writes its four waves'
+// partial sums to part[b][4 x + w] (kResidBlocks workgroups per matrix)
+constexpr int kResidBlocks = 64;
+__global__ void k_residual(const void* G, int gbf16, int n, float* part, const int* mask) {
   const int b = blockIdx.y;
   if (skip(mask, b)) return;
   const int64_t total = (int64_t)n * n;
@@ -204,30 +213,47 @@ __global__ void k_residual(const void* G, int gbf16, int n, float* resid, const 
     }
   }
   s = wave_sum(s);
-  if ((threadIdx.x & 63) == 0) atomicAdd(resid + b, s);
+  if ((threadIdx.x & 63) == 0) part[((int64_t)b * kResidBlocks + blockIdx.x) * 4 + (threadIdx.x >> 6)] = s;
 }
 
-__global__ void k_residual_finish(int batch, int n, float* resid, const int* mask) {
+// resid = sqrt(|G - I|_F^2 / n), the partials added in order (workgroups
+// beyond n rows wrote nothing and are skipped)
+__global__ void k_residual_finish(int batch, int n, const float* part, float* resid, const int* mask) {
   int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b < batch && !skip(mask, b)) resid[b] = sqrtf(resid[b] / (float)n);
+  if (b >= batch || skip(mask, b)) return;
+  const int nb = min(n, kResidBlocks);
+  float t = 0.f;
+  for (int q = 0; q < nb * 4; ++q) t += part[(int64_t)b * kResidBlocks * 4 + q];
+  resid[b] = sqrtf(t / (float)n);
 }
 
 // ------------------------------------------------------------ U column norms
 
-__global__ void k_colnorm(const float* U, int64_t ldu, int64_t sU, int m, int n, int rows_per,
-                          float* cn2, const int* mask) {
-  const int b = blockIdx.z;
+// squared column norms of U: one 16-wave workgroup per 64 columns, wave w over
+// rows w, w + 16, ..., the 16 partial sums added in wave order
+__global__ __launch_bounds__(1024) void k_colnorm(const float* U, int64_t ldu, int64_t sU, int m, int n,
+                                                  float* cn2, const int* mask) {
+  const int b = blockIdx.y;
   if (skip(mask, b)) return;
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
-  const int i0 = blockIdx.y * rows_per, i1 = min(m, i0 + rows_per);
-  const float* p = U + b * sU + j;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int j = blockIdx.x * 64 + lane;
   float s = 0.f;
-  for (int i = i0; i < i1; ++i) {
-    float v = p[(int64_t)i * ldu];
-    s += v * v;
+  if (j < n) {
+    const float* p = U + b * sU + j;
+#pragma unroll 4
+    for (int i = w; i < m; i += 16) {
+      const float v = p[(int64_t)i * ldu];
+      s += v * v;
+    }
   }
-  atomicAdd(cn2 + (int64_t)b * n + j, s);
+  __shared__ float ls[16][64];
+  ls[w][lane] = s;
+  __syncthreads();
+  if (w == 0 && j < n) {
+    float t = 0.f;
+    for (int k = 0; k < 16; ++k) t += ls[k][lane];
+    cn2[(int64_t)b * n + j] = t;
+  }
 }
 
 __global__ void k_colnorm_flag(const float* cn2, int n, float eps_qr, int* flags, const int* mask) {
@@ -1235,22 +1261,24 @@ hipError_t set_coef_launch(float* coef, const double* tab, int steps, hipStream_
   LAUNCH_CHECK();
 }
 
-hipError_t cans_check_launch(int batch, float* conv, float tol, int k, int* active, int* where,
+hipError_t cans_check_launch(int batch, const float* conv, int slots, float tol, int k, int* active, int* where,
                              int* iters, const int* iter_base, int base_stride, int* flags,
                              int* counter, hipStream_t st) {
-  hipLaunchKernelGGL(k_cans_check, dim3(1), dim3(1024), 0, st, batch, conv, tol, k, active, where,
+  hipLaunchKernelGGL(k_cans_check, dim3(1), dim3(1024), 0, st, batch, conv, slots, tol, k, active, where,
                      iters, iter_base, base_stride, flags, counter);
   LAUNCH_CHECK();
 }
 
-hipError_t residual_launch(const void* G, int gbf16, int batch, int n, float* resid, const int* mask,
-                           hipStream_t st) {
+size_t residual_part_floats(int64_t batch) { return (size_t)batch * kResidBlocks * 4; }
+
+hipError_t residual_launch(const void* G, int gbf16, int batch, int n, float* part, float* resid,
+                           const int* mask, hipStream_t st) {
   hipError_t e;
-  if ((e = fill_f32(resid, 0.f, batch, st))) return e;
-  hipLaunchKernelGGL(k_residual, dim3(std::min(n, 64), batch), dim3(256), 0, st, G, gbf16, n,
-                     resid, mask);
+  hipLaunchKernelGGL(k_residual, dim3(std::min(n, kResidBlocks), batch), dim3(256), 0, st, G, gbf16, n,
+                     part, mask);
   if ((e = hipGetLastError())) return e;
-  hipLaunchKernelGGL(k_residual_finish, dim3(cdiv(batch, 256)), dim3(256), 0, st, batch, n, resid, mask);
+  hipLaunchKernelGGL(k_residual_finish, dim3(cdiv(batch, 256)), dim3(256), 0, st, batch, n, part, resid,
+                     mask);
   LAUNCH_CHECK();
 }
 
@@ -1258,10 +1286,7 @@ hipError_t colnorm_check_launch(const float* U, int64_t ldu, int64_t sU, int bat
                                 float* colnorm2, float eps_qr, int* flags, const int* mask,
                                 hipStream_t st) {
   hipError_t e;
-  if ((e = fill_f32(colnorm2, 0.f, (int64_t)batch * n, st))) return e;
-  const int rows_per = 256;
-  hipLaunchKernelGGL(k_colnorm, dim3(cdiv(n, 256), cdiv(m, rows_per), batch), dim3(256), 0, st, U, ldu,
-                     sU, m, n, rows_per, colnorm2, mask);
+  hipLaunchKernelGGL(k_colnorm, dim3(cdiv(n, 64), batch), dim3(1024), 0, st, U, ldu, sU, m, n, colnorm2, mask);
   if ((e = hipGetLastError())) return e;
   hipLaunchKernelGGL(k_colnorm_flag, dim3(batch), dim3(256), 0, st, colnorm2, n, eps_qr, flags, mask);
   LAUNCH_CHECK();

@@ -29,12 +29,16 @@ hipError_t set_coef_launch(float* coef, const double* tab, int steps, hipStream_
 // After step k: matrices whose relative change is <= tol stop (active = 0),
 // where[b] = parity of the buffer holding their last iterate;
 // iters[b] = iter_base[b * base_stride] + k + 1 (base 0 when iter_base is
-// null); conv sums are cleared; *counter = number still active.
-hipError_t cans_check_launch(int batch, float* conv, float tol, int k, int* active, int* where,
+// null); conv: per matrix `slots` (change, output) sums of squares written by
+// the update GEMM's sub-tiles (gemm_conv_slots), added in slot order;
+// *counter = number still active.
+hipError_t cans_check_launch(int batch, const float* conv, int slots, float tol, int k, int* active, int* where,
                              int* iters, const int* iter_base, int base_stride, int* flags,
                              int* counter, hipStream_t st);
-// residual[b] = |G - I|_F / sqrt(n) from a Gram matrix G (FP32 or BF16)
-hipError_t residual_launch(const void* G, int gbf16, int batch, int n, float* resid,
+// residual[b] = |G - I|_F / sqrt(n) from a Gram matrix G (FP32 or BF16);
+// part: residual_part_floats(batch) floats of per-workgroup partial sums
+size_t residual_part_floats(int64_t batch);
+hipError_t residual_launch(const void* G, int gbf16, int batch, int n, float* part, float* resid,
                            const int* mask, hipStream_t st);
 
 // ---- U column-norm check (Algorithm 1, rank-deficiency test) --------------

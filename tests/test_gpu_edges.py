@@ -340,6 +340,27 @@ def test_repeatable(api):
         outs.append([t.cpu().numpy() for t in (U, S, V)] + [api.info_to_numpy(info)["iters"]])
     for a, b in zip(outs[0], outs[1]):
         np.testing.assert_array_equal(a, b)
+    # the benchmark's batch (256 x 512^2) on both paths, forward and backward:
+    # every reduction that feeds a decision (stop tests, sweep and restart
+    # tests, residual, column norms, features) runs in a fixed order
+    import torch
+    A, _ = inputs.square_loguniform(seed=2, batch=256, n=512)
+    Ad = dev(A)
+    probe = dev(inputs.probe(13, 256, 512))
+    rng = np.random.default_rng(7)
+    dU, dV = dev(rng.standard_normal((256, 512, 512))), dev(rng.standard_normal((256, 512, 512)))
+    dS = dev(rng.standard_normal((256, 512)))
+    for kw in (dict(), dict(precision=1, bound=1, probe=probe, fp64_sweeps=1, eigh_off_tol=1e-4,
+                                jacobi_fro_tol=1e-3)):
+        runs = []
+        for _ in range(2):
+            U, S, V, info = api.svd_fwd(Ad, handle=h, **kw)
+            dA = api.svd_bwd(U, S, V, dU, dS, dV, handle=h)
+            torch.cuda.synchronize()
+            runs.append([t.cpu().numpy() for t in (U, S, V, info, dA)])
+        for a, b in zip(runs[0], runs[1]):
+            np.testing.assert_array_equal(a, b)
+        _say(f"  256 x 512^2 {'learned' if kw else 'plain'}: two runs bit for bit equal")
 
 
 def test_autograd_svd_and_polar(api):
