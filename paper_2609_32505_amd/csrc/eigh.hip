@@ -1023,7 +1023,8 @@ static bool eigh_deferred(int64_t np) { return np <= 1024; }
 // workgroups per matrix of the restart measure (each a run of 32 x 32 tile pairs)
 static int restart_chunks(int64_t n, int64_t batch) {
   const int64_t nt = (n + 31) / 32, npairs = nt * (nt + 1) / 2;
-  return (int)std::max<int64_t>(1, std::min<int64_t>(npairs, (2048 + batch - 1) / batch));
+  const int64_t per = batch > 0 ? (2048 + batch - 1) / batch : 2048;  // an empty batch sizes nothing
+  return (int)std::max<int64_t>(1, std::min<int64_t>(npairs, per));
 }
 
 size_t eigh_ws_bytes(int64_t batch, int64_t n, int max_sweeps) {
