@@ -116,13 +116,14 @@ typedef struct {
                               its square; tightly clustered spectra need the margin (3e-3) */
   double jacobi_abs;       /* entries below jacobi_abs |H|_F are ignored by that test (1e-9) */
   double bf16_from;        /* bounded paths: FP32 steps until the interval's lower end
-                              reaches this value, BF16 steps after it (0.5).  BF16 rounding
+                              reaches this value, BF16 steps after it (0.2).  BF16 rounding
                               while a singular value is still small rotates its singular
-                              vectors and moves the small singular values: lower values buy
-                              speed with larger errors (256 x 512^2, sigma in [1e-3, 1], with
-                              the FP64 final sweep: largest per-value relative sigma error
-                              5.8e-4 at 0.5, 0.8-1e-3 at 0.3, 1.5e-3 at 0.2, 3.4e-3 at 0.1,
-                              for 0.7 ms per 256 matrices between 0.3 and 0.5) */
+                              vectors and moves the small singular values; the BF16
+                              correction (bf16_correct) removes that to first order.  With
+                              it, on 256 x 512^2 with sigma in [1e-3, 1], the largest
+                              per-value relative sigma error against the FP32 path is 1e-4
+                              from 0.5 down to 0.2 and 2e-4 at 0.1; at 0.01 it is 2e-2.
+                              Below 0.1 the column-norm test starts flagging (eps_qr) */
   double eps_K, eps_R, eps_T; /* backward regularisers (absolute, units of sigma^2):
                               K_ij = (s_i - s_j)/((s_i - s_j)^2 + eps_K),
                               R = V S (S^2 + eps_R)^-1 V^T,

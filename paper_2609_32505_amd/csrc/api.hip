@@ -1016,7 +1016,7 @@ void svdp_default_params(svdp_params* p, int64_t batch, int64_t m, int64_t n) {
   p->refine_tol = 1e-2;
   p->jacobi_tol = 3e-3;
   p->jacobi_abs = 1e-9;
-  p->bf16_from = 0.5;
+  p->bf16_from = 0.2;
   p->margin_max = 1.1;
   p->margin_min = 1.0;
   p->eigh_off_tol = 6e-6;

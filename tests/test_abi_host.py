@@ -43,7 +43,7 @@ def test_params_struct_matches_header_layout():
     assert (p.batch, p.m, p.n) == (3, 20, 10)
     assert (p.max_iters, p.pre_iters, p.refine_steps) == (50, 2, 2)
     assert p.delta == 0.99 and p.tol == 1e-5 and p.eps_qr == 1e-5
-    assert p.jacobi_tol == 3e-3 and p.bf16_from == 0.5
+    assert p.jacobi_tol == 3e-3 and p.bf16_from == 0.2
     assert p.margin_max == 1.1 and p.margin_min == 1.0
     assert p.eps_K == 0.0 and p.user_bounds is None and p.probe is None
     assert p.eigh_off_tol == 6e-6 and p.eigh_restarts == 2 and p.jacobi_fro_tol == 3e-4 and p.poly == 0
