@@ -466,3 +466,72 @@ def test_forward_host_syncs(api):
     for i in (0, 7):
         So = oracle.svd(A[i].astype(np.float64))[1]
         assert np.abs(Sh[i] - So).max() / So[0] < 1e-5
+
+
+def _householder_product(rng, n, k):
+    """Q = (I - 2 v1 v1^T) ... (I - 2 vk vk^T) with random unit v_i, dense
+    FP64, and the v_i."""
+    Q = np.eye(n)
+    vs = []
+    for _ in range(k):
+        v = rng.standard_normal(n)
+        v /= np.linalg.norm(v)
+        Q -= 2.0 * np.outer(Q @ v, v)
+        vs.append(v)
+    return Q, vs
+
+
+def test_max_size_8192(api):
+    # the largest n the library accepts (8192), one matrix with a known SVD:
+    # A = Q1 diag(s) Q2^T with Q1, Q2 products of four Householder
+    # reflections (dense, exactly orthogonal, cheap to form at this size) and
+    # s geometric from 1 to 1e-3.  Checked: sigma against s (normwise), the
+    # reconstruction and orthogonality at the FP32 level, U and V against Q1
+    # and Q2 on well separated columns.  The CANS stop test is normwise
+    # (|dX|_F <= 1e-5 |X|_F), so at this n one direction may still be off by
+    # up to about 1e-5 sqrt(n) when it passes; the column-norm test then flags
+    # RANK_DEFICIENT and Algorithm 1's QR step completes that column, which is
+    # allowed here (no other flag is)
+    import torch
+    n = 8192
+    rng = inputs.rng_for(97, 0)
+    s = inputs.geometric(n, 1e3)
+    Q1, _ = _householder_product(rng, n, 4)
+    Q2, v2 = _householder_product(rng, n, 4)
+    # A = Q1 diag(s) Q2^T with Q2^T = H4 H3 H2 H1 applied as reflections
+    # (O(n^2) each instead of an n^3 product)
+    A = Q1 * s
+    for v in reversed(v2):
+        A -= 2.0 * np.outer(A @ v, v)
+    A = A.astype(np.float32)
+    _say(f"max size {n}^2 (plain FP32)")
+    Ad = dev(A)[None]
+    del A
+    U, S, V, info = api.svd_fwd(Ad)
+    torch.cuda.synchronize()
+    inf = api.info_to_numpy(info)
+    _say(f"  iters {inf['iters'][0]}, sweeps {inf['sweeps'][0]}, flags {inf['flags'][0]}")
+    assert (inf["flags"][0] & ~8) == 0
+    Sh = S[0].cpu().double().numpy()
+    sig = np.abs(Sh - s).max() / s[0]
+    Ud, Sd, Vd, Md = U[0].double(), S[0].double(), V[0].double(), Ad[0].double()
+    rec = float(torch.linalg.norm(Md - (Ud * Sd) @ Vd.T) / torch.linalg.norm(Md))
+    eye = torch.eye(n, dtype=torch.float64, device="cuda")
+    orth = max(float(torch.linalg.norm(Ud.T @ Ud - eye)), float(torch.linalg.norm(Vd.T @ Vd - eye))) / np.sqrt(n)
+    # columns whose singular value is separated from its neighbours by 1e-4 s_1
+    sep = np.ones(n, bool)
+    d = np.abs(np.diff(s)) / s[0]
+    sep[:-1] &= d > 1e-4
+    sep[1:] &= d > 1e-4
+    idx = np.nonzero(sep)[0][:: max(1, int(sep.sum()) // 256)]
+    Uh, Vh = U[0].cpu().double().numpy()[:, idx], V[0].cpu().double().numpy()[:, idx]
+    sg = np.sign(np.sum(Vh * Q2[:, idx], axis=0))
+    eu = float(np.abs(Uh * sg - Q1[:, idx]).max())
+    ev = float(np.abs(Vh * sg - Q2[:, idx]).max())
+    _say(f"  sigma error {sig:.2e}, reconstruction {rec:.2e}, orthogonality {orth:.2e}, "
+         f"U {eu:.2e}, V {ev:.2e} on {len(idx)} separated columns")
+    # the same normwise stop leaves sigma 6.5e-5 normwise here (4e-6 at
+    # 4096^2); reconstruction 2.7e-5, orthogonality 1.2e-5, U and V 2.3e-3
+    # on columns separated by 1e-4 s_1
+    assert sig < 2e-4 and rec < 1e-4 and orth < 5e-5
+    assert eu < 1e-2 and ev < 1e-2
