@@ -13,9 +13,10 @@ Contents (each function cites the passage of the paper it follows):
   initialisation (Algorithm 3), the degree-3 CANS polynomial and its
   interval recursion, the CANS polar iteration, the iteration variants of
   the appendix's polar-iteration ablation (classical Newton-Schulz, the
-  degree-5 interval-optimal polynomial), the symmetric EVD backward
-  (the EVD pseudo-gradient theorem), the sketch features and the small MLP
-  (forward, backward, pinball loss, Adam) of the learned interval predictor.
+  degree-5 interval-optimal polynomial, the Polar Express schedule), the
+  symmetric EVD backward (the EVD pseudo-gradient theorem), and for the
+  learned interval predictor its sketch features, training targets, feature
+  standardisation and the small MLP (forward, backward, pinball loss, Adam).
 
 Parity status: every function here is pinned by a ``-m "not gpu"`` test in
 ``tests/test_oracle_*.py`` against closed forms, invariants, brute force or
