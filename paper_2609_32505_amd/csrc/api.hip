@@ -352,7 +352,7 @@ struct FwdWs {
   float* P;    // quintic steps: c3 G + c5 G^2, n x n per matrix
   float *Qt, *Bq, *UBq;  // QR preprocessing of tall matrices: Q (m x n), B = Q^T A and U_B (n x n)
   int* qmask;  // blocked QR: the flagged matrices
-  int *active, *where, *iters, *flags, *sweeps, *mask, *counter, *ksteps, *kmax, *hist, *gmask;
+  int *active, *where, *iters, *flags, *sweeps, *mask, *counter, *ksteps, *gmask;
 };
 
 FwdWs carve_fwd(void* base, const svdp_params* p, size_t* total) {
@@ -401,8 +401,6 @@ FwdWs carve_fwd(void* base, const svdp_params* p, size_t* total) {
   w.gmask = c.take<int>(b);
   w.counter = c.take<int>(16);
   w.ksteps = c.take<int>(2 * b);
-  w.kmax = c.take<int>(16);
-  w.hist = c.take<int>(4 * 64 + 8);
   w.Qt = c.take<float>(tall_qr ? b * m * n : 0);
   w.Bq = c.take<float>(tall_qr ? b * n * n : 0);
   w.UBq = c.take<float>(tall_qr ? b * n * n : 0);
@@ -495,11 +493,9 @@ hipError_t cans_step(Ctx& c, int prec, const void* Xc, void* Xn, int in_bf16, in
 
 // One quintic step (FP32): G = Xc^T Xc, P = c5 G G + c3 G, Xn = c1 Xc + Xc P,
 // with the change sums of the stop test from the last product.
-hipError_t cans5_step(Ctx& c, const float* Xc, float* Xn, const double* cf, const int* active, float* conv,
-                      int n_active) {
+hipError_t cans5_step(Ctx& c, const float* Xc, float* Xn, const double* cf, const int* active, float* conv) {
   const int m = c.m, n = c.n, B = c.batch;
   GemmArgs g = gemm_base(n, n, m, B);
-  g.work_batch = n_active;
   g.A = Xc; g.lda = n; g.sA = (int64_t)m * n;
   g.B = Xc; g.ldb = n; g.sB = (int64_t)m * n;
   g.C = c.w.G; g.ldc = n; g.sC = (int64_t)n * n;
@@ -508,7 +504,6 @@ hipError_t cans5_step(Ctx& c, const float* Xc, float* Xn, const double* cf, cons
   hipError_t e = gemm_launch(g, PREC_F32, 1, 0, c.st);
   if (e) return e;
   GemmArgs q = gemm_base(n, n, n, B);
-  q.work_batch = n_active;
   q.A = c.w.G; q.lda = n; q.sA = (int64_t)n * n;
   q.B = c.w.G; q.ldb = n; q.sB = (int64_t)n * n;
   q.C = c.w.P; q.ldc = n; q.sC = (int64_t)n * n;
@@ -518,7 +513,6 @@ hipError_t cans5_step(Ctx& c, const float* Xc, float* Xn, const double* cf, cons
   q.active = active;
   if ((e = gemm_launch(q, PREC_F32, 0, 0, c.st))) return e;
   GemmArgs u = gemm_base(m, n, n, B);
-  u.work_batch = n_active;
   u.A = Xc; u.lda = n; u.sA = (int64_t)m * n;
   u.B = c.w.P; u.ldb = n; u.sB = (int64_t)n * n;
   u.C = Xn; u.ldc = n; u.sC = (int64_t)m * n;
@@ -557,7 +551,7 @@ svdp_status conservative_fp32(Ctx& c, const int* mask) {
     for (int k = 0; k < T; ++k) {
       const float* Xc = (k & 1) ? w.X1 : w.X0;
       float* Xn = (k & 1) ? w.X0 : w.X1;
-      HIPCHK(cans5_step(c, Xc, Xn, tab3 + 3 * k, w.active, nullptr, B), "pe step");
+      HIPCHK(cans5_step(c, Xc, Xn, tab3 + 3 * k, w.active, nullptr), "pe step");
     }
     HIPCHK(fill_masked_launch(w.where, T & 1, B, mask, c.st), "where");
     HIPCHK(fill_masked_launch(w.iters, T, B, mask, c.st), "iters");
@@ -576,7 +570,7 @@ svdp_status conservative_fp32(Ctx& c, const int* mask) {
     const float* Xc = (k & 1) ? w.X1 : w.X0;
     float* Xn = (k & 1) ? w.X0 : w.X1;
     if (p->poly == SVDP_POLY_CANS5)
-      HIPCHK(cans5_step(c, Xc, Xn, tab3 + 3 * k, w.active, w.conv, 0), "cans5 step");
+      HIPCHK(cans5_step(c, Xc, Xn, tab3 + 3 * k, w.active, w.conv), "cans5 step");
     else
       HIPCHK(cans_step(c, PREC_F32, Xc, Xn, 0, 0, w.coef, 0, k, w.active, w.conv), "cans step");
     HIPCHK(cans_check_launch(B, w.conv, gemm_conv_slots(m, n), (float)p->tol, k, w.active, w.where, w.iters,
@@ -619,10 +613,10 @@ svdp_status bounded(Ctx& c) {
     HIPCHK(mlp_fwd_launch(c.h->model, c.h->model + SVDP_MLP_PARAMS, c.h->model + SVDP_MLP_PARAMS + 8, w.F, B,
                           w.mlpout, nullptr, c.st), "mlp");
     HIPCHK(bounds_launch(B, 0, w.mlpout, w.aux, nullptr, p->margin_max, p->margin_min, p->bf16_handoff,
-                         p->bf16_from, kcap, w.scale, w.coef, w.ksteps, w.kmax, nullptr, c.st), "bounds");
+                         p->bf16_from, kcap, w.scale, w.coef, w.ksteps, nullptr, c.st), "bounds");
   } else {
     HIPCHK(bounds_launch(B, 1, nullptr, nullptr, p->user_bounds, p->margin_max, p->margin_min, p->bf16_handoff,
-                         p->bf16_from, kcap, w.scale, w.coef, w.ksteps, w.kmax, nullptr, c.st), "bounds");
+                         p->bf16_from, kcap, w.scale, w.coef, w.ksteps, nullptr, c.st), "bounds");
   }
   // Every matrix runs its own schedule: K interval-optimal steps, the first
   // K1 in FP32 (while small singular values are still small: BF16 rounding

@@ -39,7 +39,6 @@ struct GemmArgs {
   void* C_bf;          // (same leading dimension and stride as C), else to C
   float* conv;         // per matrix and wave sub-tile (gemm_conv_slots slots): sum (out - Cin)^2, sum out^2
   int sym;             // output symmetric: upper tiles computed, mirrored
-  int work_batch;      // matrices actually computed (for work accounting; 0 = batch)
   int out_bf16, in_bf16, cin_bf16;
   void* Ct; int64_t ldct, sCt;  // out_bf16: also write the output transposed, Ct[j, i] (BF16)
   double* work;        // profiling: += the algorithmic flops of each tile computed

@@ -1109,7 +1109,7 @@ SVDP_DEV void cans_poly_dev(double a, double b, double& al, double& be, double& 
 __global__ void k_bounds(int batch, int mode, const float* mlp_out, const float* aux,
                          const float* user_bounds, double margin_max, double margin_min,
                          double handoff, double bf16_from, int kcap, float* scale, float* coef,
-                         int* ksteps, int* kmax, const int* mask) {
+                         int* ksteps, const int* mask) {
   int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= batch || skip(mask, b)) return;
   double smax, smin;
@@ -1147,8 +1147,6 @@ __global__ void k_bounds(int batch, int mode, const float* mlp_out, const float*
   }
   ksteps[2 * b] = K;
   ksteps[2 * b + 1] = K1;
-  atomicMax(kmax, K);
-  atomicMax(kmax + 1, K1);
 }
 
 // ------------------------------------------------------------ info
@@ -1443,13 +1441,11 @@ hipError_t adam_launch(float* p, float* m, float* v, const float* g, int64_t n, 
 
 hipError_t bounds_launch(int batch, int mode, const float* mlp_out, const float* aux,
                          const float* user_bounds, double margin_max, double margin_min, double handoff,
-                         double bf16_from, int kcap, float* scale, float* coef, int* ksteps, int* kmax,
+                         double bf16_from, int kcap, float* scale, float* coef, int* ksteps,
                          const int* mask, hipStream_t st) {
-  hipError_t e;
-  if ((e = fill_i32(kmax, 0, 2, st))) return e;
   hipLaunchKernelGGL(k_bounds, dim3(cdiv(batch, 64)), dim3(64), 0, st, batch, mode, mlp_out, aux,
                      user_bounds, margin_max, margin_min, handoff, bf16_from, kcap, scale, coef, ksteps,
-                     kmax, mask);
+                     mask);
   LAUNCH_CHECK();
 }
 
@@ -1496,22 +1492,6 @@ hipError_t count_mask_launch(int batch, const int* mask, int* counter, hipStream
 }
 
 namespace {
-// counts[4 k + c] = matrices whose step k has category c (sched_cat), for
-// k < kcap; counts[4 kcap] = matrices starting in BF16 (K1 = 0);
-// counts[4 kcap + 1] = the largest step count.
-__global__ void k_sched_counts(int batch, const int* ksteps, int kcap, int bf16, int* counts) {
-  __shared__ int h[4 * 64 + 2];
-  for (int i = threadIdx.x; i < 4 * kcap + 2; i += blockDim.x) h[i] = 0;
-  __syncthreads();
-  for (int b = threadIdx.x; b < batch; b += blockDim.x) {
-    const int K = min(max(ksteps[2 * b], 1), kcap);
-    for (int k = 0; k < K; ++k) atomicAdd(&h[4 * k + sched_cat(ksteps, b, k, bf16)], 1);
-    if (sched_cat(ksteps, b, 0, bf16) >= 2) atomicAdd(&h[4 * kcap], 1);
-    atomicMax(&h[4 * kcap + 1], K);
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < 4 * kcap + 2; i += blockDim.x) counts[i] = h[i];
-}
 // what = 0: the schedule starts in FP32; 1: it starts in BF16; 2: the last
 // iterate is in the odd buffer (K odd)
 __global__ void k_sched_mask(int batch, const int* ksteps, int bf16, int what, int* mask) {
@@ -1546,11 +1526,6 @@ __global__ void k_copy_masked1(const float* src, float* dst, int64_t per_matrix,
 }
 }  // namespace
 
-hipError_t sched_counts_launch(int batch, const int* ksteps, int kcap, int bf16, int* counts, hipStream_t st) {
-  if (kcap > 64) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_sched_counts, dim3(1), dim3(1024), 0, st, batch, ksteps, kcap, bf16, counts);
-  LAUNCH_CHECK();
-}
 hipError_t sched_mask_launch(int batch, const int* ksteps, int bf16, int what, int* mask, hipStream_t st) {
   hipLaunchKernelGGL(k_sched_mask, dim3(cdiv(batch, 256)), dim3(256), 0, st, batch, ksteps, bf16, what, mask);
   LAUNCH_CHECK();

@@ -123,14 +123,13 @@ hipError_t pinball_launch(const float* out, const float* target, int rows, float
 hipError_t adam_launch(float* p, float* m, float* v, const float* g, int64_t n, float lr, float b1,
                        float b2, float eps, int t, hipStream_t st);
 // Learned / user bounds -> per-matrix scale, interval-optimal coefficient
-// table and BF16 step count (FP64 scalar recursion); *kmax = max count.
-// ksteps[2b] = steps of matrix b to the hand-off (K), ksteps[2b+1] = FP32
-// steps before its interval's lower end reaches bf16_from (K1); kmax[0..1]
-// the batch maxima.
+// table and BF16 step count (FP64 scalar recursion): ksteps[2b] = steps of
+// matrix b to the hand-off (K), ksteps[2b+1] = FP32 steps before its
+// interval's lower end reaches bf16_from (K1).
 hipError_t bounds_launch(int batch, int mode, const float* mlp_out, const float* aux,
                          const float* user_bounds, double margin_max, double margin_min,
                          double handoff, double bf16_from, int kcap, float* scale, float* coef,
-                         int* ksteps, int* kmax, const int* mask, hipStream_t st);
+                         int* ksteps, const int* mask, hipStream_t st);
 
 // ---- info ------------------------------------------------------------------
 hipError_t info_pack_launch(int batch, const int* iters, const int* sweeps, const int* flags,
@@ -143,11 +142,6 @@ hipError_t or_flags_launch(int batch, int* flags, int bits, const int* mask, hip
 hipError_t fill_masked_launch(int* p, int v, int n, const int* mask, hipStream_t st);
 // *counter = number of nonzero mask entries
 hipError_t count_mask_launch(int batch, const int* mask, int* counter, hipStream_t st);
-// Bounded CANS schedule from the per-matrix step counts ksteps = (K, K1):
-// counts[4 k + c] = matrices whose step k has category c (sched_cat, k <
-// kcap <= 64), counts[4 kcap] = matrices starting in BF16, counts[4 kcap +
-// 1] = the largest K.
-hipError_t sched_counts_launch(int batch, const int* ksteps, int kcap, int bf16, int* counts, hipStream_t st);
 // mask[b] = schedule starts in FP32 (what 0), in BF16 (1), or K is odd (2)
 hipError_t sched_mask_launch(int batch, const int* ksteps, int bf16, int what, int* mask, hipStream_t st);
 // iters[b] = K
