@@ -51,8 +51,8 @@ constexpr int PB = 32;      // pair subproblem size
 constexpr int GS = 64;      // group size (four blocks)
 constexpr int LP = PB + 1;  // LDS pitch of 32-wide arrays
 constexpr int GP = GS + 1;  // LDS pitch of 64-wide arrays
-// per group: M_G (64 x 64) and the step-A rotations (2 x 32 x 32), FP32
-constexpr int QSTRIDE = GS * GS + 2 * PB * PB;
+// per group: M_G (64 x 64, FP32)
+constexpr int QSTRIDE = GS * GS;
 // A restart sweeps T = V^T H V formed by FP32 GEMMs, resolved to about
 // 2^-24 |H|_F: a pair whose 2 x 2 block (h_pp, h_qq, h_pq) lies entirely
 // below that level is not rotated there.  Rotating such pairs only stirs a
@@ -155,14 +155,57 @@ SVDP_DEV double lane_xor<double>(double v, int lane, int m) {
                           __builtin_amdgcn_ds_bpermute((lane ^ m) << 2, lo));
 }
 
-// Scalar Jacobi rounds t0 .. 31 (repeated inner_sweeps times) on pair w of
-// the step.  One wavefront, no workgroup barrier.  Lane l (q = l / 16,
+// DPP moves inside each row of 16 lanes (no LDS): quad_perm [1,0,3,2]
+// (lane ^ 1), quad_perm [3,2,1,0] (^ 3), row_half_mirror (^ 7), row_mirror
+// (^ 15)
+template <int CTRL>
+SVDP_DEV float dpp_mov(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+SVDP_DEV double dpp_mov(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  return __hiloint2double(__builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false),
+                          __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false));
+}
+// v[u] <- v[u] of lane ^ d, for d = 2^k - 1 in {1, 3, 7, 15} (wave-uniform)
+template <typename R>
+SVDP_DEV void xor_row(R (&v)[8], int d) {
+  if (d == 1) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = dpp_mov<0xB1>(v[u]);
+  } else if (d == 3) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = dpp_mov<0x1B>(v[u]);
+  } else if (d == 7) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = dpp_mov<0x141>(v[u]);
+  } else {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = dpp_mov<0x140>(v[u]);
+  }
+}
+
+// Scalar Jacobi rounds on pair w of the step (repeated inner_sweeps times):
+// the rounds t0 .. 15 inside the two 16-blocks, then the 16 rounds across
+// them.  One wavefront, no workgroup barrier.  Lane l (q = l / 16,
 // kx = l % 16) updates, per round, the 2 x 2 blocks (rotation kx) x
-// (rotations q + 4 u) of the subproblem, and holds rows q + 4 u of columns
-// kx and 16 + kx of the accumulated rotation J in registers (jp, jq): a
-// round rotates column pairs (a, a ^ t), which lives in lanes l and l ^ t
-// (t < 16) or l ^ (t - 16) (t >= 16), so one register exchange per entry
-// replaces LDS traffic.
+// (rotations q + 4 u) of the subproblem, and holds rows q + 4 u of two
+// columns of the accumulated rotation J in registers (jp, jq).
+//   * Inside the blocks (round t < 16) a round rotates column pairs
+//     (a, a ^ t): jp is column kx and jq column 16 + kx, and the partner
+//     columns come from lane l ^ t by a register exchange.
+//   * Across the blocks, round m = 0 .. 15 pairs index k with 16 + (k ^ m).
+//     jq holds column 16 + (kx ^ m), so both columns of the lane's pair are
+//     in the lane; between rounds jq moves to lane l ^ m ^ (m + 1), where
+//     m ^ (m + 1) is 1, 3, 7 or 15: one DPP move inside the lane's row.
+//     After the last round (m = 15) it moves back to column 16 + kx.
+// A round issues all of its LDS traffic that does not depend on the round's
+// rotations at once (the lane's four 2 x 2 blocks and, inside the blocks,
+// the partner lanes' J entries).  The lane whose blocks include the
+// diagonal block of rotation kx (q = kx mod 4, u = kx / 4) computes that
+// rotation from it, so the only round trip that waits on another lane is the
+// exchange of the 16 (c, s) pairs.
 template <typename R, int STEPB>
 SVDP_DEV void pair_solve(SolveLds<R>& L, int w, int lane, int t0, int inner_sweeps, R floor_abs, R skip_abs,
                          float& mrel, float& vsum, R (&jp)[8], R (&jq)[8]) {
@@ -170,6 +213,8 @@ SVDP_DEV void pair_solve(SolveLds<R>& L, int w, int lane, int t0, int inner_swee
   R (*X)[XP] = L.X;
   RotPair<R>* cs = L.cs[w];
   const int kx = lane & 15, q = lane >> 4;
+  const bool rlane = q == (kx & 3);  // holds the diagonal block of rotation kx
+  const int ud = kx >> 2;            // ... as its block ud
 #pragma unroll
   for (int u = 0; u < 8; ++u) {
     jp[u] = (q + 4 * u == kx) ? R(1) : R(0);
@@ -188,9 +233,36 @@ SVDP_DEV void pair_solve(SolveLds<R>& L, int w, int lane, int t0, int inner_swee
     };
     int x1, y1;
     pair_of(kx, x1, y1);
-    const int gx1 = gpos<STEPB>(w, x1), gy1 = gpos<STEPB>(w, y1);
-    if (lane < 16) {
-      const R app = X[gx1][gx1], aqq = X[gy1][gy1], apq = R(0.5) * (X[gx1][gy1] + X[gy1][gx1]);
+    R* rowx = X[gpos<STEPB>(w, x1)];
+    R* rowy = X[gpos<STEPB>(w, y1)];
+    // the lane's four 2 x 2 blocks are disjoint from every other lane's:
+    // all loads first, then all stores (one LDS round trip)
+    int cx[4], cy[4];
+    R a[4], bq[4], cq[4], d[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      int x2, y2;
+      pair_of(q + 4 * u, x2, y2);
+      cx[u] = gpos<STEPB>(w, x2);
+      cy[u] = gpos<STEPB>(w, y2);
+      a[u] = rowx[cx[u]]; bq[u] = rowx[cy[u]]; cq[u] = rowy[cx[u]]; d[u] = rowy[cy[u]];
+    }
+    // inside the blocks: the partner lane's J entries, columns kx ^ t (op)
+    // and 16 + (kx ^ t) (oq)
+    R op[8], oq[8];
+    if (!CROSS) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        op[u] = lane_xor<R>(jp[u], lane, t);
+        oq[u] = lane_xor<R>(jq[u], lane, t);
+      }
+    }
+    if (rlane) {
+      R app = a[0], aqq = d[0], bd = bq[0], cd = cq[0];
+#pragma unroll
+      for (int u = 1; u < 4; ++u)
+        if (ud == u) { app = a[u]; aqq = d[u]; bd = bq[u]; cd = cq[u]; }
+      const R apq = R(0.5) * (bd + cd);
       RotPair<R> r{R(1), R(0)};
       if (apq != R(0) && isfinite((float)apq) && fmax(fmax(fabs(app), fabs(aqq)), fabs(apq)) > skip_abs) {
         rotation_fast(app, aqq, apq, r.c, r.s);
@@ -202,40 +274,20 @@ SVDP_DEV void pair_solve(SolveLds<R>& L, int w, int lane, int t0, int inner_swee
           mrel = fmaxf(mrel, den2 > 0.f ? fabsf((float)apq) * __builtin_amdgcn_rsqf(den2) : 1e30f);
         }
       }
-      cs[lane] = r;
+      cs[kx] = r;
     }
     wave_sync();
     const RotPair<R> r1 = cs[kx];
-    R* rowx = X[gx1];
-    R* rowy = X[gy1];
-    // the lane's four 2 x 2 blocks are disjoint from every other lane's:
-    // all loads first, then all stores (one LDS round trip)
-    int cx[4], cy[4];
     RotPair<R> r2[4];
-    R a[4], bq[4], cq[4], d[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      int x2, y2;
-      pair_of(q + 4 * u, x2, y2);
-      cx[u] = gpos<STEPB>(w, x2);
-      cy[u] = gpos<STEPB>(w, y2);
-      r2[u] = cs[q + 4 * u];
-      a[u] = rowx[cx[u]]; bq[u] = rowx[cy[u]]; cq[u] = rowy[cx[u]]; d[u] = rowy[cy[u]];
-    }
-    // rotations of the lane's two J columns: column kx pairs with the
-    // partner lane's column (cross: 16 + (kx ^ m), intra: kx ^ t), and column
-    // 16 + kx with the partner's (kx ^ m, resp. 16 + (kx ^ t)).  A column
-    // that is the first of its pair becomes c x - s y, the second c x + s y:
-    // the sign goes into s once per round.
-    const int m = t & 15;
-    RotPair<R> rp, rq;
-    R sp, sq;
-    if (CROSS) {
-      rp = cs[kx];
-      rq = cs[kx ^ m];
-      sp = -rp.s;
-      sq = rq.s;
-    } else {
+    for (int u = 0; u < 4; ++u) r2[u] = cs[q + 4 * u];
+    // inside the blocks, the rotations of the lane's two J columns: column
+    // kx pairs with the partner's kx ^ t, column 16 + kx with 16 + (kx ^ t).
+    // A column that is the first of its pair becomes c x - s y, the second
+    // c x + s y: the sign goes into s once per round.
+    RotPair<R> rp{}, rq{};
+    R sp{}, sq{};
+    if (!CROSS) {
       const bool first = ((kx >> hb) & 1) == 0;
       const int xs = first ? kx : kx ^ t;
       rp = cs[compress(xs, hb)];
@@ -253,19 +305,31 @@ SVDP_DEV void pair_solve(SolveLds<R>& L, int w, int lane, int t0, int inner_swee
       if (kx == q + 4 * u && r1.s != R(0)) { y01 = 0; y10 = 0; }
       rowx[cx[u]] = y00; rowx[cy[u]] = y01; rowy[cx[u]] = y10; rowy[cy[u]] = y11;
     }
+    if (CROSS) {
+      // the pair (kx, 16 + (kx ^ m)): jp = c jp - s jq, jq = s jp + c jq
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const R op = lane_xor<R>(jp[u], lane, m);  // partner's column kx ^ m
-      const R oq = lane_xor<R>(jq[u], lane, m);  // partner's column 16 + (kx ^ m)
-      jp[u] = rp.c * jp[u] + sp * (CROSS ? oq : op);
-      jq[u] = rq.c * jq[u] + sq * (CROSS ? op : oq);
+      for (int u = 0; u < 8; ++u) {
+        const R p = jp[u], qv = jq[u];
+        jp[u] = r1.c * p - r1.s * qv;
+        jq[u] = r1.s * p + r1.c * qv;
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        jp[u] = rp.c * jp[u] + sp * op[u];
+        jq[u] = rq.c * jq[u] + sq * oq[u];
+      }
     }
     wave_sync();
   };
   for (int sw = 0; sw < inner_sweeps; ++sw) {
     int any = 0;
     for (int t = t0; t < 16; ++t) round(std::false_type{}, t, any);
-    for (int t = t0 > 16 ? t0 : 16; t < PB; ++t) round(std::true_type{}, t, any);
+    for (int m = 0; m < 16; ++m) {
+      if (m > 0) xor_row(jq, m ^ (m - 1));
+      round(std::true_type{}, 16 + m, any);
+    }
+    xor_row(jq, 15);
     // every lane of the wave takes the same exit
     if (!__any(any)) break;
   }
@@ -362,44 +426,30 @@ __global__ __launch_bounds__(128) void k_jac_solve(EighWs e, EighPhase ph, int i
   const R skip_abs = (R)skip_rel * (R)sqrtf(e.hnorm2[b]);
   float mrel = 0.f, vsum = 0.f;
   float* M = qslot(e, b, e.deferred ? ph.idx : 0) + (int64_t)gi * QSTRIDE;
-  float* JAg = M + GS * GS;  // step-A rotations (FP32), read back for M_G
   R jp[8], jq[8];
   // step A
   pair_solve<R, 0>(L, w, lane, ph.fullA ? 1 : 16, inner_sweeps, floor_abs, skip_abs, mrel, vsum, jp, jq);
   j_to_lds(L, w, lane, jp, jq);
-  for (int idx = lane; idx < PB * PB; idx += 64) JAg[w * PB * PB + idx] = L.Jf[w][idx >> 5][idx & 31];
   __syncthreads();
   if (w == 0) cross_update<R, 0>(L, L.Jf[0], L.Jf[1], lane);
   __syncthreads();
   const int kh = lane >> 5, ic = lane & 31;
-  if (ph.skipB) {
-    // M_G = J_A (block diagonal)
-    for (int idx = t; idx < GS * GS; idx += 128) {
-      const int p = idx >> 6, qq = idx & 63;
-      M[idx] = (p >> 5) == (qq >> 5) ? L.Jf[p >> 5][p & 31][qq & 31] : 0.f;
+  // the step-A rotations (FP32, the lane's entries as in j_to_lds), kept in
+  // registers through step B for M_G = J_A J_B
+  float ja[8], jb[8];
+  if (!ph.skipB) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      ja[u] = (float)jp[u];
+      jb[u] = (float)jq[u];
     }
-  } else {
     // step B
     pair_solve<R, 1>(L, w, lane, 16, inner_sweeps, floor_abs, skip_abs, mrel, vsum, jp, jq);
     j_to_lds(L, w, lane, jp, jq);
     __syncthreads();
     if (w == 0) cross_update<R, 1>(L, L.Jf[0], L.Jf[1], lane);
-    // M_G = J_A J_B, block (wa, wb): rows of step-A pair wa, columns of
-    // step-B pair wb; the shared indices are local 32 wa + 16 wb + k, k < 16
-    for (int blk = w; blk < 4; blk += 2) {
-      const int wa = blk >> 1, wb = blk & 1;
-      f16v acc = zero16();
-#pragma unroll
-      for (int kk = 0; kk < 16; kk += 2)
-        acc = mfma(JAg[wa * PB * PB + ic * PB + 16 * wb + kk + kh], L.Jf[wb][16 * wa + kk + kh][ic], acc);
-#pragma unroll
-      for (int gg = 0; gg < 4; ++gg)
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          M[(32 * wa + 8 * gg + 4 * kh + r) * GS + gpos<1>(wb, ic)] = acc[4 * gg + r];
-    }
+    __syncthreads();
   }
-  __syncthreads();
   // H[G, G] back: the tiles on and above the diagonal
   for (int idx = t; idx < 16 * 64; idx += 128) {
     const int tile = idx >> 6, qd = idx & 63, k1 = tile >> 2, k2 = tile & 3;
@@ -409,6 +459,41 @@ __global__ __launch_bounds__(128) void k_jac_solve(EighWs e, EighPhase ph, int i
 #pragma unroll
     for (int w2 = 0; w2 < 4; ++w2) v[w2] = (float)L.X[k1 * 16 + r][k2 * 16 + c + w2];
     *(f4v*)(H + tile_off(g[k1], g[k2], e.nb) + qd * 4) = v;
+  }
+  if (ph.skipB) {
+    // M_G = J_A (block diagonal)
+    for (int idx = t; idx < GS * GS; idx += 128) {
+      const int p = idx >> 6, qq = idx & 63;
+      M[idx] = (p >> 5) == (qq >> 5) ? L.Jf[p >> 5][p & 31][qq & 31] : 0.f;
+    }
+  } else {
+    // J_A into the space of H[G, G], which has been written back
+    static_assert(sizeof(L.X) >= 2 * PB * LP * sizeof(float), "J_A fits in the space of H[G, G]");
+    __syncthreads();
+    float (*JA)[PB][LP] = reinterpret_cast<float (*)[PB][LP]>(&L.X[0][0]);
+    {
+      const int kx = lane & 15, q = lane >> 4;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        JA[w][q + 4 * u][kx] = ja[u];
+        JA[w][q + 4 * u][16 + kx] = jb[u];
+      }
+    }
+    __syncthreads();
+    // M_G = J_A J_B, block (wa, wb): rows of step-A pair wa, columns of
+    // step-B pair wb; the shared indices are local 32 wa + 16 wb + k, k < 16
+    for (int blk = w; blk < 4; blk += 2) {
+      const int wa = blk >> 1, wb = blk & 1;
+      f16v acc = zero16();
+#pragma unroll
+      for (int kk = 0; kk < 16; kk += 2)
+        acc = mfma(JA[wa][ic][16 * wb + kk + kh], L.Jf[wb][16 * wa + kk + kh][ic], acc);
+#pragma unroll
+      for (int gg = 0; gg < 4; ++gg)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          M[(32 * wa + 8 * gg + 4 * kh + r) * GS + gpos<1>(wb, ic)] = acc[4 * gg + r];
+    }
   }
   // largest relative off-diagonal entry rotated by this wave (float bits),
   // and the sum of squares of the entries it rotated
