@@ -9,7 +9,7 @@ struct EighWs {
   float* Vw;      // batch x np x np: accumulated rotations as 16 x 16 tiles
   float* V2;      // batch x np x np re-orthonormalised eigenvectors (row-major)
   float* lamr;    // batch x n Rayleigh-quotient eigenvalues
-  float* Qw;      // batch x (nb/4) x (64 x 64 group rotation + 2 x 32 x 32 step-A rotations)
+  float* Qw;      // batch x nph_store x (nb/4) x (64 x 64 group rotation M_G)
   float* hnorm2;  // batch: |H|_F^2
   double* off2;   // batch: |off(sym(V^T H V))|_F^2 of the last restart measure
   float* hn_part;    // batch x (nb/4)^2 x 4: |H|_F^2 per setup workgroup and wave
