@@ -44,10 +44,6 @@ SVDP_DEV void sym_tile(int t, int T, int& tm, int& tn) {
 template <typename T>
 SVDP_DEV float ld_elem(const void* p, int64_t i) { return (float)((const T*)p)[i]; }
 
-SVDP_DEV float ld_any(const void* p, int64_t i, int isbf) {
-  return isbf ? (float)((const bf16_t*)p)[i] : ((const float*)p)[i];
-}
-
 // Profiling: the tile's algorithmic flops, 2 r c K (r x c the tile inside the
 // output), half of it on the diagonal of a symmetric output (its triangle)
 SVDP_DEV void count_tile(const GemmArgs& g, int m0, int n0, int BM, int BN, int tm, int tn) {
@@ -89,6 +85,29 @@ SVDP_DEV void epilogue(const GemmArgs& g, int b, int rowbase, int colbase, int t
       if (j >= g.N) continue;
       const float csj = cs ? cs[j] : 1.f;
       const float csij = csi ? csi[j] : 1.f;
+      // the block's 16 Cin values, all loaded before its first store: the
+      // compiler cannot tell that the output does not alias Cin, so a load
+      // placed after a store would be waited for on its own
+      float cv[16];
+      if (cin) {
+        const int ib = rowbase + mi * 32 + 4 * (lane >> 5);
+        if (g.cin_bf16) {
+          bf16_t raw[16];
+#pragma unroll
+          for (int e = 0; e < 16; ++e) {
+            const int i = ib + 8 * (e >> 2) + (e & 3);
+            raw[e] = ((const bf16_t*)cin)[i < g.M ? (int64_t)i * g.ldcin + j : 0];
+          }
+#pragma unroll
+          for (int e = 0; e < 16; ++e) cv[e] = (float)raw[e];
+        } else {
+#pragma unroll
+          for (int e = 0; e < 16; ++e) {
+            const int i = ib + 8 * (e >> 2) + (e & 3);
+            cv[e] = ((const float*)cin)[i < g.M ? (int64_t)i * g.ldcin + j : 0];
+          }
+        }
+      }
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int i0 = rowbase + mi * 32 + 8 * q + 4 * (lane >> 5);
@@ -100,7 +119,7 @@ SVDP_DEV void epilogue(const GemmArgs& g, int b, int rowbase, int colbase, int t
           if (i >= g.M) continue;
           float v = s_acc * acc[mi][ni][4 * q + r] * csj;
           if (cin) {
-            float c = ld_any(cin, (int64_t)i * g.ldcin + j, g.cin_bf16);
+            const float c = cv[4 * q + r];
             v += s_in * c * csij;
             d2 += (v - c) * (v - c);
           }
@@ -149,7 +168,7 @@ SVDP_DEV void epilogue(const GemmArgs& g, int b, int rowbase, int colbase, int t
 // ------------------------------------------------------------------ FP32
 
 template <int BM, int BN, bool TA, bool TB, bool VEC>
-__global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs g, int tiles_m, int tiles_n,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_gemm_f32(GemmArgs g, int tiles_m, int tiles_n,
                                                   int ntiles, int remap) {
   constexpr int BK = 16;
   constexpr int WM = BM / 2, WN = BN / 2;
