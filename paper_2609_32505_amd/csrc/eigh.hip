@@ -128,6 +128,16 @@ SVDP_DEV void rotation_fast(float app, float aqq, float apq, float& c, float& s)
   c = __builtin_amdgcn_rsqf(1.f + t * t);
   s = t * c;
 }
+// rotation_fast without branches: both cases of tau computed, one selected
+// (the same results wherever rotation_fast is defined)
+SVDP_DEV void rotation_sel(float app, float aqq, float apq, float& c, float& s) {
+  const float tau = (aqq - app) * __builtin_amdgcn_rcpf(2.f * apq);
+  const float tl = 0.5f * __builtin_amdgcn_rcpf(tau);
+  const float tn = copysignf(__builtin_amdgcn_rcpf(fabsf(tau) + __builtin_amdgcn_sqrtf(1.f + tau * tau)), tau);
+  const float t = fabsf(tau) > 1e10f ? tl : tn;
+  c = __builtin_amdgcn_rsqf(1.f + t * t);
+  s = t * c;
+}
 SVDP_DEV void rotation_fast(double app, double aqq, double apq, double& c, double& s) {
   rotation(app, aqq, apq, c, s);
 }
@@ -264,15 +274,26 @@ SVDP_DEV void pair_solve(SolveLds<R>& L, int w, int lane, int t0, int inner_swee
         if (ud == u) { app = a[u]; aqq = d[u]; bd = bq[u]; cd = cq[u]; }
       const R apq = R(0.5) * (bd + cd);
       RotPair<R> r{R(1), R(0)};
-      if (apq != R(0) && isfinite((float)apq) && fmax(fmax(fabs(app), fabs(aqq)), fabs(apq)) > skip_abs) {
+      const bool rot =
+          apq != R(0) && isfinite((float)apq) && fmax(fmax(fabs(app), fabs(aqq)), fabs(apq)) > skip_abs;
+      // |apq| / sqrt(|app aqq|), a convergence statistic (no IEEE rounding needed)
+      const float den2 = fabsf((float)app * (float)aqq);
+      const float rel = den2 > 0.f ? fabsf((float)apq) * __builtin_amdgcn_rsqf(den2) : 1e30f;
+      if constexpr (sizeof(R) == 4) {
+        // straight-line code on the round's critical path: the rotation is
+        // computed whatever the tests say and selected
+        float c, sn;
+        rotation_sel(app, aqq, apq, c, sn);
+        r.c = rot ? c : 1.f;
+        r.s = rot ? sn : 0.f;
+        any |= rot ? 1 : 0;
+        vsum += rot ? apq * apq : 0.f;
+        mrel = rot && fabsf(apq) > floor_abs ? fmaxf(mrel, rel) : mrel;
+      } else if (rot) {
         rotation_fast(app, aqq, apq, r.c, r.s);
         any = 1;
         vsum += (float)apq * (float)apq;
-        if (fabs(apq) > floor_abs) {
-          // |apq| / sqrt(|app aqq|), a convergence statistic (no IEEE rounding needed)
-          const float den2 = fabsf((float)app * (float)aqq);
-          mrel = fmaxf(mrel, den2 > 0.f ? fabsf((float)apq) * __builtin_amdgcn_rsqf(den2) : 1e30f);
-        }
+        if (fabs(apq) > floor_abs) mrel = fmaxf(mrel, rel);
       }
       cs[kx] = r;
     }
@@ -416,8 +437,10 @@ __global__ __launch_bounds__(128) void k_jac_solve(EighWs e, EighPhase ph, int i
     const int r = qd >> 2, c = (qd & 3) * 4;
 #pragma unroll
     for (int w2 = 0; w2 < 4; ++w2) {
-      if (tr) L.X[k1 * 16 + c + w2][k2 * 16 + r] = (R)hv[u][w2];
-      else L.X[k1 * 16 + r][k2 * 16 + c + w2] = (R)hv[u][w2];
+      // a tile below the diagonal is stored transposed (addresses selected,
+      // not branched on)
+      const int row = k1 * 16 + (tr ? c + w2 : r), col = k2 * 16 + (tr ? r : c + w2);
+      L.X[row][col] = (R)hv[u][w2];
     }
   }
   __syncthreads();
