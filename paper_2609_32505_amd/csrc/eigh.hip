@@ -270,8 +270,13 @@ SVDP_DEV void pair_solve(SolveLds<R>& L, int w, int lane, int t0, int inner_swee
     if (rlane) {
       R app = a[0], aqq = d[0], bd = bq[0], cd = cq[0];
 #pragma unroll
-      for (int u = 1; u < 4; ++u)
-        if (ud == u) { app = a[u]; aqq = d[u]; bd = bq[u]; cd = cq[u]; }
+      for (int u = 1; u < 4; ++u) {
+        const bool sel = ud == u;  // selects, not a branch per block
+        app = sel ? a[u] : app;
+        aqq = sel ? d[u] : aqq;
+        bd = sel ? bq[u] : bd;
+        cd = sel ? cq[u] : cd;
+      }
       const R apq = R(0.5) * (bd + cd);
       RotPair<R> r{R(1), R(0)};
       const bool rot =
