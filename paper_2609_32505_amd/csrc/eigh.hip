@@ -120,16 +120,8 @@ SVDP_DEV int gpos(int w, int a) {
   return a < 16 ? lo + a : hi + (a - 16);
 }
 
-SVDP_DEV void rotation_fast(float app, float aqq, float apq, float& c, float& s) {
-  const float tau = (aqq - app) * __builtin_amdgcn_rcpf(2.f * apq);
-  float t;
-  if (fabsf(tau) > 1e10f) t = 0.5f * __builtin_amdgcn_rcpf(tau);
-  else t = copysignf(__builtin_amdgcn_rcpf(fabsf(tau) + __builtin_amdgcn_sqrtf(1.f + tau * tau)), tau);
-  c = __builtin_amdgcn_rsqf(1.f + t * t);
-  s = t * c;
-}
-// rotation_fast without branches: both cases of tau computed, one selected
-// (the same results wherever rotation_fast is defined)
+// The FP32 rotation with hardware rcp/sqrt/rsq and no branches: both cases
+// of tau are computed and one is selected
 SVDP_DEV void rotation_sel(float app, float aqq, float apq, float& c, float& s) {
   const float tau = (aqq - app) * __builtin_amdgcn_rcpf(2.f * apq);
   const float tl = 0.5f * __builtin_amdgcn_rcpf(tau);

@@ -41,9 +41,6 @@ SVDP_DEV void sym_tile(int t, int T, int& tm, int& tn) {
   tn = r + t;
 }
 
-template <typename T>
-SVDP_DEV float ld_elem(const void* p, int64_t i) { return (float)((const T*)p)[i]; }
-
 // Profiling: the tile's algorithmic flops, 2 r c K (r x c the tile inside the
 // output), half of it on the diagonal of a symmetric output (its triangle)
 SVDP_DEV void count_tile(const GemmArgs& g, int m0, int n0, int BM, int BN, int tm, int tn) {
