@@ -768,14 +768,21 @@ __global__ __launch_bounds__(512) void k_jac_vsweep(EighWs e) {
   load_slice(0, 0, cur);
   for (int p = 0; p < NPH; ++p) {
     const EighPhase ph = eigh_phase(p);
+    // the sets of a phase rotate disjoint column groups: all of them are
+    // computed from the slab before one barrier, then written before another
+    f16v acc[NSET][RB];
+    int gsel[NSET];  // member block of the output column 32 ch + ic, per set
+#pragma unroll
     for (int set = 0; set < NSET; ++set) {
       if (set + 1 < NSET) load_slice(p, set + 1, nxt);
       else if (p + 1 < NPH) load_slice(p + 1, 0, nxt);
-      f16v acc[RB];
 #pragma unroll
-      for (int rb = 0; rb < RB; ++rb) acc[rb] = zero16();
+      for (int rb = 0; rb < RB; ++rb) acc[set][rb] = zero16();
       int gm[4];
       group_members(ph, set * GPS + (w >> 1), gm);
+      // selected, not indexed: gm stays in registers
+      const int mb = 2 * ch + (ic >> 4);
+      gsel[set] = mb == 0 ? gm[0] : (mb == 1 ? gm[1] : (mb == 2 ? gm[2] : gm[3]));
       if (busy) {
         // contraction index s2 + 32 kh lies in member block 2 kh + s2 / 16
         const int blk0 = kh ? gm[2] : gm[0], blk1 = kh ? gm[3] : gm[1];
@@ -788,28 +795,27 @@ __global__ __launch_bounds__(512) void k_jac_vsweep(EighWs e) {
 #pragma unroll
           for (int u = 0; u < 4; ++u)
 #pragma unroll
-            for (int rb = 0; rb < RB; ++rb) acc[rb] = mfma(a[rb][u], cur[4 * j + u], acc[rb]);
+            for (int rb = 0; rb < RB; ++rb) acc[set][rb] = mfma(a[rb][u], cur[4 * j + u], acc[set][rb]);
         }
       }
-      __syncthreads();
-      if (busy) {
-        // member block of the output column 32 ch + ic (selected, not indexed:
-        // gm stays in registers)
-        const int mb = 2 * ch + (ic >> 4);
-        const int gsel = mb == 0 ? gm[0] : (mb == 1 ? gm[1] : (mb == 2 ? gm[2] : gm[3]));
-        const int col = 16 * gsel + (ic & 15);
+#pragma unroll
+      for (int k = 0; k < 32; ++k) cur[k] = nxt[k];
+    }
+    __syncthreads();
+    if (busy) {
+#pragma unroll
+      for (int set = 0; set < NSET; ++set) {
+        const int col = 16 * gsel[set] + (ic & 15);
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
           for (int g4 = 0; g4 < 4; ++g4)
 #pragma unroll
             for (int r4 = 0; r4 < 4; ++r4)
-              Vs[(32 * rb + 8 * g4 + 4 * kh + r4) * PITCH + col] = acc[rb][4 * g4 + r4];
+              Vs[(32 * rb + 8 * g4 + 4 * kh + r4) * PITCH + col] = acc[set][rb][4 * g4 + r4];
       }
-      __syncthreads();
-#pragma unroll
-      for (int k = 0; k < 32; ++k) cur[k] = nxt[k];
     }
+    __syncthreads();
   }
   for (int idx = t; idx < R * NP / 4; idx += 512) {
     const int r = idx / (NP / 4), c = (idx - r * (NP / 4)) * 4;
