@@ -206,6 +206,7 @@ svdp_status svdp_set_model(svdp_handle* h, const float* host_model);
 #define SVDP_OP_EIGH 4
 #define SVDP_OP_FEATURES 5
 #define SVDP_OP_EIGH_BWD 6
+#define SVDP_OP_EIGH_DC 7
 svdp_status svdp_workspace_size(const svdp_params* p, int32_t op, size_t* bytes);
 
 const char* svdp_status_string(svdp_status s);
@@ -301,6 +302,31 @@ svdp_status svdp_eigh(svdp_handle* h, const svdp_params* p,
                       float* lam, int64_t slam,
                       float* V, int64_t ldv, int64_t sV,
                       svdp_info* info, void* ws, size_t ws_bytes, void* stream);
+
+/* Symmetric eigendecomposition by one level of polar-based spectral divide
+ * and conquer (the stable QDWH-eig-type method the paper's related work cites
+ * for relieving the EVD bottleneck at large n), with the same results as
+ * svdp_eigh: lam descending, V n x n.  Per matrix, in turn:
+ *   sigma = trace(H) / n; W = polar(H - sigma I) = sign(H - sigma I) by
+ *   conservative FP32 CANS (the same iteration as Algorithm 1); P = (I + W)/2
+ *   projects onto the eigenvectors above sigma, of rank k = (n + trace W)/2;
+ *   Q = [Q1 Q2] is the blocked QR of [P X1, (I - P) X2], first with X = Om,
+ *   a seeded pseudo-random matrix, then once more with X = Q (one step of
+ *   subspace iteration); T = Q^T H Q; the Jacobi eigensolver of svdp_eigh
+ *   runs on T[:k, :k] and T[k:, k:], and V = [Q1 V1, Q2 V2].
+ * The dropped coupling T[:k, k:] is held to 10 tol |T|_F (tol: the CANS stop
+ * test); a matrix that does not split (k = 0 or n, an unconverged polar
+ * iteration, |W|_F^2 off n by more than 1/2, or a larger coupling) runs
+ * svdp_eigh's solver on H itself and gets SVDP_FLAG_FALLBACK_USED.  Two host
+ * reads per matrix (k and the coupling).  Uses p->batch, p->n (m ignored), the CANS settings (delta,
+ * tol, max_iters, pre_iters) and the eigensolver settings of svdp_eigh;
+ * workspace op SVDP_OP_EIGH_DC (one matrix's worth, reused across the
+ * batch).  info: sweeps (the larger of the two halves) and flags. */
+svdp_status svdp_eigh_dc(svdp_handle* h, const svdp_params* p,
+                         const float* H, int64_t ldh, int64_t sH,
+                         float* lam, int64_t slam,
+                         float* V, int64_t ldv, int64_t sV,
+                         svdp_info* info, void* ws, size_t ws_bytes, void* stream);
 
 /* Backward of the symmetric eigendecomposition: the EVD pseudo-gradient
  * (theorem on the EVD backward, Section 4.2) with the regularised K of the

@@ -28,7 +28,7 @@ FLAG_NEG_EIGENVALUE = 4
 FLAG_RANK_DEFICIENT = 8
 FLAG_NONFINITE = 16
 FLAG_EIGH_NOT_CONVERGED = 32
-OP_SVD_FWD, OP_SVD_BWD, OP_POLAR_FWD, OP_POLAR_BWD, OP_EIGH, OP_FEATURES, OP_EIGH_BWD = range(7)
+OP_SVD_FWD, OP_SVD_BWD, OP_POLAR_FWD, OP_POLAR_BWD, OP_EIGH, OP_FEATURES, OP_EIGH_BWD, OP_EIGH_DC = range(8)
 MLP_PARAMS = 4866
 MODEL_FLOATS = MLP_PARAMS + 16
 
@@ -79,6 +79,8 @@ SIGNATURES = {
                           c_vp, c_i64, c_i64, c_vp, c_sz, c_vp]),
     "svdp_eigh": (c_i32, [c_vp, ctypes.POINTER(Params), c_vp, c_i64, c_i64, c_vp, c_i64, c_vp,
                           c_i64, c_i64, c_vp, c_vp, c_sz, c_vp]),
+    "svdp_eigh_dc": (c_i32, [c_vp, ctypes.POINTER(Params), c_vp, c_i64, c_i64, c_vp, c_i64, c_vp,
+                             c_i64, c_i64, c_vp, c_vp, c_sz, c_vp]),
     "svdp_eigh_bwd": (c_i32, [c_vp, ctypes.POINTER(Params), c_vp, c_i64, c_vp, c_i64, c_i64, c_vp, c_i64,
                               c_vp, c_i64, c_i64, c_vp, c_i64, c_i64, c_vp, c_sz, c_vp]),
     "svdp_bound_features": (c_i32, [c_vp, ctypes.POINTER(Params), c_vp, c_i64, c_i64, c_vp, c_vp,

@@ -204,6 +204,24 @@ def eigh(H, p=None, handle=None, **kw):
     return lam, V, info
 
 
+def eigh_dc(H, p=None, handle=None, **kw):
+    """lam (descending), V, info of symmetric H = V diag(lam) V^T by one level
+    of polar-based spectral divide and conquer (svdp_eigh_dc), one matrix at
+    a time."""
+    H = _batched(_req(H, "H"))
+    b, n, _ = H.shape
+    h = handle or default_handle()
+    p = _prep_params(p, kw, b, n, n)
+    lam = torch.empty((b, n), device=H.device)
+    V = torch.empty((b, n, n), device=H.device)
+    info = _info_tensor(b, H.device)
+    ws = _workspace(p, _lib.OP_EIGH_DC, H.device)
+    check(load().svdp_eigh_dc(h.ptr, ctypes.byref(p), H.data_ptr(), n, n * n, lam.data_ptr(), n,
+                              V.data_ptr(), n, n * n, info.data_ptr(), ws.data_ptr(), ws.numel(),
+                              _stream()), "svdp_eigh_dc")
+    return lam, V, info
+
+
 def eigh_bwd(lam, V, dlam=None, dV=None, p=None, handle=None, **kw):
     """dH of the symmetric EVD H = V diag(lam) V^T (the EVD pseudo-gradient
     theorem, regularised K with eps_K)."""

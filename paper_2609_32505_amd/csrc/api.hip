@@ -913,6 +913,173 @@ svdp_status svd_core(Ctx& c, float* U, int64_t ldu, int64_t sU, float* S, int64_
   return SVDP_OK;
 }
 
+// ---------------------------------------------------------------- spectral divide and conquer
+
+// The polar step of the split: one n x n matrix, conservative FP32 CANS with
+// the caller's CANS settings.
+svdp_params dc_polar_params(const svdp_params* p) {
+  svdp_params q = *p;
+  q.batch = 1;
+  q.m = p->n;
+  q.bound = SVDP_BOUND_CONSERVATIVE;
+  q.precision = SVDP_PREC_FP32;
+  q.poly = SVDP_POLY_CANS3;
+  q.probe = nullptr;
+  q.user_bounds = nullptr;
+  q.tall_qr = 0;
+  return q;
+}
+
+struct DcWs {
+  void* polar;        // the polar step's forward workspace
+  float *A, *Om, *Q, *HQ, *T, *Vd, *cs, *sigma, *qrc, *qrg, *qrr;
+  double *part, *cpl;
+  int *k, *qmask, *sw, *fl, *sweeps, *flags;
+  void* eigh;         // eigensolver workspace for one n x n matrix
+};
+
+DcWs carve_dc(void* base, const svdp_params* p, size_t* total) {
+  svdp_params q = dc_polar_params(p);
+  size_t fw = 0;
+  carve_fwd(nullptr, &q, &fw);
+  Carver c(base);
+  DcWs w;
+  const size_t n = p->n, nn = n * n;
+  w.polar = c.take_bytes(fw);
+  w.A = c.take<float>(nn);
+  w.Om = c.take<float>(nn);
+  w.Q = c.take<float>(nn);
+  w.HQ = c.take<float>(nn);
+  w.T = c.take<float>(nn);
+  w.Vd = c.take<float>(nn);
+  w.cs = c.take<float>(n);
+  w.sigma = c.take<float>(1);
+  w.qrc = c.take<float>(n * kQrBlock);
+  w.qrg = c.take<float>(kQrBlock * kQrBlock);
+  w.qrr = c.take<float>(kQrBlock * kQrBlock);
+  w.part = c.take<double>(2 * n);
+  w.cpl = c.take<double>(2);
+  w.k = c.take<int>(1);
+  w.qmask = c.take<int>(1);
+  w.sw = c.take<int>(2);
+  w.fl = c.take<int>(2);
+  w.sweeps = c.take<int>(p->batch);
+  w.flags = c.take<int>(p->batch);
+  w.eigh = c.take_bytes(eigh_ws_bytes(1, n, p->max_sweeps));
+  if (total) *total = c.off;
+  return w;
+}
+
+svdp_status read_doubles(svdp_handle* h, hipStream_t st, const double* dev, int count, double* out) {
+  HIPCHK(hipMemcpyAsync(h->host_word, dev, count * sizeof(double), hipMemcpyDeviceToHost, st), "read copy");
+  HIPCHK(hipStreamSynchronize(st), "read sync");
+  g_host_syncs.fetch_add(1);
+  std::memcpy(out, h->host_word, count * sizeof(double));
+  return SVDP_OK;
+}
+
+// One matrix by one level of polar-based spectral divide and conquer: the
+// sign of H - sigma I (sigma = trace(H) / n) is the polar factor W of that
+// shifted matrix; P = (I + W) / 2 projects onto the eigenvectors with
+// eigenvalues above sigma and has rank k = (n + trace W) / 2.  An orthonormal
+// basis Q = [Q1 Q2] of range(P) and its complement comes from the blocked QR
+// of [P Om1, (I - P) Om2] (Om random); T = Q^T H Q is then block diagonal up
+// to the coupling T[:k, k:], which is checked against 10 tol |T|_F.  Each
+// diagonal block goes to the Jacobi eigensolver, and V = Q diag(V1, V2).  A
+// matrix that does not split (k = 0 or n, the polar iteration unconverged,
+// or the coupling too large) runs the Jacobi eigensolver on H itself and is
+// flagged FALLBACK_USED.
+svdp_status eigh_dc_one(svdp_handle* h, const svdp_params* p, const DcWs& w, const float* H, int64_t ldh,
+                        float* lam, float* V, int64_t ldv, int* sweeps, int* flags, int b, hipStream_t st) {
+  const int n = (int)p->n;
+  const int64_t nn = (int64_t)n * n;
+  const EighOpts eo = eigh_opts(p);
+  svdp_params q = dc_polar_params(p);
+  HIPCHK(dc_shift_launch(H, ldh, w.A, n, w.sigma, st), "dc shift");
+  Ctx c{h, &q, carve_fwd(w.polar, &q, nullptr), st, 1, n, n, w.A, n, nn};
+  svdp_status s = polar_core(c);
+  if (s) return s;
+  HIPCHK(dc_coupling_launch(c.w.X0, c.w.X1, c.w.where, n, nullptr, w.part, w.cpl, st), "dc |W|_F");
+  HIPCHK(dc_rank_launch(c.w.X0, c.w.X1, c.w.where, w.cpl, c.w.flags, n, w.k, st), "dc rank");
+  int k = 0;
+  if ((s = read_counter(c, w.k, &k))) return s;
+  bool split = k > 0 && k < n;
+  float* Q = w.Q;
+  if (split) {
+    // Y = [P X1, (I - P) X2] = (X + W X diag(cs)) / 2, cs = +1 for the first k
+    // columns, and Q = orth(Y): first with X = Om (seeded random), then once
+    // more with X = Q (one step of subspace iteration: the first Y can be
+    // badly conditioned and keeps W's error in its range; the second is
+    // nearly orthonormal and squares that error).  orth is block
+    // Gram-Schmidt with CholeskyQR blocks, in place.
+    HIPCHK(dc_random_launch(w.Om, nn, 0x5EED0000u + (uint32_t)b, st), "dc random");
+    HIPCHK(dc_signs_launch(w.cs, n, w.k, st), "dc signs");
+    FwdWs wq = c.w;
+    wq.qrc = w.qrc; wq.qrg = w.qrg; wq.qrr = w.qrr;
+    Ctx cq{h, &q, wq, st, 1, n, n, nullptr, 0, 0};
+    const float* X = w.Om;
+    float* Y = w.Q;
+    for (int step = 0; step < 2; ++step) {
+      GemmArgs g = gemm_base(n, n, n, 1);
+      g.A = c.w.X0; g.A_alt = c.w.X1; g.a_sel = c.w.where; g.lda = n; g.sA = nn;
+      g.B = X; g.ldb = n; g.sB = nn;
+      g.C = Y; g.ldc = n; g.sC = nn;
+      g.Cin = X; g.ldcin = n; g.sCin = nn;
+      g.alpha = 0.5f; g.beta = 0.5f;
+      g.colscale = w.cs; g.cs_stride = n;
+      HIPCHK(gemm_launch(g, PREC_F32, 0, 0, st), "dc range");
+      HIPCHK(fill_i32(w.qmask, 1, 1, st), "dc qmask");
+      if ((s = qr_blocks(cq, Y, n, nn, w.qmask, 0))) return s;
+      X = Y;
+      Y = w.Om;
+    }
+    Q = w.Om;
+    // T = Q^T (H Q) and its coupling block
+    GemmArgs g1 = gemm_base(n, n, n, 1);
+    g1.A = H; g1.lda = ldh; g1.sA = nn;
+    g1.B = Q; g1.ldb = n; g1.sB = nn;
+    g1.C = w.HQ; g1.ldc = n; g1.sC = nn;
+    HIPCHK(gemm_launch(g1, PREC_F32, 0, 0, st), "dc H Q");
+    GemmArgs g2 = gemm_base(n, n, n, 1);
+    g2.A = Q; g2.lda = n; g2.sA = nn;
+    g2.B = w.HQ; g2.ldb = n; g2.sB = nn;
+    g2.C = w.T; g2.ldc = n; g2.sC = nn;
+    HIPCHK(gemm_launch(g2, PREC_F32, 1, 0, st), "dc Q^T H Q");
+    HIPCHK(dc_coupling_launch(w.T, nullptr, nullptr, n, w.k, w.part, w.cpl, st), "dc coupling");
+    double cpl[2];
+    if ((s = read_doubles(h, st, w.cpl, 2, cpl))) return s;
+    const double tol = 10.0 * p->tol;
+    split = std::isfinite(cpl[0]) && std::isfinite(cpl[1]) && cpl[0] <= tol * tol * cpl[1];
+  }
+  if (split) {
+    // the two diagonal blocks, eigenvalues descending: those above sigma first
+    HIPCHK(fill_i32(w.sw, 0, 2, st), "dc sweeps");
+    HIPCHK(fill_i32(w.fl, 0, 2, st), "dc flags");
+    EighWs e1 = eigh_ws_carve(w.eigh, 1, k, p->max_sweeps);
+    HIPCHK(eigh_run(e1, w.T, n, nn, 0, eo, lam, k, w.Vd, n, nn, w.sw, w.fl, nullptr, &h->aux, st), "dc eigh 1");
+    EighWs e2 = eigh_ws_carve(w.eigh, 1, n - k, p->max_sweeps);
+    HIPCHK(eigh_run(e2, w.T + (int64_t)k * n + k, n, nn, 0, eo, lam + k, n - k, w.Vd + (int64_t)k * n + k, n,
+                    nn, w.sw + 1, w.fl + 1, nullptr, &h->aux, st), "dc eigh 2");
+    HIPCHK(dc_info_launch(w.sw, w.fl, sweeps, flags, st), "dc info");
+    // V = [Q1 V1, Q2 V2]
+    GemmArgs v1 = gemm_base(n, k, k, 1);
+    v1.A = Q; v1.lda = n; v1.sA = nn;
+    v1.B = w.Vd; v1.ldb = n; v1.sB = nn;
+    v1.C = V; v1.ldc = ldv; v1.sC = nn;
+    HIPCHK(gemm_launch(v1, PREC_F32, 0, 0, st), "dc V1");
+    GemmArgs v2 = gemm_base(n, n - k, n - k, 1);
+    v2.A = Q + k; v2.lda = n; v2.sA = nn;
+    v2.B = w.Vd + (int64_t)k * n + k; v2.ldb = n; v2.sB = nn;
+    v2.C = V + k; v2.ldc = ldv; v2.sC = nn;
+    HIPCHK(gemm_launch(v2, PREC_F32, 0, 0, st), "dc V2");
+    return SVDP_OK;
+  }
+  EighWs e = eigh_ws_carve(w.eigh, 1, n, p->max_sweeps);
+  HIPCHK(eigh_run(e, H, ldh, nn, 0, eo, lam, n, V, ldv, nn, sweeps, flags, nullptr, &h->aux, st), "dc eigh");
+  HIPCHK(or_flags_launch(1, flags, SVDP_FLAG_FALLBACK_USED, nullptr, st), "dc fallback flag");
+  return SVDP_OK;
+}
+
 // QR preprocessing of tall matrices (the paper's rectangular experiments):
 // Q, an orthonormal basis of A's columns (block Gram-Schmidt with CholeskyQR
 // blocks, dependent columns dropped as zero columns), B = Q^T A (n x n, with
@@ -1135,6 +1302,7 @@ svdp_status svdp_workspace_size(const svdp_params* p, int32_t op, size_t* bytes)
       break;
     }
     case SVDP_OP_POLAR_BWD: total = bwd_bytes(p, 1); break;
+    case SVDP_OP_EIGH_DC: carve_dc(nullptr, p, &total); break;
     case SVDP_OP_EIGH: {
       Carver c(nullptr);
       c.take<int>(p->batch);
@@ -1555,6 +1723,33 @@ svdp_status svdp_eigh(svdp_handle* h, const svdp_params* p, const float* H, int6
   HIPCHK(eigh_run(e, H, ldh, sH, 0, eigh_opts(p), lam, slam, V, ldv, sV, sweeps, flags, nullptr,
                   &h->aux, st), "eigh");
   if (info) HIPCHK(info_pack_launch(B, nullptr, sweeps, flags, nullptr, info, nullptr, st), "info");
+  return SVDP_OK;
+}
+
+svdp_status svdp_eigh_dc(svdp_handle* h, const svdp_params* p, const float* H, int64_t ldh, int64_t sH, float* lam,
+                         int64_t slam, float* V, int64_t ldv, int64_t sV, svdp_info* info, void* ws,
+                         size_t ws_bytes, void* stream) {
+  REQ(h);
+  svdp_status s = check_common(p);
+  if (s) return s;
+  if (p->batch == 0) return SVDP_OK;
+  REQ(H); REQ(lam); REQ(V);
+  const int B = (int)p->batch, n = (int)p->n;
+  LDCHK(ldh, n, B > 1 ? sH : 0, n);
+  LDCHK(ldv, n, B > 1 ? sV : 0, n);
+  if (B > 1 && slam < n) return fail(SVDP_ERR_INVALID_ARG, "slam < n");
+  size_t need = 0;
+  svdp_workspace_size(p, SVDP_OP_EIGH_DC, &need);
+  if (!ws || ws_bytes < need) return fail(SVDP_ERR_WORKSPACE, "workspace too small");
+  hipStream_t st = (hipStream_t)stream;
+  const DcWs w = carve_dc(ws, p, nullptr);
+  HIPCHK(fill_i32(w.flags, 0, B, st), "flags");
+  HIPCHK(fill_i32(w.sweeps, 0, B, st), "sweeps");
+  for (int b = 0; b < B; ++b)
+    if ((s = eigh_dc_one(h, p, w, H + b * sH, ldh, lam + b * slam, V + b * sV, ldv, w.sweeps + b, w.flags + b,
+                         b, st)))
+      return s;
+  if (info) HIPCHK(info_pack_launch(B, nullptr, w.sweeps, w.flags, nullptr, info, nullptr, st), "info");
   return SVDP_OK;
 }
 

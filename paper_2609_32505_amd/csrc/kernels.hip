@@ -1545,3 +1545,161 @@ hipError_t copy_masked_launch(const float* src, float* dst, int batch, int64_t p
                        per_matrix, mask);
   LAUNCH_CHECK();
 }
+
+// ---- spectral divide and conquer -------------------------------------------
+namespace {
+
+// fixed-order sum of one value per thread over a 1024-thread block
+SVDP_DEV double block_sum_1024(double v, double* red) {
+  const int t = threadIdx.x;
+  red[t] = v;
+  __syncthreads();
+  for (int s = 512; s > 0; s >>= 1) {
+    if (t < s) red[t] += red[t + s];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// sigma = trace(H) / n (one block)
+__global__ __launch_bounds__(1024) void k_dc_sigma(const float* H, int64_t ldh, int n, float* sigma) {
+  __shared__ double red[1024];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += 1024) s += H[(int64_t)i * ldh + i];
+  const double mu = block_sum_1024(s, red) / n;
+  if (threadIdx.x == 0) *sigma = (float)mu;
+}
+
+// A = H - sigma I, one row per block
+__global__ void k_dc_shift(const float* H, int64_t ldh, float* A, int n, const float* sigma) {
+  const int i = blockIdx.x;
+  const float mu = *sigma;
+  for (int j = threadIdx.x; j < n; j += blockDim.x)
+    A[(int64_t)i * n + j] = H[(int64_t)i * ldh + j] - (i == j ? mu : 0.f);
+}
+
+// k = round((n + trace W) / 2), the rank of the projector (I + W) / 2, W =
+// sel[0] ? X1 : X0.  k = 0 (no split) when the polar iteration did not
+// converge or met non-finite values (flags[0]), or when |W|_F^2 (wn2[1])
+// differs from n by more than 1/2: W is then not orthogonal, as for a shifted
+// matrix with a zero direction, whose polar factor loses that direction
+__global__ __launch_bounds__(1024) void k_dc_rank(const float* X0, const float* X1, const int* sel,
+                                                 const double* wn2, const int* flags, int n, int* k) {
+  __shared__ double red[1024];
+  const float* W = sel[0] ? X1 : X0;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += 1024) s += W[(int64_t)i * n + i];
+  const double tr = block_sum_1024(s, red);
+  if (threadIdx.x == 0) {
+    const long r = lrint(0.5 * (n + tr));
+    const bool bad = (flags[0] & (SVDP_FLAG_NOT_CONVERGED | SVDP_FLAG_NONFINITE)) != 0 || !isfinite(tr) ||
+                     !(fabs(wn2[1] - n) <= 0.5);
+    *k = bad ? 0 : (int)(r < 0 ? 0 : (r > n ? n : r));
+  }
+}
+
+// the two halves' sweep counts and flags -> the matrix's (max, or)
+__global__ void k_dc_info(const int* sw, const int* fl, int* sweeps, int* flags) {
+  if (threadIdx.x == 0) {
+    *sweeps = sw[0] > sw[1] ? sw[0] : sw[1];
+    *flags |= fl[0] | fl[1];
+  }
+}
+
+// seeded uniform values in [-1, 1): a 32-bit integer hash of (seed, index)
+// (the finaliser of MurmurHash3) mapped to 24-bit fractions
+__global__ void k_dc_random(float* out, int64_t count, uint32_t seed) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) {
+    uint32_t h = seed ^ (uint32_t)(i * 0x9E3779B9u) ^ (uint32_t)(i >> 32);
+    h ^= h >> 16; h *= 0x85EBCA6Bu; h ^= h >> 13; h *= 0xC2B2AE35u; h ^= h >> 16;
+    out[i] = (float)(h >> 8) * (1.f / 8388608.f) - 1.f;
+  }
+}
+
+// cs[j] = +1 for the first k columns, -1 after
+__global__ void k_dc_signs(float* cs, int n, const int* k) {
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) cs[j] = j < *k ? 1.f : -1.f;
+}
+
+// part[2 r], part[2 r + 1] = row r's sums of T[r, j]^2 over j >= k (rows
+// r < k) and over all j (T = sel && sel[0] ? T1 : T0, n x n row-major; no k:
+// k = 0), one row per block
+__global__ void k_dc_coupling_rows(const float* T0, const float* T1, const int* sel, int n, const int* k,
+                                   double* part) {
+  __shared__ double red[2][256];
+  const int r = blockIdx.x, kk = k ? *k : 0;
+  const float* T = sel && sel[0] ? T1 : T0;
+  double e = 0.0, a = 0.0;
+  for (int j = threadIdx.x; j < n; j += 256) {
+    const double v = T[(int64_t)r * n + j];
+    a += v * v;
+    if (r < kk && j >= kk) e += v * v;
+  }
+  red[0][threadIdx.x] = e;
+  red[1][threadIdx.x] = a;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + s];
+      red[1][threadIdx.x] += red[1][threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * r] = red[0][0];
+    part[2 * r + 1] = red[1][0];
+  }
+}
+
+// out[0] = |T[:k, k:]|_F^2, out[1] = |T|_F^2: the row sums added in row order
+__global__ __launch_bounds__(1024) void k_dc_coupling_sum(const double* part, int n, double* out) {
+  __shared__ double red[1024];
+  double e = 0.0, a = 0.0;
+  for (int r = threadIdx.x; r < n; r += 1024) {
+    e += part[2 * r];
+    a += part[2 * r + 1];
+  }
+  const double se = block_sum_1024(e, red);
+  const double sa = block_sum_1024(a, red);
+  if (threadIdx.x == 0) {
+    out[0] = se;
+    out[1] = sa;
+  }
+}
+
+}  // namespace
+
+hipError_t dc_shift_launch(const float* H, int64_t ldh, float* A, int n, float* sigma, hipStream_t st) {
+  hipLaunchKernelGGL(k_dc_sigma, dim3(1), dim3(1024), 0, st, H, ldh, n, sigma);
+  hipError_t e = hipGetLastError();
+  if (e) return e;
+  hipLaunchKernelGGL(k_dc_shift, dim3(n), dim3(256), 0, st, H, ldh, A, n, sigma);
+  LAUNCH_CHECK();
+}
+hipError_t dc_rank_launch(const float* X0, const float* X1, const int* sel, const double* wn2, const int* flags,
+                          int n, int* k, hipStream_t st) {
+  hipLaunchKernelGGL(k_dc_rank, dim3(1), dim3(1024), 0, st, X0, X1, sel, wn2, flags, n, k);
+  LAUNCH_CHECK();
+}
+hipError_t dc_info_launch(const int* sw, const int* fl, int* sweeps, int* flags, hipStream_t st) {
+  hipLaunchKernelGGL(k_dc_info, dim3(1), dim3(64), 0, st, sw, fl, sweeps, flags);
+  LAUNCH_CHECK();
+}
+hipError_t dc_random_launch(float* out, int64_t count, uint32_t seed, hipStream_t st) {
+  hipLaunchKernelGGL(k_dc_random, dim3(512), dim3(256), 0, st, out, count, seed);
+  LAUNCH_CHECK();
+}
+hipError_t dc_signs_launch(float* cs, int n, const int* k, hipStream_t st) {
+  hipLaunchKernelGGL(k_dc_signs, dim3(cdiv(n, 256)), dim3(256), 0, st, cs, n, k);
+  LAUNCH_CHECK();
+}
+hipError_t dc_coupling_launch(const float* T0, const float* T1, const int* sel, int n, const int* k, double* part,
+                              double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_dc_coupling_rows, dim3(n), dim3(256), 0, st, T0, T1, sel, n, k, part);
+  hipError_t e = hipGetLastError();
+  if (e) return e;
+  hipLaunchKernelGGL(k_dc_coupling_sum, dim3(1), dim3(1024), 0, st, part, n, out);
+  LAUNCH_CHECK();
+}

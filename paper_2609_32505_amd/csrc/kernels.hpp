@@ -149,3 +149,22 @@ hipError_t sched_iters_launch(int batch, const int* ksteps, int* iters, hipStrea
 // dst[b] = src[b] (per_matrix floats, a multiple of 4) where mask[b] != 0
 hipError_t copy_masked_launch(const float* src, float* dst, int batch, int64_t per_matrix, const int* mask,
                               hipStream_t st);
+
+// ---- spectral divide and conquer (svdp_eigh_dc), one matrix per call -------
+// *sigma = trace(H) / n, A = H - sigma I (A n x n row-major)
+hipError_t dc_shift_launch(const float* H, int64_t ldh, float* A, int n, float* sigma, hipStream_t st);
+// *k = round((n + trace W) / 2) clamped to [0, n], W = sel[0] ? X1 : X0 (n x n);
+// 0 when flags[0] reports an unconverged or non-finite polar iteration or
+// when |wn2[1] - n| > 1/2 (wn2[1] = |W|_F^2)
+hipError_t dc_rank_launch(const float* X0, const float* X1, const int* sel, const double* wn2, const int* flags,
+                          int n, int* k, hipStream_t st);
+// *sweeps = max(sw[0], sw[1]), *flags |= fl[0] | fl[1]
+hipError_t dc_info_launch(const int* sw, const int* fl, int* sweeps, int* flags, hipStream_t st);
+// out[i] uniform in [-1, 1), a hash of (seed, i)
+hipError_t dc_random_launch(float* out, int64_t count, uint32_t seed, hipStream_t st);
+// cs[j] = j < *k ? 1 : -1
+hipError_t dc_signs_launch(float* cs, int n, const int* k, hipStream_t st);
+// out[0] = |T[:k, k:]|_F^2, out[1] = |T|_F^2 with T = sel && sel[0] ? T1 : T0
+// (n x n; k null: k = 0; part: 2 n doubles of row sums)
+hipError_t dc_coupling_launch(const float* T0, const float* T1, const int* sel, int n, const int* k, double* part,
+                              double* out, hipStream_t st);

@@ -75,6 +75,12 @@ def test_workspace_size_and_shape_validation():
     assert _ws(L.default_params(1, 8, 8, eigh_off_tol=-1.0), 0)[0] == 1
     assert _ws(L.default_params(1, 8, 8, jacobi_fro_tol=-1.0), 0)[0] == 1
     assert _ws(L.default_params(0, 8, 8), L.OP_SVD_FWD)[0] == 0
+    # divide and conquer: one matrix's worth (polar step, six n x n buffers and
+    # the eigensolver's), independent of the batch
+    st3, nb3 = _ws(L.default_params(1, 1024, 1024), L.OP_EIGH_DC)
+    st4, nb4 = _ws(L.default_params(1, 1024, 1024), L.OP_EIGH)
+    assert st3 == 0 and st4 == 0 and nb3 > nb4 + 6 * 1024 * 1024 * 4
+    assert _ws(L.default_params(8, 1024, 1024), L.OP_EIGH_DC)[1] - nb3 < 1024
 
 
 def test_status_strings():
