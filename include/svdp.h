@@ -303,25 +303,36 @@ svdp_status svdp_eigh(svdp_handle* h, const svdp_params* p,
                       float* V, int64_t ldv, int64_t sV,
                       svdp_info* info, void* ws, size_t ws_bytes, void* stream);
 
-/* Symmetric eigendecomposition by one level of polar-based spectral divide
- * and conquer (the stable QDWH-eig-type method the paper's related work cites
- * for relieving the EVD bottleneck at large n), with the same results as
- * svdp_eigh: lam descending, V n x n.  Per matrix, in turn:
- *   sigma = trace(H) / n; W = polar(H - sigma I) = sign(H - sigma I) by
+/* Symmetric eigendecomposition by polar-based spectral divide and conquer
+ * (the stable QDWH-eig-type method the paper's related work cites for
+ * relieving the EVD bottleneck at large n), with the same results as
+ * svdp_eigh: lam descending, V n x n.  H is taken as its symmetric part.
+ * A split of a symmetric piece M (s x s):
+ *   sigma = trace(M) / s; W = polar(M - sigma I) = sign(M - sigma I) by
  *   conservative FP32 CANS (the same iteration as Algorithm 1); P = (I + W)/2
- *   projects onto the eigenvectors above sigma, of rank k = (n + trace W)/2;
- *   Q = [Q1 Q2] is the blocked QR of [P X1, (I - P) X2], first with X = Om,
- *   a seeded pseudo-random matrix, then once more with X = Q (one step of
- *   subspace iteration); T = Q^T H Q; the Jacobi eigensolver of svdp_eigh
- *   runs on T[:k, :k] and T[k:, k:], and V = [Q1 V1, Q2 V2].
- * The dropped coupling T[:k, k:] is held to 10 tol |T|_F (tol: the CANS stop
- * test); a matrix that does not split (k = 0 or n, an unconverged polar
- * iteration, |W|_F^2 off n by more than 1/2, or a larger coupling) runs
- * svdp_eigh's solver on H itself and gets SVDP_FLAG_FALLBACK_USED.  Two host
- * reads per matrix (k and the coupling).  Uses p->batch, p->n (m ignored), the CANS settings (delta,
- * tol, max_iters, pre_iters) and the eigensolver settings of svdp_eigh;
- * workspace op SVDP_OP_EIGH_DC (one matrix's worth, reused across the
- * batch).  info: sweeps (the larger of the two halves) and flags. */
+ *   projects onto the eigenvectors above sigma, of rank k = (s + trace W)/2;
+ *   Q = [Q1 Q2] spans P's range and its complement: the blocked QR of
+ *   [P Om1, (I - P) Om2] with Om a seeded pseudo-random matrix, then one
+ *   step of subspace iteration, [P Q1, (I - P) Q2] orthonormalised block by
+ *   block by Newton-Schulz; T = Q^T M Q (symmetrised), whose diagonal blocks
+ *   T[:k, :k] and T[k:, k:] are the two new pieces; V = [Q1 V1, Q2 V2] once
+ *   they are solved.  The dropped coupling T[:k, k:] is held to
+ *   10 tol |T|_F (tol: the CANS stop test).
+ * Each matrix is split once; pieces above 1024 are split again, to 4 levels
+ * (16 pieces at most).  Every piece is solved by svdp_eigh's solver shifted
+ * by its mean eigenvalue: those of at most 1024, zero-padded to the largest,
+ * as one batch; a larger one (at the depth limit, or one that does not
+ * split) alone.  A piece does not split when k = 0 or s, the polar
+ * iteration is unconverged, |W|_F^2 is off s by more than 1/2, a
+ * Newton-Schulz block stays off orthonormal, or the coupling is larger; when
+ * that happens to the first split, the matrix runs svdp_eigh's solver on H
+ * itself and gets SVDP_FLAG_FALLBACK_USED.  Two host reads per split (k,
+ * then the coupling and orthonormality checks).  Uses p->batch, p->n (m
+ * ignored), the CANS settings (delta, tol, max_iters, pre_iters) and the
+ * eigensolver settings of svdp_eigh; workspace op SVDP_OP_EIGH_DC (one
+ * matrix's worth, reused across the batch: about 32 n^2 floats at
+ * n = 4096, 27 n^2 at 8192).  info: sweeps (the largest over the pieces)
+ * and flags. */
 svdp_status svdp_eigh_dc(svdp_handle* h, const svdp_params* p,
                          const float* H, int64_t ldh, int64_t sH,
                          float* lam, int64_t slam,

@@ -930,12 +930,25 @@ svdp_params dc_polar_params(const svdp_params* p) {
   return q;
 }
 
+// Pieces of at most kDcLeafMax go to one batched Jacobi solve; larger ones
+// are split again, down to kDcDepth levels (so at most kDcLeaves pieces).
+constexpr int kDcLeafMax = 1024;
+constexpr int kDcDepth = 4;
+constexpr int kDcLeaves = 1 << kDcDepth;
+
 struct DcWs {
-  void* polar;        // the polar step's forward workspace
-  float *A, *Om, *Q, *HQ, *T, *Vd, *cs, *sigma, *qrc, *qrg, *qrr;
+  void* polar;              // the polar step's forward workspace (for n)
+  float *A, *Om, *HQ;       // n x n temporaries of one split
+  float *cs, *sigma, *mu, *qrc, *qrg, *qrr;  // mu: each leaf's shift
   double *part, *cpl;
-  int *k, *qmask, *sw, *fl, *sweeps, *flags;
-  void* eigh;         // eigensolver workspace for one n x n matrix
+  int *k, *qmask, *sw, *fl, *map, *sweeps, *flags;
+  float* pool;              // Q, T, W of every split piece (bump-allocated)
+  size_t pool_floats;
+  float *Hl, *Vl, *laml;    // the batched leaf solve: up to leaf_count zero-padded pieces
+  int leaf_n;               // their largest size, min(n, kDcLeafMax)
+  int leaf_count;           // 2 when n <= kDcLeafMax (only the first split happens), else kDcLeaves
+  void* eigh;               // eigensolver workspace for one n x n matrix
+  void* eigh_leaf;          // ... for kDcLeaves matrices of leaf_n
 };
 
 DcWs carve_dc(void* base, const svdp_params* p, size_t* total) {
@@ -945,27 +958,38 @@ DcWs carve_dc(void* base, const svdp_params* p, size_t* total) {
   Carver c(base);
   DcWs w;
   const size_t n = p->n, nn = n * n;
+  const size_t L = std::min<size_t>(n, kDcLeafMax);
   w.polar = c.take_bytes(fw);
   w.A = c.take<float>(nn);
   w.Om = c.take<float>(nn);
-  w.Q = c.take<float>(nn);
   w.HQ = c.take<float>(nn);
-  w.T = c.take<float>(nn);
-  w.Vd = c.take<float>(nn);
   w.cs = c.take<float>(n);
   w.sigma = c.take<float>(1);
+  w.mu = c.take<float>(kDcLeaves);
   w.qrc = c.take<float>(n * kQrBlock);
   w.qrg = c.take<float>(kQrBlock * kQrBlock);
   w.qrr = c.take<float>(kQrBlock * kQrBlock);
   w.part = c.take<double>(2 * n);
-  w.cpl = c.take<double>(2);
+  w.cpl = c.take<double>(6);
   w.k = c.take<int>(1);
   w.qmask = c.take<int>(1);
-  w.sw = c.take<int>(2);
-  w.fl = c.take<int>(2);
+  w.sw = c.take<int>(kDcLeaves);
+  w.fl = c.take<int>(kDcLeaves);
+  w.map = c.take<int>(L);
   w.sweeps = c.take<int>(p->batch);
   w.flags = c.take<int>(p->batch);
+  // the split pieces at one depth are disjoint, so their sizes s_i add up to
+  // at most n and their s_i^2 to at most n^2: 3 n^2 per level, plus alignment
+  w.pool_floats = 3 * nn * kDcDepth + 3 * 64 * kDcLeaves;
+  w.pool = c.take<float>(w.pool_floats);
+  w.leaf_n = (int)L;
+  w.leaf_count = n <= (size_t)kDcLeafMax ? 2 : kDcLeaves;
+  const size_t LC = w.leaf_count;
+  w.Hl = c.take<float>(LC * L * L);
+  w.Vl = c.take<float>(LC * L * L);
+  w.laml = c.take<float>(LC * L);
   w.eigh = c.take_bytes(eigh_ws_bytes(1, n, p->max_sweeps));
+  w.eigh_leaf = c.take_bytes(eigh_ws_bytes(LC, L, p->max_sweeps));
   if (total) *total = c.off;
   return w;
 }
@@ -978,105 +1002,248 @@ svdp_status read_doubles(svdp_handle* h, hipStream_t st, const double* dev, int 
   return SVDP_OK;
 }
 
-// One matrix by one level of polar-based spectral divide and conquer: the
-// sign of H - sigma I (sigma = trace(H) / n) is the polar factor W of that
-// shifted matrix; P = (I + W) / 2 projects onto the eigenvectors with
-// eigenvalues above sigma and has rank k = (n + trace W) / 2.  An orthonormal
-// basis Q = [Q1 Q2] of range(P) and its complement comes from the blocked QR
-// of [P Om1, (I - P) Om2] (Om random); T = Q^T H Q is then block diagonal up
-// to the coupling T[:k, k:], which is checked against 10 tol |T|_F.  Each
-// diagonal block goes to the Jacobi eigensolver, and V = Q diag(V1, V2).  A
-// matrix that does not split (k = 0 or n, the polar iteration unconverged,
-// or the coupling too large) runs the Jacobi eigensolver on H itself and is
-// flagged FALLBACK_USED.
+// One piece of the divide and conquer: the symmetric s x s input M (pitch
+// ldm), whose eigenvalues go to lam[off, off + s) and eigenvectors to V
+// (s x s, pitch ldv).  A split piece keeps Q (its basis), T = Q^T M Q and W
+// (the eigenvectors of T's two diagonal blocks, block-diagonal).
+struct DcPiece {
+  int off, s, k, depth;
+  const float* M;
+  int64_t ldm;
+  float* V;
+  int64_t ldv;
+  float *Q, *T, *W;
+  bool split;
+};
+
+// The split of one piece by the sign of M - sigma I (sigma = trace(M) / s,
+// M taken as its symmetric part (M + M^T) / 2), the polar factor W of that
+// shifted matrix: P = (I + W) / 2 projects onto the eigenvectors with
+// eigenvalues above sigma and has rank k = (s + trace W) / 2.  An
+// orthonormal basis Q = [Q1 Q2] of range(P) and its complement comes from
+// Y = [P X1, (I - P) X2] twice: first with X = Om (seeded random), Y made
+// orthonormal by the blocked QR; then once more with X = that basis (one
+// step of subspace iteration: the first Y can be badly conditioned and keeps
+// W's error in its range; the second is nearly orthonormal and squares that
+// error), whose first k columns and then the rest, projected twice against
+// them, are made orthonormal by three Newton-Schulz steps each (right
+// multiplications, so each block keeps its span).  Then T = Q^T M Q (made
+// exactly symmetric: the polar factor of a slightly non-symmetric piece
+// misplaces the directions near its sigma), block diagonal up to the
+// coupling T[:k, k:], which must stay below 10 tol |T|_F.  *ok = 0 (and Q, T
+// unused) when the piece does not split: k = 0 or s, the polar iteration
+// unconverged or non-finite, |W|_F^2 off s by more than 1/2, a Newton-Schulz
+// block whose last Gram matrix is off I by more than 1e-3 (Frobenius), or
+// too large a coupling.
+svdp_status dc_split(svdp_handle* h, const svdp_params* p, const DcWs& w, DcPiece& pc, uint32_t seed,
+                     hipStream_t st, bool* ok) {
+  *ok = false;
+  const int s = pc.s;
+  const int64_t ss = (int64_t)s * s;
+  svdp_params q = dc_polar_params(p);
+  q.m = q.n = s;
+  HIPCHK(dc_shift_launch(pc.M, pc.ldm, w.A, s, s, w.sigma, st), "dc shift");
+  Ctx c{h, &q, carve_fwd(w.polar, &q, nullptr), st, 1, s, s, w.A, s, ss};
+  svdp_status r = polar_core(c);
+  if (r) return r;
+  HIPCHK(dc_coupling_launch(c.w.X0, c.w.X1, c.w.where, s, nullptr, w.part, w.cpl, st), "dc |W|_F");
+  HIPCHK(dc_rank_launch(c.w.X0, c.w.X1, c.w.where, w.cpl, c.w.flags, s, w.k, st), "dc rank");
+  int k = 0;
+  if ((r = read_counter(c, w.k, &k))) return r;
+  if (k <= 0 || k >= s) return SVDP_OK;
+  HIPCHK(dc_random_launch(w.Om, ss, seed, st), "dc random");
+  HIPCHK(dc_signs_launch(w.cs, s, w.k, st), "dc signs");
+  // Y = (X + W X diag(cs)) / 2, cs = +1 for the first k columns
+  auto range = [&](const float* X, float* Y) {
+    GemmArgs g = gemm_base(s, s, s, 1);
+    g.A = c.w.X0; g.A_alt = c.w.X1; g.a_sel = c.w.where; g.lda = s; g.sA = ss;
+    g.B = X; g.ldb = s; g.sB = ss;
+    g.C = Y; g.ldc = s; g.sC = ss;
+    g.Cin = X; g.ldcin = s; g.sCin = ss;
+    g.alpha = 0.5f; g.beta = 0.5f;
+    g.colscale = w.cs; g.cs_stride = s;
+    return gemm_launch(g, PREC_F32, 0, 0, st);
+  };
+  HIPCHK(range(w.Om, w.HQ), "dc range 1");
+  FwdWs wq = c.w;
+  wq.qrc = w.qrc; wq.qrg = w.qrg; wq.qrr = w.qrr;
+  Ctx cq{h, &q, wq, st, 1, s, s, nullptr, 0, 0};
+  HIPCHK(fill_i32(w.qmask, 1, 1, st), "dc qmask");
+  if ((r = qr_blocks(cq, w.HQ, s, ss, w.qmask, 0))) return r;
+  HIPCHK(range(w.HQ, w.Om), "dc range 2");
+  // Newton-Schulz on the s x cols block at column c0: Z = Y (3 I - Y^T Y) / 2,
+  // from Om to Q, back and to Q again; |G - I|_F^2 of the last G to dev
+  auto newton_schulz = [&](int c0, int cols, double* dev) -> hipError_t {
+    float* src = w.Om + c0;
+    float* dst = pc.Q + c0;
+    for (int it = 0; it < 3; ++it) {
+      GemmArgs g = gemm_base(cols, cols, s, 1);  // G = Y^T Y
+      g.A = src; g.lda = s; g.sA = ss;
+      g.B = src; g.ldb = s; g.sB = ss;
+      g.C = w.A; g.ldc = cols; g.sC = ss;
+      g.sym = 1;
+      hipError_t e = gemm_launch(g, PREC_F32, 1, 0, st);
+      if (e) return e;
+      if (it == 2 && (e = dc_dev_launch(w.A, cols, w.part, dev, st))) return e;
+      GemmArgs u = gemm_base(s, cols, cols, 1);  // Z = 1.5 Y - 0.5 Y G
+      u.A = src; u.lda = s; u.sA = ss;
+      u.B = w.A; u.ldb = cols; u.sB = ss;
+      u.C = dst; u.ldc = s; u.sC = ss;
+      u.Cin = src; u.ldcin = s; u.sCin = ss;
+      u.alpha = -0.5f; u.beta = 1.5f;
+      if ((e = gemm_launch(u, PREC_F32, 0, 0, st))) return e;
+      std::swap(src, dst);
+    }
+    return hipSuccess;
+  };
+  HIPCHK(newton_schulz(0, k, w.cpl + 2), "dc orth Q1");
+  for (int pass = 0; pass < 2; ++pass) {  // Y2 <- Y2 - Q1 (Q1^T Y2)
+    GemmArgs g = gemm_base(k, s - k, s, 1);
+    g.A = pc.Q; g.lda = s; g.sA = ss;
+    g.B = w.Om + k; g.ldb = s; g.sB = ss;
+    g.C = w.A; g.ldc = s - k; g.sC = ss;
+    HIPCHK(gemm_launch(g, PREC_F32, 1, 0, st), "dc project");
+    GemmArgs u = gemm_base(s, s - k, k, 1);
+    u.A = pc.Q; u.lda = s; u.sA = ss;
+    u.B = w.A; u.ldb = s - k; u.sB = ss;
+    u.C = w.Om + k; u.ldc = s; u.sC = ss;
+    u.Cin = w.Om + k; u.ldcin = s; u.sCin = ss;
+    u.alpha = -1.f; u.beta = 1.f;
+    HIPCHK(gemm_launch(u, PREC_F32, 0, 0, st), "dc project update");
+  }
+  HIPCHK(newton_schulz(k, s - k, w.cpl + 4), "dc orth Q2");
+  // T = Q^T (M Q) and its coupling block
+  GemmArgs g1 = gemm_base(s, s, s, 1);
+  g1.A = pc.M; g1.lda = pc.ldm; g1.sA = ss;
+  g1.B = pc.Q; g1.ldb = s; g1.sB = ss;
+  g1.C = w.Om; g1.ldc = s; g1.sC = ss;
+  HIPCHK(gemm_launch(g1, PREC_F32, 0, 0, st), "dc M Q");
+  GemmArgs g2 = gemm_base(s, s, s, 1);
+  g2.A = pc.Q; g2.lda = s; g2.sA = ss;
+  g2.B = w.Om; g2.ldb = s; g2.sB = ss;
+  g2.C = pc.T; g2.ldc = s; g2.sC = ss;
+  HIPCHK(gemm_launch(g2, PREC_F32, 1, 0, st), "dc Q^T M Q");
+  // symmetric in exact arithmetic: the pieces' own polar factors need it to be so
+  HIPCHK(dc_sym_launch(pc.T, s, s, st), "dc sym");
+  HIPCHK(dc_coupling_launch(pc.T, nullptr, nullptr, s, w.k, w.part, w.cpl, st), "dc coupling");
+  double cpl[6];
+  if ((r = read_doubles(h, st, w.cpl, 6, cpl))) return r;
+  const double tol = 10.0 * p->tol;
+  *ok = std::isfinite(cpl[0]) && std::isfinite(cpl[1]) && cpl[0] <= tol * tol * cpl[1] && cpl[2] <= 1e-6 &&
+        cpl[4] <= 1e-6;
+  pc.k = k;
+  return SVDP_OK;
+}
+
+// One matrix by polar-based spectral divide and conquer.  The matrix is
+// split once; a piece larger than kDcLeafMax is split again (to kDcDepth
+// levels).  The pieces of at most kDcLeafMax, zero-padded to the largest of
+// them, run through the Jacobi eigensolver as one batch; a larger piece (one
+// that did not split, or at the depth limit) runs alone.  Each piece is
+// solved shifted by its mean eigenvalue mu = trace / s, added back after:
+// the eigenvectors do not change, and the solver's rounding and stop tests,
+// which scale with the matrix's norm, then scale with the piece's spread
+// rather than its offset from zero.  Then, from the
+// deepest split up, V = Q diag(V1, V2).  Eigenvalues come out descending: a
+// split puts the part above its sigma first.  A matrix whose first split
+// fails runs the Jacobi eigensolver on H itself and is flagged
+// FALLBACK_USED.
 svdp_status eigh_dc_one(svdp_handle* h, const svdp_params* p, const DcWs& w, const float* H, int64_t ldh,
                         float* lam, float* V, int64_t ldv, int* sweeps, int* flags, int b, hipStream_t st) {
   const int n = (int)p->n;
-  const int64_t nn = (int64_t)n * n;
   const EighOpts eo = eigh_opts(p);
-  svdp_params q = dc_polar_params(p);
-  HIPCHK(dc_shift_launch(H, ldh, w.A, n, w.sigma, st), "dc shift");
-  Ctx c{h, &q, carve_fwd(w.polar, &q, nullptr), st, 1, n, n, w.A, n, nn};
-  svdp_status s = polar_core(c);
-  if (s) return s;
-  HIPCHK(dc_coupling_launch(c.w.X0, c.w.X1, c.w.where, n, nullptr, w.part, w.cpl, st), "dc |W|_F");
-  HIPCHK(dc_rank_launch(c.w.X0, c.w.X1, c.w.where, w.cpl, c.w.flags, n, w.k, st), "dc rank");
-  int k = 0;
-  if ((s = read_counter(c, w.k, &k))) return s;
-  bool split = k > 0 && k < n;
-  float* Q = w.Q;
-  if (split) {
-    // Y = [P X1, (I - P) X2] = (X + W X diag(cs)) / 2, cs = +1 for the first k
-    // columns, and Q = orth(Y): first with X = Om (seeded random), then once
-    // more with X = Q (one step of subspace iteration: the first Y can be
-    // badly conditioned and keeps W's error in its range; the second is
-    // nearly orthonormal and squares that error).  orth is block
-    // Gram-Schmidt with CholeskyQR blocks, in place.
-    HIPCHK(dc_random_launch(w.Om, nn, 0x5EED0000u + (uint32_t)b, st), "dc random");
-    HIPCHK(dc_signs_launch(w.cs, n, w.k, st), "dc signs");
-    FwdWs wq = c.w;
-    wq.qrc = w.qrc; wq.qrg = w.qrg; wq.qrr = w.qrr;
-    Ctx cq{h, &q, wq, st, 1, n, n, nullptr, 0, 0};
-    const float* X = w.Om;
-    float* Y = w.Q;
-    for (int step = 0; step < 2; ++step) {
-      GemmArgs g = gemm_base(n, n, n, 1);
-      g.A = c.w.X0; g.A_alt = c.w.X1; g.a_sel = c.w.where; g.lda = n; g.sA = nn;
-      g.B = X; g.ldb = n; g.sB = nn;
-      g.C = Y; g.ldc = n; g.sC = nn;
-      g.Cin = X; g.ldcin = n; g.sCin = nn;
-      g.alpha = 0.5f; g.beta = 0.5f;
-      g.colscale = w.cs; g.cs_stride = n;
-      HIPCHK(gemm_launch(g, PREC_F32, 0, 0, st), "dc range");
-      HIPCHK(fill_i32(w.qmask, 1, 1, st), "dc qmask");
-      if ((s = qr_blocks(cq, Y, n, nn, w.qmask, 0))) return s;
-      X = Y;
-      Y = w.Om;
+  std::vector<DcPiece> pcs;
+  pcs.push_back({0, n, 0, 0, H, ldh, V, ldv, nullptr, nullptr, nullptr, false});
+  size_t used = 0;
+  auto take = [&](size_t count) {
+    float* r = w.pool + used;
+    used += (count + 63) / 64 * 64;
+    return r;
+  };
+  std::vector<int> small, large;  // leaves: batched / alone
+  svdp_status r;
+  for (size_t i = 0; i < pcs.size(); ++i) {
+    DcPiece pc = pcs[i];
+    bool ok = false;
+    if (i == 0 || (pc.s > kDcLeafMax && pc.depth < kDcDepth)) {
+      const size_t mark = used, ss = (size_t)pc.s * pc.s;
+      pc.Q = take(ss);
+      pc.T = take(ss);
+      pc.W = take(ss);
+      if (used > w.pool_floats) return fail(SVDP_ERR_WORKSPACE, "divide and conquer pool overrun");
+      if ((r = dc_split(h, p, w, pc, 0x5EED0000u ^ ((uint32_t)b << 8) ^ (uint32_t)i, st, &ok))) return r;
+      if (!ok) used = mark;
     }
-    Q = w.Om;
-    // T = Q^T (H Q) and its coupling block
-    GemmArgs g1 = gemm_base(n, n, n, 1);
-    g1.A = H; g1.lda = ldh; g1.sA = nn;
-    g1.B = Q; g1.ldb = n; g1.sB = nn;
-    g1.C = w.HQ; g1.ldc = n; g1.sC = nn;
-    HIPCHK(gemm_launch(g1, PREC_F32, 0, 0, st), "dc H Q");
-    GemmArgs g2 = gemm_base(n, n, n, 1);
-    g2.A = Q; g2.lda = n; g2.sA = nn;
-    g2.B = w.HQ; g2.ldb = n; g2.sB = nn;
-    g2.C = w.T; g2.ldc = n; g2.sC = nn;
-    HIPCHK(gemm_launch(g2, PREC_F32, 1, 0, st), "dc Q^T H Q");
-    HIPCHK(dc_coupling_launch(w.T, nullptr, nullptr, n, w.k, w.part, w.cpl, st), "dc coupling");
-    double cpl[2];
-    if ((s = read_doubles(h, st, w.cpl, 2, cpl))) return s;
-    const double tol = 10.0 * p->tol;
-    split = std::isfinite(cpl[0]) && std::isfinite(cpl[1]) && cpl[0] <= tol * tol * cpl[1];
+    if (ok) {
+      pc.split = true;
+      pcs[i] = pc;
+      const int k = pc.k, s = pc.s;
+      const int64_t d = (int64_t)k * s + k;
+      pcs.push_back({pc.off, k, 0, pc.depth + 1, pc.T, s, pc.W, s, nullptr, nullptr, nullptr, false});
+      pcs.push_back({pc.off + k, s - k, 0, pc.depth + 1, pc.T + d, s, pc.W + d, s, nullptr, nullptr, nullptr,
+                     false});
+    } else if (i == 0) {
+      EighWs e = eigh_ws_carve(w.eigh, 1, n, p->max_sweeps);
+      HIPCHK(eigh_run(e, H, ldh, (int64_t)n * n, 0, eo, lam, n, V, ldv, (int64_t)n * n, sweeps, flags, nullptr,
+                      &h->aux, st), "dc eigh");
+      HIPCHK(or_flags_launch(1, flags, SVDP_FLAG_FALLBACK_USED, nullptr, st), "dc fallback flag");
+      return SVDP_OK;
+    } else {
+      (pc.s <= w.leaf_n ? small : large).push_back((int)i);
+    }
   }
-  if (split) {
-    // the two diagonal blocks, eigenvalues descending: those above sigma first
-    HIPCHK(fill_i32(w.sw, 0, 2, st), "dc sweeps");
-    HIPCHK(fill_i32(w.fl, 0, 2, st), "dc flags");
-    EighWs e1 = eigh_ws_carve(w.eigh, 1, k, p->max_sweeps);
-    HIPCHK(eigh_run(e1, w.T, n, nn, 0, eo, lam, k, w.Vd, n, nn, w.sw, w.fl, nullptr, &h->aux, st), "dc eigh 1");
-    EighWs e2 = eigh_ws_carve(w.eigh, 1, n - k, p->max_sweeps);
-    HIPCHK(eigh_run(e2, w.T + (int64_t)k * n + k, n, nn, 0, eo, lam + k, n - k, w.Vd + (int64_t)k * n + k, n,
-                    nn, w.sw + 1, w.fl + 1, nullptr, &h->aux, st), "dc eigh 2");
-    HIPCHK(dc_info_launch(w.sw, w.fl, sweeps, flags, st), "dc info");
-    // V = [Q1 V1, Q2 V2]
-    GemmArgs v1 = gemm_base(n, k, k, 1);
-    v1.A = Q; v1.lda = n; v1.sA = nn;
-    v1.B = w.Vd; v1.ldb = n; v1.sB = nn;
-    v1.C = V; v1.ldc = ldv; v1.sC = nn;
+  const int nslots = (int)(small.size() + large.size());
+  if (nslots > kDcLeaves) return fail(SVDP_ERR_WORKSPACE, "divide and conquer leaf overrun");
+  HIPCHK(fill_i32(w.sw, 0, kDcLeaves, st), "dc sweeps");
+  HIPCHK(fill_i32(w.fl, 0, kDcLeaves, st), "dc flags");
+  if (!small.empty()) {
+    int P = 1;
+    for (int i : small) P = std::max(P, pcs[i].s);
+    const int L = (int)small.size();
+    if (L > w.leaf_count) return fail(SVDP_ERR_WORKSPACE, "divide and conquer leaf overrun");
+    const int64_t PP = (int64_t)P * P;
+    HIPCHK(fill_f32(w.Hl, 0.f, L * PP, st), "dc leaf zero");
+    for (int l = 0; l < L; ++l) {
+      const DcPiece& pc = pcs[small[l]];
+      HIPCHK(dc_shift_launch(pc.M, pc.ldm, w.Hl + l * PP, P, pc.s, w.mu + l, st), "dc leaf shift");
+    }
+    EighWs e = eigh_ws_carve(w.eigh_leaf, L, P, p->max_sweeps);
+    HIPCHK(eigh_run(e, w.Hl, P, PP, 0, eo, w.laml, P, w.Vl, P, PP, w.sw, w.fl, nullptr, &h->aux, st),
+           "dc leaf eigh");
+    for (int l = 0; l < L; ++l) {
+      const DcPiece& pc = pcs[small[l]];
+      HIPCHK(dc_leaf_launch(w.Vl + l * PP, w.laml + (int64_t)l * P, w.mu + l, P, pc.s, w.map, lam + pc.off, pc.V,
+                            pc.ldv, w.fl + l, st), "dc leaf extract");
+    }
+  }
+  for (size_t j = 0; j < large.size(); ++j) {
+    const DcPiece& pc = pcs[large[j]];
+    const int slot = (int)(small.size() + j);
+    const int64_t ss = (int64_t)pc.s * pc.s;
+    EighWs e = eigh_ws_carve(w.eigh, 1, pc.s, p->max_sweeps);
+    HIPCHK(dc_shift_launch(pc.M, pc.ldm, w.A, pc.s, pc.s, w.mu + slot, st), "dc piece shift");
+    HIPCHK(eigh_run(e, w.A, pc.s, ss, 0, eo, lam + pc.off, pc.s, pc.V, pc.ldv, ss, w.sw + slot, w.fl + slot,
+                    nullptr, &h->aux, st), "dc piece eigh");
+    HIPCHK(dc_add_launch(lam + pc.off, pc.s, w.mu + slot, st), "dc piece unshift");
+  }
+  HIPCHK(dc_info_launch(w.sw, w.fl, nslots, sweeps, flags, st), "dc info");
+  // V = Q diag(V1, V2), children before their parent
+  for (size_t i = pcs.size(); i-- > 0;) {
+    const DcPiece& pc = pcs[i];
+    if (!pc.split) continue;
+    const int k = pc.k, s = pc.s;
+    const int64_t ss = (int64_t)s * s, d = (int64_t)k * s + k;
+    GemmArgs v1 = gemm_base(s, k, k, 1);
+    v1.A = pc.Q; v1.lda = s; v1.sA = ss;
+    v1.B = pc.W; v1.ldb = s; v1.sB = ss;
+    v1.C = pc.V; v1.ldc = pc.ldv; v1.sC = ss;
     HIPCHK(gemm_launch(v1, PREC_F32, 0, 0, st), "dc V1");
-    GemmArgs v2 = gemm_base(n, n - k, n - k, 1);
-    v2.A = Q + k; v2.lda = n; v2.sA = nn;
-    v2.B = w.Vd + (int64_t)k * n + k; v2.ldb = n; v2.sB = nn;
-    v2.C = V + k; v2.ldc = ldv; v2.sC = nn;
+    GemmArgs v2 = gemm_base(s, s - k, s - k, 1);
+    v2.A = pc.Q + k; v2.lda = s; v2.sA = ss;
+    v2.B = pc.W + d; v2.ldb = s; v2.sB = ss;
+    v2.C = pc.V + k; v2.ldc = pc.ldv; v2.sC = ss;
     HIPCHK(gemm_launch(v2, PREC_F32, 0, 0, st), "dc V2");
-    return SVDP_OK;
   }
-  EighWs e = eigh_ws_carve(w.eigh, 1, n, p->max_sweeps);
-  HIPCHK(eigh_run(e, H, ldh, nn, 0, eo, lam, n, V, ldv, nn, sweeps, flags, nullptr, &h->aux, st), "dc eigh");
-  HIPCHK(or_flags_launch(1, flags, SVDP_FLAG_FALLBACK_USED, nullptr, st), "dc fallback flag");
   return SVDP_OK;
 }
 

@@ -1572,12 +1572,29 @@ __global__ __launch_bounds__(1024) void k_dc_sigma(const float* H, int64_t ldh, 
   if (threadIdx.x == 0) *sigma = (float)mu;
 }
 
-// A = H - sigma I, one row per block
-__global__ void k_dc_shift(const float* H, int64_t ldh, float* A, int n, const float* sigma) {
-  const int i = blockIdx.x;
-  const float mu = *sigma;
-  for (int j = threadIdx.x; j < n; j += blockDim.x)
-    A[(int64_t)i * n + j] = H[(int64_t)i * ldh + j] - (i == j ? mu : 0.f);
+// dst = (src + src^T) / 2 - sigma I (s x s; sigma null: 0), exactly
+// symmetric.  One 32 x 32 tile pair (I, J), (J, I) with I <= J per block,
+// both read into LDS before either is written, so dst may be src.
+__global__ __launch_bounds__(256) void k_dc_sym(const float* src, int64_t lds, float* dst, int64_t ldd, int s,
+                                               const float* sigma) {
+  const int I = blockIdx.y, J = blockIdx.x;
+  if (I > J) return;
+  __shared__ float a[32][33], b[32][33];  // tile (I, J) and tile (J, I)
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const float mu = sigma ? *sigma : 0.f;
+  for (int r = ty; r < 32; r += 8) {
+    const int i = I * 32 + r, j = J * 32 + tx;
+    a[r][tx] = (i < s && j < s) ? src[(int64_t)i * lds + j] : 0.f;
+    const int i2 = J * 32 + r, j2 = I * 32 + tx;
+    b[r][tx] = (i2 < s && j2 < s) ? src[(int64_t)i2 * lds + j2] : 0.f;
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int i = I * 32 + r, j = J * 32 + tx;
+    if (i < s && j < s) dst[(int64_t)i * ldd + j] = 0.5f * (a[r][tx] + b[tx][r]) - (i == j ? mu : 0.f);
+    const int i2 = J * 32 + r, j2 = I * 32 + tx;
+    if (I != J && i2 < s && j2 < s) dst[(int64_t)i2 * ldd + j2] = 0.5f * (b[r][tx] + a[tx][r]);
+  }
 }
 
 // k = round((n + trace W) / 2), the rank of the projector (I + W) / 2, W =
@@ -1600,11 +1617,67 @@ __global__ __launch_bounds__(1024) void k_dc_rank(const float* X0, const float* 
   }
 }
 
-// the two halves' sweep counts and flags -> the matrix's (max, or)
-__global__ void k_dc_info(const int* sw, const int* fl, int* sweeps, int* flags) {
+// the pieces' sweep counts and flags -> the matrix's (max, or)
+__global__ void k_dc_info(const int* sw, const int* fl, int count, int* sweeps, int* flags) {
   if (threadIdx.x == 0) {
-    *sweeps = sw[0] > sw[1] ? sw[0] : sw[1];
-    *flags |= fl[0] | fl[1];
+    int m = 0, f = 0;
+    for (int i = 0; i < count; ++i) {
+      m = sw[i] > m ? sw[i] : m;
+      f |= fl[i];
+    }
+    *sweeps = m;
+    *flags |= f;
+  }
+}
+
+// x[i] += *mu
+__global__ void k_dc_add(float* x, int n, const float* mu) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] += *mu;
+}
+
+// A piece of size s solved inside a zero-padded P x P matrix: its padding
+// rows and columns are zero, never rotated, so the padding eigenpairs are
+// (0, e_j) for j >= s and the piece's eigenvectors are zero in rows >= s.
+// Column c of V (P x P, row-major, columns the eigenvectors) is padding when
+// its squared norm over rows s.. exceeds 1/2.  map[c] = the position of c
+// among the piece's columns in order (-1 for padding); EIGH_NOT_CONVERGED
+// when the count is not s.  One block of 1024 threads, P <= 1024.
+__global__ __launch_bounds__(1024) void k_dc_leaf_map(const float* V, int P, int s, int* map, int* flags) {
+  __shared__ int scan[1024];
+  const int c = threadIdx.x;
+  int real = 0;
+  if (c < P) {
+    float pad = 0.f;
+    for (int i = s; i < P; ++i) {
+      const float v = V[(int64_t)i * P + c];
+      pad += v * v;
+    }
+    real = pad <= 0.5f ? 1 : 0;
+  }
+  scan[c] = real;
+  __syncthreads();
+  for (int d = 1; d < 1024; d <<= 1) {  // inclusive Hillis-Steele scan
+    const int add = c >= d ? scan[c - d] : 0;
+    __syncthreads();
+    scan[c] += add;
+    __syncthreads();
+  }
+  if (c < P) map[c] = real ? scan[c] - 1 : -1;
+  if (c == 0 && scan[1023] != s) *flags |= SVDP_FLAG_EIGH_NOT_CONVERGED;
+}
+
+// The piece's eigenpairs in order: lam_out[map[c]] = lam[c] + mu, and row i < s
+// of V_out (pitch ldo) from row i of V (P x P); one row per block.  Positions
+// beyond s (a miscount, already flagged) are not written.
+__global__ void k_dc_leaf_extract(const float* V, const float* lam, const float* mu, int P, int s, const int* map,
+                                  float* lam_out, float* V_out, int64_t ldo) {
+  const int64_t i = blockIdx.x;
+  for (int c = threadIdx.x; c < P; c += blockDim.x) {
+    const int d = map[c];
+    if (d < 0 || d >= s) continue;
+    V_out[i * ldo + d] = V[i * P + c];
+    if (i == 0) lam_out[d] = lam[c] + *mu;
   }
 }
 
@@ -1653,6 +1726,28 @@ __global__ void k_dc_coupling_rows(const float* T0, const float* T1, const int* 
   }
 }
 
+// part[2 r] = row r's sum of (G[r, j] - delta_rj)^2, part[2 r + 1] = 0 (G
+// n x n row-major), one row per block
+__global__ void k_dc_dev_rows(const float* G, int n, double* part) {
+  __shared__ double red[256];
+  const int r = blockIdx.x;
+  double e = 0.0;
+  for (int j = threadIdx.x; j < n; j += 256) {
+    const double v = (double)G[(int64_t)r * n + j] - (r == j ? 1.0 : 0.0);
+    e += v * v;
+  }
+  red[threadIdx.x] = e;
+  __syncthreads();
+  for (int t = 128; t > 0; t >>= 1) {
+    if (threadIdx.x < t) red[threadIdx.x] += red[threadIdx.x + t];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * r] = red[0];
+    part[2 * r + 1] = 0.0;
+  }
+}
+
 // out[0] = |T[:k, k:]|_F^2, out[1] = |T|_F^2: the row sums added in row order
 __global__ __launch_bounds__(1024) void k_dc_coupling_sum(const double* part, int n, double* out) {
   __shared__ double red[1024];
@@ -1671,11 +1766,22 @@ __global__ __launch_bounds__(1024) void k_dc_coupling_sum(const double* part, in
 
 }  // namespace
 
-hipError_t dc_shift_launch(const float* H, int64_t ldh, float* A, int n, float* sigma, hipStream_t st) {
+hipError_t dc_shift_launch(const float* H, int64_t ldh, float* A, int64_t lda, int n, float* sigma,
+                           hipStream_t st) {
   hipLaunchKernelGGL(k_dc_sigma, dim3(1), dim3(1024), 0, st, H, ldh, n, sigma);
   hipError_t e = hipGetLastError();
   if (e) return e;
-  hipLaunchKernelGGL(k_dc_shift, dim3(n), dim3(256), 0, st, H, ldh, A, n, sigma);
+  const unsigned nt = (unsigned)cdiv(n, 32);
+  hipLaunchKernelGGL(k_dc_sym, dim3(nt, nt), dim3(256), 0, st, H, ldh, A, lda, n, sigma);
+  LAUNCH_CHECK();
+}
+hipError_t dc_add_launch(float* x, int n, const float* mu, hipStream_t st) {
+  hipLaunchKernelGGL(k_dc_add, dim3(cdiv(n, 256)), dim3(256), 0, st, x, n, mu);
+  LAUNCH_CHECK();
+}
+hipError_t dc_sym_launch(float* T, int64_t ldt, int n, hipStream_t st) {
+  const unsigned nt = (unsigned)cdiv(n, 32);
+  hipLaunchKernelGGL(k_dc_sym, dim3(nt, nt), dim3(256), 0, st, T, ldt, T, ldt, n, nullptr);
   LAUNCH_CHECK();
 }
 hipError_t dc_rank_launch(const float* X0, const float* X1, const int* sel, const double* wn2, const int* flags,
@@ -1683,8 +1789,17 @@ hipError_t dc_rank_launch(const float* X0, const float* X1, const int* sel, cons
   hipLaunchKernelGGL(k_dc_rank, dim3(1), dim3(1024), 0, st, X0, X1, sel, wn2, flags, n, k);
   LAUNCH_CHECK();
 }
-hipError_t dc_info_launch(const int* sw, const int* fl, int* sweeps, int* flags, hipStream_t st) {
-  hipLaunchKernelGGL(k_dc_info, dim3(1), dim3(64), 0, st, sw, fl, sweeps, flags);
+hipError_t dc_info_launch(const int* sw, const int* fl, int count, int* sweeps, int* flags, hipStream_t st) {
+  hipLaunchKernelGGL(k_dc_info, dim3(1), dim3(64), 0, st, sw, fl, count, sweeps, flags);
+  LAUNCH_CHECK();
+}
+hipError_t dc_leaf_launch(const float* V, const float* lam, const float* mu, int P, int s, int* map, float* lam_out,
+                          float* V_out, int64_t ldo, int* flags, hipStream_t st) {
+  if (P < 1 || P > 1024 || s < 1 || s > P) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_dc_leaf_map, dim3(1), dim3(1024), 0, st, V, P, s, map, flags);
+  hipError_t e = hipGetLastError();
+  if (e) return e;
+  hipLaunchKernelGGL(k_dc_leaf_extract, dim3(s), dim3(256), 0, st, V, lam, mu, P, s, map, lam_out, V_out, ldo);
   LAUNCH_CHECK();
 }
 hipError_t dc_random_launch(float* out, int64_t count, uint32_t seed, hipStream_t st) {
@@ -1693,6 +1808,13 @@ hipError_t dc_random_launch(float* out, int64_t count, uint32_t seed, hipStream_
 }
 hipError_t dc_signs_launch(float* cs, int n, const int* k, hipStream_t st) {
   hipLaunchKernelGGL(k_dc_signs, dim3(cdiv(n, 256)), dim3(256), 0, st, cs, n, k);
+  LAUNCH_CHECK();
+}
+hipError_t dc_dev_launch(const float* G, int n, double* part, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_dc_dev_rows, dim3(n), dim3(256), 0, st, G, n, part);
+  hipError_t e = hipGetLastError();
+  if (e) return e;
+  hipLaunchKernelGGL(k_dc_coupling_sum, dim3(1), dim3(1024), 0, st, part, n, out);
   LAUNCH_CHECK();
 }
 hipError_t dc_coupling_launch(const float* T0, const float* T1, const int* sel, int n, const int* k, double* part,

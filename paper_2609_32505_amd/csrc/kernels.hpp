@@ -151,19 +151,33 @@ hipError_t copy_masked_launch(const float* src, float* dst, int batch, int64_t p
                               hipStream_t st);
 
 // ---- spectral divide and conquer (svdp_eigh_dc), one matrix per call -------
-// *sigma = trace(H) / n, A = H - sigma I (A n x n row-major)
-hipError_t dc_shift_launch(const float* H, int64_t ldh, float* A, int n, float* sigma, hipStream_t st);
+// *sigma = trace(H) / n, A = (H + H^T) / 2 - sigma I (A n x n, pitch lda)
+hipError_t dc_shift_launch(const float* H, int64_t ldh, float* A, int64_t lda, int n, float* sigma,
+                           hipStream_t st);
+// x[i] += *mu, i < n
+hipError_t dc_add_launch(float* x, int n, const float* mu, hipStream_t st);
+// T <- (T + T^T) / 2 in place (n x n, pitch ldt), exactly symmetric
+hipError_t dc_sym_launch(float* T, int64_t ldt, int n, hipStream_t st);
 // *k = round((n + trace W) / 2) clamped to [0, n], W = sel[0] ? X1 : X0 (n x n);
 // 0 when flags[0] reports an unconverged or non-finite polar iteration or
 // when |wn2[1] - n| > 1/2 (wn2[1] = |W|_F^2)
 hipError_t dc_rank_launch(const float* X0, const float* X1, const int* sel, const double* wn2, const int* flags,
                           int n, int* k, hipStream_t st);
-// *sweeps = max(sw[0], sw[1]), *flags |= fl[0] | fl[1]
-hipError_t dc_info_launch(const int* sw, const int* fl, int* sweeps, int* flags, hipStream_t st);
+// *sweeps = max of sw[0 .. count), *flags |= the or of fl[0 .. count)
+hipError_t dc_info_launch(const int* sw, const int* fl, int count, int* sweeps, int* flags, hipStream_t st);
+// A piece of size s solved zero-padded to P x P (V, lam: the solver's output,
+// P <= 1024): its s eigenpairs, in the solver's order, to lam_out (plus *mu)
+// and the s x s V_out (pitch ldo); padding columns are told apart by their
+// weight in rows s.. (map: P ints of scratch); *flags gets
+// EIGH_NOT_CONVERGED if they are not exactly P - s
+hipError_t dc_leaf_launch(const float* V, const float* lam, const float* mu, int P, int s, int* map, float* lam_out,
+                          float* V_out, int64_t ldo, int* flags, hipStream_t st);
 // out[i] uniform in [-1, 1), a hash of (seed, i)
 hipError_t dc_random_launch(float* out, int64_t count, uint32_t seed, hipStream_t st);
 // cs[j] = j < *k ? 1 : -1
 hipError_t dc_signs_launch(float* cs, int n, const int* k, hipStream_t st);
+// out[0] = |G - I|_F^2, out[1] = 0 (G n x n; part: 2 n doubles of row sums)
+hipError_t dc_dev_launch(const float* G, int n, double* part, double* out, hipStream_t st);
 // out[0] = |T[:k, k:]|_F^2, out[1] = |T|_F^2 with T = sel && sel[0] ? T1 : T0
 // (n x n; k null: k = 0; part: 2 n doubles of row sums)
 hipError_t dc_coupling_launch(const float* T0, const float* T1, const int* sel, int n, const int* k, double* part,

@@ -131,9 +131,12 @@ def test_eigh_dc_multiple_of_identity(api):
 
 @pytest.mark.parametrize("n", [2048, 4096])
 def test_eigh_dc_large_against_jacobi_with_timing(api, n):
-    """One large matrix (the paper's single-matrix setting): the split's
-    eigenvalues against the Jacobi solver's and the reconstruction, and the
-    time of both solvers (printed; the second call of each is timed)."""
+    """One large matrix (the paper's single-matrix setting): the eigenvalues
+    against the known spectrum and the Jacobi solver's, the reconstruction,
+    and the time of both solvers (the second call of each is timed).  At
+    4096 the divide and conquer must be the faster (about 2x measured:
+    splits down to pieces of 1024 solved as one batch, against 128 phases
+    per sweep of one batch-1 Jacobi solve)."""
     import torch
     rng = inputs.rng_for(320 + n, 0)
     Q = inputs.orthonormal(rng, n, n)
@@ -165,4 +168,37 @@ def test_eigh_dc_large_against_jacobi_with_timing(api, n):
          f"sweeps {inf['sweeps'][0]}")
     assert inf["flags"][0] & 2 == 0
     assert err < 1e-5 and err_j < 1e-5
+    assert recon < 2e-5
+    if n >= 4096:
+        assert times["dc"] < times["jacobi"]
+
+
+def test_eigh_dc_heavy_tailed_spectrum_recurses(api):
+    """A log-normal spectrum (2048, sigma 2): the mean sits far above the
+    median, so each split keeps only about a sixth of its piece above sigma
+    and the larger piece is split again, down to the depth limit, where a
+    piece above the batched solve's size runs alone.  Eigenvalues against
+    the known spectrum and the Jacobi solver, V orthonormal, H reconstructed
+    (errors relative to max |lambda|)."""
+    n = 2048
+    _say(f"eigh_dc heavy-tailed n={n}")
+    rng = inputs.rng_for(330 + n, 0)
+    Q = inputs.orthonormal(rng, n, n)
+    lam = rng.lognormal(0.0, 2.0, n)
+    H = ((Q * lam) @ Q.T).astype(np.float32)[None]
+    lam_d, V_d, info = api.eigh_dc(dev(H))
+    lam_j, _, _ = api.eigh(dev(H))
+    lam_d, V_d, lam_j = host(lam_d)[0], host(V_d)[0], host(lam_j)[0]
+    inf = api.info_to_numpy(info)
+    scale = np.abs(lam).max()
+    err = np.abs(lam_d - np.sort(lam)[::-1]).max() / scale
+    err_j = np.abs(lam_d - lam_j).max() / scale
+    orth = np.abs(V_d.T @ V_d - np.eye(n)).max()
+    recon = np.linalg.norm((V_d * lam_d) @ V_d.T - H[0]) / np.linalg.norm(H[0])
+    _say(f"  lam_err {err:.2e}, vs jacobi {err_j:.2e}, orth {orth:.2e}, recon {recon:.2e}, "
+         f"flags {inf['flags'][0]}, sweeps {inf['sweeps'][0]}")
+    assert inf["flags"][0] & 2 == 0
+    assert np.all(np.diff(lam_d) <= 1e-6 * scale)
+    assert err < 1e-5 and err_j < 1e-5
+    assert orth < 1e-5
     assert recon < 2e-5
