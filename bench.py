@@ -199,6 +199,47 @@ def phase_table(L, steps):
     return out
 
 
+def eigh_dc_bench(args):
+    """One N x N symmetric matrix with a uniform spectrum in [-1, 2] (the
+    paper's single-matrix setting for its EVD bottleneck): milliseconds per
+    call of svdp_eigh_dc and svdp_eigh, and their eigenvalue errors against
+    the known spectrum (relative to max |lambda|) and reconstruction."""
+    import numpy as np
+    import torch
+    from paper_2609_32505_amd import api, inputs
+
+    n = args.eigh_dc
+    rng = inputs.rng_for(320 + n, 0)
+    Q = inputs.orthonormal(rng, n, n)
+    lam = rng.uniform(-1.0, 2.0, n)
+    H = ((Q * lam) @ Q.T).astype(np.float32)
+    Hd = torch.from_numpy(H[None]).cuda()
+    ref = np.sort(lam)[::-1]
+    out = {"metric": "symmetric EVD of one matrix, ms per call", "unit": "ms", "higher_is_better": False,
+           "config": {"workload": f"one {n} x {n} FP32 symmetric matrix, eigenvalues uniform in [-1, 2]"},
+           "steps": args.steps, "warmup": args.warmup, "data": "synthetic"}
+    solvers = {"dc": api.eigh_dc, "jacobi": api.eigh}
+    for name in (("dc", "jacobi") if args.solver == "both" else (args.solver,)):
+        fn = solvers[name]
+        for _ in range(args.warmup):
+            res = fn(Hd)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            res = fn(Hd)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / max(args.steps, 1)
+        lam_g = res[0].cpu().double().numpy()[0]
+        V = res[1].cpu().double().numpy()[0]
+        recon = float(np.linalg.norm((V * lam_g) @ V.T - H) / np.linalg.norm(H))
+        out[name] = {"ms": round(ms, 2), "lam_err": float(np.abs(lam_g - ref).max() / np.abs(ref).max()),
+                     "recon": recon, "flags": int(api.info_to_numpy(res[2])["flags"][0])}
+        log(f"{name}: {ms:.1f} ms per call")
+    if "dc" in out and "jacobi" in out:
+        out["speedup_dc_vs_jacobi"] = round(out["jacobi"]["ms"] / out["dc"]["ms"], 3)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -218,11 +259,19 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="with --profile-only: first copy a 256 MiB buffer (a kernel of known traffic "
                          "for scaling HBM counters)")
+    ap.add_argument("--eigh-dc", type=int, default=0, metavar="N",
+                    help="instead of the SVD step: one N x N symmetric EVD by divide and conquer and by "
+                         "the Jacobi solver, timed over --steps calls after --warmup")
+    ap.add_argument("--solver", choices=("both", "dc", "jacobi"), default="both",
+                    help="with --eigh-dc: the solvers to run (one alone for rocprofv3)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print(json.dumps({"error": "the benchmark runs on one GPU only (a batch shards by matrix across "
                                    "GPUs); run with --gpus 1"}))
         sys.exit(2)
+    if args.eigh_dc:
+        eigh_dc_bench(args)
+        return
 
     import numpy as np
     import torch

@@ -409,17 +409,24 @@ __global__ void k_qr_mask(int batch, const int* flags, const int* mask, int* qma
 // instead: its row of R' is taken as e_k (no trailing update) and its column
 // of Rinv as zero, so Z Rinv has a zero column there and the other columns
 // stay orthonormal and independent of it.
+// Layout: the Cholesky's trailing updates give thread t the 4 x 4 block of
+// rows 4 (t / 16).. and columns 4 (t % 16).., one barrier per step: every
+// thread takes step k's pivot itself, and the rows are scaled only after the
+// last step (the update uses A[k][i] A[k][j] / r_k^2), so row k is never
+// written while step k reads it.  The inverse runs up the rows, four
+// adjacent lanes per column of R'^-1 summing interleaved terms.
 __global__ __launch_bounds__(256) void k_qr_chol(const float* G, float* Rinv, int bc, const int* qmask,
                                                  int zero_dep) {
   const int b = blockIdx.x;
   if (!qmask[b]) return;
-  __shared__ double A[64][65];
-  __shared__ float X[64][65];  // R'^-1
-  __shared__ double d[64];
+  __shared__ double A[64][65];  // G', then R' (upper, scaled at the end)
+  __shared__ double X[64][65];  // R'^-1
+  __shared__ double d[64], rd[64];
+  __shared__ int dep[64];
+  __shared__ double gmax;
   const int t = threadIdx.x;
   // per-matrix stride 64 x 64 whatever bc (the layout of the block GEMMs)
   const float* Gb = G + (int64_t)b * 64 * 64;
-  __shared__ double gmax;
   if (t == 0) {
     double mx = 0.0;
     for (int j = 0; j < bc; ++j) mx = fmax(mx, (double)Gb[(int64_t)j * bc + j]);
@@ -428,49 +435,59 @@ __global__ __launch_bounds__(256) void k_qr_chol(const float* G, float* Rinv, in
   __syncthreads();
   for (int j = t; j < bc; j += 256) d[j] = sqrt(fmax((double)Gb[(int64_t)j * bc + j], 1e-30 * gmax));
   __syncthreads();
-  for (int idx = t; idx < bc * bc; idx += 256) {
-    const int i = idx / bc, j = idx - i * bc;
-    A[i][j] = (double)Gb[idx] / (d[i] * d[j]);
-    X[i][j] = 0.f;
+  for (int idx = t; idx < 64 * 64; idx += 256) {
+    const int i = idx >> 6, j = idx & 63;
+    A[i][j] = (i < bc && j < bc) ? (double)Gb[i * bc + j] / (d[i] * d[j]) : 0.0;
   }
   __syncthreads();
-  __shared__ int dep[64];
-  for (int k = t; k < 64; k += 256) dep[k] = 0;
-  __syncthreads();
+  const int i0 = (t >> 4) * 4, j0 = (t & 15) * 4;
   for (int k = 0; k < bc; ++k) {
+    const double piv = A[k][k];
+    const bool dk = zero_dep && !(piv > 1e-13);
+    const double r = dk ? 1.0 : (piv > 1e-12 ? sqrt(piv) : 1e-6);
     if (t == 0) {
-      const double piv = A[k][k];
-      if (zero_dep && !(piv > 1e-13)) {
-        dep[k] = 1;
-        A[k][k] = 1.0;
-      } else {
-        A[k][k] = piv > 1e-12 ? sqrt(piv) : 1e-6;
+      dep[k] = dk;
+      rd[k] = r;
+    }
+    if (!dk && j0 + 3 > k && i0 <= j0 + 3) {
+      const double inv = 1.0 / (r * r);
+      double ai[4], aj[4];
+      for (int q = 0; q < 4; ++q) {
+        ai[q] = A[k][i0 + q];
+        aj[q] = A[k][j0 + q] * inv;
+      }
+      for (int p = 0; p < 4; ++p) {
+        const int i = i0 + p;
+        if (i <= k || i >= bc) continue;
+        for (int q = 0; q < 4; ++q) {
+          const int j = j0 + q;
+          if (j >= i && j < bc) A[i][j] -= ai[p] * aj[q];
+        }
       }
     }
     __syncthreads();
-    for (int j = k + 1 + t; j < bc; j += 256) A[k][j] = dep[k] ? 0.0 : A[k][j] / A[k][k];
-    __syncthreads();
-    const int w = bc - k - 1;
-    for (int idx = t; idx < w * w; idx += 256) {
-      const int i = k + 1 + idx / w, j = k + 1 + idx % w;
-      if (j >= i) A[i][j] -= A[k][i] * A[k][j];
-    }
-    __syncthreads();
   }
-  // X = R'^-1 (upper), one column per thread, back substitution
-  if (t < bc) {
-    const int j = t;
-    for (int i = j; i >= 0; --i) {
-      double s = i == j ? 1.0 : 0.0;
-      for (int k = i + 1; k <= j; ++k) s -= A[i][k] * (double)X[k][j];
-      X[i][j] = (float)(s / A[i][i]);
-    }
+  // R' row k = A[k][k..] / r_k (a dropped column: e_k)
+  for (int idx = t; idx < 64 * 64; idx += 256) {
+    const int i = idx >> 6, j = idx & 63;
+    if (i < bc && j < bc && j >= i) A[i][j] = j == i ? rd[i] : (dep[i] ? 0.0 : A[i][j] / rd[i]);
   }
   __syncthreads();
+  // X = R'^-1: row i from the rows below it
+  const int jc = t >> 2, part = t & 3;
+  for (int i = bc - 1; i >= 0; --i) {
+    double acc = 0.0;
+    if (jc < bc && jc > i)
+      for (int k = i + 1 + part; k <= jc; k += 4) acc += A[i][k] * X[k][jc];
+    acc += __shfl_xor(acc, 1);
+    acc += __shfl_xor(acc, 2);
+    if (part == 0 && jc < bc) X[i][jc] = jc < i ? 0.0 : ((jc == i ? 1.0 : 0.0) - acc) / A[i][i];
+    __syncthreads();
+  }
   float* Rb = Rinv + (int64_t)b * 64 * 64;
   for (int idx = t; idx < bc * bc; idx += 256) {
     const int i = idx / bc, j = idx - i * bc;
-    Rb[idx] = (j >= i && !dep[j]) ? (float)((double)X[i][j] / d[i]) : 0.f;
+    Rb[idx] = (j >= i && !dep[j]) ? (float)(X[i][j] / d[i]) : 0.f;
   }
 }
 
