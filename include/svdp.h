@@ -306,7 +306,8 @@ svdp_status svdp_eigh(svdp_handle* h, const svdp_params* p,
 /* Symmetric eigendecomposition by polar-based spectral divide and conquer
  * (the stable QDWH-eig-type method the paper's related work cites for
  * relieving the EVD bottleneck at large n), with the same results as
- * svdp_eigh: lam descending, V n x n.  H is taken as its symmetric part.
+ * svdp_eigh: lam descending, V n x n.  H is taken as its symmetric part
+ * (H + H^T) / 2: inside the SVD, the symmetric matrix nearest to W^T A.
  * A split of a symmetric piece M (s x s):
  *   sigma = trace(M) / s; W = polar(M - sigma I) = sign(M - sigma I) by
  *   conservative FP32 CANS (the same iteration as Algorithm 1); P = (I + W)/2

@@ -1634,7 +1634,9 @@ __global__ __launch_bounds__(1024) void k_dc_rank(const float* X0, const float* 
   }
 }
 
-// the pieces' sweep counts and flags -> the matrix's (max, or)
+// the pieces' sweep counts and flags -> the matrix's (max, or).  The pieces
+// are solved shifted by their mean eigenvalue, so their NEG_EIGENVALUE says
+// nothing about the matrix and is dropped.
 __global__ void k_dc_info(const int* sw, const int* fl, int count, int* sweeps, int* flags) {
   if (threadIdx.x == 0) {
     int m = 0, f = 0;
@@ -1643,8 +1645,91 @@ __global__ void k_dc_info(const int* sw, const int* fl, int count, int* sweeps, 
       f |= fl[i];
     }
     *sweeps = m;
-    *flags |= f;
+    *flags |= f & ~SVDP_FLAG_NEG_EIGENVALUE;
   }
+}
+
+// *flags |= NEG_EIGENVALUE when some lam[i] < -neg_tol max |lam| (one block)
+__global__ __launch_bounds__(1024) void k_dc_neg(const float* lam, int n, float neg_tol, int* flags) {
+  __shared__ float vmax, vneg;
+  if (threadIdx.x == 0) { vmax = 0.f; vneg = 0.f; }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const float d = lam[i];
+    if (!isfinite(d)) continue;
+    atomicMax((int*)&vmax, __float_as_int(fabsf(d)));  // |d| >= 0: int order = float order
+    if (d < 0.f) atomicMax((int*)&vneg, __float_as_int(-d));
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && vneg > neg_tol * vmax) *flags |= SVDP_FLAG_NEG_EIGENVALUE;
+}
+
+// The SVD's order of an eigendecomposition of H = W^T A (one matrix, lam
+// descending by value): lam <- |lam| descending (ties by index), sgn = the
+// signs, perm = the source positions, flags as the Jacobi solver raises them
+// for H (NONFINITE; NEG_EIGENVALUE below -neg_tol max |lam|).  One block of
+// 1024 threads, dynamic LDS 8 P2 bytes (P2 = next power of two >= n); the
+// signs are read from lam before a barrier, the sorted values written after.
+__global__ __launch_bounds__(1024) void k_dc_abs_sort(float* lam, int n, float* sgn, int* perm, float neg_tol,
+                                                     int* flags) {
+  extern __shared__ unsigned char smem[];
+  int P2 = 1;
+  while (P2 < n) P2 <<= 1;
+  float* key = (float*)smem;
+  int* idx = (int*)(key + P2);
+  __shared__ float vmax, vneg;
+  __shared__ int bad;
+  if (threadIdx.x == 0) { vmax = 0.f; vneg = 0.f; bad = 0; }
+  __syncthreads();
+  for (int i = threadIdx.x; i < P2; i += blockDim.x) {
+    float d = i < n ? lam[i] : 0.f;
+    if (i < n && !isfinite(d)) { bad = 1; d = 0.f; }
+    key[i] = i < n ? fabsf(d) : -INFINITY;
+    idx[i] = i;
+    if (i < n) {
+      atomicMax((int*)&vmax, __float_as_int(fabsf(d)));  // |d| >= 0: int order = float order
+      if (d < 0.f) atomicMax((int*)&vneg, __float_as_int(-d));
+    }
+  }
+  __syncthreads();
+  for (int size = 2; size <= P2; size <<= 1)
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = threadIdx.x; i < P2; i += blockDim.x) {
+        const int j = i ^ stride;
+        if (j > i) {
+          const bool desc = (i & size) == 0;
+          const float ki = key[i], kj = key[j];
+          const int ii = idx[i], ij = idx[j];
+          const bool i_first = ki > kj || (ki == kj && ii < ij);
+          if (desc != i_first) {
+            key[i] = kj; key[j] = ki;
+            idx[i] = ij; idx[j] = ii;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  for (int c = threadIdx.x; c < n; c += blockDim.x) sgn[c] = lam[idx[c]] < 0.f ? -1.f : 1.f;
+  __syncthreads();
+  for (int c = threadIdx.x; c < n; c += blockDim.x) {
+    lam[c] = key[c];
+    perm[c] = idx[c];
+  }
+  if (threadIdx.x == 0) {
+    int f = 0;
+    if (bad) f |= SVDP_FLAG_NONFINITE;
+    if (vneg > neg_tol * vmax) f |= SVDP_FLAG_NEG_EIGENVALUE;
+    if (f) *flags |= f;
+  }
+}
+
+// V[i, c] <- V[i, perm[c]] (n x n, pitch ldv), one row per block through LDS
+__global__ void k_dc_permute_cols(float* V, int64_t ldv, int n, const int* perm) {
+  extern __shared__ float row[];
+  float* v = V + (int64_t)blockIdx.x * ldv;
+  for (int c = threadIdx.x; c < n; c += blockDim.x) row[c] = v[c];
+  __syncthreads();
+  for (int c = threadIdx.x; c < n; c += blockDim.x) v[c] = row[perm[c]];
 }
 
 // x[i] += *mu
@@ -1790,6 +1875,21 @@ hipError_t dc_shift_launch(const float* H, int64_t ldh, float* A, int64_t lda, i
   if (e) return e;
   const unsigned nt = (unsigned)cdiv(n, 32);
   hipLaunchKernelGGL(k_dc_sym, dim3(nt, nt), dim3(256), 0, st, H, ldh, A, lda, n, sigma);
+  LAUNCH_CHECK();
+}
+hipError_t dc_abs_order_launch(float* lam, float* V, int64_t ldv, int n, float* sgn, int* perm, float neg_tol,
+                               int* flags, hipStream_t st) {
+  if (n < 1 || n > 8192) return hipErrorInvalidValue;
+  int P2 = 1;
+  while (P2 < n) P2 <<= 1;
+  hipLaunchKernelGGL(k_dc_abs_sort, dim3(1), dim3(1024), (size_t)8 * P2, st, lam, n, sgn, perm, neg_tol, flags);
+  hipError_t e = hipGetLastError();
+  if (e) return e;
+  hipLaunchKernelGGL(k_dc_permute_cols, dim3(n), dim3(256), (size_t)4 * n, st, V, ldv, n, perm);
+  LAUNCH_CHECK();
+}
+hipError_t dc_neg_launch(const float* lam, int n, float neg_tol, int* flags, hipStream_t st) {
+  hipLaunchKernelGGL(k_dc_neg, dim3(1), dim3(1024), 0, st, lam, n, neg_tol, flags);
   LAUNCH_CHECK();
 }
 hipError_t dc_add_launch(float* x, int n, const float* mu, hipStream_t st) {

@@ -156,6 +156,12 @@ hipError_t dc_shift_launch(const float* H, int64_t ldh, float* A, int64_t lda, i
                            hipStream_t st);
 // x[i] += *mu, i < n
 hipError_t dc_add_launch(float* x, int n, const float* mu, hipStream_t st);
+// The SVD's order of one eigendecomposition (lam descending by value, V n x n
+// pitch ldv, n <= 8192): lam <- |lam| descending, sgn = the signs, V's columns
+// permuted to match (perm: n ints of scratch); *flags |= NONFINITE and
+// NEG_EIGENVALUE (an eigenvalue below -neg_tol max |lam|)
+hipError_t dc_abs_order_launch(float* lam, float* V, int64_t ldv, int n, float* sgn, int* perm, float neg_tol,
+                               int* flags, hipStream_t st);
 // T <- (T + T^T) / 2 in place (n x n, pitch ldt), exactly symmetric
 hipError_t dc_sym_launch(float* T, int64_t ldt, int n, hipStream_t st);
 // *k = round((n + trace W) / 2) clamped to [0, n], W = sel[0] ? X1 : X0 (n x n);
@@ -163,7 +169,10 @@ hipError_t dc_sym_launch(float* T, int64_t ldt, int n, hipStream_t st);
 // when |wn2[1] - n| > 1/2 (wn2[1] = |W|_F^2)
 hipError_t dc_rank_launch(const float* X0, const float* X1, const int* sel, const double* wn2, const int* flags,
                           int n, int* k, hipStream_t st);
-// *sweeps = max of sw[0 .. count), *flags |= the or of fl[0 .. count)
+// *flags |= NEG_EIGENVALUE when some lam[i] < -neg_tol max |lam|
+hipError_t dc_neg_launch(const float* lam, int n, float neg_tol, int* flags, hipStream_t st);
+// *sweeps = max of sw[0 .. count), *flags |= the or of fl[0 .. count) without
+// NEG_EIGENVALUE (the pieces are shifted)
 hipError_t dc_info_launch(const int* sw, const int* fl, int count, int* sweeps, int* flags, hipStream_t st);
 // A piece of size s solved zero-padded to P x P (V, lam: the solver's output,
 // P <= 1024): its s eigenpairs, in the solver's order, to lam_out (plus *mu)

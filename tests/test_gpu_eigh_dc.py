@@ -3,6 +3,7 @@
 eigensolver (svdp_eigh) on the same matrices.  Every call goes through the
 C ABI (libsvdp.so) via the ctypes binding."""
 import sys
+import time
 
 import numpy as np
 import pytest
@@ -202,3 +203,57 @@ def test_eigh_dc_heavy_tailed_spectrum_recurses(api):
     assert err < 1e-5 and err_j < 1e-5
     assert orth < 1e-5
     assert recon < 2e-5
+
+
+def test_svd_single_large_matrix_takes_divide_and_conquer(api):
+    """A single FP32 matrix of n >= 2048 takes the SVD's EVD step by divide
+    and conquer; the same matrix twice in a batch takes the batched Jacobi.
+    Both against the generating factors (sigma log-uniform in [1e-3, 1]):
+    singular values normwise, reconstruction and orthogonality as in the
+    paper's Tables 1-2 (relative Frobenius), U and V on well-separated
+    columns, and the two routes against each other.  No route may flag a
+    fallback, a negative eigenvalue of H (it is positive definite here),
+    non-finite values or an unconverged eigensolver."""
+    import torch
+    n = 2048
+    _say(f"svd single {n} via divide and conquer")
+    rng = inputs.rng_for(340, 0)
+    U0 = inputs.orthonormal(rng, n, n)
+    V0 = inputs.orthonormal(rng, n, n)
+    s = np.sort(10.0 ** rng.uniform(-3.0, 0.0, n))[::-1]
+    A = ((U0 * s) @ V0.T).astype(np.float32)
+    Ad = dev(A[None])
+    api.svd_fwd(Ad)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    U1, S1, V1, info1 = api.svd_fwd(Ad)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    U2, S2, V2, info2 = api.svd_fwd(dev(np.stack([A, A])))
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    i1, i2 = api.info_to_numpy(info1), api.info_to_numpy(info2)
+    gap = np.abs(np.diff(s)) / s[0]
+    sep = np.ones(n, bool)
+    sep[:-1] &= gap > 1e-3
+    sep[1:] &= gap > 1e-3
+    out = {}
+    for name, (U, S, V) in (("dc", (U1[0], S1[0], V1[0])), ("jacobi", (U2[0], S2[0], V2[0]))):
+        U, S, V = host(U), host(S), host(V)
+        sig = np.linalg.norm(S - s) / np.linalg.norm(s)
+        recon = np.linalg.norm((U * S) @ V.T - A) / np.linalg.norm(A)
+        ou = np.linalg.norm(U.T @ U - np.eye(n)) / np.sqrt(n)
+        ov = np.linalg.norm(V.T @ V - np.eye(n)) / np.sqrt(n)
+        sg = np.sign(np.sum(V * V0, axis=0))
+        sg[sg == 0] = 1.0
+        verr = np.abs(V * sg - V0)[:, sep].max()
+        uerr = np.abs(U * sg - U0)[:, sep].max()
+        out[name] = S
+        _say(f"  {name}: sigma {sig:.2e}, recon {recon:.2e}, orth U {ou:.2e} V {ov:.2e}, "
+             f"U {uerr:.2e} V {verr:.2e} on {sep.sum()} columns")
+        assert sig < 1e-5 and recon < 1.5e-5 and ou < 1e-5 and ov < 1e-5
+        assert uerr < 1e-3 and verr < 1e-3
+    _say(f"  single (divide and conquer) {1e3 * (t1 - t0):.0f} ms, pair (Jacobi) {1e3 * (t2 - t1):.0f} ms; "
+         f"flags {i1['flags'][0]} / {i2['flags'][0]}, sweeps {i1['sweeps'][0]} / {i2['sweeps'][0]}")
+    assert np.linalg.norm(out["dc"] - out["jacobi"]) / np.linalg.norm(s) < 1e-5
+    assert i1["flags"][0] & (2 | 4 | 16 | 32) == 0 and i2["flags"][0] & (2 | 4 | 16 | 32) == 0
