@@ -312,10 +312,11 @@ svdp_status svdp_eigh(svdp_handle* h, const svdp_params* p,
  *   sigma = trace(M) / s; W = polar(M - sigma I) = sign(M - sigma I) by
  *   conservative FP32 CANS (the same iteration as Algorithm 1); P = (I + W)/2
  *   projects onto the eigenvectors above sigma, of rank k = (s + trace W)/2;
- *   Q = [Q1 Q2] spans P's range and its complement: the blocked QR of
- *   [P Om1, (I - P) Om2] with Om a seeded pseudo-random matrix, then one
- *   step of subspace iteration, [P Q1, (I - P) Q2] orthonormalised block by
- *   block by Newton-Schulz; T = Q^T M Q (symmetrised), whose diagonal blocks
+ *   Q = [Q1 Q2] spans P's range and its complement: the polar factors (the
+ *   same CANS) of P Om1 and of (I - P) Om2 with P Om1's span projected out,
+ *   Om a seeded pseudo-random matrix, then one step of subspace iteration,
+ *   [P Q1, (I - P) Q2] orthonormalised block by block by Newton-Schulz;
+ *   T = Q^T M Q (symmetrised), whose diagonal blocks
  *   T[:k, :k] and T[k:, k:] are the two new pieces; V = [Q1 V1, Q2 V2] once
  *   they are solved.  The dropped coupling T[:k, k:] is held to
  *   10 tol |T|_F (tol: the CANS stop test).

@@ -974,10 +974,11 @@ constexpr int kDcLeaves = 1 << kDcDepth;
 
 struct DcWs {
   void* polar;              // the polar step's forward workspace (for n)
+  void* polar2;             // ... and that of the first basis's polar factors
   float *A, *Om, *HQ;       // n x n temporaries of one split
-  float *cs, *sigma, *mu, *qrc, *qrg, *qrr;  // mu: each leaf's shift
+  float *cs, *sigma, *mu;   // mu: each leaf's shift
   double *part, *cpl;
-  int *k, *qmask, *sw, *fl, *map, *sweeps, *flags;
+  int *k, *sw, *fl, *map, *sweeps, *flags;
   float* pool;              // Q, T, W of every split piece (bump-allocated)
   size_t pool_floats;
   float *Hl, *Vl, *laml;    // the batched leaf solve: up to leaf_count zero-padded pieces
@@ -996,19 +997,16 @@ DcWs carve_dc(void* base, const svdp_params* p, size_t* total) {
   const size_t n = p->n, nn = n * n;
   const size_t L = std::min<size_t>(n, kDcLeafMax);
   w.polar = c.take_bytes(fw);
+  w.polar2 = c.take_bytes(fw);
   w.A = c.take<float>(nn);
   w.Om = c.take<float>(nn);
   w.HQ = c.take<float>(nn);
   w.cs = c.take<float>(n);
   w.sigma = c.take<float>(1);
   w.mu = c.take<float>(kDcLeaves);
-  w.qrc = c.take<float>(n * kQrBlock);
-  w.qrg = c.take<float>(kQrBlock * kQrBlock);
-  w.qrr = c.take<float>(kQrBlock * kQrBlock);
   w.part = c.take<double>(2 * n);
   w.cpl = c.take<double>(6);
   w.k = c.take<int>(1);
-  w.qmask = c.take<int>(1);
   w.sw = c.take<int>(kDcLeaves);
   w.fl = c.take<int>(kDcLeaves);
   w.map = c.take<int>(L);
@@ -1065,13 +1063,15 @@ struct DcPiece {
 // shifted matrix: P = (I + W) / 2 projects onto the eigenvectors with
 // eigenvalues above sigma and has rank k = (s + trace W) / 2.  An
 // orthonormal basis Q = [Q1 Q2] of range(P) and its complement comes from
-// Y = [P X1, (I - P) X2] twice: first with X = Om (seeded random), Y made
-// orthonormal by the blocked QR; then once more with X = that basis (one
-// step of subspace iteration: the first Y can be badly conditioned and keeps
-// W's error in its range; the second is nearly orthonormal and squares that
-// error), whose first k columns and then the rest, projected twice against
-// them, are made orthonormal by three Newton-Schulz steps each (right
-// multiplications, so each block keeps its span).  Then T = Q^T M Q (made
+// Y = [P X1, (I - P) X2] twice: first with X = Om (seeded random), its two
+// blocks made orthonormal by their polar factors (the second block after
+// two projections against the first's); then once more with X = that basis
+// (one step of subspace iteration: the first Y can be badly conditioned and
+// keeps W's error in its range; the second is nearly orthonormal and squares
+// that error), whose first k columns and then the rest, projected twice
+// against them, are made orthonormal by three Newton-Schulz steps each.
+// Polar factors and Newton-Schulz steps are right multiplications, so each
+// block keeps its span.  Then T = Q^T M Q (made
 // exactly symmetric: the polar factor of a slightly non-symmetric piece
 // misplaces the directions near its sigma), block diagonal up to the
 // coupling T[:k, k:], which must stay below 10 tol |T|_F.  *ok = 0 (and Q, T
@@ -1109,12 +1109,42 @@ svdp_status dc_split(svdp_handle* h, const svdp_params* p, const DcWs& w, DcPiec
     return gemm_launch(g, PREC_F32, 0, 0, st);
   };
   HIPCHK(range(w.Om, w.HQ), "dc range 1");
-  FwdWs wq = c.w;
-  wq.qrc = w.qrc; wq.qrg = w.qrg; wq.qrr = w.qrr;
-  Ctx cq{h, &q, wq, st, 1, s, s, nullptr, 0, 0};
-  HIPCHK(fill_i32(w.qmask, 1, 1, st), "dc qmask");
-  if ((r = qr_blocks(cq, w.HQ, s, ss, w.qmask, 0))) return r;
-  HIPCHK(range(w.HQ, w.Om), "dc range 2");
+  // Y2 <- Y2 - Q1 (Q1^T Y2) for the s x (s - k) block at Y (pitch s), Q1 the
+  // first k columns of pc.Q
+  auto project = [&](float* Y2) -> hipError_t {
+    GemmArgs g = gemm_base(k, s - k, s, 1);
+    g.A = pc.Q; g.lda = s; g.sA = ss;
+    g.B = Y2; g.ldb = s; g.sB = ss;
+    g.C = w.A; g.ldc = s - k; g.sC = ss;
+    hipError_t e = gemm_launch(g, PREC_F32, 1, 0, st);
+    if (e) return e;
+    GemmArgs u = gemm_base(s, s - k, k, 1);
+    u.A = pc.Q; u.lda = s; u.sA = ss;
+    u.B = w.A; u.ldb = s - k; u.sB = ss;
+    u.C = Y2; u.ldc = s; u.sC = ss;
+    u.Cin = Y2; u.ldcin = s; u.sCin = ss;
+    u.alpha = -1.f; u.beta = 1.f;
+    return gemm_launch(u, PREC_F32, 0, 0, st);
+  };
+  // the first basis: polar factors (conservative FP32 CANS) of Y1 and of Y2
+  // with Y1's span projected out, into pc.Q.  A polar factor spans its
+  // input's columns, and CANS converges from a badly conditioned input,
+  // where CholeskyQR would not; what it leaves off orthonormal the
+  // Newton-Schulz check below catches.
+  auto basis = [&](const float* Y, int cols, float* dst) -> svdp_status {
+    svdp_params q2 = dc_polar_params(p);
+    q2.m = s;
+    q2.n = cols;
+    Ctx c2{h, &q2, carve_fwd(w.polar2, &q2, nullptr, false), st, 1, s, cols, Y, s, ss};
+    svdp_status r2 = polar_core(c2);
+    if (r2) return r2;
+    HIPCHK(dc_copy_sel_launch(c2.w.X0, c2.w.X1, c2.w.where, cols, dst, s, s, cols, st), "dc basis");
+    return SVDP_OK;
+  };
+  if ((r = basis(w.HQ, k, pc.Q))) return r;
+  for (int pass = 0; pass < 2; ++pass) HIPCHK(project(w.HQ + k), "dc project 1");
+  if ((r = basis(w.HQ + k, s - k, pc.Q + k))) return r;
+  HIPCHK(range(pc.Q, w.Om), "dc range 2");
   // Newton-Schulz on the s x cols block at column c0: Z = Y (3 I - Y^T Y) / 2,
   // from Om to Q, back and to Q again; |G - I|_F^2 of the last G to dev
   auto newton_schulz = [&](int c0, int cols, double* dev) -> hipError_t {
@@ -1141,20 +1171,7 @@ svdp_status dc_split(svdp_handle* h, const svdp_params* p, const DcWs& w, DcPiec
     return hipSuccess;
   };
   HIPCHK(newton_schulz(0, k, w.cpl + 2), "dc orth Q1");
-  for (int pass = 0; pass < 2; ++pass) {  // Y2 <- Y2 - Q1 (Q1^T Y2)
-    GemmArgs g = gemm_base(k, s - k, s, 1);
-    g.A = pc.Q; g.lda = s; g.sA = ss;
-    g.B = w.Om + k; g.ldb = s; g.sB = ss;
-    g.C = w.A; g.ldc = s - k; g.sC = ss;
-    HIPCHK(gemm_launch(g, PREC_F32, 1, 0, st), "dc project");
-    GemmArgs u = gemm_base(s, s - k, k, 1);
-    u.A = pc.Q; u.lda = s; u.sA = ss;
-    u.B = w.A; u.ldb = s - k; u.sB = ss;
-    u.C = w.Om + k; u.ldc = s; u.sC = ss;
-    u.Cin = w.Om + k; u.ldcin = s; u.sCin = ss;
-    u.alpha = -1.f; u.beta = 1.f;
-    HIPCHK(gemm_launch(u, PREC_F32, 0, 0, st), "dc project update");
-  }
+  for (int pass = 0; pass < 2; ++pass) HIPCHK(project(w.Om + k), "dc project 2");
   HIPCHK(newton_schulz(k, s - k, w.cpl + 4), "dc orth Q2");
   // T = Q^T (M Q) and its coupling block
   GemmArgs g1 = gemm_base(s, s, s, 1);

@@ -1732,6 +1732,14 @@ __global__ void k_dc_permute_cols(float* V, int64_t ldv, int n, const int* perm)
   for (int c = threadIdx.x; c < n; c += blockDim.x) v[c] = row[perm[c]];
 }
 
+// dst (rows x cols, pitch ldd) <- sel[0] ? X1 : X0 (pitch lds), one row per block
+__global__ void k_dc_copy_sel(const float* X0, const float* X1, const int* sel, int64_t lds, float* dst,
+                              int64_t ldd, int cols) {
+  const float* src = sel[0] ? X1 : X0;
+  const int64_t i = blockIdx.x;
+  for (int j = threadIdx.x; j < cols; j += blockDim.x) dst[i * ldd + j] = src[i * lds + j];
+}
+
 // x[i] += *mu
 __global__ void k_dc_add(float* x, int n, const float* mu) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1890,6 +1898,12 @@ hipError_t dc_abs_order_launch(float* lam, float* V, int64_t ldv, int n, float* 
 }
 hipError_t dc_neg_launch(const float* lam, int n, float neg_tol, int* flags, hipStream_t st) {
   hipLaunchKernelGGL(k_dc_neg, dim3(1), dim3(1024), 0, st, lam, n, neg_tol, flags);
+  LAUNCH_CHECK();
+}
+hipError_t dc_copy_sel_launch(const float* X0, const float* X1, const int* sel, int64_t lds, float* dst,
+                              int64_t ldd, int rows, int cols, hipStream_t st) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_dc_copy_sel, dim3(rows), dim3(256), 0, st, X0, X1, sel, lds, dst, ldd, cols);
   LAUNCH_CHECK();
 }
 hipError_t dc_add_launch(float* x, int n, const float* mu, hipStream_t st) {

@@ -154,6 +154,9 @@ hipError_t copy_masked_launch(const float* src, float* dst, int batch, int64_t p
 // *sigma = trace(H) / n, A = (H + H^T) / 2 - sigma I (A n x n, pitch lda)
 hipError_t dc_shift_launch(const float* H, int64_t ldh, float* A, int64_t lda, int n, float* sigma,
                            hipStream_t st);
+// dst (rows x cols, pitch ldd) <- sel[0] ? X1 : X0 (pitch lds)
+hipError_t dc_copy_sel_launch(const float* X0, const float* X1, const int* sel, int64_t lds, float* dst,
+                              int64_t ldd, int rows, int cols, hipStream_t st);
 // x[i] += *mu, i < n
 hipError_t dc_add_launch(float* x, int n, const float* mu, hipStream_t st);
 // The SVD's order of one eigendecomposition (lam descending by value, V n x n
