@@ -22,11 +22,14 @@
  *     the default stream).  Calls return after enqueueing: the iteration
  *     control of CANS, of the bounded schedule and refinement, of the Jacobi
  *     sweeps and of the eigensolver restarts runs on the device (fixed
- *     budgets of launches whose workgroups skip converged matrices).  Two
- *     forward steps read a device count back, which synchronises `stream`:
- *     the bounded paths' fallback test (learned / user bounds), and the QR
- *     step of Algorithm 1 when it runs blocked (n > 512); svdp_host_syncs()
- *     counts them.
+ *     budgets of launches whose workgroups skip converged matrices).  Three
+ *     forward steps read device values back, which synchronises `stream`:
+ *     the bounded paths' fallback test (learned / user bounds), the QR step
+ *     of Algorithm 1 when it runs blocked (n > 512), and the EVD step of a
+ *     single FP32 matrix from n = 2048, which runs by the divide and conquer
+ *     of svdp_eigh_dc (two reads per split); svdp_host_syncs() counts them.
+ *     That EVD route also enlarges svd_polar_fwd's workspace by the
+ *     divide and conquer's (SVDP_OP_EIGH_DC's for batch 1).
  *   - Errors: arguments are checked before anything is launched; a non-OK
  *     status means no work was enqueued, except SVDP_ERR_HIP, which reports
  *     a failed launch or copy (svdp_last_error() gives the HIP message).

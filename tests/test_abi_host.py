@@ -81,6 +81,15 @@ def test_workspace_size_and_shape_validation():
     st4, nb4 = _ws(L.default_params(1, 1024, 1024), L.OP_EIGH)
     assert st3 == 0 and st4 == 0 and nb3 > nb4 + 6 * 1024 * 1024 * 4
     assert _ws(L.default_params(8, 1024, 1024), L.OP_EIGH_DC)[1] - nb3 < 1024
+    # a single FP32 matrix from n = 2048 takes the SVD's EVD step by divide
+    # and conquer: its forward workspace holds that solver's, which polar_fwd's,
+    # the BF16 path's and a batch's do not
+    one = _ws(L.default_params(1, 2048, 2048), L.OP_SVD_FWD)[1]
+    dcw = _ws(L.default_params(1, 2048, 2048), L.OP_EIGH_DC)[1]
+    assert one >= dcw + _ws(L.default_params(1, 2048, 2048), L.OP_POLAR_FWD)[1]
+    assert _ws(L.default_params(1, 2048, 2048, precision=1), L.OP_SVD_FWD)[1] < one - dcw // 2
+    assert _ws(L.default_params(2, 2048, 2048), L.OP_SVD_FWD)[1] < 2 * one - dcw
+    assert _ws(L.default_params(1, 2047, 2047), L.OP_SVD_FWD)[1] < one - dcw // 2
 
 
 def test_status_strings():
