@@ -1068,7 +1068,9 @@ struct DcPiece {
 // two projections against the first's); then once more with X = that basis
 // (one step of subspace iteration: the first Y can be badly conditioned and
 // keeps W's error in its range; the second is nearly orthonormal and squares
-// that error), whose first k columns and then the rest, projected twice
+// that error -- W is an odd polynomial of the shifted piece, so its error is
+// in its eigenvalues, and P's wrong-side eigenvalues enter squared), whose
+// first k columns and then the rest, projected twice
 // against them, are made orthonormal by three Newton-Schulz steps each.
 // Polar factors and Newton-Schulz steps are right multiplications, so each
 // block keeps its span.  Then T = Q^T M Q (made
