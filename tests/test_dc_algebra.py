@@ -163,3 +163,24 @@ def test_order_by_magnitude_keeps_the_svd():
     U = (W @ V2) * sgn
     assert np.abs((U * S) @ V2.T - W @ H2).max() < 1e-12
     assert np.abs(U.T @ U - np.eye(n)).max() < 1e-12
+
+
+def test_an_error_that_does_not_commute_with_m_is_not_squared():
+    """W off by a generic symmetric error eps E: the subspace iteration step
+    converges to P's own invariant subspace, which E moves at first order,
+    so the dropped coupling stays first order in eps (the split relies on W
+    being a function of the shifted piece)."""
+    rng = inputs.rng_for(901, 0)
+    n = 80
+    lam = np.concatenate([rng.uniform(-1.0, -0.3, n // 2), rng.uniform(0.3, 1.0, n - n // 2)])
+    M, _ = _sym(rng, n, lam)
+    W0 = _polar(M)
+    E = rng.standard_normal((n, n))
+    E = 0.5 * (E + E.T)
+    E /= np.linalg.norm(E, 2)
+    Om = rng.uniform(-1.0, 1.0, (n, n))
+    t = []
+    for eps in (1e-3, 1e-4):
+        _, _, _, T = _split(M, W0 + eps * E, Om)
+        t.append(np.linalg.norm(T[n - n // 2:, :n - n // 2]) / np.linalg.norm(T))
+    assert 5 < t[0] / t[1] < 20
