@@ -199,8 +199,8 @@ def phase_table(L, steps):
     return out
 
 
-def eigh_dc_bench(args):
-    """One N x N symmetric matrix with a uniform spectrum in [-1, 2] (the
+def evd_single(n, steps, warmup, solver="both"):
+    """One n x n symmetric matrix with a uniform spectrum in [-1, 2] (the
     paper's single-matrix setting for its EVD bottleneck): milliseconds per
     call of svdp_eigh_dc and svdp_eigh, and their eigenvalue errors against
     the known spectrum (relative to max |lambda|) and reconstruction."""
@@ -208,7 +208,6 @@ def eigh_dc_bench(args):
     import torch
     from paper_2609_32505_amd import api, inputs
 
-    n = args.eigh_dc
     rng = inputs.rng_for(320 + n, 0)
     Q = inputs.orthonormal(rng, n, n)
     lam = rng.uniform(-1.0, 2.0, n)
@@ -217,18 +216,18 @@ def eigh_dc_bench(args):
     ref = np.sort(lam)[::-1]
     out = {"metric": "symmetric EVD of one matrix, ms per call", "unit": "ms", "higher_is_better": False,
            "config": {"workload": f"one {n} x {n} FP32 symmetric matrix, eigenvalues uniform in [-1, 2]"},
-           "steps": args.steps, "warmup": args.warmup, "data": "synthetic"}
+           "steps": steps, "warmup": warmup, "data": "synthetic"}
     solvers = {"dc": api.eigh_dc, "jacobi": api.eigh}
-    for name in (("dc", "jacobi") if args.solver == "both" else (args.solver,)):
+    for name in (("dc", "jacobi") if solver == "both" else (solver,)):
         fn = solvers[name]
-        for _ in range(args.warmup):
+        for _ in range(warmup):
             res = fn(Hd)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(args.steps):
+        for _ in range(steps):
             res = fn(Hd)
         torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) * 1e3 / max(args.steps, 1)
+        ms = (time.perf_counter() - t0) * 1e3 / max(steps, 1)
         lam_g = res[0].cpu().double().numpy()[0]
         V = res[1].cpu().double().numpy()[0]
         recon = float(np.linalg.norm((V * lam_g) @ V.T - H) / np.linalg.norm(H))
@@ -237,7 +236,11 @@ def eigh_dc_bench(args):
         log(f"{name}: {ms:.1f} ms per call")
     if "dc" in out and "jacobi" in out:
         out["speedup_dc_vs_jacobi"] = round(out["jacobi"]["ms"] / out["dc"]["ms"], 3)
-    print(json.dumps(out), flush=True)
+    return out
+
+
+def eigh_dc_bench(args):
+    print(json.dumps(evd_single(args.eigh_dc, args.steps, args.warmup, args.solver)), flush=True)
 
 
 def main():
@@ -500,6 +503,15 @@ def main():
         "cpu_baseline": cpu,
         "paper_context": PAPER_CONTEXT,
     }
+    # context beside the headline, after its timed legs: one 4096^2 symmetric
+    # EVD by the divide and conquer and by the block Jacobi
+    try:
+        evd = evd_single(4096, steps=2, warmup=1)
+        rec["evd_single_4096"] = {k: evd[k] for k in ("dc", "jacobi", "speedup_dc_vs_jacobi")}
+        rec["evd_single_4096"]["note"] = ("ms per call of svdp_eigh_dc and svdp_eigh on one 4096 x 4096 matrix, "
+                                          "eigenvalues uniform in [-1, 2] (python3 bench.py --eigh-dc 4096)")
+    except Exception as e:  # context only: the headline line does not depend on it
+        rec["evd_single_4096"] = {"error": str(e)}
     print(json.dumps(rec), flush=True)
 
 
