@@ -212,7 +212,10 @@ svdp_status svdp_set_model(svdp_handle* h, const float* host_model);
 #define SVDP_OP_EIGH_DC 7
 svdp_status svdp_workspace_size(const svdp_params* p, int32_t op, size_t* bytes);
 
-const char* svdp_status_string(svdp_status s);
+/* name of a status code; any other value gives "unknown status" (the code
+ * is taken as an int, so a value from a foreign caller outside svdp_status
+ * is defined behaviour) */
+const char* svdp_status_string(int32_t status);
 /* message of the last failing call on this thread (static storage) */
 const char* svdp_last_error(void);
 

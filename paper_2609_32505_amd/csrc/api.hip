@@ -1426,7 +1426,7 @@ void svdp_default_params(svdp_params* p, int64_t batch, int64_t m, int64_t n) {
   p->tall_qr = 1;
 }
 
-const char* svdp_status_string(svdp_status s) {
+const char* svdp_status_string(int32_t s) {
   switch (s) {
     case SVDP_OK: return "ok";
     case SVDP_ERR_INVALID_ARG: return "invalid argument";
